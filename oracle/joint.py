@@ -1,0 +1,82 @@
+"""Joint sky-signal and C_l-amplitude Metropolis move (paper Sect. 2.2.2,
+after Racine et al. 2016), reduced to one parameter: C_l(q) = q C_l^fid.
+
+Steps of the move (the paper's enumerated algorithm, steps 2-4):
+1. propose q' = q exp(sigma xi) (Gaussian transition in ln q);
+2. solve the mean field a^(q') (eq. mean-field-map);
+3. rescale the fluctuation f^_s = C(q')^{1/2} C(q)^{-1/2} f^ = sqrt(q'/q) f^;
+4. evaluate ln pi(q') with f^_s (eq. acceptance-rate and the pi(theta)
+   definition after it) and ln A = ln pi(q') - ln pi(q) + ln(q'/q);
+5. accept iff ln u < ln A; only when accepted solve a fresh fluctuation
+   f^(q') with new w0, w1 (eq. fluc-map) and re-evaluate ln pi with it.
+
+Readings: the garbled middle term of pi is read as a^T S^-1 a^ (completing
+the square makes it exact); the prior is uniform in q, so the lognormal
+proposal contributes the Jacobian factor q'/q; ties ln u = ln A reject.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from .cr import CROperator, Problem, pcg
+
+
+def scaled_problem(fid: Problem, q: float) -> Problem:
+    return Problem(fid.nside, fid.lmax, q * fid.cl, fid.bl, fid.ninv, fid.lmin)
+
+
+def lnpi_terms(op: CROperator, d: np.ndarray, ahat: np.ndarray, fhat: np.ndarray):
+    """(chi^2 of the mean field, a^T S^-1 a^, f^T B^T N^-1 B f^)."""
+    res = d - op.sht.synth(op.b * op.project(ahat))
+    chi2 = float(np.sum(op.p.ninv * res * res))
+    prior = op.dot(ahat, op.sinv * ahat)
+    ff = op.sht.synth(op.b * op.project(fhat))
+    fluct = float(np.sum(op.p.ninv * ff * ff))
+    return chi2, prior, fluct
+
+
+def lnpi(op: CROperator, d, ahat, fhat) -> float:
+    return -0.5 * sum(lnpi_terms(op, d, ahat, fhat))
+
+
+@dataclass
+class ChainState:
+    q: float
+    ahat: np.ndarray
+    fhat: np.ndarray
+    lnpi: float
+
+
+def init_state(fid: Problem, d, q: float, w0, w1, tol: float, maxiter: int = 20000) -> ChainState:
+    """Algorithm step 1 with a fixed amplitude q instead of a Boltzmann code."""
+    op = CROperator(scaled_problem(fid, q))
+    ahat, _ = pcg(op, op.rhs(d=d), tol, maxiter)
+    fhat, _ = pcg(op, op.rhs(w0=w0, w1=w1), tol, maxiter)
+    return ChainState(q, ahat, fhat, lnpi(op, d, ahat, fhat))
+
+
+@dataclass
+class StepResult:
+    accepted: bool
+    lnA: float
+    q_new: float
+    lnpi_new: float
+
+
+def joint_step(fid: Problem, d, state: ChainState, xi: float, u: float, w0_new, w1_new,
+               sigma_lnq: float, tol: float, maxiter: int = 20000):
+    q_new = state.q * math.exp(sigma_lnq * xi)
+    op = CROperator(scaled_problem(fid, q_new))
+    ahat, _ = pcg(op, op.rhs(d=d), tol, maxiter)
+    f_scaled = math.sqrt(q_new / state.q) * state.fhat
+    lp_new = lnpi(op, d, ahat, f_scaled)
+    lnA = lp_new - state.lnpi + math.log(q_new / state.q)
+    accepted = math.log(u) < lnA
+    if not accepted:
+        return state, StepResult(False, lnA, q_new, lp_new)
+    fhat, _ = pcg(op, op.rhs(w0=w0_new, w1=w1_new), tol, maxiter)
+    new = ChainState(q_new, ahat, fhat, lnpi(op, d, ahat, fhat))
+    return new, StepResult(True, lnA, q_new, lp_new)
