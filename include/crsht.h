@@ -1,0 +1,231 @@
+/*
+ * crsht -- constrained-realization solves and spherical-harmonic transforms on
+ * HEALPix, for AMD Instinct MI355X (gfx950).
+ *
+ * The library solves the constrained-realization (CR) system of Eskilt et al.
+ * 2023 (arXiv:2306.15511), Sect. 2.2.1, eq. (mapmakingeq):
+ *
+ *     (S^-1 + B Y^T N^-1 Y B) s = B Y^T N^-1 d + S^-1/2 w0 + B Y^T N^-1/2 w1
+ *
+ * with S = diag(C_l) the signal covariance, B = diag(b_l) the beam, Y the
+ * spherical-harmonic synthesis onto HEALPix pixels (RING order), Y^T its exact
+ * transpose, N^-1 the per-pixel inverse noise variance (0 = masked), d the
+ * map and w0, w1 unit white-noise draws. The paper's "B" (beam and projection)
+ * is Y B here. It also implements one joint C_l-amplitude / sky Metropolis
+ * move (Sect. 2.2.2, eq. acceptance-rate and the algorithm that follows it).
+ *
+ * Conventions
+ *   - a_lm of a real field: m >= 0 only, m-major (for m = 0..mmax, l = m..lmax),
+ *     complex interleaved float64: element (l, m) of column c is at
+ *     alm[2*(c*nalm + mstart(m) + l - m) + {0: Re, 1: Im}],
+ *     mstart(m) = m*(lmax+1) - m*(m-1)/2, nalm = mstart(mmax+1).
+ *     Im a_l0 is ignored on input and written as 0.
+ *   - Y_lm = Delta_lm P_lm(cos theta) e^{i m phi} with one overall (-1)^m
+ *     (paper App. A); (Y a)_p = sum_l [a_l0 lambda_l0 + 2 Re sum_{m>0} a_lm Y_lm(p)].
+ *   - (Y^T x)_lm = sum_p x_p Y*_lm(p): the plain transpose, no quadrature weight.
+ *     It is the adjoint of Y under <a,c> = sum_l a_l0 c_l0 + 2 sum_{m>0} Re(a_lm c*_lm).
+ *   - Maps: float64 [nrhs][npix], HEALPix RING order (Gorski et al. 2005).
+ *   - Column c of a batched call is array slice c; columns are independent.
+ *
+ * Memory and streams
+ *   - Pointers documented as "device" are caller-owned device memory on the
+ *     plan's device; the library never frees or keeps them past the call.
+ *     Pointers documented as "host" are host memory.
+ *   - A plan owns its tables and workspace (allocated at creation, sized for
+ *     nrhs_max columns); calls allocate nothing.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream). Transforms
+ *     and cr_apply are asynchronous on it. cr_solve, cr_rhs_and_solve style
+ *     calls and joint_cl_step synchronise `stream` (they read convergence
+ *     scalars); their outputs are complete when they return.
+ *   - A plan is not thread-safe: concurrent calls need distinct plans.
+ *
+ * Errors: functions return CR_OK (0) or a negative code detected before or
+ * while enqueueing work; numerical outcomes go to cr_stats.status.
+ */
+#ifndef CRSHT_H
+#define CRSHT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CR_OK = 0,
+  CR_EINVAL = -1,    /* invalid argument (sizes, NULL pointers, bad spectra) */
+  CR_ENOMEM = -2,    /* device allocation failed at plan creation */
+  CR_EDEVICE = -3,   /* a HIP runtime call or kernel launch failed */
+  CR_ENOTSUP = -4,   /* valid but not supported by this build */
+  CR_NOCONV = 1,     /* maxiter reached; the last iterate is written */
+  CR_BREAKDOWN = 2   /* <p, A p> <= 0 or non-finite; output undefined */
+};
+
+typedef struct crsht_plan crsht_plan;
+
+/* Arithmetic of the Legendre contraction.
+ * CR_F64: float64 throughout.
+ * CR_MIXED: lambda_lm recurrence, CG vectors, dot products and scalars in
+ *   float64; Legendre sums accumulated in float32 from float32-rounded
+ *   recurrence values and coefficients; used by cr_solve as the inner
+ *   operator of float64 iterative refinement. */
+typedef enum { CR_F64 = 0, CR_MIXED = 1 } cr_prec;
+
+/* Create a plan for HEALPix resolution nside (power of two not required,
+ * 1 <= nside <= 8192), band limit lmax >= 0 and mmax (<= lmax; pass -1 for
+ * mmax = lmax), ncomp = 1 (temperature), for up to nrhs_max >= 1 columns per
+ * call. Builds the ring table (Gorski et al. 2005), the recurrence tables of
+ * lambda_lm (paper App. A normalisation) and the per-ring FFT tables, and
+ * allocates the workspace on the current HIP device.
+ * Returns CR_EINVAL, CR_ENOTSUP (ncomp != 1) or CR_ENOMEM on failure
+ * (*out set to NULL). */
+int crsht_plan_create(int nside, int lmax, int mmax, int ncomp, int nrhs_max, crsht_plan **out);
+
+/* Free a plan and everything it owns. NULL is allowed. */
+void crsht_plan_destroy(crsht_plan *plan);
+
+/* Static string describing a status code. */
+const char *crsht_strerror(int status);
+
+typedef struct {
+  int nside, lmax, mmax, ncomp, nrhs_max, nrings;
+  int64_t npix, nalm;
+  int64_t workspace_bytes;   /* device memory owned by the plan */
+} crsht_info;
+
+/* Fill *info (host). */
+int crsht_plan_info(const crsht_plan *plan, crsht_info *info);
+
+/* Pixel-centre coordinates z = cos(theta) and phi of every pixel, RING order,
+ * written to host arrays of npix doubles each. */
+int crsht_pixel_coords(const crsht_plan *plan, double *z_host, double *phi_host);
+
+/* Synthesis Y (paper Sect. 2.1, a(n) = sum a_lm Y_lm(n)).
+ * alm: device, [nrhs][nalm] complex; map: device, [nrhs][npix].
+ * 1 <= nrhs <= nrhs_max. prec: CR_F64 or CR_MIXED. Asynchronous. */
+int sht_synth(const crsht_plan *plan, int nrhs, const double *alm, double *map, cr_prec prec, void *stream);
+
+/* Adjoint synthesis Y^T (the transpose; paper App. A pixel sums).
+ * map: device [nrhs][npix]; alm: device [nrhs][nalm] complex. Asynchronous. */
+int sht_synth_adjoint(const crsht_plan *plan, int nrhs, const double *map, double *alm, cr_prec prec,
+                      void *stream);
+
+/* Analysis: alm = (4 pi / Npix) Y^T map, followed by n_iter >= 0 Jacobi
+ * corrections alm += (4 pi / Npix) Y^T (map - Y alm) (App. A: the pixel sum as
+ * Npix/(4 pi) times the sphere integral). FP64. Asynchronous. */
+int sht_analysis(const crsht_plan *plan, int nrhs, const double *map, double *alm, int n_iter, void *stream);
+
+/* The statement of the problem (paper Sect. 2.2.1, r = B a + n; App. A N^-1). */
+typedef struct {
+  const double *cl;    /* host, [lmax+1]: C_l (temperature). Modes with l < lmin are fixed to 0;
+                          C_l must be > 0 and finite for lmin <= l <= lmax. */
+  const double *bl;    /* host, [lmax+1]: beam transfer function b_l (finite). */
+  const double *ninv;  /* device, [npix]: inverse noise variance per pixel, >= 0, 0 = masked. */
+  int lmin;            /* first constrained multipole, 0 <= lmin <= lmax (2 for C_0 = C_1 = 0). */
+} cr_problem;
+
+typedef struct {
+  double tol;          /* target relative residual ||b - A s|| / ||b|| (real-field norm), > 0 */
+  int maxiter;         /* maximum CG iterations (all refinement sweeps together), >= 1 */
+  cr_prec prec;        /* CR_F64: plain PCG; CR_MIXED: FP64 refinement around a mixed inner PCG */
+  double inner_tol;    /* CR_MIXED: relative tolerance of each inner solve (e.g. 1e-2); ignored for CR_F64 */
+  int max_refine;      /* CR_MIXED: maximum refinement sweeps */
+  int check_every;     /* iterations between host convergence checks (>= 1; 0 = 8) */
+} cr_opts;
+
+typedef struct {
+  int status;              /* CR_OK, CR_NOCONV or CR_BREAKDOWN */
+  int iters;               /* CG iterations (inner iterations summed for CR_MIXED) */
+  int refinements;         /* refinement sweeps (0 for CR_F64) */
+  double rel_resid_true;   /* ||b - A s|| / ||b|| evaluated in FP64 at exit */
+} cr_stats;
+
+/* Jacobi preconditioner diagonal (the paper's "standard diagonal
+ * preconditioner", Sect. 5): D_lm = 1/C_l + b_l^2 sum_r lambda_lm(z_r)^2 W_r,
+ * W_r = sum of N^-1 over ring r. diag: device [nalm] float64 (1 where l < lmin).
+ * Asynchronous. */
+int cr_precond(const crsht_plan *plan, const cr_problem *prob, double *diag, void *stream);
+
+/* Right-hand side of eq. mapmakingeq: b = B Y^T N^-1 d + S^-1/2 w0 + B Y^T N^-1/2 w1,
+ * restricted to l >= lmin. d, w1: device maps [nrhs][npix]; w0: device alm
+ * [nrhs][nalm]; any of the three may be NULL (term omitted). b: device
+ * [nrhs][nalm]. Asynchronous. */
+int cr_rhs(const crsht_plan *plan, const cr_problem *prob, int nrhs, const double *d, const double *w0,
+           const double *w1, double *b, void *stream);
+
+/* The operator alone: Ax = (S^-1 + B Y^T N^-1 Y B) x on l >= lmin (0 below).
+ * x, Ax: device [nrhs][nalm]. Asynchronous. */
+int cr_apply(const crsht_plan *plan, const cr_problem *prob, int nrhs, const double *x, double *Ax,
+             cr_prec prec, void *stream);
+
+/* Solve eq. mapmakingeq for nrhs independent columns by Jacobi-preconditioned
+ * conjugate gradients (Shewchuk 1994) from s = 0. The right-hand side is
+ * assembled as in cr_rhs from d, w0, w1 (NULL = omitted: d only gives the mean
+ * field of eq. mean-field-map, w0 and w1 only the fluctuation of eq. fluc-map),
+ * unless rhs is non-NULL (device [nrhs][nalm]), which is used as b directly.
+ * s_out: device [nrhs][nalm]. stats: host, nrhs entries.
+ * Blocks until the solve has finished on `stream`. */
+int cr_solve(const crsht_plan *plan, const cr_problem *prob, int nrhs, const double *d, const double *w0,
+             const double *w1, const double *rhs, double *s_out, const cr_opts *opts, cr_stats *stats,
+             void *stream);
+
+/* ln pi of the joint move (Sect. 2.2.2, definition of pi(theta)) for the
+ * amplitude-scaled spectrum C_l(q) = q cl:
+ *   ln pi = -1/2 (d - Y B a)^T N^-1 (d - Y B a) - 1/2 a^T S(q)^-1 a - 1/2 f^T B Y^T N^-1 Y B f
+ * d: device map; ahat, fhat: device alm [nalm]. Result to *lnpi (host).
+ * Blocks until done. */
+int cr_lnpi(const crsht_plan *plan, const cr_problem *fid, double q, const double *d, const double *ahat,
+            const double *fhat, double *lnpi, void *stream);
+
+/* State of one amplitude chain (host struct, device arrays of nalm complex). */
+typedef struct {
+  double q;            /* current amplitude, C_l = q * fid.cl */
+  double lnpi;         /* ln pi(q) of the current (ahat, fhat) */
+  double *ahat;        /* device [nalm]: mean field at q */
+  double *fhat;        /* device [nalm]: fluctuation at q */
+} cr_chain;
+
+/* Randomness of one move, drawn by the caller. */
+typedef struct {
+  double xi;           /* standard normal: proposal ln q' = ln q + sigma_lnq xi */
+  double u;            /* uniform in (0,1): accept iff ln u < ln A */
+  const double *w0;    /* device [nalm]: fresh w0 for the fluctuation solve on acceptance */
+  const double *w1;    /* device [npix]: fresh w1 */
+  double sigma_lnq;    /* proposal width in ln q (> 0) */
+} cr_draws;
+
+typedef struct {
+  int accepted;
+  double lnA;          /* ln of the acceptance ratio (FP64) */
+  double q_new;        /* proposed amplitude */
+  double lnpi_new;     /* ln pi at the proposal with the rescaled fluctuation */
+  cr_stats mean_stats; /* mean-field solve */
+  cr_stats fluct_stats;/* fluctuation solve (zeros if rejected) */
+} cr_step_out;
+
+/* One joint C_l-amplitude / sky move (paper Sect. 2.2.2, algorithm steps 2-4):
+ * propose q' = q exp(sigma xi); solve the mean field at q'; rescale the
+ * fluctuation by sqrt(q'/q); ln A = ln pi(q') - ln pi(q) + ln(q'/q) (uniform
+ * prior in q; Gaussian proposal in ln q); accept iff ln u < ln A, and only then
+ * solve a fresh fluctuation with draws->w0, w1 and update *state (q, lnpi,
+ * ahat, fhat in place). Needs nrhs_max >= 1; uses the plan workspace.
+ * `out` is host. Blocks until done. */
+int joint_cl_step(const crsht_plan *plan, const cr_problem *fid, const double *d, cr_chain *state,
+                  const cr_draws *draws, const cr_opts *opts, cr_step_out *out, void *stream);
+
+/* Per-kernel timing for measurement (not needed for computation).
+ * crsht_timing_enable(plan, 1) synchronises the device, clears the counters
+ * and makes the library bracket every launch of the tracked kernels with a
+ * pair of HIP events on the launch stream; 0 turns it off. Tracked kernels:
+ * 0 = Legendre synthesis, 1 = Legendre adjoint (incl. the preconditioner
+ * diagonal pass), 2 = ring (azimuthal FFT) pass.
+ * crsht_timing_read waits for the recorded events and returns the summed
+ * duration (milliseconds) and the number of launches since enabling. */
+int crsht_timing_enable(const crsht_plan *plan, int on);
+int crsht_timing_read(const crsht_plan *plan, int kernel, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CRSHT_H */

@@ -138,3 +138,24 @@ class SHT:
         R = self.rings
         return np.array([ninv[int(R.first[k]):int(R.first[k]) + int(R.nphi[k])].sum()
                          for k in range(R.nrings)])
+
+
+def synth_rings(sht: SHT, alm: np.ndarray, ring_idx) -> dict:
+    """Map values on selected rings only (ring index -> pixel values), the
+    same two sums as SHT.synth restricted to those rings."""
+    R = sht.rings
+    ring_idx = list(ring_idx)
+    z, st = R.z[ring_idx], R.sin_theta[ring_idx]
+    F = np.zeros((sht.mmax + 1, len(ring_idx)), dtype=np.complex128)
+    for l, lam in lambda_rows(sht.lmax, sht.mmax, z, st):
+        top = lam.shape[0] - 1
+        F[:top + 1] += lam * alm[sht._idx(l, top)][:, None]
+    m = np.arange(sht.mmax + 1)
+    wm = np.where(m == 0, 1.0, 2.0)
+    out = {}
+    for j, k in enumerate(ring_idx):
+        n = int(R.nphi[k])
+        c = np.zeros(n, dtype=np.complex128)
+        np.add.at(c, m % n, wm * F[:, j] * np.exp(1j * m * R.phi0[k]))
+        out[k] = (n * np.fft.ifft(c)).real
+    return out

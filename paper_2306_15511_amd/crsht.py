@@ -1,0 +1,334 @@
+"""Python binding of libcrsht (include/crsht.h): argument marshalling only.
+
+Device memory and streams come from PyTorch (ROCm); every computation runs in
+the library's HIP kernels. a_lm tensors are complex128 of shape [nalm] or
+[nrhs, nalm] (m-major, m >= 0); maps are float64 [npix] or [nrhs, npix] in
+HEALPix RING order. The library must be built (``python -m
+paper_2306_15511_amd.build``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcrsht.so")
+
+CR_OK, CR_EINVAL, CR_ENOMEM, CR_EDEVICE, CR_ENOTSUP = 0, -1, -2, -3, -4
+CR_NOCONV, CR_BREAKDOWN = 1, 2
+CR_F64, CR_MIXED = 0, 1
+
+
+class CrshtError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__("%s failed: %s (%d)" % (where, strerror(code), code))
+        self.code = code
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("nside", ctypes.c_int), ("lmax", ctypes.c_int), ("mmax", ctypes.c_int), ("ncomp", ctypes.c_int),
+                ("nrhs_max", ctypes.c_int), ("nrings", ctypes.c_int), ("npix", ctypes.c_int64),
+                ("nalm", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("cl", ctypes.POINTER(ctypes.c_double)), ("bl", ctypes.POINTER(ctypes.c_double)),
+                ("ninv", ctypes.c_void_p), ("lmin", ctypes.c_int)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("prec", ctypes.c_int),
+                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int), ("check_every", ctypes.c_int)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("refinements", ctypes.c_int),
+                ("rel_resid_true", ctypes.c_double)]
+
+
+class _Chain(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_double), ("lnpi", ctypes.c_double), ("ahat", ctypes.c_void_p),
+                ("fhat", ctypes.c_void_p)]
+
+
+class _Draws(ctypes.Structure):
+    _fields_ = [("xi", ctypes.c_double), ("u", ctypes.c_double), ("w0", ctypes.c_void_p),
+                ("w1", ctypes.c_void_p), ("sigma_lnq", ctypes.c_double)]
+
+
+class _StepOut(ctypes.Structure):
+    _fields_ = [("accepted", ctypes.c_int), ("lnA", ctypes.c_double), ("q_new", ctypes.c_double),
+                ("lnpi_new", ctypes.c_double), ("mean_stats", _Stats), ("fluct_stats", _Stats)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libcrsht.so is not built (%s); run python -m paper_2306_15511_amd.build" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, vp, i, d = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "crsht_plan_create": ([i, i, i, i, i, ctypes.POINTER(ctypes.c_void_p)], i),
+        "crsht_plan_destroy": ([P], None),
+        "crsht_strerror": ([i], ctypes.c_char_p),
+        "crsht_plan_info": ([P, ctypes.POINTER(_Info)], i),
+        "crsht_pixel_coords": ([P, vp, vp], i),
+        "sht_synth": ([P, i, vp, vp, i, vp], i),
+        "sht_synth_adjoint": ([P, i, vp, vp, i, vp], i),
+        "sht_analysis": ([P, i, vp, vp, i, vp], i),
+        "cr_precond": ([P, ctypes.POINTER(_Problem), vp, vp], i),
+        "cr_rhs": ([P, ctypes.POINTER(_Problem), i, vp, vp, vp, vp, vp], i),
+        "cr_apply": ([P, ctypes.POINTER(_Problem), i, vp, vp, i, vp], i),
+        "cr_solve": ([P, ctypes.POINTER(_Problem), i, vp, vp, vp, vp, vp, ctypes.POINTER(_Opts),
+                      ctypes.POINTER(_Stats), vp], i),
+        "cr_lnpi": ([P, ctypes.POINTER(_Problem), d, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp], i),
+        "joint_cl_step": ([P, ctypes.POINTER(_Problem), vp, ctypes.POINTER(_Chain), ctypes.POINTER(_Draws),
+                           ctypes.POINTER(_Opts), ctypes.POINTER(_StepOut), vp], i),
+        "crsht_timing_enable": ([P, i], i),
+        "crsht_timing_read": ([P, i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], i),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+
+EXPORTED = ("crsht_plan_create", "crsht_plan_destroy", "crsht_strerror", "crsht_plan_info", "crsht_pixel_coords",
+            "sht_synth", "sht_synth_adjoint", "sht_analysis", "cr_precond", "cr_rhs", "cr_apply", "cr_solve",
+            "cr_lnpi", "joint_cl_step", "crsht_timing_enable", "crsht_timing_read")
+
+
+def lib():
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return _lib.crsht_strerror(int(code)).decode()
+
+
+def _check(rc: int, where: str):
+    if rc < 0:
+        raise CrshtError(rc, where)
+    return rc
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _nrhs(t, per: int, dtype) -> int:
+    if t.dtype != dtype:
+        raise TypeError("expected %s, got %s" % (dtype, t.dtype))
+    if t.numel() % per or t.numel() == 0:
+        raise ValueError("tensor size %d is not a multiple of %d" % (t.numel(), per))
+    return t.numel() // per
+
+
+class Plan:
+    """Geometry, tables and workspace for one (nside, lmax, mmax, nrhs_max)."""
+
+    def __init__(self, nside: int, lmax: int, mmax: int = -1, nrhs_max: int = 1, ncomp: int = 1):
+        h = ctypes.c_void_p()
+        _check(_lib.crsht_plan_create(nside, lmax, mmax, ncomp, nrhs_max, ctypes.byref(h)), "crsht_plan_create")
+        self._h = h
+        info = _Info()
+        _check(_lib.crsht_plan_info(h, ctypes.byref(info)), "crsht_plan_info")
+        self.nside, self.lmax, self.mmax = info.nside, info.lmax, info.mmax
+        self.nrhs_max, self.nrings = info.nrhs_max, info.nrings
+        self.npix, self.nalm = int(info.npix), int(info.nalm)
+        self.workspace_bytes = int(info.workspace_bytes)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.crsht_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pixel_coords(self):
+        import numpy as np
+        z = np.empty(self.npix)
+        phi = np.empty(self.npix)
+        _check(_lib.crsht_pixel_coords(self._h, z.ctypes.data_as(ctypes.c_void_p), phi.ctypes.data_as(ctypes.c_void_p)),
+               "crsht_pixel_coords")
+        return z, phi
+
+
+KERNEL_LEGENDRE_SYNTH, KERNEL_LEGENDRE_ADJOINT, KERNEL_RING = 0, 1, 2
+
+
+def timing_enable(plan: Plan, on: bool = True):
+    _check(_lib.crsht_timing_enable(plan.handle, 1 if on else 0), "crsht_timing_enable")
+
+
+def timing_read(plan: Plan, kernel: int):
+    """(total milliseconds, launches) of a tracked kernel since timing_enable."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(_lib.crsht_timing_read(plan.handle, kernel, ctypes.byref(ms), ctypes.byref(n)), "crsht_timing_read")
+    return ms.value, n.value
+
+
+# ---------------------------------------------------------------- transforms
+def synth(plan: Plan, alm: torch.Tensor, out: torch.Tensor | None = None, prec: int = CR_F64) -> torch.Tensor:
+    n = _nrhs(alm, plan.nalm, torch.complex128)
+    if out is None:
+        out = torch.empty((n, plan.npix) if alm.dim() > 1 else (plan.npix,), dtype=torch.float64, device=alm.device)
+    _check(_lib.sht_synth(plan.handle, n, _ptr(alm), _ptr(out), prec, _stream()), "sht_synth")
+    return out
+
+
+def adjoint(plan: Plan, m: torch.Tensor, out: torch.Tensor | None = None, prec: int = CR_F64) -> torch.Tensor:
+    n = _nrhs(m, plan.npix, torch.float64)
+    if out is None:
+        out = torch.empty((n, plan.nalm) if m.dim() > 1 else (plan.nalm,), dtype=torch.complex128, device=m.device)
+    _check(_lib.sht_synth_adjoint(plan.handle, n, _ptr(m), _ptr(out), prec, _stream()), "sht_synth_adjoint")
+    return out
+
+
+def analysis(plan: Plan, m: torch.Tensor, n_iter: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
+    n = _nrhs(m, plan.npix, torch.float64)
+    if out is None:
+        out = torch.empty((n, plan.nalm) if m.dim() > 1 else (plan.nalm,), dtype=torch.complex128, device=m.device)
+    _check(_lib.sht_analysis(plan.handle, n, _ptr(m), _ptr(out), n_iter, _stream()), "sht_analysis")
+    return out
+
+
+# ---------------------------------------------------------------- CR system
+@dataclass
+class Problem:
+    """cl, bl: host float64 arrays of lmax+1; ninv: device float64 [npix]."""
+    cl: object
+    bl: object
+    ninv: torch.Tensor
+    lmin: int = 2
+
+    def _c(self, q: float = 1.0):
+        import numpy as np
+        self._cl = np.ascontiguousarray(self.cl, dtype=np.float64)
+        self._bl = np.ascontiguousarray(self.bl, dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        return _Problem(self._cl.ctypes.data_as(dp), self._bl.ctypes.data_as(dp), _ptr(self.ninv), self.lmin)
+
+
+@dataclass
+class Stats:
+    status: int
+    iters: int
+    refinements: int
+    rel_resid_true: float
+
+
+def precond(plan: Plan, prob: Problem) -> torch.Tensor:
+    out = torch.empty(plan.nalm, dtype=torch.float64, device=prob.ninv.device)
+    p = prob._c()
+    _check(_lib.cr_precond(plan.handle, ctypes.byref(p), _ptr(out), _stream()), "cr_precond")
+    return out
+
+
+def rhs(plan: Plan, prob: Problem, d=None, w0=None, w1=None, nrhs: int = 1) -> torch.Tensor:
+    out = torch.empty((nrhs, plan.nalm), dtype=torch.complex128, device=prob.ninv.device)
+    p = prob._c()
+    _check(_lib.cr_rhs(plan.handle, ctypes.byref(p), nrhs, _ptr(d), _ptr(w0), _ptr(w1), _ptr(out), _stream()),
+           "cr_rhs")
+    return out
+
+
+def apply(plan: Plan, prob: Problem, x: torch.Tensor, prec: int = CR_F64) -> torch.Tensor:
+    n = _nrhs(x, plan.nalm, torch.complex128)
+    out = torch.empty_like(x)
+    p = prob._c()
+    _check(_lib.cr_apply(plan.handle, ctypes.byref(p), n, _ptr(x), _ptr(out), prec, _stream()), "cr_apply")
+    return out
+
+
+def solve(plan: Plan, prob: Problem, d=None, w0=None, w1=None, rhs_vec=None, nrhs: int = 1, tol: float = 1e-6,
+          maxiter: int = 10000, prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 50,
+          check_every: int = 8, out: torch.Tensor | None = None):
+    """Returns (s [nrhs, nalm] complex128, [Stats])."""
+    if out is None:
+        out = torch.empty((nrhs, plan.nalm), dtype=torch.complex128, device=prob.ninv.device)
+    p = prob._c()
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every)
+    st = (_Stats * nrhs)()
+    _check(_lib.cr_solve(plan.handle, ctypes.byref(p), nrhs, _ptr(d), _ptr(w0), _ptr(w1), _ptr(rhs_vec), _ptr(out),
+                         ctypes.byref(o), st, _stream()), "cr_solve")
+    return out, [Stats(s.status, s.iters, s.refinements, s.rel_resid_true) for s in st]
+
+
+def lnpi(plan: Plan, fid: Problem, q: float, d: torch.Tensor, ahat: torch.Tensor, fhat: torch.Tensor) -> float:
+    p = fid._c()
+    v = ctypes.c_double()
+    _check(_lib.cr_lnpi(plan.handle, ctypes.byref(p), q, _ptr(d), _ptr(ahat), _ptr(fhat), ctypes.byref(v),
+                        _stream()), "cr_lnpi")
+    return v.value
+
+
+@dataclass
+class Chain:
+    q: float
+    lnpi: float
+    ahat: torch.Tensor
+    fhat: torch.Tensor
+
+
+@dataclass
+class StepResult:
+    accepted: bool
+    lnA: float
+    q_new: float
+    lnpi_new: float
+    mean_stats: Stats
+    fluct_stats: Stats
+
+
+def joint_step(plan: Plan, fid: Problem, d: torch.Tensor, chain: Chain, xi: float, u: float, w0: torch.Tensor,
+               w1: torch.Tensor, sigma_lnq: float = 0.02, tol: float = 1e-6, maxiter: int = 10000,
+               prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 50) -> StepResult:
+    p = fid._c()
+    c = _Chain(chain.q, chain.lnpi, _ptr(chain.ahat), _ptr(chain.fhat))
+    dr = _Draws(xi, u, _ptr(w0), _ptr(w1), sigma_lnq)
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, 8)
+    r = _StepOut()
+    _check(_lib.joint_cl_step(plan.handle, ctypes.byref(p), _ptr(d), ctypes.byref(c), ctypes.byref(dr),
+                              ctypes.byref(o), ctypes.byref(r), _stream()), "joint_cl_step")
+    chain.q, chain.lnpi = c.q, c.lnpi
+
+    def st(s):
+        return Stats(s.status, s.iters, s.refinements, s.rel_resid_true)
+
+    return StepResult(bool(r.accepted), r.lnA, r.q_new, r.lnpi_new, st(r.mean_stats), st(r.fluct_stats))
+
+
+def nalm(lmax: int, mmax: int | None = None) -> int:
+    mmax = lmax if mmax is None else mmax
+    return (mmax + 1) * (lmax + 1) - (mmax * (mmax + 1)) // 2
+
+
+__all__ = ["Plan", "Problem", "Stats", "Chain", "StepResult", "synth", "adjoint", "analysis", "precond", "rhs",
+           "apply", "solve", "lnpi", "joint_step", "CR_F64", "CR_MIXED", "CrshtError", "strerror", "EXPORTED"]
+_ = math

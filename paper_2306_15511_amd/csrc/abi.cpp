@@ -1,0 +1,379 @@
+// Public C entry points: transforms, the constrained-realization operator,
+// its right-hand side, preconditioned conjugate gradients and the joint
+// amplitude move. Host orchestration only; every arithmetic step runs in the
+// kernels of legendre.hip, ring.hip and vec.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+using namespace crsht;
+
+namespace {
+
+#define CR_TRY(expr)                           \
+  do {                                         \
+    hipError_t e_ = (expr);                    \
+    if (e_ != hipSuccess) return CR_EDEVICE;   \
+  } while (0)
+
+#define CR_CHECK(expr)       \
+  do {                       \
+    int r_ = (expr);         \
+    if (r_ != CR_OK) return r_; \
+  } while (0)
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+const double2* C2(const double* p) { return reinterpret_cast<const double2*>(p); }
+double2* C2(double* p) { return reinterpret_cast<double2*>(p); }
+
+int64_t eo_stride(const crsht_plan* P) { return (int64_t)P->g.npairs * (P->g.mmax + 1) * 2; }
+
+int check_plan(const crsht_plan* P, int nrhs) {
+  if (!P) return CR_EINVAL;
+  if (nrhs < 1 || nrhs > P->nrhs_max) return CR_EINVAL;
+  return CR_OK;
+}
+
+// ---- problem set-up: per-l factors for amplitude q (C_l -> q C_l)
+int set_problem(const crsht_plan* P, const cr_problem* prob, double q, hipStream_t s) {
+  if (!prob || !prob->cl || !prob->bl || !prob->ninv) return CR_EINVAL;
+  const int lmax = P->g.lmax;
+  if (prob->lmin < 0 || prob->lmin > lmax) return CR_EINVAL;
+  if (!(q > 0.0) || !std::isfinite(q)) return CR_EINVAL;
+  std::vector<double> perl(4 * (size_t)(lmax + 1), 0.0);
+  for (int l = 0; l <= lmax; ++l) {
+    const double b = prob->bl[l];
+    if (!std::isfinite(b)) return CR_EINVAL;
+    perl[2 * (lmax + 1) + l] = b;
+    if (l < prob->lmin) continue;
+    const double c = q * prob->cl[l];
+    if (!(c > 0.0) || !std::isfinite(c)) return CR_EINVAL;
+    perl[l] = 1.0 / c;
+    perl[(lmax + 1) + l] = 1.0 / std::sqrt(c);
+    perl[3 * (lmax + 1) + l] = 1.0;
+  }
+  CR_TRY(hipMemcpyAsync(P->w.perl, perl.data(), perl.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  CR_TRY(launch_expand(P, P->w.perl, s));
+  CR_TRY(hipStreamSynchronize(s));  // perl (host vector) must outlive the copy
+  return CR_OK;
+}
+
+// A x for x already projected; pt = bk * x must be in w.alm_a.
+// out = sinv * x + bk * (Y^T N^-1 Y)(pt); partials of <x, out> per m.
+int operator_core(const crsht_plan* P, int nrhs, const double2* x, const double2* pt, const double* ninv,
+                  double2* out, hipStream_t s) {
+  CR_TRY(launch_legendre_synth(P, nrhs, pt, P->w.eo, s));
+  CR_TRY(launch_ring(P, nrhs, RING_FUSED, P->w.eo, nullptr, ninv, P->w.geo, s));
+  CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, out, 1, x, P->w.sinv, P->w.bk, P->w.partial, false, s));
+  return CR_OK;
+}
+
+// Jacobi diagonal into w.diag
+int compute_diag(const crsht_plan* P, const double* ninv, hipStream_t s) {
+  CR_TRY(launch_ring_weights(P, ninv, P->w.ring_w, s));
+  CR_TRY(launch_legendre_adjoint(P, 1, nullptr, reinterpret_cast<double2*>(P->w.diag), 2, nullptr, P->w.sinv,
+                                 P->w.bk, nullptr, true, s));
+  return CR_OK;
+}
+
+// b = B Y^T (N^-1 d + N^-1/2 w1) + S^-1/2 w0 into out
+int assemble_rhs(const crsht_plan* P, int nrhs, const double* ninv, const double* d, const double* w0,
+                 const double* w1, double2* out, hipStream_t s) {
+  const double2* braw = nullptr;
+  if (d || w1) {
+    CR_TRY(launch_pix_rhs(P, nrhs, ninv, d, w1, P->w.map_a, s));
+    CR_TRY(launch_ring(P, nrhs, RING_ADJOINT, nullptr, P->w.map_a, nullptr, P->w.geo, s));
+    CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, P->w.alm_b, 0, nullptr, P->w.bk, nullptr, nullptr, false, s));
+    braw = P->w.alm_b;
+  }
+  CR_TRY(launch_rhs_finish(P, nrhs, braw, w0 ? C2(w0) : nullptr, out, s));
+  return CR_OK;
+}
+
+int synth_f64(const crsht_plan* P, int nrhs, const double2* alm, const double* scale, double* map, hipStream_t s) {
+  CR_TRY(launch_scale_alm(P, nrhs, alm, scale, P->w.alm_a, s));
+  CR_TRY(launch_legendre_synth(P, nrhs, P->w.alm_a, P->w.eo, s));
+  CR_TRY(launch_ring(P, nrhs, RING_SYNTH, P->w.eo, map, nullptr, nullptr, s));
+  return CR_OK;
+}
+
+int adjoint_f64(const crsht_plan* P, int nrhs, const double* map, double2* alm, hipStream_t s) {
+  CR_TRY(launch_ring(P, nrhs, RING_ADJOINT, nullptr, const_cast<double*>(map), nullptr, P->w.geo, s));
+  CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, alm, 0, nullptr, nullptr, nullptr, nullptr, false, s));
+  return CR_OK;
+}
+
+int read_scalars(const crsht_plan* P, int nrhs, hipStream_t s) {
+  CR_TRY(hipMemcpyAsync(P->w.host_scal, P->w.scal, (size_t)nrhs * kScalSlots * sizeof(double),
+                        hipMemcpyDeviceToHost, s));
+  CR_TRY(hipStreamSynchronize(s));
+  return CR_OK;
+}
+
+int write_scalars(const crsht_plan* P, int nrhs, hipStream_t s) {
+  CR_TRY(hipMemcpyAsync(P->w.scal, P->w.host_scal, (size_t)nrhs * kScalSlots * sizeof(double),
+                        hipMemcpyHostToDevice, s));
+  CR_TRY(hipStreamSynchronize(s));
+  return CR_OK;
+}
+
+// true relative residual ||b - A x|| / ||b|| per column into rel[]; leaves r = b - A x
+int true_residual(const crsht_plan* P, int nrhs, const double* ninv, const double2* x, const double2* b,
+                  double2* r, std::vector<double>& rel, hipStream_t s) {
+  const int64_t na = P->g.nalm;
+  CR_TRY(launch_scale_alm(P, nrhs, x, P->w.bk, P->w.alm_a, s));
+  CR_CHECK(operator_core(P, nrhs, x, P->w.alm_a, ninv, P->w.cg_q, s));
+  CR_TRY(launch_residual(P, nrhs, b, P->w.cg_q, r, s));
+  const int nb = vec_reduce_blocks(P);
+  CR_TRY(launch_sum_rows(P, nrhs, nb, s));
+  CR_CHECK(read_scalars(P, nrhs, s));
+  rel.assign(nrhs, 0.0);
+  for (int c = 0; c < nrhs; ++c) {
+    const double* sc = P->w.host_scal + c * kScalSlots;
+    rel[c] = sc[S_AUX1] > 0.0 ? std::sqrt(sc[S_AUX0] / sc[S_AUX1]) : 0.0;
+  }
+  (void)na;
+  return CR_OK;
+}
+
+// PCG on the problem already set up (sinv, bk, diag in the workspace) with
+// b in w.cg_b; solution in w.cg_x.
+int pcg_f64(const crsht_plan* P, int nrhs, const double* ninv, double tol, int maxiter, int check_every,
+            cr_stats* stats, hipStream_t s) {
+  const int64_t na = P->g.nalm;
+  const int nb = vec_reduce_blocks(P);
+  const int nbm = P->g.mmax + 1;
+  Workspace const& w = P->w;
+  CR_TRY(hipMemsetAsync(w.cg_x, 0, (size_t)nrhs * na * sizeof(double2), s));
+  CR_TRY(hipMemcpyAsync(w.cg_r, w.cg_b, (size_t)nrhs * na * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  CR_TRY(launch_cg_start(P, nrhs, w.cg_b, w.cg_r, w.cg_z, w.cg_p, w.alm_a, s));
+  CR_TRY(launch_cg_scalars(P, nrhs, 0, nb, tol, 0, s));
+  CR_CHECK(read_scalars(P, nrhs, s));
+
+  std::vector<int> status(nrhs, CR_OK);
+  std::vector<double> rel(nrhs, 0.0);
+  int it = 0;
+  bool finished = false;
+  while (!finished) {
+    bool all_done = true;
+    for (int c = 0; c < nrhs; ++c) all_done &= P->w.host_scal[c * kScalSlots + S_DONE] != 0.0;
+    if (!all_done && it < maxiter) {
+      const int n = std::min(check_every, maxiter - it);
+      for (int k = 0; k < n; ++k) {
+        CR_CHECK(operator_core(P, nrhs, w.cg_p, w.alm_a, ninv, w.cg_q, s));
+        CR_TRY(launch_cg_scalars(P, nrhs, 1, nbm, tol, 0, s));
+        CR_TRY(launch_cg_update(P, nrhs, w.cg_x, w.cg_r, w.cg_z, w.cg_p, w.cg_q, s));
+        CR_TRY(launch_cg_scalars(P, nrhs, 2, nb, tol, 0, s));
+        CR_TRY(launch_cg_pupdate(P, nrhs, w.cg_z, w.cg_p, w.alm_a, s));
+      }
+      it += n;
+      CR_CHECK(read_scalars(P, nrhs, s));
+      continue;
+    }
+    // all columns stopped (or out of iterations): confirm with the true residual
+    std::vector<double> keep_scal(P->w.host_scal, P->w.host_scal + (size_t)nrhs * kScalSlots);
+    CR_CHECK(true_residual(P, nrhs, ninv, w.cg_x, w.cg_b, w.cg_r, rel, s));
+    std::memcpy(P->w.host_scal, keep_scal.data(), keep_scal.size() * sizeof(double));
+    bool restart = false;
+    for (int c = 0; c < nrhs; ++c) {
+      double* sc = P->w.host_scal + c * kScalSlots;
+      const bool broke = sc[S_BREAK] != 0.0;
+      if (!broke && rel[c] > tol && it < maxiter && sc[S_BB] > 0.0) {
+        sc[S_DONE] = 0.0;  // restart this column from its true residual
+        restart = true;
+      } else {
+        sc[S_DONE] = 1.0;
+      }
+    }
+    if (!restart) {
+      finished = true;
+      break;
+    }
+    CR_CHECK(write_scalars(P, nrhs, s));
+    CR_TRY(launch_cg_start(P, nrhs, w.cg_b, w.cg_r, w.cg_z, w.cg_p, w.alm_a, s));
+    CR_TRY(launch_cg_scalars(P, nrhs, 0, nb, tol, 1, s));
+    CR_CHECK(read_scalars(P, nrhs, s));
+  }
+  for (int c = 0; c < nrhs; ++c) {
+    const double* sc = P->w.host_scal + c * kScalSlots;
+    stats[c].iters = (int)sc[S_ITERS];
+    stats[c].refinements = 0;
+    stats[c].rel_resid_true = rel[c];
+    if (sc[S_BREAK] != 0.0 || !std::isfinite(rel[c]))
+      stats[c].status = CR_BREAKDOWN;
+    else if (rel[c] > tol)
+      stats[c].status = CR_NOCONV;
+    else
+      stats[c].status = CR_OK;
+  }
+  return CR_OK;
+}
+
+int solve_core(const crsht_plan* P, const cr_problem* prob, double q, int nrhs, const double* d, const double* w0,
+               const double* w1, const double* rhs, double* s_out, const cr_opts* opts, cr_stats* stats,
+               hipStream_t s) {
+  if (!opts || !stats || !s_out) return CR_EINVAL;
+  if (!(opts->tol > 0.0) || opts->maxiter < 1) return CR_EINVAL;
+  if (opts->prec != CR_F64) return CR_ENOTSUP;
+  const int every = opts->check_every > 0 ? opts->check_every : 8;
+  CR_CHECK(set_problem(P, prob, q, s));
+  CR_CHECK(compute_diag(P, prob->ninv, s));
+  if (rhs)
+    CR_TRY(launch_project(P, nrhs, C2(rhs), P->w.cg_b, s));
+  else
+    CR_CHECK(assemble_rhs(P, nrhs, prob->ninv, d, w0, w1, P->w.cg_b, s));
+  CR_CHECK(pcg_f64(P, nrhs, prob->ninv, opts->tol, opts->maxiter, every, stats, s));
+  CR_TRY(hipMemcpyAsync(s_out, P->w.cg_x, (size_t)nrhs * P->g.nalm * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  CR_TRY(hipStreamSynchronize(s));
+  return CR_OK;
+}
+
+// terms of ln pi into host t[3]: chi^2 of the mean field, a^T S^-1 a, f^T B^T N^-1 B f
+int lnpi_terms(const crsht_plan* P, const double* ninv, const double* d, const double2* ahat, const double2* fhat,
+               double t[3], hipStream_t s) {
+  const int npart = P->w.npart;
+  const int nbp = std::min<int64_t>(npart, (P->g.npix + 255) / 256);
+  const int nba = std::min<int64_t>(npart, (P->g.nalm + 255) / 256);
+  double* pa = P->w.partial;
+  CR_TRY(hipMemsetAsync(pa, 0, 3 * (size_t)npart * sizeof(double), s));
+  // Y B ahat
+  CR_CHECK(synth_f64(P, 1, ahat, P->w.bk, P->w.map_a, s));
+  CR_TRY(launch_pix_wsq(P, ninv, d, P->w.map_a, pa, nbp, s));
+  CR_TRY(launch_alm_wquad(P, P->w.sinv, ahat, pa + npart, nba, s));
+  CR_CHECK(synth_f64(P, 1, fhat, P->w.bk, P->w.map_a, s));
+  CR_TRY(launch_pix_wsq(P, ninv, P->w.map_a, nullptr, pa + 2 * npart, nbp, s));
+  CR_TRY(launch_sum_rows(P, 1, std::max(nbp, nba), s));
+  CR_CHECK(read_scalars(P, 1, s));
+  t[0] = P->w.host_scal[S_AUX0];
+  t[1] = P->w.host_scal[S_AUX1];
+  t[2] = P->w.host_scal[S_AUX2];
+  return CR_OK;
+}
+
+}  // namespace
+
+// ============================================================== transforms
+extern "C" int sht_synth(const crsht_plan* P, int nrhs, const double* alm, double* map, cr_prec prec,
+                         void* stream) {
+  CR_CHECK(check_plan(P, nrhs));
+  if (!alm || !map) return CR_EINVAL;
+  if (prec != CR_F64) return CR_ENOTSUP;
+  return synth_f64(P, nrhs, C2(alm), P->t.rec_kappa, map, S(stream));
+}
+
+extern "C" int sht_synth_adjoint(const crsht_plan* P, int nrhs, const double* map, double* alm, cr_prec prec,
+                                 void* stream) {
+  CR_CHECK(check_plan(P, nrhs));
+  if (!alm || !map) return CR_EINVAL;
+  if (prec != CR_F64) return CR_ENOTSUP;
+  return adjoint_f64(P, nrhs, map, C2(alm), S(stream));
+}
+
+extern "C" int sht_analysis(const crsht_plan* P, int nrhs, const double* map, double* alm, int n_iter,
+                            void* stream) {
+  CR_CHECK(check_plan(P, nrhs));
+  if (!alm || !map || n_iter < 0) return CR_EINVAL;
+  hipStream_t s = S(stream);
+  const double wq = 4.0 * M_PI / (double)P->g.npix;
+  const int64_t na = (int64_t)nrhs * P->g.nalm, np = (int64_t)nrhs * P->g.npix;
+  CR_CHECK(adjoint_f64(P, nrhs, map, C2(alm), s));
+  CR_TRY(launch_alm_axpby(na, wq, C2(alm), 0.0, nullptr, C2(alm), s));
+  for (int it = 0; it < n_iter; ++it) {
+    CR_CHECK(synth_f64(P, nrhs, C2(alm), P->t.rec_kappa, P->w.map_a, s));
+    CR_TRY(launch_map_axpby(np, 1.0, map, -1.0, P->w.map_a, P->w.map_a, s));
+    CR_CHECK(adjoint_f64(P, nrhs, P->w.map_a, P->w.alm_b, s));
+    CR_TRY(launch_alm_axpby(na, 1.0, C2(alm), wq, P->w.alm_b, C2(alm), s));
+  }
+  return CR_OK;
+}
+
+// ============================================================== CR system
+extern "C" int cr_precond(const crsht_plan* P, const cr_problem* prob, double* diag, void* stream) {
+  CR_CHECK(check_plan(P, 1));
+  if (!diag) return CR_EINVAL;
+  hipStream_t s = S(stream);
+  CR_CHECK(set_problem(P, prob, 1.0, s));
+  CR_CHECK(compute_diag(P, prob->ninv, s));
+  CR_TRY(hipMemcpyAsync(diag, P->w.diag, P->g.nalm * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return CR_OK;
+}
+
+extern "C" int cr_rhs(const crsht_plan* P, const cr_problem* prob, int nrhs, const double* d, const double* w0,
+                      const double* w1, double* b, void* stream) {
+  CR_CHECK(check_plan(P, nrhs));
+  if (!b) return CR_EINVAL;
+  hipStream_t s = S(stream);
+  CR_CHECK(set_problem(P, prob, 1.0, s));
+  return assemble_rhs(P, nrhs, prob->ninv, d, w0, w1, C2(b), s);
+}
+
+extern "C" int cr_apply(const crsht_plan* P, const cr_problem* prob, int nrhs, const double* x, double* Ax,
+                        cr_prec prec, void* stream) {
+  CR_CHECK(check_plan(P, nrhs));
+  if (!x || !Ax) return CR_EINVAL;
+  if (prec != CR_F64) return CR_ENOTSUP;
+  hipStream_t s = S(stream);
+  CR_CHECK(set_problem(P, prob, 1.0, s));
+  CR_TRY(launch_project(P, nrhs, C2(x), P->w.alm_b, s));
+  CR_TRY(launch_scale_alm(P, nrhs, P->w.alm_b, P->w.bk, P->w.alm_a, s));
+  return operator_core(P, nrhs, P->w.alm_b, P->w.alm_a, prob->ninv, C2(Ax), s);
+}
+
+extern "C" int cr_solve(const crsht_plan* P, const cr_problem* prob, int nrhs, const double* d, const double* w0,
+                        const double* w1, const double* rhs, double* s_out, const cr_opts* opts, cr_stats* stats,
+                        void* stream) {
+  CR_CHECK(check_plan(P, nrhs));
+  return solve_core(P, prob, 1.0, nrhs, d, w0, w1, rhs, s_out, opts, stats, S(stream));
+}
+
+extern "C" int cr_lnpi(const crsht_plan* P, const cr_problem* fid, double q, const double* d, const double* ahat,
+                       const double* fhat, double* lnpi, void* stream) {
+  CR_CHECK(check_plan(P, 1));
+  if (!d || !ahat || !fhat || !lnpi) return CR_EINVAL;
+  hipStream_t s = S(stream);
+  CR_CHECK(set_problem(P, fid, q, s));
+  double t[3];
+  CR_CHECK(lnpi_terms(P, fid->ninv, d, C2(ahat), C2(fhat), t, s));
+  *lnpi = -0.5 * (t[0] + t[1] + t[2]);
+  return CR_OK;
+}
+
+extern "C" int joint_cl_step(const crsht_plan* P, const cr_problem* fid, const double* d, cr_chain* state,
+                             const cr_draws* dr, const cr_opts* opts, cr_step_out* out, void* stream) {
+  CR_CHECK(check_plan(P, 1));
+  if (!fid || !d || !state || !dr || !opts || !out || !state->ahat || !state->fhat) return CR_EINVAL;
+  if (!(dr->sigma_lnq > 0.0) || !(dr->u > 0.0 && dr->u < 1.0) || !std::isfinite(dr->xi)) return CR_EINVAL;
+  if (!(state->q > 0.0) || !std::isfinite(state->lnpi)) return CR_EINVAL;
+  hipStream_t s = S(stream);
+  std::memset(out, 0, sizeof(*out));
+  const double qn = state->q * std::exp(dr->sigma_lnq * dr->xi);
+  out->q_new = qn;
+  // 1) mean field at q'
+  double* ahat_n = reinterpret_cast<double*>(P->w.alm_c);
+  CR_CHECK(solve_core(P, fid, qn, 1, d, nullptr, nullptr, nullptr, ahat_n, opts, &out->mean_stats, s));
+  // 2) rescaled fluctuation sqrt(q'/q) f
+  const int64_t na = P->g.nalm;
+  CR_TRY(launch_alm_axpby(na, std::sqrt(qn / state->q), C2(state->fhat), 0.0, nullptr, P->w.alm_d, s));
+  // 3) ln pi(q') and ln A (problem factors are still those of q')
+  double t[3];
+  CR_CHECK(lnpi_terms(P, fid->ninv, d, P->w.alm_c, P->w.alm_d, t, s));
+  out->lnpi_new = -0.5 * (t[0] + t[1] + t[2]);
+  out->lnA = out->lnpi_new - state->lnpi + std::log(qn / state->q);
+  out->accepted = std::log(dr->u) < out->lnA ? 1 : 0;
+  if (!out->accepted) return CR_OK;
+  // 4) accepted: fresh fluctuation at q', then ln pi of the new state
+  if (!dr->w0 && !dr->w1) return CR_EINVAL;
+  CR_CHECK(solve_core(P, fid, qn, 1, nullptr, dr->w0, dr->w1, nullptr, state->fhat, opts, &out->fluct_stats, s));
+  CR_TRY(hipMemcpyAsync(state->ahat, P->w.alm_c, na * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  CR_CHECK(lnpi_terms(P, fid->ninv, d, P->w.alm_c, C2(state->fhat), t, s));
+  state->q = qn;
+  state->lnpi = -0.5 * (t[0] + t[1] + t[2]);
+  CR_TRY(hipStreamSynchronize(s));
+  return CR_OK;
+}

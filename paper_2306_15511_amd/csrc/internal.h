@@ -1,0 +1,192 @@
+// Internal declarations shared by the translation units of libcrsht.
+// Nothing here is part of the public C ABI (include/crsht.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <utility>
+#include <vector>
+
+#include "../../include/crsht.h"
+
+namespace crsht {
+
+// Underflow handling of the Legendre recurrence. A recurrence value is carried
+// as v * 2^(kScaleBits * k) with an integer k <= 0. While k < 0 the true value
+// is below 2^-100 (|v| <= 2^500) and contributes nothing at double precision;
+// each time |v| exceeds 2^500 the pair (v_{l-1}, v_l) is multiplied by
+// 2^-kScaleBits and k grows by one. At k == 0 the value is an ordinary double.
+constexpr int kScaleBits = 600;
+constexpr double kRescaleAbove = 0x1p500;     // |v| above this triggers rescaling
+constexpr double kRescaleBy = 0x1p-600;       // 2^-kScaleBits
+
+// Sizes of a plan.
+struct Geometry {
+  int nside = 0, lmax = 0, mmax = 0;
+  int nrings = 0;     // 4 nside - 1
+  int npairs = 0;     // 2 nside: north ring i and its mirror 4 nside - i; the equator is paired with itself
+  int64_t npix = 0;
+  int64_t nalm = 0;   // stored complex coefficients, m-major
+  int fft_max = 0;    // largest FFT length used by the ring kernels (power of two)
+};
+
+// Device-resident tables of a plan (all owned by the plan).
+struct Tables {
+  // per ring pair p (index 0 .. npairs-1; north ring index p, south ring nrings-1-p)
+  double* pair_z = nullptr;        // cos(theta) of the north ring
+  int* pair_nphi = nullptr;        // pixels per ring
+  double* pair_phi0 = nullptr;     // azimuth of the first pixel
+  int64_t* pair_first_n = nullptr; // first pixel of the north ring
+  int64_t* pair_first_s = nullptr; // first pixel of the south ring (== north for the equator)
+  int* pair_fft_len = nullptr;     // FFT length: nphi if a power of two, else Bluestein length
+  int64_t* pair_bs_off = nullptr;  // offset into bs_chirp (nphi entries) / bs_kern (fft_len entries); -1 if unused
+  int64_t* pair_bk_off = nullptr;
+  double2* bs_chirp = nullptr;     // exp(-i pi j^2 / n), j < n
+  double2* bs_kern = nullptr;      // FFT of the conjugate chirp filter, scaled by 1/L
+  double2* twiddle = nullptr;      // exp(-2 pi i j / fft_max), j < fft_max/2
+
+  // Legendre recurrence (scaled form mu_l = lambda_l / kappa_l):
+  //   mu_m = lambda_mm, mu_{m-1} = 0, mu_l = alpha_lm z mu_{l-1} - mu_{l-2} for l > m
+  double* rec_alpha = nullptr;     // [nalm] alpha_lm (index of (l,m)); alpha_{m+1,m} = 1, alpha_mm unused
+  double* rec_kappa = nullptr;     // [nalm] kappa_lm, lambda_lm = kappa_lm mu_lm
+  double* lmm_v = nullptr;         // [mmax+1][npairs] start value mantissa
+  int* lmm_k = nullptr;            // [mmax+1][npairs] start scale index k <= 0
+  int64_t* mstart = nullptr;       // [mmax+2] index of a_{m,m}; mstart[mmax+1] = nalm
+  int* idx_l = nullptr;            // [nalm] l of each stored coefficient
+  int* idx_m = nullptr;            // [nalm] m of each stored coefficient
+};
+
+// Workspace, allocated once at plan creation for nrhs_max columns.
+struct Workspace {
+  double2* eo = nullptr;       // [nrhs][npairs][mmax+1][2]  (E, O) Legendre sums
+  double2* geo = nullptr;      // [nrhs][npairs][mmax+1][2]  (G_N + G_S, G_N - G_S)
+  double2* alm_a = nullptr;    // [nrhs][nalm] scratch a_lm vectors
+  double2* alm_b = nullptr;
+  double2* cg_x = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr, *cg_b = nullptr;
+  double2* cg_d = nullptr;     // refinement correction
+  double2* alm_c = nullptr;    // [nalm] joint-move mean field at the proposal
+  double2* alm_d = nullptr;    // [nalm] joint-move rescaled fluctuation
+  double* map_a = nullptr;     // [nrhs][npix] scratch maps
+  double* ring_w = nullptr;    // [npairs] ring sums of N^-1 (north + south)
+  double* diag = nullptr;      // [nalm] Jacobi diagonal D_lm
+  double* sinv = nullptr;      // [nalm] 1/C_l on kept modes, 0 otherwise
+  double* sinvhalf = nullptr;  // [nalm] C_l^-1/2
+  double* bk = nullptr;        // [nalm] b_l kappa_lm on kept modes
+  double* perl = nullptr;      // [4][lmax+1] per-l 1/C_l, C_l^-1/2, b_l, keep (device)
+  double* partial = nullptr;   // [nrhs][npart] block partial sums
+  double* scal = nullptr;      // [nrhs][kScalSlots] CG scalars
+  double* host_scal = nullptr; // pinned mirror of scal
+  int npart = 0;
+};
+
+constexpr int kScalSlots = 16;
+// slots of the per-column scalar block
+enum ScalSlot {
+  S_RZ = 0,      // <r, z>
+  S_PQ = 1,      // <p, A p>
+  S_ALPHA = 2,
+  S_BETA = 3,
+  S_RR = 4,      // <r, r>
+  S_BB = 5,      // <b, b>
+  S_DONE = 6,    // 1 when the column has converged (or broken down)
+  S_REL = 7,     // last relative residual
+  S_ITERS = 8,   // iterations taken
+  S_BREAK = 9,   // 1 on breakdown
+  S_RZ_NEW = 10,
+  S_AUX0 = 11,
+  S_AUX1 = 12,
+  S_AUX2 = 13,
+};
+
+constexpr int kTimedKernels = 3;  // 0 Legendre synthesis, 1 Legendre adjoint, 2 ring pass
+struct Timing {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events[kTimedKernels];
+  hipEvent_t open[kTimedKernels] = {nullptr, nullptr, nullptr};
+  hipEvent_t open_end[kTimedKernels] = {nullptr, nullptr, nullptr};
+  double total_ms[kTimedKernels] = {0, 0, 0};
+  int64_t count[kTimedKernels] = {0, 0, 0};
+};
+
+}  // namespace crsht
+
+struct crsht_plan {
+  crsht::Geometry g;
+  int ncomp = 1;
+  int nrhs_max = 1;
+  int device = 0;
+  int64_t workspace_bytes_ = 0;
+  crsht::Tables t;
+  crsht::Workspace w;
+  crsht::Timing timing;
+  // host copies used for argument checks and bookkeeping
+  std::vector<int> h_nphi;
+  std::vector<int64_t> h_first;
+  std::vector<double> h_z, h_phi0;
+};
+
+namespace crsht {
+
+// ---- timing (timing.cpp) ----
+void timing_begin(const crsht_plan* P, int id, hipStream_t s);
+void timing_end(const crsht_plan* P, int id, hipStream_t s);
+void timing_clear(crsht_plan* P);
+
+// ---- Legendre step (legendre.hip) ----
+// Synthesis: eo[c][p][m] = (E, O) with E/O the sums over l of even/odd (l-m)
+// of mu_lm(z_p) * alms[c][idx(l,m)], alms already multiplied by kappa (and
+// whatever diagonal factor the caller folds in).
+hipError_t launch_legendre_synth(const crsht_plan* P, int nrhs, const double2* alms, double2* eo,
+                                 hipStream_t s);
+// Adjoint: raw[c][idx(l,m)] = sum_p mu_lm(z_p) * (G_E or G_O by parity)[c][p][m].
+// mode 0: out = s * raw with s = sinv if non-NULL (any per-index factor, e.g.
+//   b_l kappa_lm for B Y^T), else kappa (plain Y^T);
+// mode 1: CG operator epilogue out = sinv * pin + bk * raw, and the partial
+//   <pin, out> of block m at partial[c * 4 * npart + m];
+// square: D = sinv + bk^2 * sum mu^2 W_p (preconditioner diagonal) into
+//   (double*)out, 1 where the mode is not kept.
+hipError_t launch_legendre_adjoint(const crsht_plan* P, int nrhs, const double2* geo, double2* out,
+                                   int mode, const double2* pin, const double* sinv, const double* bk,
+                                   double* partial, bool square, hipStream_t s);
+
+// ---- ring step (ring.hip) ----
+// mode SYNTH: eo -> map;  ADJOINT: map -> geo;  FUSED: eo -> (map * ninv) -> geo
+enum RingMode { RING_SYNTH = 0, RING_ADJOINT = 1, RING_FUSED = 2 };
+hipError_t launch_ring(const crsht_plan* P, int nrhs, RingMode mode, const double2* eo, double* map,
+                       const double* ninv, double2* geo, hipStream_t s);
+size_t ring_lds_bytes(const crsht_plan* P);
+
+// ---- vector kernels (vec.hip) ----
+// Reductions write per-block partial sums to w.partial (column c, row r at
+// partial[(c * 4 + r) * npart + block]) and a one-block kernel sums them.
+int vec_reduce_blocks(const crsht_plan* P);
+hipError_t launch_expand(const crsht_plan* P, const double* perl, hipStream_t s);
+hipError_t launch_scale_alm(const crsht_plan* P, int nrhs, const double2* in, const double* f, double2* out,
+                            hipStream_t s);
+hipError_t launch_ring_weights(const crsht_plan* P, const double* ninv, double* w, hipStream_t s);
+hipError_t launch_pix_rhs(const crsht_plan* P, int nrhs, const double* ninv, const double* d, const double* w1,
+                          double* u, hipStream_t s);
+hipError_t launch_rhs_finish(const crsht_plan* P, int nrhs, const double2* raw, const double2* w0, double2* out,
+                             hipStream_t s);
+hipError_t launch_project(const crsht_plan* P, int nrhs, const double2* x, double2* out, hipStream_t s);
+hipError_t launch_map_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out,
+                            hipStream_t s);
+hipError_t launch_alm_axpby(int64_t n, double a, const double2* x, double b, const double2* y, double2* out,
+                            hipStream_t s);
+hipError_t launch_cg_start(const crsht_plan* P, int nrhs, const double2* b, const double2* r, double2* z,
+                           double2* p, double2* pt, hipStream_t s);
+hipError_t launch_cg_scalars(const crsht_plan* P, int nrhs, int what, int nb, double tol, int restart,
+                             hipStream_t s);
+hipError_t launch_cg_update(const crsht_plan* P, int nrhs, double2* x, double2* r, double2* z, const double2* p,
+                            const double2* q, hipStream_t s);
+hipError_t launch_cg_pupdate(const crsht_plan* P, int nrhs, const double2* z, double2* p, double2* pt,
+                             hipStream_t s);
+hipError_t launch_residual(const crsht_plan* P, int nrhs, const double2* b, const double2* ax, double2* r,
+                           hipStream_t s);
+hipError_t launch_sum_rows(const crsht_plan* P, int nrhs, int nb, hipStream_t s);
+hipError_t launch_pix_wsq(const crsht_plan* P, const double* w, const double* x, const double* y, double* partial,
+                          int nb, hipStream_t s);
+hipError_t launch_alm_wquad(const crsht_plan* P, const double* f, const double2* a, double* partial, int nb,
+                            hipStream_t s);
+
+}  // namespace crsht

@@ -1,0 +1,488 @@
+// Elementwise and reduction kernels on a_lm vectors and maps: problem set-up,
+// right-hand-side assembly, the vector part of preconditioned conjugate
+// gradients (Shewchuk 1994, PCG with a diagonal preconditioner), and FP64
+// reductions in a fixed order (block partial sums, then one block summing the
+// partials), so results are run-to-run reproducible.
+#include "internal.h"
+
+namespace crsht {
+namespace {
+
+constexpr int kVecBlock = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  // fixed-order tree reduction over the block
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// per-index problem arrays from per-l arrays:
+// sinv = keep/C_l, sinvhalf = keep/sqrt(C_l), bk = keep b_l kappa_lm
+__global__ void k_expand(int64_t nalm, const int* __restrict__ idx_l, const double* __restrict__ kappa,
+                         const double* __restrict__ perl, int lmax, double* __restrict__ sinv,
+                         double* __restrict__ sinvhalf, double* __restrict__ bk) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nalm) return;
+  const int l = idx_l[i];
+  const double keep = perl[3 * (lmax + 1) + l];
+  sinv[i] = perl[l];
+  sinvhalf[i] = perl[(lmax + 1) + l];
+  bk[i] = keep * perl[2 * (lmax + 1) + l] * kappa[i];
+}
+
+__global__ void k_scale(int64_t nalm, int nrhs, const double2* __restrict__ in, const double* __restrict__ f,
+                        double2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nalm) return;
+  const double s = f[i];
+  for (int c = 0; c < nrhs; ++c) {
+    const double2 v = in[c * nalm + i];
+    out[c * nalm + i] = make_double2(s * v.x, s * v.y);
+  }
+}
+
+__global__ void k_ring_weights(int npairs, const int* __restrict__ nphi, const int64_t* __restrict__ fn,
+                               const int64_t* __restrict__ fs, const double* __restrict__ ninv,
+                               double* __restrict__ w) {
+  __shared__ double sh[kVecBlock];
+  const int p = blockIdx.x;
+  const int n = nphi[p];
+  const bool eq = fn[p] == fs[p];
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    acc += ninv[fn[p] + j];
+    if (!eq) acc += ninv[fs[p] + j];
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) w[p] = acc;
+}
+
+// u = ninv * d + sqrt(ninv) * w1 (either may be absent)
+__global__ void k_pix_rhs(int64_t npix, int nrhs, const double* __restrict__ ninv, const double* __restrict__ d,
+                          const double* __restrict__ w1, double* __restrict__ u) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npix) return;
+  const double n = ninv[i];
+  const double sn = sqrt(n);
+  for (int c = 0; c < nrhs; ++c) {
+    double v = 0.0;
+    if (d) v = n * d[c * npix + i];
+    if (w1) v = fma(sn, w1[c * npix + i], v);
+    u[c * npix + i] = v;
+  }
+}
+
+// out = braw + sinvhalf * w0 (either may be absent); braw = B Y^T u already
+// scaled; Im of m = 0 forced to 0
+__global__ void k_rhs_finish(int64_t nalm, int nrhs, const int* __restrict__ idx_m, const double* __restrict__ bk,
+                             const double* __restrict__ sinvhalf, const double2* __restrict__ raw,
+                             const double2* __restrict__ w0, double2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nalm) return;
+  const double sh = sinvhalf[i];
+  const bool m0 = idx_m[i] == 0;
+  for (int c = 0; c < nrhs; ++c) {
+    double2 v = raw ? raw[c * nalm + i] : make_double2(0.0, 0.0);
+    if (w0) {
+      const double2 w = w0[c * nalm + i];
+      v.x = fma(sh, w.x, v.x);
+      v.y = fma(sh, w.y, v.y);
+    }
+    if (m0) v.y = 0.0;
+    out[c * nalm + i] = v;
+  }
+}
+
+// out = x on kept modes (sinv > 0), 0 elsewhere, Im of m = 0 set to 0
+__global__ void k_project(int64_t nalm, int nrhs, const int* __restrict__ idx_m, const double* __restrict__ sinv,
+                          const double2* __restrict__ x, double2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nalm) return;
+  const bool keep = sinv[i] > 0.0;
+  const bool m0 = idx_m[i] == 0;
+  for (int c = 0; c < nrhs; ++c) {
+    double2 v = keep ? x[c * nalm + i] : make_double2(0.0, 0.0);
+    if (m0) v.y = 0.0;
+    out[c * nalm + i] = v;
+  }
+}
+
+// map = a - b (for analysis corrections), and map *= s
+__global__ void k_map_axpby(int64_t n, double a, const double* __restrict__ x, double b,
+                            const double* __restrict__ y, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = a * x[i] + (y ? b * y[i] : 0.0);
+}
+
+__global__ void k_alm_axpby(int64_t n, double a, const double2* __restrict__ x, double b,
+                            const double2* __restrict__ y, double2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 u = x[i];
+  double2 v = make_double2(a * u.x, a * u.y);
+  if (y) {
+    const double2 w = y[i];
+    v.x = fma(b, w.x, v.x);
+    v.y = fma(b, w.y, v.y);
+  }
+  out[i] = v;
+}
+
+// ---------------------------------------------------------------- PCG pieces
+// weighted dot partials of one column: w_m (a.x c.x + a.y c.y)
+__device__ __forceinline__ double wdot(int m, double2 a, double2 c) {
+  return (m == 0 ? 1.0 : 2.0) * fma(a.x, c.x, a.y * c.y);
+}
+
+// start: x = 0 (or given), r = b - A x0 computed by caller in r, z = r / D,
+// p = z, pt = bk * p; partial sums of <r,z>, <r,r>, <b,b>
+__global__ void k_cg_start(int64_t nalm, const int* __restrict__ idx_m, const double* __restrict__ diag,
+                           const double* __restrict__ bk, const double2* __restrict__ b,
+                           const double2* __restrict__ r, double2* __restrict__ z, double2* __restrict__ p,
+                           double2* __restrict__ pt, double* __restrict__ partial, int npart,
+                           const double* __restrict__ scal) {
+  __shared__ double sh[kVecBlock];
+  const int c = blockIdx.y;
+  double rz = 0.0, rr = 0.0, bb = 0.0;
+  {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nalm; i += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t ci = c * nalm + i;
+      const int m = idx_m[i];
+      const double2 rv = r[ci];
+      const double dinv = 1.0 / diag[i];
+      double2 zv = make_double2(rv.x * dinv, rv.y * dinv);
+      z[ci] = zv;
+      p[ci] = zv;
+      pt[ci] = make_double2(bk[i] * zv.x, bk[i] * zv.y);
+      rz += wdot(m, rv, zv);
+      rr += wdot(m, rv, rv);
+      bb += wdot(m, b[ci], b[ci]);
+    }
+  }
+  rz = block_sum(rz, sh);
+  rr = block_sum(rr, sh);
+  bb = block_sum(bb, sh);
+  if (threadIdx.x == 0) {
+    double* pa = partial + (size_t)c * npart * 4;
+    pa[blockIdx.x] = rz;
+    pa[npart + blockIdx.x] = rr;
+    pa[2 * npart + blockIdx.x] = bb;
+  }
+}
+
+// sums partial[c][slot-row][0..nb) into scal; what = 0: start, 1: alpha, 2: beta
+__global__ void k_cg_scalars(int what, int nb, const double* __restrict__ partial, int npart,
+                             double* __restrict__ scal, double tol, int restart) {
+  __shared__ double sh[kVecBlock];
+  const int c = blockIdx.x;
+  const double* pa = partial + (size_t)c * npart * 4;
+  double* sc = scal + c * kScalSlots;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    s0 += pa[i];
+    if (what != 1) {
+      s1 += pa[npart + i];
+      s2 += pa[2 * npart + i];
+    }
+  }
+  s0 = block_sum(s0, sh);
+  s1 = block_sum(s1, sh);
+  s2 = block_sum(s2, sh);
+  if (threadIdx.x != 0) return;
+  if (what == 0) {  // after k_cg_start: fresh start, or restart of the columns not done
+    if (restart && sc[S_DONE] != 0.0) return;
+    sc[S_RZ] = s0;
+    sc[S_RR] = s1;
+    if (!restart) {
+      sc[S_BB] = s2;
+      sc[S_ITERS] = 0.0;
+      sc[S_BREAK] = 0.0;
+    }
+    const double bb = sc[S_BB];
+    sc[S_REL] = bb > 0.0 ? sqrt(s1 / bb) : 0.0;
+    sc[S_DONE] = (bb == 0.0) ? 1.0 : 0.0;
+  } else if (what == 1) {  // alpha = <r,z>/<p,Ap>
+    if (sc[S_DONE] != 0.0) return;
+    sc[S_PQ] = s0;
+    if (!(s0 > 0.0) || !isfinite(s0) || !isfinite(sc[S_RZ])) {
+      sc[S_BREAK] = 1.0;
+      sc[S_DONE] = 1.0;
+      sc[S_ALPHA] = 0.0;
+    } else {
+      sc[S_ALPHA] = sc[S_RZ] / s0;
+    }
+  } else {  // beta after the update
+    if (sc[S_DONE] != 0.0) return;
+    const double rznew = s0, rr = s1;
+    sc[S_ITERS] += 1.0;
+    sc[S_BETA] = rznew / sc[S_RZ];
+    sc[S_RZ] = rznew;
+    sc[S_RR] = rr;
+    sc[S_REL] = sqrt(rr / sc[S_BB]);
+    if (!isfinite(rr)) {
+      sc[S_BREAK] = 1.0;
+      sc[S_DONE] = 1.0;
+    } else if (sc[S_REL] <= tol) {
+      sc[S_DONE] = 1.0;
+    }
+  }
+}
+
+// x += alpha p; r -= alpha q; z = r / D; partial <r,z>, <r,r>
+__global__ void k_cg_update(int64_t nalm, const int* __restrict__ idx_m, const double* __restrict__ diag,
+                            const double* __restrict__ bk, double2* __restrict__ x, double2* __restrict__ r,
+                            double2* __restrict__ z, const double2* __restrict__ p, const double2* __restrict__ q,
+                            double* __restrict__ partial, int npart, const double* __restrict__ scal) {
+  __shared__ double sh[kVecBlock];
+  const int c = blockIdx.y;
+  const double* sc = scal + c * kScalSlots;
+  const bool skip = sc[S_DONE] != 0.0;
+  const double a = sc[S_ALPHA];
+  double rz = 0.0, rr = 0.0;
+  if (!skip) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nalm; i += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t ci = c * nalm + i;
+      const int m = idx_m[i];
+      const double2 pv = p[ci], qv = q[ci];
+      double2 xv = x[ci], rv = r[ci];
+      xv.x = fma(a, pv.x, xv.x);
+      xv.y = fma(a, pv.y, xv.y);
+      rv.x = fma(-a, qv.x, rv.x);
+      rv.y = fma(-a, qv.y, rv.y);
+      x[ci] = xv;
+      r[ci] = rv;
+      const double dinv = 1.0 / diag[i];
+      const double2 zv = make_double2(rv.x * dinv, rv.y * dinv);
+      z[ci] = zv;
+      rz += wdot(m, rv, zv);
+      rr += wdot(m, rv, rv);
+    }
+  }
+  rz = block_sum(rz, sh);
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    double* pa = partial + (size_t)c * npart * 4;
+    pa[blockIdx.x] = rz;
+    pa[npart + blockIdx.x] = rr;
+  }
+}
+
+// p = z + beta p; pt = bk p
+__global__ void k_cg_pupdate(int64_t nalm, const double* __restrict__ bk, const double2* __restrict__ z,
+                             double2* __restrict__ p, double2* __restrict__ pt, const double* __restrict__ scal) {
+  const int c = blockIdx.y;
+  const double* sc = scal + c * kScalSlots;
+  if (sc[S_DONE] != 0.0) return;
+  const double beta = sc[S_BETA];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nalm; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ci = c * nalm + i;
+    const double2 zv = z[ci];
+    double2 pv = p[ci];
+    pv.x = fma(beta, pv.x, zv.x);
+    pv.y = fma(beta, pv.y, zv.y);
+    p[ci] = pv;
+    pt[ci] = make_double2(bk[i] * pv.x, bk[i] * pv.y);
+  }
+}
+
+// r = b - Ax; partial <r,r> into row 1 (row 0: <r,r> as well)
+__global__ void k_residual(int64_t nalm, const int* __restrict__ idx_m, const double2* __restrict__ b,
+                           const double2* __restrict__ ax, double2* __restrict__ r, double* __restrict__ partial,
+                           int npart) {
+  __shared__ double sh[kVecBlock];
+  const int c = blockIdx.y;
+  double rr = 0.0, bb = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nalm; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ci = c * nalm + i;
+    const int m = idx_m[i];
+    const double2 bv = b[ci], av = ax[ci];
+    const double2 rv = make_double2(bv.x - av.x, bv.y - av.y);
+    r[ci] = rv;
+    rr += wdot(m, rv, rv);
+    bb += wdot(m, bv, bv);
+  }
+  rr = block_sum(rr, sh);
+  bb = block_sum(bb, sh);
+  if (threadIdx.x == 0) {
+    double* pa = partial + (size_t)c * npart * 4;
+    pa[blockIdx.x] = rr;
+    pa[npart + blockIdx.x] = bb;
+    pa[2 * npart + blockIdx.x] = 0.0;
+  }
+}
+
+// sum rows 0, 1, 2 of the partials of column c into scal[c][AUX0..AUX2]
+__global__ void k_sum_rows(int nb, const double* __restrict__ partial, int npart, double* __restrict__ scal) {
+  __shared__ double sh[kVecBlock];
+  const int c = blockIdx.x;
+  const double* pa = partial + (size_t)c * npart * 4;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    s0 += pa[i];
+    s1 += pa[npart + i];
+    s2 += pa[2 * npart + i];
+  }
+  s0 = block_sum(s0, sh);
+  s1 = block_sum(s1, sh);
+  s2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    scal[c * kScalSlots + S_AUX0] = s0;
+    scal[c * kScalSlots + S_AUX1] = s1;
+    scal[c * kScalSlots + S_AUX2] = s2;
+  }
+}
+
+// sum_p ninv (a - b)^2 style pixel reductions: partial of sum w x^2 (w may be null -> 1)
+__global__ void k_pix_wsq(int64_t npix, const double* __restrict__ w, const double* __restrict__ x,
+                          const double* __restrict__ y, double* __restrict__ partial) {
+  __shared__ double sh[kVecBlock];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = y ? x[i] - y[i] : x[i];
+    acc = fma(w ? w[i] * v : v, v, acc);
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// partial of w_m a^T (f a) (f per index)
+__global__ void k_alm_wquad(int64_t nalm, const int* __restrict__ idx_m, const double* __restrict__ f,
+                            const double2* __restrict__ a, double* __restrict__ partial) {
+  __shared__ double sh[kVecBlock];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nalm; i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 v = a[i];
+    acc += f[i] * wdot(idx_m[i], v, v);
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+int nblocks(int64_t n) {
+  int64_t b = (n + kVecBlock - 1) / kVecBlock;
+  return (int)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+int vec_reduce_blocks(const crsht_plan* P) {
+  int64_t b = (P->g.nalm + kVecBlock - 1) / kVecBlock;
+  int cap = P->w.npart;
+  if (cap > 1024) cap = 1024;
+  return (int)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+hipError_t launch_expand(const crsht_plan* P, const double* perl, hipStream_t s) {
+  hipLaunchKernelGGL(k_expand, dim3(nblocks(P->g.nalm)), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_l,
+                     P->t.rec_kappa, perl, P->g.lmax, P->w.sinv, P->w.sinvhalf, P->w.bk);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_alm(const crsht_plan* P, int nrhs, const double2* in, const double* f, double2* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(nblocks(P->g.nalm)), dim3(kVecBlock), 0, s, P->g.nalm, nrhs, in, f, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ring_weights(const crsht_plan* P, const double* ninv, double* w, hipStream_t s) {
+  hipLaunchKernelGGL(k_ring_weights, dim3(P->g.npairs), dim3(kVecBlock), 0, s, P->g.npairs, P->t.pair_nphi,
+                     P->t.pair_first_n, P->t.pair_first_s, ninv, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_pix_rhs(const crsht_plan* P, int nrhs, const double* ninv, const double* d, const double* w1,
+                          double* u, hipStream_t s) {
+  hipLaunchKernelGGL(k_pix_rhs, dim3(nblocks(P->g.npix)), dim3(kVecBlock), 0, s, P->g.npix, nrhs, ninv, d, w1, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_finish(const crsht_plan* P, int nrhs, const double2* raw, const double2* w0, double2* out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_rhs_finish, dim3(nblocks(P->g.nalm)), dim3(kVecBlock), 0, s, P->g.nalm, nrhs, P->t.idx_m,
+                     P->w.bk, P->w.sinvhalf, raw, w0, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(const crsht_plan* P, int nrhs, const double2* x, double2* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_project, dim3(nblocks(P->g.nalm)), dim3(kVecBlock), 0, s, P->g.nalm, nrhs, P->t.idx_m,
+                     P->w.sinv, x, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_map_axpby, dim3(nblocks(n)), dim3(kVecBlock), 0, s, n, a, x, b, y, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_alm_axpby(int64_t n, double a, const double2* x, double b, const double2* y, double2* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_alm_axpby, dim3(nblocks(n)), dim3(kVecBlock), 0, s, n, a, x, b, y, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_start(const crsht_plan* P, int nrhs, const double2* b, const double2* r, double2* z,
+                           double2* p, double2* pt, hipStream_t s) {
+  const int nb = vec_reduce_blocks(P);
+  hipLaunchKernelGGL(k_cg_start, dim3(nb, nrhs), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_m, P->w.diag,
+                     P->w.bk, b, r, z, p, pt, P->w.partial, P->w.npart, P->w.scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_scalars(const crsht_plan* P, int nrhs, int what, int nb, double tol, int restart,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_scalars, dim3(nrhs), dim3(kVecBlock), 0, s, what, nb, P->w.partial, P->w.npart,
+                     P->w.scal, tol, restart);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(const crsht_plan* P, int nrhs, double2* x, double2* r, double2* z, const double2* p,
+                            const double2* q, hipStream_t s) {
+  const int nb = vec_reduce_blocks(P);
+  hipLaunchKernelGGL(k_cg_update, dim3(nb, nrhs), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_m, P->w.diag,
+                     P->w.bk, x, r, z, p, q, P->w.partial, P->w.npart, P->w.scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_pupdate(const crsht_plan* P, int nrhs, const double2* z, double2* p, double2* pt,
+                             hipStream_t s) {
+  const int nb = vec_reduce_blocks(P);
+  hipLaunchKernelGGL(k_cg_pupdate, dim3(nb, nrhs), dim3(kVecBlock), 0, s, P->g.nalm, P->w.bk, z, p, pt,
+                     P->w.scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const crsht_plan* P, int nrhs, const double2* b, const double2* ax, double2* r,
+                           hipStream_t s) {
+  const int nb = vec_reduce_blocks(P);
+  hipLaunchKernelGGL(k_residual, dim3(nb, nrhs), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_m, b, ax, r,
+                     P->w.partial, P->w.npart);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_rows(const crsht_plan* P, int nrhs, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_rows, dim3(nrhs), dim3(kVecBlock), 0, s, nb, P->w.partial, P->w.npart, P->w.scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_pix_wsq(const crsht_plan* P, const double* w, const double* x, const double* y, double* partial,
+                          int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_pix_wsq, dim3(nb), dim3(kVecBlock), 0, s, P->g.npix, w, x, y, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_alm_wquad(const crsht_plan* P, const double* f, const double2* a, double* partial, int nb,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_alm_wquad, dim3(nb), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_m, f, a, partial);
+  return hipGetLastError();
+}
+
+}  // namespace crsht

@@ -1,0 +1,134 @@
+"""GPU parity of the constrained-realization pieces (C ABI) against the oracle:
+Jacobi diagonal, right-hand side, operator, PCG solves (dense Cholesky at small
+Nside, oracle residual at larger), batched columns, special cases, status."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import crinputs as ci
+from oracle import cr, dense, healpix
+from tests.gpu_helpers import masked_problem, real_rel, rel, tc
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def _m():
+    from paper_2306_15511_amd import crsht as m
+    return m
+
+
+def _gpu_problem(m, P):
+    return m.Problem(P.cl, P.bl, tc(P.ninv), P.lmin)
+
+
+@pytest.mark.parametrize("nside", [4, 8, 32])
+def test_precond_rhs_apply(nside):
+    m = _m()
+    print("case", nside, flush=True)
+    wl, P, op, d = masked_problem(nside)
+    plan = m.Plan(nside, wl.lmax, nrhs_max=2)
+    gp = _gpu_problem(m, P)
+    assert rel(m.precond(plan, gp).cpu().numpy(), op.diag()) < TOL
+    w0, w1 = wl.w0(), wl.w1()
+    for args in ((d, w0, w1), (d, None, None), (None, w0, None), (None, None, w1)):
+        ref = op.rhs(*args)
+        got = m.rhs(plan, gp, *[None if v is None else tc(v) for v in args]).cpu().numpy()[0]
+        assert rel(got, ref) < TOL
+    rng = np.random.default_rng(5)
+    X = np.stack([ci.white_alm(rng, wl.lmax) for _ in range(2)])
+    got = m.apply(plan, gp, tc(X)).cpu().numpy()
+    for c in range(2):
+        assert rel(got[c], op.apply(X[c])) < TOL
+
+
+@pytest.mark.parametrize("nside", [4, 8])
+def test_solve_matches_dense_cholesky(nside):
+    m = _m()
+    wl, P, op, d = masked_problem(nside)
+    plan = m.Plan(nside, wl.lmax)
+    gp = _gpu_problem(m, P)
+    w0, w1 = wl.w0(), wl.w1()
+    s, st = m.solve(plan, gp, tc(d), tc(w0), tc(w1), tol=1e-13, maxiter=5000)
+    assert st[0].status == 0 and st[0].rel_resid_true <= 1e-13
+    D = dense.DenseY(nside, wl.lmax, lmin=2)
+    ref = D.cr_solve(P.cl, P.bl, P.ninv, op.rhs(d, w0, w1))
+    assert real_rel(op, s.cpu().numpy()[0], ref) < TOL
+
+
+def test_solve_nside32_oracle_residual_and_iterations():
+    m = _m()
+    nside = 32
+    wl, P, op, d = masked_problem(nside)
+    plan = m.Plan(nside, wl.lmax)
+    gp = _gpu_problem(m, P)
+    w0, w1 = wl.w0(), wl.w1()
+    s, st = m.solve(plan, gp, tc(d), tc(w0), tc(w1), tol=1e-8, maxiter=20000)
+    x = s.cpu().numpy()[0]
+    b = op.rhs(d, w0, w1)
+    res = real_rel(op, op.apply(x), b)       # oracle-evaluated residual of the GPU solution
+    assert res <= 1.5e-8
+    assert abs(res - st[0].rel_resid_true) < 1e-10
+    xo, info = cr.pcg(op, b, 1e-8, 20000)
+    assert abs(info.iters - st[0].iters) <= max(2, info.iters // 50)
+    print("iters gpu", st[0].iters, "oracle", info.iters, "diff", real_rel(op, x, xo), flush=True)
+    assert real_rel(op, x, xo) < 1e-5
+
+
+def test_batched_columns_independent():
+    m = _m()
+    nside = 8
+    wl, P, op, d = masked_problem(nside)
+    plan = m.Plan(nside, wl.lmax, nrhs_max=3)
+    gp = _gpu_problem(m, P)
+    rng = np.random.default_rng(9)
+    W0 = np.stack([ci.white_alm(rng, wl.lmax) for _ in range(3)])
+    W1 = np.stack([rng.standard_normal(P.ninv.size) for _ in range(3)])
+    D3 = np.stack([d, 2 * d, -d])
+    s, st = m.solve(plan, gp, tc(D3), tc(W0), tc(W1), nrhs=3, tol=1e-12)
+    Dd = dense.DenseY(nside, wl.lmax, lmin=2)
+    for c in range(3):
+        ref = Dd.cr_solve(P.cl, P.bl, P.ninv, op.rhs(D3[c], W0[c], W1[c]))
+        assert st[c].status == 0
+        assert real_rel(op, s.cpu().numpy()[c], ref) < 1e-9
+
+
+def test_fully_masked_gives_prior_draw():
+    m = _m()
+    nside = 8
+    wl, P, op, d = masked_problem(nside)
+    plan = m.Plan(nside, wl.lmax)
+    gp = m.Problem(P.cl, P.bl, torch.zeros(P.ninv.size, dtype=torch.float64, device="cuda"), 2)
+    w0 = wl.w0()
+    s, st = m.solve(plan, gp, tc(d), tc(w0), tc(wl.w1()), tol=1e-14)
+    ref = op.project(op.shalf * w0)
+    assert rel(s.cpu().numpy()[0], ref) < 1e-12
+
+
+def test_rhs_override_and_nonconvergence_status():
+    m = _m()
+    nside = 8
+    wl, P, op, d = masked_problem(nside)
+    plan = m.Plan(nside, wl.lmax)
+    gp = _gpu_problem(m, P)
+    b = op.rhs(d, wl.w0(), wl.w1())
+    s, st = m.solve(plan, gp, rhs_vec=tc(b[None, :]), tol=1e-12)
+    Dd = dense.DenseY(nside, wl.lmax, lmin=2)
+    assert real_rel(op, s.cpu().numpy()[0], Dd.cr_solve(P.cl, P.bl, P.ninv, b)) < 1e-9
+    s1, st1 = m.solve(plan, gp, rhs_vec=tc(b[None, :]), tol=1e-12, maxiter=1)
+    assert st1[0].status == m.CR_NOCONV and st1[0].iters == 1
+
+
+def test_invalid_spectrum_rejected():
+    m = _m()
+    nside = 4
+    wl, P, op, d = masked_problem(nside)
+    plan = m.Plan(nside, wl.lmax)
+    cl = P.cl.copy()
+    cl[5] = -1.0
+    gp = m.Problem(cl, P.bl, tc(P.ninv), 2)
+    with pytest.raises(m.CrshtError):
+        m.solve(plan, gp, tc(d))
+    _ = math, healpix
