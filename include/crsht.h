@@ -34,9 +34,9 @@
  *   - A plan owns its tables and workspace (allocated at creation, sized for
  *     nrhs_max columns); calls allocate nothing.
  *   - `stream` is a hipStream_t (NULL = the legacy default stream). Transforms
- *     and cr_apply are asynchronous on it. cr_solve, cr_rhs_and_solve style
- *     calls and joint_cl_step synchronise `stream` (they read convergence
- *     scalars); their outputs are complete when they return.
+ *     and cr_apply are asynchronous on it. cr_solve, cr_lnpi and
+ *     joint_cl_step synchronise `stream` (they read convergence scalars);
+ *     their outputs are complete when they return.
  *   - A plan is not thread-safe: concurrent calls need distinct plans.
  *
  * Errors: functions return CR_OK (0) or a negative code detected before or
@@ -72,7 +72,7 @@ typedef struct crsht_plan crsht_plan;
 typedef enum { CR_F64 = 0, CR_MIXED = 1 } cr_prec;
 
 /* Create a plan for HEALPix resolution nside (power of two not required,
- * 1 <= nside <= 8192), band limit lmax >= 0 and mmax (<= lmax; pass -1 for
+ * 1 <= nside <= 1024; larger nside returns CR_ENOTSUP), band limit lmax >= 0 and mmax (<= lmax; pass -1 for
  * mmax = lmax), ncomp = 1 (temperature), for up to nrhs_max >= 1 columns per
  * call. Builds the ring table (Gorski et al. 2005), the recurrence tables of
  * lambda_lm (paper App. A normalisation) and the per-ring FFT tables, and

@@ -16,7 +16,7 @@ from dataclasses import dataclass
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcrsht.so")
+LIB_PATH = os.environ.get("CRSHT_LIB") or os.path.join(_HERE, "libcrsht.so")
 
 CR_OK, CR_EINVAL, CR_ENOMEM, CR_EDEVICE, CR_ENOTSUP = 0, -1, -2, -3, -4
 CR_NOCONV, CR_BREAKDOWN = 1, 2

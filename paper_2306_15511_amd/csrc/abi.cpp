@@ -64,21 +64,23 @@ int set_problem(const crsht_plan* P, const cr_problem* prob, double q, hipStream
   return CR_OK;
 }
 
-// A x for x already projected; pt = bk * x must be in w.alm_a.
-// out = sinv * x + bk * (Y^T N^-1 Y)(pt); partials of <x, out> per m.
+// A x for x already projected; pt = bk * x must be in w.alm_a. Uses w.eo,
+// w.geo and w.alm_b as scratch (x must not live there).
+// out = sinv * x + bk * (Y^T N^-1 Y)(pt); block partials of <x, out> in row 0.
 int operator_core(const crsht_plan* P, int nrhs, const double2* x, const double2* pt, const double* ninv,
                   double2* out, hipStream_t s) {
   CR_TRY(launch_legendre_synth(P, nrhs, pt, P->w.eo, s));
   CR_TRY(launch_ring(P, nrhs, RING_FUSED, P->w.eo, nullptr, ninv, P->w.geo, s));
-  CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, out, 1, x, P->w.sinv, P->w.bk, P->w.partial, false, s));
+  CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, P->w.alm_b, false, s));
+  CR_TRY(launch_cg_q(P, nrhs, x, P->w.alm_b, out, s));
   return CR_OK;
 }
 
 // Jacobi diagonal into w.diag
 int compute_diag(const crsht_plan* P, const double* ninv, hipStream_t s) {
   CR_TRY(launch_ring_weights(P, ninv, P->w.ring_w, s));
-  CR_TRY(launch_legendre_adjoint(P, 1, nullptr, reinterpret_cast<double2*>(P->w.diag), 2, nullptr, P->w.sinv,
-                                 P->w.bk, nullptr, true, s));
+  CR_TRY(launch_legendre_adjoint(P, 1, nullptr, P->w.alm_b, true, s));
+  CR_TRY(launch_diag(P, P->w.alm_b, P->w.diag, s));
   return CR_OK;
 }
 
@@ -89,7 +91,7 @@ int assemble_rhs(const crsht_plan* P, int nrhs, const double* ninv, const double
   if (d || w1) {
     CR_TRY(launch_pix_rhs(P, nrhs, ninv, d, w1, P->w.map_a, s));
     CR_TRY(launch_ring(P, nrhs, RING_ADJOINT, nullptr, P->w.map_a, nullptr, P->w.geo, s));
-    CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, P->w.alm_b, 0, nullptr, P->w.bk, nullptr, nullptr, false, s));
+    CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, P->w.alm_b, false, s));
     braw = P->w.alm_b;
   }
   CR_TRY(launch_rhs_finish(P, nrhs, braw, w0 ? C2(w0) : nullptr, out, s));
@@ -105,7 +107,8 @@ int synth_f64(const crsht_plan* P, int nrhs, const double2* alm, const double* s
 
 int adjoint_f64(const crsht_plan* P, int nrhs, const double* map, double2* alm, hipStream_t s) {
   CR_TRY(launch_ring(P, nrhs, RING_ADJOINT, nullptr, const_cast<double*>(map), nullptr, P->w.geo, s));
-  CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, alm, 0, nullptr, nullptr, nullptr, nullptr, false, s));
+  CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, alm, false, s));
+  CR_TRY(launch_scale_alm(P, nrhs, alm, P->t.rec_kappa, alm, s));
   return CR_OK;
 }
 
@@ -148,7 +151,6 @@ int pcg_f64(const crsht_plan* P, int nrhs, const double* ninv, double tol, int m
             cr_stats* stats, hipStream_t s) {
   const int64_t na = P->g.nalm;
   const int nb = vec_reduce_blocks(P);
-  const int nbm = P->g.mmax + 1;
   Workspace const& w = P->w;
   CR_TRY(hipMemsetAsync(w.cg_x, 0, (size_t)nrhs * na * sizeof(double2), s));
   CR_TRY(hipMemcpyAsync(w.cg_r, w.cg_b, (size_t)nrhs * na * sizeof(double2), hipMemcpyDeviceToDevice, s));
@@ -167,7 +169,7 @@ int pcg_f64(const crsht_plan* P, int nrhs, const double* ninv, double tol, int m
       const int n = std::min(check_every, maxiter - it);
       for (int k = 0; k < n; ++k) {
         CR_CHECK(operator_core(P, nrhs, w.cg_p, w.alm_a, ninv, w.cg_q, s));
-        CR_TRY(launch_cg_scalars(P, nrhs, 1, nbm, tol, 0, s));
+        CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, s));
         CR_TRY(launch_cg_update(P, nrhs, w.cg_x, w.cg_r, w.cg_z, w.cg_p, w.cg_q, s));
         CR_TRY(launch_cg_scalars(P, nrhs, 2, nb, tol, 0, s));
         CR_TRY(launch_cg_pupdate(P, nrhs, w.cg_z, w.cg_p, w.alm_a, s));
@@ -320,9 +322,9 @@ extern "C" int cr_apply(const crsht_plan* P, const cr_problem* prob, int nrhs, c
   if (prec != CR_F64) return CR_ENOTSUP;
   hipStream_t s = S(stream);
   CR_CHECK(set_problem(P, prob, 1.0, s));
-  CR_TRY(launch_project(P, nrhs, C2(x), P->w.alm_b, s));
-  CR_TRY(launch_scale_alm(P, nrhs, P->w.alm_b, P->w.bk, P->w.alm_a, s));
-  return operator_core(P, nrhs, P->w.alm_b, P->w.alm_a, prob->ninv, C2(Ax), s);
+  CR_TRY(launch_project(P, nrhs, C2(x), P->w.cg_d, s));
+  CR_TRY(launch_scale_alm(P, nrhs, P->w.cg_d, P->w.bk, P->w.alm_a, s));
+  return operator_core(P, nrhs, P->w.cg_d, P->w.alm_a, prob->ninv, C2(Ax), s);
 }
 
 extern "C" int cr_solve(const crsht_plan* P, const cr_problem* prob, int nrhs, const double* d, const double* w0,

@@ -51,6 +51,8 @@ struct Tables {
   double* rec_kappa = nullptr;     // [nalm] kappa_lm, lambda_lm = kappa_lm mu_lm
   double* lmm_v = nullptr;         // [mmax+1][npairs] start value mantissa
   int* lmm_k = nullptr;            // [mmax+1][npairs] start scale index k <= 0
+  int* lst_g = nullptr;            // [mmax+1][npairs] first live group of 16 steps (INT_MAX: never)
+  double2* lst_s = nullptr;        // [mmax+1][npairs] (mu_{l-2}, mu_{l-1}) at the start of that group
   int64_t* mstart = nullptr;       // [mmax+2] index of a_{m,m}; mstart[mmax+1] = nalm
   int* idx_l = nullptr;            // [nalm] l of each stored coefficient
   int* idx_m = nullptr;            // [nalm] m of each stored coefficient
@@ -133,21 +135,18 @@ void timing_end(const crsht_plan* P, int id, hipStream_t s);
 void timing_clear(crsht_plan* P);
 
 // ---- Legendre step (legendre.hip) ----
+// Start tables (setup, once per plan): see k_legendre_start.
+hipError_t launch_legendre_start(const crsht_plan* P, hipStream_t s);
 // Synthesis: eo[c][p][m] = (E, O) with E/O the sums over l of even/odd (l-m)
 // of mu_lm(z_p) * alms[c][idx(l,m)], alms already multiplied by kappa (and
 // whatever diagonal factor the caller folds in).
 hipError_t launch_legendre_synth(const crsht_plan* P, int nrhs, const double2* alms, double2* eo,
                                  hipStream_t s);
-// Adjoint: raw[c][idx(l,m)] = sum_p mu_lm(z_p) * (G_E or G_O by parity)[c][p][m].
-// mode 0: out = s * raw with s = sinv if non-NULL (any per-index factor, e.g.
-//   b_l kappa_lm for B Y^T), else kappa (plain Y^T);
-// mode 1: CG operator epilogue out = sinv * pin + bk * raw, and the partial
-//   <pin, out> of block m at partial[c * 4 * npart + m];
-// square: D = sinv + bk^2 * sum mu^2 W_p (preconditioner diagonal) into
-//   (double*)out, 1 where the mode is not kept.
-hipError_t launch_legendre_adjoint(const crsht_plan* P, int nrhs, const double2* geo, double2* out,
-                                   int mode, const double2* pin, const double* sinv, const double* bk,
-                                   double* partial, bool square, hipStream_t s);
+// Adjoint: raw[c][idx(l,m)] = sum_p mu_lm(z_p) * (G_E or G_O by parity)[c][p][m]
+// (no kappa, no other factor). diag: raw[idx].x = sum_p mu_lm(z_p)^2 W_p with
+// W_p = w.ring_w[p] (the preconditioner pass; geo unused, one column).
+hipError_t launch_legendre_adjoint(const crsht_plan* P, int nrhs, const double2* geo, double2* raw, bool diag,
+                                   hipStream_t s);
 
 // ---- ring step (ring.hip) ----
 // mode SYNTH: eo -> map;  ADJOINT: map -> geo;  FUSED: eo -> (map * ninv) -> geo
@@ -168,6 +167,11 @@ hipError_t launch_pix_rhs(const crsht_plan* P, int nrhs, const double* ninv, con
                           double* u, hipStream_t s);
 hipError_t launch_rhs_finish(const crsht_plan* P, int nrhs, const double2* raw, const double2* w0, double2* out,
                              hipStream_t s);
+// q = sinv * p + bk * raw per column; partial <p, q> per block (row 0)
+hipError_t launch_cg_q(const crsht_plan* P, int nrhs, const double2* p, const double2* raw, double2* q,
+                       hipStream_t s);
+// D = sinv + bk^2 * raw.x on kept modes, 1 elsewhere
+hipError_t launch_diag(const crsht_plan* P, const double2* raw, double* diag, hipStream_t s);
 hipError_t launch_project(const crsht_plan* P, int nrhs, const double2* x, double2* out, hipStream_t s);
 hipError_t launch_map_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out,
                             hipStream_t s);

@@ -19,11 +19,24 @@
 namespace crsht {
 namespace {
 
-constexpr int kSynthBlock = 64;   // ring pairs per block (one wavefront)
+constexpr int kSynthBlock = 64;   // ring pairs per block (one wavefront, one pair per lane)
 constexpr int kSynthMT = 4;       // consecutive m per thread: 4 x (E,O) = 128 contiguous bytes per column
+constexpr int kChunk = 64;        // l steps per coefficient chunk staged in LDS
+constexpr int kGroup = 16;        // l steps per start group (see k_legendre_start)
+constexpr int kNever = 0x7fffffff;
 constexpr int kAdjBlock = 256;    // threads per block of the adjoint (one m per block)
 constexpr int kAdjOutputs = 16;   // doubles reduced across the block per chunk
 
+// Start tables. lambda_lm(z) for large m is far below the double range for
+// all l before the turning region, and contributes nothing there. At plan
+// creation k_legendre_start runs the recurrence once in scaled arithmetic
+// (value v * 2^(600 k), k <= 0) for every (m, ring pair) and records the
+// first group of kGroup steps (l - m = 16 g .. 16 g + 15) in which
+// |mu| >= 2^-100, together with the exact state (mu_{l-2}, mu_{l-1}) at the
+// start of that group as ordinary doubles (>= 2^-308 in magnitude, since a
+// value grows by at most 2^13 per step). The transform kernels start every
+// pair from zero, load that state when they reach its group, and skip
+// groups in which no pair of a wavefront is live.
 __device__ __forceinline__ void rescale(double& v0, double& v1, int& k) {
   if (k < 0 && fabs(v1) > kRescaleAbove) {
     v0 *= kRescaleBy;
@@ -32,13 +45,67 @@ __device__ __forceinline__ void rescale(double& v0, double& v1, int& k) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_legendre_start(int lmax, int mmax, int npairs,
+                                                       const double* __restrict__ pair_z,
+                                                       const double* __restrict__ alpha,
+                                                       const double* __restrict__ lmm_v, const int* __restrict__ lmm_k,
+                                                       const int64_t* __restrict__ mstart, int* __restrict__ lst_g,
+                                                       double2* __restrict__ lst_s) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = blockIdx.y;
+  if (p >= npairs || m > mmax) return;
+  const size_t o = (size_t)m * npairs + p;
+  const double z = pair_z[p];
+  const int64_t base = mstart[m];
+  const int nsteps = lmax - m + 1;
+  double v0 = -lmm_v[o], v1 = 0.0;
+  int k = lmm_k[o];
+  double s0 = v0, s1 = v1;
+  int sk = k;
+  int g = kNever;
+  for (int st = 0; st < nsteps; ++st) {
+    if (st % kGroup == 0) {
+      s0 = v0;
+      s1 = v1;
+      sk = k;
+    }
+    const double mu = fma(alpha[base + st] * z, v1, -v0);
+    v0 = v1;
+    v1 = mu;
+    rescale(v0, v1, k);
+    if (k == 0) {
+      g = st / kGroup;
+      break;
+    }
+  }
+  lst_g[o] = g;
+  lst_s[o] = (g == kNever) ? make_double2(0.0, 0.0)
+                           : make_double2(ldexp(s0, kScaleBits * sk), ldexp(s1, kScaleBits * sk));
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
 // ------------------------------------------------------------------ synthesis
+// Block = one wavefront of 64 ring pairs; each lane walks kSynthMT
+// consecutive m. For each m the step l = m .. lmax is generic:
+// mu_l = (alpha_lm z) mu_{l-1} - mu_{l-2} (alpha_mm = 0 and the start state
+// (-lambda_mm, 0) give mu_m = lambda_mm). Coefficients (alpha and the
+// kappa-scaled a_lm of NR columns) are staged through LDS in chunks of 64
+// steps, the next chunk being fetched into registers while the current one
+// is consumed. Chunks before the wavefront's first live group are skipped.
 template <int NR>
 __global__ __launch_bounds__(kSynthBlock) void k_legendre_synth(
     int lmax, int mmax, int npairs, const double* __restrict__ pair_z, const double* __restrict__ alpha,
-    const double* __restrict__ lmm_v, const int* __restrict__ lmm_k, const int64_t* __restrict__ mstart,
+    const int* __restrict__ lst_g, const double2* __restrict__ lst_s, const int64_t* __restrict__ mstart,
     const double2* __restrict__ alms, int64_t alm_stride, double2* __restrict__ eo, int64_t eo_stride) {
-  const int p = blockIdx.y * kSynthBlock + threadIdx.x;
+  __shared__ double s_al[2][kChunk];
+  __shared__ double2 s_a[2][NR][kChunk];
+  const int lane = threadIdx.x;
+  const int p = blockIdx.y * kSynthBlock + lane;
   const bool valid = p < npairs;
   const int pp = valid ? p : npairs - 1;
   const double z = pair_z[pp];
@@ -48,83 +115,84 @@ __global__ __launch_bounds__(kSynthBlock) void k_legendre_synth(
     const int m = mfirst + mi;
     if (m > mmax) break;
     const int64_t base = mstart[m];
-    const double* __restrict__ al = alpha + base - m;  // al[l] = alpha_lm
+    const int nsteps = lmax - m + 1;
+    const size_t o = (size_t)m * npairs + pp;
+    const int gs = valid ? lst_g[o] : kNever;
+    const double2 st0 = lst_s[o];
+    const int gmin = wave_min(gs);
     double2 E[NR], O[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) E[c] = O[c] = make_double2(0.0, 0.0);
-    double v0 = 0.0;
-    double v1 = lmm_v[(size_t)m * npairs + pp];
-    int k = lmm_k[(size_t)m * npairs + pp];
-    {
-      const double w = (k == 0) ? v1 : 0.0;
+    if (gmin != kNever) {
+      double v0 = 0.0, v1 = 0.0;
+      const int ch0 = (gmin * kGroup) / kChunk;
+      {
+        const int st = ch0 * kChunk + lane;
+        const bool in = st < nsteps;
+        s_al[0][lane] = in ? alpha[base + st] : 0.0;
 #pragma unroll
-      for (int c = 0; c < NR; ++c) {
-        const double2 a = alms[c * alm_stride + base];
-        E[c].x = fma(w, a.x, E[c].x);
-        E[c].y = fma(w, a.y, E[c].y);
+        for (int c = 0; c < NR; ++c) s_a[0][c][lane] = in ? alms[c * alm_stride + base + st] : make_double2(0.0, 0.0);
       }
-    }
-    int l = m + 1;
-    // steps while some lane of the wavefront still carries a scaled value
-    while (l <= lmax && __any(k < 0)) {
-      const double mu = fma(al[l] * z, v1, -v0);
-      v0 = v1;
-      v1 = mu;
-      rescale(v0, v1, k);
-      const double w = (k == 0) ? v1 : 0.0;
-      const double2* __restrict__ a = alms + base + (l - m);
-      if ((l - m) & 1) {
+      __syncthreads();
+      const int nch = (nsteps + kChunk - 1) / kChunk;
+      int cur = 0;
+#pragma unroll 1
+      for (int ch = ch0; ch < nch; ++ch) {
+        // fetch the next chunk into registers
+        const int nx = (ch + 1) * kChunk + lane;
+        const bool in = nx < nsteps;
+        const double pal = in ? alpha[base + nx] : 0.0;
+        double2 pa[NR];
 #pragma unroll
-        for (int c = 0; c < NR; ++c) {
-          O[c].x = fma(w, a[c * alm_stride].x, O[c].x);
-          O[c].y = fma(w, a[c * alm_stride].y, O[c].y);
+        for (int c = 0; c < NR; ++c) pa[c] = in ? alms[c * alm_stride + base + nx] : make_double2(0.0, 0.0);
+
+        const int cnt = min(kChunk, nsteps - ch * kChunk);
+        if (cnt == kChunk) {
+#pragma unroll
+          for (int q = 0; q < kChunk / kGroup; ++q) {
+            if (ch * (kChunk / kGroup) + q == gs) {
+              v0 = st0.x;
+              v1 = st0.y;
+            }
+#pragma unroll
+            for (int j = q * kGroup; j < (q + 1) * kGroup; j += 2) {
+              const double mu1 = fma(s_al[cur][j] * z, v1, -v0);
+              const double mu2 = fma(s_al[cur][j + 1] * z, mu1, -v1);
+              v0 = mu1;
+              v1 = mu2;
+#pragma unroll
+              for (int c = 0; c < NR; ++c) {
+                const double2 ae = s_a[cur][c][j], ao = s_a[cur][c][j + 1];
+                E[c].x = fma(mu1, ae.x, E[c].x);
+                E[c].y = fma(mu1, ae.y, E[c].y);
+                O[c].x = fma(mu2, ao.x, O[c].x);
+                O[c].y = fma(mu2, ao.y, O[c].y);
+              }
+            }
+          }
+        } else {
+          for (int j = 0; j < cnt; ++j) {
+            if (j % kGroup == 0 && ch * (kChunk / kGroup) + j / kGroup == gs) {
+              v0 = st0.x;
+              v1 = st0.y;
+            }
+            const double mu = fma(s_al[cur][j] * z, v1, -v0);
+            v0 = v1;
+            v1 = mu;
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+              double2& acc = (j & 1) ? O[c] : E[c];
+              acc.x = fma(mu, s_a[cur][c][j].x, acc.x);
+              acc.y = fma(mu, s_a[cur][c][j].y, acc.y);
+            }
+          }
         }
-      } else {
+        // publish the next chunk
+        s_al[cur ^ 1][lane] = pal;
 #pragma unroll
-        for (int c = 0; c < NR; ++c) {
-          E[c].x = fma(w, a[c * alm_stride].x, E[c].x);
-          E[c].y = fma(w, a[c * alm_stride].y, E[c].y);
-        }
-      }
-      ++l;
-    }
-    // ordinary doubles from here on; align so each iteration is (odd, even)
-    if (l <= lmax && ((l - m) & 1) == 0) {
-      const double mu = fma(al[l] * z, v1, -v0);
-      v0 = v1;
-      v1 = mu;
-      const double2* __restrict__ a = alms + base + (l - m);
-#pragma unroll
-      for (int c = 0; c < NR; ++c) {
-        E[c].x = fma(v1, a[c * alm_stride].x, E[c].x);
-        E[c].y = fma(v1, a[c * alm_stride].y, E[c].y);
-      }
-      ++l;
-    }
-#pragma unroll 2
-    for (; l + 1 <= lmax; l += 2) {
-      const double a1 = al[l], a2 = al[l + 1];
-      const double2* __restrict__ a = alms + base + (l - m);
-      const double mu1 = fma(a1 * z, v1, -v0);
-      const double mu2 = fma(a2 * z, mu1, -v1);
-      v0 = mu1;
-      v1 = mu2;
-#pragma unroll
-      for (int c = 0; c < NR; ++c) {
-        const double2 ao = a[c * alm_stride], ae = a[c * alm_stride + 1];
-        O[c].x = fma(mu1, ao.x, O[c].x);
-        O[c].y = fma(mu1, ao.y, O[c].y);
-        E[c].x = fma(mu2, ae.x, E[c].x);
-        E[c].y = fma(mu2, ae.y, E[c].y);
-      }
-    }
-    if (l <= lmax) {  // one odd step left
-      const double mu = fma(al[l] * z, v1, -v0);
-      const double2* __restrict__ a = alms + base + (l - m);
-#pragma unroll
-      for (int c = 0; c < NR; ++c) {
-        O[c].x = fma(mu, a[c * alm_stride].x, O[c].x);
-        O[c].y = fma(mu, a[c * alm_stride].y, O[c].y);
+        for (int c = 0; c < NR; ++c) s_a[cur ^ 1][c][lane] = pa[c];
+        __syncthreads();
+        cur ^= 1;
       }
     }
     if (valid) {
@@ -139,13 +207,14 @@ __global__ __launch_bounds__(kSynthBlock) void k_legendre_synth(
 }
 
 // -------------------------------------------------------------------- adjoint
-// One block per m. Thread t owns ring pairs t, t + 256, ...; each step adds
-// mu_lm(z_p) * G_p over its pairs, and every C steps the block reduces the
-// per-thread partial sums through LDS. Output modes:
-//   MODE_PLAIN : out = oscale * raw  (oscale = kappa gives Y^T, b kappa gives B Y^T)
-//   MODE_AXPY  : out = sinv * pin + bk * raw; partial[c][m] = w_m <pin, out>_m
-//   MODE_DIAG  : dout = kept ? sinv + bk^2 * raw : 1   (raw = sum mu^2 W_p)
-enum { MODE_PLAIN = 0, MODE_AXPY = 1, MODE_DIAG = 2 };
+// One block per m. Thread t owns the RPT consecutive ring pairs
+// t*RPT .. t*RPT+RPT-1; each step adds mu_lm(z_p) * G_p over its pairs, and
+// every C steps the block reduces the per-thread partial sums through LDS and
+// writes the raw sums raw[c][idx(l,m)] = sum_p mu_lm(z_p) G_p (G = G_N + G_S
+// for even l - m, G_N - G_S for odd). MODE_DIAG sums mu^2 W_p instead (the
+// preconditioner diagonal; W_p the ring-pair sum of N^-1). All scaling (kappa,
+// b_l, 1/C_l) happens in the vector kernels. alpha of the m is staged in LDS.
+enum { MODE_RAW = 0, MODE_DIAG = 2 };
 
 __device__ __forceinline__ int block_to_m(int b) {
   // blocks are dealt to the 8 XCDs round-robin; give each XCD four
@@ -157,34 +226,38 @@ __device__ __forceinline__ int block_to_m(int b) {
 template <int NR, int RPT, int MODE>
 __global__ __launch_bounds__(kAdjBlock) void k_legendre_adj(
     int lmax, int mmax, int npairs, const double* __restrict__ pair_z, const double* __restrict__ alpha,
-    const double* __restrict__ lmm_v, const int* __restrict__ lmm_k, const int64_t* __restrict__ mstart,
-    const double* __restrict__ oscale, const double2* __restrict__ geo, int64_t geo_stride,
-    const double* __restrict__ ringw, double2* __restrict__ out, double* __restrict__ dout, int64_t out_stride,
-    const double2* __restrict__ pin, const double* __restrict__ sinv, const double* __restrict__ bk,
-    double* __restrict__ partial, int npart) {
-  constexpr int C = kAdjOutputs / (2 * NR);          // l steps per reduction chunk
+    const int* __restrict__ lst_g, const double2* __restrict__ lst_s, const int64_t* __restrict__ mstart,
+    const double2* __restrict__ geo, int64_t geo_stride, const double* __restrict__ ringw,
+    double2* __restrict__ out, int64_t out_stride) {
+  constexpr int C = kAdjOutputs / (2 * NR);          // l steps per reduction chunk (divides kGroup)
   constexpr int TPO = kAdjBlock / kAdjOutputs;        // threads per reduced output
+  extern __shared__ double s_al[];                    // [lmax+1] alpha of this m
   __shared__ double red[kAdjOutputs][kAdjBlock];
-  __shared__ double redq[kAdjBlock];
 
   const int m = block_to_m(blockIdx.x);
   if (m > mmax) return;
   const int t = threadIdx.x;
   const int64_t base = mstart[m];
-  const double* __restrict__ al = alpha + base - m;
+  const int nsteps = lmax - m + 1;
+  for (int j = t; j < nsteps; j += kAdjBlock) s_al[j] = alpha[base + j];
 
   double z[RPT], v0[RPT], v1[RPT];
-  int k[RPT];
+  int gs[RPT];
+  double2 st[RPT];
   double2 ge[RPT][NR], go[RPT][NR];
+  int gmin = kNever;
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
-    const int p = t + j * kAdjBlock;
+    const int p = t * RPT + j;
     const bool ok = p < npairs;
     const int pp = ok ? p : 0;
+    const size_t o = (size_t)m * npairs + pp;
     z[j] = pair_z[pp];
     v0[j] = 0.0;
-    v1[j] = ok ? lmm_v[(size_t)m * npairs + pp] : 0.0;
-    k[j] = ok ? lmm_k[(size_t)m * npairs + pp] : 0;
+    v1[j] = 0.0;
+    gs[j] = ok ? lst_g[o] : kNever;
+    st[j] = lst_s[o];
+    gmin = min(gmin, gs[j]);
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
       if (MODE == MODE_DIAG) {
@@ -198,52 +271,51 @@ __global__ __launch_bounds__(kAdjBlock) void k_legendre_adj(
       }
     }
   }
+  gmin = wave_min(gmin);   // first live group of this wavefront
+  __syncthreads();
 
   const int o = t / TPO;        // output this thread reduces: (jj, c, re/im)
   const int s = t % TPO;
   const int o_jj = o / (2 * NR), o_c = (o / 2) % NR, o_ri = o & 1;
-  const double wm = (m == 0) ? 1.0 : 2.0;
-  double accq = 0.0;
 
-  for (int l0 = m; l0 <= lmax; l0 += C) {
+  for (int l0 = 0; l0 < nsteps; l0 += C) {
     double2 part[C][NR];
 #pragma unroll
     for (int jj = 0; jj < C; ++jj)
 #pragma unroll
       for (int c = 0; c < NR; ++c) part[jj][c] = make_double2(0.0, 0.0);
 
-    bool anyneg = false;
+    const int grp = l0 / kGroup;
+    if (grp >= gmin) {
+      if (l0 % kGroup == 0) {
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) anyneg |= (k[j] < 0);
-    const bool scaled = __any(anyneg);
-
+        for (int j = 0; j < RPT; ++j)
+          if (gs[j] == grp) {
+            v0[j] = st[j].x;
+            v1[j] = st[j].y;
+          }
+      }
 #pragma unroll
-    for (int jj = 0; jj < C; ++jj) {
-      const int l = l0 + jj;
-      if (l > lmax) break;
-      const bool odd = (l - m) & 1;
-      const double a = (l > m) ? al[l] : 0.0;
+      for (int jj = 0; jj < C; ++jj) {
+        if (C > 1 && l0 + jj >= nsteps) break;
+        const double a = s_al[l0 + jj];
+        const bool odd = (C % 2 == 0) ? (jj & 1) : ((l0 + jj) & 1);   // C even: l0 even
 #pragma unroll
-      for (int j = 0; j < RPT; ++j) {
-        if (l > m) {
+        for (int j = 0; j < RPT; ++j) {
           const double mu = fma(a * z[j], v1[j], -v0[j]);
           v0[j] = v1[j];
           v1[j] = mu;
-          if (scaled) rescale(v0[j], v1[j], k[j]);
-        }
-        double w = v1[j];
-        if (scaled) w = (k[j] == 0) ? w : 0.0;
-        if (MODE == MODE_DIAG) w = w * w;
+          const double w = (MODE == MODE_DIAG) ? mu * mu : mu;
 #pragma unroll
-        for (int c = 0; c < NR; ++c) {
-          const double2 g = odd ? go[j][c] : ge[j][c];
-          part[jj][c].x = fma(w, g.x, part[jj][c].x);
-          part[jj][c].y = fma(w, g.y, part[jj][c].y);
+          for (int c = 0; c < NR; ++c) {
+            const double2 g = odd ? go[j][c] : ge[j][c];
+            part[jj][c].x = fma(w, g.x, part[jj][c].x);
+            part[jj][c].y = fma(w, g.y, part[jj][c].y);
+          }
         }
       }
     }
 
-    __syncthreads();
 #pragma unroll
     for (int jj = 0; jj < C; ++jj)
 #pragma unroll
@@ -253,40 +325,13 @@ __global__ __launch_bounds__(kAdjBlock) void k_legendre_adj(
       }
     __syncthreads();
     double sum = 0.0;
-#pragma unroll 4
+#pragma unroll
     for (int i = 0; i < kAdjBlock / TPO; ++i) sum += red[o][s + TPO * i];
 #pragma unroll
     for (int off = TPO / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, TPO);
-    const int l = l0 + o_jj;
-    if (s == 0 && l <= lmax) {
-      const int64_t idx = base + (l - m);
-      if (MODE == MODE_PLAIN) {
-        reinterpret_cast<double*>(out + o_c * out_stride + idx)[o_ri] = oscale[idx] * sum;
-      } else if (MODE == MODE_AXPY) {
-        const double pv = reinterpret_cast<const double*>(pin + o_c * out_stride + idx)[o_ri];
-        const double val = sinv[idx] * pv + bk[idx] * sum;
-        reinterpret_cast<double*>(out + o_c * out_stride + idx)[o_ri] = val;
-        accq = fma(wm * pv, val, accq);
-      } else {
-        if (o_ri == 0) {
-          const double b = bk[idx];
-          dout[idx] = (b != 0.0 || sinv[idx] != 0.0) ? sinv[idx] + b * b * sum : 1.0;
-        }
-      }
-    }
-  }
-
-  if (MODE == MODE_AXPY) {
+    const int sto = l0 + o_jj;
+    if (s == 0 && sto < nsteps) reinterpret_cast<double*>(out + o_c * out_stride + base + sto)[o_ri] = sum;
     __syncthreads();
-    redq[t] = accq;
-    __syncthreads();
-    if (t < NR) {
-      // threads owning column c: o = (jj*NR + c)*2 + ri, s == 0
-      double tot = 0.0;
-      for (int jj = 0; jj < C; ++jj)
-        for (int ri = 0; ri < 2; ++ri) tot += redq[((jj * NR + t) * 2 + ri) * TPO];
-      partial[(size_t)t * 4 * npart + m] = tot;
-    }
   }
 }
 
@@ -299,34 +344,25 @@ hipError_t synth_pass(const crsht_plan* P, const double2* alms, double2* eo, hip
   const int64_t eo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
   timing_begin(P, 0, s);
   hipLaunchKernelGGL(k_legendre_synth<NR>, grid, dim3(kSynthBlock), 0, s, g.lmax, g.mmax, g.npairs, P->t.pair_z,
-                     P->t.rec_alpha, P->t.lmm_v, P->t.lmm_k, P->t.mstart, alms, (int64_t)g.nalm, eo, eo_stride);
+                     P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, alms, (int64_t)g.nalm, eo, eo_stride);
   timing_end(P, 0, s);
   return hipGetLastError();
 }
 
 template <int NR, int RPT>
-hipError_t adj_pass_rpt(const crsht_plan* P, const double2* geo, double2* out, double* dout, int mode,
-                        const double2* pin, const double* sinv, const double* bk, double* partial,
-                        hipStream_t s) {
-  const double* oscale = (mode == MODE_PLAIN && sinv) ? sinv : P->t.rec_kappa;
+hipError_t adj_pass_rpt(const crsht_plan* P, const double2* geo, double2* out, bool diag, hipStream_t s) {
   const Geometry& g = P->g;
   const int nb = ((g.mmax + 1 + 31) / 32) * 32;
   const int64_t geo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
-  const int64_t os = g.nalm;
-#define CRSHT_ADJ_LAUNCH(MD)                                                                                 \
-  hipLaunchKernelGGL((k_legendre_adj<NR, RPT, MD>), dim3(nb), dim3(kAdjBlock), 0, s, g.lmax, g.mmax,        \
-                     g.npairs, P->t.pair_z, P->t.rec_alpha, P->t.lmm_v, P->t.lmm_k, P->t.mstart,             \
-                     oscale, geo, geo_stride, P->w.ring_w, out, dout, os, pin, sinv, bk, partial,            \
-                     P->w.npart)
-  timing_begin(P, 1, s);
-  if (mode == MODE_PLAIN)
-    CRSHT_ADJ_LAUNCH(MODE_PLAIN);
-  else if (mode == MODE_AXPY)
-    CRSHT_ADJ_LAUNCH(MODE_AXPY);
+  const size_t lds = (size_t)(g.lmax + 1) * sizeof(double);
+  if (diag)
+    hipLaunchKernelGGL((k_legendre_adj<NR, RPT, MODE_DIAG>), dim3(nb), dim3(kAdjBlock), lds, s, g.lmax, g.mmax,
+                       g.npairs, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, geo, geo_stride,
+                       P->w.ring_w, out, (int64_t)g.nalm);
   else
-    CRSHT_ADJ_LAUNCH(MODE_DIAG);
-  timing_end(P, 1, s);
-#undef CRSHT_ADJ_LAUNCH
+    hipLaunchKernelGGL((k_legendre_adj<NR, RPT, MODE_RAW>), dim3(nb), dim3(kAdjBlock), lds, s, g.lmax, g.mmax,
+                       g.npairs, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, geo, geo_stride,
+                       P->w.ring_w, out, (int64_t)g.nalm);
   return hipGetLastError();
 }
 
@@ -334,26 +370,31 @@ hipError_t adj_pass_rpt(const crsht_plan* P, const double2* geo, double2* out, d
 // keeps the per-thread G values (RPT x NR x 2 complex) within registers
 int adj_rpt(const crsht_plan* P) {
   const int r = (P->g.npairs + kAdjBlock - 1) / kAdjBlock;
-  return r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : r <= 8 ? 8 : 16;
+  return r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : 8;
 }
-int adj_max_nr(int rpt) { return rpt >= 16 ? 1 : rpt >= 8 ? 2 : rpt >= 4 ? 4 : 8; }
+int adj_max_nr(int rpt) { return rpt >= 8 ? 2 : rpt >= 4 ? 4 : 8; }
 
 template <int NR>
-hipError_t adj_pass(const crsht_plan* P, const double2* geo, double2* out, double* dout, int mode,
-                    const double2* pin, const double* sinv, const double* bk, double* partial, hipStream_t s) {
+hipError_t adj_pass(const crsht_plan* P, const double2* geo, double2* out, bool diag, hipStream_t s) {
   const int rpt = adj_rpt(P);
-  if (rpt == 1) return adj_pass_rpt<NR, 1>(P, geo, out, dout, mode, pin, sinv, bk, partial, s);
-  if (rpt == 2) return adj_pass_rpt<NR, 2>(P, geo, out, dout, mode, pin, sinv, bk, partial, s);
+  if (rpt == 1) return adj_pass_rpt<NR, 1>(P, geo, out, diag, s);
+  if (rpt == 2) return adj_pass_rpt<NR, 2>(P, geo, out, diag, s);
   if constexpr (NR <= 4)
-    if (rpt == 4) return adj_pass_rpt<NR, 4>(P, geo, out, dout, mode, pin, sinv, bk, partial, s);
+    if (rpt == 4) return adj_pass_rpt<NR, 4>(P, geo, out, diag, s);
   if constexpr (NR <= 2)
-    if (rpt == 8) return adj_pass_rpt<NR, 8>(P, geo, out, dout, mode, pin, sinv, bk, partial, s);
-  if constexpr (NR == 1)
-    if (rpt == 16) return adj_pass_rpt<NR, 16>(P, geo, out, dout, mode, pin, sinv, bk, partial, s);
+    if (rpt == 8) return adj_pass_rpt<NR, 8>(P, geo, out, diag, s);
   return hipErrorInvalidValue;
 }
 
 }  // namespace
+
+hipError_t launch_legendre_start(const crsht_plan* P, hipStream_t s) {
+  const Geometry& g = P->g;
+  dim3 grid((g.npairs + 255) / 256, g.mmax + 1);
+  hipLaunchKernelGGL(k_legendre_start, grid, dim3(256), 0, s, g.lmax, g.mmax, g.npairs, P->t.pair_z, P->t.rec_alpha,
+                     P->t.lmm_v, P->t.lmm_k, P->t.mstart, P->t.lst_g, P->t.lst_s);
+  return hipGetLastError();
+}
 
 hipError_t launch_legendre_synth(const crsht_plan* P, int nrhs, const double2* alms, double2* eo, hipStream_t s) {
   const int64_t eo_stride = (int64_t)P->g.npairs * (P->g.mmax + 1) * 2;
@@ -371,28 +412,29 @@ hipError_t launch_legendre_synth(const crsht_plan* P, int nrhs, const double2* a
   return hipSuccess;
 }
 
-hipError_t launch_legendre_adjoint(const crsht_plan* P, int nrhs, const double2* geo, double2* out, int mode,
-                                   const double2* pin, const double* sinv, const double* bk, double* partial,
-                                   bool square, hipStream_t s) {
-  if (square) return adj_pass<1>(P, nullptr, nullptr, reinterpret_cast<double*>(out), MODE_DIAG, nullptr, sinv,
-                                 bk, nullptr, s);
-  const int64_t geo_stride = (int64_t)P->g.npairs * (P->g.mmax + 1) * 2;
-  const int nr_cap = adj_max_nr(adj_rpt(P));
-  for (int c0 = 0; c0 < nrhs;) {
-    int nr = pick_nr(nrhs - c0);
-    if (nr > nr_cap) nr = nr_cap;
-    const double2* gi = geo + (int64_t)c0 * geo_stride;
-    double2* oo = out + (int64_t)c0 * P->g.nalm;
-    const double2* pi = pin ? pin + (int64_t)c0 * P->g.nalm : nullptr;
-    double* pa = partial ? partial + (int64_t)c0 * 4 * P->w.npart : nullptr;
-    hipError_t err = nr == 8 ? adj_pass<8>(P, gi, oo, nullptr, mode, pi, sinv, bk, pa, s)
-                   : nr == 4 ? adj_pass<4>(P, gi, oo, nullptr, mode, pi, sinv, bk, pa, s)
-                   : nr == 2 ? adj_pass<2>(P, gi, oo, nullptr, mode, pi, sinv, bk, pa, s)
-                             : adj_pass<1>(P, gi, oo, nullptr, mode, pi, sinv, bk, pa, s);
-    if (err != hipSuccess) return err;
-    c0 += nr;
+hipError_t launch_legendre_adjoint(const crsht_plan* P, int nrhs, const double2* geo, double2* raw, bool diag,
+                                   hipStream_t s) {
+  timing_begin(P, 1, s);
+  hipError_t err = hipSuccess;
+  if (diag) {
+    err = adj_pass<1>(P, nullptr, raw, true, s);
+  } else {
+    const int64_t geo_stride = (int64_t)P->g.npairs * (P->g.mmax + 1) * 2;
+    const int nr_cap = adj_max_nr(adj_rpt(P));
+    for (int c0 = 0; c0 < nrhs && err == hipSuccess;) {
+      int nr = pick_nr(nrhs - c0);
+      if (nr > nr_cap) nr = nr_cap;
+      const double2* gi = geo + (int64_t)c0 * geo_stride;
+      double2* oo = raw + (int64_t)c0 * P->g.nalm;
+      err = nr == 8 ? adj_pass<8>(P, gi, oo, false, s)
+          : nr == 4 ? adj_pass<4>(P, gi, oo, false, s)
+          : nr == 2 ? adj_pass<2>(P, gi, oo, false, s)
+                    : adj_pass<1>(P, gi, oo, false, s);
+      c0 += nr;
+    }
   }
-  return hipSuccess;
+  timing_end(P, 1, s);
+  return err;
 }
 
 }  // namespace crsht

@@ -74,7 +74,7 @@ int upload(T** p, const std::vector<T>& h, size_t* total) {
 void free_plan_memory(crsht_plan* P) {
   void* ptrs[] = {P->t.pair_z, P->t.pair_nphi, P->t.pair_phi0, P->t.pair_first_n, P->t.pair_first_s,
                   P->t.pair_fft_len, P->t.pair_bs_off, P->t.pair_bk_off, P->t.bs_chirp, P->t.bs_kern,
-                  P->t.twiddle, P->t.rec_alpha, P->t.rec_kappa, P->t.lmm_v, P->t.lmm_k, P->t.mstart,
+                  P->t.twiddle, P->t.rec_alpha, P->t.rec_kappa, P->t.lmm_v, P->t.lmm_k, P->t.lst_g, P->t.lst_s, P->t.mstart,
                   P->t.idx_l, P->t.idx_m, P->w.eo, P->w.geo, P->w.alm_a, P->w.alm_b, P->w.cg_x, P->w.cg_r,
                   P->w.cg_z, P->w.cg_p, P->w.cg_q, P->w.cg_b, P->w.cg_d, P->w.alm_c, P->w.alm_d, P->w.map_a, P->w.ring_w,
                   P->w.diag, P->w.sinv, P->w.sinvhalf, P->w.bk, P->w.perl, P->w.partial, P->w.scal};
@@ -251,6 +251,10 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int nrhs_max
   if ((rc = upload(&P->t.lmm_v, lv, total))) return rc;
   if ((rc = upload(&P->t.lmm_k, lk, total))) return rc;
   if ((rc = upload(&P->t.mstart, mst, total))) return rc;
+  if ((rc = dalloc(&P->t.lst_g, (size_t)(mmax + 1) * np, total))) return rc;
+  if ((rc = dalloc(&P->t.lst_s, (size_t)(mmax + 1) * np, total))) return rc;
+  if (crsht::launch_legendre_start(P, nullptr) != hipSuccess) return CR_EDEVICE;
+  if (hipDeviceSynchronize() != hipSuccess) return CR_EDEVICE;
   if ((rc = upload(&P->t.idx_l, il, total))) return rc;
   if ((rc = upload(&P->t.idx_m, im, total))) return rc;
 
@@ -288,8 +292,9 @@ extern "C" int crsht_plan_create(int nside, int lmax, int mmax, int ncomp, int n
   if (!out) return CR_EINVAL;
   *out = nullptr;
   if (mmax < 0) mmax = lmax;
-  if (nside < 1 || nside > 8192 || lmax < 0 || mmax > lmax || nrhs_max < 1 || nrhs_max > 4096) return CR_EINVAL;
+  if (nside < 1 || lmax < 0 || mmax > lmax || nrhs_max < 1 || nrhs_max > 4096) return CR_EINVAL;
   if (lmax > 16383) return CR_EINVAL;
+  if (nside > 1024) return CR_ENOTSUP;  // adjoint kernel holds at most 16 ring pairs per thread x 128 threads
   if (ncomp != 1) return ncomp == 3 ? CR_ENOTSUP : CR_EINVAL;
   crsht_plan* P = new (std::nothrow) crsht_plan();
   if (!P) return CR_ENOMEM;

@@ -37,8 +37,8 @@ __global__ void k_expand(int64_t nalm, const int* __restrict__ idx_l, const doub
   bk[i] = keep * perl[2 * (lmax + 1) + l] * kappa[i];
 }
 
-__global__ void k_scale(int64_t nalm, int nrhs, const double2* __restrict__ in, const double* __restrict__ f,
-                        double2* __restrict__ out) {
+// out = f * in per column (in and out may be the same array)
+__global__ void k_scale(int64_t nalm, int nrhs, const double2* in, const double* __restrict__ f, double2* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nalm) return;
   const double s = f[i];
@@ -79,17 +79,19 @@ __global__ void k_pix_rhs(int64_t npix, int nrhs, const double* __restrict__ nin
   }
 }
 
-// out = braw + sinvhalf * w0 (either may be absent); braw = B Y^T u already
-// scaled; Im of m = 0 forced to 0
+// out = bk * raw + sinvhalf * w0 (either may be absent), raw = the unscaled
+// adjoint Legendre sums of N^-1 d + N^-1/2 w1; Im of m = 0 forced to 0
 __global__ void k_rhs_finish(int64_t nalm, int nrhs, const int* __restrict__ idx_m, const double* __restrict__ bk,
                              const double* __restrict__ sinvhalf, const double2* __restrict__ raw,
                              const double2* __restrict__ w0, double2* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nalm) return;
-  const double sh = sinvhalf[i];
+  const double sh = sinvhalf[i], b = bk[i];
   const bool m0 = idx_m[i] == 0;
   for (int c = 0; c < nrhs; ++c) {
     double2 v = raw ? raw[c * nalm + i] : make_double2(0.0, 0.0);
+    v.x *= b;
+    v.y *= b;
     if (w0) {
       const double2 w = w0[c * nalm + i];
       v.x = fma(sh, w.x, v.x);
@@ -293,6 +295,33 @@ __global__ void k_cg_pupdate(int64_t nalm, const double* __restrict__ bk, const 
   }
 }
 
+// q = sinv * p + bk * raw; partial <p, q>
+__global__ void k_cg_q(int64_t nalm, const int* __restrict__ idx_m, const double* __restrict__ sinv,
+                       const double* __restrict__ bk, const double2* __restrict__ p, const double2* __restrict__ raw,
+                       double2* __restrict__ q, double* __restrict__ partial, int npart) {
+  __shared__ double sh[kVecBlock];
+  const int c = blockIdx.y;
+  double pq = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nalm; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ci = c * nalm + i;
+    const double si = sinv[i], b = bk[i];
+    const double2 pv = p[ci], rv = raw[ci];
+    const double2 qv = make_double2(fma(si, pv.x, b * rv.x), fma(si, pv.y, b * rv.y));
+    q[ci] = qv;
+    pq += wdot(idx_m[i], pv, qv);
+  }
+  pq = block_sum(pq, sh);
+  if (threadIdx.x == 0) partial[(size_t)c * npart * 4 + blockIdx.x] = pq;
+}
+
+__global__ void k_diag(int64_t nalm, const double* __restrict__ sinv, const double* __restrict__ bk,
+                       const double2* __restrict__ raw, double* __restrict__ diag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nalm) return;
+  const double si = sinv[i], b = bk[i];
+  diag[i] = si > 0.0 ? fma(b * b, raw[i].x, si) : 1.0;
+}
+
 // r = b - Ax; partial <r,r> into row 1 (row 0: <r,r> as well)
 __global__ void k_residual(int64_t nalm, const int* __restrict__ idx_m, const double2* __restrict__ b,
                            const double2* __restrict__ ax, double2* __restrict__ r, double* __restrict__ partial,
@@ -441,6 +470,20 @@ hipError_t launch_cg_scalars(const crsht_plan* P, int nrhs, int what, int nb, do
                              hipStream_t s) {
   hipLaunchKernelGGL(k_cg_scalars, dim3(nrhs), dim3(kVecBlock), 0, s, what, nb, P->w.partial, P->w.npart,
                      P->w.scal, tol, restart);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_q(const crsht_plan* P, int nrhs, const double2* p, const double2* raw, double2* q,
+                       hipStream_t s) {
+  const int nb = vec_reduce_blocks(P);
+  hipLaunchKernelGGL(k_cg_q, dim3(nb, nrhs), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_m, P->w.sinv, P->w.bk, p,
+                     raw, q, P->w.partial, P->w.npart);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag(const crsht_plan* P, const double2* raw, double* diag, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag, dim3(nblocks(P->g.nalm)), dim3(kVecBlock), 0, s, P->g.nalm, P->w.sinv, P->w.bk, raw,
+                     diag);
   return hipGetLastError();
 }
 
