@@ -97,6 +97,7 @@ def main():
     ap.add_argument("--nside", type=int, default=512)
     ap.add_argument("--lmax", type=int, default=None)
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--prec", choices=["f64", "mixed"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -132,8 +133,11 @@ def main():
     out = torch.empty((R, plan.nalm), dtype=torch.complex128, device=dev)
     torch.cuda.synchronize()
 
+    prec = crsht.CR_MIXED if args.prec == "mixed" else crsht.CR_F64
+
     def step():
-        return crsht.solve(plan, prob, d, w0, w1, nrhs=R, tol=wl.tol, maxiter=20000, out=out, check_every=16)
+        return crsht.solve(plan, prob, d, w0, w1, nrhs=R, tol=wl.tol, maxiter=20000, out=out, check_every=16,
+                           prec=prec, inner_tol=1e-2)
 
     for _ in range(args.warmup):
         _, st = step()

@@ -64,11 +64,13 @@ enum {
 typedef struct crsht_plan crsht_plan;
 
 /* Arithmetic of the Legendre contraction.
- * CR_F64: float64 throughout.
- * CR_MIXED: lambda_lm recurrence, CG vectors, dot products and scalars in
- *   float64; Legendre sums accumulated in float32 from float32-rounded
- *   recurrence values and coefficients; used by cr_solve as the inner
- *   operator of float64 iterative refinement. */
+ * CR_F64: float64 throughout (vector ALU).
+ * CR_MIXED: the lambda_lm recurrence stays float64; recurrence values and
+ *   a_lm / ring coefficients are rounded to float and split into bf16 hi + lo
+ *   parts, and each product is formed as hi*hi + hi*lo + lo*hi on the matrix
+ *   cores with float32 accumulation (relative error about 5e-6 per transform).
+ *   Ring FFTs, CG vectors, dot products and scalars stay float64. In cr_solve
+ *   it is the inner operator of float64 iterative refinement. */
 typedef enum { CR_F64 = 0, CR_MIXED = 1 } cr_prec;
 
 /* Create a plan for HEALPix resolution nside (power of two not required,

@@ -68,10 +68,16 @@ int set_problem(const crsht_plan* P, const cr_problem* prob, double q, hipStream
 // w.geo and w.alm_b as scratch (x must not live there).
 // out = sinv * x + bk * (Y^T N^-1 Y)(pt); block partials of <x, out> in row 0.
 int operator_core(const crsht_plan* P, int nrhs, const double2* x, const double2* pt, const double* ninv,
-                  double2* out, hipStream_t s) {
-  CR_TRY(launch_legendre_synth(P, nrhs, pt, P->w.eo, s));
+                  double2* out, hipStream_t s, bool mixed = false) {
+  if (mixed)
+    CR_TRY(launch_legendre_synth_mixed(P, nrhs, pt, nullptr, P->w.eo, s));
+  else
+    CR_TRY(launch_legendre_synth(P, nrhs, pt, P->w.eo, s));
   CR_TRY(launch_ring(P, nrhs, RING_FUSED, P->w.eo, nullptr, ninv, P->w.geo, s));
-  CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, P->w.alm_b, false, s));
+  if (mixed)
+    CR_TRY(launch_legendre_adjoint_mixed(P, nrhs, P->w.geo, P->w.alm_b, s));
+  else
+    CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, P->w.alm_b, false, s));
   CR_TRY(launch_cg_q(P, nrhs, x, P->w.alm_b, out, s));
   return CR_OK;
 }
@@ -98,16 +104,24 @@ int assemble_rhs(const crsht_plan* P, int nrhs, const double* ninv, const double
   return CR_OK;
 }
 
-int synth_f64(const crsht_plan* P, int nrhs, const double2* alm, const double* scale, double* map, hipStream_t s) {
-  CR_TRY(launch_scale_alm(P, nrhs, alm, scale, P->w.alm_a, s));
-  CR_TRY(launch_legendre_synth(P, nrhs, P->w.alm_a, P->w.eo, s));
+int synth_f64(const crsht_plan* P, int nrhs, const double2* alm, const double* scale, double* map, hipStream_t s,
+              bool mixed = false) {
+  if (mixed) {
+    CR_TRY(launch_legendre_synth_mixed(P, nrhs, alm, scale, P->w.eo, s));
+  } else {
+    CR_TRY(launch_scale_alm(P, nrhs, alm, scale, P->w.alm_a, s));
+    CR_TRY(launch_legendre_synth(P, nrhs, P->w.alm_a, P->w.eo, s));
+  }
   CR_TRY(launch_ring(P, nrhs, RING_SYNTH, P->w.eo, map, nullptr, nullptr, s));
   return CR_OK;
 }
 
-int adjoint_f64(const crsht_plan* P, int nrhs, const double* map, double2* alm, hipStream_t s) {
+int adjoint_f64(const crsht_plan* P, int nrhs, const double* map, double2* alm, hipStream_t s, bool mixed = false) {
   CR_TRY(launch_ring(P, nrhs, RING_ADJOINT, nullptr, const_cast<double*>(map), nullptr, P->w.geo, s));
-  CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, alm, false, s));
+  if (mixed)
+    CR_TRY(launch_legendre_adjoint_mixed(P, nrhs, P->w.geo, alm, s));
+  else
+    CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, alm, false, s));
   CR_TRY(launch_scale_alm(P, nrhs, alm, P->t.rec_kappa, alm, s));
   return CR_OK;
 }
@@ -145,30 +159,33 @@ int true_residual(const crsht_plan* P, int nrhs, const double* ninv, const doubl
   return CR_OK;
 }
 
-// PCG on the problem already set up (sinv, bk, diag in the workspace) with
-// b in w.cg_b; solution in w.cg_x.
-int pcg_f64(const crsht_plan* P, int nrhs, const double* ninv, double tol, int maxiter, int check_every,
-            cr_stats* stats, hipStream_t s) {
+// PCG on the problem already set up (sinv, bk, diag in the workspace) for the
+// right-hand side b (device, [nrhs][nalm]); solution in w.cg_x. Scratch:
+// w.cg_r, cg_z, cg_p, cg_q, alm_a, alm_b, eo, geo. With verify, a column
+// whose recursive residual meets tol is confirmed against the true FP64
+// residual and restarted from it if it does not; rel[] then holds the true
+// relative residuals. iters[] receives the iterations per column.
+int pcg_run(const crsht_plan* P, int nrhs, const double* ninv, const double2* b, double tol, int maxiter,
+            int check_every, bool mixed, bool verify, std::vector<int>& iters, std::vector<double>& rel,
+            std::vector<int>& broke, hipStream_t s) {
   const int64_t na = P->g.nalm;
   const int nb = vec_reduce_blocks(P);
   Workspace const& w = P->w;
   CR_TRY(hipMemsetAsync(w.cg_x, 0, (size_t)nrhs * na * sizeof(double2), s));
-  CR_TRY(hipMemcpyAsync(w.cg_r, w.cg_b, (size_t)nrhs * na * sizeof(double2), hipMemcpyDeviceToDevice, s));
-  CR_TRY(launch_cg_start(P, nrhs, w.cg_b, w.cg_r, w.cg_z, w.cg_p, w.alm_a, s));
+  CR_TRY(hipMemcpyAsync(w.cg_r, b, (size_t)nrhs * na * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  CR_TRY(launch_cg_start(P, nrhs, b, w.cg_r, w.cg_z, w.cg_p, w.alm_a, s));
   CR_TRY(launch_cg_scalars(P, nrhs, 0, nb, tol, 0, s));
   CR_CHECK(read_scalars(P, nrhs, s));
 
-  std::vector<int> status(nrhs, CR_OK);
-  std::vector<double> rel(nrhs, 0.0);
+  rel.assign(nrhs, 0.0);
   int it = 0;
-  bool finished = false;
-  while (!finished) {
+  for (;;) {
     bool all_done = true;
     for (int c = 0; c < nrhs; ++c) all_done &= P->w.host_scal[c * kScalSlots + S_DONE] != 0.0;
     if (!all_done && it < maxiter) {
       const int n = std::min(check_every, maxiter - it);
       for (int k = 0; k < n; ++k) {
-        CR_CHECK(operator_core(P, nrhs, w.cg_p, w.alm_a, ninv, w.cg_q, s));
+        CR_CHECK(operator_core(P, nrhs, w.cg_p, w.alm_a, ninv, w.cg_q, s, mixed));
         CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, s));
         CR_TRY(launch_cg_update(P, nrhs, w.cg_x, w.cg_r, w.cg_z, w.cg_p, w.cg_q, s));
         CR_TRY(launch_cg_scalars(P, nrhs, 2, nb, tol, 0, s));
@@ -178,36 +195,48 @@ int pcg_f64(const crsht_plan* P, int nrhs, const double* ninv, double tol, int m
       CR_CHECK(read_scalars(P, nrhs, s));
       continue;
     }
+    if (!verify) {
+      for (int c = 0; c < nrhs; ++c) rel[c] = P->w.host_scal[c * kScalSlots + S_REL];
+      break;
+    }
     // all columns stopped (or out of iterations): confirm with the true residual
     std::vector<double> keep_scal(P->w.host_scal, P->w.host_scal + (size_t)nrhs * kScalSlots);
-    CR_CHECK(true_residual(P, nrhs, ninv, w.cg_x, w.cg_b, w.cg_r, rel, s));
+    CR_CHECK(true_residual(P, nrhs, ninv, w.cg_x, b, w.cg_r, rel, s));
     std::memcpy(P->w.host_scal, keep_scal.data(), keep_scal.size() * sizeof(double));
     bool restart = false;
     for (int c = 0; c < nrhs; ++c) {
       double* sc = P->w.host_scal + c * kScalSlots;
-      const bool broke = sc[S_BREAK] != 0.0;
-      if (!broke && rel[c] > tol && it < maxiter && sc[S_BB] > 0.0) {
+      const bool br = sc[S_BREAK] != 0.0;
+      if (!br && rel[c] > tol && it < maxiter && sc[S_BB] > 0.0) {
         sc[S_DONE] = 0.0;  // restart this column from its true residual
         restart = true;
       } else {
         sc[S_DONE] = 1.0;
       }
     }
-    if (!restart) {
-      finished = true;
-      break;
-    }
+    if (!restart) break;
     CR_CHECK(write_scalars(P, nrhs, s));
-    CR_TRY(launch_cg_start(P, nrhs, w.cg_b, w.cg_r, w.cg_z, w.cg_p, w.alm_a, s));
+    CR_TRY(launch_cg_start(P, nrhs, b, w.cg_r, w.cg_z, w.cg_p, w.alm_a, s));
     CR_TRY(launch_cg_scalars(P, nrhs, 0, nb, tol, 1, s));
     CR_CHECK(read_scalars(P, nrhs, s));
   }
+  iters.assign(nrhs, 0);
+  broke.assign(nrhs, 0);
   for (int c = 0; c < nrhs; ++c) {
     const double* sc = P->w.host_scal + c * kScalSlots;
-    stats[c].iters = (int)sc[S_ITERS];
-    stats[c].refinements = 0;
+    iters[c] = (int)sc[S_ITERS];
+    broke[c] = sc[S_BREAK] != 0.0 ? 1 : 0;
+  }
+  return CR_OK;
+}
+
+int fill_stats(int nrhs, double tol, const std::vector<int>& iters, const std::vector<int>& refine,
+               const std::vector<double>& rel, const std::vector<int>& broke, cr_stats* stats) {
+  for (int c = 0; c < nrhs; ++c) {
+    stats[c].iters = iters[c];
+    stats[c].refinements = refine[c];
     stats[c].rel_resid_true = rel[c];
-    if (sc[S_BREAK] != 0.0 || !std::isfinite(rel[c]))
+    if (broke[c] || !std::isfinite(rel[c]))
       stats[c].status = CR_BREAKDOWN;
     else if (rel[c] > tol)
       stats[c].status = CR_NOCONV;
@@ -217,12 +246,54 @@ int pcg_f64(const crsht_plan* P, int nrhs, const double* ninv, double tol, int m
   return CR_OK;
 }
 
+// FP64 iterative refinement around the mixed-precision PCG: r = b - A x in
+// FP64, inner PCG on A_mixed d = r to inner_tol, x += d, until ||r|| <= tol ||b||.
+int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_opts* o, std::vector<int>& iters,
+                  std::vector<int>& refine, std::vector<double>& rel, std::vector<int>& broke, hipStream_t s) {
+  const int64_t na = P->g.nalm;
+  Workspace const& w = P->w;
+  const int every = o->check_every > 0 ? o->check_every : 8;
+  const double itol = (o->inner_tol > 0.0 && o->inner_tol < 1.0) ? o->inner_tol : 1e-2;
+  const int maxref = o->max_refine > 0 ? o->max_refine : 30;
+  iters.assign(nrhs, 0);
+  refine.assign(nrhs, 0);
+  broke.assign(nrhs, 0);
+  CR_TRY(hipMemsetAsync(w.cg_xacc, 0, (size_t)nrhs * na * sizeof(double2), s));
+  for (int sweep = 0;; ++sweep) {
+    CR_CHECK(true_residual(P, nrhs, ninv, w.cg_xacc, w.cg_b, w.cg_r, rel, s));
+    int maxit = 0;
+    bool all = true;
+    for (int c = 0; c < nrhs; ++c) {
+      maxit = std::max(maxit, iters[c]);
+      all &= (rel[c] <= o->tol) || broke[c];
+    }
+    if (all || sweep >= maxref || maxit >= o->maxiter) break;
+    CR_TRY(hipMemcpyAsync(w.cg_bin, w.cg_r, (size_t)nrhs * na * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    for (int c = 0; c < nrhs; ++c)
+      if (rel[c] <= o->tol || broke[c])
+        CR_TRY(hipMemsetAsync(w.cg_bin + (size_t)c * na, 0, (size_t)na * sizeof(double2), s));
+    std::vector<int> it_in, br_in;
+    std::vector<double> rel_in;
+    CR_CHECK(pcg_run(P, nrhs, ninv, w.cg_bin, itol, o->maxiter - maxit, every, true, false, it_in, rel_in, br_in,
+                     s));
+    for (int c = 0; c < nrhs; ++c) {
+      if (rel[c] <= o->tol || broke[c]) continue;
+      iters[c] += it_in[c];
+      refine[c] += 1;
+      broke[c] |= br_in[c];
+    }
+    CR_TRY(launch_alm_axpby((int64_t)nrhs * na, 1.0, w.cg_xacc, 1.0, w.cg_x, w.cg_xacc, s));
+  }
+  CR_TRY(hipMemcpyAsync(w.cg_x, w.cg_xacc, (size_t)nrhs * na * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  return CR_OK;
+}
+
 int solve_core(const crsht_plan* P, const cr_problem* prob, double q, int nrhs, const double* d, const double* w0,
                const double* w1, const double* rhs, double* s_out, const cr_opts* opts, cr_stats* stats,
                hipStream_t s) {
   if (!opts || !stats || !s_out) return CR_EINVAL;
   if (!(opts->tol > 0.0) || opts->maxiter < 1) return CR_EINVAL;
-  if (opts->prec != CR_F64) return CR_ENOTSUP;
+  if (opts->prec != CR_F64 && opts->prec != CR_MIXED) return CR_EINVAL;
   const int every = opts->check_every > 0 ? opts->check_every : 8;
   CR_CHECK(set_problem(P, prob, q, s));
   CR_CHECK(compute_diag(P, prob->ninv, s));
@@ -230,7 +301,16 @@ int solve_core(const crsht_plan* P, const cr_problem* prob, double q, int nrhs, 
     CR_TRY(launch_project(P, nrhs, C2(rhs), P->w.cg_b, s));
   else
     CR_CHECK(assemble_rhs(P, nrhs, prob->ninv, d, w0, w1, P->w.cg_b, s));
-  CR_CHECK(pcg_f64(P, nrhs, prob->ninv, opts->tol, opts->maxiter, every, stats, s));
+  std::vector<int> iters, refine, broke;
+  std::vector<double> rel;
+  if (opts->prec == CR_MIXED) {
+    CR_CHECK(solve_refined(P, nrhs, prob->ninv, opts, iters, refine, rel, broke, s));
+  } else {
+    CR_CHECK(pcg_run(P, nrhs, prob->ninv, P->w.cg_b, opts->tol, opts->maxiter, every, false, true, iters, rel, broke,
+                     s));
+    refine.assign(nrhs, 0);
+  }
+  fill_stats(nrhs, opts->tol, iters, refine, rel, broke, stats);
   CR_TRY(hipMemcpyAsync(s_out, P->w.cg_x, (size_t)nrhs * P->g.nalm * sizeof(double2), hipMemcpyDeviceToDevice, s));
   CR_TRY(hipStreamSynchronize(s));
   return CR_OK;
@@ -265,16 +345,16 @@ extern "C" int sht_synth(const crsht_plan* P, int nrhs, const double* alm, doubl
                          void* stream) {
   CR_CHECK(check_plan(P, nrhs));
   if (!alm || !map) return CR_EINVAL;
-  if (prec != CR_F64) return CR_ENOTSUP;
-  return synth_f64(P, nrhs, C2(alm), P->t.rec_kappa, map, S(stream));
+  if (prec != CR_F64 && prec != CR_MIXED) return CR_EINVAL;
+  return synth_f64(P, nrhs, C2(alm), P->t.rec_kappa, map, S(stream), prec == CR_MIXED);
 }
 
 extern "C" int sht_synth_adjoint(const crsht_plan* P, int nrhs, const double* map, double* alm, cr_prec prec,
                                  void* stream) {
   CR_CHECK(check_plan(P, nrhs));
   if (!alm || !map) return CR_EINVAL;
-  if (prec != CR_F64) return CR_ENOTSUP;
-  return adjoint_f64(P, nrhs, map, C2(alm), S(stream));
+  if (prec != CR_F64 && prec != CR_MIXED) return CR_EINVAL;
+  return adjoint_f64(P, nrhs, map, C2(alm), S(stream), prec == CR_MIXED);
 }
 
 extern "C" int sht_analysis(const crsht_plan* P, int nrhs, const double* map, double* alm, int n_iter,
@@ -319,12 +399,12 @@ extern "C" int cr_apply(const crsht_plan* P, const cr_problem* prob, int nrhs, c
                         cr_prec prec, void* stream) {
   CR_CHECK(check_plan(P, nrhs));
   if (!x || !Ax) return CR_EINVAL;
-  if (prec != CR_F64) return CR_ENOTSUP;
+  if (prec != CR_F64 && prec != CR_MIXED) return CR_EINVAL;
   hipStream_t s = S(stream);
   CR_CHECK(set_problem(P, prob, 1.0, s));
   CR_TRY(launch_project(P, nrhs, C2(x), P->w.cg_d, s));
   CR_TRY(launch_scale_alm(P, nrhs, P->w.cg_d, P->w.bk, P->w.alm_a, s));
-  return operator_core(P, nrhs, P->w.cg_d, P->w.alm_a, prob->ninv, C2(Ax), s);
+  return operator_core(P, nrhs, P->w.cg_d, P->w.alm_a, prob->ninv, C2(Ax), s, prec == CR_MIXED);
 }
 
 extern "C" int cr_solve(const crsht_plan* P, const cr_problem* prob, int nrhs, const double* d, const double* w0,

@@ -54,6 +54,13 @@ struct Tables {
   int* lst_g = nullptr;            // [mmax+1][npairs] first live group of 16 steps (INT_MAX: never)
   double2* lst_s = nullptr;        // [mmax+1][npairs] (mu_{l-2}, mu_{l-1}) at the start of that group
   int64_t* mstart = nullptr;       // [mmax+2] index of a_{m,m}; mstart[mmax+1] = nalm
+  double* ones = nullptr;          // [nalm] 1.0
+  // mixed-precision (MFMA) Legendre step
+  int64_t* mx_cstart = nullptr;    // [mmax+2] first 32-step synthesis chunk of each m
+  int64_t* mx_tstart = nullptr;    // [mmax+2] first 64-step adjoint tile of each m
+  int* mx_tile_m = nullptr;        // [ntiles] m of each adjoint tile
+  double2* mx_ckpt = nullptr;      // [ntiles][npairs] recurrence state at each tile start
+  int64_t mx_ntiles = 0;
   int* idx_l = nullptr;            // [nalm] l of each stored coefficient
   int* idx_m = nullptr;            // [nalm] m of each stored coefficient
 };
@@ -78,10 +85,15 @@ struct Workspace {
   double* partial = nullptr;   // [nrhs][npart] block partial sums
   double* scal = nullptr;      // [nrhs][kScalSlots] CG scalars
   double* host_scal = nullptr; // pinned mirror of scal
+  double2* cg_xacc = nullptr;  // [nrhs][nalm] refinement: accumulated solution
+  double2* cg_bin = nullptr;   // [nrhs][nalm] refinement: right-hand side of the inner solve
+  void* mx_ab = nullptr;       // bf16 synthesis operand tiles (one group of kMixedCols columns)
+  void* mx_ag = nullptr;       // bf16 adjoint operand tiles
   int npart = 0;
 };
 
 constexpr int kScalSlots = 16;
+constexpr int kMixedCols = 32;   // MFMA N: 16 right-hand sides (re, im) per column group
 // slots of the per-column scalar block
 enum ScalSlot {
   S_RZ = 0,      // <r, z>
@@ -147,6 +159,19 @@ hipError_t launch_legendre_synth(const crsht_plan* P, int nrhs, const double2* a
 // W_p = w.ring_w[p] (the preconditioner pass; geo unused, one column).
 hipError_t launch_legendre_adjoint(const crsht_plan* P, int nrhs, const double2* geo, double2* raw, bool diag,
                                    hipStream_t s);
+
+// ---- mixed-precision Legendre step (legendre_mfma.hip) ----
+int64_t mixed_ab_bytes(const Geometry& g);
+int64_t mixed_ag_bytes(const Geometry& g);
+void mixed_starts(const Geometry& g, std::vector<int64_t>& cst, std::vector<int64_t>& tst, std::vector<int>& tm);
+hipError_t launch_checkpoints(const crsht_plan* P, hipStream_t s);
+// eo = (E, O) sums with mu (FP64 recurrence) and f * alm rounded to bf16x3,
+// FP32 accumulation; f == nullptr means 1
+hipError_t launch_legendre_synth_mixed(const crsht_plan* P, int nrhs, const double2* alm, const double* f,
+                                       double2* eo, hipStream_t s);
+// raw sums as launch_legendre_adjoint (non-diag), bf16x3 / FP32 accumulation
+hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const double2* geo, double2* raw,
+                                         hipStream_t s);
 
 // ---- ring step (ring.hip) ----
 // mode SYNTH: eo -> map;  ADJOINT: map -> geo;  FUSED: eo -> (map * ninv) -> geo

@@ -74,7 +74,9 @@ int upload(T** p, const std::vector<T>& h, size_t* total) {
 void free_plan_memory(crsht_plan* P) {
   void* ptrs[] = {P->t.pair_z, P->t.pair_nphi, P->t.pair_phi0, P->t.pair_first_n, P->t.pair_first_s,
                   P->t.pair_fft_len, P->t.pair_bs_off, P->t.pair_bk_off, P->t.bs_chirp, P->t.bs_kern,
-                  P->t.twiddle, P->t.rec_alpha, P->t.rec_kappa, P->t.lmm_v, P->t.lmm_k, P->t.lst_g, P->t.lst_s, P->t.mstart,
+                  P->t.twiddle, P->t.rec_alpha, P->t.rec_kappa, P->t.lmm_v, P->t.lmm_k, P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.ones,
+                  P->t.mx_cstart, P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_ckpt, P->w.cg_xacc, P->w.cg_bin,
+                  P->w.mx_ab, P->w.mx_ag,
                   P->t.idx_l, P->t.idx_m, P->w.eo, P->w.geo, P->w.alm_a, P->w.alm_b, P->w.cg_x, P->w.cg_r,
                   P->w.cg_z, P->w.cg_p, P->w.cg_q, P->w.cg_b, P->w.cg_d, P->w.alm_c, P->w.alm_d, P->w.map_a, P->w.ring_w,
                   P->w.diag, P->w.sinv, P->w.sinvhalf, P->w.bk, P->w.perl, P->w.partial, P->w.scal};
@@ -255,6 +257,22 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int nrhs_max
   if ((rc = dalloc(&P->t.lst_s, (size_t)(mmax + 1) * np, total))) return rc;
   if (crsht::launch_legendre_start(P, nullptr) != hipSuccess) return CR_EDEVICE;
   if (hipDeviceSynchronize() != hipSuccess) return CR_EDEVICE;
+  {
+    std::vector<double> ones(g.nalm, 1.0);
+    if ((rc = upload(&P->t.ones, ones, total))) return rc;
+  }
+  {
+    std::vector<int64_t> cst, tst;
+    std::vector<int> tm;
+    crsht::mixed_starts(g, cst, tst, tm);
+    P->t.mx_ntiles = (int64_t)tm.size();
+    if ((rc = upload(&P->t.mx_cstart, cst, total))) return rc;
+    if ((rc = upload(&P->t.mx_tstart, tst, total))) return rc;
+    if ((rc = upload(&P->t.mx_tile_m, tm, total))) return rc;
+    if ((rc = dalloc(&P->t.mx_ckpt, (size_t)P->t.mx_ntiles * np, total))) return rc;
+    if (crsht::launch_checkpoints(P, nullptr) != hipSuccess) return CR_EDEVICE;
+    if (hipDeviceSynchronize() != hipSuccess) return CR_EDEVICE;
+  }
   if ((rc = upload(&P->t.idx_l, il, total))) return rc;
   if ((rc = upload(&P->t.idx_m, im, total))) return rc;
 
@@ -269,6 +287,15 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int nrhs_max
   double2** avec[] = {&w.alm_a, &w.alm_b, &w.cg_x, &w.cg_r, &w.cg_z, &w.cg_p, &w.cg_q, &w.cg_b, &w.cg_d};
   for (double2** a : avec)
     if ((rc = dalloc(a, na, total))) return rc;
+  if ((rc = dalloc(&w.cg_xacc, na, total))) return rc;
+  if ((rc = dalloc(&w.cg_bin, na, total))) return rc;
+  {
+    unsigned char *ab = nullptr, *ag = nullptr;
+    if ((rc = dalloc(&ab, (size_t)crsht::mixed_ab_bytes(g), total))) return rc;
+    w.mx_ab = ab;
+    if ((rc = dalloc(&ag, (size_t)crsht::mixed_ag_bytes(g), total))) return rc;
+    w.mx_ag = ag;
+  }
   if ((rc = dalloc(&w.alm_c, (size_t)g.nalm, total))) return rc;
   if ((rc = dalloc(&w.alm_d, (size_t)g.nalm, total))) return rc;
   if ((rc = dalloc(&w.map_a, R * (size_t)g.npix, total))) return rc;
