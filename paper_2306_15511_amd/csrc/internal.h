@@ -43,7 +43,7 @@ struct Tables {
   int64_t* pair_bk_off = nullptr;
   double2* bs_chirp = nullptr;     // exp(-i pi j^2 / n), j < n
   double2* bs_kern = nullptr;      // FFT of the conjugate chirp filter, scaled by 1/L
-  double2* twiddle = nullptr;      // exp(-2 pi i j / fft_max), j < fft_max/2
+  double2* twiddle = nullptr;      // exp(-2 pi i j / fft_max), j < fft_max
 
   // Legendre recurrence (scaled form mu_l = lambda_l / kappa_l):
   //   mu_m = lambda_mm, mu_{m-1} = 0, mu_l = alpha_lm z mu_{l-1} - mu_{l-2} for l > m

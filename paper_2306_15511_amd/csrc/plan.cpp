@@ -174,8 +174,8 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int nrhs_max
     for (int j = 0; j < L; ++j)
       kern.push_back(make_double2((double)(b[j].real() / (ld)L), (double)(b[j].imag() / (ld)L)));
   }
-  std::vector<double2> tw(fft_max / 2);
-  for (int j = 0; j < fft_max / 2; ++j) {
+  std::vector<double2> tw(fft_max);
+  for (int j = 0; j < fft_max; ++j) {
     const ld ang = -2.0L * kPi * (ld)j / (ld)fft_max;
     tw[j] = make_double2((double)cosl(ang), (double)sinl(ang));
   }
@@ -321,7 +321,7 @@ extern "C" int crsht_plan_create(int nside, int lmax, int mmax, int ncomp, int n
   if (mmax < 0) mmax = lmax;
   if (nside < 1 || lmax < 0 || mmax > lmax || nrhs_max < 1 || nrhs_max > 4096) return CR_EINVAL;
   if (lmax > 16383) return CR_EINVAL;
-  if (nside > 1024) return CR_ENOTSUP;  // adjoint kernel holds at most 16 ring pairs per thread x 128 threads
+  if (nside > 1024) return CR_ENOTSUP;  // FP64 adjoint: at most 8 ring pairs per thread x 256 threads
   if (ncomp != 1) return ncomp == 3 ? CR_ENOTSUP : CR_EINVAL;
   crsht_plan* P = new (std::nothrow) crsht_plan();
   if (!P) return CR_ENOMEM;
