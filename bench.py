@@ -141,7 +141,7 @@ def main():
 
     for _ in range(args.warmup):
         _, st = step()
-        print("warmup: iters %s resid %s" % ([s.iters for s in st], [s.rel_resid_true for s in st]),
+        print("warmup: iters %s resid %s" % ([s.iters for s in st], ["%.2e" % s.rel_resid_true for s in st]),
               file=sys.stderr, flush=True)
     crsht.timing_enable(plan, True)
     torch.cuda.synchronize()
@@ -152,7 +152,8 @@ def main():
         _, st = step()
         iters.append(max(s.iters for s in st))
         stats.append(st)
-        print("step %d: iters %s resid %s" % (k, [s.iters for s in st], [s.rel_resid_true for s in st]),
+        print("step %d: iters %s refinements %s resid %s" % (k, [s.iters for s in st], [s.refinements for s in st],
+                                                             ["%.2e" % s.rel_resid_true for s in st]),
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0

@@ -129,16 +129,18 @@ typedef struct {
 typedef struct {
   double tol;          /* target relative residual ||b - A s|| / ||b|| (real-field norm), > 0 */
   int maxiter;         /* maximum CG iterations (all refinement sweeps together), >= 1 */
-  cr_prec prec;        /* CR_F64: plain PCG; CR_MIXED: FP64 refinement around a mixed inner PCG */
-  double inner_tol;    /* CR_MIXED: relative tolerance of each inner solve (e.g. 1e-2); ignored for CR_F64 */
-  int max_refine;      /* CR_MIXED: maximum refinement sweeps */
+  cr_prec prec;        /* CR_F64: plain PCG; CR_MIXED: PCG on the mixed operator with FP64 residual
+                          replacement (iterative refinement that keeps the search directions) */
+  double inner_tol;    /* CR_MIXED: the FP64 true residual replaces the recursive one each time the latter
+                          has dropped by this factor (0 < inner_tol < 1, e.g. 1e-2); ignored for CR_F64 */
+  int max_refine;      /* CR_MIXED: maximum number of FP64 residual replacements (0 = 1000) */
   int check_every;     /* iterations between host convergence checks (>= 1; 0 = 8) */
 } cr_opts;
 
 typedef struct {
   int status;              /* CR_OK, CR_NOCONV or CR_BREAKDOWN */
   int iters;               /* CG iterations (inner iterations summed for CR_MIXED) */
-  int refinements;         /* refinement sweeps (0 for CR_F64) */
+  int refinements;         /* FP64 residual replacements (0 for CR_F64) */
   double rel_resid_true;   /* ||b - A s|| / ||b|| evaluated in FP64 at exit */
 } cr_stats;
 

@@ -246,45 +246,104 @@ int fill_stats(int nrhs, double tol, const std::vector<int>& iters, const std::v
   return CR_OK;
 }
 
-// FP64 iterative refinement around the mixed-precision PCG: r = b - A x in
-// FP64, inner PCG on A_mixed d = r to inner_tol, x += d, until ||r|| <= tol ||b||.
+// FP64 refinement around the mixed-precision PCG by residual replacement
+// ("reliable updates"): PCG runs with the mixed operator, and whenever the
+// recursive residual of a column has dropped by inner_tol since the last
+// replacement (or claims convergence), the residuals of all columns are
+// replaced by the true FP64 residuals b - A x; z and <r,z> are recomputed and
+// the search directions kept, so the Krylov space is not discarded. A column
+// stops when its true relative residual is at most tol.
 int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_opts* o, std::vector<int>& iters,
                   std::vector<int>& refine, std::vector<double>& rel, std::vector<int>& broke, hipStream_t s) {
+  // PCG on the mixed-precision operator with FP64 vectors and reliable updates:
+  // every time a column's recursive residual has fallen by inner_tol since its
+  // last replacement (or claims convergence), r is replaced by the FP64 true
+  // residual b - A x right after the x, r update and before the direction
+  // update, so beta and p continue from the replaced residual.  A column whose
+  // true residual did not fall since its last replacement restarts its
+  // direction (beta = 0).
   const int64_t na = P->g.nalm;
+  const int nb = vec_reduce_blocks(P);
   Workspace const& w = P->w;
   const int every = o->check_every > 0 ? o->check_every : 8;
   const double itol = (o->inner_tol > 0.0 && o->inner_tol < 1.0) ? o->inner_tol : 1e-2;
-  const int maxref = o->max_refine > 0 ? o->max_refine : 30;
-  iters.assign(nrhs, 0);
+  const int maxref = o->max_refine > 0 ? o->max_refine : 1000;
+  const double tol = o->tol;
   refine.assign(nrhs, 0);
-  broke.assign(nrhs, 0);
-  CR_TRY(hipMemsetAsync(w.cg_xacc, 0, (size_t)nrhs * na * sizeof(double2), s));
-  for (int sweep = 0;; ++sweep) {
-    CR_CHECK(true_residual(P, nrhs, ninv, w.cg_xacc, w.cg_b, w.cg_r, rel, s));
-    int maxit = 0;
-    bool all = true;
+  CR_TRY(hipMemsetAsync(w.cg_x, 0, (size_t)nrhs * na * sizeof(double2), s));
+  CR_TRY(hipMemcpyAsync(w.cg_r, w.cg_b, (size_t)nrhs * na * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  CR_TRY(launch_cg_start(P, nrhs, w.cg_b, w.cg_r, w.cg_z, w.cg_p, w.alm_a, s));
+  CR_TRY(launch_cg_scalars(P, nrhs, 0, nb, tol, 0, s));
+  CR_CHECK(read_scalars(P, nrhs, s));
+  std::vector<double> last(nrhs, 1.0);   // true relative residual at the last replacement
+  rel.assign(nrhs, 1.0);
+  int it = 0, nrep = 0;
+  bool pending = false;                  // direction update of the last iteration not yet applied
+  for (;;) {
+    bool need = false;
+    std::vector<char> trig(nrhs, 0);
     for (int c = 0; c < nrhs; ++c) {
-      maxit = std::max(maxit, iters[c]);
-      all &= (rel[c] <= o->tol) || broke[c];
+      const double* sc = P->w.host_scal + c * kScalSlots;
+      if (sc[S_BREAK] != 0.0 || rel[c] <= tol) continue;
+      if (sc[S_DONE] != 0.0 || sc[S_REL] <= itol * last[c]) need = true, trig[c] = 1;
     }
-    if (all || sweep >= maxref || maxit >= o->maxiter) break;
-    CR_TRY(hipMemcpyAsync(w.cg_bin, w.cg_r, (size_t)nrhs * na * sizeof(double2), hipMemcpyDeviceToDevice, s));
-    for (int c = 0; c < nrhs; ++c)
-      if (rel[c] <= o->tol || broke[c])
-        CR_TRY(hipMemsetAsync(w.cg_bin + (size_t)c * na, 0, (size_t)na * sizeof(double2), s));
-    std::vector<int> it_in, br_in;
-    std::vector<double> rel_in;
-    CR_CHECK(pcg_run(P, nrhs, ninv, w.cg_bin, itol, o->maxiter - maxit, every, true, false, it_in, rel_in, br_in,
-                     s));
-    for (int c = 0; c < nrhs; ++c) {
-      if (rel[c] <= o->tol || broke[c]) continue;
-      iters[c] += it_in[c];
-      refine[c] += 1;
-      broke[c] |= br_in[c];
+    if (need && pending && nrep < maxref) {
+      std::vector<double> keep(P->w.host_scal, P->w.host_scal + (size_t)nrhs * kScalSlots);
+      CR_CHECK(true_residual(P, nrhs, ninv, w.cg_x, w.cg_b, w.cg_r, rel, s));
+      ++nrep;
+      std::memcpy(P->w.host_scal, keep.data(), keep.size() * sizeof(double));
+      bool cont = false;
+      for (int c = 0; c < nrhs; ++c) {
+        double* sc = P->w.host_scal + c * kScalSlots;
+        if (sc[S_BREAK] != 0.0) continue;
+        sc[S_RESTART] = (trig[c] && rel[c] >= last[c]) ? 1.0 : 0.0;
+        last[c] = rel[c];
+        refine[c] += 1;
+        if (rel[c] <= tol) {
+          sc[S_DONE] = 1.0;
+        } else if (it < o->maxiter) {
+          sc[S_DONE] = 0.0;
+          cont = true;
+        } else {
+          sc[S_DONE] = 1.0;
+        }
+      }
+      if (!cont) break;
+      // z = D^-1 r from the replaced residual, beta = <r,z>/<r,z>_prev
+      CR_CHECK(write_scalars(P, nrhs, s));
+      CR_TRY(launch_cg_replace(P, nrhs, w.cg_r, w.cg_z, s));
+      CR_TRY(launch_cg_scalars(P, nrhs, 3, nb, tol, 0, s));
     }
-    CR_TRY(launch_alm_axpby((int64_t)nrhs * na, 1.0, w.cg_xacc, 1.0, w.cg_x, w.cg_xacc, s));
+    if (pending) {
+      CR_TRY(launch_cg_pupdate(P, nrhs, w.cg_z, w.cg_p, w.alm_a, s));
+      pending = false;
+    }
+    bool any = false;
+    for (int c = 0; c < nrhs; ++c) any |= P->w.host_scal[c * kScalSlots + S_DONE] == 0.0;
+    if (!any) break;   // every column confirmed by its true residual (or broken down)
+    if (it >= o->maxiter) {
+      CR_CHECK(true_residual(P, nrhs, ninv, w.cg_x, w.cg_b, w.cg_r, rel, s));
+      break;
+    }
+    const int n = std::min(every, o->maxiter - it);
+    for (int k = 0; k < n; ++k) {
+      if (pending) CR_TRY(launch_cg_pupdate(P, nrhs, w.cg_z, w.cg_p, w.alm_a, s));
+      CR_CHECK(operator_core(P, nrhs, w.cg_p, w.alm_a, ninv, w.cg_q, s, true));
+      CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, s));
+      CR_TRY(launch_cg_update(P, nrhs, w.cg_x, w.cg_r, w.cg_z, w.cg_p, w.cg_q, s));
+      CR_TRY(launch_cg_scalars(P, nrhs, 2, nb, tol, 0, s));
+      pending = true;
+    }
+    it += n;
+    CR_CHECK(read_scalars(P, nrhs, s));
   }
-  CR_TRY(hipMemcpyAsync(w.cg_x, w.cg_xacc, (size_t)nrhs * na * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  iters.assign(nrhs, 0);
+  broke.assign(nrhs, 0);
+  for (int c = 0; c < nrhs; ++c) {
+    const double* sc = P->w.host_scal + c * kScalSlots;
+    iters[c] = (int)sc[S_ITERS];
+    broke[c] = sc[S_BREAK] != 0.0 ? 1 : 0;
+  }
   return CR_OK;
 }
 

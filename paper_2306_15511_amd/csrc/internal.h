@@ -106,10 +106,11 @@ enum ScalSlot {
   S_REL = 7,     // last relative residual
   S_ITERS = 8,   // iterations taken
   S_BREAK = 9,   // 1 on breakdown
-  S_RZ_NEW = 10,
+  S_RZ_PREV = 10,  // <r, z> of the previous iteration (beta after a residual replacement)
   S_AUX0 = 11,
   S_AUX1 = 12,
   S_AUX2 = 13,
+  S_RESTART = 14,  // host flag: the next replacement restarts the direction (beta = 0)
 };
 
 constexpr int kTimedKernels = 3;  // 0 Legendre synthesis, 1 Legendre adjoint, 2 ring pass
@@ -208,6 +209,7 @@ hipError_t launch_cg_scalars(const crsht_plan* P, int nrhs, int what, int nb, do
                              hipStream_t s);
 hipError_t launch_cg_update(const crsht_plan* P, int nrhs, double2* x, double2* r, double2* z, const double2* p,
                             const double2* q, hipStream_t s);
+hipError_t launch_cg_replace(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s);
 hipError_t launch_cg_pupdate(const crsht_plan* P, int nrhs, const double2* z, double2* p, double2* pt,
                              hipStream_t s);
 hipError_t launch_residual(const crsht_plan* P, int nrhs, const double2* b, const double2* ax, double2* r,

@@ -180,7 +180,8 @@ __global__ void k_cg_start(int64_t nalm, const int* __restrict__ idx_m, const do
   }
 }
 
-// sums partial[c][slot-row][0..nb) into scal; what = 0: start, 1: alpha, 2: beta
+// sums partial[c][slot-row][0..nb) into scal; what = 0: start, 1: alpha, 2: beta,
+// 3: residual replacement
 __global__ void k_cg_scalars(int what, int nb, const double* __restrict__ partial, int npart,
                              double* __restrict__ scal, double tol, int restart) {
   __shared__ double sh[kVecBlock];
@@ -221,10 +222,17 @@ __global__ void k_cg_scalars(int what, int nb, const double* __restrict__ partia
     } else {
       sc[S_ALPHA] = sc[S_RZ] / s0;
     }
+  } else if (what == 3) {  // residual replaced after the update: beta from the new <r,z>
+    if (sc[S_DONE] != 0.0) return;
+    sc[S_BETA] = sc[S_RESTART] != 0.0 ? 0.0 : s0 / sc[S_RZ_PREV];
+    sc[S_RZ] = s0;
+    sc[S_RR] = s1;
+    sc[S_REL] = sc[S_BB] > 0.0 ? sqrt(s1 / sc[S_BB]) : 0.0;
   } else {  // beta after the update
     if (sc[S_DONE] != 0.0) return;
     const double rznew = s0, rr = s1;
     sc[S_ITERS] += 1.0;
+    sc[S_RZ_PREV] = sc[S_RZ];
     sc[S_BETA] = rznew / sc[S_RZ];
     sc[S_RZ] = rznew;
     sc[S_RR] = rr;
@@ -267,6 +275,32 @@ __global__ void k_cg_update(int64_t nalm, const int* __restrict__ idx_m, const d
       rz += wdot(m, rv, zv);
       rr += wdot(m, rv, rv);
     }
+  }
+  rz = block_sum(rz, sh);
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    double* pa = partial + (size_t)c * npart * 4;
+    pa[blockIdx.x] = rz;
+    pa[npart + blockIdx.x] = rr;
+  }
+}
+
+// residual replacement: z = r / D; partial <r,z>, <r,r> (p untouched)
+__global__ void k_cg_replace(int64_t nalm, const int* __restrict__ idx_m, const double* __restrict__ diag,
+                             const double2* __restrict__ r, double2* __restrict__ z, double* __restrict__ partial,
+                             int npart) {
+  __shared__ double sh[kVecBlock];
+  const int c = blockIdx.y;
+  double rz = 0.0, rr = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nalm; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ci = c * nalm + i;
+    const int m = idx_m[i];
+    const double2 rv = r[ci];
+    const double dinv = 1.0 / diag[i];
+    const double2 zv = make_double2(rv.x * dinv, rv.y * dinv);
+    z[ci] = zv;
+    rz += wdot(m, rv, zv);
+    rr += wdot(m, rv, rv);
   }
   rz = block_sum(rz, sh);
   rr = block_sum(rr, sh);
@@ -492,6 +526,13 @@ hipError_t launch_cg_update(const crsht_plan* P, int nrhs, double2* x, double2* 
   const int nb = vec_reduce_blocks(P);
   hipLaunchKernelGGL(k_cg_update, dim3(nb, nrhs), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_m, P->w.diag,
                      P->w.bk, x, r, z, p, q, P->w.partial, P->w.npart, P->w.scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_replace(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s) {
+  const int nb = vec_reduce_blocks(P);
+  hipLaunchKernelGGL(k_cg_replace, dim3(nb, nrhs), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_m, P->w.diag, r, z,
+                     P->w.partial, P->w.npart);
   return hipGetLastError();
 }
 
