@@ -4,20 +4,24 @@
 Workload (temperature, HEALPix Nside 512, lmax 1535): C_l = A/(l(l+1)) with a
 100 uK pixel rms, Gaussian beam FWHM 10 arcmin, anisotropic white noise
 sigma_p = 30 uK / sqrt(h_p) with h_p = 1 + 4 sin^2(ecliptic-like latitude),
-N^-1 = 0 in the band |b| < 20 deg, data d = Y B a_true + n, fresh w0/w1; one
-step = one full constrained-realization solve (right-hand side, Jacobi
-diagonal and all PCG iterations, FP64) to relative residual 1e-6, for
-`--nrhs` independent columns at once. Inputs are resident on the GPU before
-timing starts.
+N^-1 = 0 in the band |b| < 20 deg, data d = Y B a_true + n, fresh w0/w1 per
+column. One step = one full constrained-realization solve (right-hand side,
+Jacobi diagonal and all PCG iterations) to a true relative residual of 1e-6
+for `--nrhs` independent columns at once. The default is the batched
+mixed-precision form (16 columns, bf16x3 MFMA Legendre steps inside PCG with
+FP64 vectors, scalars and residual replacement); `--prec f64` runs the plain
+FP64 form. Unless `--no-f64-compare` is given, one plain FP64 single-column
+solve of column 0 is timed as well (reported beside the headline, never as
+`value`). Inputs are resident on the GPU before timing starts.
 
-Prints one JSON line (see the keys below). --gpus N with N > 1 is refused:
-this build runs on one GPU.
+Prints one JSON line. --gpus N with N > 1 is refused: this build runs on one
+GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -27,8 +31,16 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+# MI355X published peaks
+FP64_VECTOR_PEAK_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+BF16_MFMA_PEAK_TFLOPS = 2500.0     # dense
 HBM_PEAK_GBS = 8000.0
+
+# HBM traffic of a kernel per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# runs of `paper_2306_15511_amd/kernel_probe.py operator --nrhs 16 --prec mixed`
+# at Nside 512, scaled by the same counters on a 1 GiB copy (FETCH x 2.0,
+# WRITE x 1.0); valid only while the kernel's source file hashes to `src`.
+TRAFFIC = {}
 
 
 def legendre_triples(nside: int, lmax: int, mmax: int) -> int:
@@ -36,27 +48,34 @@ def legendre_triples(nside: int, lmax: int, mmax: int) -> int:
     return sum(lmax - m + 1 for m in range(mmax + 1)) * (2 * nside)
 
 
-def cpu_baseline(wl, iters: int):
+def pick_nr(n: int) -> int:
+    return 8 if n >= 8 else 4 if n >= 4 else 2 if n >= 2 else 1
+
+
+def src_hash(rel: str) -> str:
+    with open(os.path.join(ROOT, "paper_2306_15511_amd", "csrc", rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def cpu_baseline(wl, iters: int, iters_src: str):
     """Oracle (numpy FP64) SHT pair on a bounded sample: the Legendre and
-    azimuthal steps of one synthesis + adjoint restricted to every 8th ring
-    pair, scaled to the full ring count; solves/s = 1/(t_pair * iters)."""
+    azimuthal steps of one synthesis + adjoint restricted to every 16th ring,
+    scaled to the full ring count; solves/s = 1/(t_pair * iters)."""
     from oracle import sht as osht
     from oracle.legendre import lambda_rows
     import crinputs as ci
     S = osht.SHT(wl.nside, wl.lmax)
     R = S.rings
     nr = R.nrings
-    sel = np.arange(0, nr, 16)        # 1 in 16 rings = 1 in 8 ring pairs
+    sel = np.arange(0, nr, 16)
     a = ci.white_alm(np.random.default_rng(1), wl.lmax)
     x = np.random.default_rng(2).standard_normal(S.npix)
     t0 = time.perf_counter()
-    # Legendre synthesis on the sampled rings
     z, st = R.z[sel], R.sin_theta[sel]
     F = np.zeros((S.mmax + 1, sel.size), dtype=np.complex128)
     for l, lam in lambda_rows(S.lmax, S.mmax, z, st):
         top = lam.shape[0] - 1
         F[:top + 1] += lam * a[S._idx(l, top)][:, None]
-    # azimuthal synthesis + adjoint on the sampled rings
     m = np.arange(S.mmax + 1)
     G = np.empty_like(F)
     for j, k in enumerate(sel):
@@ -66,7 +85,6 @@ def cpu_baseline(wl, iters: int):
         _ = (n * np.fft.ifft(c)).real
         X = np.fft.fft(x[f0:f0 + n])
         G[:, j] = np.exp(-1j * m * R.phi0[k]) * X[m % n]
-    # Legendre adjoint on the sampled rings
     out = np.zeros(S.nalm, dtype=np.complex128)
     for l, lam in lambda_rows(S.lmax, S.mmax, z, st):
         top = lam.shape[0] - 1
@@ -76,15 +94,14 @@ def cpu_baseline(wl, iters: int):
     cores = len(os.sched_getaffinity(0))
     try:
         import threadpoolctl
-        info = threadpoolctl.threadpool_info()
-        used = max([d.get("num_threads", 1) for d in info] or [1])
+        used = max([d.get("num_threads", 1) for d in threadpoolctl.threadpool_info()] or [1])
         cores = min(cores, used) if used else cores
     except Exception:
         pass
     return {"value": 1.0 / (t_pair * max(iters, 1)), "unit": "solves/s", "cores": cores, "kind": "oracle",
             "sample": "numpy FP64 oracle SHT pair (Legendre + FFT synthesis and adjoint) on %d of %d rings "
-                      "(%.1f s), scaled to all rings: %.1f s per SHT pair; solves/s = 1/(s per pair x %d GPU "
-                      "iterations)" % (sel.size, nr, t, t_pair, iters),
+                      "(%.1f s), scaled to all rings: %.1f s per SHT pair; solves/s = 1/(s per pair x %d "
+                      "iterations, %s)" % (sel.size, nr, t, t_pair, iters, iters_src),
             "sht_pairs_per_s": 1.0 / t_pair}
 
 
@@ -93,12 +110,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--nrhs", type=int, default=16)
     ap.add_argument("--nside", type=int, default=512)
     ap.add_argument("--lmax", type=int, default=None)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--prec", choices=["f64", "mixed"], default="f64")
+    ap.add_argument("--prec", choices=["f64", "mixed"], default="mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f64-compare", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported "
@@ -114,6 +132,7 @@ def main():
     wl = ci.workload_masked_t(nside, lmax, fwhm_arcmin=10.0, cfg=2)
     wl.tol = args.tol
     R = args.nrhs
+    mixed = args.prec == "mixed"
     dev = torch.device("cuda:0")
     plan = crsht.Plan(nside, lmax, nrhs_max=R)
     z, phi = plan.pixel_coords()
@@ -133,11 +152,25 @@ def main():
     out = torch.empty((R, plan.nalm), dtype=torch.complex128, device=dev)
     torch.cuda.synchronize()
 
-    prec = crsht.CR_MIXED if args.prec == "mixed" else crsht.CR_F64
+    prec = crsht.CR_MIXED if mixed else crsht.CR_F64
 
     def step():
         return crsht.solve(plan, prob, d, w0, w1, nrhs=R, tol=wl.tol, maxiter=20000, out=out, check_every=16,
                            prec=prec, inner_tol=1e-2)
+
+    f64_cmp = None
+    if not args.no_f64_compare:
+        out1 = torch.empty((1, plan.nalm), dtype=torch.complex128, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st1 = crsht.solve(plan, prob, d[:1], w0[:1], w1[:1], nrhs=1, tol=wl.tol, maxiter=20000, out=out1,
+                             check_every=16, prec=crsht.CR_F64)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter() - t0
+        f64_cmp = {"form": "plain FP64 PCG, 1 column (column 0 of the batch)", "solves_per_s": 1.0 / t1,
+                   "iters": st1[0].iters, "rel_resid_true": st1[0].rel_resid_true}
+        print("f64 single: %.3f s, iters %d, resid %.2e" % (t1, st1[0].iters, st1[0].rel_resid_true),
+              file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         _, st = step()
@@ -146,32 +179,60 @@ def main():
     crsht.timing_enable(plan, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters = []
     stats = []
     for k in range(args.steps):
         _, st = step()
-        iters.append(max(s.iters for s in st))
         stats.append(st)
         print("step %d: iters %s refinements %s resid %s" % (k, [s.iters for s in st], [s.refinements for s in st],
                                                              ["%.2e" % s.rel_resid_true for s in st]),
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms_syn, n_syn = crsht.timing_read(plan, crsht.KERNEL_LEGENDRE_SYNTH)
-    ms_adj, n_adj = crsht.timing_read(plan, crsht.KERNEL_LEGENDRE_ADJOINT)
-    ms_ring, n_ring = crsht.timing_read(plan, crsht.KERNEL_RING)
+    tm = {k: crsht.timing_read(plan, k) for k in range(5)}
     crsht.timing_enable(plan, False)
 
     solves = args.steps * R
     sps = solves / dt
     tot_iters = sum(sum(s.iters for s in st) for st in stats)
-    # operator applications per solve = iterations + final true-residual check(s)
-    pairs_per_s = tot_iters / dt
+
+    # algorithmic work per timed unit (one launch; an FP64 adjoint unit is a whole transform)
     T = legendre_triples(nside, lmax, lmax)
-    flops_syn = (3 + 4 * R) * T        # recurrence (mul + FMA) + complex contraction per column
-    avg_syn = ms_syn / max(n_syn, 1) * 1e-3
-    avg_adj = ms_adj / max(n_adj, 1) * 1e-3
-    achieved = flops_syn / avg_syn / 1e12 if avg_syn > 0 else 0.0
+    eo_bytes = 2 * nside * (lmax + 1) * 2 * 16         # Legendre sums of one column (E and O, complex FP64)
+    groups = []
+    n = R
+    while n > 0:
+        groups.append(pick_nr(n))
+        n -= groups[-1]
+    kinfo = {
+        2: ("k_ring<RING_FUSED> (azimuthal FFT pass, N^-1 fused)", "hbm", R * 2 * eo_bytes + plan.npix * 8,
+            HBM_PEAK_GBS, "GB/s", "ring.hip"),
+    }
+    if mixed:
+        for kid, name in ((3, "k_synth_mfma (bf16x3 MFMA Legendre synthesis)"),
+                          (4, "k_adj_mfma (bf16x3 MFMA Legendre adjoint)")):
+            kinfo[kid] = (name, "mfma", 4 * min(R, 16) * T, BF16_MFMA_PEAK_TFLOPS, "TFLOP/s", "legendre_mfma.hip")
+    else:
+        kinfo[0] = ("k_legendre_synth (FP64 VALU)", "alu", sum((3 + 4 * g) * T for g in groups) / len(groups),
+                    FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s", "legendre.hip")
+        kinfo[1] = ("k_legendre_adj (FP64 VALU, whole transform)", "alu", sum((3 + 4 * g) * T for g in groups),
+                    FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s", "legendre.hip")
+    roofs = {}
+    for kid, (name, bound, work, peak, unit, src) in kinfo.items():
+        ms, nl = tm[kid]
+        if nl == 0:
+            continue
+        avg = ms / nl * 1e-3
+        achieved = work / avg / (1e9 if unit == "GB/s" else 1e12)
+        tr = TRAFFIC.get(name.split(" ")[0])
+        traffic = None
+        if tr is not None and tr["src"] == src_hash(src):
+            traffic = tr["bytes"]
+        roofs[name] = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+                       "traffic": traffic, "work_per_launch": work, "avg_launch_ms": avg * 1e3,
+                       "launches": nl, "total_ms": ms}
+    dom = max(roofs, key=lambda k: roofs[k]["total_ms"])
+    roof = dict(roofs[dom])
+    roof["kernel"] = dom
     res = {
         "metric": "constrained-realization CG solves/s at Nside=512, lmax=1535; SHT pairs/s",
         "value": sps,
@@ -183,23 +244,28 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "bf16x3+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": "T-only CR solve, Nside %d, lmax %d, hit-pattern noise, |b|<20deg mask, "
-                               "FWHM 10', tol %g, FP64 PCG" % (nside, lmax, wl.tol),
-                   "nside": nside, "lmax": lmax, "nrhs": R, "tol": wl.tol, "precision": "CR_F64"},
-        "sht_pairs_per_s": pairs_per_s,
+        "config": {"workload": "T-only constrained-realization PCG solve, Nside %d, lmax %d, hit-pattern noise, "
+                               "|b|<20deg mask, FWHM 10', true residual %g, %d columns per solve, %s"
+                               % (nside, lmax, wl.tol, R, "bf16x3 MFMA Legendre + FP64 vectors and residual "
+                                  "replacement" if mixed else "FP64"),
+                   "nside": nside, "lmax": lmax, "nrhs": R, "tol": wl.tol,
+                   "precision": "CR_MIXED" if mixed else "CR_F64"},
+        "sht_pairs_per_s": tot_iters / dt,
         "iters_per_solve": tot_iters / solves,
         "rel_resid_true_max": max(s.rel_resid_true for st in stats for s in st),
-        "kernel_ms": {"legendre_synth": avg_syn * 1e3, "legendre_adjoint": avg_adj * 1e3,
-                      "ring": ms_ring / max(n_ring, 1)},
-        "roofline": {"bound": "alu", "kernel": "k_legendre_synth (FP64 VALU)", "achieved": achieved,
-                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "flops_per_launch": flops_syn, "launches": n_syn},
+        "roofline": roof,
+        "kernels": roofs,
     }
+    if f64_cmp is not None:
+        res["f64_single_column"] = f64_cmp
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(wl, int(round(tot_iters / solves)))
+        if f64_cmp is not None:
+            it, src = f64_cmp["iters"], "the FP64 GPU solve's count for column 0"
+        else:
+            it, src = int(round(tot_iters / solves)), "the benchmarked solves' mean count"
+        res["cpu_baseline"] = cpu_baseline(wl, it, src)
     print(json.dumps(res))
     plan.close()
 

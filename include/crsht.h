@@ -221,8 +221,9 @@ int joint_cl_step(const crsht_plan *plan, const cr_problem *fid, const double *d
  * crsht_timing_enable(plan, 1) synchronises the device, clears the counters
  * and makes the library bracket every launch of the tracked kernels with a
  * pair of HIP events on the launch stream; 0 turns it off. Tracked kernels:
- * 0 = Legendre synthesis, 1 = Legendre adjoint (incl. the preconditioner
- * diagonal pass), 2 = ring (azimuthal FFT) pass.
+ * 0 = FP64 Legendre synthesis, 1 = FP64 Legendre adjoint (incl. the
+ * preconditioner diagonal pass), 2 = ring (azimuthal FFT) pass,
+ * 3 = bf16x3 MFMA Legendre synthesis, 4 = bf16x3 MFMA Legendre adjoint.
  * crsht_timing_read waits for the recorded events and returns the summed
  * duration (milliseconds) and the number of launches since enabling. */
 int crsht_timing_enable(const crsht_plan *plan, int on);

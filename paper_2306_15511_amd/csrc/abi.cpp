@@ -31,6 +31,8 @@ hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 const double2* C2(const double* p) { return reinterpret_cast<const double2*>(p); }
 double2* C2(double* p) { return reinterpret_cast<double2*>(p); }
+// the Legendre-sum buffers hold float2 values in the mixed-precision path
+float2* F2(double2* p) { return reinterpret_cast<float2*>(p); }
 
 int64_t eo_stride(const crsht_plan* P) { return (int64_t)P->g.npairs * (P->g.mmax + 1) * 2; }
 
@@ -70,12 +72,12 @@ int set_problem(const crsht_plan* P, const cr_problem* prob, double q, hipStream
 int operator_core(const crsht_plan* P, int nrhs, const double2* x, const double2* pt, const double* ninv,
                   double2* out, hipStream_t s, bool mixed = false) {
   if (mixed)
-    CR_TRY(launch_legendre_synth_mixed(P, nrhs, pt, nullptr, P->w.eo, s));
+    CR_TRY(launch_legendre_synth_mixed(P, nrhs, pt, nullptr, F2(P->w.eo), s));
   else
     CR_TRY(launch_legendre_synth(P, nrhs, pt, P->w.eo, s));
-  CR_TRY(launch_ring(P, nrhs, RING_FUSED, P->w.eo, nullptr, ninv, P->w.geo, s));
+  CR_TRY(launch_ring(P, nrhs, RING_FUSED, P->w.eo, nullptr, ninv, P->w.geo, mixed, s));
   if (mixed)
-    CR_TRY(launch_legendre_adjoint_mixed(P, nrhs, P->w.geo, P->w.alm_b, s));
+    CR_TRY(launch_legendre_adjoint_mixed(P, nrhs, F2(P->w.geo), P->w.alm_b, s));
   else
     CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, P->w.alm_b, false, s));
   CR_TRY(launch_cg_q(P, nrhs, x, P->w.alm_b, out, s));
@@ -96,7 +98,7 @@ int assemble_rhs(const crsht_plan* P, int nrhs, const double* ninv, const double
   const double2* braw = nullptr;
   if (d || w1) {
     CR_TRY(launch_pix_rhs(P, nrhs, ninv, d, w1, P->w.map_a, s));
-    CR_TRY(launch_ring(P, nrhs, RING_ADJOINT, nullptr, P->w.map_a, nullptr, P->w.geo, s));
+    CR_TRY(launch_ring(P, nrhs, RING_ADJOINT, nullptr, P->w.map_a, nullptr, P->w.geo, false, s));
     CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, P->w.alm_b, false, s));
     braw = P->w.alm_b;
   }
@@ -107,19 +109,19 @@ int assemble_rhs(const crsht_plan* P, int nrhs, const double* ninv, const double
 int synth_f64(const crsht_plan* P, int nrhs, const double2* alm, const double* scale, double* map, hipStream_t s,
               bool mixed = false) {
   if (mixed) {
-    CR_TRY(launch_legendre_synth_mixed(P, nrhs, alm, scale, P->w.eo, s));
+    CR_TRY(launch_legendre_synth_mixed(P, nrhs, alm, scale, F2(P->w.eo), s));
   } else {
     CR_TRY(launch_scale_alm(P, nrhs, alm, scale, P->w.alm_a, s));
     CR_TRY(launch_legendre_synth(P, nrhs, P->w.alm_a, P->w.eo, s));
   }
-  CR_TRY(launch_ring(P, nrhs, RING_SYNTH, P->w.eo, map, nullptr, nullptr, s));
+  CR_TRY(launch_ring(P, nrhs, RING_SYNTH, P->w.eo, map, nullptr, nullptr, mixed, s));
   return CR_OK;
 }
 
 int adjoint_f64(const crsht_plan* P, int nrhs, const double* map, double2* alm, hipStream_t s, bool mixed = false) {
-  CR_TRY(launch_ring(P, nrhs, RING_ADJOINT, nullptr, const_cast<double*>(map), nullptr, P->w.geo, s));
+  CR_TRY(launch_ring(P, nrhs, RING_ADJOINT, nullptr, const_cast<double*>(map), nullptr, P->w.geo, mixed, s));
   if (mixed)
-    CR_TRY(launch_legendre_adjoint_mixed(P, nrhs, P->w.geo, alm, s));
+    CR_TRY(launch_legendre_adjoint_mixed(P, nrhs, F2(P->w.geo), alm, s));
   else
     CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, alm, false, s));
   CR_TRY(launch_scale_alm(P, nrhs, alm, P->t.rec_kappa, alm, s));

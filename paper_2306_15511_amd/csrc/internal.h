@@ -44,6 +44,10 @@ struct Tables {
   double2* bs_chirp = nullptr;     // exp(-i pi j^2 / n), j < n
   double2* bs_kern = nullptr;      // FFT of the conjugate chirp filter, scaled by 1/L
   double2* twiddle = nullptr;      // exp(-2 pi i j / fft_max), j < fft_max
+  float2* bs_chirp32 = nullptr;    // the same three tables rounded to float (mixed-precision ring pass)
+  float2* bs_kern32 = nullptr;
+  float2* twiddle32 = nullptr;
+  int* ring_pairs = nullptr;       // ring pairs grouped by FFT-length class (RingClass::off, count)
 
   // Legendre recurrence (scaled form mu_l = lambda_l / kappa_l):
   //   mu_m = lambda_mm, mu_{m-1} = 0, mu_l = alpha_lm z mu_{l-1} - mu_{l-2} for l > m
@@ -65,10 +69,16 @@ struct Tables {
   int* idx_m = nullptr;            // [nalm] m of each stored coefficient
 };
 
+// Ring pairs of one FFT-length class: t.ring_pairs[off .. off + count) all have
+// an FFT length <= L (L is a power of two; the ring kernel's LDS and block size).
+struct RingClass {
+  int L = 0, off = 0, count = 0;
+};
+
 // Workspace, allocated once at plan creation for nrhs_max columns.
 struct Workspace {
-  double2* eo = nullptr;       // [nrhs][npairs][mmax+1][2]  (E, O) Legendre sums
-  double2* geo = nullptr;      // [nrhs][npairs][mmax+1][2]  (G_N + G_S, G_N - G_S)
+  double2* eo = nullptr;       // [nrhs][npairs][mmax+1][2]  (E, O) Legendre sums (float2 in the mixed path)
+  double2* geo = nullptr;      // [nrhs][npairs][mmax+1][2]  (G_N + G_S, G_N - G_S) (float2 in the mixed path)
   double2* alm_a = nullptr;    // [nrhs][nalm] scratch a_lm vectors
   double2* alm_b = nullptr;
   double2* cg_x = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr, *cg_b = nullptr;
@@ -113,14 +123,16 @@ enum ScalSlot {
   S_RESTART = 14,  // host flag: the next replacement restarts the direction (beta = 0)
 };
 
-constexpr int kTimedKernels = 3;  // 0 Legendre synthesis, 1 Legendre adjoint, 2 ring pass
+// 0 FP64 Legendre synthesis, 1 FP64 Legendre adjoint, 2 ring pass,
+// 3 MFMA (bf16x3) Legendre synthesis, 4 MFMA Legendre adjoint
+constexpr int kTimedKernels = 5;
 struct Timing {
   bool on = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events[kTimedKernels];
-  hipEvent_t open[kTimedKernels] = {nullptr, nullptr, nullptr};
-  hipEvent_t open_end[kTimedKernels] = {nullptr, nullptr, nullptr};
-  double total_ms[kTimedKernels] = {0, 0, 0};
-  int64_t count[kTimedKernels] = {0, 0, 0};
+  hipEvent_t open[kTimedKernels] = {};
+  hipEvent_t open_end[kTimedKernels] = {};
+  double total_ms[kTimedKernels] = {};
+  int64_t count[kTimedKernels] = {};
 };
 
 }  // namespace crsht
@@ -134,6 +146,7 @@ struct crsht_plan {
   crsht::Tables t;
   crsht::Workspace w;
   crsht::Timing timing;
+  std::vector<crsht::RingClass> ring_cls;
   // host copies used for argument checks and bookkeeping
   std::vector<int> h_nphi;
   std::vector<int64_t> h_first;
@@ -166,20 +179,23 @@ int64_t mixed_ab_bytes(const Geometry& g);
 int64_t mixed_ag_bytes(const Geometry& g);
 void mixed_starts(const Geometry& g, std::vector<int64_t>& cst, std::vector<int64_t>& tst, std::vector<int>& tm);
 hipError_t launch_checkpoints(const crsht_plan* P, hipStream_t s);
-// eo = (E, O) sums with mu (FP64 recurrence) and f * alm rounded to bf16x3,
-// FP32 accumulation; f == nullptr means 1
+// eo = (E, O) sums (float2) with mu (FP64 recurrence) and f * alm rounded to
+// bf16x3, FP32 accumulation; f == nullptr means 1
 hipError_t launch_legendre_synth_mixed(const crsht_plan* P, int nrhs, const double2* alm, const double* f,
-                                       double2* eo, hipStream_t s);
-// raw sums as launch_legendre_adjoint (non-diag), bf16x3 / FP32 accumulation
-hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const double2* geo, double2* raw,
+                                       float2* eo, hipStream_t s);
+// raw sums as launch_legendre_adjoint (non-diag) from float2 geo, bf16x3 /
+// FP32 accumulation
+hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const float2* geo, double2* raw,
                                          hipStream_t s);
 
 // ---- ring step (ring.hip) ----
 // mode SYNTH: eo -> map;  ADJOINT: map -> geo;  FUSED: eo -> (map * ninv) -> geo
+// eo / geo are double2 arrays, or float2 arrays with f32 (maps and N^-1 FP64)
 enum RingMode { RING_SYNTH = 0, RING_ADJOINT = 1, RING_FUSED = 2 };
-hipError_t launch_ring(const crsht_plan* P, int nrhs, RingMode mode, const double2* eo, double* map,
-                       const double* ninv, double2* geo, hipStream_t s);
-size_t ring_lds_bytes(const crsht_plan* P);
+hipError_t launch_ring(const crsht_plan* P, int nrhs, RingMode mode, const void* eo, double* map,
+                       const double* ninv, void* geo, bool f32, hipStream_t s);
+void ring_classes(const std::vector<int>& fft_len, std::vector<RingClass>& cls, std::vector<int>& pairs);
+size_t ring_lds_bytes(const crsht_plan* P, bool f32);
 
 // ---- vector kernels (vec.hip) ----
 // Reductions write per-block partial sums to w.partial (column c, row r at

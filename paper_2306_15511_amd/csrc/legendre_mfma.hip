@@ -128,7 +128,7 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
                                                    const int* __restrict__ lst_g, const double2* __restrict__ lst_s,
                                                    const int64_t* __restrict__ mstart,
                                                    const int64_t* __restrict__ cstart,
-                                                   const bf16x8* __restrict__ ab, double2* __restrict__ eo,
+                                                   const bf16x8* __restrict__ ab, float2* __restrict__ eo,
                                                    int64_t eo_stride) {
   // tile[q][h][pair][16 k] bf16: 2 x 2 x 64 x 32 bytes
   __shared__ bf16x8 tile[2][2][64][2];
@@ -215,9 +215,9 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
     for (int t = 0; t < 2; ++t) {
       const int pr = blockIdx.y * 64 + 32 * t + i;
       if (pr >= npairs) continue;
-      double* dst = reinterpret_cast<double*>(eo + rhs * eo_stride + ((size_t)pr * (mmax + 1) + m) * 2);
-      dst[comp] = (double)(t ? dE1[r] : dE0[r]);
-      dst[2 + comp] = (double)(t ? dO1[r] : dO0[r]);
+      float* dst = reinterpret_cast<float*>(eo + rhs * eo_stride + ((size_t)pr * (mmax + 1) + m) * 2);
+      dst[comp] = t ? dE1[r] : dE0[r];
+      dst[2 + comp] = t ? dO1[r] : dO0[r];
     }
   }
 }
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
 // ag tiles: for each (m, block of 16 pairs), parity q, half h, the MFMA A
 // operand A[c][k] = G_q[pair = 16 kb + k][col c] in lane order (lane
 // c + 32 (k/8) holds 8 bf16), from the FP64 ring-pass output geo.
-__global__ __launch_bounds__(64) void k_prep_adj(int mmax, int npairs, int nrhs, const double2* __restrict__ geo,
+__global__ __launch_bounds__(64) void k_prep_adj(int mmax, int npairs, int nrhs, const float2* __restrict__ geo,
                                                  int64_t geo_stride, bf16x8* __restrict__ ag) {
   const int kb = blockIdx.x, m = blockIdx.y;
   const int nkb = (npairs + 15) / 16;
@@ -240,13 +240,13 @@ __global__ __launch_bounds__(64) void k_prep_adj(int mmax, int npairs, int nrhs,
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
       const int pr = kb * 16 + 8 * kg + v;
-      double x = 0.0;
+      float x = 0.0f;
       if (rhs < nrhs && pr < npairs) {
-        const double2 g = geo[rhs * geo_stride + ((size_t)pr * (mmax + 1) + m) * 2 + q];
+        const float2 g = geo[rhs * geo_stride + ((size_t)pr * (mmax + 1) + m) * 2 + q];
         x = comp ? g.y : g.x;
       }
       __bf16 h, l;
-      split_bf16((float)x, h, l);
+      split_bf16(x, h, l);
       hi[v] = h;
       lo[v] = l;
     }
@@ -407,7 +407,7 @@ hipError_t launch_checkpoints(const crsht_plan* P, hipStream_t s) {
 
 // columns of one group: at most kMixedCols / 2 right-hand sides
 hipError_t launch_legendre_synth_mixed(const crsht_plan* P, int nrhs, const double2* alm, const double* f,
-                                       double2* eo, hipStream_t s) {
+                                       float2* eo, hipStream_t s) {
   if (!f) f = P->t.ones;
   const Geometry& g = P->g;
   const int64_t eo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
@@ -417,19 +417,19 @@ hipError_t launch_legendre_synth_mixed(const crsht_plan* P, int nrhs, const doub
     dim3 gp((g.lmax + kSynChunk) / kSynChunk, g.mmax + 1);
     hipLaunchKernelGGL(k_prep_synth, gp, dim3(64), 0, s, g.lmax, nr, P->t.mstart, P->t.mx_cstart,
                        alm + (int64_t)c0 * g.nalm, (int64_t)g.nalm, f, ab);
-    timing_begin(P, 0, s);
+    timing_begin(P, 3, s);
     dim3 gs(g.mmax + 1, (g.npairs + 63) / 64);
     hipLaunchKernelGGL(k_synth_mfma, gs, dim3(64), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.pair_z, P->t.rec_alpha,
                        P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.mx_cstart, (const bf16x8*)ab,
                        eo + (int64_t)c0 * eo_stride, eo_stride);
-    timing_end(P, 0, s);
+    timing_end(P, 3, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const double2* geo, double2* raw,
+hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const float2* geo, double2* raw,
                                          hipStream_t s) {
   const Geometry& g = P->g;
   const int64_t geo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
@@ -439,12 +439,12 @@ hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const do
     dim3 gp((g.npairs + 15) / 16, g.mmax + 1);
     hipLaunchKernelGGL(k_prep_adj, gp, dim3(64), 0, s, g.mmax, g.npairs, nr, geo + (int64_t)c0 * geo_stride,
                        geo_stride, ag);
-    timing_begin(P, 1, s);
+    timing_begin(P, 4, s);
     hipLaunchKernelGGL(k_adj_mfma, dim3((unsigned)P->t.mx_ntiles), dim3(kAdjWaves * 64), 0, s, g.lmax, g.mmax,
                        g.npairs, nr, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
                        P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_ckpt, (const bf16x8*)ag,
                        raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm);
-    timing_end(P, 1, s);
+    timing_end(P, 4, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

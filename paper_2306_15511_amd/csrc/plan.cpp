@@ -74,7 +74,7 @@ int upload(T** p, const std::vector<T>& h, size_t* total) {
 void free_plan_memory(crsht_plan* P) {
   void* ptrs[] = {P->t.pair_z, P->t.pair_nphi, P->t.pair_phi0, P->t.pair_first_n, P->t.pair_first_s,
                   P->t.pair_fft_len, P->t.pair_bs_off, P->t.pair_bk_off, P->t.bs_chirp, P->t.bs_kern,
-                  P->t.twiddle, P->t.rec_alpha, P->t.rec_kappa, P->t.lmm_v, P->t.lmm_k, P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.ones,
+                  P->t.twiddle, P->t.bs_chirp32, P->t.bs_kern32, P->t.twiddle32, P->t.ring_pairs, P->t.rec_alpha, P->t.rec_kappa, P->t.lmm_v, P->t.lmm_k, P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.ones,
                   P->t.mx_cstart, P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_ckpt, P->w.cg_xacc, P->w.cg_bin,
                   P->w.mx_ab, P->w.mx_ag,
                   P->t.idx_l, P->t.idx_m, P->w.eo, P->w.geo, P->w.alm_a, P->w.alm_b, P->w.cg_x, P->w.cg_r,
@@ -248,6 +248,19 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int nrhs_max
   if ((rc = upload(&P->t.bs_chirp, chirp, total))) return rc;
   if ((rc = upload(&P->t.bs_kern, kern, total))) return rc;
   if ((rc = upload(&P->t.twiddle, tw, total))) return rc;
+  {
+    auto to32 = [](const std::vector<double2>& v) {
+      std::vector<float2> o(v.size());
+      for (size_t i = 0; i < v.size(); ++i) o[i] = make_float2((float)v[i].x, (float)v[i].y);
+      return o;
+    };
+    if ((rc = upload(&P->t.bs_chirp32, to32(chirp), total))) return rc;
+    if ((rc = upload(&P->t.bs_kern32, to32(kern), total))) return rc;
+    if ((rc = upload(&P->t.twiddle32, to32(tw), total))) return rc;
+    std::vector<int> rp;
+    crsht::ring_classes(pfft, P->ring_cls, rp);
+    if ((rc = upload(&P->t.ring_pairs, rp, total))) return rc;
+  }
   if ((rc = upload(&P->t.rec_alpha, alpha, total))) return rc;
   if ((rc = upload(&P->t.rec_kappa, kappa, total))) return rc;
   if ((rc = upload(&P->t.lmm_v, lv, total))) return rc;

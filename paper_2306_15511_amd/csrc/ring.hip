@@ -12,57 +12,93 @@
 // Fused operator pass: synthesis, multiply by N^-1 per pixel (N^-1 is
 // diagonal in pixels), adjoint, with the map kept in LDS.
 //
+// On every HEALPix ring n phi0 is pi (or phi0 = 0), so e^{i (m + n) phi0} =
+// sigma e^{i m phi0} with sigma = -1 (or +1): all aliases m = k + s n of one
+// frequency share the phase e^{i k phi0} up to the sign sigma^s, and one
+// sincospi per frequency serves every alias.
+//
 // DFT lengths n = 4i that are not powers of two use Bluestein's chirp-z
 // algorithm: X_k = c_k sum_j (x_j c_j) conj(c_{k-j}), c_j = exp(-i pi j^2/n),
 // a cyclic convolution of power-of-two length L >= 2n - 1 with the FFT of the
 // conjugate chirp precomputed per ring. Power-of-two FFTs are in-place
 // Stockham passes of radix 16 (8, 4, 2 for the last): each thread loads R
-// points from LDS into registers, applies the inter-pass twiddles, does an
-// R-point DFT in registers and writes back; natural order in and out.
+// points from LDS into registers, applies the inter-pass twiddles (one table
+// load, the other powers by multiplication), does an R-point DFT in registers
+// and writes back; natural order in and out. LDS arrays are padded by one
+// element every 16 so that the strided writes of a pass spread over the banks.
+//
+// Ring pairs are launched by classes of FFT length (LDS and block size sized
+// to the class) and the (pair, column) blocks of one pair are kept on one XCD
+// so that N^-1 and the Bluestein tables of the ring are shared in its L2.
+// The kernels are instantiated for double (FP64 path) and float (the
+// azimuthal step of the mixed-precision path); maps and N^-1 stay FP64.
 #include "internal.h"
 
 namespace crsht {
 namespace {
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+template <class V> struct RealOf;
+template <> struct RealOf<double2> { using T = double; };
+template <> struct RealOf<float2> { using T = float; };
+template <class V> using Re = typename RealOf<V>::T;
+
+__device__ __forceinline__ double fmr(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fmr(float a, float b, float c) { return fmaf(a, b, c); }
+
+template <class V> __device__ __forceinline__ V mk(Re<V> x, Re<V> y) {
+  V v;
+  v.x = x;
+  v.y = y;
+  return v;
 }
-__device__ __forceinline__ double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
-__device__ __forceinline__ double2 add2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 sub2(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+template <class V> __device__ __forceinline__ V zero() { return mk<V>(Re<V>(0), Re<V>(0)); }
+template <class V> __device__ __forceinline__ V cmul(V a, V b) {
+  return mk<V>(fmr(a.x, b.x, -a.y * b.y), fmr(a.x, b.y, a.y * b.x));
+}
+template <class V> __device__ __forceinline__ V conj2(V a) { return mk<V>(a.x, -a.y); }
+template <class V> __device__ __forceinline__ V add2(V a, V b) { return mk<V>(a.x + b.x, a.y + b.y); }
+template <class V> __device__ __forceinline__ V sub2(V a, V b) { return mk<V>(a.x - b.x, a.y - b.y); }
+template <class V> __device__ __forceinline__ V scl(Re<V> s, V a) { return mk<V>(s * a.x, s * a.y); }
+
 __device__ __forceinline__ int ilog2(int n) { return 31 - __clz(n); }
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+
+// LDS-only barrier: waits for this wavefront's LDS operations, not for its
+// global loads in flight (prefetched operands stay in flight across it)
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // exp(-2 pi i q / 16), q = 0..15
-__device__ __forceinline__ double2 root16(int q) {
-  constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173, r2 = 0.70710678118654752440;
+template <class V> __device__ __forceinline__ V root16(int q) {
+  using R = Re<V>;
+  constexpr R c1 = R(0.92387953251128675613), s1 = R(0.38268343236508977173), r2 = R(0.70710678118654752440);
   switch (q & 15) {
-    case 0: return make_double2(1.0, 0.0);
-    case 1: return make_double2(c1, -s1);
-    case 2: return make_double2(r2, -r2);
-    case 3: return make_double2(s1, -c1);
-    case 4: return make_double2(0.0, -1.0);
-    case 5: return make_double2(-s1, -c1);
-    case 6: return make_double2(-r2, -r2);
-    case 7: return make_double2(-c1, -s1);
-    case 8: return make_double2(-1.0, 0.0);
-    case 9: return make_double2(-c1, s1);
-    case 10: return make_double2(-r2, r2);
-    case 11: return make_double2(-s1, c1);
-    case 12: return make_double2(0.0, 1.0);
-    case 13: return make_double2(s1, c1);
-    case 14: return make_double2(r2, r2);
-    default: return make_double2(c1, s1);
+    case 0: return mk<V>(R(1), R(0));
+    case 1: return mk<V>(c1, -s1);
+    case 2: return mk<V>(r2, -r2);
+    case 3: return mk<V>(s1, -c1);
+    case 4: return mk<V>(R(0), R(-1));
+    case 5: return mk<V>(-s1, -c1);
+    case 6: return mk<V>(-r2, -r2);
+    case 7: return mk<V>(-c1, -s1);
+    case 8: return mk<V>(R(-1), R(0));
+    case 9: return mk<V>(-c1, s1);
+    case 10: return mk<V>(-r2, r2);
+    case 11: return mk<V>(-s1, c1);
+    case 12: return mk<V>(R(0), R(1));
+    case 13: return mk<V>(s1, c1);
+    case 14: return mk<V>(r2, r2);
+    default: return mk<V>(c1, s1);
   }
 }
 
 // multiply by exp(-2 pi i q/16) (conjugate root if inv), q a compile-time constant after unrolling
-__device__ __forceinline__ double2 mul_root(double2 a, int q, bool inv) {
+template <class V> __device__ __forceinline__ V mul_root(V a, int q, bool inv) {
   q &= 15;
   if (q == 0) return a;
-  if (q == 8) return make_double2(-a.x, -a.y);
-  if (q == 4) return inv ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
-  if (q == 12) return inv ? make_double2(a.y, -a.x) : make_double2(-a.y, a.x);
-  const double2 w = root16(q);
+  if (q == 8) return mk<V>(-a.x, -a.y);
+  if (q == 4) return inv ? mk<V>(-a.y, a.x) : mk<V>(a.y, -a.x);
+  if (q == 12) return inv ? mk<V>(a.y, -a.x) : mk<V>(-a.y, a.x);
+  const V w = root16<V>(q);
   return cmul(a, inv ? conj2(w) : w);
 }
 
@@ -73,10 +109,10 @@ __host__ __device__ constexpr int brev_c(int i, int bits) {
 }
 
 // R-point DFT in registers (natural order in and out), R = 2, 4, 8, 16
-template <int R>
-__device__ __forceinline__ void dft_reg(double2 (&v)[R], bool inv) {
+template <int R, class V>
+__device__ __forceinline__ void dft_reg(V (&v)[R], bool inv) {
   constexpr int B = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
-  double2 t[R];
+  V t[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) t[brev_c(i, B)] = v[i];
 #pragma unroll
@@ -85,8 +121,8 @@ __device__ __forceinline__ void dft_reg(double2 (&v)[R], bool inv) {
     for (int g = 0; g < R; g += 2 * h) {
 #pragma unroll
       for (int j = 0; j < h; ++j) {
-        const double2 a = t[g + j];
-        const double2 b = mul_root(t[g + j + h], j * (16 / (2 * h)), inv);
+        const V a = t[g + j];
+        const V b = mul_root(t[g + j + h], j * (16 / (2 * h)), inv);
         t[g + j] = add2(a, b);
         t[g + j + h] = sub2(a, b);
       }
@@ -98,34 +134,41 @@ __device__ __forceinline__ void dft_reg(double2 (&v)[R], bool inv) {
 
 // one in-place Stockham pass of radix R over N points with stride Ns
 // (Govindaraju et al. 2008 formulation). tw: exp(-2 pi i q / fmax), q < fmax.
-// Every thread handles up to J = 16 / R butterflies, so any N <= 16 blockDim
-// fits; all inputs are read into registers before the barrier that precedes
-// the writes, which makes the pass in place.
-template <int R>
-__device__ __forceinline__ void stockham_pass(double2* x, int N, int Ns, const double2* __restrict__ tw, int fmax,
-                                              bool inv) {
-  constexpr int J = 16 / R;
+// Blocks have at least N/8 threads, so a thread handles at most J = 8/R
+// butterflies; all inputs are read into registers before the barrier that
+// precedes the writes, which makes the pass in place. The twiddles w^r of a
+// butterfly come from one table load w and products (at most six roundings).
+template <int R, class V>
+__device__ __forceinline__ void stockham_pass(V* x, int N, int Ns, const V* __restrict__ tw, int fmax, bool inv) {
+  constexpr int J = R >= 8 ? 1 : 8 / R;
   const int nt = N / R;
-  double2 v[J][R];
+  V v[J][R];
 #pragma unroll
   for (int u = 0; u < J; ++u) {
     const int j = threadIdx.x + u * blockDim.x;
     if (j < nt) {
-      const int k = j % Ns;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[u][r] = x[j + r * nt];
+      for (int r = 0; r < R; ++r) v[u][r] = x[pad(j + r * nt)];
       if (Ns > 1) {
-        const int step = k * (fmax / (Ns * R));
+        const int k = j % Ns;
+        V w1 = tw[k * (fmax / (Ns * R))];
+        if (inv) w1.y = -w1.y;
+        const V w2 = cmul(w1, w1);
+        const V w3 = cmul(w2, w1);
+        const V w4 = cmul(w2, w2);
+        V anc = w4;   // w^(r - r % 4) for the current group of four
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          const double2 w = tw[r * step];
-          v[u][r] = cmul(v[u][r], inv ? conj2(w) : w);
+          if (r % 4 == 0 && r > 4) anc = cmul(anc, w4);
+          const V lo = (r % 4 == 1) ? w1 : (r % 4 == 2) ? w2 : w3;
+          const V wr = (r % 4 == 0) ? anc : (r < 4) ? lo : cmul(anc, lo);
+          v[u][r] = cmul(v[u][r], wr);
         }
       }
       dft_reg<R>(v[u], inv);
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int u = 0; u < J; ++u) {
     const int j = threadIdx.x + u * blockDim.x;
@@ -133,15 +176,16 @@ __device__ __forceinline__ void stockham_pass(double2* x, int N, int Ns, const d
       const int k = j % Ns;
       const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) x[base + r * Ns] = v[u][r];
+      for (int r = 0; r < R; ++r) x[pad(base + r * Ns)] = v[u][r];
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
-// length-N (power of two, N <= 16 blockDim) DFT in place, natural order
-__device__ void fft_pow2(double2* x, int N, const double2* __restrict__ tw, int fmax, bool inv) {
-  __syncthreads();
+// length-N (power of two, N <= 8 blockDim) DFT in place, natural order
+template <class V>
+__device__ __forceinline__ void fft_pow2(V* x, int N, const V* __restrict__ tw, int fmax, bool inv) {
+  lds_barrier();
   int b = ilog2(N);
   int Ns = 1;
   while (b >= 4) {
@@ -154,16 +198,19 @@ __device__ void fft_pow2(double2* x, int N, const double2* __restrict__ tw, int 
   else if (b == 1) stockham_pass<2>(x, N, Ns, tw, fmax, inv);
 }
 
+template <class V>
 struct PairInfo {
   int n, L, den;
   int64_t fn, fs;
   bool equator, blue;
-  const double2* chirp;
-  const double2* kern;
+  Re<V> sigma;        // e^{i n phi0}
+  const V* chirp;
+  const V* kern;
 };
 
-__device__ __forceinline__ PairInfo pair_info(const Tables& T, int p, int nside) {
-  PairInfo q;
+template <class V>
+__device__ __forceinline__ PairInfo<V> pair_info(const Tables& T, int p, int nside, const V* chirp, const V* kern) {
+  PairInfo<V> q;
   q.n = T.pair_nphi[p];
   q.L = T.pair_fft_len[p];
   q.fn = T.pair_first_n[p];
@@ -174,239 +221,406 @@ __device__ __forceinline__ PairInfo pair_info(const Tables& T, int p, int nside)
   // phi0 = pi/(4i) in the polar caps, 0 or pi/(4 nside) in the belt
   if (i < nside) q.den = 4 * i;
   else q.den = ((i + nside) & 1) ? 0 : 4 * nside;
-  q.chirp = q.blue ? T.bs_chirp + T.pair_bs_off[p] : nullptr;
-  q.kern = q.blue ? T.bs_kern + T.pair_bk_off[p] : nullptr;
+  q.sigma = q.den == 0 ? Re<V>(1) : Re<V>(-1);
+  q.chirp = q.blue ? chirp + T.pair_bs_off[p] : nullptr;
+  q.kern = q.blue ? kern + T.pair_bk_off[p] : nullptr;
   return q;
 }
 
-// e^{i m phi0} with phi0 = pi / den (den = 0 means phi0 = 0); m reduced
+// e^{i k phi0} with phi0 = pi / den (den = 0 means phi0 = 0); k reduced
 // exactly modulo 2 den before the trigonometric call.
-__device__ __forceinline__ double2 phase(int m, int den) {
+__device__ __forceinline__ double2 phase_of(double2*, int k, int den) {
   if (den == 0) return make_double2(1.0, 0.0);
-  const int r = m % (2 * den);
+  const int r = k % (2 * den);
   double s, c;
   sincospi((double)r / (double)den, &s, &c);
   return make_double2(c, s);
 }
+__device__ __forceinline__ float2 phase_of(float2*, int k, int den) {
+  if (den == 0) return make_float2(1.0f, 0.0f);
+  const int r = k % (2 * den);
+  float s, c;
+  sincospif((float)r / (float)den, &s, &c);
+  return make_float2(c, s);
+}
+template <class V> __device__ __forceinline__ V phase(int k, int den) { return phase_of((V*)nullptr, k, den); }
 
-// Hermitian spectrum h = c_N + i c_S of a ring pair into buf[0..n).
-// For 0 <= k <= n/2 let A = sum_{m = k mod n} F'(m) and
-// B = sum_{m = -k mod n, m >= 1} F'(m), F' = F e^{i m phi0} (F(0) real):
-// c_k = A + conj B and c_{n-k} = B + conj A, so every F(m) is read once.
-// When n/2 + 1 < blockDim the alias sums of one k are split over S threads
-// (alias indices s, s + S, ...) whose partial sums are combined in a fixed
-// order through LDS (scratch, at least blockDim x 8 doubles); the result is
-// the same sum regrouped. Bluestein rings store conj(h_k) c_k (chirp) instead.
-// alias sums of frequency k over the aliases s, s + S, s + 2S, ...
-__device__ __forceinline__ void alias_sums(const double2* __restrict__ eo, int mmax, int n, int den, int k, int s,
-                                           int S, double2& aN, double2& aS, double2& bN, double2& bS) {
-  aN = make_double2(0.0, 0.0);
-  aS = aN;
-  bN = aN;
-  bS = aN;
-  for (int m = k + s * n; m <= mmax; m += S * n) {
-    const double2 E = eo[2 * m], O = eo[2 * m + 1];
-    double2 fn = add2(E, O), fs = sub2(E, O);
-    if (m == 0) {
-      fn.y = 0.0;
-      fs.y = 0.0;
-    }
-    const double2 ph = phase(m, den);
-    aN = add2(aN, cmul(fn, ph));
-    aS = add2(aS, cmul(fs, ph));
-  }
-  if (k > 0 && 2 * k != n) {
-    for (int m = n - k + s * n; m <= mmax; m += S * n) {
-      const double2 E = eo[2 * m], O = eo[2 * m + 1];
-      const double2 ph = phase(m, den);
-      bN = add2(bN, cmul(add2(E, O), ph));
-      bS = add2(bS, cmul(sub2(E, O), ph));
-    }
-  }
+template <class V> __device__ __forceinline__ Re<V> sign_pow(Re<V> sigma, int e) {
+  return (sigma < Re<V>(0) && (e & 1)) ? Re<V>(-1) : Re<V>(1);
 }
 
-// h_k and h_{n-k} from the complete alias sums of k, stored in buf
-__device__ __forceinline__ void store_spectrum(double2* buf, const PairInfo& q, const double2* __restrict__ eo, int k,
-                                               double2 aN, double2 aS, double2 bN, double2 bS) {
+// h_k and h_{n-k} of the Hermitian spectrum h = c_N + i c_S from the
+// phased alias sums of k: A = sum_{m = k mod n, m >= 0} F'(m) and
+// B = sum_{m = -k mod n, m >= 1} F'(m), F' = F e^{i m phi0} (F(0) real), so
+// that c_k = A + conj B and c_{n-k} = B + conj A. e0, o0: E and O of m = 0
+// (used for k = 0). Bluestein rings store conj(h_k) c_k (chirp) instead.
+template <class V>
+__device__ __forceinline__ void store_spectrum(V* buf, const PairInfo<V>& q, int k, V aN, V aS, V bN, V bS, V e0,
+                                               V o0, V chk, V chnk) {
   const int n = q.n;
   if (k == 0 || 2 * k == n) {
     // k = 0: B = A without the m = 0 term; k = n/2: the two alias sets coincide
     bN = aN;
     bS = aS;
     if (k == 0) {
-      const double2 E = eo[0], O = eo[1];
-      bN.x -= E.x + O.x;
-      bS.x -= E.x - O.x;
+      bN.x -= e0.x + o0.x;
+      bS.x -= e0.x - o0.x;
     }
   }
-  double2 cn = add2(aN, conj2(bN)), cs = add2(aS, conj2(bS));
-  double2 cnn = add2(bN, conj2(aN)), csn = add2(bS, conj2(aS));
-  if (q.equator) cs = csn = make_double2(0.0, 0.0);
-  double2 hk = make_double2(cn.x - cs.y, cn.y + cs.x);
-  double2 hnk = make_double2(cnn.x - csn.y, cnn.y + csn.x);
+  V cn = add2(aN, conj2(bN)), cs = add2(aS, conj2(bS));
+  V cnn = add2(bN, conj2(aN)), csn = add2(bS, conj2(aS));
+  if (q.equator) cs = csn = zero<V>();
+  V hk = mk<V>(cn.x - cs.y, cn.y + cs.x);
+  V hnk = mk<V>(cnn.x - csn.y, cnn.y + csn.x);
   if (q.blue) {
-    hk = cmul(conj2(hk), q.chirp[k]);
-    if (k > 0) hnk = cmul(conj2(hnk), q.chirp[n - k]);
+    hk = cmul(conj2(hk), chk);
+    if (k > 0) hnk = cmul(conj2(hnk), chnk);
   }
-  buf[k] = hk;
-  if (k > 0) buf[n - k] = hnk;   // k = n/2 writes the same value twice
+  buf[pad(k)] = hk;
+  if (k > 0) buf[pad(n - k)] = hnk;   // k = n/2 writes the same value twice
 }
 
-__device__ void spectrum(double2* buf, double* scratch, const PairInfo& q, const double2* __restrict__ eo,
-                         int mmax) {
+// further aliases m = first + s n (s = 1, 2, ...) of one set, signed sigma^s
+template <class V>
+__device__ __forceinline__ void more_aliases(const V* __restrict__ eo, int mmax, int n, Re<V> sigma, int first, V& sN,
+                                             V& sS) {
+  Re<V> sg = sigma;
+  for (int m = first + n; m <= mmax; m += n) {
+    const V E = eo[2 * m], O = eo[2 * m + 1];
+    sN = add2(sN, scl(sg, add2(E, O)));
+    sS = add2(sS, scl(sg, sub2(E, O)));
+    sg *= sigma;
+  }
+}
+
+template <class V>
+__device__ void spectrum(V* buf, Re<V>* scratch, const PairInfo<V>& q, const V* __restrict__ eo, int mmax) {
   const int n = q.n, nk = n / 2 + 1;
-  const int S = (int)blockDim.x / nk;
-  double2 aN, aS, bN, bS;
+  const int B = blockDim.x;
+  const int S = B / nk;
+  const V e0 = eo[0], o0 = eo[1];
   if (S <= 1) {
-    for (int k = threadIdx.x; k < nk; k += blockDim.x) {
-      alias_sums(eo, mmax, n, q.den, k, 0, 1, aN, aS, bN, bS);
-      store_spectrum(buf, q, eo, k, aN, aS, bN, bS);
+    // frequencies k = t + u B, two at a time: the first alias of both sets
+    // (and the chirp) of both is loaded before any use
+    constexpr int U = 2;
+    for (int k0 = threadIdx.x; k0 < nk; k0 += U * B) {
+    V ea[U], oa[U], eb[U], ob[U], ca[U], cb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * B;
+      ea[u] = oa[u] = eb[u] = ob[u] = ca[u] = cb[u] = zero<V>();
+      if (k < nk) {
+        if (k <= mmax) {
+          ea[u] = eo[2 * k];
+          oa[u] = eo[2 * k + 1];
+        }
+        const int mb = n - k;
+        if (k > 0 && 2 * k != n && mb <= mmax) {
+          eb[u] = eo[2 * mb];
+          ob[u] = eo[2 * mb + 1];
+        }
+        if (q.blue) {
+          ca[u] = q.chirp[k];
+          if (k > 0) cb[u] = q.chirp[n - k];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * B;
+      if (k < nk) {
+        V aN = add2(ea[u], oa[u]), aS = sub2(ea[u], oa[u]);
+        if (k == 0) aN.y = aS.y = Re<V>(0);
+        if (k <= mmax) more_aliases(eo, mmax, n, q.sigma, k, aN, aS);
+        V bN = zero<V>(), bS = zero<V>();
+        if (k > 0 && 2 * k != n && n - k <= mmax) {
+          V tN = add2(eb[u], ob[u]), tS = sub2(eb[u], ob[u]);
+          more_aliases(eo, mmax, n, q.sigma, n - k, tN, tS);
+          bN = scl(q.sigma, tN);
+          bS = scl(q.sigma, tS);
+        }
+        const V ph = phase<V>(k, q.den);
+        aN = cmul(aN, ph);
+        aS = cmul(aS, ph);
+        bN = cmul(bN, conj2(ph));
+        bS = cmul(bS, conj2(ph));
+        store_spectrum(buf, q, k, aN, aS, bN, bS, e0, o0, ca[u], cb[u]);
+      }
+    }
     }
     return;
   }
+  // small rings: the alias sums of one k are split over S threads (aliases
+  // s, s + S, ... of each set) and combined in a fixed order through LDS
   const int t = threadIdx.x;
   const int k = t / S, s = t % S;
-  if (k < nk) alias_sums(eo, mmax, n, q.den, k, s, S, aN, aS, bN, bS);
-  else aN = aS = bN = bS = make_double2(0.0, 0.0);
-  // combine the S partial sums of each k in order of s
-  double* sc = scratch + (size_t)t * 8;
+  V aN = zero<V>(), aS = zero<V>(), bN = zero<V>(), bS = zero<V>();
+  if (k < nk) {
+    for (int j = s, m = k + s * n; m <= mmax; j += S, m += S * n) {
+      const V E = eo[2 * m], O = eo[2 * m + 1];
+      V fn = add2(E, O), fs = sub2(E, O);
+      if (m == 0) fn.y = fs.y = Re<V>(0);
+      const Re<V> sg = sign_pow<V>(q.sigma, j);
+      aN = add2(aN, scl(sg, fn));
+      aS = add2(aS, scl(sg, fs));
+    }
+    if (k > 0 && 2 * k != n) {
+      for (int j = s, m = n - k + s * n; m <= mmax; j += S, m += S * n) {
+        const V E = eo[2 * m], O = eo[2 * m + 1];
+        const Re<V> sg = sign_pow<V>(q.sigma, j + 1);
+        bN = add2(bN, scl(sg, add2(E, O)));
+        bS = add2(bS, scl(sg, sub2(E, O)));
+      }
+    }
+  }
+  Re<V>* sc = scratch + (size_t)t * 8;
   sc[0] = aN.x; sc[1] = aN.y; sc[2] = aS.x; sc[3] = aS.y;
   sc[4] = bN.x; sc[5] = bN.y; sc[6] = bS.x; sc[7] = bS.y;
-  __syncthreads();
+  lds_barrier();
   if (k < nk && s == 0) {
     for (int u = 1; u < S; ++u) {
-      const double* o = scratch + (size_t)(t + u) * 8;
+      const Re<V>* o = scratch + (size_t)(t + u) * 8;
       aN.x += o[0]; aN.y += o[1]; aS.x += o[2]; aS.y += o[3];
       bN.x += o[4]; bN.y += o[5]; bS.x += o[6]; bS.y += o[7];
     }
-    store_spectrum(buf, q, eo, k, aN, aS, bN, bS);
+    const V ph = phase<V>(k, q.den);
+    aN = cmul(aN, ph);
+    aS = cmul(aS, ph);
+    bN = cmul(bN, conj2(ph));
+    bS = cmul(bS, conj2(ph));
+    const V ck = q.blue ? q.chirp[k] : zero<V>();
+    const V cnk = (q.blue && k > 0) ? q.chirp[n - k] : zero<V>();
+    store_spectrum(buf, q, k, aN, aS, bN, bS, e0, o0, ck, cnk);
+  }
+  lds_barrier();   // scratch is read before anything else is written there
+}
+
+// multiply buf[0..L) by the ring's Bluestein kernel (loads issued first)
+template <class V>
+__device__ __forceinline__ void kern_mul(V* buf, const PairInfo<V>& q) {
+  constexpr int U = 8;   // L <= 8 blockDim
+  V kv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = threadIdx.x + u * blockDim.x;
+    kv[u] = j < q.L ? q.kern[j] : zero<V>();
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = threadIdx.x + u * blockDim.x;
+    if (j < q.L) buf[pad(j)] = cmul(buf[pad(j)], kv[u]);
   }
 }
 
 // Z_j = map_N[j] + i map_S[j] for j < n, left in buf[0..n) (natural order)
-__device__ void ring_inverse(double2* buf, double* scratch, const PairInfo& q, const double2* __restrict__ eo,
-                             int mmax, const double2* __restrict__ tw, int fmax) {
+template <class V>
+__device__ void ring_inverse(V* buf, Re<V>* scratch, const PairInfo<V>& q, const V* __restrict__ eo, int mmax,
+                             const V* __restrict__ tw, int fmax) {
   spectrum(buf, scratch, q, eo, mmax);
   if (!q.blue) {
     fft_pow2(buf, q.n, tw, fmax, true);
   } else {
     // IDFT(h) = conj(DFT(conj h)); DFT by chirp-z
-    for (int j = q.n + threadIdx.x; j < q.L; j += blockDim.x) buf[j] = make_double2(0.0, 0.0);
+    for (int j = q.n + threadIdx.x; j < q.L; j += blockDim.x) buf[pad(j)] = zero<V>();
     fft_pow2(buf, q.L, tw, fmax, false);
-    for (int j = threadIdx.x; j < q.L; j += blockDim.x) buf[j] = cmul(buf[j], q.kern[j]);
+    kern_mul(buf, q);
     fft_pow2(buf, q.L, tw, fmax, true);
-    for (int j = threadIdx.x; j < q.n; j += blockDim.x) buf[j] = conj2(cmul(buf[j], q.chirp[j]));
-    __syncthreads();
+    for (int j = threadIdx.x; j < q.n; j += blockDim.x) buf[pad(j)] = conj2(cmul(buf[pad(j)], q.chirp[j]));
+    lds_barrier();
   }
 }
 
-// forward DFT of z_j (buf[0..n), natural order) in place; X_k in buf[k]
-__device__ void ring_forward(double2* buf, const PairInfo& q, const double2* __restrict__ tw, int fmax) {
+// forward DFT of z_j (buf[0..n), natural order) in place; X_k in buf[k],
+// except that Bluestein rings leave X_k / c_k (the final chirp factor is
+// applied where the spectrum is read, in write_geo)
+template <class V>
+__device__ void ring_forward(V* buf, const PairInfo<V>& q, const V* __restrict__ tw, int fmax) {
   if (!q.blue) {
     fft_pow2(buf, q.n, tw, fmax, false);
   } else {
     for (int j = threadIdx.x; j < q.L; j += blockDim.x)
-      buf[j] = j < q.n ? cmul(buf[j], q.chirp[j]) : make_double2(0.0, 0.0);
+      buf[pad(j)] = j < q.n ? cmul(buf[pad(j)], q.chirp[j]) : zero<V>();
     fft_pow2(buf, q.L, tw, fmax, false);
-    for (int j = threadIdx.x; j < q.L; j += blockDim.x) buf[j] = cmul(buf[j], q.kern[j]);
+    kern_mul(buf, q);
     fft_pow2(buf, q.L, tw, fmax, true);
-    for (int j = threadIdx.x; j < q.n; j += blockDim.x) buf[j] = cmul(buf[j], q.chirp[j]);
-    __syncthreads();
   }
 }
 
-// G_E = G_N + G_S and G_O = G_N - G_S for m = 0..mmax.
-__device__ void write_geo(double2* __restrict__ geo, const double2* buf, const PairInfo& q, int mmax) {
-  for (int m = threadIdx.x; m <= mmax; m += blockDim.x) {
-    const int k = m % q.n;
-    const int kn = (q.n - k) % q.n;
-    const double2 X = buf[k], Xm = conj2(buf[kn]);
+// G_E = G_N + G_S and G_O = G_N - G_S for m = 0..mmax, by frequency k = m mod n
+template <class V>
+__device__ void write_geo(V* __restrict__ geo, const V* buf, const PairInfo<V>& q, int mmax) {
+  const int n = q.n;
+  const int kmax = n < mmax + 1 ? n : mmax + 1;
+  for (int k = threadIdx.x; k < kmax; k += blockDim.x) {
+    const int kn = (n - k) % n;
+    V X = buf[pad(k)], Xm = buf[pad(kn)];
+    if (q.blue) {
+      X = cmul(X, q.chirp[k]);
+      Xm = cmul(Xm, q.chirp[kn]);
+    }
+    Xm = conj2(Xm);
+    const Re<V> h = Re<V>(0.5);
     // X_N = (X + conj X(-k))/2, X_S = (X - conj X(-k))/(2i)
-    const double2 XN = make_double2(0.5 * (X.x + Xm.x), 0.5 * (X.y + Xm.y));
-    const double2 XS = make_double2(0.5 * (X.y - Xm.y), -0.5 * (X.x - Xm.x));
-    const double2 ph = conj2(phase(m, q.den));
-    const double2 GN = cmul(XN, ph);
-    const double2 GS = q.equator ? make_double2(0.0, 0.0) : cmul(XS, ph);
-    geo[2 * m] = add2(GN, GS);
-    geo[2 * m + 1] = sub2(GN, GS);
+    const V XN = mk<V>(h * (X.x + Xm.x), h * (X.y + Xm.y));
+    const V XS = mk<V>(h * (X.y - Xm.y), -h * (X.x - Xm.x));
+    const V ph = conj2(phase<V>(k, q.den));
+    const V GN = cmul(XN, ph);
+    const V GS = q.equator ? zero<V>() : cmul(XS, ph);
+    V gE = add2(GN, GS), gO = sub2(GN, GS);
+    for (int m = k; m <= mmax; m += n) {
+      geo[2 * m] = gE;
+      geo[2 * m + 1] = gO;
+      gE = scl(q.sigma, gE);
+      gO = scl(q.sigma, gO);
+    }
   }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(1024) void k_ring(Tables T, int nside, int mmax, int fmax,
-                                              const double2* __restrict__ eo, int64_t eo_stride,
-                                              double* __restrict__ map, int64_t map_stride,
-                                              const double* __restrict__ ninv, double2* __restrict__ geo,
-                                              int64_t geo_stride) {
-  extern __shared__ double2 buf[];
-  // spectrum scratch (blockDim x 8 doubles) after the FFT buffer
-  double* scratch = reinterpret_cast<double*>(buf + fmax);
-  const int p = blockIdx.x, c = blockIdx.y;
-  const PairInfo q = pair_info(T, p, nside);
-  const double2* __restrict__ eop = eo + c * eo_stride + (size_t)p * (mmax + 1) * 2;
-  double2* __restrict__ geop = geo + c * geo_stride + (size_t)p * (mmax + 1) * 2;
+template <class V, int MODE, int NT>
+__global__ __launch_bounds__(NT) void k_ring(Tables T, int nside, int mmax, int fmax, const int* __restrict__ pairs,
+                                              int npc, int nrhs, int Lc, const V* __restrict__ tw,
+                                              const V* __restrict__ chirp, const V* __restrict__ kern,
+                                              const V* __restrict__ eo, int64_t eo_stride, double* __restrict__ map,
+                                              int64_t map_stride, const double* __restrict__ ninv,
+                                              V* __restrict__ geo, int64_t geo_stride) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  V* buf = reinterpret_cast<V*>(lds_raw);
+  // spectrum scratch of small rings (blockDim x 8 reals) in the upper half
+  Re<V>* scratch = reinterpret_cast<Re<V>*>(buf + pad(Lc / 2));
+  // blocks b, b + 8, ... run on one XCD: give them consecutive (pair, column) items
+  const int b = blockIdx.x;
+  const int g = (b & 7) * (int)(gridDim.x >> 3) + (b >> 3);
+  if (g >= npc * nrhs) return;
+  const int p = pairs[g / nrhs], c = g % nrhs;
+  const PairInfo<V> q = pair_info<V>(T, p, nside, chirp, kern);
+  const V* __restrict__ eop = eo + c * eo_stride + (size_t)p * (mmax + 1) * 2;
+  V* __restrict__ geop = geo + c * geo_stride + (size_t)p * (mmax + 1) * 2;
   double* __restrict__ mp = map + c * map_stride;
 
-  if (MODE == RING_SYNTH || MODE == RING_FUSED) ring_inverse(buf, scratch, q, eop, mmax, T.twiddle, fmax);
-
-  if (MODE == RING_SYNTH) {
+  if (MODE == RING_FUSED) {
+    ring_inverse(buf, scratch, q, eop, mmax, tw, fmax);
+    // N^-1 of the ring (n <= 8 blockDim): all loads issued before the products
+    constexpr int U = 8;
+    Re<V> wn[U], ws[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = threadIdx.x + u * blockDim.x;
+      wn[u] = j < q.n ? (Re<V>)ninv[q.fn + j] : Re<V>(0);
+      ws[u] = (j < q.n && !q.equator) ? (Re<V>)ninv[q.fs + j] : Re<V>(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = threadIdx.x + u * blockDim.x;
+      if (j < q.n) {
+        const V Z = buf[pad(j)];
+        buf[pad(j)] = mk<V>(Z.x * wn[u], Z.y * ws[u]);
+      }
+    }
+  } else if (MODE == RING_SYNTH) {
+    ring_inverse(buf, scratch, q, eop, mmax, tw, fmax);
     for (int j = threadIdx.x; j < q.n; j += blockDim.x) {
-      const double2 Z = buf[j];
-      mp[q.fn + j] = Z.x;
-      if (!q.equator) mp[q.fs + j] = Z.y;
+      const V Z = buf[pad(j)];
+      mp[q.fn + j] = (double)Z.x;
+      if (!q.equator) mp[q.fs + j] = (double)Z.y;
     }
     return;
-  }
-
-  if (MODE == RING_FUSED) {
-    for (int j = threadIdx.x; j < q.n; j += blockDim.x) {
-      const double2 Z = buf[j];
-      buf[j] = make_double2(Z.x * ninv[q.fn + j], q.equator ? 0.0 : Z.y * ninv[q.fs + j]);
-    }
   } else {  // RING_ADJOINT: load the pixels
     for (int j = threadIdx.x; j < q.n; j += blockDim.x)
-      buf[j] = make_double2(mp[q.fn + j], q.equator ? 0.0 : mp[q.fs + j]);
+      buf[pad(j)] = mk<V>((Re<V>)mp[q.fn + j], q.equator ? Re<V>(0) : (Re<V>)mp[q.fs + j]);
   }
-  ring_forward(buf, q, T.twiddle, fmax);
+  ring_forward(buf, q, tw, fmax);
+  lds_barrier();
   write_geo(geop, buf, q, mmax);
+}
+
+int ring_threads(int Lc) { return Lc / 8 < 64 ? 64 : Lc / 8; }
+
+template <class V>
+size_t ring_lds(int Lc) {
+  return (size_t)(Lc + Lc / 16) * sizeof(V);
+}
+
+template <class V, int MODE>
+hipError_t ring_launch(const crsht_plan* P, int nrhs, const V* eo, double* map, const double* ninv, V* geo,
+                       const V* tw, const V* chirp, const V* kern, hipStream_t s) {
+  const Geometry& g = P->g;
+  const int64_t stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
+  for (const RingClass& rc : P->ring_cls) {
+    const size_t lds = ring_lds<V>(rc.L);
+    const int nt = ring_threads(rc.L);
+    const int64_t items = (int64_t)rc.count * nrhs;
+    const unsigned nb = (unsigned)((items + 7) / 8 * 8);
+#define CRSHT_RING_LAUNCH(NT)                                                                                   \
+  do {                                                                                                          \
+    if (lds > 65536)                                                                                            \
+      (void)hipFuncSetAttribute((const void*)k_ring<V, MODE, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,   \
+                                (int)lds);                                                                      \
+    hipLaunchKernelGGL((k_ring<V, MODE, NT>), dim3(nb), dim3(nt), lds, s, P->t, g.nside, g.mmax, g.fft_max,      \
+                       P->t.ring_pairs + rc.off, rc.count, nrhs, rc.L, tw, chirp, kern, eo, stride, map,         \
+                       (int64_t)g.npix, ninv, geo, stride);                                                     \
+  } while (0)
+    if (nt <= 512)
+      CRSHT_RING_LAUNCH(512);
+    else
+      CRSHT_RING_LAUNCH(1024);
+#undef CRSHT_RING_LAUNCH
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <class V>
+hipError_t ring_mode(const crsht_plan* P, int nrhs, RingMode mode, const V* eo, double* map, const double* ninv,
+                     V* geo, const V* tw, const V* chirp, const V* kern, hipStream_t s) {
+  if (mode == RING_SYNTH) return ring_launch<V, RING_SYNTH>(P, nrhs, eo, map, ninv, geo, tw, chirp, kern, s);
+  if (mode == RING_ADJOINT) return ring_launch<V, RING_ADJOINT>(P, nrhs, eo, map, ninv, geo, tw, chirp, kern, s);
+  return ring_launch<V, RING_FUSED>(P, nrhs, eo, map, ninv, geo, tw, chirp, kern, s);
 }
 
 }  // namespace
 
-// threads per ring block: fft_pow2 needs N <= 16 blockDim for every N <= fft_max
-int ring_block(const crsht_plan* P) {
-  int t = P->g.fft_max / 16;
-  if (t < 64) t = 64;
-  return t;
-}
-size_t ring_lds_bytes(const crsht_plan* P) {
-  return (size_t)P->g.fft_max * sizeof(double2) + (size_t)ring_block(P) * 8 * sizeof(double);
+// classes of ring pairs by FFT length: pairs with L <= 512 share one class,
+// every larger power of two has its own
+void ring_classes(const std::vector<int>& fft_len, std::vector<RingClass>& cls, std::vector<int>& pairs) {
+  cls.clear();
+  pairs.clear();
+  int Lmax = 512;
+  for (int L : fft_len) Lmax = L > Lmax ? L : Lmax;
+  for (int Lc = 512; Lc <= Lmax; Lc *= 2) {
+    RingClass rc;
+    rc.L = Lc;
+    rc.off = (int)pairs.size();
+    for (int p = 0; p < (int)fft_len.size(); ++p) {
+      const int L = fft_len[p];
+      if ((Lc == 512 && L <= 512) || (Lc > 512 && L == Lc)) pairs.push_back(p);
+    }
+    rc.count = (int)pairs.size() - rc.off;
+    if (rc.count > 0) cls.push_back(rc);
+  }
 }
 
-hipError_t launch_ring(const crsht_plan* P, int nrhs, RingMode mode, const double2* eo, double* map,
-                       const double* ninv, double2* geo, hipStream_t s) {
-  const Geometry& g = P->g;
-  const int64_t eo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
-  const size_t lds = ring_lds_bytes(P);
-  dim3 grid(g.npairs, nrhs);
-  const int bt = ring_block(P);
-#define CRSHT_RING(MD)                                                                                   \
-  do {                                                                                                   \
-    if (lds > 65536)                                                                                     \
-      (void)hipFuncSetAttribute((const void*)k_ring<MD>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-    hipLaunchKernelGGL(k_ring<MD>, grid, dim3(bt), lds, s, P->t, g.nside, g.mmax, g.fft_max, eo,           \
-                       eo_stride, map, (int64_t)g.npix, ninv, geo, eo_stride);                           \
-  } while (0)
+size_t ring_lds_bytes(const crsht_plan* P, bool f32) {
+  size_t mx = 0;
+  for (const RingClass& rc : P->ring_cls) {
+    const size_t b = f32 ? ring_lds<float2>(rc.L) : ring_lds<double2>(rc.L);
+    mx = b > mx ? b : mx;
+  }
+  return mx;
+}
+
+hipError_t launch_ring(const crsht_plan* P, int nrhs, RingMode mode, const void* eo, double* map,
+                       const double* ninv, void* geo, bool f32, hipStream_t s) {
   timing_begin(P, 2, s);
-  if (mode == RING_SYNTH)
-    CRSHT_RING(RING_SYNTH);
-  else if (mode == RING_ADJOINT)
-    CRSHT_RING(RING_ADJOINT);
+  hipError_t e;
+  if (f32)
+    e = ring_mode<float2>(P, nrhs, mode, (const float2*)eo, map, ninv, (float2*)geo, P->t.twiddle32, P->t.bs_chirp32,
+                          P->t.bs_kern32, s);
   else
-    CRSHT_RING(RING_FUSED);
+    e = ring_mode<double2>(P, nrhs, mode, (const double2*)eo, map, ninv, (double2*)geo, P->t.twiddle, P->t.bs_chirp,
+                           P->t.bs_kern, s);
   timing_end(P, 2, s);
-#undef CRSHT_RING
-  return hipGetLastError();
+  return e;
 }
 
 }  // namespace crsht

@@ -1,11 +1,11 @@
 """Short fixed workloads for hardware-counter runs (rocprofv3 --pmc).
 
-    python -m paper_2306_15511_amd.kernel_probe operator --nside 512 --reps 3
+    python -m paper_2306_15511_amd.kernel_probe operator --nside 512 --nrhs 16 --prec mixed --reps 3
     python -m paper_2306_15511_amd.kernel_probe copy --mib 1024 --reps 3
 
 `operator` applies the constrained-realization operator (Legendre synthesis,
 fused ring pass, Legendre adjoint, vector epilogue) `reps` times on the
-benchmark workload; `copy` copies a float64 buffer of known size so the
+benchmark workload, in FP64 or with the bf16x3 MFMA Legendre steps; `copy` copies a float64 buffer of known size so the
 FETCH_SIZE / WRITE_SIZE counters can be calibrated against exact bytes.
 """
 from __future__ import annotations
@@ -29,6 +29,7 @@ def main():
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--mib", type=int, default=1024)
+    ap.add_argument("--prec", choices=["f64", "mixed"], default="f64")
     a = ap.parse_args()
     dev = torch.device("cuda:0")
     if a.what == "copy":
@@ -48,8 +49,9 @@ def main():
     z, phi = plan.pixel_coords()
     prob = crsht.Problem(wl.cl(), wl.bl(), torch.from_numpy(wl.ninv(z, phi)).to(dev), 2)
     x = torch.from_numpy(np.stack([ci.white_alm(np.random.default_rng(c), lmax) for c in range(a.nrhs)])).to(dev)
+    prec = crsht.CR_MIXED if a.prec == "mixed" else crsht.CR_F64
     for _ in range(a.reps):
-        crsht.apply(plan, prob, x)
+        crsht.apply(plan, prob, x, prec=prec)
     torch.cuda.synchronize()
     print("applied operator x %d at nside %d" % (a.reps, a.nside))
     plan.close()
