@@ -197,7 +197,8 @@ def main():
 
     # algorithmic work per timed unit (one launch; an FP64 adjoint unit is a whole transform)
     T = legendre_triples(nside, lmax, lmax)
-    eo_bytes = 2 * nside * (lmax + 1) * 2 * 16         # Legendre sums of one column (E and O, complex FP64)
+    # Legendre sums of one column (E and O, complex; float2 in the mixed path)
+    eo_bytes = 2 * nside * (lmax + 1) * 2 * (8 if mixed else 16)
     groups = []
     n = R
     while n > 0:
