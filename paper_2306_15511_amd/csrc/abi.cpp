@@ -84,6 +84,18 @@ int operator_core(const crsht_plan* P, int nrhs, const double2* x, const double2
   return CR_OK;
 }
 
+// A p inside the mixed-precision PCG: with update, first p = z + beta p per
+// column (fused with the MFMA operand preparation). out = sinv * p + bk *
+// (Y^T N^-1 Y)(bk p); block partials of <p, out> in row 0.
+int operator_core_cg(const crsht_plan* P, int nrhs, bool update, const double* ninv, double2* out, hipStream_t s) {
+  Workspace const& w = P->w;
+  CR_TRY(launch_legendre_synth_mixed_cg(P, nrhs, w.cg_z, w.cg_p, update, F2(w.eo), s));
+  CR_TRY(launch_ring(P, nrhs, RING_FUSED, w.eo, nullptr, ninv, w.geo, true, s));
+  CR_TRY(launch_legendre_adjoint_mixed(P, nrhs, F2(w.geo), w.alm_b, s));
+  CR_TRY(launch_cg_q(P, nrhs, w.cg_p, w.alm_b, out, s));
+  return CR_OK;
+}
+
 // Jacobi diagonal into w.diag
 int compute_diag(const crsht_plan* P, const double* ninv, hipStream_t s) {
   CR_TRY(launch_ring_weights(P, ninv, P->w.ring_w, s));
@@ -311,14 +323,11 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
         }
       }
       if (!cont) break;
-      // z = D^-1 r from the replaced residual, beta = <r,z>/<r,z>_prev
+      // z = D^-1 r from the replaced residual, beta = <r,z>/<r,z>_prev; the
+      // direction update stays pending (fused into the next operator)
       CR_CHECK(write_scalars(P, nrhs, s));
       CR_TRY(launch_cg_replace(P, nrhs, w.cg_r, w.cg_z, s));
       CR_TRY(launch_cg_scalars(P, nrhs, 3, nb, tol, 0, s));
-    }
-    if (pending) {
-      CR_TRY(launch_cg_pupdate(P, nrhs, w.cg_z, w.cg_p, w.alm_a, s));
-      pending = false;
     }
     bool any = false;
     for (int c = 0; c < nrhs; ++c) any |= P->w.host_scal[c * kScalSlots + S_DONE] == 0.0;
@@ -329,8 +338,7 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
     }
     const int n = std::min(every, o->maxiter - it);
     for (int k = 0; k < n; ++k) {
-      if (pending) CR_TRY(launch_cg_pupdate(P, nrhs, w.cg_z, w.cg_p, w.alm_a, s));
-      CR_CHECK(operator_core(P, nrhs, w.cg_p, w.alm_a, ninv, w.cg_q, s, true));
+      CR_CHECK(operator_core_cg(P, nrhs, pending, ninv, w.cg_q, s));
       CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, s));
       CR_TRY(launch_cg_update(P, nrhs, w.cg_x, w.cg_r, w.cg_z, w.cg_p, w.cg_q, s));
       CR_TRY(launch_cg_scalars(P, nrhs, 2, nb, tol, 0, s));

@@ -63,6 +63,8 @@ struct Tables {
   int64_t* mx_cstart = nullptr;    // [mmax+2] first 32-step synthesis chunk of each m
   int64_t* mx_tstart = nullptr;    // [mmax+2] first 64-step adjoint tile of each m
   int* mx_tile_m = nullptr;        // [ntiles] m of each adjoint tile
+  int* mx_order = nullptr;         // [8][mx_maxq] adjoint tile of (XCD, slot), -1 past the end
+  int mx_maxq = 0;
   double2* mx_ckpt = nullptr;      // [ntiles][npairs] recurrence state at each tile start
   int64_t mx_ntiles = 0;
   int* idx_l = nullptr;            // [nalm] l of each stored coefficient
@@ -177,12 +179,18 @@ hipError_t launch_legendre_adjoint(const crsht_plan* P, int nrhs, const double2*
 // ---- mixed-precision Legendre step (legendre_mfma.hip) ----
 int64_t mixed_ab_bytes(const Geometry& g);
 int64_t mixed_ag_bytes(const Geometry& g);
-void mixed_starts(const Geometry& g, std::vector<int64_t>& cst, std::vector<int64_t>& tst, std::vector<int>& tm);
+void mixed_starts(const Geometry& g, std::vector<int64_t>& cst, std::vector<int64_t>& tst, std::vector<int>& tm,
+                  std::vector<int>& order, int& maxq);
 hipError_t launch_checkpoints(const crsht_plan* P, hipStream_t s);
 // eo = (E, O) sums (float2) with mu (FP64 recurrence) and f * alm rounded to
 // bf16x3, FP32 accumulation; f == nullptr means 1
 hipError_t launch_legendre_synth_mixed(const crsht_plan* P, int nrhs, const double2* alm, const double* f,
                                        float2* eo, hipStream_t s);
+// the same inside PCG: p = z + beta p per column (scalars in w.scal; skipped
+// for done columns or when !update) fused with the operand preparation, then
+// eo from bk * p
+hipError_t launch_legendre_synth_mixed_cg(const crsht_plan* P, int nrhs, const double2* z, double2* p, bool update,
+                                          float2* eo, hipStream_t s);
 // raw sums as launch_legendre_adjoint (non-diag) from float2 geo, bf16x3 /
 // FP32 accumulation
 hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const float2* geo, double2* raw,

@@ -14,6 +14,8 @@
 // MFMA 32x32x16 bf16 lane layout (checked on the device): A[i][k] in lane
 // i + 32 (k / 8), element k % 8; B[k][j] in lane j + 32 (k / 8), element k % 8;
 // D[i][j] in lane j + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace crsht {
@@ -28,10 +30,26 @@ constexpr int kSynChunk = 32;   // steps per synthesis K chunk (16 even + 16 odd
 constexpr int kAdjTile = 64;    // steps per adjoint output tile (32 even + 32 odd)
 constexpr int kAdjWaves = 4;
 
+// Blocks are dealt to the 8 XCDs round-robin by linear block index. The m of
+// the j-th m-slot of an XCD: each XCD takes 4 consecutive m out of every 32,
+// which balances long and short m over the XCDs and keeps neighbouring m (and
+// all ring-pair blocks of one m) in one L2.
+__host__ __device__ __forceinline__ int xcd_m(int j, int xcd) { return (j >> 2) * 32 + xcd * 4 + (j & 3); }
+__host__ __device__ __forceinline__ int m_xcd(int m) { return (m & 31) >> 2; }
+
 __device__ __forceinline__ int wave_min(int v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
   return v;
+}
+
+// double -> float, kept as a separate rounding step (the empty asm stops the
+// compiler from folding double -> float -> bf16 into a direct double -> bf16
+// conversion, which it emulates with round-to-odd at several times the cost)
+__device__ __forceinline__ float to_f32(double x) {
+  float f = (float)x;
+  asm volatile("" : "+v"(f));
+  return f;
 }
 
 // float -> (hi, lo) bf16 with hi = RNE(x), lo = RNE(x - hi)
@@ -117,6 +135,68 @@ __global__ __launch_bounds__(64) void k_prep_synth(int lmax, int nrhs, const int
   }
 }
 
+// PCG direction update fused with the synthesis operands: for the chunk
+// (m, c), p = z + beta p per column (unless the column is done or `update` is
+// 0), written back in FP64, and the ab tiles built from bk * p. z, p: [rhs][nalm]
+// at column stride nalm; the block stages bk * p (float) in LDS as
+// [q][rhs][comp][16 steps] so that each lane reads its 8 steps contiguously.
+__global__ __launch_bounds__(64) void k_pupdate_prep(int lmax, int nrhs, int64_t nalm, const int64_t* __restrict__ mstart,
+                                                     const int64_t* __restrict__ cstart, const double* __restrict__ bk,
+                                                     const double2* __restrict__ z, double2* __restrict__ p,
+                                                     const double* __restrict__ scal, int update,
+                                                     bf16x8* __restrict__ ab) {
+  __shared__ __attribute__((aligned(16))) float st_lds[2][16][2][16];
+  const int m = blockIdx.y, c = blockIdx.x;
+  const int nsteps = lmax - m + 1;
+  if (c * kSynChunk >= nsteps) return;
+  const int lane = threadIdx.x;
+  const int64_t base = mstart[m];
+  // element phase: lane -> step lane & 31, columns (lane >> 5) + 2 i
+  const int st = c * kSynChunk + (lane & 31);
+  const bool live = st < nsteps;
+  const double f = live ? bk[base + st] : 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int rhs = (lane >> 5) + 2 * i;
+    double2 pv = make_double2(0.0, 0.0);
+    if (rhs < nrhs && live) {
+      const int64_t e = rhs * nalm + base + st;
+      pv = p[e];
+      const double* sc = scal + rhs * kScalSlots;
+      if (update && sc[S_DONE] == 0.0) {
+        const double beta = sc[S_BETA];
+        const double2 zv = z[e];
+        pv.x = fma(beta, pv.x, zv.x);
+        pv.y = fma(beta, pv.y, zv.y);
+        p[e] = pv;
+      }
+    }
+    const int q = (lane & 31) & 1, n = (lane & 31) >> 1;
+    st_lds[q][rhs][0][n] = to_f32(f * pv.x);
+    st_lds[q][rhs][1][n] = to_f32(f * pv.y);
+  }
+  __syncthreads();
+  // tile phase: lane j + 32 kg, j = 2 rhs + comp, holds steps 2 (8 kg + v) + q
+  const int j = lane & 31, kg = lane >> 5;
+  bf16x8* dst = ab + (size_t)(cstart[m] + c) * 4 * 64;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const float* src = &st_lds[q][j >> 1][j & 1][8 * kg];
+    const float4 a4 = *reinterpret_cast<const float4*>(src), b4 = *reinterpret_cast<const float4*>(src + 4);
+    const float x[8] = {a4.x, a4.y, a4.z, a4.w, b4.x, b4.y, b4.z, b4.w};
+    bf16x8 hi, lo;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      __bf16 h, l;
+      split_bf16(x[v], h, l);
+      hi[v] = h;
+      lo[v] = l;
+    }
+    dst[(q * 2 + 0) * 64 + lane] = hi;
+    dst[(q * 2 + 1) * 64 + lane] = lo;
+  }
+}
+
 // ----------------------------------------------------------------- synthesis
 // One wavefront per (m, block of 64 ring pairs): lane p runs the recurrence
 // of pair p for a chunk of 32 steps, writes mu (bf16 hi, lo; even and odd
@@ -132,9 +212,12 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
                                                    int64_t eo_stride) {
   // tile[q][h][pair][16 k] bf16: 2 x 2 x 64 x 32 bytes
   __shared__ bf16x8 tile[2][2][64][2];
-  const int m = blockIdx.x;
+  const int npb = (npairs + 63) / 64;
+  const int q8 = blockIdx.x >> 3;
+  const int m = xcd_m(q8 / npb, blockIdx.x & 7), pb = q8 % npb;
+  if (m > mmax) return;
   const int lane = threadIdx.x;
-  const int p = blockIdx.y * 64 + lane;
+  const int p = pb * 64 + lane;
   const bool valid = p < npairs;
   const int pp = valid ? p : npairs - 1;
   const size_t o = (size_t)m * npairs + pp;
@@ -155,21 +238,40 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
       const bf16x8* src = ab + (size_t)(cstart[m] + c) * 4 * 64;
       const bf16x8 bEh = src[0 * 64 + lane], bEl = src[1 * 64 + lane];
       const bf16x8 bOh = src[2 * 64 + lane], bOl = src[3 * 64 + lane];
+      // recurrence over the chunk: alpha is wave-uniform (scalar loads), the
+      // start state is injected by selects at the 16-step group boundaries
+      const int st0 = c * kSynChunk;
+      const double* __restrict__ ac = alpha + __builtin_amdgcn_readfirstlane((int)(base + st0));
       float mu32[kSynChunk];
+      if (st0 + kSynChunk <= nsteps) {
 #pragma unroll
-      for (int s = 0; s < kSynChunk; ++s) {
-        const int st = c * kSynChunk + s;
-        if (s % kGroup == 0 && st / kGroup == gs) {
-          v0 = s0.x;
-          v1 = s0.y;
-        }
-        double mu = 0.0;
-        if (st < nsteps) {
-          mu = fma(alpha[base + st] * z, v1, -v0);
+        for (int s = 0; s < kSynChunk; ++s) {
+          if (s % kGroup == 0) {
+            const bool inj = (st0 + s) / kGroup == gs;
+            v0 = inj ? s0.x : v0;
+            v1 = inj ? s0.y : v1;
+          }
+          const double mu = fma(ac[s] * z, v1, -v0);
           v0 = v1;
           v1 = mu;
+          mu32[s] = to_f32(mu);
         }
-        mu32[s] = (float)mu;
+      } else {
+#pragma unroll
+        for (int s = 0; s < kSynChunk; ++s) {
+          if (s % kGroup == 0) {
+            const bool inj = (st0 + s) / kGroup == gs;
+            v0 = inj ? s0.x : v0;
+            v1 = inj ? s0.y : v1;
+          }
+          double mu = 0.0;
+          if (st0 + s < nsteps) {
+            mu = fma(ac[s] * z, v1, -v0);
+            v0 = v1;
+            v1 = mu;
+          }
+          mu32[s] = to_f32(mu);
+        }
       }
       bf16x8 eh[2], el[2], oh[2], ol[2];
 #pragma unroll
@@ -213,7 +315,7 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
     const int i = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      const int pr = blockIdx.y * 64 + 32 * t + i;
+      const int pr = pb * 64 + 32 * t + i;
       if (pr >= npairs) continue;
       float* dst = reinterpret_cast<float*>(eo + rhs * eo_stride + ((size_t)pr * (mmax + 1) + m) * 2);
       dst[comp] = t ? dE1[r] : dE0[r];
@@ -225,33 +327,56 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
 // -------------------------------------------------------- adjoint operands
 // ag tiles: for each (m, block of 16 pairs), parity q, half h, the MFMA A
 // operand A[c][k] = G_q[pair = 16 kb + k][col c] in lane order (lane
-// c + 32 (k/8) holds 8 bf16), from the FP64 ring-pass output geo.
-__global__ __launch_bounds__(64) void k_prep_adj(int mmax, int npairs, int nrhs, const float2* __restrict__ geo,
-                                                 int64_t geo_stride, bf16x8* __restrict__ ag) {
-  const int kb = blockIdx.x, m = blockIdx.y;
+// c + 32 (k/8) holds 8 bf16), from the ring-pass output geo
+// [rhs][pair][m][q] (float2). A block transposes 16 pairs x 8 m x 16
+// columns through LDS: rows (rhs, pair) of 8 m are read coalesced, the
+// operand vectors are written contiguously.
+constexpr int kPrepM = 8;                       // m per block
+constexpr int kPrepMS = 2 * 16 * 2 * 16 + 8;   // floats per m in LDS ([q][rhs][comp][pair], padded)
+__global__ __launch_bounds__(256) void k_prep_adj(int mmax, int npairs, int nrhs, const float2* __restrict__ geo,
+                                                  int64_t geo_stride, bf16x8* __restrict__ ag) {
+  __shared__ __attribute__((aligned(16))) float G[kPrepM * kPrepMS];
+  const int kb = blockIdx.x, m0 = blockIdx.y * kPrepM;
   const int nkb = (npairs + 15) / 16;
-  const int lane = threadIdx.x;
-  const int cidx = lane & 31, kg = lane >> 5;
-  const int rhs = cidx >> 1, comp = cidx & 1;
-  bf16x8* dst = ag + ((size_t)m * nkb + kb) * 4 * 64;
+  const int t = threadIdx.x;
+  // load: row = rhs * 16 + pair (256 rows), 8 m per row, one float4 (q = 0, 1) per (row, m)
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    bf16x8 hi, lo;
+  for (int i = 0; i < 8; ++i) {
+    const int e = t + i * 256;             // (row, m) item
+    const int mm = e & (kPrepM - 1), row = e >> 3;
+    const int rhs = row >> 4, pr = row & 15;
+    const int pair = kb * 16 + pr, m = m0 + mm;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (rhs < nrhs && pair < npairs && m <= mmax)
+      v = *reinterpret_cast<const float4*>(geo + rhs * geo_stride + ((size_t)pair * (mmax + 1) + m) * 2);
+    float* d = G + mm * kPrepMS + rhs * 32 + pr;
+    d[0 * 512 + 0] = v.x;    // q = 0, re
+    d[0 * 512 + 16] = v.y;   // q = 0, im
+    d[1 * 512 + 0] = v.z;    // q = 1, re
+    d[1 * 512 + 16] = v.w;   // q = 1, im
+  }
+  __syncthreads();
+  // write: thread (q, lane) of one m builds the hi and lo operand vectors
+  const int q = (t >> 6) & 1, lane = t & 63;
+  const int c = lane & 31, kg = lane >> 5;
+#pragma unroll
+  for (int pass = 0; pass < kPrepM / 2; ++pass) {
+    const int mm = pass * 2 + (t >> 7), m = m0 + mm;
+    if (m > mmax) continue;
+    const float* src = G + mm * kPrepMS + q * 512 + c * 16 + kg * 8;
+    const float4 lo4 = *reinterpret_cast<const float4*>(src), hi4 = *reinterpret_cast<const float4*>(src + 4);
+    const float x[8] = {lo4.x, lo4.y, lo4.z, lo4.w, hi4.x, hi4.y, hi4.z, hi4.w};
+    bf16x8 h8, l8;
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
-      const int pr = kb * 16 + 8 * kg + v;
-      float x = 0.0f;
-      if (rhs < nrhs && pr < npairs) {
-        const float2 g = geo[rhs * geo_stride + ((size_t)pr * (mmax + 1) + m) * 2 + q];
-        x = comp ? g.y : g.x;
-      }
       __bf16 h, l;
-      split_bf16(x, h, l);
-      hi[v] = h;
-      lo[v] = l;
+      split_bf16(x[v], h, l);
+      h8[v] = h;
+      l8[v] = l;
     }
-    dst[(q * 2 + 0) * 64 + lane] = hi;
-    dst[(q * 2 + 1) * 64 + lane] = lo;
+    bf16x8* dst = ag + ((size_t)m * nkb + kb) * 4 * 64;
+    dst[(q * 2 + 0) * 64 + lane] = h8;
+    dst[(q * 2 + 1) * 64 + lane] = l8;
   }
 }
 
@@ -268,17 +393,49 @@ constexpr int kRowB = 64 * 2;   // bytes per LDS row: 64 pairs of bf16
 // one B-fragment load fall on different LDS banks
 __device__ __forceinline__ int swz(int row, int chunk) { return ((chunk ^ (row & 7)) << 4); }
 
+// One tile of the recurrence for this lane's ring pair: mu (bf16 hi, lo) of
+// the 64 steps into the wavefront's LDS tile [q][h][step / 2][pair]. The
+// start state is injected by selects at the 16-step group boundaries; with
+// TAIL, steps at or past slim give mu = 0.
+template <bool TAIL>
+__device__ __forceinline__ void adj_tile_steps(unsigned char* my, int lane, int st0, int slim, int gs, double2 s0,
+                                               double z, double v0, double v1, int av_lo, int av_hi) {
+  const int cb0 = (lane & 7) * 2;
+  for (int g = 0; g < kAdjTile / kGroup; ++g) {
+    const bool inj = st0 / kGroup + g == gs;
+    v0 = inj ? s0.x : v0;
+    v1 = inj ? s0.y : v1;
+#pragma unroll
+    for (int j = 0; j < kGroup; ++j) {
+      const int s = g * kGroup + j;
+      const double a = __hiloint2double(__builtin_amdgcn_readlane(av_hi, s), __builtin_amdgcn_readlane(av_lo, s));
+      double mu = fma(a * z, v1, -v0);
+      if (TAIL) mu = s < slim ? mu : 0.0;
+      v0 = v1;
+      v1 = mu;
+      __bf16 h, l;
+      split_bf16(to_f32(mu), h, l);
+      const int q = j & 1, n = s >> 1;
+      const int cb = swz(n, lane >> 3) + cb0;
+      *reinterpret_cast<__bf16*>(my + ((q * 2 + 0) * 32 + n) * kRowB + cb) = h;
+      *reinterpret_cast<__bf16*>(my + ((q * 2 + 1) * 32 + n) * kRowB + cb) = l;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs, int nrhs,
                                                   const double* __restrict__ pair_z, const double* __restrict__ alpha,
                                                   const int* __restrict__ lst_g, const double2* __restrict__ lst_s,
                                                   const int64_t* __restrict__ mstart,
                                                   const int64_t* __restrict__ tstart,
-                                                  const int* __restrict__ tile_m, const double2* __restrict__ ckpt,
+                                                  const int* __restrict__ tile_m, const int* __restrict__ order,
+                                                  int maxq, const double2* __restrict__ ckpt,
                                                   const bf16x8* __restrict__ ag, double2* __restrict__ out,
                                                   int64_t out_stride) {
   // per wavefront: [q][h][32 steps][kRowB bytes]; reused for the partial results
   __shared__ __attribute__((aligned(16))) unsigned char lds[kAdjWaves][2][2][32][kRowB];
-  const int tid = blockIdx.x;                 // global tile id
+  const int tid = order[(blockIdx.x & 7) * maxq + (blockIdx.x >> 3)];   // tiles of one m stay on one XCD
+  if (tid < 0) return;
   const int m = tile_m[tid];
   const int T = tid - (int)tstart[m];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -303,26 +460,16 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
     const double2 s0 = lst_s[o];
     const double2 ck = valid ? ckpt[(size_t)(tstart[m] + T) * npairs + pp] : make_double2(0.0, 0.0);
     double v0 = ck.x, v1 = ck.y;
-#pragma unroll 4
-    for (int s = 0; s < kAdjTile; ++s) {
-      const int st = st0 + s;
-      if (s % kGroup == 0 && st / kGroup == gs) {
-        v0 = s0.x;
-        v1 = s0.y;
-      }
-      double mu = 0.0;
-      if (st < nsteps) {
-        mu = fma(alpha[base + st] * z, v1, -v0);
-        v0 = v1;
-        v1 = mu;
-      }
-      __bf16 h, l;
-      split_bf16((float)mu, h, l);
-      const int q = s & 1, n = s >> 1;
-      const int cb = swz(n, lane >> 3) + (lane & 7) * 2;
-      *reinterpret_cast<__bf16*>(my + ((q * 2 + 0) * 32 + n) * kRowB + cb) = h;
-      *reinterpret_cast<__bf16*>(my + ((q * 2 + 1) * 32 + n) * kRowB + cb) = l;
-    }
+    // alpha of the tile: lane s holds alpha of step s (one coalesced load),
+    // broadcast per step by readlane (no scalar loads, which would wait on
+    // the LDS counter behind the tile writes)
+    const int slim = min(kAdjTile, nsteps - st0);
+    const double av = lane < slim ? alpha[base + st0 + lane] : 0.0;
+    const int av_lo = __double2loint(av), av_hi = __double2hiint(av);
+    if (slim == kAdjTile)
+      adj_tile_steps<false>(my, lane, st0, slim, gs, s0, z, v0, v1, av_lo, av_hi);
+    else
+      adj_tile_steps<true>(my, lane, st0, slim, gs, s0, z, v0, v1, av_lo, av_hi);
     // the tile is private to this wavefront and LDS accesses of one
     // wavefront complete in order: a compiler barrier suffices
     __builtin_amdgcn_wave_barrier();
@@ -384,7 +531,8 @@ int64_t mixed_adj_tiles(const Geometry& g) {
 }
 int64_t mixed_ab_bytes(const Geometry& g) { return mixed_synth_chunks(g) * 4 * 64 * 16; }
 int64_t mixed_ag_bytes(const Geometry& g) { return (int64_t)(g.mmax + 1) * ((g.npairs + 15) / 16) * 4 * 64 * 16; }
-void mixed_starts(const Geometry& g, std::vector<int64_t>& cst, std::vector<int64_t>& tst, std::vector<int>& tm) {
+void mixed_starts(const Geometry& g, std::vector<int64_t>& cst, std::vector<int64_t>& tst, std::vector<int>& tm,
+                  std::vector<int>& order, int& maxq) {
   cst.assign(g.mmax + 2, 0);
   tst.assign(g.mmax + 2, 0);
   tm.clear();
@@ -395,6 +543,21 @@ void mixed_starts(const Geometry& g, std::vector<int64_t>& cst, std::vector<int6
     tst[m + 1] = tst[m] + nt;
     for (int t = 0; t < nt; ++t) tm.push_back(m);
   }
+  // adjoint launch order: per XCD the tiles of its m (xcd_m), m ascending
+  std::vector<std::vector<int>> per(8);
+  for (int m = 0; m <= g.mmax; ++m)
+    for (int64_t t = tst[m]; t < tst[m + 1]; ++t) per[m_xcd(m)].push_back((int)t);
+  maxq = 0;
+  for (auto& v : per) maxq = std::max(maxq, (int)v.size());
+  order.assign((size_t)8 * maxq, -1);
+  for (int x = 0; x < 8; ++x)
+    for (size_t q = 0; q < per[x].size(); ++q) order[(size_t)x * maxq + q] = per[x][q];
+}
+
+int synth_mfma_blocks(const Geometry& g) {
+  const int npb = (g.npairs + 63) / 64;
+  const int jmax = (g.mmax + 32) / 32 * 4;   // m-slots per XCD covering m = 0..mmax
+  return 8 * jmax * npb;
 }
 
 hipError_t launch_checkpoints(const crsht_plan* P, hipStream_t s) {
@@ -418,7 +581,30 @@ hipError_t launch_legendre_synth_mixed(const crsht_plan* P, int nrhs, const doub
     hipLaunchKernelGGL(k_prep_synth, gp, dim3(64), 0, s, g.lmax, nr, P->t.mstart, P->t.mx_cstart,
                        alm + (int64_t)c0 * g.nalm, (int64_t)g.nalm, f, ab);
     timing_begin(P, 3, s);
-    dim3 gs(g.mmax + 1, (g.npairs + 63) / 64);
+    dim3 gs(synth_mfma_blocks(g));
+    hipLaunchKernelGGL(k_synth_mfma, gs, dim3(64), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.pair_z, P->t.rec_alpha,
+                       P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.mx_cstart, (const bf16x8*)ab,
+                       eo + (int64_t)c0 * eo_stride, eo_stride);
+    timing_end(P, 3, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_legendre_synth_mixed_cg(const crsht_plan* P, int nrhs, const double2* z, double2* p, bool update,
+                                          float2* eo, hipStream_t s) {
+  const Geometry& g = P->g;
+  const int64_t eo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
+  bf16x8* ab = reinterpret_cast<bf16x8*>(P->w.mx_ab);
+  for (int c0 = 0; c0 < nrhs; c0 += kMixedCols / 2) {
+    const int nr = min(nrhs - c0, kMixedCols / 2);
+    dim3 gp((g.lmax + kSynChunk) / kSynChunk, g.mmax + 1);
+    hipLaunchKernelGGL(k_pupdate_prep, gp, dim3(64), 0, s, g.lmax, nr, g.nalm, P->t.mstart, P->t.mx_cstart,
+                       P->w.bk, z + (int64_t)c0 * g.nalm, p + (int64_t)c0 * g.nalm,
+                       P->w.scal + (int64_t)c0 * kScalSlots, update ? 1 : 0, ab);
+    timing_begin(P, 3, s);
+    dim3 gs(synth_mfma_blocks(g));
     hipLaunchKernelGGL(k_synth_mfma, gs, dim3(64), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.pair_z, P->t.rec_alpha,
                        P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.mx_cstart, (const bf16x8*)ab,
                        eo + (int64_t)c0 * eo_stride, eo_stride);
@@ -436,13 +622,13 @@ hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const fl
   bf16x8* ag = reinterpret_cast<bf16x8*>(P->w.mx_ag);
   for (int c0 = 0; c0 < nrhs; c0 += kMixedCols / 2) {
     const int nr = min(nrhs - c0, kMixedCols / 2);
-    dim3 gp((g.npairs + 15) / 16, g.mmax + 1);
-    hipLaunchKernelGGL(k_prep_adj, gp, dim3(64), 0, s, g.mmax, g.npairs, nr, geo + (int64_t)c0 * geo_stride,
+    dim3 gp((g.npairs + 15) / 16, (g.mmax + kPrepM) / kPrepM);
+    hipLaunchKernelGGL(k_prep_adj, gp, dim3(256), 0, s, g.mmax, g.npairs, nr, geo + (int64_t)c0 * geo_stride,
                        geo_stride, ag);
     timing_begin(P, 4, s);
-    hipLaunchKernelGGL(k_adj_mfma, dim3((unsigned)P->t.mx_ntiles), dim3(kAdjWaves * 64), 0, s, g.lmax, g.mmax,
+    hipLaunchKernelGGL(k_adj_mfma, dim3(8u * (unsigned)P->t.mx_maxq), dim3(kAdjWaves * 64), 0, s, g.lmax, g.mmax,
                        g.npairs, nr, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
-                       P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_ckpt, (const bf16x8*)ag,
+                       P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_order, P->t.mx_maxq, P->t.mx_ckpt, (const bf16x8*)ag,
                        raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm);
     timing_end(P, 4, s);
     hipError_t e = hipGetLastError();
