@@ -48,7 +48,7 @@ __device__ __forceinline__ int wave_min(int v) {
 // conversion, which it emulates with round-to-odd at several times the cost)
 __device__ __forceinline__ float to_f32(double x) {
   float f = (float)x;
-  asm volatile("" : "+v"(f));
+  asm("" : "+v"(f));
   return f;
 }
 
@@ -56,6 +56,23 @@ __device__ __forceinline__ float to_f32(double x) {
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   hi = (__bf16)x;
   lo = (__bf16)(x - (float)hi);
+}
+
+// v_permlane32_swap per dword: t0 = (lanes 0-31: k0 own, lanes 32-63: k1 of
+// lane - 32), t1 = (lanes 0-31: k0 of lane + 32, lanes 32-63: k1 own)
+// (lane layout checked on the device)
+__device__ __forceinline__ void swap_halves(bf16x8 k0, bf16x8 k1, bf16x8& t0, bf16x8& t1) {
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 a = __builtin_bit_cast(u32x4, k0), b = __builtin_bit_cast(u32x4, k1);
+  u32x4 r0, r1;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const auto r = __builtin_amdgcn_permlane32_swap(a[i], b[i], false, false);
+    r0[i] = r[0];
+    r1[i] = r[1];
+  }
+  t0 = __builtin_bit_cast(bf16x8, r0);
+  t1 = __builtin_bit_cast(bf16x8, r1);
 }
 
 __device__ __forceinline__ f32x16 mfma3(bf16x8 ah, bf16x8 al, bf16x8 bh, bf16x8 bl, f32x16 d) {
@@ -210,8 +227,6 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
                                                    const int64_t* __restrict__ cstart,
                                                    const bf16x8* __restrict__ ab, float2* __restrict__ eo,
                                                    int64_t eo_stride) {
-  // tile[q][h][pair][16 k] bf16: 2 x 2 x 64 x 32 bytes
-  __shared__ bf16x8 tile[2][2][64][2];
   const int npb = (npairs + 63) / 64;
   const int q8 = blockIdx.x >> 3;
   const int m = xcd_m(q8 / npb, blockIdx.x & 7), pb = q8 % npb;
@@ -232,18 +247,30 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
   if (gmin != kNever) {
     const int nch = (nsteps + kSynChunk - 1) / kSynChunk;
     double v0 = 0.0, v1 = 0.0;
-    const int row = lane & 31, kg = lane >> 5;
-    for (int c = (gmin * kGroup) / kSynChunk; c < nch; ++c) {
-      // operands of this chunk (independent of the recurrence: issue first)
-      const bf16x8* src = ab + (size_t)(cstart[m] + c) * 4 * 64;
-      const bf16x8 bEh = src[0 * 64 + lane], bEl = src[1 * 64 + lane];
-      const bf16x8 bOh = src[2 * 64 + lane], bOl = src[3 * 64 + lane];
+    const bf16x8* abm = ab + (size_t)cstart[m] * 4 * 64 + lane;
+    const int cfirst = (gmin * kGroup) / kSynChunk;
+    // operands are loaded one chunk ahead (their latency overlaps a chunk)
+    bf16x8 nEh = abm[(size_t)cfirst * 256 + 0], nEl = abm[(size_t)cfirst * 256 + 64];
+    bf16x8 nOh = abm[(size_t)cfirst * 256 + 128], nOl = abm[(size_t)cfirst * 256 + 192];
+    for (int c = cfirst; c < nch; ++c) {
+      const bf16x8 bEh = nEh, bEl = nEl, bOh = nOh, bOl = nOl;
+      if (c + 1 < nch) {
+        const bf16x8* src = abm + (size_t)(c + 1) * 256;
+        nEh = src[0];
+        nEl = src[64];
+        nOh = src[128];
+        nOl = src[192];
+      }
       // recurrence over the chunk: alpha is wave-uniform (scalar loads), the
       // start state is injected by selects at the 16-step group boundaries
       const int st0 = c * kSynChunk;
       const double* __restrict__ ac = alpha + __builtin_amdgcn_readfirstlane((int)(base + st0));
       float mu32[kSynChunk];
       if (st0 + kSynChunk <= nsteps) {
+        // all 32 scalar loads issued before the first use (one wait per chunk)
+        double a[kSynChunk];
+#pragma unroll
+        for (int s = 0; s < kSynChunk; ++s) a[s] = ac[s];
 #pragma unroll
         for (int s = 0; s < kSynChunk; ++s) {
           if (s % kGroup == 0) {
@@ -251,7 +278,7 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
             v0 = inj ? s0.x : v0;
             v1 = inj ? s0.y : v1;
           }
-          const double mu = fma(ac[s] * z, v1, -v0);
+          const double mu = fma(a[s] * z, v1, -v0);
           v0 = v1;
           v1 = mu;
           mu32[s] = to_f32(mu);
@@ -286,20 +313,14 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
           oh[h][v] = a;
           ol[h][v] = b;
         }
-      __syncthreads();   // previous chunk's tile reads are done
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        tile[0][0][lane][h] = eh[h];
-        tile[0][1][lane][h] = el[h];
-        tile[1][0][lane][h] = oh[h];
-        tile[1][1][lane][h] = ol[h];
-      }
-      __syncthreads();
-      // A fragments: lane holds A[row][8 kg .. 8 kg + 7] of M tile t (pairs 32 t + row)
-      const bf16x8 aEh0 = tile[0][0][row][kg], aEl0 = tile[0][1][row][kg];
-      const bf16x8 aOh0 = tile[1][0][row][kg], aOl0 = tile[1][1][row][kg];
-      const bf16x8 aEh1 = tile[0][0][32 + row][kg], aEl1 = tile[0][1][32 + row][kg];
-      const bf16x8 aOh1 = tile[1][0][32 + row][kg], aOl1 = tile[1][1][32 + row][kg];
+      // A fragments (lane row + 32 kg holds A[row][8 kg .. 8 kg + 7] of M tile t,
+      // pairs 32 t + row): lane p owns all 16 k of its pair, so one
+      // permlane32 swap of (k 0..7, k 8..15) gives both tiles' fragments
+      bf16x8 aEh0, aEh1, aEl0, aEl1, aOh0, aOh1, aOl0, aOl1;
+      swap_halves(eh[0], eh[1], aEh0, aEh1);
+      swap_halves(el[0], el[1], aEl0, aEl1);
+      swap_halves(oh[0], oh[1], aOh0, aOh1);
+      swap_halves(ol[0], ol[1], aOl0, aOl1);
       dE0 = mfma3(aEh0, aEl0, bEh, bEl, dE0);
       dE1 = mfma3(aEh1, aEl1, bEh, bEl, dE1);
       dO0 = mfma3(aOh0, aOl0, bOh, bOl, dO0);
@@ -448,48 +469,74 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
   const int row = lane & 31, kg = lane >> 5;
   unsigned char* my = &lds[w][0][0][0][0];
 
-  for (int r0 = w * per; r0 < min(npairs, (w + 1) * per); r0 += 64) {
+  // per-pair data of a round (start group, z, start state, checkpoint)
+  struct PairData {
+    int gs;
+    double z;
+    double2 s0, ck;
+  };
+  const int rend = min(npairs, (w + 1) * per);
+  auto load_pairs = [&](int r0) {
+    PairData d;
     const int p = r0 + lane;
     const bool valid = p < npairs;
     const int pp = valid ? p : npairs - 1;
     const size_t o = (size_t)m * npairs + pp;
-    const int gs = valid ? lst_g[o] : kNever;
+    d.gs = valid ? lst_g[o] : kNever;
+    d.z = pair_z[pp];
+    d.s0 = lst_s[o];
+    d.ck = valid ? ckpt[(size_t)(tstart[m] + T) * npairs + pp] : make_double2(0.0, 0.0);
+    return d;
+  };
+  PairData cur = load_pairs(min(w * per, npairs - 1));
+  for (int r0 = w * per; r0 < rend; r0 += 64) {
+    // the next round's pair data is loaded while this round runs
+    PairData nxt = cur;
+    if (r0 + 64 < rend) nxt = load_pairs(r0 + 64);
+    const int gs = cur.gs;
     // skip the round when no pair becomes live before the end of the tile
-    if (wave_min(gs) > (st0 + kAdjTile - 1) / kGroup) continue;
-    const double z = pair_z[pp];
-    const double2 s0 = lst_s[o];
-    const double2 ck = valid ? ckpt[(size_t)(tstart[m] + T) * npairs + pp] : make_double2(0.0, 0.0);
-    double v0 = ck.x, v1 = ck.y;
-    // alpha of the tile: lane s holds alpha of step s (one coalesced load),
-    // broadcast per step by readlane (no scalar loads, which would wait on
-    // the LDS counter behind the tile writes)
-    const int slim = min(kAdjTile, nsteps - st0);
-    const double av = lane < slim ? alpha[base + st0 + lane] : 0.0;
-    const int av_lo = __double2loint(av), av_hi = __double2hiint(av);
-    if (slim == kAdjTile)
-      adj_tile_steps<false>(my, lane, st0, slim, gs, s0, z, v0, v1, av_lo, av_hi);
-    else
-      adj_tile_steps<true>(my, lane, st0, slim, gs, s0, z, v0, v1, av_lo, av_hi);
-    // the tile is private to this wavefront and LDS accesses of one
-    // wavefront complete in order: a compiler barrier suffices
-    __builtin_amdgcn_wave_barrier();
+    if (wave_min(gs) <= (st0 + kAdjTile - 1) / kGroup) {
+      // G operands of the round's 4 blocks of 16 pairs, issued before the recurrence
+      bf16x8 aq[4][4];
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-      const int gkb = r0 / 16 + kb;
-      if (gkb >= nkb) break;
-      const bf16x8* a = ag + ((size_t)m * nkb + gkb) * 4 * 64;
-      const bf16x8 aEh = a[0 * 64 + lane], aEl = a[1 * 64 + lane];
-      const bf16x8 aOh = a[2 * 64 + lane], aOl = a[3 * 64 + lane];
-      // B[k][n] = mu(pair 16 kb + k, step pair n): lane n + 32 (k/8) reads 8 pairs of row n
-      const int off = swz(row, 2 * kb + kg);
-      const bf16x8 bEh = *reinterpret_cast<const bf16x8*>(my + ((0 * 2 + 0) * 32 + row) * kRowB + off);
-      const bf16x8 bEl = *reinterpret_cast<const bf16x8*>(my + ((0 * 2 + 1) * 32 + row) * kRowB + off);
-      const bf16x8 bOh = *reinterpret_cast<const bf16x8*>(my + ((1 * 2 + 0) * 32 + row) * kRowB + off);
-      const bf16x8 bOl = *reinterpret_cast<const bf16x8*>(my + ((1 * 2 + 1) * 32 + row) * kRowB + off);
-      dE = mfma3(aEh, aEl, bEh, bEl, dE);
-      dO = mfma3(aOh, aOl, bOh, bOl, dO);
+      for (int kb = 0; kb < 4; ++kb) {
+        const int gkb = min(r0 / 16 + kb, nkb - 1);
+        const bf16x8* a = ag + ((size_t)m * nkb + gkb) * 4 * 64;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) aq[kb][u] = a[u * 64 + lane];
+      }
+      const double z = cur.z;
+      const double2 s0 = cur.s0;
+      double v0 = cur.ck.x, v1 = cur.ck.y;
+      // alpha of the tile: lane s holds alpha of step s (one coalesced load),
+      // broadcast per step by readlane (no scalar loads, which would wait on
+      // the LDS counter behind the tile writes)
+      const int slim = min(kAdjTile, nsteps - st0);
+      const double av = lane < slim ? alpha[base + st0 + lane] : 0.0;
+      const int av_lo = __double2loint(av), av_hi = __double2hiint(av);
+      if (slim == kAdjTile)
+        adj_tile_steps<false>(my, lane, st0, slim, gs, s0, z, v0, v1, av_lo, av_hi);
+      else
+        adj_tile_steps<true>(my, lane, st0, slim, gs, s0, z, v0, v1, av_lo, av_hi);
+      // the tile is private to this wavefront and LDS accesses of one
+      // wavefront complete in order: a compiler barrier suffices
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) {
+        const int gkb = r0 / 16 + kb;
+        if (gkb >= nkb) break;
+        // B[k][n] = mu(pair 16 kb + k, step pair n): lane n + 32 (k/8) reads 8 pairs of row n
+        const int off = swz(row, 2 * kb + kg);
+        const bf16x8 bEh = *reinterpret_cast<const bf16x8*>(my + ((0 * 2 + 0) * 32 + row) * kRowB + off);
+        const bf16x8 bEl = *reinterpret_cast<const bf16x8*>(my + ((0 * 2 + 1) * 32 + row) * kRowB + off);
+        const bf16x8 bOh = *reinterpret_cast<const bf16x8*>(my + ((1 * 2 + 0) * 32 + row) * kRowB + off);
+        const bf16x8 bOl = *reinterpret_cast<const bf16x8*>(my + ((1 * 2 + 1) * 32 + row) * kRowB + off);
+        dE = mfma3(aq[kb][0], aq[kb][1], bEh, bEl, dE);
+        dO = mfma3(aq[kb][2], aq[kb][3], bOh, bOl, dO);
+      }
+      __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_wave_barrier();
+    cur = nxt;
   }
   // one block-wide barrier, reached once by every wavefront; each wavefront
   // reuses its own tile area for its partial result red[w][q][r][lane]
