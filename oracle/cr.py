@@ -155,6 +155,8 @@ class HarmonicDiagonalOperator:
         self.keep = (ls >= lmin).astype(np.float64)
         c = np.where(ls >= lmin, cl[ls], 1.0)
         self.C, self.b, self.nl = c, bl[ls], nl
+        self.sinv = self.keep / c
+        self.sinvhalf = self.keep / np.sqrt(c)
 
     def project(self, a):
         out = a * self.keep
@@ -170,6 +172,10 @@ class HarmonicDiagonalOperator:
 
     def apply(self, x):
         return self.project((1.0 / self.C + self.b ** 2 / self.nl) * x)
+
+    def apply_data_term(self, x):
+        """M x with M = B^T N^-1 B = b_l^2 / N_l."""
+        return self.project(self.b ** 2 / self.nl * x)
 
     def diag(self):
         return np.where(self.keep > 0, 1.0 / self.C + self.b ** 2 / self.nl, 1.0)
