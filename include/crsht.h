@@ -145,7 +145,7 @@ typedef struct {
 } cr_stats;
 
 /* Jacobi preconditioner diagonal (the paper's "standard diagonal
- * preconditioner", Sect. 5): D_lm = 1/C_l + b_l^2 sum_r lambda_lm(z_r)^2 W_r,
+ * preconditioner", Sect. 4): D_lm = 1/C_l + b_l^2 sum_r lambda_lm(z_r)^2 W_r,
  * W_r = sum of N^-1 over ring r. diag: device [nalm] float64 (1 where l < lmin).
  * Asynchronous. */
 int cr_precond(const crsht_plan *plan, const cr_problem *prob, double *diag, void *stream);
@@ -216,6 +216,41 @@ typedef struct {
  * `out` is host. Blocks until done. */
 int joint_cl_step(const crsht_plan *plan, const cr_problem *fid, const double *d, cr_chain *state,
                   const cr_draws *draws, const cr_opts *opts, cr_step_out *out, void *stream);
+
+/* Gradient of the synthesis for reverse-mode differentiation of a real
+ * function L of the map: alm_grad = w_m Y^T map_grad with w_0 = 1 (Im of m = 0
+ * set to 0) and w_{m>0} = 2, i.e. dL/dRe a_lm + i dL/dIm a_lm for a complex
+ * leaf that stores the m >= 0 half of a real field (the convention of
+ * torch.autograd for complex tensors). map_grad: device [nrhs][npix];
+ * alm_grad: device [nrhs][nalm]. prec as for sht_synth_adjoint. Asynchronous. */
+int sht_synth_grad(const crsht_plan *plan, int nrhs, const double *map_grad, double *alm_grad, cr_prec prec,
+                   void *stream);
+
+/* Data term of the posterior (Sect. 2.2.1, r = B a + n):
+ *   chi^2(a) = (d - Y B a)^T N^-1 (d - Y B a)
+ * and its gradient in the real-field inner product <a,c> = sum_l a_l0 c_l0 +
+ * 2 sum_{m>0} Re(a_lm c*_lm):  g = -2 B Y^T N^-1 (d - Y B a), on the modes the
+ * problem keeps (l >= lmin; 0 elsewhere), so that d chi^2 = <g, da>.
+ * d: device [nrhs][npix]; a, grad: device [nrhs][nalm]; chi2: host [nrhs] or
+ * NULL. FP64. Blocks until done. */
+int cr_grad_chi2(const crsht_plan *plan, const cr_problem *prob, int nrhs, const double *d, const double *a,
+                 double *grad, double *chi2, void *stream);
+
+/* Derivative of L = ln pi (Sect. 2.2.2, definition of pi(theta)) at the
+ * spectrum of `prob`, with respect to per-bin log-amplitudes theta_k of
+ * C_l -> C_l exp(theta_k) for edges[k] <= l < edges[k+1] (k < nbins), at fixed
+ * w0, w1:
+ *   dL/dtheta_k = 1/2 a^T S^-1_k a + 1/2 lambda^T S^-1/2_k w0 - lambda^T S^-1_k f,
+ * with a the mean field, f the fluctuation and lambda = A^-1 B Y^T N^-1 Y B f
+ * (one adjoint solve); X_k is X restricted to bin k. Three solves with
+ * `opts`; their statistics go to stats[0..2] (host; mean field, fluctuation,
+ * adjoint). d: device map; w0: device alm [nalm] or NULL; w1: device map or
+ * NULL; edges: host, nbins + 1 strictly increasing values in [0, lmax + 1];
+ * grad: host [nbins]; *lnpi (host) receives L. Needs nrhs_max >= 1; uses the
+ * plan workspace. Blocks until done. */
+int cr_grad_lnpi(const crsht_plan *plan, const cr_problem *prob, const double *d, const double *w0,
+                 const double *w1, int nbins, const int *edges, const cr_opts *opts, double *grad,
+                 double *lnpi, cr_stats *stats, void *stream);
 
 /* Per-kernel timing for measurement (not needed for computation).
  * crsht_timing_enable(plan, 1) synchronises the device, clears the counters

@@ -4,7 +4,7 @@ Paper, Sect. 2.2.1: completing the square in the joint posterior gives the
 precision S^-1 + B^T N^-1 B of the sky amplitudes; the mean field
 (eq. mean-field-map), the constrained realization (eq. mapmakingeq) and the
 fluctuation map (eq. fluc-map) all solve systems with that matrix, by
-conjugate gradients (Shewchuk 1994) with a diagonal preconditioner (Sect. 5).
+conjugate gradients (Shewchuk 1994) with a diagonal preconditioner (Sect. 4).
 
 Readings used here:
 * the paper's B (beam + projection to pixels) is Y diag(b_l);

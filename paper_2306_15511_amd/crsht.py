@@ -87,6 +87,11 @@ def _load():
         "cr_lnpi": ([P, ctypes.POINTER(_Problem), d, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp], i),
         "joint_cl_step": ([P, ctypes.POINTER(_Problem), vp, ctypes.POINTER(_Chain), ctypes.POINTER(_Draws),
                            ctypes.POINTER(_Opts), ctypes.POINTER(_StepOut), vp], i),
+        "sht_synth_grad": ([P, i, vp, vp, i, vp], i),
+        "cr_grad_chi2": ([P, ctypes.POINTER(_Problem), i, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp], i),
+        "cr_grad_lnpi": ([P, ctypes.POINTER(_Problem), vp, vp, vp, i, ctypes.POINTER(ctypes.c_int),
+                          ctypes.POINTER(_Opts), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                          ctypes.POINTER(_Stats), vp], i),
         "crsht_timing_enable": ([P, i], i),
         "crsht_timing_read": ([P, i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], i),
     }
@@ -101,7 +106,8 @@ _lib = _load()
 
 EXPORTED = ("crsht_plan_create", "crsht_plan_destroy", "crsht_strerror", "crsht_plan_info", "crsht_pixel_coords",
             "sht_synth", "sht_synth_adjoint", "sht_analysis", "cr_precond", "cr_rhs", "cr_apply", "cr_solve",
-            "cr_lnpi", "joint_cl_step", "crsht_timing_enable", "crsht_timing_read")
+            "cr_lnpi", "joint_cl_step", "sht_synth_grad", "cr_grad_chi2", "cr_grad_lnpi", "crsht_timing_enable",
+            "crsht_timing_read")
 
 
 def lib():
@@ -325,11 +331,72 @@ def joint_step(plan: Plan, fid: Problem, d: torch.Tensor, chain: Chain, xi: floa
     return StepResult(bool(r.accepted), r.lnA, r.q_new, r.lnpi_new, st(r.mean_stats), st(r.fluct_stats))
 
 
+# ---------------------------------------------------------------- gradients
+def synth_grad(plan: Plan, map_grad: torch.Tensor, out: torch.Tensor | None = None, prec: int = CR_F64):
+    """w_m Y^T map_grad (torch.autograd convention for the complex m >= 0 leaf)."""
+    n = _nrhs(map_grad, plan.npix, torch.float64)
+    if out is None:
+        out = torch.empty((n, plan.nalm) if map_grad.dim() > 1 else (plan.nalm,), dtype=torch.complex128,
+                          device=map_grad.device)
+    _check(_lib.sht_synth_grad(plan.handle, n, _ptr(map_grad), _ptr(out), prec, _stream()), "sht_synth_grad")
+    return out
+
+
+class SynthFunction(torch.autograd.Function):
+    """map = Y alm with the synthesis kernel forward and sht_synth_grad backward."""
+
+    @staticmethod
+    def forward(ctx, alm, plan, prec):
+        ctx.plan, ctx.prec = plan, prec
+        return synth(plan, alm.contiguous(), prec=prec)
+
+    @staticmethod
+    def backward(ctx, g):
+        return synth_grad(ctx.plan, g.contiguous(), prec=ctx.prec), None, None
+
+
+def synth_ad(plan: Plan, alm: torch.Tensor, prec: int = CR_F64) -> torch.Tensor:
+    """Differentiable synthesis (torch.autograd)."""
+    return SynthFunction.apply(alm, plan, prec)
+
+
+def grad_chi2(plan: Plan, prob: Problem, d: torch.Tensor, a: torch.Tensor):
+    """(g, chi2) with chi2 = (d - Y B a)^T N^-1 (d - Y B a) per column and g
+    its gradient in the real-field inner product."""
+    n = _nrhs(a, plan.nalm, torch.complex128)
+    g = torch.empty_like(a)
+    c = (ctypes.c_double * n)()
+    p = prob._c()
+    _check(_lib.cr_grad_chi2(plan.handle, ctypes.byref(p), n, _ptr(d), _ptr(a), _ptr(g), c, _stream()),
+           "cr_grad_chi2")
+    return g, [c[k] for k in range(n)]
+
+
+def grad_lnpi(plan: Plan, prob: Problem, d: torch.Tensor, w0, w1, edges, tol: float = 1e-10, maxiter: int = 20000,
+              prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 0, check_every: int = 8):
+    """(dlnpi/dtheta [nbins] numpy, ln pi, [Stats x 3]) for per-bin log-amplitudes
+    of C_l on [edges[k], edges[k+1])."""
+    import numpy as np
+    e = np.ascontiguousarray(edges, dtype=np.int32)
+    nb = e.size - 1
+    g = np.zeros(nb)
+    v = ctypes.c_double()
+    st = (_Stats * 3)()
+    p = prob._c()
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every)
+    _check(_lib.cr_grad_lnpi(plan.handle, ctypes.byref(p), _ptr(d), _ptr(w0), _ptr(w1), nb,
+                             e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(o),
+                             g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(v), st, _stream()),
+           "cr_grad_lnpi")
+    return g, v.value, [Stats(x.status, x.iters, x.refinements, x.rel_resid_true) for x in st]
+
+
 def nalm(lmax: int, mmax: int | None = None) -> int:
     mmax = lmax if mmax is None else mmax
     return (mmax + 1) * (lmax + 1) - (mmax * (mmax + 1)) // 2
 
 
 __all__ = ["Plan", "Problem", "Stats", "Chain", "StepResult", "synth", "adjoint", "analysis", "precond", "rhs",
-           "apply", "solve", "lnpi", "joint_step", "CR_F64", "CR_MIXED", "CrshtError", "strerror", "EXPORTED"]
+           "apply", "solve", "lnpi", "joint_step", "synth_grad", "synth_ad", "SynthFunction", "grad_chi2", "grad_lnpi",
+           "CR_F64", "CR_MIXED", "CrshtError", "strerror", "EXPORTED"]
 _ = math

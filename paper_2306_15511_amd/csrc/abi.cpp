@@ -70,7 +70,7 @@ int set_problem(const crsht_plan* P, const cr_problem* prob, double q, hipStream
 // w.geo and w.alm_b as scratch (x must not live there).
 // out = sinv * x + bk * (Y^T N^-1 Y)(pt); block partials of <x, out> in row 0.
 int operator_core(const crsht_plan* P, int nrhs, const double2* x, const double2* pt, const double* ninv,
-                  double2* out, hipStream_t s, bool mixed = false) {
+                  double2* out, hipStream_t s, bool mixed = false, bool prior = true) {
   if (mixed)
     CR_TRY(launch_legendre_synth_mixed(P, nrhs, pt, nullptr, F2(P->w.eo), s));
   else
@@ -80,7 +80,7 @@ int operator_core(const crsht_plan* P, int nrhs, const double2* x, const double2
     CR_TRY(launch_legendre_adjoint_mixed(P, nrhs, F2(P->w.geo), P->w.alm_b, s));
   else
     CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, P->w.alm_b, false, s));
-  CR_TRY(launch_cg_q(P, nrhs, x, P->w.alm_b, out, s));
+  CR_TRY(launch_cg_q(P, nrhs, x, P->w.alm_b, out, s, prior));
   return CR_OK;
 }
 
@@ -492,6 +492,82 @@ extern "C" int cr_lnpi(const crsht_plan* P, const cr_problem* fid, double q, con
   double t[3];
   CR_CHECK(lnpi_terms(P, fid->ninv, d, C2(ahat), C2(fhat), t, s));
   *lnpi = -0.5 * (t[0] + t[1] + t[2]);
+  return CR_OK;
+}
+
+extern "C" int sht_synth_grad(const crsht_plan* P, int nrhs, const double* map_grad, double* alm_grad,
+                              cr_prec prec, void* stream) {
+  CR_CHECK(check_plan(P, nrhs));
+  if (!map_grad || !alm_grad) return CR_EINVAL;
+  if (prec != CR_F64 && prec != CR_MIXED) return CR_EINVAL;
+  hipStream_t s = S(stream);
+  CR_CHECK(adjoint_f64(P, nrhs, map_grad, C2(alm_grad), s, prec == CR_MIXED));
+  CR_TRY(launch_mweight(P, nrhs, C2(alm_grad), s));
+  return CR_OK;
+}
+
+extern "C" int cr_grad_chi2(const crsht_plan* P, const cr_problem* prob, int nrhs, const double* d, const double* a,
+                            double* grad, double* chi2, void* stream) {
+  CR_CHECK(check_plan(P, nrhs));
+  if (!prob || !d || !a || !grad) return CR_EINVAL;
+  hipStream_t s = S(stream);
+  CR_CHECK(set_problem(P, prob, 1.0, s));
+  const int64_t np = P->g.npix;
+  // model map Y B a (B restricted to the kept modes) and chi^2 per column
+  CR_CHECK(synth_f64(P, nrhs, C2(a), P->w.bk, P->w.map_a, s));
+  if (chi2) {
+    const int npart = P->w.npart;
+    const int nbp = std::min<int64_t>(npart, (np + 255) / 256);
+    for (int c = 0; c < nrhs; ++c) {
+      CR_TRY(launch_pix_wsq(P, prob->ninv, d + c * np, P->w.map_a + c * np, P->w.partial, nbp, s));
+      CR_TRY(launch_sum_rows(P, 1, nbp, s));
+      CR_CHECK(read_scalars(P, 1, s));
+      chi2[c] = P->w.host_scal[S_AUX0];
+    }
+  }
+  // g = -2 B Y^T N^-1 (d - Y B a)
+  CR_TRY(launch_pix_wres(P, nrhs, prob->ninv, d, P->w.map_a, P->w.map_a, s));
+  CR_TRY(launch_ring(P, nrhs, RING_ADJOINT, nullptr, P->w.map_a, nullptr, P->w.geo, false, s));
+  CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, P->w.alm_b, false, s));   // raw sums (no kappa)
+  CR_TRY(launch_scale_alm(P, nrhs, P->w.alm_b, P->w.bk, C2(grad), s));          // b_l kappa_lm on kept modes
+  CR_TRY(launch_alm_axpby((int64_t)nrhs * P->g.nalm, -2.0, C2(grad), 0.0, nullptr, C2(grad), s));
+  CR_TRY(launch_project(P, nrhs, C2(grad), C2(grad), s));
+  CR_TRY(hipStreamSynchronize(s));
+  return CR_OK;
+}
+
+extern "C" int cr_grad_lnpi(const crsht_plan* P, const cr_problem* prob, const double* d, const double* w0,
+                            const double* w1, int nbins, const int* edges, const cr_opts* opts, double* grad,
+                            double* lnpi, cr_stats* stats, void* stream) {
+  CR_CHECK(check_plan(P, 1));
+  if (!prob || !d || !edges || !opts || !grad || !lnpi || !stats) return CR_EINVAL;
+  if (nbins < 1 || nbins > P->g.lmax + 1) return CR_EINVAL;
+  for (int k = 0; k <= nbins; ++k) {
+    if (edges[k] < 0 || edges[k] > P->g.lmax + 1) return CR_EINVAL;
+    if (k > 0 && edges[k] <= edges[k - 1]) return CR_EINVAL;
+  }
+  hipStream_t s = S(stream);
+  Workspace const& w = P->w;
+  const int64_t na = P->g.nalm;
+  // mean field a^ (alm_c) and fluctuation f^ (alm_d)
+  CR_CHECK(solve_core(P, prob, 1.0, 1, d, nullptr, nullptr, nullptr, reinterpret_cast<double*>(w.alm_c), opts,
+                      &stats[0], s));
+  CR_CHECK(solve_core(P, prob, 1.0, 1, nullptr, w0, w1, nullptr, reinterpret_cast<double*>(w.alm_d), opts,
+                      &stats[1], s));
+  // u = M f^ = B Y^T N^-1 Y B f^ (cg_bin), then the adjoint solve lambda = A^-1 u (cg_xacc)
+  CR_TRY(launch_scale_alm(P, 1, w.alm_d, w.bk, w.alm_a, s));
+  CR_CHECK(operator_core(P, 1, w.alm_d, w.alm_a, prob->ninv, w.cg_bin, s, false, false));
+  CR_CHECK(solve_core(P, prob, 1.0, 1, nullptr, nullptr, nullptr, reinterpret_cast<const double*>(w.cg_bin),
+                      reinterpret_cast<double*>(w.cg_xacc), opts, &stats[2], s));
+  // per-bin terms (problem factors sinv, sinvhalf are those of prob)
+  CR_TRY(hipMemcpyAsync(w.bin_edges, edges, (size_t)(nbins + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  CR_TRY(launch_bin_grad(P, nbins, w.bin_edges, w.alm_c, w.alm_d, w.cg_xacc, w0 ? C2(w0) : nullptr, w.bin_grad, s));
+  CR_TRY(hipMemcpyAsync(grad, w.bin_grad, (size_t)nbins * sizeof(double), hipMemcpyDeviceToHost, s));
+  CR_TRY(hipStreamSynchronize(s));
+  double t[3];
+  CR_CHECK(lnpi_terms(P, prob->ninv, d, w.alm_c, w.alm_d, t, s));
+  *lnpi = -0.5 * (t[0] + t[1] + t[2]);
+  (void)na;
   return CR_OK;
 }
 

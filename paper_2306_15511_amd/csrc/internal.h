@@ -99,12 +99,16 @@ struct Workspace {
   double* host_scal = nullptr; // pinned mirror of scal
   double2* cg_xacc = nullptr;  // [nrhs][nalm] refinement: accumulated solution
   double2* cg_bin = nullptr;   // [nrhs][nalm] refinement: right-hand side of the inner solve
+  int* bin_edges = nullptr;    // [lmax+2] multipole bin edges of a gradient call
+  double* bin_part = nullptr;  // [lmax+1][kBinSlices][3] per-bin partial sums
+  double* bin_grad = nullptr;  // [lmax+1] per-bin gradient
   void* mx_ab = nullptr;       // bf16 synthesis operand tiles (one group of kMixedCols columns)
   void* mx_ag = nullptr;       // bf16 adjoint operand tiles
   int npart = 0;
 };
 
 constexpr int kScalSlots = 16;
+constexpr int kBinSlices = 16;   // m slices per multipole bin in the gradient reductions
 constexpr int kMixedCols = 32;   // MFMA N: 16 right-hand sides (re, im) per column group
 // slots of the per-column scalar block
 enum ScalSlot {
@@ -217,9 +221,10 @@ hipError_t launch_pix_rhs(const crsht_plan* P, int nrhs, const double* ninv, con
                           double* u, hipStream_t s);
 hipError_t launch_rhs_finish(const crsht_plan* P, int nrhs, const double2* raw, const double2* w0, double2* out,
                              hipStream_t s);
-// q = sinv * p + bk * raw per column; partial <p, q> per block (row 0)
+// q = sinv * p + bk * raw per column (sinv term omitted when w.sinv is not
+// passed, see operator_core); partial <p, q> per block (row 0)
 hipError_t launch_cg_q(const crsht_plan* P, int nrhs, const double2* p, const double2* raw, double2* q,
-                       hipStream_t s);
+                       hipStream_t s, bool prior = true);
 // D = sinv + bk^2 * raw.x on kept modes, 1 elsewhere
 hipError_t launch_diag(const crsht_plan* P, const double2* raw, double* diag, hipStream_t s);
 hipError_t launch_project(const crsht_plan* P, int nrhs, const double2* x, double2* out, hipStream_t s);
@@ -239,6 +244,16 @@ hipError_t launch_cg_pupdate(const crsht_plan* P, int nrhs, const double2* z, do
 hipError_t launch_residual(const crsht_plan* P, int nrhs, const double2* b, const double2* ax, double2* r,
                            hipStream_t s);
 hipError_t launch_sum_rows(const crsht_plan* P, int nrhs, int nb, hipStream_t s);
+// u = N^-1 (d - m) per column
+hipError_t launch_pix_wres(const crsht_plan* P, int nrhs, const double* ninv, const double* d, const double* m,
+                           double* u, hipStream_t s);
+// a *= w_m (2 for m > 0), Im a_l0 = 0, in place
+hipError_t launch_mweight(const crsht_plan* P, int nrhs, double2* a, hipStream_t s);
+// grad[k] = <a,S^-1_k a>/2 + <lam,S^-1/2_k w0>/2 - <lam,S^-1_k f> for the bins of
+// edges (device, nbins + 1 entries); w0 may be null
+hipError_t launch_bin_grad(const crsht_plan* P, int nbins, const int* edges, const double2* ahat,
+                           const double2* fhat, const double2* lam, const double2* w0, double* grad,
+                           hipStream_t s);
 hipError_t launch_pix_wsq(const crsht_plan* P, const double* w, const double* x, const double* y, double* partial,
                           int nb, hipStream_t s);
 hipError_t launch_alm_wquad(const crsht_plan* P, const double* f, const double2* a, double* partial, int nb,

@@ -338,7 +338,7 @@ __global__ void k_cg_q(int64_t nalm, const int* __restrict__ idx_m, const double
   double pq = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nalm; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t ci = c * nalm + i;
-    const double si = sinv[i], b = bk[i];
+    const double si = sinv ? sinv[i] : 0.0, b = bk[i];
     const double2 pv = p[ci], rv = raw[ci];
     const double2 qv = make_double2(fma(si, pv.x, b * rv.x), fma(si, pv.y, b * rv.y));
     q[ci] = qv;
@@ -434,6 +434,80 @@ int nblocks(int64_t n) {
   return (int)(b < 1 ? 1 : b);
 }
 
+// u = N^-1 (d - m) per column (data residual weighted by the inverse noise)
+__global__ void k_pix_wres(int64_t npix, int nrhs, const double* __restrict__ ninv, const double* __restrict__ d,
+                           const double* m, double* u) {   // u may alias m (element-wise)
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npix) return;
+  const double n = ninv[i];
+  for (int c = 0; c < nrhs; ++c) u[c * npix + i] = n * (d[c * npix + i] - m[c * npix + i]);
+}
+
+// real-field weights of the synthesis gradient: x 2 for m > 0, Im of m = 0 set to 0
+__global__ void k_mweight(int64_t nalm, int nrhs, const int* __restrict__ idx_m, double2* a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nalm) return;
+  const bool m0 = idx_m[i] == 0;
+  for (int c = 0; c < nrhs; ++c) {
+    double2 v = a[c * nalm + i];
+    if (m0) v.y = 0.0;
+    else v = make_double2(2.0 * v.x, 2.0 * v.y);
+    a[c * nalm + i] = v;
+  }
+}
+
+// Per multipole bin k = blockIdx.x (l in [edges[k], edges[k+1])), slice
+// blockIdx.y of the m values: partial sums of
+//   t1 = <a^, S^-1_k a^>,  t2 = <lambda, S^-1/2_k w0>,  t3 = <lambda, S^-1_k f^>
+// in the real-field inner product. The elements of (l, m) for one m are
+// contiguous in l, so each m contributes a coalesced run.
+__global__ void k_bin_terms(int mmax, const int64_t* __restrict__ mstart, const int* __restrict__ edges,
+                            const double* __restrict__ sinv, const double* __restrict__ sinvhalf,
+                            const double2* __restrict__ ahat, const double2* __restrict__ fhat,
+                            const double2* __restrict__ lam, const double2* __restrict__ w0,
+                            double* __restrict__ partial) {
+  __shared__ double sh[kVecBlock];
+  const int k = blockIdx.x, sl = blockIdx.y, S = gridDim.y;
+  const int l0 = edges[k], l1 = edges[k + 1];
+  double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+  const int mtop = min(mmax, l1 - 1);
+  for (int m = sl; m <= mtop; m += S) {
+    const int lo = max(l0, m);
+    const int64_t base = mstart[m] - m;
+    for (int l = lo + threadIdx.x; l < l1; l += blockDim.x) {
+      const int64_t i = base + l;
+      const double2 a = ahat[i], f = fhat[i], L = lam[i];
+      const double si = sinv[i];
+      t1 += si * wdot(m, a, a);
+      t3 += si * wdot(m, L, f);
+      if (w0) t2 += sinvhalf[i] * wdot(m, L, w0[i]);
+    }
+  }
+  t1 = block_sum(t1, sh);
+  t2 = block_sum(t2, sh);
+  t3 = block_sum(t3, sh);
+  if (threadIdx.x == 0) {
+    double* o = partial + ((size_t)k * S + sl) * 3;
+    o[0] = t1;
+    o[1] = t2;
+    o[2] = t3;
+  }
+}
+
+// d ln pi / d theta_k = t1/2 + t2/2 - t3, slices summed in a fixed order
+__global__ void k_bin_grad(int nbins, int S, const double* __restrict__ partial, double* __restrict__ grad) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nbins) return;
+  double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+  for (int sl = 0; sl < S; ++sl) {
+    const double* o = partial + ((size_t)k * S + sl) * 3;
+    t1 += o[0];
+    t2 += o[1];
+    t3 += o[2];
+  }
+  grad[k] = 0.5 * t1 + 0.5 * t2 - t3;
+}
+
 }  // namespace
 
 int vec_reduce_blocks(const crsht_plan* P) {
@@ -508,10 +582,10 @@ hipError_t launch_cg_scalars(const crsht_plan* P, int nrhs, int what, int nb, do
 }
 
 hipError_t launch_cg_q(const crsht_plan* P, int nrhs, const double2* p, const double2* raw, double2* q,
-                       hipStream_t s) {
+                       hipStream_t s, bool prior) {
   const int nb = vec_reduce_blocks(P);
-  hipLaunchKernelGGL(k_cg_q, dim3(nb, nrhs), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_m, P->w.sinv, P->w.bk, p,
-                     raw, q, P->w.partial, P->w.npart);
+  hipLaunchKernelGGL(k_cg_q, dim3(nb, nrhs), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_m,
+                     prior ? P->w.sinv : nullptr, P->w.bk, p, raw, q, P->w.partial, P->w.npart);
   return hipGetLastError();
 }
 
@@ -566,6 +640,28 @@ hipError_t launch_pix_wsq(const crsht_plan* P, const double* w, const double* x,
 hipError_t launch_alm_wquad(const crsht_plan* P, const double* f, const double2* a, double* partial, int nb,
                             hipStream_t s) {
   hipLaunchKernelGGL(k_alm_wquad, dim3(nb), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_m, f, a, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_pix_wres(const crsht_plan* P, int nrhs, const double* ninv, const double* d, const double* m,
+                           double* u, hipStream_t s) {
+  hipLaunchKernelGGL(k_pix_wres, dim3(nblocks(P->g.npix)), dim3(kVecBlock), 0, s, P->g.npix, nrhs, ninv, d, m, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_mweight(const crsht_plan* P, int nrhs, double2* a, hipStream_t s) {
+  hipLaunchKernelGGL(k_mweight, dim3(nblocks(P->g.nalm)), dim3(kVecBlock), 0, s, P->g.nalm, nrhs, P->t.idx_m, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_grad(const crsht_plan* P, int nbins, const int* edges, const double2* ahat,
+                           const double2* fhat, const double2* lam, const double2* w0, double* grad,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_bin_terms, dim3(nbins, kBinSlices), dim3(kVecBlock), 0, s, P->g.mmax, P->t.mstart, edges,
+                     P->w.sinv, P->w.sinvhalf, ahat, fhat, lam, w0, P->w.bin_part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bin_grad, dim3((nbins + 63) / 64), dim3(64), 0, s, nbins, kBinSlices, P->w.bin_part, grad);
   return hipGetLastError();
 }
 
