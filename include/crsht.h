@@ -173,6 +173,19 @@ int cr_solve(const crsht_plan *plan, const cr_problem *prob, int nrhs, const dou
              const double *w1, const double *rhs, double *s_out, const cr_opts *opts, cr_stats *stats,
              void *stream);
 
+/* Many independent problems at once (each with its own plan, so Nside, lmax
+ * and the noise model may all differ): problem i solves eq. mapmakingeq for
+ * one column with plans[i], probs[i], d[i], w0[i], w1[i] (device; any of the
+ * three arrays of pointers, or an entry, may be NULL = term omitted) into
+ * s_out[i] (device [nalm_i]); stats: host [nprob]. The plans must be
+ * distinct (each solve uses its plan's workspace). The library drives the
+ * problems concurrently, largest first, each on a stream of its own, after
+ * waiting for `stream`; all share `opts`. Returns the first error of any
+ * problem (the others are still solved). Blocks until all are done. */
+int cr_solve_batched(const crsht_plan *const *plans, const cr_problem *probs, int nprob, const double *const *d,
+                     const double *const *w0, const double *const *w1, double *const *s_out, const cr_opts *opts,
+                     cr_stats *stats, void *stream);
+
 /* ln pi of the joint move (Sect. 2.2.2, definition of pi(theta)) for the
  * amplitude-scaled spectrum C_l(q) = q cl:
  *   ln pi = -1/2 (d - Y B a)^T N^-1 (d - Y B a) - 1/2 a^T S(q)^-1 a - 1/2 f^T B Y^T N^-1 Y B f

@@ -87,6 +87,10 @@ def _load():
         "cr_lnpi": ([P, ctypes.POINTER(_Problem), d, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp], i),
         "joint_cl_step": ([P, ctypes.POINTER(_Problem), vp, ctypes.POINTER(_Chain), ctypes.POINTER(_Draws),
                            ctypes.POINTER(_Opts), ctypes.POINTER(_StepOut), vp], i),
+        "cr_solve_batched": ([ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(_Problem), i,
+                              ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                              ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                              ctypes.POINTER(_Opts), ctypes.POINTER(_Stats), vp], i),
         "sht_synth_grad": ([P, i, vp, vp, i, vp], i),
         "cr_grad_chi2": ([P, ctypes.POINTER(_Problem), i, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp], i),
         "cr_grad_lnpi": ([P, ctypes.POINTER(_Problem), vp, vp, vp, i, ctypes.POINTER(ctypes.c_int),
@@ -106,7 +110,7 @@ _lib = _load()
 
 EXPORTED = ("crsht_plan_create", "crsht_plan_destroy", "crsht_strerror", "crsht_plan_info", "crsht_pixel_coords",
             "sht_synth", "sht_synth_adjoint", "sht_analysis", "cr_precond", "cr_rhs", "cr_apply", "cr_solve",
-            "cr_lnpi", "joint_cl_step", "sht_synth_grad", "cr_grad_chi2", "cr_grad_lnpi", "crsht_timing_enable",
+            "cr_lnpi", "joint_cl_step", "cr_solve_batched", "sht_synth_grad", "cr_grad_chi2", "cr_grad_lnpi", "crsht_timing_enable",
             "crsht_timing_read")
 
 
@@ -287,6 +291,32 @@ def solve(plan: Plan, prob: Problem, d=None, w0=None, w1=None, rhs_vec=None, nrh
     return out, [Stats(s.status, s.iters, s.refinements, s.rel_resid_true) for s in st]
 
 
+def solve_batched(plans, probs, d=None, w0=None, w1=None, tol: float = 1e-6, maxiter: int = 20000,
+                  prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 0, check_every: int = 16,
+                  out=None):
+    """Independent single-column problems (own plan each). d, w0, w1: lists of
+    tensors (or None). Returns (list of s [nalm] complex128, [Stats])."""
+    n = len(plans)
+    if len(probs) != n:
+        raise ValueError("one problem per plan")
+    if out is None:
+        out = [torch.empty(pl.nalm, dtype=torch.complex128, device=pr.ninv.device) for pl, pr in zip(plans, probs)]
+    VP = ctypes.c_void_p * n
+
+    def arr(ts):
+        if ts is None:
+            return None
+        return VP(*[(_ptr(t).value if t is not None else None) for t in ts])
+
+    hp = VP(*[pl.handle.value for pl in plans])
+    pa = (_Problem * n)(*[pr._c() for pr in probs])
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every)
+    st = (_Stats * n)()
+    _check(_lib.cr_solve_batched(hp, pa, n, arr(d), arr(w0), arr(w1), VP(*[_ptr(t).value for t in out]),
+                                 ctypes.byref(o), st, _stream()), "cr_solve_batched")
+    return out, [Stats(x.status, x.iters, x.refinements, x.rel_resid_true) for x in st]
+
+
 def lnpi(plan: Plan, fid: Problem, q: float, d: torch.Tensor, ahat: torch.Tensor, fhat: torch.Tensor) -> float:
     p = fid._c()
     v = ctypes.c_double()
@@ -397,6 +427,6 @@ def nalm(lmax: int, mmax: int | None = None) -> int:
 
 
 __all__ = ["Plan", "Problem", "Stats", "Chain", "StepResult", "synth", "adjoint", "analysis", "precond", "rhs",
-           "apply", "solve", "lnpi", "joint_step", "synth_grad", "synth_ad", "SynthFunction", "grad_chi2", "grad_lnpi",
+           "apply", "solve", "solve_batched", "lnpi", "joint_step", "synth_grad", "synth_ad", "SynthFunction", "grad_chi2", "grad_lnpi",
            "CR_F64", "CR_MIXED", "CrshtError", "strerror", "EXPORTED"]
 _ = math

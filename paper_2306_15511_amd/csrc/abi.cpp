@@ -5,8 +5,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <numeric>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -28,6 +31,8 @@ namespace {
   } while (0)
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+constexpr int kBatchWorkers = 16;   // host threads driving problems of one batched solve
 
 const double2* C2(const double* p) { return reinterpret_cast<const double2*>(p); }
 double2* C2(double* p) { return reinterpret_cast<double2*>(p); }
@@ -481,6 +486,56 @@ extern "C" int cr_solve(const crsht_plan* P, const cr_problem* prob, int nrhs, c
                         void* stream) {
   CR_CHECK(check_plan(P, nrhs));
   return solve_core(P, prob, 1.0, nrhs, d, w0, w1, rhs, s_out, opts, stats, S(stream));
+}
+
+extern "C" int cr_solve_batched(const crsht_plan* const* plans, const cr_problem* probs, int nprob,
+                                const double* const* d, const double* const* w0, const double* const* w1,
+                                double* const* s_out, const cr_opts* opts, cr_stats* stats, void* stream) {
+  if (!plans || !probs || nprob < 1 || !s_out || !opts || !stats) return CR_EINVAL;
+  for (int i = 0; i < nprob; ++i) {
+    CR_CHECK(check_plan(plans[i], 1));
+    if (!s_out[i]) return CR_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return CR_EINVAL;   // each problem needs its own workspace
+  }
+  // the caller's stream has produced the inputs
+  CR_TRY(hipStreamSynchronize(S(stream)));
+  std::vector<hipStream_t> st(nprob, nullptr);
+  int rc = CR_OK;
+  for (int i = 0; i < nprob && rc == CR_OK; ++i) {
+    if (hipSetDevice(plans[i]->device) != hipSuccess || hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking) != hipSuccess)
+      rc = CR_EDEVICE;
+  }
+  if (rc == CR_OK) {
+    // largest problems first; a pool of host workers, each driving one
+    // problem's PCG on that problem's stream, keeps several solves in flight
+    std::vector<int> order(nprob);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return plans[a]->g.npix * (int64_t)plans[a]->g.lmax >
+                                                plans[b]->g.npix * (int64_t)plans[b]->g.lmax; });
+    std::vector<int> res(nprob, CR_OK);
+    std::atomic<int> next{0};
+    auto worker = [&]() {
+      for (int k; (k = next.fetch_add(1)) < nprob;) {
+        const int i = order[k];
+        if (hipSetDevice(plans[i]->device) != hipSuccess) {
+          res[i] = CR_EDEVICE;
+          continue;
+        }
+        res[i] = solve_core(plans[i], &probs[i], 1.0, 1, d ? d[i] : nullptr, w0 ? w0[i] : nullptr,
+                            w1 ? w1[i] : nullptr, nullptr, s_out[i], opts, &stats[i], st[i]);
+      }
+    };
+    const int nw = std::min(nprob, kBatchWorkers);
+    std::vector<std::thread> pool;
+    for (int k = 0; k < nw; ++k) pool.emplace_back(worker);
+    for (auto& t : pool) t.join();
+    for (int i = 0; i < nprob && rc == CR_OK; ++i) rc = res[i];
+  }
+  for (hipStream_t x : st)
+    if (x) (void)hipStreamDestroy(x);
+  return rc;
 }
 
 extern "C" int cr_lnpi(const crsht_plan* P, const cr_problem* fid, double q, const double* d, const double* ahat,
