@@ -40,7 +40,11 @@ HBM_PEAK_GBS = 8000.0
 # runs of `paper_2306_15511_amd/kernel_probe.py operator --nrhs 16 --prec mixed`
 # at Nside 512, scaled by the same counters on a 1 GiB copy (FETCH x 2.0,
 # WRITE x 1.0); valid only while the kernel's source file hashes to `src`.
-TRAFFIC = {}
+TRAFFIC = {
+    "k_adj_mfma": {"bytes": 959889818, "src": "4bb2b2ec354d97cb"},
+    "k_synth_mfma": {"bytes": 1321213952, "src": "4bb2b2ec354d97cb"},
+    "k_ring<RING_FUSED>": {"bytes": 851707494, "src": "b9fa70a40ebe481a"},   # one fused pass (4 class launches)
+}
 
 
 def legendre_triples(nside: int, lmax: int, mmax: int) -> int:
