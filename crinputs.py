@@ -75,6 +75,15 @@ def cl_powerlaw(lmax: int, amp: float, lmin: int = 2) -> np.ndarray:
     return cl
 
 
+def cl_tqu(lmax: int, amp: float, te_corr: float = 0.3, lmin: int = 2) -> np.ndarray:
+    """[4][lmax+1] spectra TT, EE, BB, TE of the polarised workload:
+    C^TT = A/(l(l+1)), C^EE = 0.05 C^TT, C^BB = 0.005 C^TT,
+    C^TE = te_corr sqrt(C^TT C^EE) (zero below lmin)."""
+    tt = cl_powerlaw(lmax, amp, lmin)
+    ee, bb = 0.05 * tt, 0.005 * tt
+    return np.stack([tt, ee, bb, te_corr * np.sqrt(tt * ee)])
+
+
 def gaussian_beam(lmax: int, fwhm_rad: float) -> np.ndarray:
     """b_l = exp(-l(l+1) sigma_b^2 / 2), sigma_b = FWHM / sqrt(8 ln 2); no pixel window."""
     sig = fwhm_rad / math.sqrt(8.0 * math.log(2.0))

@@ -24,6 +24,10 @@ App. A):
 * ``joint``    - the joint (C_l amplitude, sky) Metropolis move and ln pi.
 * ``grad``     - gradients of chi^2 with respect to a_lm and of ln pi with
   respect to binned C_l (adjoint CG).
+* ``spin2``    - spin-2 functions W, X (+-2Y = (W +- X) e^{i m phi}) and the
+  polarised synthesis (a_E, a_B) -> (Q, U) with its transpose.
+* ``cr_tqu``   - the T+Q+U constrained-realization operator with 3x3 spectra
+  blocks and per-component N^-1.
 
 All arithmetic is float64 / complex128.
 """
