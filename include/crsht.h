@@ -26,6 +26,14 @@
  *     It is the adjoint of Y under <a,c> = sum_l a_l0 c_l0 + 2 sum_{m>0} Re(a_lm c*_lm).
  *   - Maps: float64 [nrhs][npix], HEALPix RING order (Gorski et al. 2005).
  *   - Column c of a batched call is array slice c; columns are independent.
+ *   - Plans with ncomp = 3 (temperature and polarisation, the T, E, B spectra
+ *     and the 3x3 covariance blocks of Sect. 2.2.2): a column holds three
+ *     coefficient blocks (a_T, a_E, a_B), alm [nrhs][3][nalm], and three maps
+ *     (T, Q, U), map [nrhs][3][npix]; everything documented below as [nalm]
+ *     or [npix] per column is [3][nalm] or [3][npix] for such plans. Q and U
+ *     follow the HEALPix / COSMO convention: Q +- iU = sum (+-2 a_lm)(+-2 Y_lm)
+ *     with +-2 a_lm = -(a_E +- i a_B) and +-2 Y_lm the spin-raised scalar
+ *     harmonics (Goldberg et al. 1967) divided by sqrt((l-1) l (l+1) (l+2)).
  *
  * Memory and streams
  *   - Pointers documented as "device" are caller-owned device memory on the
@@ -75,12 +83,12 @@ typedef enum { CR_F64 = 0, CR_MIXED = 1 } cr_prec;
 
 /* Create a plan for HEALPix resolution nside (power of two not required,
  * 1 <= nside <= 1024; larger nside returns CR_ENOTSUP), band limit lmax >= 0 and mmax (<= lmax; pass -1 for
- * mmax = lmax), ncomp = 1 (temperature), for up to nrhs_max >= 1 columns per
- * call. Builds the ring table (Gorski et al. 2005), the recurrence tables of
- * lambda_lm (paper App. A normalisation) and the per-ring FFT tables, and
- * allocates the workspace on the current HIP device.
- * Returns CR_EINVAL, CR_ENOTSUP (ncomp != 1) or CR_ENOMEM on failure
- * (*out set to NULL). */
+ * mmax = lmax), ncomp = 1 (temperature) or 3 (temperature and polarisation),
+ * for up to nrhs_max >= 1 columns per call. Builds the ring table (Gorski et
+ * al. 2005), the recurrence tables of lambda_lm (paper App. A normalisation)
+ * and the per-ring FFT tables, and allocates the workspace on the current HIP
+ * device (a ncomp = 3 plan holds 9 Legendre-sum columns per right-hand side).
+ * Returns CR_EINVAL, CR_ENOTSUP or CR_ENOMEM on failure (*out set to NULL). */
 int crsht_plan_create(int nside, int lmax, int mmax, int ncomp, int nrhs_max, crsht_plan **out);
 
 /* Free a plan and everything it owns. NULL is allowed. */
@@ -120,10 +128,15 @@ int sht_analysis(const crsht_plan *plan, int nrhs, const double *map, double *al
 /* The statement of the problem (paper Sect. 2.2.1, r = B a + n; App. A N^-1). */
 typedef struct {
   const double *cl;    /* host, [lmax+1]: C_l (temperature). Modes with l < lmin are fixed to 0;
-                          C_l must be > 0 and finite for lmin <= l <= lmax. */
-  const double *bl;    /* host, [lmax+1]: beam transfer function b_l (finite). */
-  const double *ninv;  /* device, [npix]: inverse noise variance per pixel, >= 0, 0 = masked. */
-  int lmin;            /* first constrained multipole, 0 <= lmin <= lmax (2 for C_0 = C_1 = 0). */
+                          C_l must be > 0 and finite for lmin <= l <= lmax.
+                          ncomp = 3: [4][lmax+1] = TT, EE, BB, TE; per l >= lmin the block
+                          [[TT, TE], [TE, EE]] must be positive definite and BB > 0 (TB = EB = 0).
+                          S^-1/2 is the symmetric principal root of the block inverse. */
+  const double *bl;    /* host, [lmax+1]: beam transfer function b_l (finite), all components. */
+  const double *ninv;  /* device, [npix]: inverse noise variance per pixel, >= 0, 0 = masked.
+                          ncomp = 3: [3][npix] for T, Q, U (no Q-U noise correlation). */
+  int lmin;            /* first constrained multipole, 0 <= lmin <= lmax (2 for C_0 = C_1 = 0);
+                          ncomp = 3 requires lmin >= 2. */
 } cr_problem;
 
 typedef struct {
@@ -147,7 +160,10 @@ typedef struct {
 /* Jacobi preconditioner diagonal (the paper's "standard diagonal
  * preconditioner", Sect. 4): D_lm = 1/C_l + b_l^2 sum_r lambda_lm(z_r)^2 W_r,
  * W_r = sum of N^-1 over ring r. diag: device [nalm] float64 (1 where l < lmin).
- * Asynchronous. */
+ * ncomp = 3: diag [3][nalm] with the diagonal entries of the S^-1 blocks, W_r
+ * of N_T^-1 for T and the mean of the Q and U ring sums for E and B (the
+ * spin-0 lambda_lm stand in for the spin-2 functions: an approximation that
+ * only needs to stay positive). Asynchronous. */
 int cr_precond(const crsht_plan *plan, const cr_problem *prob, double *diag, void *stream);
 
 /* Right-hand side of eq. mapmakingeq: b = B Y^T N^-1 d + S^-1/2 w0 + B Y^T N^-1/2 w1,
@@ -190,7 +206,7 @@ int cr_solve_batched(const crsht_plan *const *plans, const cr_problem *probs, in
  * amplitude-scaled spectrum C_l(q) = q cl:
  *   ln pi = -1/2 (d - Y B a)^T N^-1 (d - Y B a) - 1/2 a^T S(q)^-1 a - 1/2 f^T B Y^T N^-1 Y B f
  * d: device map; ahat, fhat: device alm [nalm]. Result to *lnpi (host).
- * Blocks until done. */
+ * Temperature plans only (CR_ENOTSUP for ncomp = 3). Blocks until done. */
 int cr_lnpi(const crsht_plan *plan, const cr_problem *fid, double q, const double *d, const double *ahat,
             const double *fhat, double *lnpi, void *stream);
 
@@ -220,7 +236,8 @@ typedef struct {
   cr_stats fluct_stats;/* fluctuation solve (zeros if rejected) */
 } cr_step_out;
 
-/* One joint C_l-amplitude / sky move (paper Sect. 2.2.2, algorithm steps 2-4):
+/* One joint C_l-amplitude / sky move (paper Sect. 2.2.2, algorithm steps 2-4),
+ * temperature plans (ncomp = 1; CR_ENOTSUP otherwise):
  * propose q' = q exp(sigma xi); solve the mean field at q'; rescale the
  * fluctuation by sqrt(q'/q); ln A = ln pi(q') - ln pi(q) + ln(q'/q) (uniform
  * prior in q; Gaussian proposal in ln q); accept iff ln u < ln A, and only then
@@ -245,7 +262,7 @@ int sht_synth_grad(const crsht_plan *plan, int nrhs, const double *map_grad, dou
  * 2 sum_{m>0} Re(a_lm c*_lm):  g = -2 B Y^T N^-1 (d - Y B a), on the modes the
  * problem keeps (l >= lmin; 0 elsewhere), so that d chi^2 = <g, da>.
  * d: device [nrhs][npix]; a, grad: device [nrhs][nalm]; chi2: host [nrhs] or
- * NULL. FP64. Blocks until done. */
+ * NULL (ncomp = 3: the sum over T, Q, U). FP64. Blocks until done. */
 int cr_grad_chi2(const crsht_plan *plan, const cr_problem *prob, int nrhs, const double *d, const double *a,
                  double *grad, double *chi2, void *stream);
 
@@ -260,7 +277,8 @@ int cr_grad_chi2(const crsht_plan *plan, const cr_problem *prob, int nrhs, const
  * adjoint). d: device map; w0: device alm [nalm] or NULL; w1: device map or
  * NULL; edges: host, nbins + 1 strictly increasing values in [0, lmax + 1];
  * grad: host [nbins]; *lnpi (host) receives L. Needs nrhs_max >= 1; uses the
- * plan workspace. Blocks until done. */
+ * plan workspace. Temperature plans only (CR_ENOTSUP for ncomp = 3). Blocks
+ * until done. */
 int cr_grad_lnpi(const crsht_plan *plan, const cr_problem *prob, const double *d, const double *w0,
                  const double *w1, int nbins, const int *edges, const cr_opts *opts, double *grad,
                  double *lnpi, cr_stats *stats, void *stream);

@@ -3,7 +3,8 @@
 Device memory and streams come from PyTorch (ROCm); every computation runs in
 the library's HIP kernels. a_lm tensors are complex128 of shape [nalm] or
 [nrhs, nalm] (m-major, m >= 0); maps are float64 [npix] or [nrhs, npix] in
-HEALPix RING order. The library must be built (``python -m
+HEALPix RING order. Plans with ncomp = 3 (T, E, B / T, Q, U) take a_lm of
+shape [3, nalm] or [nrhs, 3, nalm] and maps [3, npix] or [nrhs, 3, npix]. The library must be built (``python -m
 paper_2306_15511_amd.build``); importing this module without it raises.
 """
 from __future__ import annotations
@@ -162,6 +163,12 @@ class Plan:
         self.nside, self.lmax, self.mmax = info.nside, info.lmax, info.mmax
         self.nrhs_max, self.nrings = info.nrhs_max, info.nrings
         self.npix, self.nalm = int(info.npix), int(info.nalm)
+        self.ncomp = int(info.ncomp)
+        self.vlen = self.ncomp * self.nalm      # coefficients per column
+        self.mlen = self.ncomp * self.npix      # map values per column
+
+    def alm_shape(self, nrhs: int):
+        return (nrhs, self.nalm) if self.ncomp == 1 else (nrhs, self.ncomp, self.nalm)
         self.workspace_bytes = int(info.workspace_bytes)
 
     @property
@@ -206,25 +213,25 @@ def timing_read(plan: Plan, kernel: int):
 
 # ---------------------------------------------------------------- transforms
 def synth(plan: Plan, alm: torch.Tensor, out: torch.Tensor | None = None, prec: int = CR_F64) -> torch.Tensor:
-    n = _nrhs(alm, plan.nalm, torch.complex128)
+    n = _nrhs(alm, plan.vlen, torch.complex128)
     if out is None:
-        out = torch.empty((n, plan.npix) if alm.dim() > 1 else (plan.npix,), dtype=torch.float64, device=alm.device)
+        out = torch.empty(tuple(alm.shape[:-1]) + (plan.npix,), dtype=torch.float64, device=alm.device)
     _check(_lib.sht_synth(plan.handle, n, _ptr(alm), _ptr(out), prec, _stream()), "sht_synth")
     return out
 
 
 def adjoint(plan: Plan, m: torch.Tensor, out: torch.Tensor | None = None, prec: int = CR_F64) -> torch.Tensor:
-    n = _nrhs(m, plan.npix, torch.float64)
+    n = _nrhs(m, plan.mlen, torch.float64)
     if out is None:
-        out = torch.empty((n, plan.nalm) if m.dim() > 1 else (plan.nalm,), dtype=torch.complex128, device=m.device)
+        out = torch.empty(tuple(m.shape[:-1]) + (plan.nalm,), dtype=torch.complex128, device=m.device)
     _check(_lib.sht_synth_adjoint(plan.handle, n, _ptr(m), _ptr(out), prec, _stream()), "sht_synth_adjoint")
     return out
 
 
 def analysis(plan: Plan, m: torch.Tensor, n_iter: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
-    n = _nrhs(m, plan.npix, torch.float64)
+    n = _nrhs(m, plan.mlen, torch.float64)
     if out is None:
-        out = torch.empty((n, plan.nalm) if m.dim() > 1 else (plan.nalm,), dtype=torch.complex128, device=m.device)
+        out = torch.empty(tuple(m.shape[:-1]) + (plan.nalm,), dtype=torch.complex128, device=m.device)
     _check(_lib.sht_analysis(plan.handle, n, _ptr(m), _ptr(out), n_iter, _stream()), "sht_analysis")
     return out
 
@@ -232,7 +239,9 @@ def analysis(plan: Plan, m: torch.Tensor, n_iter: int = 0, out: torch.Tensor | N
 # ---------------------------------------------------------------- CR system
 @dataclass
 class Problem:
-    """cl, bl: host float64 arrays of lmax+1; ninv: device float64 [npix]."""
+    """cl, bl: host float64 arrays of lmax+1; ninv: device float64 [npix].
+    Plans with ncomp = 3: cl [4, lmax+1] (TT, EE, BB, TE), ninv [3, npix]
+    (T, Q, U), lmin >= 2."""
     cl: object
     bl: object
     ninv: torch.Tensor
@@ -255,14 +264,14 @@ class Stats:
 
 
 def precond(plan: Plan, prob: Problem) -> torch.Tensor:
-    out = torch.empty(plan.nalm, dtype=torch.float64, device=prob.ninv.device)
+    out = torch.empty(plan.alm_shape(1)[1:], dtype=torch.float64, device=prob.ninv.device)
     p = prob._c()
     _check(_lib.cr_precond(plan.handle, ctypes.byref(p), _ptr(out), _stream()), "cr_precond")
     return out
 
 
 def rhs(plan: Plan, prob: Problem, d=None, w0=None, w1=None, nrhs: int = 1) -> torch.Tensor:
-    out = torch.empty((nrhs, plan.nalm), dtype=torch.complex128, device=prob.ninv.device)
+    out = torch.empty(plan.alm_shape(nrhs), dtype=torch.complex128, device=prob.ninv.device)
     p = prob._c()
     _check(_lib.cr_rhs(plan.handle, ctypes.byref(p), nrhs, _ptr(d), _ptr(w0), _ptr(w1), _ptr(out), _stream()),
            "cr_rhs")
@@ -270,7 +279,7 @@ def rhs(plan: Plan, prob: Problem, d=None, w0=None, w1=None, nrhs: int = 1) -> t
 
 
 def apply(plan: Plan, prob: Problem, x: torch.Tensor, prec: int = CR_F64) -> torch.Tensor:
-    n = _nrhs(x, plan.nalm, torch.complex128)
+    n = _nrhs(x, plan.vlen, torch.complex128)
     out = torch.empty_like(x)
     p = prob._c()
     _check(_lib.cr_apply(plan.handle, ctypes.byref(p), n, _ptr(x), _ptr(out), prec, _stream()), "cr_apply")
@@ -280,9 +289,9 @@ def apply(plan: Plan, prob: Problem, x: torch.Tensor, prec: int = CR_F64) -> tor
 def solve(plan: Plan, prob: Problem, d=None, w0=None, w1=None, rhs_vec=None, nrhs: int = 1, tol: float = 1e-6,
           maxiter: int = 10000, prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 50,
           check_every: int = 8, out: torch.Tensor | None = None):
-    """Returns (s [nrhs, nalm] complex128, [Stats])."""
+    """Returns (s [nrhs, nalm] complex128 ([nrhs, 3, nalm] for ncomp = 3), [Stats])."""
     if out is None:
-        out = torch.empty((nrhs, plan.nalm), dtype=torch.complex128, device=prob.ninv.device)
+        out = torch.empty(plan.alm_shape(nrhs), dtype=torch.complex128, device=prob.ninv.device)
     p = prob._c()
     o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every)
     st = (_Stats * nrhs)()
@@ -300,7 +309,8 @@ def solve_batched(plans, probs, d=None, w0=None, w1=None, tol: float = 1e-6, max
     if len(probs) != n:
         raise ValueError("one problem per plan")
     if out is None:
-        out = [torch.empty(pl.nalm, dtype=torch.complex128, device=pr.ninv.device) for pl, pr in zip(plans, probs)]
+        out = [torch.empty(pl.alm_shape(1)[1:], dtype=torch.complex128, device=pr.ninv.device)
+               for pl, pr in zip(plans, probs)]
     VP = ctypes.c_void_p * n
 
     def arr(ts):
@@ -364,10 +374,9 @@ def joint_step(plan: Plan, fid: Problem, d: torch.Tensor, chain: Chain, xi: floa
 # ---------------------------------------------------------------- gradients
 def synth_grad(plan: Plan, map_grad: torch.Tensor, out: torch.Tensor | None = None, prec: int = CR_F64):
     """w_m Y^T map_grad (torch.autograd convention for the complex m >= 0 leaf)."""
-    n = _nrhs(map_grad, plan.npix, torch.float64)
+    n = _nrhs(map_grad, plan.mlen, torch.float64)
     if out is None:
-        out = torch.empty((n, plan.nalm) if map_grad.dim() > 1 else (plan.nalm,), dtype=torch.complex128,
-                          device=map_grad.device)
+        out = torch.empty(tuple(map_grad.shape[:-1]) + (plan.nalm,), dtype=torch.complex128, device=map_grad.device)
     _check(_lib.sht_synth_grad(plan.handle, n, _ptr(map_grad), _ptr(out), prec, _stream()), "sht_synth_grad")
     return out
 
@@ -393,7 +402,7 @@ def synth_ad(plan: Plan, alm: torch.Tensor, prec: int = CR_F64) -> torch.Tensor:
 def grad_chi2(plan: Plan, prob: Problem, d: torch.Tensor, a: torch.Tensor):
     """(g, chi2) with chi2 = (d - Y B a)^T N^-1 (d - Y B a) per column and g
     its gradient in the real-field inner product."""
-    n = _nrhs(a, plan.nalm, torch.complex128)
+    n = _nrhs(a, plan.vlen, torch.complex128)
     g = torch.empty_like(a)
     c = (ctypes.c_double * n)()
     p = prob._c()

@@ -47,9 +47,54 @@ int check_plan(const crsht_plan* P, int nrhs) {
   return CR_OK;
 }
 
+// ---- T+Q+U problem set-up: per-l 3x3 blocks of S^-1 and S^-1/2 (TT, TE and
+// EE coupled, BB apart, TB = EB = 0) for amplitude q. For the symmetric
+// positive definite 2x2 block M = [[a, b], [b, c]] of S^-1 the principal
+// square root is (M + sqrt(det M) I) / sqrt(tr M + 2 sqrt(det M)).
+int set_problem_tqu(const crsht_plan* P, const cr_problem* prob, double q, hipStream_t s) {
+  const int lmax = P->g.lmax;
+  if (prob->lmin < 2 || prob->lmin > lmax) return CR_EINVAL;   // E and B start at l = 2
+  const double* tt = prob->cl;
+  const double* ee = prob->cl + (lmax + 1);
+  const double* bb = prob->cl + 2 * (lmax + 1);
+  const double* te = prob->cl + 3 * (lmax + 1);
+  std::vector<double> perl(4 * (size_t)(lmax + 1), 0.0), blk(8 * (size_t)(lmax + 1), 0.0);
+  for (int l = 0; l <= lmax; ++l) {
+    const double b = prob->bl[l];
+    if (!std::isfinite(b)) return CR_EINVAL;
+    perl[2 * (lmax + 1) + l] = b;
+    if (l < prob->lmin) continue;
+    const double ctt = q * tt[l], cee = q * ee[l], cbb = q * bb[l], cte = q * te[l];
+    const double det = ctt * cee - cte * cte;
+    if (!(ctt > 0.0) || !(cee > 0.0) || !(cbb > 0.0) || !(det > 0.0) || !std::isfinite(det) ||
+        !std::isfinite(cbb))
+      return CR_EINVAL;
+    const double a = cee / det, bo = -cte / det, c = ctt / det;   // S^-1 of the (T, E) block
+    const double sd = std::sqrt(a * c - bo * bo);
+    const double nrm = 1.0 / std::sqrt(a + c + 2.0 * sd);
+    double* o = &blk[8 * (size_t)l];
+    o[0] = a;
+    o[1] = bo;
+    o[2] = c;
+    o[3] = 1.0 / cbb;
+    o[4] = (a + sd) * nrm;
+    o[5] = bo * nrm;
+    o[6] = (c + sd) * nrm;
+    o[7] = 1.0 / std::sqrt(cbb);
+    perl[3 * (lmax + 1) + l] = 1.0;
+  }
+  CR_TRY(hipMemcpyAsync(P->w.perl, perl.data(), perl.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  CR_TRY(hipMemcpyAsync(P->w.sblk, blk.data(), blk.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  CR_TRY(launch_expand_tqu(P, P->w.perl, s));
+  CR_TRY(hipStreamSynchronize(s));  // host vectors must outlive the copies
+  return CR_OK;
+}
+
 // ---- problem set-up: per-l factors for amplitude q (C_l -> q C_l)
 int set_problem(const crsht_plan* P, const cr_problem* prob, double q, hipStream_t s) {
   if (!prob || !prob->cl || !prob->bl || !prob->ninv) return CR_EINVAL;
+  if (!(q > 0.0) || !std::isfinite(q)) return CR_EINVAL;
+  if (P->ncomp == 3) return set_problem_tqu(P, prob, q, s);
   const int lmax = P->g.lmax;
   if (prob->lmin < 0 || prob->lmin > lmax) return CR_EINVAL;
   if (!(q > 0.0) || !std::isfinite(q)) return CR_EINVAL;
@@ -71,11 +116,61 @@ int set_problem(const crsht_plan* P, const cr_problem* prob, double q, hipStream
   return CR_OK;
 }
 
+// column layout of the ring pass of a T+Q+U plan (maps [nrhs][3][npix])
+RingCols tqu_cols(const crsht_plan* P) {
+  RingCols c;
+  c.group = 3;
+  c.eo_cols = 9;
+  c.geo_cols = 7;
+  c.ninv_stride = P->g.npix;
+  return c;
+}
+
+// Legendre sums and Q, U spectra of f * (a_T, a_E, a_B) (f per coefficient,
+// null = 1) into w.eo; scratch w.alm_a
+int tqu_spectra(const crsht_plan* P, int nrhs, const double2* alm, const double* f, hipStream_t s, bool mixed) {
+  Workspace const& w = P->w;
+  CR_TRY(launch_pol_prep_synth(P, nrhs, alm, f, w.alm_a, s));
+  if (mixed)
+    CR_TRY(launch_legendre_synth_mixed(P, 9 * nrhs, w.alm_a, nullptr, F2(w.eo), s));
+  else
+    CR_TRY(launch_legendre_synth(P, 9 * nrhs, w.alm_a, w.eo, s));
+  CR_TRY(launch_pol_combine_synth(P, nrhs, w.eo, mixed, s));
+  return CR_OK;
+}
+
+// f * (a_T, a_E, a_B) from the azimuthal adjoints in w.geo (T, Q, U in group
+// columns 0..2); scratch w.alm_b
+int tqu_from_geo(const crsht_plan* P, int nrhs, const double* f, double2* out, hipStream_t s, bool mixed) {
+  Workspace const& w = P->w;
+  CR_TRY(launch_pol_pre_adjoint(P, nrhs, w.geo, mixed, s));
+  if (mixed)
+    CR_TRY(launch_legendre_adjoint_mixed(P, 7 * nrhs, F2(w.geo), w.alm_b, s));
+  else
+    CR_TRY(launch_legendre_adjoint(P, 7 * nrhs, w.geo, w.alm_b, false, s));
+  CR_TRY(launch_pol_combine_adjoint(P, nrhs, w.alm_b, f, out, s));
+  return CR_OK;
+}
+
+// T+Q+U operator: out = S^-1 x + B Y^T N^-1 Y B x (S^-1 term only with prior);
+// block partials of <x, out> in row 0. Scratch: w.eo, w.geo, w.alm_a, w.alm_b.
+int operator_core_tqu(const crsht_plan* P, int nrhs, const double2* x, const double* ninv, double2* out,
+                      hipStream_t s, bool mixed, bool prior) {
+  Workspace const& w = P->w;
+  CR_CHECK(tqu_spectra(P, nrhs, x, w.bl_keep, s, mixed));
+  CR_TRY(launch_ring(P, 3 * nrhs, RING_FUSED, w.eo, nullptr, ninv, w.geo, mixed, s, tqu_cols(P)));
+  CR_CHECK(tqu_from_geo(P, nrhs, w.bl_keep, w.alm_a, s, mixed));
+  CR_TRY(launch_cg_q_tqu(P, nrhs, x, w.alm_a, out, s, prior));
+  return CR_OK;
+}
+
 // A x for x already projected; pt = bk * x must be in w.alm_a. Uses w.eo,
 // w.geo and w.alm_b as scratch (x must not live there).
 // out = sinv * x + bk * (Y^T N^-1 Y)(pt); block partials of <x, out> in row 0.
+// (T+Q+U plans: pt unused.)
 int operator_core(const crsht_plan* P, int nrhs, const double2* x, const double2* pt, const double* ninv,
                   double2* out, hipStream_t s, bool mixed = false, bool prior = true) {
+  if (P->ncomp == 3) return operator_core_tqu(P, nrhs, x, ninv, out, s, mixed, prior);
   if (mixed)
     CR_TRY(launch_legendre_synth_mixed(P, nrhs, pt, nullptr, F2(P->w.eo), s));
   else
@@ -94,6 +189,10 @@ int operator_core(const crsht_plan* P, int nrhs, const double2* x, const double2
 // (Y^T N^-1 Y)(bk p); block partials of <p, out> in row 0.
 int operator_core_cg(const crsht_plan* P, int nrhs, bool update, const double* ninv, double2* out, hipStream_t s) {
   Workspace const& w = P->w;
+  if (P->ncomp == 3) {
+    if (update) CR_TRY(launch_cg_pupdate(P, nrhs, w.cg_z, w.cg_p, w.alm_a, s));
+    return operator_core_tqu(P, nrhs, w.cg_p, ninv, out, s, true, true);
+  }
   CR_TRY(launch_legendre_synth_mixed_cg(P, nrhs, w.cg_z, w.cg_p, update, F2(w.eo), s));
   CR_TRY(launch_ring(P, nrhs, RING_FUSED, w.eo, nullptr, ninv, w.geo, true, s));
   CR_TRY(launch_legendre_adjoint_mixed(P, nrhs, F2(w.geo), w.alm_b, s));
@@ -103,6 +202,17 @@ int operator_core_cg(const crsht_plan* P, int nrhs, bool update, const double* n
 
 // Jacobi diagonal into w.diag
 int compute_diag(const crsht_plan* P, const double* ninv, hipStream_t s) {
+  if (P->ncomp == 3) {
+    // T entries with the T ring weights; E and B entries with the mean of the
+    // Q and U ring weights (spin-0 functions stand in for the spin-2 ones)
+    const int64_t np = P->g.npix, na = P->g.nalm;
+    CR_TRY(launch_ring_weights(P, ninv, P->w.ring_w, s));
+    CR_TRY(launch_legendre_adjoint(P, 1, nullptr, P->w.alm_b, true, s));
+    CR_TRY(launch_ring_weights(P, ninv + np, P->w.ring_w, s, ninv + 2 * np, 0.5));
+    CR_TRY(launch_legendre_adjoint(P, 1, nullptr, P->w.alm_b + na, true, s));
+    CR_TRY(launch_diag_tqu(P, P->w.alm_b, P->w.alm_b + na, P->w.diag, s));
+    return CR_OK;
+  }
   CR_TRY(launch_ring_weights(P, ninv, P->w.ring_w, s));
   CR_TRY(launch_legendre_adjoint(P, 1, nullptr, P->w.alm_b, true, s));
   CR_TRY(launch_diag(P, P->w.alm_b, P->w.diag, s));
@@ -112,6 +222,17 @@ int compute_diag(const crsht_plan* P, const double* ninv, hipStream_t s) {
 // b = B Y^T (N^-1 d + N^-1/2 w1) + S^-1/2 w0 into out
 int assemble_rhs(const crsht_plan* P, int nrhs, const double* ninv, const double* d, const double* w0,
                  const double* w1, double2* out, hipStream_t s) {
+  if (P->ncomp == 3) {
+    const double2* dterm = nullptr;
+    if (d || w1) {
+      CR_TRY(launch_pix_rhs(P, nrhs, ninv, d, w1, P->w.map_a, s));
+      CR_TRY(launch_ring(P, 3 * nrhs, RING_ADJOINT, nullptr, P->w.map_a, nullptr, P->w.geo, false, s, tqu_cols(P)));
+      CR_CHECK(tqu_from_geo(P, nrhs, P->w.bl_keep, P->w.alm_a, s, false));
+      dterm = P->w.alm_a;
+    }
+    CR_TRY(launch_rhs_finish_tqu(P, nrhs, dterm, w0 ? C2(w0) : nullptr, out, s));
+    return CR_OK;
+  }
   const double2* braw = nullptr;
   if (d || w1) {
     CR_TRY(launch_pix_rhs(P, nrhs, ninv, d, w1, P->w.map_a, s));
@@ -123,8 +244,16 @@ int assemble_rhs(const crsht_plan* P, int nrhs, const double* ninv, const double
   return CR_OK;
 }
 
+// map = Y (scale * alm). T plans: scale per coefficient with kappa folded in
+// (rec_kappa for the plain transform). T+Q+U plans: scale is a per-coefficient
+// factor without kappa (null = 1; P->t.rec_kappa is read as null).
 int synth_f64(const crsht_plan* P, int nrhs, const double2* alm, const double* scale, double* map, hipStream_t s,
               bool mixed = false) {
+  if (P->ncomp == 3) {
+    CR_CHECK(tqu_spectra(P, nrhs, alm, scale == P->t.rec_kappa ? nullptr : scale, s, mixed));
+    CR_TRY(launch_ring(P, 3 * nrhs, RING_SYNTH, P->w.eo, map, nullptr, nullptr, mixed, s, tqu_cols(P)));
+    return CR_OK;
+  }
   if (mixed) {
     CR_TRY(launch_legendre_synth_mixed(P, nrhs, alm, scale, F2(P->w.eo), s));
   } else {
@@ -136,6 +265,11 @@ int synth_f64(const crsht_plan* P, int nrhs, const double2* alm, const double* s
 }
 
 int adjoint_f64(const crsht_plan* P, int nrhs, const double* map, double2* alm, hipStream_t s, bool mixed = false) {
+  if (P->ncomp == 3) {
+    CR_TRY(launch_ring(P, 3 * nrhs, RING_ADJOINT, nullptr, const_cast<double*>(map), nullptr, P->w.geo, mixed, s,
+                       tqu_cols(P)));
+    return tqu_from_geo(P, nrhs, nullptr, alm, s, mixed);
+  }
   CR_TRY(launch_ring(P, nrhs, RING_ADJOINT, nullptr, const_cast<double*>(map), nullptr, P->w.geo, mixed, s));
   if (mixed)
     CR_TRY(launch_legendre_adjoint_mixed(P, nrhs, F2(P->w.geo), alm, s));
@@ -163,7 +297,7 @@ int write_scalars(const crsht_plan* P, int nrhs, hipStream_t s) {
 int true_residual(const crsht_plan* P, int nrhs, const double* ninv, const double2* x, const double2* b,
                   double2* r, std::vector<double>& rel, hipStream_t s) {
   const int64_t na = P->g.nalm;
-  CR_TRY(launch_scale_alm(P, nrhs, x, P->w.bk, P->w.alm_a, s));
+  if (P->ncomp == 1) CR_TRY(launch_scale_alm(P, nrhs, x, P->w.bk, P->w.alm_a, s));
   CR_CHECK(operator_core(P, nrhs, x, P->w.alm_a, ninv, P->w.cg_q, s));
   CR_TRY(launch_residual(P, nrhs, b, P->w.cg_q, r, s));
   const int nb = vec_reduce_blocks(P);
@@ -187,7 +321,7 @@ int true_residual(const crsht_plan* P, int nrhs, const double* ninv, const doubl
 int pcg_run(const crsht_plan* P, int nrhs, const double* ninv, const double2* b, double tol, int maxiter,
             int check_every, bool mixed, bool verify, std::vector<int>& iters, std::vector<double>& rel,
             std::vector<int>& broke, hipStream_t s) {
-  const int64_t na = P->g.nalm;
+  const int64_t na = vlen(P);
   const int nb = vec_reduce_blocks(P);
   Workspace const& w = P->w;
   CR_TRY(hipMemsetAsync(w.cg_x, 0, (size_t)nrhs * na * sizeof(double2), s));
@@ -281,7 +415,7 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
   // update, so beta and p continue from the replaced residual.  A column whose
   // true residual did not fall since its last replacement restarts its
   // direction (beta = 0).
-  const int64_t na = P->g.nalm;
+  const int64_t na = vlen(P);
   const int nb = vec_reduce_blocks(P);
   Workspace const& w = P->w;
   const int every = o->check_every > 0 ? o->check_every : 8;
@@ -385,7 +519,7 @@ int solve_core(const crsht_plan* P, const cr_problem* prob, double q, int nrhs, 
     refine.assign(nrhs, 0);
   }
   fill_stats(nrhs, opts->tol, iters, refine, rel, broke, stats);
-  CR_TRY(hipMemcpyAsync(s_out, P->w.cg_x, (size_t)nrhs * P->g.nalm * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  CR_TRY(hipMemcpyAsync(s_out, P->w.cg_x, (size_t)nrhs * vlen(P) * sizeof(double2), hipMemcpyDeviceToDevice, s));
   CR_TRY(hipStreamSynchronize(s));
   return CR_OK;
 }
@@ -437,7 +571,7 @@ extern "C" int sht_analysis(const crsht_plan* P, int nrhs, const double* map, do
   if (!alm || !map || n_iter < 0) return CR_EINVAL;
   hipStream_t s = S(stream);
   const double wq = 4.0 * M_PI / (double)P->g.npix;
-  const int64_t na = (int64_t)nrhs * P->g.nalm, np = (int64_t)nrhs * P->g.npix;
+  const int64_t na = (int64_t)nrhs * vlen(P), np = (int64_t)nrhs * P->ncomp * P->g.npix;
   CR_CHECK(adjoint_f64(P, nrhs, map, C2(alm), s));
   CR_TRY(launch_alm_axpby(na, wq, C2(alm), 0.0, nullptr, C2(alm), s));
   for (int it = 0; it < n_iter; ++it) {
@@ -456,7 +590,7 @@ extern "C" int cr_precond(const crsht_plan* P, const cr_problem* prob, double* d
   hipStream_t s = S(stream);
   CR_CHECK(set_problem(P, prob, 1.0, s));
   CR_CHECK(compute_diag(P, prob->ninv, s));
-  CR_TRY(hipMemcpyAsync(diag, P->w.diag, P->g.nalm * sizeof(double), hipMemcpyDeviceToDevice, s));
+  CR_TRY(hipMemcpyAsync(diag, P->w.diag, vlen(P) * sizeof(double), hipMemcpyDeviceToDevice, s));
   return CR_OK;
 }
 
@@ -477,7 +611,7 @@ extern "C" int cr_apply(const crsht_plan* P, const cr_problem* prob, int nrhs, c
   hipStream_t s = S(stream);
   CR_CHECK(set_problem(P, prob, 1.0, s));
   CR_TRY(launch_project(P, nrhs, C2(x), P->w.cg_d, s));
-  CR_TRY(launch_scale_alm(P, nrhs, P->w.cg_d, P->w.bk, P->w.alm_a, s));
+  if (P->ncomp == 1) CR_TRY(launch_scale_alm(P, nrhs, P->w.cg_d, P->w.bk, P->w.alm_a, s));
   return operator_core(P, nrhs, P->w.cg_d, P->w.alm_a, prob->ninv, C2(Ax), s, prec == CR_MIXED);
 }
 
@@ -541,6 +675,7 @@ extern "C" int cr_solve_batched(const crsht_plan* const* plans, const cr_problem
 extern "C" int cr_lnpi(const crsht_plan* P, const cr_problem* fid, double q, const double* d, const double* ahat,
                        const double* fhat, double* lnpi, void* stream) {
   CR_CHECK(check_plan(P, 1));
+  if (P->ncomp != 1) return CR_ENOTSUP;
   if (!d || !ahat || !fhat || !lnpi) return CR_EINVAL;
   hipStream_t s = S(stream);
   CR_CHECK(set_problem(P, fid, q, s));
@@ -568,24 +703,37 @@ extern "C" int cr_grad_chi2(const crsht_plan* P, const cr_problem* prob, int nrh
   hipStream_t s = S(stream);
   CR_CHECK(set_problem(P, prob, 1.0, s));
   const int64_t np = P->g.npix;
+  const int nc = P->ncomp;
   // model map Y B a (B restricted to the kept modes) and chi^2 per column
-  CR_CHECK(synth_f64(P, nrhs, C2(a), P->w.bk, P->w.map_a, s));
+  CR_CHECK(synth_f64(P, nrhs, C2(a), nc == 3 ? P->w.bl_keep : P->w.bk, P->w.map_a, s));
   if (chi2) {
     const int npart = P->w.npart;
     const int nbp = std::min<int64_t>(npart, (np + 255) / 256);
     for (int c = 0; c < nrhs; ++c) {
-      CR_TRY(launch_pix_wsq(P, prob->ninv, d + c * np, P->w.map_a + c * np, P->w.partial, nbp, s));
+      for (int k = 0; k < 3; ++k) {   // one partial row per component (rows unused by T plans hold 0)
+        const int64_t off = ((int64_t)c * nc + k) * np;
+        if (k < nc)
+          CR_TRY(launch_pix_wsq(P, prob->ninv + k * np, d + off, P->w.map_a + off, P->w.partial + k * npart, nbp, s));
+        else
+          CR_TRY(hipMemsetAsync(P->w.partial + k * npart, 0, nbp * sizeof(double), s));
+      }
       CR_TRY(launch_sum_rows(P, 1, nbp, s));
       CR_CHECK(read_scalars(P, 1, s));
-      chi2[c] = P->w.host_scal[S_AUX0];
+      const double* sc = P->w.host_scal;
+      chi2[c] = sc[S_AUX0] + sc[S_AUX1] + sc[S_AUX2];
     }
   }
   // g = -2 B Y^T N^-1 (d - Y B a)
   CR_TRY(launch_pix_wres(P, nrhs, prob->ninv, d, P->w.map_a, P->w.map_a, s));
-  CR_TRY(launch_ring(P, nrhs, RING_ADJOINT, nullptr, P->w.map_a, nullptr, P->w.geo, false, s));
-  CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, P->w.alm_b, false, s));   // raw sums (no kappa)
-  CR_TRY(launch_scale_alm(P, nrhs, P->w.alm_b, P->w.bk, C2(grad), s));          // b_l kappa_lm on kept modes
-  CR_TRY(launch_alm_axpby((int64_t)nrhs * P->g.nalm, -2.0, C2(grad), 0.0, nullptr, C2(grad), s));
+  if (nc == 3) {
+    CR_TRY(launch_ring(P, 3 * nrhs, RING_ADJOINT, nullptr, P->w.map_a, nullptr, P->w.geo, false, s, tqu_cols(P)));
+    CR_CHECK(tqu_from_geo(P, nrhs, P->w.bl_keep, C2(grad), s, false));
+  } else {
+    CR_TRY(launch_ring(P, nrhs, RING_ADJOINT, nullptr, P->w.map_a, nullptr, P->w.geo, false, s));
+    CR_TRY(launch_legendre_adjoint(P, nrhs, P->w.geo, P->w.alm_b, false, s));   // raw sums (no kappa)
+    CR_TRY(launch_scale_alm(P, nrhs, P->w.alm_b, P->w.bk, C2(grad), s));          // b_l kappa_lm on kept modes
+  }
+  CR_TRY(launch_alm_axpby((int64_t)nrhs * vlen(P), -2.0, C2(grad), 0.0, nullptr, C2(grad), s));
   CR_TRY(launch_project(P, nrhs, C2(grad), C2(grad), s));
   CR_TRY(hipStreamSynchronize(s));
   return CR_OK;
@@ -595,6 +743,7 @@ extern "C" int cr_grad_lnpi(const crsht_plan* P, const cr_problem* prob, const d
                             const double* w1, int nbins, const int* edges, const cr_opts* opts, double* grad,
                             double* lnpi, cr_stats* stats, void* stream) {
   CR_CHECK(check_plan(P, 1));
+  if (P->ncomp != 1) return CR_ENOTSUP;
   if (!prob || !d || !edges || !opts || !grad || !lnpi || !stats) return CR_EINVAL;
   if (nbins < 1 || nbins > P->g.lmax + 1) return CR_EINVAL;
   for (int k = 0; k <= nbins; ++k) {
@@ -629,6 +778,7 @@ extern "C" int cr_grad_lnpi(const crsht_plan* P, const cr_problem* prob, const d
 extern "C" int joint_cl_step(const crsht_plan* P, const cr_problem* fid, const double* d, cr_chain* state,
                              const cr_draws* dr, const cr_opts* opts, cr_step_out* out, void* stream) {
   CR_CHECK(check_plan(P, 1));
+  if (P->ncomp != 1) return CR_ENOTSUP;
   if (!fid || !d || !state || !dr || !opts || !out || !state->ahat || !state->fhat) return CR_EINVAL;
   if (!(dr->sigma_lnq > 0.0) || !(dr->u > 0.0 && dr->u < 1.0) || !std::isfinite(dr->xi)) return CR_EINVAL;
   if (!(state->q > 0.0) || !std::isfinite(state->lnpi)) return CR_EINVAL;

@@ -69,6 +69,7 @@ struct Tables {
   int64_t mx_ntiles = 0;
   int* idx_l = nullptr;            // [nalm] l of each stored coefficient
   int* idx_m = nullptr;            // [nalm] m of each stored coefficient
+  int* idx_mv = nullptr;           // [ncomp * nalm] m of each element of a solver vector
 };
 
 // Ring pairs of one FFT-length class: t.ring_pairs[off .. off + count) all have
@@ -92,7 +93,9 @@ struct Workspace {
   double* diag = nullptr;      // [nalm] Jacobi diagonal D_lm
   double* sinv = nullptr;      // [nalm] 1/C_l on kept modes, 0 otherwise
   double* sinvhalf = nullptr;  // [nalm] C_l^-1/2
-  double* bk = nullptr;        // [nalm] b_l kappa_lm on kept modes
+  double* bk = nullptr;        // [ncomp * nalm] b_l kappa_lm on kept modes (repeated per component)
+  double* bl_keep = nullptr;   // [nalm] b_l on kept modes
+  double* sblk = nullptr;      // [lmax+1][8] T+Q+U: S^-1 (TT, TE, EE, BB) and S^-1/2 (TT, TE, EE, BB)
   double* perl = nullptr;      // [4][lmax+1] per-l 1/C_l, C_l^-1/2, b_l, keep (device)
   double* partial = nullptr;   // [nrhs][npart] block partial sums
   double* scal = nullptr;      // [nrhs][kScalSlots] CG scalars
@@ -161,6 +164,9 @@ struct crsht_plan {
 
 namespace crsht {
 
+// elements of one solver vector column: ncomp blocks of nalm coefficients
+inline int64_t vlen(const crsht_plan* P) { return (int64_t)P->ncomp * P->g.nalm; }
+
 // ---- timing (timing.cpp) ----
 void timing_begin(const crsht_plan* P, int id, hipStream_t s);
 void timing_end(const crsht_plan* P, int id, hipStream_t s);
@@ -204,10 +210,42 @@ hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const fl
 // mode SYNTH: eo -> map;  ADJOINT: map -> geo;  FUSED: eo -> (map * ninv) -> geo
 // eo / geo are double2 arrays, or float2 arrays with f32 (maps and N^-1 FP64)
 enum RingMode { RING_SYNTH = 0, RING_ADJOINT = 1, RING_FUSED = 2 };
+// Column layout of a ring launch: logical column c (maps c * npix) is
+// component k = c % group of group c / group; its Legendre sums are column
+// (c / group) * eo_cols + k of eo, (c / group) * geo_cols + k of geo, and its
+// N^-1 is ninv + k * ninv_stride. The default is one plain column per map.
+struct RingCols {
+  int group = 1, eo_cols = 1, geo_cols = 1;
+  int64_t ninv_stride = 0;
+};
 hipError_t launch_ring(const crsht_plan* P, int nrhs, RingMode mode, const void* eo, double* map,
-                       const double* ninv, void* geo, bool f32, hipStream_t s);
+                       const double* ninv, void* geo, bool f32, hipStream_t s, RingCols cols = RingCols());
 void ring_classes(const std::vector<int>& fft_len, std::vector<RingClass>& cls, std::vector<int>& pairs);
 size_t ring_lds_bytes(const crsht_plan* P, bool f32);
+
+// ---- spin-2 part of T+Q+U plans (pol.hip) ----
+// alm [nrhs][3][nalm] (times f per element, may be null) -> 9 scalar
+// coefficient columns per T+Q+U column [nrhs][9][nalm] (kappa folded in)
+hipError_t launch_pol_prep_synth(const crsht_plan* P, int nrhs, const double2* alm, const double* f, double2* out,
+                                 hipStream_t s);
+// Legendre sums of the 9 columns -> Q, U spectra over group columns 1, 2
+hipError_t launch_pol_combine_synth(const crsht_plan* P, int nrhs, void* eo, bool f32, hipStream_t s);
+// azimuthal adjoints of Q, U (group columns 1, 2 of 7) -> weighted copies in 3..6
+hipError_t launch_pol_pre_adjoint(const crsht_plan* P, int nrhs, void* geo, bool f32, hipStream_t s);
+// raw Legendre adjoints [nrhs][7][nalm] -> f * (a_T, a_E, a_B) [nrhs][3][nalm]
+hipError_t launch_pol_combine_adjoint(const crsht_plan* P, int nrhs, const double2* raw, const double* f,
+                                      double2* out, hipStream_t s);
+// per-element problem arrays of a T+Q+U plan from w.sblk and the b_l / keep
+// rows of perl: sinv, sinvhalf = diagonals of the blocks, bk = b_l kappa_lm
+// (x3), bl_keep = b_l on kept modes
+hipError_t launch_expand_tqu(const crsht_plan* P, const double* perl, hipStream_t s);
+// q = S^-1 p + dterm (3x3 blocks; S^-1 omitted without prior); partial <p, q>
+hipError_t launch_cg_q_tqu(const crsht_plan* P, int nrhs, const double2* p, const double2* dterm, double2* q,
+                           hipStream_t s, bool prior = true);
+hipError_t launch_rhs_finish_tqu(const crsht_plan* P, int nrhs, const double2* dterm, const double2* w0,
+                                 double2* out, hipStream_t s);
+hipError_t launch_diag_tqu(const crsht_plan* P, const double2* rawt, const double2* rawp, double* diag,
+                           hipStream_t s);
 
 // ---- vector kernels (vec.hip) ----
 // Reductions write per-block partial sums to w.partial (column c, row r at
@@ -216,7 +254,9 @@ int vec_reduce_blocks(const crsht_plan* P);
 hipError_t launch_expand(const crsht_plan* P, const double* perl, hipStream_t s);
 hipError_t launch_scale_alm(const crsht_plan* P, int nrhs, const double2* in, const double* f, double2* out,
                             hipStream_t s);
-hipError_t launch_ring_weights(const crsht_plan* P, const double* ninv, double* w, hipStream_t s);
+// w[p] = scale * ring sums of ninv (+ ninv2 when given) over both rings of pair p
+hipError_t launch_ring_weights(const crsht_plan* P, const double* ninv, double* w, hipStream_t s,
+                               const double* ninv2 = nullptr, double scale = 1.0);
 hipError_t launch_pix_rhs(const crsht_plan* P, int nrhs, const double* ninv, const double* d, const double* w1,
                           double* u, hipStream_t s);
 hipError_t launch_rhs_finish(const crsht_plan* P, int nrhs, const double2* raw, const double2* w0, double2* out,

@@ -77,7 +77,7 @@ void free_plan_memory(crsht_plan* P) {
                   P->t.twiddle, P->t.bs_chirp32, P->t.bs_kern32, P->t.twiddle32, P->t.ring_pairs, P->t.rec_alpha, P->t.rec_kappa, P->t.lmm_v, P->t.lmm_k, P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.ones,
                   P->t.mx_cstart, P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_order, P->t.mx_ckpt, P->w.cg_xacc, P->w.cg_bin, P->w.bin_edges, P->w.bin_part, P->w.bin_grad,
                   P->w.mx_ab, P->w.mx_ag,
-                  P->t.idx_l, P->t.idx_m, P->w.eo, P->w.geo, P->w.alm_a, P->w.alm_b, P->w.cg_x, P->w.cg_r,
+                  P->t.idx_l, P->t.idx_m, P->w.eo, P->w.geo, P->w.alm_a, P->w.alm_b, P->w.cg_x, P->w.cg_r, P->t.idx_mv, P->w.bl_keep, P->w.sblk,
                   P->w.cg_z, P->w.cg_p, P->w.cg_q, P->w.cg_b, P->w.cg_d, P->w.alm_c, P->w.alm_d, P->w.map_a, P->w.ring_w,
                   P->w.diag, P->w.sinv, P->w.sinvhalf, P->w.bk, P->w.perl, P->w.partial, P->w.scal};
   for (void* p : ptrs)
@@ -87,7 +87,7 @@ void free_plan_memory(crsht_plan* P) {
 
 }  // namespace
 
-static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int nrhs_max, size_t* total) {
+static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int ncomp, int nrhs_max, size_t* total) {
   Geometry& g = P->g;
   g.nside = nside;
   g.lmax = lmax;
@@ -290,20 +290,32 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int nrhs_max
   }
   if ((rc = upload(&P->t.idx_l, il, total))) return rc;
   if ((rc = upload(&P->t.idx_m, im, total))) return rc;
+  {
+    std::vector<int> imv;
+    for (int k = 0; k < ncomp; ++k) imv.insert(imv.end(), im.begin(), im.end());
+    if ((rc = upload(&P->t.idx_mv, imv, total))) return rc;
+  }
 
   // ---------------- workspace
+  // A T+Q+U column expands to 9 scalar Legendre columns in the synthesis (T,
+  // and T0..T3 of E and B) and 7 in the adjoint (T, Q, U and four weighted
+  // copies of Q and U); solver vectors hold 3 blocks of nalm.
   const size_t R = (size_t)nrhs_max;
-  const size_t neo = R * (size_t)np * (size_t)(mmax + 1) * 2;
+  const size_t C = (size_t)ncomp;
+  const size_t ceo = ncomp == 3 ? 9 : 1, cgeo = ncomp == 3 ? 7 : 1;
+  const size_t neo1 = (size_t)np * (size_t)(mmax + 1) * 2;
   const size_t na = R * (size_t)g.nalm;
   crsht::Workspace& w = P->w;
   w.npart = (mmax + 1) > 1024 ? (mmax + 1) : 1024;
-  if ((rc = dalloc(&w.eo, neo, total))) return rc;
-  if ((rc = dalloc(&w.geo, neo, total))) return rc;
-  double2** avec[] = {&w.alm_a, &w.alm_b, &w.cg_x, &w.cg_r, &w.cg_z, &w.cg_p, &w.cg_q, &w.cg_b, &w.cg_d};
+  if ((rc = dalloc(&w.eo, R * ceo * neo1, total))) return rc;
+  if ((rc = dalloc(&w.geo, R * cgeo * neo1, total))) return rc;
+  if ((rc = dalloc(&w.alm_a, ceo * na, total))) return rc;
+  if ((rc = dalloc(&w.alm_b, cgeo * na, total))) return rc;
+  double2** avec[] = {&w.cg_x, &w.cg_r, &w.cg_z, &w.cg_p, &w.cg_q, &w.cg_b, &w.cg_d};
   for (double2** a : avec)
-    if ((rc = dalloc(a, na, total))) return rc;
-  if ((rc = dalloc(&w.cg_xacc, na, total))) return rc;
-  if ((rc = dalloc(&w.cg_bin, na, total))) return rc;
+    if ((rc = dalloc(a, C * na, total))) return rc;
+  if ((rc = dalloc(&w.cg_xacc, C * na, total))) return rc;
+  if ((rc = dalloc(&w.cg_bin, C * na, total))) return rc;
   {
     unsigned char *ab = nullptr, *ag = nullptr;
     if ((rc = dalloc(&ab, (size_t)crsht::mixed_ab_bytes(g), total))) return rc;
@@ -311,13 +323,15 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int nrhs_max
     if ((rc = dalloc(&ag, (size_t)crsht::mixed_ag_bytes(g), total))) return rc;
     w.mx_ag = ag;
   }
-  if ((rc = dalloc(&w.alm_c, (size_t)g.nalm, total))) return rc;
-  if ((rc = dalloc(&w.alm_d, (size_t)g.nalm, total))) return rc;
-  if ((rc = dalloc(&w.map_a, R * (size_t)g.npix, total))) return rc;
+  if ((rc = dalloc(&w.alm_c, C * (size_t)g.nalm, total))) return rc;
+  if ((rc = dalloc(&w.alm_d, C * (size_t)g.nalm, total))) return rc;
+  if ((rc = dalloc(&w.map_a, R * C * (size_t)g.npix, total))) return rc;
   if ((rc = dalloc(&w.ring_w, (size_t)np, total))) return rc;
   double** dvec[] = {&w.diag, &w.sinv, &w.sinvhalf, &w.bk};
   for (double** a : dvec)
-    if ((rc = dalloc(a, (size_t)g.nalm, total))) return rc;
+    if ((rc = dalloc(a, C * (size_t)g.nalm, total))) return rc;
+  if ((rc = dalloc(&w.bl_keep, (size_t)g.nalm, total))) return rc;
+  if ((rc = dalloc(&w.sblk, 8 * (size_t)(lmax + 1), total))) return rc;
   if ((rc = dalloc(&w.perl, 4 * (size_t)(lmax + 1), total))) return rc;
   if ((rc = dalloc(&w.partial, R * (size_t)w.npart * 4, total))) return rc;
   if ((rc = dalloc(&w.bin_edges, (size_t)lmax + 2, total))) return rc;
@@ -340,7 +354,7 @@ extern "C" int crsht_plan_create(int nside, int lmax, int mmax, int ncomp, int n
   if (nside < 1 || lmax < 0 || mmax > lmax || nrhs_max < 1 || nrhs_max > 4096) return CR_EINVAL;
   if (lmax > 16383) return CR_EINVAL;
   if (nside > 1024) return CR_ENOTSUP;  // FP64 adjoint: at most 8 ring pairs per thread x 256 threads
-  if (ncomp != 1) return ncomp == 3 ? CR_ENOTSUP : CR_EINVAL;
+  if (ncomp != 1 && ncomp != 3) return CR_EINVAL;
   crsht_plan* P = new (std::nothrow) crsht_plan();
   if (!P) return CR_ENOMEM;
   P->ncomp = ncomp;
@@ -350,7 +364,7 @@ extern "C" int crsht_plan_create(int nside, int lmax, int mmax, int ncomp, int n
     return CR_EDEVICE;
   }
   size_t total = 0;
-  int rc = build_plan(P, nside, lmax, mmax, nrhs_max, &total);
+  int rc = build_plan(P, nside, lmax, mmax, ncomp, nrhs_max, &total);
   if (rc != CR_OK) {
     free_plan_memory(P);
     delete P;

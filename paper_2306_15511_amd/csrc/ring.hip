@@ -482,7 +482,7 @@ __global__ __launch_bounds__(NT) void k_ring(Tables T, int nside, int mmax, int 
                                               const V* __restrict__ chirp, const V* __restrict__ kern,
                                               const V* __restrict__ eo, int64_t eo_stride, double* __restrict__ map,
                                               int64_t map_stride, const double* __restrict__ ninv,
-                                              V* __restrict__ geo, int64_t geo_stride) {
+                                              V* __restrict__ geo, int64_t geo_stride, RingCols rc) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   V* buf = reinterpret_cast<V*>(lds_raw);
   // spectrum scratch of small rings (blockDim x 8 reals) in the upper half
@@ -493,9 +493,12 @@ __global__ __launch_bounds__(NT) void k_ring(Tables T, int nside, int mmax, int 
   if (g >= npc * nrhs) return;
   const int p = pairs[g / nrhs], c = g % nrhs;
   const PairInfo<V> q = pair_info<V>(T, p, nside, chirp, kern);
-  const V* __restrict__ eop = eo + c * eo_stride + (size_t)p * (mmax + 1) * 2;
-  V* __restrict__ geop = geo + c * geo_stride + (size_t)p * (mmax + 1) * 2;
+  // logical column c = component kc of group gq (T+Q+U plans: 3 maps per group)
+  const int gq = c / rc.group, kc = c % rc.group;
+  const V* __restrict__ eop = eo + ((int64_t)gq * rc.eo_cols + kc) * eo_stride + (size_t)p * (mmax + 1) * 2;
+  V* __restrict__ geop = geo + ((int64_t)gq * rc.geo_cols + kc) * geo_stride + (size_t)p * (mmax + 1) * 2;
   double* __restrict__ mp = map + c * map_stride;
+  if (ninv) ninv += kc * rc.ninv_stride;
 
   if (MODE == RING_FUSED) {
     ring_inverse(buf, scratch, q, eop, mmax, tw, fmax);
@@ -542,7 +545,7 @@ size_t ring_lds(int Lc) {
 
 template <class V, int MODE>
 hipError_t ring_launch(const crsht_plan* P, int nrhs, const V* eo, double* map, const double* ninv, V* geo,
-                       const V* tw, const V* chirp, const V* kern, hipStream_t s) {
+                       const V* tw, const V* chirp, const V* kern, RingCols cols, hipStream_t s) {
   const Geometry& g = P->g;
   const int64_t stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
   for (const RingClass& rc : P->ring_cls) {
@@ -557,7 +560,7 @@ hipError_t ring_launch(const crsht_plan* P, int nrhs, const V* eo, double* map, 
                                 (int)lds);                                                                      \
     hipLaunchKernelGGL((k_ring<V, MODE, NT>), dim3(nb), dim3(nt), lds, s, P->t, g.nside, g.mmax, g.fft_max,      \
                        P->t.ring_pairs + rc.off, rc.count, nrhs, rc.L, tw, chirp, kern, eo, stride, map,         \
-                       (int64_t)g.npix, ninv, geo, stride);                                                     \
+                       (int64_t)g.npix, ninv, geo, stride, cols);                                               \
   } while (0)
     if (nt <= 512)
       CRSHT_RING_LAUNCH(512);
@@ -572,10 +575,11 @@ hipError_t ring_launch(const crsht_plan* P, int nrhs, const V* eo, double* map, 
 
 template <class V>
 hipError_t ring_mode(const crsht_plan* P, int nrhs, RingMode mode, const V* eo, double* map, const double* ninv,
-                     V* geo, const V* tw, const V* chirp, const V* kern, hipStream_t s) {
-  if (mode == RING_SYNTH) return ring_launch<V, RING_SYNTH>(P, nrhs, eo, map, ninv, geo, tw, chirp, kern, s);
-  if (mode == RING_ADJOINT) return ring_launch<V, RING_ADJOINT>(P, nrhs, eo, map, ninv, geo, tw, chirp, kern, s);
-  return ring_launch<V, RING_FUSED>(P, nrhs, eo, map, ninv, geo, tw, chirp, kern, s);
+                     V* geo, const V* tw, const V* chirp, const V* kern, RingCols cols, hipStream_t s) {
+  if (mode == RING_SYNTH) return ring_launch<V, RING_SYNTH>(P, nrhs, eo, map, ninv, geo, tw, chirp, kern, cols, s);
+  if (mode == RING_ADJOINT)
+    return ring_launch<V, RING_ADJOINT>(P, nrhs, eo, map, ninv, geo, tw, chirp, kern, cols, s);
+  return ring_launch<V, RING_FUSED>(P, nrhs, eo, map, ninv, geo, tw, chirp, kern, cols, s);
 }
 
 }  // namespace
@@ -610,15 +614,15 @@ size_t ring_lds_bytes(const crsht_plan* P, bool f32) {
 }
 
 hipError_t launch_ring(const crsht_plan* P, int nrhs, RingMode mode, const void* eo, double* map,
-                       const double* ninv, void* geo, bool f32, hipStream_t s) {
+                       const double* ninv, void* geo, bool f32, hipStream_t s, RingCols cols) {
   timing_begin(P, 2, s);
   hipError_t e;
   if (f32)
     e = ring_mode<float2>(P, nrhs, mode, (const float2*)eo, map, ninv, (float2*)geo, P->t.twiddle32, P->t.bs_chirp32,
-                          P->t.bs_kern32, s);
+                          P->t.bs_kern32, cols, s);
   else
     e = ring_mode<double2>(P, nrhs, mode, (const double2*)eo, map, ninv, (double2*)geo, P->t.twiddle, P->t.bs_chirp,
-                           P->t.bs_kern, s);
+                           P->t.bs_kern, cols, s);
   timing_end(P, 2, s);
   return e;
 }

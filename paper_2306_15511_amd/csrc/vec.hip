@@ -4,24 +4,13 @@
 // reductions in a fixed order (block partial sums, then one block summing the
 // partials), so results are run-to-run reproducible.
 #include "internal.h"
+#include "devutil.h"
 
 namespace crsht {
 namespace {
 
 constexpr int kVecBlock = 256;
 
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  // fixed-order tree reduction over the block
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  const double r = sh[0];
-  __syncthreads();
-  return r;
-}
 
 // per-index problem arrays from per-l arrays:
 // sinv = keep/C_l, sinvhalf = keep/sqrt(C_l), bk = keep b_l kappa_lm
@@ -50,7 +39,7 @@ __global__ void k_scale(int64_t nalm, int nrhs, const double2* in, const double*
 
 __global__ void k_ring_weights(int npairs, const int* __restrict__ nphi, const int64_t* __restrict__ fn,
                                const int64_t* __restrict__ fs, const double* __restrict__ ninv,
-                               double* __restrict__ w) {
+                               const double* __restrict__ ninv2, double scale, double* __restrict__ w) {
   __shared__ double sh[kVecBlock];
   const int p = blockIdx.x;
   const int n = nphi[p];
@@ -59,23 +48,31 @@ __global__ void k_ring_weights(int npairs, const int* __restrict__ nphi, const i
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
     acc += ninv[fn[p] + j];
     if (!eq) acc += ninv[fs[p] + j];
+    if (ninv2) {
+      acc += ninv2[fn[p] + j];
+      if (!eq) acc += ninv2[fs[p] + j];
+    }
   }
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) w[p] = acc;
+  if (threadIdx.x == 0) w[p] = scale * acc;
 }
 
-// u = ninv * d + sqrt(ninv) * w1 (either may be absent)
-__global__ void k_pix_rhs(int64_t npix, int nrhs, const double* __restrict__ ninv, const double* __restrict__ d,
-                          const double* __restrict__ w1, double* __restrict__ u) {
+// u = ninv * d + sqrt(ninv) * w1 (either may be absent); maps [nrhs][ncomp][npix],
+// ninv [ncomp][npix]
+__global__ void k_pix_rhs(int64_t npix, int nrhs, int ncomp, const double* __restrict__ ninv,
+                          const double* __restrict__ d, const double* __restrict__ w1, double* __restrict__ u) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npix) return;
-  const double n = ninv[i];
-  const double sn = sqrt(n);
-  for (int c = 0; c < nrhs; ++c) {
-    double v = 0.0;
-    if (d) v = n * d[c * npix + i];
-    if (w1) v = fma(sn, w1[c * npix + i], v);
-    u[c * npix + i] = v;
+  for (int k = 0; k < ncomp; ++k) {
+    const double n = ninv[k * npix + i];
+    const double sn = sqrt(n);
+    for (int c = 0; c < nrhs; ++c) {
+      const int64_t j = ((int64_t)c * ncomp + k) * npix + i;
+      double v = 0.0;
+      if (d) v = n * d[j];
+      if (w1) v = fma(sn, w1[j], v);
+      u[j] = v;
+    }
   }
 }
 
@@ -140,9 +137,6 @@ __global__ void k_alm_axpby(int64_t n, double a, const double2* __restrict__ x, 
 
 // ---------------------------------------------------------------- PCG pieces
 // weighted dot partials of one column: w_m (a.x c.x + a.y c.y)
-__device__ __forceinline__ double wdot(int m, double2 a, double2 c) {
-  return (m == 0 ? 1.0 : 2.0) * fma(a.x, c.x, a.y * c.y);
-}
 
 // start: x = 0 (or given), r = b - A x0 computed by caller in r, z = r / D,
 // p = z, pt = bk * p; partial sums of <r,z>, <r,r>, <b,b>
@@ -434,13 +428,19 @@ int nblocks(int64_t n) {
   return (int)(b < 1 ? 1 : b);
 }
 
-// u = N^-1 (d - m) per column (data residual weighted by the inverse noise)
-__global__ void k_pix_wres(int64_t npix, int nrhs, const double* __restrict__ ninv, const double* __restrict__ d,
-                           const double* m, double* u) {   // u may alias m (element-wise)
+// u = N^-1 (d - m) per column (data residual weighted by the inverse noise);
+// maps [nrhs][ncomp][npix], ninv [ncomp][npix]
+__global__ void k_pix_wres(int64_t npix, int nrhs, int ncomp, const double* __restrict__ ninv,
+                           const double* __restrict__ d, const double* m, double* u) {   // u may alias m
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npix) return;
-  const double n = ninv[i];
-  for (int c = 0; c < nrhs; ++c) u[c * npix + i] = n * (d[c * npix + i] - m[c * npix + i]);
+  for (int k = 0; k < ncomp; ++k) {
+    const double n = ninv[k * npix + i];
+    for (int c = 0; c < nrhs; ++c) {
+      const int64_t j = ((int64_t)c * ncomp + k) * npix + i;
+      u[j] = n * (d[j] - m[j]);
+    }
+  }
 }
 
 // real-field weights of the synthesis gradient: x 2 for m > 0, Im of m = 0 set to 0
@@ -511,7 +511,7 @@ __global__ void k_bin_grad(int nbins, int S, const double* __restrict__ partial,
 }  // namespace
 
 int vec_reduce_blocks(const crsht_plan* P) {
-  int64_t b = (P->g.nalm + kVecBlock - 1) / kVecBlock;
+  int64_t b = (vlen(P) + kVecBlock - 1) / kVecBlock;
   int cap = P->w.npart;
   if (cap > 1024) cap = 1024;
   return (int)(b < 1 ? 1 : (b > cap ? cap : b));
@@ -529,15 +529,17 @@ hipError_t launch_scale_alm(const crsht_plan* P, int nrhs, const double2* in, co
   return hipGetLastError();
 }
 
-hipError_t launch_ring_weights(const crsht_plan* P, const double* ninv, double* w, hipStream_t s) {
+hipError_t launch_ring_weights(const crsht_plan* P, const double* ninv, double* w, hipStream_t s,
+                               const double* ninv2, double scale) {
   hipLaunchKernelGGL(k_ring_weights, dim3(P->g.npairs), dim3(kVecBlock), 0, s, P->g.npairs, P->t.pair_nphi,
-                     P->t.pair_first_n, P->t.pair_first_s, ninv, w);
+                     P->t.pair_first_n, P->t.pair_first_s, ninv, ninv2, scale, w);
   return hipGetLastError();
 }
 
 hipError_t launch_pix_rhs(const crsht_plan* P, int nrhs, const double* ninv, const double* d, const double* w1,
                           double* u, hipStream_t s) {
-  hipLaunchKernelGGL(k_pix_rhs, dim3(nblocks(P->g.npix)), dim3(kVecBlock), 0, s, P->g.npix, nrhs, ninv, d, w1, u);
+  hipLaunchKernelGGL(k_pix_rhs, dim3(nblocks(P->g.npix)), dim3(kVecBlock), 0, s, P->g.npix, nrhs, P->ncomp, ninv, d,
+                     w1, u);
   return hipGetLastError();
 }
 
@@ -549,7 +551,7 @@ hipError_t launch_rhs_finish(const crsht_plan* P, int nrhs, const double2* raw, 
 }
 
 hipError_t launch_project(const crsht_plan* P, int nrhs, const double2* x, double2* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_project, dim3(nblocks(P->g.nalm)), dim3(kVecBlock), 0, s, P->g.nalm, nrhs, P->t.idx_m,
+  hipLaunchKernelGGL(k_project, dim3(nblocks(vlen(P))), dim3(kVecBlock), 0, s, vlen(P), nrhs, P->t.idx_mv,
                      P->w.sinv, x, out);
   return hipGetLastError();
 }
@@ -569,7 +571,7 @@ hipError_t launch_alm_axpby(int64_t n, double a, const double2* x, double b, con
 hipError_t launch_cg_start(const crsht_plan* P, int nrhs, const double2* b, const double2* r, double2* z,
                            double2* p, double2* pt, hipStream_t s) {
   const int nb = vec_reduce_blocks(P);
-  hipLaunchKernelGGL(k_cg_start, dim3(nb, nrhs), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_m, P->w.diag,
+  hipLaunchKernelGGL(k_cg_start, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, P->w.diag,
                      P->w.bk, b, r, z, p, pt, P->w.partial, P->w.npart, P->w.scal);
   return hipGetLastError();
 }
@@ -598,14 +600,14 @@ hipError_t launch_diag(const crsht_plan* P, const double2* raw, double* diag, hi
 hipError_t launch_cg_update(const crsht_plan* P, int nrhs, double2* x, double2* r, double2* z, const double2* p,
                             const double2* q, hipStream_t s) {
   const int nb = vec_reduce_blocks(P);
-  hipLaunchKernelGGL(k_cg_update, dim3(nb, nrhs), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_m, P->w.diag,
+  hipLaunchKernelGGL(k_cg_update, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, P->w.diag,
                      P->w.bk, x, r, z, p, q, P->w.partial, P->w.npart, P->w.scal);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_replace(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s) {
   const int nb = vec_reduce_blocks(P);
-  hipLaunchKernelGGL(k_cg_replace, dim3(nb, nrhs), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_m, P->w.diag, r, z,
+  hipLaunchKernelGGL(k_cg_replace, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, P->w.diag, r, z,
                      P->w.partial, P->w.npart);
   return hipGetLastError();
 }
@@ -613,7 +615,7 @@ hipError_t launch_cg_replace(const crsht_plan* P, int nrhs, const double2* r, do
 hipError_t launch_cg_pupdate(const crsht_plan* P, int nrhs, const double2* z, double2* p, double2* pt,
                              hipStream_t s) {
   const int nb = vec_reduce_blocks(P);
-  hipLaunchKernelGGL(k_cg_pupdate, dim3(nb, nrhs), dim3(kVecBlock), 0, s, P->g.nalm, P->w.bk, z, p, pt,
+  hipLaunchKernelGGL(k_cg_pupdate, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->w.bk, z, p, pt,
                      P->w.scal);
   return hipGetLastError();
 }
@@ -621,7 +623,7 @@ hipError_t launch_cg_pupdate(const crsht_plan* P, int nrhs, const double2* z, do
 hipError_t launch_residual(const crsht_plan* P, int nrhs, const double2* b, const double2* ax, double2* r,
                            hipStream_t s) {
   const int nb = vec_reduce_blocks(P);
-  hipLaunchKernelGGL(k_residual, dim3(nb, nrhs), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_m, b, ax, r,
+  hipLaunchKernelGGL(k_residual, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, b, ax, r,
                      P->w.partial, P->w.npart);
   return hipGetLastError();
 }
@@ -645,12 +647,13 @@ hipError_t launch_alm_wquad(const crsht_plan* P, const double* f, const double2*
 
 hipError_t launch_pix_wres(const crsht_plan* P, int nrhs, const double* ninv, const double* d, const double* m,
                            double* u, hipStream_t s) {
-  hipLaunchKernelGGL(k_pix_wres, dim3(nblocks(P->g.npix)), dim3(kVecBlock), 0, s, P->g.npix, nrhs, ninv, d, m, u);
+  hipLaunchKernelGGL(k_pix_wres, dim3(nblocks(P->g.npix)), dim3(kVecBlock), 0, s, P->g.npix, nrhs, P->ncomp, ninv,
+                     d, m, u);
   return hipGetLastError();
 }
 
 hipError_t launch_mweight(const crsht_plan* P, int nrhs, double2* a, hipStream_t s) {
-  hipLaunchKernelGGL(k_mweight, dim3(nblocks(P->g.nalm)), dim3(kVecBlock), 0, s, P->g.nalm, nrhs, P->t.idx_m, a);
+  hipLaunchKernelGGL(k_mweight, dim3(nblocks(vlen(P))), dim3(kVecBlock), 0, s, vlen(P), nrhs, P->t.idx_mv, a);
   return hipGetLastError();
 }
 

@@ -1,0 +1,219 @@
+"""GPU parity of T+Q+U plans (C ABI) against the oracle of oracle/cr_tqu.py and
+oracle/spin2.py: spin-0 + spin-2 synthesis and its adjoint, the Jacobi
+diagonal, right-hand side and operator with the 3x3 spectra blocks, PCG
+solves (FP64 and mixed with FP64 residual replacement) and the chi^2 gradient.
+
+FP64 tolerance: the spin-2 functions are formed from scalar Legendre sums with
+the ring factors 1/sin^2 and cos/sin^2 applied afterwards; the polar rings
+(sin^2 ~ 2 / (3 nside^2)) amplify rounding of the sums by up to that factor,
+which stays far below 1e-10 at the sizes here."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import crinputs as ci
+from oracle import cr, cr_tqu, healpix
+from tests.gpu_helpers import rel, tc
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+MIXED_TOL = 1e-4
+
+
+def _m():
+    from paper_2306_15511_amd import crsht as m
+    return m
+
+
+def _problem(nside, lmax=None, te=0.3):
+    lmax = 3 * nside - 1 if lmax is None else lmax
+    wl = ci.workload_masked_t(nside, lmax, fwhm_arcmin=60.0 * 64 / nside, cfg=2)
+    z, phi = healpix.pixel_coords(nside)
+    nt = wl.ninv(z, phi)
+    P = cr_tqu.ProblemTQU(nside, lmax, ci.cl_tqu(lmax, wl.amp, te), wl.bl(), nt, nt / 2.0)
+    return wl, P, cr_tqu.CROperatorTQU(P)
+
+
+def _gpu_problem(m, P):
+    ninv = np.stack([P.ninv_t, P.ninv_p, P.ninv_p])
+    return m.Problem(np.ascontiguousarray(P.cl), P.bl, tc(ninv), P.lmin)
+
+
+def _alm3(rng, lmax, op):
+    return op.project(np.stack([ci.white_alm(rng, lmax) for _ in range(3)]))
+
+
+def _data(rng, op, P):
+    """d = Y B s + n for a draw s of the prior (3 maps)."""
+    npix = op.sht.npix
+    s = op._block(np.linalg.cholesky(_cov_blocks(P))[op.ls], _alm3(rng, P.lmax, op))
+    noise = rng.standard_normal((3, npix)) / np.sqrt(np.maximum(op._ninv(), 1e-30)) * (op._ninv() > 0)
+    return op.synth(op.b * op.project(s)) + noise
+
+
+def _cov_blocks(P):
+    C = np.zeros((P.lmax + 1, 3, 3))
+    C[:, 0, 0], C[:, 1, 1], C[:, 2, 2] = P.cl[0], P.cl[1], P.cl[2]
+    C[:, 0, 1] = C[:, 1, 0] = P.cl[3]
+    C[:2] = np.eye(3)   # unused modes (projected out)
+    return C
+
+
+def real_rel3(op, a, b):
+    d = a - b
+    return math.sqrt(max(op.dot(d, d), 0.0)) / math.sqrt(max(op.dot(b, b), 1e-300))
+
+
+@pytest.mark.parametrize("nside", [4, 8, 32])
+def test_tqu_synth_adjoint(nside):
+    m = _m()
+    print("case tqu transforms nside", nside, flush=True)
+    wl, P, op = _problem(nside)
+    plan = m.Plan(nside, P.lmax, nrhs_max=2, ncomp=3)
+    rng = np.random.default_rng(nside)
+    A = np.stack([_alm3(rng, P.lmax, op) for _ in range(2)])
+    maps = m.synth(plan, tc(A)).cpu().numpy()
+    assert maps.shape == (2, 3, op.sht.npix)
+    for c in range(2):
+        ref = op.synth(A[c])
+        for k in range(3):
+            assert rel(maps[c, k], ref[k]) < TOL, (c, k, rel(maps[c, k], ref[k]))
+    M = rng.standard_normal((2, 3, op.sht.npix))
+    got = m.adjoint(plan, tc(M)).cpu().numpy()
+    for c in range(2):
+        ref = op.adjoint(M[c])
+        for k in range(3):
+            assert rel(got[c, k], ref[k]) < TOL, (c, k, rel(got[c, k], ref[k]))
+
+
+@pytest.mark.parametrize("nside", [4, 8, 16])
+def test_tqu_precond_rhs_apply(nside):
+    m = _m()
+    print("case tqu operator nside", nside, flush=True)
+    wl, P, op = _problem(nside)
+    plan = m.Plan(nside, P.lmax, nrhs_max=2, ncomp=3)
+    gp = _gpu_problem(m, P)
+    assert rel(m.precond(plan, gp).cpu().numpy(), op.diag()) < TOL
+    rng = np.random.default_rng(7)
+    d = _data(rng, op, P)
+    w0 = np.stack([ci.white_alm(rng, P.lmax) for _ in range(3)])
+    w1 = rng.standard_normal((3, op.sht.npix))
+    for args in ((d, w0, w1), (d, None, None), (None, w0, None), (None, None, w1)):
+        ref = op.rhs(*args)
+        got = m.rhs(plan, gp, *[None if v is None else tc(v) for v in args]).cpu().numpy()[0]
+        assert real_rel3(op, got, ref) < TOL
+    X = np.stack([_alm3(rng, P.lmax, op) for _ in range(2)])
+    got = m.apply(plan, gp, tc(X)).cpu().numpy()
+    for c in range(2):
+        assert real_rel3(op, got[c], op.apply(X[c])) < TOL
+
+
+def test_tqu_solve_matches_oracle_pcg():
+    m = _m()
+    nside = 4
+    wl, P, op = _problem(nside, 11)
+    plan = m.Plan(nside, P.lmax, ncomp=3)
+    gp = _gpu_problem(m, P)
+    rng = np.random.default_rng(11)
+    d = _data(rng, op, P)
+    w0 = np.stack([ci.white_alm(rng, P.lmax) for _ in range(3)])
+    w1 = rng.standard_normal((3, op.sht.npix))
+    s, st = m.solve(plan, gp, tc(d), tc(w0), tc(w1), tol=1e-13, maxiter=5000)
+    assert st[0].status == 0 and st[0].rel_resid_true <= 1e-13
+    xo, info = cr.pcg(op, op.rhs(d, w0, w1), 1e-13, 5000)
+    assert info.converged
+    assert real_rel3(op, s.cpu().numpy()[0], xo) < TOL
+
+
+@pytest.mark.parametrize("nside", [16, 32])
+def test_tqu_solve_oracle_residual(nside):
+    m = _m()
+    print("case tqu solve nside", nside, flush=True)
+    wl, P, op = _problem(nside)
+    plan = m.Plan(nside, P.lmax, nrhs_max=2, ncomp=3)
+    gp = _gpu_problem(m, P)
+    rng = np.random.default_rng(nside + 1)
+    d = np.stack([_data(rng, op, P) for _ in range(2)])
+    w0 = np.stack([np.stack([ci.white_alm(rng, P.lmax) for _ in range(3)]) for _ in range(2)])
+    w1 = rng.standard_normal((2, 3, op.sht.npix))
+    s, st = m.solve(plan, gp, tc(d), tc(w0), tc(w1), nrhs=2, tol=1e-8, maxiter=20000)
+    for c in range(2):
+        b = op.rhs(d[c], w0[c], w1[c])
+        res = real_rel3(op, op.apply(s.cpu().numpy()[c]), b)
+        print("col", c, "iters", st[c].iters, "res", res, flush=True)
+        assert st[c].status == 0
+        assert res <= 1.5e-8
+        assert abs(res - st[c].rel_resid_true) < 1e-10
+
+
+@pytest.mark.parametrize("nside", [8, 32])
+def test_tqu_mixed_transforms(nside):
+    m = _m()
+    print("case tqu mixed transforms nside", nside, flush=True)
+    wl, P, op = _problem(nside)
+    plan = m.Plan(nside, P.lmax, ncomp=3)
+    rng = np.random.default_rng(3)
+    a = _alm3(rng, P.lmax, op)
+    got = m.synth(plan, tc(a), prec=m.CR_MIXED).cpu().numpy()
+    ref = op.synth(a)
+    errs = [rel(got[k], ref[k]) for k in range(3)]
+    M = rng.standard_normal((3, op.sht.npix))
+    ga = m.adjoint(plan, tc(M), prec=m.CR_MIXED).cpu().numpy()
+    ra = op.adjoint(M)
+    errs += [rel(ga[k], ra[k]) for k in range(3)]
+    print("mixed rel errors (T, Q, U maps; T, E, B alm)", errs, flush=True)
+    assert max(errs) < MIXED_TOL
+
+
+def test_tqu_mixed_solve_oracle_residual():
+    m = _m()
+    nside = 32
+    wl, P, op = _problem(nside)
+    plan = m.Plan(nside, P.lmax, ncomp=3)
+    gp = _gpu_problem(m, P)
+    rng = np.random.default_rng(5)
+    d = _data(rng, op, P)
+    w0 = np.stack([ci.white_alm(rng, P.lmax) for _ in range(3)])
+    w1 = rng.standard_normal((3, op.sht.npix))
+    s, st = m.solve(plan, gp, tc(d), tc(w0), tc(w1), tol=1e-6, maxiter=20000, prec=m.CR_MIXED)
+    b = op.rhs(d, w0, w1)
+    res = real_rel3(op, op.apply(s.cpu().numpy()[0]), b)
+    print("mixed tqu iters", st[0].iters, "refinements", st[0].refinements, "res", res, flush=True)
+    assert st[0].status == 0
+    assert res <= 1.05e-6
+    assert abs(res - st[0].rel_resid_true) <= 1e-9
+
+
+@pytest.mark.parametrize("nside", [8, 16])
+def test_tqu_grad_chi2(nside):
+    m = _m()
+    wl, P, op = _problem(nside)
+    plan = m.Plan(nside, P.lmax, nrhs_max=2, ncomp=3)
+    gp = _gpu_problem(m, P)
+    rng = np.random.default_rng(9)
+    d = np.stack([_data(rng, op, P) for _ in range(2)])
+    a = np.stack([_alm3(rng, P.lmax, op) for _ in range(2)])
+    g, chi2 = m.grad_chi2(plan, gp, tc(d), tc(a))
+    g = g.cpu().numpy()
+    n = op._ninv()
+    for c in range(2):
+        r = d[c] - op.synth(op.b * a[c])
+        ref_chi2 = float(np.sum(n * r * r))
+        ref_g = op.project(-2.0 * op.b * op.adjoint(n * r))
+        assert abs(chi2[c] - ref_chi2) <= 1e-10 * ref_chi2
+        assert real_rel3(op, g[c], ref_g) < TOL
+
+
+def test_tqu_rejects_unsupported():
+    m = _m()
+    wl, P, op = _problem(4, 11)
+    plan = m.Plan(4, 11, ncomp=3)
+    bad = m.Problem(np.ascontiguousarray(P.cl), P.bl, tc(np.stack([P.ninv_t] * 3)), 1)
+    with pytest.raises(m.CrshtError):
+        m.precond(plan, bad)
+    cl = np.array(P.cl)
+    cl[3, 5] = 2.0 * math.sqrt(cl[0, 5] * cl[1, 5])    # |TE| > sqrt(TT EE): not positive definite
+    with pytest.raises(m.CrshtError):
+        m.precond(plan, m.Problem(cl, P.bl, tc(np.stack([P.ninv_t] * 3)), 2))
