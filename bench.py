@@ -12,7 +12,10 @@ mixed-precision form (16 columns, bf16x3 MFMA Legendre steps inside PCG with
 FP64 vectors, scalars and residual replacement); `--prec f64` runs the plain
 FP64 form. Unless `--no-f64-compare` is given, one plain FP64 single-column
 solve of column 0 is timed as well (reported beside the headline, never as
-`value`). Inputs are resident on the GPU before timing starts.
+`value`). Inputs are resident on the GPU before timing starts. The timed steps
+replay each block of check_every PCG iterations as a captured HIP graph; the
+per-kernel launch times come from one extra step with HIP events around every
+launch of the tracked kernels.
 
 Prints one JSON line. --gpus N with N > 1 is refused: this build runs on one
 GPU.
@@ -61,38 +64,59 @@ def src_hash(rel: str) -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def cpu_baseline(wl, iters: int, iters_src: str):
+def cpu_baseline(wl, iters: int, iters_src: str, tqu: bool = False):
     """Oracle (numpy FP64) SHT pair on a bounded sample: the Legendre and
     azimuthal steps of one synthesis + adjoint restricted to every 16th ring,
-    scaled to the full ring count; solves/s = 1/(t_pair * iters)."""
+    scaled to the full ring count; solves/s = 1/(t_pair * iters). With tqu the
+    pair also carries the spin-2 part (W, X rows of oracle/spin2.py for E and
+    B, and the Q, U ring FFTs)."""
     from oracle import sht as osht
+    from oracle import spin2
     from oracle.legendre import lambda_rows
     import crinputs as ci
     S = osht.SHT(wl.nside, wl.lmax)
     R = S.rings
     nr = R.nrings
     sel = np.arange(0, nr, 16)
-    a = ci.white_alm(np.random.default_rng(1), wl.lmax)
-    x = np.random.default_rng(2).standard_normal(S.npix)
+    nmap = 3 if tqu else 1
+    a = [ci.white_alm(np.random.default_rng(1 + k), wl.lmax) for k in range(nmap)]
+    x = [np.random.default_rng(20 + k).standard_normal(S.npix) for k in range(nmap)]
     t0 = time.perf_counter()
     z, st = R.z[sel], R.sin_theta[sel]
-    F = np.zeros((S.mmax + 1, sel.size), dtype=np.complex128)
+    F = np.zeros((nmap, S.mmax + 1, sel.size), dtype=np.complex128)
     for l, lam in lambda_rows(S.lmax, S.mmax, z, st):
         top = lam.shape[0] - 1
-        F[:top + 1] += lam * a[S._idx(l, top)][:, None]
+        F[0, :top + 1] += lam * a[0][S._idx(l, top)][:, None]
+    if tqu:
+        for l, W, X in spin2.wx_rows(S.lmax, S.mmax, z, st):
+            if l < 2:
+                continue
+            top = W.shape[0] - 1
+            e, b = a[1][S._idx(l, top)][:, None], a[2][S._idx(l, top)][:, None]
+            F[1, :top + 1] -= W * e + 1j * X * b
+            F[2, :top + 1] -= W * b - 1j * X * e
     m = np.arange(S.mmax + 1)
     G = np.empty_like(F)
     for j, k in enumerate(sel):
         n, f0 = int(R.nphi[k]), int(R.first[k])
-        c = np.zeros(n, dtype=np.complex128)
-        np.add.at(c, m % n, np.where(m == 0, 1.0, 2.0) * F[:, j] * np.exp(1j * m * R.phi0[k]))
-        _ = (n * np.fft.ifft(c)).real
-        X = np.fft.fft(x[f0:f0 + n])
-        G[:, j] = np.exp(-1j * m * R.phi0[k]) * X[m % n]
-    out = np.zeros(S.nalm, dtype=np.complex128)
+        for q in range(nmap):
+            c = np.zeros(n, dtype=np.complex128)
+            np.add.at(c, m % n, np.where(m == 0, 1.0, 2.0) * F[q, :, j] * np.exp(1j * m * R.phi0[k]))
+            _ = (n * np.fft.ifft(c)).real
+            Xf = np.fft.fft(x[q][f0:f0 + n])
+            G[q, :, j] = np.exp(-1j * m * R.phi0[k]) * Xf[m % n]
+    out = np.zeros((nmap, S.nalm), dtype=np.complex128)
     for l, lam in lambda_rows(S.lmax, S.mmax, z, st):
         top = lam.shape[0] - 1
-        out[S._idx(l, top)] = np.sum(lam * G[:top + 1], axis=1)
+        out[0, S._idx(l, top)] = np.sum(lam * G[0, :top + 1], axis=1)
+    if tqu:
+        for l, W, X in spin2.wx_rows(S.lmax, S.mmax, z, st):
+            if l < 2:
+                continue
+            top = W.shape[0] - 1
+            i = S._idx(l, top)
+            out[1, i] = np.sum(-W * G[1, :top + 1] - 1j * X * G[2, :top + 1], axis=1)
+            out[2, i] = np.sum(1j * X * G[1, :top + 1] - W * G[2, :top + 1], axis=1)
     t = time.perf_counter() - t0
     t_pair = t * nr / sel.size
     cores = len(os.sched_getaffinity(0))
@@ -103,9 +127,9 @@ def cpu_baseline(wl, iters: int, iters_src: str):
     except Exception:
         pass
     return {"value": 1.0 / (t_pair * max(iters, 1)), "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": "numpy FP64 oracle SHT pair (Legendre + FFT synthesis and adjoint) on %d of %d rings "
+            "sample": "numpy FP64 oracle %sSHT pair (Legendre + FFT synthesis and adjoint) on %d of %d rings "
                       "(%.1f s), scaled to all rings: %.1f s per SHT pair; solves/s = 1/(s per pair x %d "
-                      "iterations, %s)" % (sel.size, nr, t, t_pair, iters, iters_src),
+                      "iterations, %s)" % ("T+Q+U " if tqu else "", sel.size, nr, t, t_pair, iters, iters_src),
             "sht_pairs_per_s": 1.0 / t_pair}
 
 
@@ -168,14 +192,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--nrhs", type=int, default=16)
+    ap.add_argument("--nrhs", type=int, default=None, help="columns per solve (default 16; 2 for --workload tqu)")
     ap.add_argument("--nside", type=int, default=512)
     ap.add_argument("--lmax", type=int, default=None)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--prec", choices=["f64", "mixed"], default="mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64-compare", action="store_true")
-    ap.add_argument("--workload", choices=["headline", "batched64"], default="headline")
+    ap.add_argument("--workload", choices=["headline", "tqu", "batched64"], default="headline")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported "
@@ -193,25 +217,44 @@ def main():
     lmax = 3 * nside - 1 if args.lmax is None else args.lmax
     wl = ci.workload_masked_t(nside, lmax, fwhm_arcmin=10.0, cfg=2)
     wl.tol = args.tol
-    R = args.nrhs
+    tqu = args.workload == "tqu"
+    nc = 3 if tqu else 1
+    R = args.nrhs if args.nrhs else (2 if tqu else 16)
     mixed = args.prec == "mixed"
     dev = torch.device("cuda:0")
-    plan = crsht.Plan(nside, lmax, nrhs_max=R)
+    plan = crsht.Plan(nside, lmax, nrhs_max=R, ncomp=nc)
     z, phi = plan.pixel_coords()
-    ninv = torch.from_numpy(wl.ninv(z, phi)).to(dev)
-    cl, bl = wl.cl(), wl.bl()
+    bl = wl.bl()
+    ls, _ = ci.alm_lm_arrays(lmax)
+    sig = wl.sigma_map(z, phi)
+    if tqu:
+        # T+Q+U: C^EE = 0.05 C^TT, C^BB = 0.005 C^TT, TE correlation 0.3;
+        # sigma_QU = sqrt(2) sigma_T with the same hits and mask
+        cl = ci.cl_tqu(lmax, wl.amp, 0.3)
+        nt = wl.ninv(z, phi)
+        ninv = torch.from_numpy(np.stack([nt, nt / 2.0, nt / 2.0])).to(dev)
+        A = np.stack([bl[ls] * ci.signal_alm_tqu(ci.rng_for(2, c, ci.STREAM_SIGNAL), cl, lmax) for c in range(R)])
+        noise = np.stack([np.stack([f * sig * ci.white_map(ci.rng_for(2, c, ci.STREAM_NOISE + 10 * k), wl.npix)
+                                    for k, f in enumerate((1.0, 2 ** 0.5, 2 ** 0.5))]) for c in range(R)])
+        w0 = np.stack([np.stack([ci.white_alm(ci.rng_for(2, c, ci.STREAM_W0 + 10 * k), lmax) for k in range(3)])
+                       for c in range(R)])
+        w1 = np.stack([np.stack([ci.white_map(ci.rng_for(2, c, ci.STREAM_W1 + 10 * k), wl.npix) for k in range(3)])
+                       for c in range(R)])
+    else:
+        cl = wl.cl()
+        ninv = torch.from_numpy(wl.ninv(z, phi)).to(dev)
+        A = np.stack([bl[ls] * ci.signal_alm(ci.rng_for(2, c, ci.STREAM_SIGNAL), cl, lmax) for c in range(R)])
+        noise = np.stack([sig * ci.white_map(ci.rng_for(2, c, ci.STREAM_NOISE), wl.npix) for c in range(R)])
+        w0 = np.stack([ci.white_alm(ci.rng_for(2, c, ci.STREAM_W0), lmax) for c in range(R)])
+        w1 = np.stack([ci.white_map(ci.rng_for(2, c, ci.STREAM_W1), wl.npix) for c in range(R)])
     prob = crsht.Problem(cl, bl, ninv, 2)
     # inputs: d = Y B a_true + n per column (synthesised on the GPU), w0, w1
-    ls, _ = ci.alm_lm_arrays(lmax)
-    A = np.stack([bl[ls] * ci.signal_alm(ci.rng_for(2, c, ci.STREAM_SIGNAL), cl, lmax) for c in range(R)])
     d = crsht.synth(plan, torch.from_numpy(A).to(dev))
-    noise = np.stack([wl.sigma_map(z, phi) * ci.white_map(ci.rng_for(2, c, ci.STREAM_NOISE), wl.npix)
-                      for c in range(R)])
     d += torch.from_numpy(noise).to(dev)
-    w0 = torch.from_numpy(np.stack([ci.white_alm(ci.rng_for(2, c, ci.STREAM_W0), lmax) for c in range(R)])).to(dev)
-    w1 = torch.from_numpy(np.stack([ci.white_map(ci.rng_for(2, c, ci.STREAM_W1), wl.npix)
-                                    for c in range(R)])).to(dev)
-    out = torch.empty((R, plan.nalm), dtype=torch.complex128, device=dev)
+    w0 = torch.from_numpy(w0).to(dev)
+    w1 = torch.from_numpy(w1).to(dev)
+    del A, noise
+    out = torch.empty(plan.alm_shape(R), dtype=torch.complex128, device=dev)
     torch.cuda.synchronize()
 
     prec = crsht.CR_MIXED if mixed else crsht.CR_F64
@@ -222,7 +265,7 @@ def main():
 
     f64_cmp = None
     if not args.no_f64_compare:
-        out1 = torch.empty((1, plan.nalm), dtype=torch.complex128, device=dev)
+        out1 = torch.empty(plan.alm_shape(1), dtype=torch.complex128, device=dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, st1 = crsht.solve(plan, prob, d[:1], w0[:1], w1[:1], nrhs=1, tol=wl.tol, maxiter=20000, out=out1,
@@ -238,7 +281,6 @@ def main():
         _, st = step()
         print("warmup: iters %s resid %s" % ([s.iters for s in st], ["%.2e" % s.rel_resid_true for s in st]),
               file=sys.stderr, flush=True)
-    crsht.timing_enable(plan, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
@@ -250,8 +292,13 @@ def main():
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # per-kernel launch times: one more (untimed) step with HIP events around
+    # every launch of the tracked kernels (direct launches, no graph replay)
+    crsht.timing_enable(plan, True)
+    _, st = step()
     tm = {k: crsht.timing_read(plan, k) for k in range(5)}
     crsht.timing_enable(plan, False)
+    print("kernel-timing step: iters %s" % [s.iters for s in st], file=sys.stderr, flush=True)
 
     solves = args.steps * R
     sps = solves / dt
@@ -261,23 +308,32 @@ def main():
     T = legendre_triples(nside, lmax, lmax)
     # Legendre sums of one column (E and O, complex; float2 in the mixed path)
     eo_bytes = 2 * nside * (lmax + 1) * 2 * (8 if mixed else 16)
-    groups = []
-    n = R
-    while n > 0:
-        groups.append(pick_nr(n))
-        n -= groups[-1]
+    # scalar Legendre columns per transform: a T+Q+U column is 9 in the
+    # synthesis and 7 in the adjoint; the ring pass sees nc maps per column
+    cs, ca = (9 * R, 7 * R) if tqu else (R, R)
+
+    def groups(n):
+        out = []
+        while n > 0:
+            out.append(pick_nr(n))
+            n -= out[-1]
+        return out
+
     kinfo = {
-        2: ("k_ring<RING_FUSED> (azimuthal FFT pass, N^-1 fused)", "hbm", R * 2 * eo_bytes + plan.npix * 8,
-            HBM_PEAK_GBS, "GB/s", "ring.hip"),
+        2: ("k_ring<RING_FUSED> (azimuthal FFT pass, N^-1 fused)", "hbm",
+            nc * R * 2 * eo_bytes + nc * plan.npix * 8, HBM_PEAK_GBS, "GB/s", "ring.hip"),
     }
     if mixed:
-        for kid, name in ((3, "k_synth_mfma (bf16x3 MFMA Legendre synthesis)"),
-                          (4, "k_adj_mfma (bf16x3 MFMA Legendre adjoint)")):
-            kinfo[kid] = (name, "mfma", 4 * min(R, 16) * T, BF16_MFMA_PEAK_TFLOPS, "TFLOP/s", "legendre_mfma.hip")
+        # average work per launch: columns go in launches of at most 16
+        kinfo[3] = ("k_synth_mfma (bf16x3 MFMA Legendre synthesis)", "mfma", 4 * T * cs / -(-cs // 16),
+                    BF16_MFMA_PEAK_TFLOPS, "TFLOP/s", "legendre_mfma.hip")
+        kinfo[4] = ("k_adj_mfma (bf16x3 MFMA Legendre adjoint)", "mfma", 4 * T * ca / -(-ca // 16),
+                    BF16_MFMA_PEAK_TFLOPS, "TFLOP/s", "legendre_mfma.hip")
     else:
-        kinfo[0] = ("k_legendre_synth (FP64 VALU)", "alu", sum((3 + 4 * g) * T for g in groups) / len(groups),
+        gs, ga = groups(cs), groups(ca)
+        kinfo[0] = ("k_legendre_synth (FP64 VALU)", "alu", sum((3 + 4 * g) * T for g in gs) / len(gs),
                     FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s", "legendre.hip")
-        kinfo[1] = ("k_legendre_adj (FP64 VALU, whole transform)", "alu", sum((3 + 4 * g) * T for g in groups),
+        kinfo[1] = ("k_legendre_adj (FP64 VALU, whole transform)", "alu", sum((3 + 4 * g) * T for g in ga),
                     FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s", "legendre.hip")
     roofs = {}
     for kid, (name, bound, work, peak, unit, src) in kinfo.items():
@@ -286,7 +342,7 @@ def main():
             continue
         avg = ms / nl * 1e-3
         achieved = work / avg / (1e9 if unit == "GB/s" else 1e12)
-        tr = TRAFFIC.get(name.split(" ")[0])
+        tr = None if tqu else TRAFFIC.get(name.split(" ")[0])
         traffic = None
         if tr is not None and tr["src"] == src_hash(src):
             traffic = tr["bytes"]
@@ -296,6 +352,8 @@ def main():
     dom = max(roofs, key=lambda k: roofs[k]["total_ms"])
     roof = dict(roofs[dom])
     roof["kernel"] = dom
+    what = ("T+Q+U (spin-0 and spin-2) constrained-realization PCG solve, C^EE = 0.05 C^TT, C^BB = 0.005 C^TT, "
+            "TE correlation 0.3, sigma_QU = sqrt(2) sigma_T" if tqu else "T-only constrained-realization PCG solve")
     res = {
         "metric": "constrained-realization CG solves/s at Nside=512, lmax=1535; SHT pairs/s",
         "value": sps,
@@ -309,11 +367,11 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16x3+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": "T-only constrained-realization PCG solve, Nside %d, lmax %d, hit-pattern noise, "
+        "config": {"workload": "%s, Nside %d, lmax %d, hit-pattern noise, "
                                "|b|<20deg mask, FWHM 10', true residual %g, %d columns per solve, %s"
-                               % (nside, lmax, wl.tol, R, "bf16x3 MFMA Legendre + FP64 vectors and residual "
+                               % (what, nside, lmax, wl.tol, R, "bf16x3 MFMA Legendre + FP64 vectors and residual "
                                   "replacement" if mixed else "FP64"),
-                   "nside": nside, "lmax": lmax, "nrhs": R, "tol": wl.tol,
+                   "nside": nside, "lmax": lmax, "nrhs": R, "ncomp": nc, "tol": wl.tol,
                    "precision": "CR_MIXED" if mixed else "CR_F64"},
         "sht_pairs_per_s": tot_iters / dt,
         "iters_per_solve": tot_iters / solves,
@@ -328,7 +386,7 @@ def main():
             it, src = f64_cmp["iters"], "the FP64 GPU solve's count for column 0"
         else:
             it, src = int(round(tot_iters / solves)), "the benchmarked solves' mean count"
-        res["cpu_baseline"] = cpu_baseline(wl, it, src)
+        res["cpu_baseline"] = cpu_baseline(wl, it, src, tqu)
     print(json.dumps(res))
     plan.close()
 

@@ -117,6 +117,20 @@ def signal_alm(rng: np.random.Generator, cl: np.ndarray, lmax: int, mmax: int | 
     return np.sqrt(np.clip(cl, 0.0, None))[ls] * white_alm(rng, lmax, mmax)
 
 
+def signal_alm_tqu(rng: np.random.Generator, cl4: np.ndarray, lmax: int) -> np.ndarray:
+    """(a_T, a_E, a_B) [3][nalm] drawn from the 3x3 blocks of cl4 = (TT, EE,
+    BB, TE): a_T = sqrt(TT) g1, a_E = TE/sqrt(TT) g1 + sqrt(EE - TE^2/TT) g2,
+    a_B = sqrt(BB) g3 with unit real-field draws g (0 where TT <= 0)."""
+    ls, _ = alm_lm_arrays(lmax)
+    tt, ee, bb, te = (np.asarray(c, dtype=np.float64) for c in cl4)
+    ok = tt > 0
+    st = np.sqrt(np.where(ok, tt, 0.0))
+    x = np.where(ok, te / np.where(ok, st, 1.0), 0.0)
+    y = np.sqrt(np.clip(ee - x * x, 0.0, None))
+    g = [white_alm(rng, lmax) for _ in range(3)]
+    return np.stack([st[ls] * g[0], x[ls] * g[0] + y[ls] * g[1], np.sqrt(np.clip(bb, 0.0, None))[ls] * g[2]])
+
+
 # --------------------------------------------------------------------------
 # Noise and mask patterns, given pixel coordinates (z = cos theta, phi)
 # --------------------------------------------------------------------------

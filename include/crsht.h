@@ -148,6 +148,11 @@ typedef struct {
                           has dropped by this factor (0 < inner_tol < 1, e.g. 1e-2); ignored for CR_F64 */
   int max_refine;      /* CR_MIXED: maximum number of FP64 residual replacements (0 = 1000) */
   int check_every;     /* iterations between host convergence checks (>= 1; 0 = 8) */
+  int use_graph;       /* 1: each block of check_every iterations is captured once as a HIP graph
+                          (plan-owned, re-captured when nrhs, ninv, tol, precision or the block
+                          length change) and replayed on `stream`; 0: every kernel is launched
+                          directly. Results are identical either way. Ignored while kernel timing
+                          is enabled. */
 } cr_opts;
 
 typedef struct {

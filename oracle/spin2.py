@@ -75,11 +75,12 @@ class PolSHT:
         self.nside, self.lmax, self.mmax = nside, lmax, self.s.mmax
         self.npix, self.nalm = self.s.npix, self.s.nalm
 
-    def spectra(self, aE: np.ndarray, aB: np.ndarray):
+    def spectra(self, aE: np.ndarray, aB: np.ndarray, ring_idx=None):
         R = self.s.rings
-        GQ = np.zeros((self.mmax + 1, R.nrings), dtype=np.complex128)
+        rows = np.arange(R.nrings) if ring_idx is None else np.asarray(list(ring_idx))
+        GQ = np.zeros((self.mmax + 1, rows.size), dtype=np.complex128)
         GU = np.zeros_like(GQ)
-        for l, W, X in wx_rows(self.lmax, self.mmax, R.z, R.sin_theta):
+        for l, W, X in wx_rows(self.lmax, self.mmax, R.z[rows], R.sin_theta[rows]):
             if l < 2:
                 continue
             top = W.shape[0] - 1
@@ -92,6 +93,26 @@ class PolSHT:
     def synth(self, aE: np.ndarray, aB: np.ndarray):
         GQ, GU = self.spectra(np.asarray(aE, dtype=np.complex128), np.asarray(aB, dtype=np.complex128))
         return self.s.phi_synth(GQ), self.s.phi_synth(GU)
+
+    def synth_rings(self, aE: np.ndarray, aB: np.ndarray, ring_idx) -> dict:
+        """(Q, U) pixel values on selected rings only (ring index -> pair of
+        arrays): the same spectra restricted to those rings, each synthesised
+        like a spin-0 field."""
+        R = self.s.rings
+        ring_idx = list(ring_idx)
+        GQ, GU = self.spectra(np.asarray(aE, dtype=np.complex128), np.asarray(aB, dtype=np.complex128), ring_idx)
+        m = np.arange(self.mmax + 1)
+        wm = np.where(m == 0, 1.0, 2.0)
+        out = {}
+        for j, k in enumerate(ring_idx):
+            n = int(R.nphi[k])
+            maps = []
+            for G in (GQ, GU):
+                c = np.zeros(n, dtype=np.complex128)
+                np.add.at(c, m % n, wm * G[:, j] * np.exp(1j * m * R.phi0[k]))
+                maps.append((n * np.fft.ifft(c)).real)
+            out[k] = tuple(maps)
+        return out
 
     def adjoint(self, Q: np.ndarray, U: np.ndarray):
         R = self.s.rings

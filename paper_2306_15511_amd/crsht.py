@@ -43,7 +43,8 @@ class _Problem(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("prec", ctypes.c_int),
-                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int), ("check_every", ctypes.c_int)]
+                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("use_graph", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -288,12 +289,13 @@ def apply(plan: Plan, prob: Problem, x: torch.Tensor, prec: int = CR_F64) -> tor
 
 def solve(plan: Plan, prob: Problem, d=None, w0=None, w1=None, rhs_vec=None, nrhs: int = 1, tol: float = 1e-6,
           maxiter: int = 10000, prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 50,
-          check_every: int = 8, out: torch.Tensor | None = None):
-    """Returns (s [nrhs, nalm] complex128 ([nrhs, 3, nalm] for ncomp = 3), [Stats])."""
+          check_every: int = 8, out: torch.Tensor | None = None, use_graph: bool = True):
+    """Returns (s [nrhs, nalm] complex128 ([nrhs, 3, nalm] for ncomp = 3), [Stats]).
+    use_graph: replay each block of check_every iterations as a captured HIP graph."""
     if out is None:
         out = torch.empty(plan.alm_shape(nrhs), dtype=torch.complex128, device=prob.ninv.device)
     p = prob._c()
-    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every)
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every, int(use_graph))
     st = (_Stats * nrhs)()
     _check(_lib.cr_solve(plan.handle, ctypes.byref(p), nrhs, _ptr(d), _ptr(w0), _ptr(w1), _ptr(rhs_vec), _ptr(out),
                          ctypes.byref(o), st, _stream()), "cr_solve")
@@ -302,7 +304,7 @@ def solve(plan: Plan, prob: Problem, d=None, w0=None, w1=None, rhs_vec=None, nrh
 
 def solve_batched(plans, probs, d=None, w0=None, w1=None, tol: float = 1e-6, maxiter: int = 20000,
                   prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 0, check_every: int = 16,
-                  out=None):
+                  out=None, use_graph: bool = True):
     """Independent single-column problems (own plan each). d, w0, w1: lists of
     tensors (or None). Returns (list of s [nalm] complex128, [Stats])."""
     n = len(plans)
@@ -320,7 +322,7 @@ def solve_batched(plans, probs, d=None, w0=None, w1=None, tol: float = 1e-6, max
 
     hp = VP(*[pl.handle.value for pl in plans])
     pa = (_Problem * n)(*[pr._c() for pr in probs])
-    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every)
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every, int(use_graph))
     st = (_Stats * n)()
     _check(_lib.cr_solve_batched(hp, pa, n, arr(d), arr(w0), arr(w1), VP(*[_ptr(t).value for t in out]),
                                  ctypes.byref(o), st, _stream()), "cr_solve_batched")
@@ -355,11 +357,12 @@ class StepResult:
 
 def joint_step(plan: Plan, fid: Problem, d: torch.Tensor, chain: Chain, xi: float, u: float, w0: torch.Tensor,
                w1: torch.Tensor, sigma_lnq: float = 0.02, tol: float = 1e-6, maxiter: int = 10000,
-               prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 50) -> StepResult:
+               prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 50,
+               use_graph: bool = True) -> StepResult:
     p = fid._c()
     c = _Chain(chain.q, chain.lnpi, _ptr(chain.ahat), _ptr(chain.fhat))
     dr = _Draws(xi, u, _ptr(w0), _ptr(w1), sigma_lnq)
-    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, 8)
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, 8, int(use_graph))
     r = _StepOut()
     _check(_lib.joint_cl_step(plan.handle, ctypes.byref(p), _ptr(d), ctypes.byref(c), ctypes.byref(dr),
                               ctypes.byref(o), ctypes.byref(r), _stream()), "joint_cl_step")
@@ -412,7 +415,8 @@ def grad_chi2(plan: Plan, prob: Problem, d: torch.Tensor, a: torch.Tensor):
 
 
 def grad_lnpi(plan: Plan, prob: Problem, d: torch.Tensor, w0, w1, edges, tol: float = 1e-10, maxiter: int = 20000,
-              prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 0, check_every: int = 8):
+              prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 0, check_every: int = 8,
+              use_graph: bool = True):
     """(dlnpi/dtheta [nbins] numpy, ln pi, [Stats x 3]) for per-bin log-amplitudes
     of C_l on [edges[k], edges[k+1])."""
     import numpy as np
@@ -422,7 +426,7 @@ def grad_lnpi(plan: Plan, prob: Problem, d: torch.Tensor, w0, w1, edges, tol: fl
     v = ctypes.c_double()
     st = (_Stats * 3)()
     p = prob._c()
-    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every)
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every, int(use_graph))
     _check(_lib.cr_grad_lnpi(plan.handle, ctypes.byref(p), _ptr(d), _ptr(w0), _ptr(w1), nb,
                              e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(o),
                              g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(v), st, _stream()),

@@ -279,6 +279,37 @@ int adjoint_f64(const crsht_plan* P, int nrhs, const double* map, double2* alm, 
   return CR_OK;
 }
 
+// Runs body(stream) -- a fixed sequence of kernel launches -- on s. With
+// use_graph the sequence is captured once on the plan's capture stream into a
+// HIP graph (kept with its key) and replayed on s; a different key
+// re-captures. Kernel timing (per-launch events) forces direct launches.
+template <class F>
+int run_block(const crsht_plan* Pc, const GraphKey& key, bool use_graph, hipStream_t s, F body) {
+  crsht_plan* P = const_cast<crsht_plan*>(Pc);
+  if (!use_graph || P->timing.on || !P->cap_stream) return body(s);
+  if (!(P->graph_exec && P->graph_key == key)) {
+    if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
+    P->graph_exec = nullptr;
+    P->graph_key = GraphKey();
+    CR_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = body(P->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(P->cap_stream, &g);
+    if (rc != CR_OK || e != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc != CR_OK ? rc : CR_EDEVICE;
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return CR_EDEVICE;
+    P->graph_exec = ex;
+    P->graph_key = key;
+  }
+  CR_TRY(hipGraphLaunch(P->graph_exec, s));
+  return CR_OK;
+}
+
 int read_scalars(const crsht_plan* P, int nrhs, hipStream_t s) {
   CR_TRY(hipMemcpyAsync(P->w.host_scal, P->w.scal, (size_t)nrhs * kScalSlots * sizeof(double),
                         hipMemcpyDeviceToHost, s));
@@ -320,7 +351,7 @@ int true_residual(const crsht_plan* P, int nrhs, const double* ninv, const doubl
 // relative residuals. iters[] receives the iterations per column.
 int pcg_run(const crsht_plan* P, int nrhs, const double* ninv, const double2* b, double tol, int maxiter,
             int check_every, bool mixed, bool verify, std::vector<int>& iters, std::vector<double>& rel,
-            std::vector<int>& broke, hipStream_t s) {
+            std::vector<int>& broke, hipStream_t s, bool use_graph = false) {
   const int64_t na = vlen(P);
   const int nb = vec_reduce_blocks(P);
   Workspace const& w = P->w;
@@ -337,13 +368,22 @@ int pcg_run(const crsht_plan* P, int nrhs, const double* ninv, const double2* b,
     for (int c = 0; c < nrhs; ++c) all_done &= P->w.host_scal[c * kScalSlots + S_DONE] != 0.0;
     if (!all_done && it < maxiter) {
       const int n = std::min(check_every, maxiter - it);
-      for (int k = 0; k < n; ++k) {
-        CR_CHECK(operator_core(P, nrhs, w.cg_p, w.alm_a, ninv, w.cg_q, s, mixed));
-        CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, s));
-        CR_TRY(launch_cg_update(P, nrhs, w.cg_x, w.cg_r, w.cg_z, w.cg_p, w.cg_q, s));
-        CR_TRY(launch_cg_scalars(P, nrhs, 2, nb, tol, 0, s));
-        CR_TRY(launch_cg_pupdate(P, nrhs, w.cg_z, w.cg_p, w.alm_a, s));
-      }
+      GraphKey key;
+      key.kind = mixed ? 2 : 0;
+      key.nrhs = nrhs;
+      key.n = n;
+      key.ninv = ninv;
+      key.tol = tol;
+      CR_CHECK(run_block(P, key, use_graph, s, [&](hipStream_t q) -> int {
+        for (int k = 0; k < n; ++k) {
+          CR_CHECK(operator_core(P, nrhs, w.cg_p, w.alm_a, ninv, w.cg_q, q, mixed));
+          CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, q));
+          CR_TRY(launch_cg_update(P, nrhs, w.cg_x, w.cg_r, w.cg_z, w.cg_p, w.cg_q, q));
+          CR_TRY(launch_cg_scalars(P, nrhs, 2, nb, tol, 0, q));
+          CR_TRY(launch_cg_pupdate(P, nrhs, w.cg_z, w.cg_p, w.alm_a, q));
+        }
+        return CR_OK;
+      }));
       it += n;
       CR_CHECK(read_scalars(P, nrhs, s));
       continue;
@@ -476,13 +516,24 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
       break;
     }
     const int n = std::min(every, o->maxiter - it);
-    for (int k = 0; k < n; ++k) {
-      CR_CHECK(operator_core_cg(P, nrhs, pending, ninv, w.cg_q, s));
-      CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, s));
-      CR_TRY(launch_cg_update(P, nrhs, w.cg_x, w.cg_r, w.cg_z, w.cg_p, w.cg_q, s));
-      CR_TRY(launch_cg_scalars(P, nrhs, 2, nb, tol, 0, s));
-      pending = true;
-    }
+    GraphKey key;
+    key.kind = 1;
+    key.nrhs = nrhs;
+    key.n = n;
+    key.first_update = pending ? 1 : 0;
+    key.ninv = ninv;
+    key.tol = tol;
+    const bool first = pending;
+    CR_CHECK(run_block(P, key, o->use_graph != 0, s, [&](hipStream_t q) -> int {
+      for (int k = 0; k < n; ++k) {
+        CR_CHECK(operator_core_cg(P, nrhs, k > 0 || first, ninv, w.cg_q, q));
+        CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, q));
+        CR_TRY(launch_cg_update(P, nrhs, w.cg_x, w.cg_r, w.cg_z, w.cg_p, w.cg_q, q));
+        CR_TRY(launch_cg_scalars(P, nrhs, 2, nb, tol, 0, q));
+      }
+      return CR_OK;
+    }));
+    pending = true;
     it += n;
     CR_CHECK(read_scalars(P, nrhs, s));
   }
@@ -515,7 +566,7 @@ int solve_core(const crsht_plan* P, const cr_problem* prob, double q, int nrhs, 
     CR_CHECK(solve_refined(P, nrhs, prob->ninv, opts, iters, refine, rel, broke, s));
   } else {
     CR_CHECK(pcg_run(P, nrhs, prob->ninv, P->w.cg_b, opts->tol, opts->maxiter, every, false, true, iters, rel, broke,
-                     s));
+                     s, opts->use_graph != 0));
     refine.assign(nrhs, 0);
   }
   fill_stats(nrhs, opts->tol, iters, refine, rel, broke, stats);

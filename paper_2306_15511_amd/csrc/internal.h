@@ -113,6 +113,7 @@ struct Workspace {
 constexpr int kScalSlots = 16;
 constexpr int kBinSlices = 16;   // m slices per multipole bin in the gradient reductions
 constexpr int kMixedCols = 32;   // MFMA N: 16 right-hand sides (re, im) per column group
+constexpr int kMaxGroups = 2;    // column groups sharing one recurrence pass of an MFMA kernel launch
 // slots of the per-column scalar block
 enum ScalSlot {
   S_RZ = 0,      // <r, z>
@@ -146,8 +147,27 @@ struct Timing {
 
 }  // namespace crsht
 
+namespace crsht {
+// identity of a captured PCG iteration block: replayed only for the same
+// launch sequence and arguments
+struct GraphKey {
+  int kind = -1;            // 0: FP64 PCG block, 1: mixed PCG block
+  int nrhs = 0, n = 0;      // columns, iterations in the block
+  int first_update = 0;     // mixed: the block starts with a pending direction update
+  const void* ninv = nullptr;
+  double tol = 0.0;
+  bool operator==(const GraphKey& o) const {
+    return kind == o.kind && nrhs == o.nrhs && n == o.n && first_update == o.first_update && ninv == o.ninv &&
+           tol == o.tol;
+  }
+};
+}  // namespace crsht
+
 struct crsht_plan {
   crsht::Geometry g;
+  hipStream_t cap_stream = nullptr;     // stream used only to capture iteration blocks
+  hipGraphExec_t graph_exec = nullptr;  // last captured block
+  crsht::GraphKey graph_key;
   int ncomp = 1;
   int nrhs_max = 1;
   int device = 0;
@@ -221,6 +241,8 @@ struct RingCols {
 hipError_t launch_ring(const crsht_plan* P, int nrhs, RingMode mode, const void* eo, double* map,
                        const double* ninv, void* geo, bool f32, hipStream_t s, RingCols cols = RingCols());
 void ring_classes(const std::vector<int>& fft_len, std::vector<RingClass>& cls, std::vector<int>& pairs);
+// plan set-up: allow the dynamic LDS of the ring kernels the plan's classes need
+hipError_t ring_prepare(const crsht_plan* P);
 size_t ring_lds_bytes(const crsht_plan* P, bool f32);
 
 // ---- spin-2 part of T+Q+U plans (pol.hip) ----

@@ -83,6 +83,10 @@ void free_plan_memory(crsht_plan* P) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (P->w.host_scal) (void)hipHostFree(P->w.host_scal);
+  if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
+  if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+  P->graph_exec = nullptr;
+  P->cap_stream = nullptr;
 }
 
 }  // namespace
@@ -260,6 +264,7 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int ncomp, i
     std::vector<int> rp;
     crsht::ring_classes(pfft, P->ring_cls, rp);
     if ((rc = upload(&P->t.ring_pairs, rp, total))) return rc;
+    if (crsht::ring_prepare(P) != hipSuccess) return CR_EDEVICE;
   }
   if ((rc = upload(&P->t.rec_alpha, alpha, total))) return rc;
   if ((rc = upload(&P->t.rec_kappa, kappa, total))) return rc;
@@ -344,6 +349,10 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int ncomp, i
     return CR_ENOMEM;
   }
   if (hipMemset(w.scal, 0, R * crsht::kScalSlots * sizeof(double)) != hipSuccess) return CR_EDEVICE;
+  if (hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    P->cap_stream = nullptr;
+    return CR_EDEVICE;
+  }
   return CR_OK;
 }
 

@@ -555,9 +555,6 @@ hipError_t ring_launch(const crsht_plan* P, int nrhs, const V* eo, double* map, 
     const unsigned nb = (unsigned)((items + 7) / 8 * 8);
 #define CRSHT_RING_LAUNCH(NT)                                                                                   \
   do {                                                                                                          \
-    if (lds > 65536)                                                                                            \
-      (void)hipFuncSetAttribute((const void*)k_ring<V, MODE, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,   \
-                                (int)lds);                                                                      \
     hipLaunchKernelGGL((k_ring<V, MODE, NT>), dim3(nb), dim3(nt), lds, s, P->t, g.nside, g.mmax, g.fft_max,      \
                        P->t.ring_pairs + rc.off, rc.count, nrhs, rc.L, tw, chirp, kern, eo, stride, map,         \
                        (int64_t)g.npix, ninv, geo, stride, cols);                                               \
@@ -582,7 +579,30 @@ hipError_t ring_mode(const crsht_plan* P, int nrhs, RingMode mode, const V* eo, 
   return ring_launch<V, RING_FUSED>(P, nrhs, eo, map, ninv, geo, tw, chirp, kern, cols, s);
 }
 
+// dynamic LDS above 64 KiB must be allowed per kernel before launches
+template <class V, int MODE>
+hipError_t ring_allow_lds(const crsht_plan* P) {
+  for (const RingClass& rc : P->ring_cls) {
+    const size_t lds = ring_lds<V>(rc.L);
+    if (lds <= 65536) continue;
+    const void* f = ring_threads(rc.L) <= 512 ? (const void*)k_ring<V, MODE, 512> : (const void*)k_ring<V, MODE, 1024>;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 }  // namespace
+
+hipError_t ring_prepare(const crsht_plan* P) {
+  hipError_t e;
+  if ((e = ring_allow_lds<float2, RING_SYNTH>(P)) != hipSuccess) return e;
+  if ((e = ring_allow_lds<float2, RING_ADJOINT>(P)) != hipSuccess) return e;
+  if ((e = ring_allow_lds<float2, RING_FUSED>(P)) != hipSuccess) return e;
+  if ((e = ring_allow_lds<double2, RING_SYNTH>(P)) != hipSuccess) return e;
+  if ((e = ring_allow_lds<double2, RING_ADJOINT>(P)) != hipSuccess) return e;
+  return ring_allow_lds<double2, RING_FUSED>(P);
+}
 
 // classes of ring pairs by FFT length: pairs with L <= 512 share one class,
 // every larger power of two has its own

@@ -217,3 +217,62 @@ def test_tqu_rejects_unsupported():
     cl[3, 5] = 2.0 * math.sqrt(cl[0, 5] * cl[1, 5])    # |TE| > sqrt(TT EE): not positive definite
     with pytest.raises(m.CrshtError):
         m.precond(plan, m.Problem(cl, P.bl, tc(np.stack([P.ninv_t] * 3)), 2))
+
+
+def test_tqu_nside128_full_maps():
+    m = _m()
+    nside = 128
+    print("case tqu nside128", flush=True)
+    wl, P, op = _problem(nside)
+    plan = m.Plan(nside, P.lmax, ncomp=3)
+    rng = np.random.default_rng(128)
+    a = _alm3(rng, P.lmax, op)
+    got = m.synth(plan, tc(a)).cpu().numpy()
+    ref = op.synth(a)
+    errs = [rel(got[k], ref[k]) for k in range(3)]
+    gm = m.synth(plan, tc(a), prec=m.CR_MIXED).cpu().numpy()
+    errs_m = [rel(gm[k], ref[k]) for k in range(3)]
+    M = rng.standard_normal((3, op.sht.npix))
+    ga = m.adjoint(plan, tc(M)).cpu().numpy()
+    ra = op.adjoint(M)
+    errs += [rel(ga[k], ra[k]) for k in range(3)]
+    gam = m.adjoint(plan, tc(M), prec=m.CR_MIXED).cpu().numpy()
+    errs_m += [rel(gam[k], ra[k]) for k in range(3)]
+    print("fp64", errs, "mixed", errs_m, flush=True)
+    assert max(errs) < TOL
+    assert max(errs_m) < MIXED_TOL
+
+
+def test_tqu_nside512_sampled_rings_and_adjointness():
+    # the T+Q+U benchmark size: sampled rings of Q and U against the oracle,
+    # adjointness of the three-component transform pair
+    m = _m()
+    from oracle import spin2
+    nside, lmax = 512, 1535
+    print("case tqu nside512", flush=True)
+    plan = m.Plan(nside, lmax, ncomp=3)
+    pol = spin2.PolSHT(nside, lmax)
+    rng = np.random.default_rng(512)
+    ls, ms = ci.alm_lm_arrays(lmax)
+    a = np.stack([ci.white_alm(rng, lmax) for _ in range(3)])
+    a[:, ls < 2] = 0.0
+    a[:, ms == 0] = a[:, ms == 0].real
+    got = m.synth(plan, tc(a)).cpu().numpy()
+    gm = m.synth(plan, tc(a), prec=m.CR_MIXED).cpu().numpy()
+    rings = [0, 1, 2, 37, 300, 511, 512, 900, 1023, 1500, 2045, 2046]
+    ref = pol.synth_rings(a[1], a[2], rings)
+    R = pol.s.rings
+    worst_m = 0.0
+    for k in rings:
+        f, n = int(R.first[k]), int(R.nphi[k])
+        for q in range(2):
+            e = rel(got[1 + q, f:f + n], ref[k][q])
+            assert e < TOL, (k, q, e)
+            worst_m = max(worst_m, rel(gm[1 + q, f:f + n], ref[k][q]))
+    print("mixed worst sampled-ring rel error", worst_m, flush=True)
+    y = rng.standard_normal((3, pol.npix))
+    ya = m.adjoint(plan, tc(y)).cpu().numpy()
+    lhs = float(np.sum(got * y))
+    from oracle.sht import dot
+    rhs = sum(dot(a[k], ya[k], lmax, lmax) for k in range(3))
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(got) * np.linalg.norm(y)

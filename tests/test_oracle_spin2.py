@@ -110,3 +110,18 @@ def test_axisymmetric_e_and_b_modes():
     assert np.max(np.abs(U)) < 1e-13 * np.max(np.abs(Q))
     Q, U = P.synth(np.zeros_like(a0), a0)
     assert np.max(np.abs(Q)) < 1e-13 * np.max(np.abs(U))
+
+
+def test_synth_rings_equals_full_synthesis():
+    nside, lmax = 8, 23
+    P = spin2.PolSHT(nside, lmax)
+    rng = np.random.default_rng(4)
+    aE, aB = _proj(ci.white_alm(rng, lmax), lmax), _proj(ci.white_alm(rng, lmax), lmax)
+    Q, U = P.synth(aE, aB)
+    rings = [0, 3, 14, 15, 16, 30]
+    got = P.synth_rings(aE, aB, rings)
+    R = P.s.rings
+    for k in rings:
+        f, n = int(R.first[k]), int(R.nphi[k])
+        assert np.allclose(got[k][0], Q[f:f + n], rtol=0, atol=1e-13 * np.abs(Q).max())
+        assert np.allclose(got[k][1], U[f:f + n], rtol=0, atol=1e-13 * np.abs(U).max())
