@@ -113,7 +113,8 @@ struct Workspace {
 constexpr int kScalSlots = 16;
 constexpr int kBinSlices = 16;   // m slices per multipole bin in the gradient reductions
 constexpr int kMixedCols = 32;   // MFMA N: 16 right-hand sides (re, im) per column group
-constexpr int kMaxGroups = 2;    // column groups sharing one recurrence pass of an MFMA kernel launch
+constexpr int kMaxGroups = 2;    // column groups sharing one recurrence pass of an MFMA synthesis launch
+constexpr int kAdjGroups = 1;    // column groups per MFMA adjoint launch
 // slots of the per-column scalar block
 enum ScalSlot {
   S_RZ = 0,      // <r, z>

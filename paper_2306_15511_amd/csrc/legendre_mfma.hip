@@ -58,6 +58,33 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
+// 32 consecutive doubles at a wave-uniform address (scalar loads)
+__device__ __forceinline__ void load_alpha32(double* dst, const double* __restrict__ alpha, int64_t idx) {
+  const double* __restrict__ p = alpha + __builtin_amdgcn_readfirstlane((int)idx);
+#pragma unroll
+  for (int s = 0; s < kSynChunk; ++s) dst[s] = p[s];
+}
+
+// bf16 hi / lo vectors of x[2 v + q], v = 0..7 (one parity of 16 steps):
+// hi = RNE(x) converted two at a time, its float value recovered from the
+// packed bits, lo = RNE(x - hi), also two at a time
+__device__ __forceinline__ void split8(const float* x, int q, bf16x8& hi, bf16x8& lo) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 h4, l4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float a = x[2 * (2 * i) + q], b = x[2 * (2 * i + 1) + q];
+    const unsigned hp = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){a, b}, bf16x2));
+    const float ha = __uint_as_float(hp << 16), hb = __uint_as_float(hp & 0xffff0000u);
+    h4[i] = hp;
+    l4[i] = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){a - ha, b - hb}, bf16x2));
+  }
+  hi = __builtin_bit_cast(bf16x8, h4);
+  lo = __builtin_bit_cast(bf16x8, l4);
+}
+
 // v_permlane32_swap per dword: t0 = (lanes 0-31: k0 own, lanes 32-63: k1 of
 // lane - 32), t1 = (lanes 0-31: k0 of lane + 32, lanes 32-63: k1 own)
 // (lane layout checked on the device)
@@ -122,15 +149,15 @@ __global__ __launch_bounds__(256) void k_checkpoints(int lmax, int mmax, int npa
 __global__ __launch_bounds__(64) void k_prep_synth(int lmax, int nrhs, const int64_t* __restrict__ mstart,
                                                    const int64_t* __restrict__ cstart, const double2* __restrict__ alm,
                                                    int64_t alm_stride, const double* __restrict__ f,
-                                                   bf16x8* __restrict__ ab) {
-  const int m = blockIdx.y, c = blockIdx.x;
+                                                   bf16x8* __restrict__ ab, int64_t ab_gstride) {
+  const int m = blockIdx.y, c = blockIdx.x, grp = blockIdx.z;   // group grp: right-hand sides 16 grp ..
   const int nsteps = lmax - m + 1;
   if (c * kSynChunk >= nsteps) return;
   const int lane = threadIdx.x;
   const int j = lane & 31, kg = lane >> 5;
-  const int rhs = j >> 1, comp = j & 1;
+  const int rhs = 16 * grp + (j >> 1), comp = j & 1;
   const int64_t base = mstart[m];
-  bf16x8* dst = ab + (size_t)(cstart[m] + c) * 4 * 64;
+  bf16x8* dst = ab + grp * ab_gstride + (size_t)(cstart[m] + c) * 4 * 64;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     bf16x8 hi, lo;
@@ -161,9 +188,14 @@ __global__ __launch_bounds__(64) void k_pupdate_prep(int lmax, int nrhs, int64_t
                                                      const int64_t* __restrict__ cstart, const double* __restrict__ bk,
                                                      const double2* __restrict__ z, double2* __restrict__ p,
                                                      const double* __restrict__ scal, int update,
-                                                     bf16x8* __restrict__ ab) {
+                                                     bf16x8* __restrict__ ab, int64_t ab_gstride) {
   __shared__ __attribute__((aligned(16))) float st_lds[2][16][2][16];
-  const int m = blockIdx.y, c = blockIdx.x;
+  const int m = blockIdx.y, c = blockIdx.x, grp = blockIdx.z;   // group grp: right-hand sides 16 grp ..
+  nrhs -= 16 * grp;
+  z += (int64_t)16 * grp * nalm;
+  p += (int64_t)16 * grp * nalm;
+  scal += 16 * grp * kScalSlots;
+  ab += grp * ab_gstride;
   const int nsteps = lmax - m + 1;
   if (c * kSynChunk >= nsteps) return;
   const int lane = threadIdx.x;
@@ -220,13 +252,14 @@ __global__ __launch_bounds__(64) void k_pupdate_prep(int lmax, int nrhs, int64_t
 // steps apart) to an LDS tile [pair][k], then the wavefront multiplies the
 // two 32-pair M tiles by the chunk's ab tiles. Chunks before the first live
 // group of the 64 pairs are skipped.
+template <int NG>
 __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npairs, int nrhs,
                                                    const double* __restrict__ pair_z, const double* __restrict__ alpha,
                                                    const int* __restrict__ lst_g, const double2* __restrict__ lst_s,
                                                    const int64_t* __restrict__ mstart,
                                                    const int64_t* __restrict__ cstart,
-                                                   const bf16x8* __restrict__ ab, float2* __restrict__ eo,
-                                                   int64_t eo_stride) {
+                                                   const bf16x8* __restrict__ ab, int64_t ab_gstride,
+                                                   float2* __restrict__ eo, int64_t eo_stride) {
   const int npb = (npairs + 63) / 64;
   const int q8 = blockIdx.x >> 3;
   const int m = xcd_m(q8 / npb, blockIdx.x & 7), pb = q8 % npb;
@@ -239,38 +272,37 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
   const double z = pair_z[pp];
   const int gs = valid ? lst_g[o] : kNever;
   const double2 s0 = lst_s[o];
-  const int gmin = wave_min(gs);
+  const int gmin = __builtin_amdgcn_readfirstlane(wave_min(gs));   // wave-uniform: scalar loop control
   const int64_t base = mstart[m];
   const int nsteps = lmax - m + 1;
 
-  f32x16 dE0 = {}, dE1 = {}, dO0 = {}, dO1 = {};
+  f32x16 dE0[NG], dE1[NG], dO0[NG], dO1[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) dE0[g] = dE1[g] = dO0[g] = dO1[g] = f32x16{};
   if (gmin != kNever) {
     const int nch = (nsteps + kSynChunk - 1) / kSynChunk;
     double v0 = 0.0, v1 = 0.0;
     const bf16x8* abm = ab + (size_t)cstart[m] * 4 * 64 + lane;
     const int cfirst = (gmin * kGroup) / kSynChunk;
-    // operands are loaded one chunk ahead (their latency overlaps a chunk)
-    bf16x8 nEh = abm[(size_t)cfirst * 256 + 0], nEl = abm[(size_t)cfirst * 256 + 64];
-    bf16x8 nOh = abm[(size_t)cfirst * 256 + 128], nOl = abm[(size_t)cfirst * 256 + 192];
     for (int c = cfirst; c < nch; ++c) {
-      const bf16x8 bEh = nEh, bEl = nEl, bOh = nOh, bOl = nOl;
-      if (c + 1 < nch) {
-        const bf16x8* src = abm + (size_t)(c + 1) * 256;
-        nEh = src[0];
-        nEl = src[64];
-        nOh = src[128];
-        nOl = src[192];
+      // operands of this chunk, consumed after the recurrence (which hides
+      // their latency)
+      bf16x8 bEh[NG], bEl[NG], bOh[NG], bOl[NG];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const bf16x8* src = abm + g * ab_gstride + (size_t)c * 256;
+        bEh[g] = src[0];
+        bEl[g] = src[64];
+        bOh[g] = src[128];
+        bOl[g] = src[192];
       }
-      // recurrence over the chunk: alpha is wave-uniform (scalar loads), the
-      // start state is injected by selects at the 16-step group boundaries
       const int st0 = c * kSynChunk;
-      const double* __restrict__ ac = alpha + __builtin_amdgcn_readfirstlane((int)(base + st0));
       float mu32[kSynChunk];
       if (st0 + kSynChunk <= nsteps) {
-        // all 32 scalar loads issued before the first use (one wait per chunk)
+        // alpha is wave-uniform: all 32 scalar loads issued before the first
+        // use (one wait per chunk)
         double a[kSynChunk];
-#pragma unroll
-        for (int s = 0; s < kSynChunk; ++s) a[s] = ac[s];
+        load_alpha32(a, alpha, base + st0);
 #pragma unroll
         for (int s = 0; s < kSynChunk; ++s) {
           if (s % kGroup == 0) {
@@ -284,6 +316,7 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
           mu32[s] = to_f32(mu);
         }
       } else {
+        const double* __restrict__ ac = alpha + __builtin_amdgcn_readfirstlane((int)(base + st0));
 #pragma unroll
         for (int s = 0; s < kSynChunk; ++s) {
           if (s % kGroup == 0) {
@@ -302,17 +335,10 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
       }
       bf16x8 eh[2], el[2], oh[2], ol[2];
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int v = 0; v < 8; ++v) {
-          __bf16 a, b;
-          split_bf16(mu32[2 * (8 * h + v)], a, b);
-          eh[h][v] = a;
-          el[h][v] = b;
-          split_bf16(mu32[2 * (8 * h + v) + 1], a, b);
-          oh[h][v] = a;
-          ol[h][v] = b;
-        }
+      for (int h = 0; h < 2; ++h) {
+        split8(mu32 + 16 * h, 0, eh[h], el[h]);
+        split8(mu32 + 16 * h, 1, oh[h], ol[h]);
+      }
       // A fragments (lane row + 32 kg holds A[row][8 kg .. 8 kg + 7] of M tile t,
       // pairs 32 t + row): lane p owns all 16 k of its pair, so one
       // permlane32 swap of (k 0..7, k 8..15) gives both tiles' fragments
@@ -321,26 +347,33 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
       swap_halves(el[0], el[1], aEl0, aEl1);
       swap_halves(oh[0], oh[1], aOh0, aOh1);
       swap_halves(ol[0], ol[1], aOl0, aOl1);
-      dE0 = mfma3(aEh0, aEl0, bEh, bEl, dE0);
-      dE1 = mfma3(aEh1, aEl1, bEh, bEl, dE1);
-      dO0 = mfma3(aOh0, aOl0, bOh, bOl, dO0);
-      dO1 = mfma3(aOh1, aOl1, bOh, bOl, dO1);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        dE0[g] = mfma3(aEh0, aEl0, bEh[g], bEl[g], dE0[g]);
+        dE1[g] = mfma3(aEh1, aEl1, bEh[g], bEl[g], dE1[g]);
+        dO0[g] = mfma3(aOh0, aOl0, bOh[g], bOl[g], dO0[g]);
+        dO1[g] = mfma3(aOh1, aOl1, bOh[g], bOl[g], dO1[g]);
+      }
     }
   }
   // D[i][j]: lane j + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4
   const int j = lane & 31;
-  const int rhs = j >> 1, comp = j & 1;
-  if (rhs >= nrhs) return;
+  const int comp = j & 1;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+  for (int g = 0; g < NG; ++g) {
+    const int rhs = 16 * g + (j >> 1);
+    if (rhs >= nrhs) continue;
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int pr = pb * 64 + 32 * t + i;
-      if (pr >= npairs) continue;
-      float* dst = reinterpret_cast<float*>(eo + rhs * eo_stride + ((size_t)pr * (mmax + 1) + m) * 2);
-      dst[comp] = t ? dE1[r] : dE0[r];
-      dst[2 + comp] = t ? dO1[r] : dO0[r];
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int pr = pb * 64 + 32 * t + i;
+        if (pr >= npairs) continue;
+        float* dst = reinterpret_cast<float*>(eo + rhs * eo_stride + ((size_t)pr * (mmax + 1) + m) * 2);
+        dst[comp] = t ? dE1[g][r] : dE0[g][r];
+        dst[2 + comp] = t ? dO1[g][r] : dO0[g][r];
+      }
     }
   }
 }
@@ -355,9 +388,12 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
 constexpr int kPrepM = 8;                       // m per block
 constexpr int kPrepMS = 2 * 16 * 2 * 16 + 8;   // floats per m in LDS ([q][rhs][comp][pair], padded)
 __global__ __launch_bounds__(256) void k_prep_adj(int mmax, int npairs, int nrhs, const float2* __restrict__ geo,
-                                                  int64_t geo_stride, bf16x8* __restrict__ ag) {
+                                                  int64_t geo_stride, bf16x8* __restrict__ ag, int64_t ag_gstride) {
   __shared__ __attribute__((aligned(16))) float G[kPrepM * kPrepMS];
-  const int kb = blockIdx.x, m0 = blockIdx.y * kPrepM;
+  const int kb = blockIdx.x, m0 = blockIdx.y * kPrepM, grp = blockIdx.z;   // right-hand sides 16 grp ..
+  nrhs -= 16 * grp;
+  geo += (int64_t)16 * grp * geo_stride;
+  ag += grp * ag_gstride;
   const int nkb = (npairs + 15) / 16;
   const int t = threadIdx.x;
   // load: row = rhs * 16 + pair (256 rows), 8 m per row, one float4 (q = 0, 1) per (row, m)
@@ -444,6 +480,7 @@ __device__ __forceinline__ void adj_tile_steps(unsigned char* my, int lane, int 
   }
 }
 
+template <int NG>
 __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs, int nrhs,
                                                   const double* __restrict__ pair_z, const double* __restrict__ alpha,
                                                   const int* __restrict__ lst_g, const double2* __restrict__ lst_s,
@@ -451,8 +488,8 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
                                                   const int64_t* __restrict__ tstart,
                                                   const int* __restrict__ tile_m, const int* __restrict__ order,
                                                   int maxq, const double2* __restrict__ ckpt,
-                                                  const bf16x8* __restrict__ ag, double2* __restrict__ out,
-                                                  int64_t out_stride) {
+                                                  const bf16x8* __restrict__ ag, int64_t ag_gstride,
+                                                  double2* __restrict__ out, int64_t out_stride) {
   // per wavefront: [q][h][32 steps][kRowB bytes]; reused for the partial results
   __shared__ __attribute__((aligned(16))) unsigned char lds[kAdjWaves][2][2][32][kRowB];
   const int tid = order[(blockIdx.x & 7) * maxq + (blockIdx.x >> 3)];   // tiles of one m stay on one XCD
@@ -465,7 +502,9 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
   const int st0 = T * kAdjTile;
   const int nkb = (npairs + 15) / 16;
   const int per = ((npairs + kAdjWaves * 64 - 1) / (kAdjWaves * 64)) * 64;   // pairs per wavefront
-  f32x16 dE = {}, dO = {};
+  f32x16 dE[NG], dO[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) dE[g] = dO[g] = f32x16{};
   const int row = lane & 31, kg = lane >> 5;
   unsigned char* my = &lds[w][0][0][0][0];
 
@@ -522,17 +561,31 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
       // wavefront complete in order: a compiler barrier suffices
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
-      for (int kb = 0; kb < 4; ++kb) {
-        const int gkb = r0 / 16 + kb;
-        if (gkb >= nkb) break;
-        // B[k][n] = mu(pair 16 kb + k, step pair n): lane n + 32 (k/8) reads 8 pairs of row n
-        const int off = swz(row, 2 * kb + kg);
-        const bf16x8 bEh = *reinterpret_cast<const bf16x8*>(my + ((0 * 2 + 0) * 32 + row) * kRowB + off);
-        const bf16x8 bEl = *reinterpret_cast<const bf16x8*>(my + ((0 * 2 + 1) * 32 + row) * kRowB + off);
-        const bf16x8 bOh = *reinterpret_cast<const bf16x8*>(my + ((1 * 2 + 0) * 32 + row) * kRowB + off);
-        const bf16x8 bOl = *reinterpret_cast<const bf16x8*>(my + ((1 * 2 + 1) * 32 + row) * kRowB + off);
-        dE = mfma3(aq[kb][0], aq[kb][1], bEh, bEl, dE);
-        dO = mfma3(aq[kb][2], aq[kb][3], bOh, bOl, dO);
+      for (int g = 0; g < NG; ++g) {
+        if (g > 0) {
+          // operands of the next column group, loaded after the previous
+          // group's products are issued (keeps one group in registers)
+#pragma unroll
+          for (int kb = 0; kb < 4; ++kb) {
+            const int gkb = min(r0 / 16 + kb, nkb - 1);
+            const bf16x8* a = ag + g * ag_gstride + ((size_t)m * nkb + gkb) * 4 * 64;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) aq[kb][u] = a[u * 64 + lane];
+          }
+        }
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+          const int gkb = r0 / 16 + kb;
+          if (gkb >= nkb) break;
+          // B[k][n] = mu(pair 16 kb + k, step pair n): lane n + 32 (k/8) reads 8 pairs of row n
+          const int off = swz(row, 2 * kb + kg);
+          const bf16x8 bEh = *reinterpret_cast<const bf16x8*>(my + ((0 * 2 + 0) * 32 + row) * kRowB + off);
+          const bf16x8 bEl = *reinterpret_cast<const bf16x8*>(my + ((0 * 2 + 1) * 32 + row) * kRowB + off);
+          const bf16x8 bOh = *reinterpret_cast<const bf16x8*>(my + ((1 * 2 + 0) * 32 + row) * kRowB + off);
+          const bf16x8 bOl = *reinterpret_cast<const bf16x8*>(my + ((1 * 2 + 1) * 32 + row) * kRowB + off);
+          dE[g] = mfma3(aq[kb][0], aq[kb][1], bEh, bEl, dE[g]);
+          dO[g] = mfma3(aq[kb][2], aq[kb][3], bOh, bOl, dO[g]);
+        }
       }
       __builtin_amdgcn_wave_barrier();
     }
@@ -540,23 +593,26 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
   }
   // one block-wide barrier, reached once by every wavefront; each wavefront
   // reuses its own tile area for its partial result red[w][q][r][lane]
+  // (NG x 8 KiB of the wavefront's 16 KiB tile area)
   float* redw = reinterpret_cast<float*>(my);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    redw[(0 * 16 + r) * 64 + lane] = dE[r];
-    redw[(1 * 16 + r) * 64 + lane] = dO[r];
-  }
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      redw[((2 * g + 0) * 16 + r) * 64 + lane] = dE[g][r];
+      redw[((2 * g + 1) * 16 + r) * 64 + lane] = dO[g][r];
+    }
   __syncthreads();
   // D[c][n] at lane n + 32 ((c/4)%2), register 4 (c/8) + c%4; sum the wavefronts
-  for (int e = threadIdx.x; e < 2 * 16 * 64; e += blockDim.x) {
-    const int q = e / (16 * 64), r = (e / 64) % 16, ln = e % 64;
+  for (int e = threadIdx.x; e < NG * 2 * 16 * 64; e += blockDim.x) {
+    const int g = e / (2 * 16 * 64), q = (e / (16 * 64)) % 2, r = (e / 64) % 16, ln = e % 64;
     float acc = 0.f;
 #pragma unroll
     for (int ww = 0; ww < kAdjWaves; ++ww)
-      acc += reinterpret_cast<const float*>(&lds[ww][0][0][0][0])[(q * 16 + r) * 64 + ln];
+      acc += reinterpret_cast<const float*>(&lds[ww][0][0][0][0])[((2 * g + q) * 16 + r) * 64 + ln];
     const int c = 8 * (r / 4) + 4 * (ln >> 5) + (r % 4);
     const int n = ln & 31;
-    const int rhs = c >> 1, comp = c & 1;
+    const int rhs = 16 * g + (c >> 1), comp = c & 1;
     const int st = st0 + 2 * n + q;
     if (rhs < nrhs && st < nsteps)
       reinterpret_cast<double*>(out + rhs * out_stride + base + st)[comp] = (double)acc;
@@ -576,8 +632,12 @@ int64_t mixed_adj_tiles(const Geometry& g) {
   for (int m = 0; m <= g.mmax; ++m) n += (g.lmax - m + 1 + kAdjTile - 1) / kAdjTile;
   return n;
 }
-int64_t mixed_ab_bytes(const Geometry& g) { return mixed_synth_chunks(g) * 4 * 64 * 16; }
-int64_t mixed_ag_bytes(const Geometry& g) { return (int64_t)(g.mmax + 1) * ((g.npairs + 15) / 16) * 4 * 64 * 16; }
+// operand tiles of one group of 16 right-hand sides (bf16x8 units) and the
+// buffers for kMaxGroups groups
+int64_t ab_group(const Geometry& g) { return mixed_synth_chunks(g) * 4 * 64; }
+int64_t ag_group(const Geometry& g) { return (int64_t)(g.mmax + 1) * ((g.npairs + 15) / 16) * 4 * 64; }
+int64_t mixed_ab_bytes(const Geometry& g) { return kMaxGroups * ab_group(g) * 16; }
+int64_t mixed_ag_bytes(const Geometry& g) { return kAdjGroups * ag_group(g) * 16; }
 void mixed_starts(const Geometry& g, std::vector<int64_t>& cst, std::vector<int64_t>& tst, std::vector<int>& tm,
                   std::vector<int>& order, int& maxq) {
   cst.assign(g.mmax + 2, 0);
@@ -615,25 +675,42 @@ hipError_t launch_checkpoints(const crsht_plan* P, hipStream_t s) {
   return hipGetLastError();
 }
 
-// columns of one group: at most kMixedCols / 2 right-hand sides
+// Columns go in launches of at most kMaxGroups groups of 16 right-hand sides
+// (kMixedCols / 2); the recurrence of a launch is shared by all its columns.
+int launch_groups(int nr) { return (nr + kMixedCols / 2 - 1) / (kMixedCols / 2); }
+
+hipError_t synth_mfma_launch(const crsht_plan* P, int nr, const bf16x8* ab, float2* eo, int64_t eo_stride,
+                             hipStream_t s) {
+  const Geometry& g = P->g;
+  dim3 gs(synth_mfma_blocks(g));
+  timing_begin(P, 3, s);
+  if (launch_groups(nr) > 1)
+    hipLaunchKernelGGL(k_synth_mfma<2>, gs, dim3(64), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.pair_z,
+                       P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.mx_cstart, ab, ab_group(g), eo,
+                       eo_stride);
+  else
+    hipLaunchKernelGGL(k_synth_mfma<1>, gs, dim3(64), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.pair_z,
+                       P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.mx_cstart, ab, ab_group(g), eo,
+                       eo_stride);
+  timing_end(P, 3, s);
+  return hipGetLastError();
+}
+
 hipError_t launch_legendre_synth_mixed(const crsht_plan* P, int nrhs, const double2* alm, const double* f,
                                        float2* eo, hipStream_t s) {
   if (!f) f = P->t.ones;
   const Geometry& g = P->g;
   const int64_t eo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
   bf16x8* ab = reinterpret_cast<bf16x8*>(P->w.mx_ab);
-  for (int c0 = 0; c0 < nrhs; c0 += kMixedCols / 2) {
-    const int nr = min(nrhs - c0, kMixedCols / 2);
-    dim3 gp((g.lmax + kSynChunk) / kSynChunk, g.mmax + 1);
+  const int per = kMaxGroups * (kMixedCols / 2);
+  for (int c0 = 0; c0 < nrhs; c0 += per) {
+    const int nr = min(nrhs - c0, per);
+    dim3 gp((g.lmax + kSynChunk) / kSynChunk, g.mmax + 1, launch_groups(nr));
     hipLaunchKernelGGL(k_prep_synth, gp, dim3(64), 0, s, g.lmax, nr, P->t.mstart, P->t.mx_cstart,
-                       alm + (int64_t)c0 * g.nalm, (int64_t)g.nalm, f, ab);
-    timing_begin(P, 3, s);
-    dim3 gs(synth_mfma_blocks(g));
-    hipLaunchKernelGGL(k_synth_mfma, gs, dim3(64), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.pair_z, P->t.rec_alpha,
-                       P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.mx_cstart, (const bf16x8*)ab,
-                       eo + (int64_t)c0 * eo_stride, eo_stride);
-    timing_end(P, 3, s);
+                       alm + (int64_t)c0 * g.nalm, (int64_t)g.nalm, f, ab, ab_group(g));
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = synth_mfma_launch(P, nr, ab, eo + (int64_t)c0 * eo_stride, eo_stride, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -644,19 +721,16 @@ hipError_t launch_legendre_synth_mixed_cg(const crsht_plan* P, int nrhs, const d
   const Geometry& g = P->g;
   const int64_t eo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
   bf16x8* ab = reinterpret_cast<bf16x8*>(P->w.mx_ab);
-  for (int c0 = 0; c0 < nrhs; c0 += kMixedCols / 2) {
-    const int nr = min(nrhs - c0, kMixedCols / 2);
-    dim3 gp((g.lmax + kSynChunk) / kSynChunk, g.mmax + 1);
+  const int per = kMaxGroups * (kMixedCols / 2);
+  for (int c0 = 0; c0 < nrhs; c0 += per) {
+    const int nr = min(nrhs - c0, per);
+    dim3 gp((g.lmax + kSynChunk) / kSynChunk, g.mmax + 1, launch_groups(nr));
     hipLaunchKernelGGL(k_pupdate_prep, gp, dim3(64), 0, s, g.lmax, nr, g.nalm, P->t.mstart, P->t.mx_cstart,
                        P->w.bk, z + (int64_t)c0 * g.nalm, p + (int64_t)c0 * g.nalm,
-                       P->w.scal + (int64_t)c0 * kScalSlots, update ? 1 : 0, ab);
-    timing_begin(P, 3, s);
-    dim3 gs(synth_mfma_blocks(g));
-    hipLaunchKernelGGL(k_synth_mfma, gs, dim3(64), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.pair_z, P->t.rec_alpha,
-                       P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.mx_cstart, (const bf16x8*)ab,
-                       eo + (int64_t)c0 * eo_stride, eo_stride);
-    timing_end(P, 3, s);
+                       P->w.scal + (int64_t)c0 * kScalSlots, update ? 1 : 0, ab, ab_group(g));
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = synth_mfma_launch(P, nr, ab, eo + (int64_t)c0 * eo_stride, eo_stride, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -667,18 +741,30 @@ hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const fl
   const Geometry& g = P->g;
   const int64_t geo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
   bf16x8* ag = reinterpret_cast<bf16x8*>(P->w.mx_ag);
-  for (int c0 = 0; c0 < nrhs; c0 += kMixedCols / 2) {
-    const int nr = min(nrhs - c0, kMixedCols / 2);
-    dim3 gp((g.npairs + 15) / 16, (g.mmax + kPrepM) / kPrepM);
+  // one column group per adjoint launch: two groups raise the register use
+  // to one wavefront per SIMD, which costs more than the shared recurrence
+  // saves (measured at Nside 512)
+  const int per = kAdjGroups * (kMixedCols / 2);
+  for (int c0 = 0; c0 < nrhs; c0 += per) {
+    const int nr = min(nrhs - c0, per);
+    dim3 gp((g.npairs + 15) / 16, (g.mmax + kPrepM) / kPrepM, launch_groups(nr));
     hipLaunchKernelGGL(k_prep_adj, gp, dim3(256), 0, s, g.mmax, g.npairs, nr, geo + (int64_t)c0 * geo_stride,
-                       geo_stride, ag);
-    timing_begin(P, 4, s);
-    hipLaunchKernelGGL(k_adj_mfma, dim3(8u * (unsigned)P->t.mx_maxq), dim3(kAdjWaves * 64), 0, s, g.lmax, g.mmax,
-                       g.npairs, nr, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
-                       P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_order, P->t.mx_maxq, P->t.mx_ckpt, (const bf16x8*)ag,
-                       raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm);
-    timing_end(P, 4, s);
+                       geo_stride, ag, ag_group(g));
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    timing_begin(P, 4, s);
+    if (launch_groups(nr) > 1)
+      hipLaunchKernelGGL(k_adj_mfma<2>, dim3(8u * (unsigned)P->t.mx_maxq), dim3(kAdjWaves * 64), 0, s, g.lmax,
+                         g.mmax, g.npairs, nr, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
+                         P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_order, P->t.mx_maxq, P->t.mx_ckpt,
+                         (const bf16x8*)ag, ag_group(g), raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm);
+    else
+      hipLaunchKernelGGL(k_adj_mfma<1>, dim3(8u * (unsigned)P->t.mx_maxq), dim3(kAdjWaves * 64), 0, s, g.lmax,
+                         g.mmax, g.npairs, nr, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
+                         P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_order, P->t.mx_maxq, P->t.mx_ckpt,
+                         (const bf16x8*)ag, ag_group(g), raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm);
+    timing_end(P, 4, s);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -25,7 +25,7 @@ def _m():
 
 
 @pytest.mark.parametrize("nside,lmax,nrhs", [(4, 11, 1), (8, 23, 3), (16, 47, 1), (32, 95, 2), (64, 191, 17),
-                                             (128, 383, 1), (6, 17, 2)])
+                                             (128, 383, 1), (6, 17, 2), (32, 95, 33), (16, 47, 40)])
 def test_mixed_transforms_against_oracle(nside, lmax, nrhs):
     m = _m()
     print("case", nside, lmax, nrhs, flush=True)
@@ -83,3 +83,21 @@ def test_refined_solve_reaches_tolerance(nside):
         assert abs(res - stm[c].rel_resid_true) <= 1e-9
         assert stm[c].refinements >= 1
     _ = math, cr
+
+
+def test_refined_solve_many_columns():
+    # 20 columns: the MFMA steps run two column groups in one launch (16 + 4)
+    m = _m()
+    nside, nrhs = 16, 20
+    wl, P, op, d = masked_problem(nside)
+    plan = m.Plan(nside, wl.lmax, nrhs_max=nrhs)
+    gp = m.Problem(P.cl, P.bl, tc(P.ninv), 2)
+    rng = np.random.default_rng(77)
+    W0 = np.stack([ci.white_alm(rng, wl.lmax) for _ in range(nrhs)])
+    W1 = rng.standard_normal((nrhs, P.ninv.size))
+    D = np.stack([d * (0.5 + 0.05 * c) for c in range(nrhs)])
+    sm, stm = m.solve(plan, gp, tc(D), tc(W0), tc(W1), nrhs=nrhs, tol=1e-6, prec=m.CR_MIXED)
+    x = sm.cpu().numpy()
+    for c in range(nrhs):
+        res = real_rel(op, op.apply(x[c]), op.rhs(D[c], W0[c], W1[c]))
+        assert stm[c].status == 0 and res <= 1.05e-6, (c, res)
