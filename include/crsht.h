@@ -81,6 +81,9 @@ typedef struct crsht_plan crsht_plan;
  *   it is the inner operator of float64 iterative refinement. */
 typedef enum { CR_F64 = 0, CR_MIXED = 1 } cr_prec;
 
+/* Preconditioner of cr_solve (cr_opts.precond). */
+enum { CR_PC_JACOBI = 0, CR_PC_BLOCK = 1 };
+
 /* Create a plan for HEALPix resolution nside (power of two not required,
  * 1 <= nside <= 1024; larger nside returns CR_ENOTSUP), band limit lmax >= 0 and mmax (<= lmax; pass -1 for
  * mmax = lmax), ncomp = 1 (temperature) or 3 (temperature and polarisation),
@@ -148,6 +151,9 @@ typedef struct {
                           has dropped by this factor (0 < inner_tol < 1, e.g. 1e-2); ignored for CR_F64 */
   int max_refine;      /* CR_MIXED: maximum number of FP64 residual replacements (0 = 1000) */
   int check_every;     /* iterations between host convergence checks (>= 1; 0 = 8) */
+  int precond;         /* CR_PC_JACOBI (0): the Jacobi diagonal of cr_precond, rebuilt by every solve;
+                          CR_PC_BLOCK (1): the per-m block preconditioner stored in the plan by
+                          cr_block_precond_build (temperature plans; CR_EINVAL if none is built) */
   int use_graph;       /* 1: each block of check_every iterations is captured once as a HIP graph
                           (plan-owned, re-captured when nrhs, ninv, tol, precision or the block
                           length change) and replayed on `stream`; 0: every kernel is launched
@@ -170,6 +176,30 @@ typedef struct {
  * spin-0 lambda_lm stand in for the spin-2 functions: an approximation that
  * only needs to stay positive). Asynchronous. */
 int cr_precond(const crsht_plan *plan, const cr_problem *prob, double *diag, void *stream);
+
+/* Per-m block preconditioner (paper App. A; Sect. 4 names better
+ * preconditioners as the main lever on the cost of the solve). For every m and
+ * parity q of l - m, the dense matrix
+ *   M_mq[l, l'] = delta_ll' / C_l + b_l b_l' sum_r lambda_lm(z_r) lambda_l'm(z_r) W_r,
+ * l, l' = m + q, m + q + 2, ..., with W_r the ring sum of N^-1 averaged over
+ * ring r and its mirror ring (exact m-blocks of the operator for a noise
+ * model that depends on latitude only and is symmetric under z -> -z, as for
+ * the paper's constant-latitude mask; an SPD preconditioner otherwise; rows
+ * l < lmin are the identity) is formed in FP64, inverted by Cholesky
+ * factorisation (rocBLAS SYRK for the Gram matrices, rocSOLVER potrf/potri
+ * for the factorisation and inverse, on blocks padded to multiples of 32
+ * with the identity) and stored in FP32, full symmetric, in the plan (about
+ * 2 (lmax + 1)^3 / 3 bytes; allocated by this call, freed with the plan or
+ * by the next build). Built once per noise model, beam and spectrum shape,
+ * it stays valid when the spectrum is rescaled (joint_cl_step): PCG only
+ * needs a fixed symmetric positive definite preconditioner.
+ * Temperature plans (CR_ENOTSUP for ncomp = 3); CR_EINVAL if a block is not
+ * positive definite. Blocks until done. */
+int cr_block_precond_build(crsht_plan *plan, const cr_problem *prob, void *stream);
+
+/* z = M^-1 r with the stored block preconditioner, per column (the real and
+ * imaginary parts alike). r, z: device [nrhs][nalm], distinct. Asynchronous. */
+int cr_block_precond_apply(const crsht_plan *plan, int nrhs, const double *r, double *z, void *stream);
 
 /* Right-hand side of eq. mapmakingeq: b = B Y^T N^-1 d + S^-1/2 w0 + B Y^T N^-1/2 w1,
  * restricted to l >= lmin. d, w1: device maps [nrhs][npix]; w0: device alm

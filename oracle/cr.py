@@ -104,16 +104,22 @@ class PCGInfo:
     history: list
 
 
-def pcg(op, b: np.ndarray, tol: float, maxiter: int = 10000, precond: np.ndarray | None = None,
+def pcg(op, b: np.ndarray, tol: float, maxiter: int = 10000, precond=None,
         x0: np.ndarray | None = None) -> tuple[np.ndarray, PCGInfo]:
-    """Jacobi-preconditioned conjugate gradients in the real-field inner product."""
-    D = op.diag() if precond is None else precond
+    """Preconditioned conjugate gradients in the real-field inner product.
+    precond: None (Jacobi diagonal of op), an array D (z = r / D) or a
+    callable r -> z (symmetric positive definite)."""
+    if callable(precond):
+        apply_pc = precond
+    else:
+        D = op.diag() if precond is None else precond
+        apply_pc = lambda r: r / D
     bnorm = op.norm(b)
     x = np.zeros_like(b) if x0 is None else op.project(np.array(x0, dtype=np.complex128))
     if bnorm == 0.0:
         return np.zeros_like(b), PCGInfo(0, 0.0, True, [])
     r = b - op.apply(x) if x0 is not None else b.copy()
-    z = op.project(r / D)
+    z = op.project(apply_pc(r))
     p = z.copy()
     rz = op.dot(r, z)
     hist = []
@@ -131,11 +137,11 @@ def pcg(op, b: np.ndarray, tol: float, maxiter: int = 10000, precond: np.ndarray
             if op.norm(rt) / bnorm <= tol:
                 break
             r = rt
-            z = op.project(r / D)
+            z = op.project(apply_pc(r))
             p = z.copy()
             rz = op.dot(r, z)
             continue
-        z = op.project(r / D)
+        z = op.project(apply_pc(r))
         rz_new = op.dot(r, z)
         p = z + (rz_new / rz) * p
         rz = rz_new

@@ -22,6 +22,7 @@ LIB_PATH = os.environ.get("CRSHT_LIB") or os.path.join(_HERE, "libcrsht.so")
 CR_OK, CR_EINVAL, CR_ENOMEM, CR_EDEVICE, CR_ENOTSUP = 0, -1, -2, -3, -4
 CR_NOCONV, CR_BREAKDOWN = 1, 2
 CR_F64, CR_MIXED = 0, 1
+CR_PC_JACOBI, CR_PC_BLOCK = 0, 1
 
 
 class CrshtError(RuntimeError):
@@ -44,7 +45,7 @@ class _Problem(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("prec", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("use_graph", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("use_graph", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -82,6 +83,8 @@ def _load():
         "sht_synth_adjoint": ([P, i, vp, vp, i, vp], i),
         "sht_analysis": ([P, i, vp, vp, i, vp], i),
         "cr_precond": ([P, ctypes.POINTER(_Problem), vp, vp], i),
+        "cr_block_precond_build": ([P, ctypes.POINTER(_Problem), vp], i),
+        "cr_block_precond_apply": ([P, i, vp, vp, vp], i),
         "cr_rhs": ([P, ctypes.POINTER(_Problem), i, vp, vp, vp, vp, vp], i),
         "cr_apply": ([P, ctypes.POINTER(_Problem), i, vp, vp, i, vp], i),
         "cr_solve": ([P, ctypes.POINTER(_Problem), i, vp, vp, vp, vp, vp, ctypes.POINTER(_Opts),
@@ -112,8 +115,8 @@ _lib = _load()
 
 EXPORTED = ("crsht_plan_create", "crsht_plan_destroy", "crsht_strerror", "crsht_plan_info", "crsht_pixel_coords",
             "sht_synth", "sht_synth_adjoint", "sht_analysis", "cr_precond", "cr_rhs", "cr_apply", "cr_solve",
-            "cr_lnpi", "joint_cl_step", "cr_solve_batched", "sht_synth_grad", "cr_grad_chi2", "cr_grad_lnpi", "crsht_timing_enable",
-            "crsht_timing_read")
+            "cr_lnpi", "joint_cl_step", "cr_solve_batched", "sht_synth_grad", "cr_grad_chi2", "cr_grad_lnpi",
+            "cr_block_precond_build", "cr_block_precond_apply", "crsht_timing_enable", "crsht_timing_read")
 
 
 def lib():
@@ -271,6 +274,22 @@ def precond(plan: Plan, prob: Problem) -> torch.Tensor:
     return out
 
 
+def block_precond_build(plan: Plan, prob: Problem):
+    """Build the per-m block preconditioner of prob into the plan (used by
+    solves with precond=CR_PC_BLOCK)."""
+    p = prob._c()
+    _check(_lib.cr_block_precond_build(plan.handle, ctypes.byref(p), _stream()), "cr_block_precond_build")
+    torch.cuda.synchronize()
+
+
+def block_precond_apply(plan: Plan, r: torch.Tensor) -> torch.Tensor:
+    """z = M^-1 r with the plan's block preconditioner."""
+    n = _nrhs(r, plan.vlen, torch.complex128)
+    z = torch.empty_like(r)
+    _check(_lib.cr_block_precond_apply(plan.handle, n, _ptr(r), _ptr(z), _stream()), "cr_block_precond_apply")
+    return z
+
+
 def rhs(plan: Plan, prob: Problem, d=None, w0=None, w1=None, nrhs: int = 1) -> torch.Tensor:
     out = torch.empty(plan.alm_shape(nrhs), dtype=torch.complex128, device=prob.ninv.device)
     p = prob._c()
@@ -289,13 +308,14 @@ def apply(plan: Plan, prob: Problem, x: torch.Tensor, prec: int = CR_F64) -> tor
 
 def solve(plan: Plan, prob: Problem, d=None, w0=None, w1=None, rhs_vec=None, nrhs: int = 1, tol: float = 1e-6,
           maxiter: int = 10000, prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 50,
-          check_every: int = 8, out: torch.Tensor | None = None, use_graph: bool = True):
+          check_every: int = 8, out: torch.Tensor | None = None, use_graph: bool = True,
+          precond: int = CR_PC_JACOBI):
     """Returns (s [nrhs, nalm] complex128 ([nrhs, 3, nalm] for ncomp = 3), [Stats]).
     use_graph: replay each block of check_every iterations as a captured HIP graph."""
     if out is None:
         out = torch.empty(plan.alm_shape(nrhs), dtype=torch.complex128, device=prob.ninv.device)
     p = prob._c()
-    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every, int(use_graph))
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every, int(precond), int(use_graph))
     st = (_Stats * nrhs)()
     _check(_lib.cr_solve(plan.handle, ctypes.byref(p), nrhs, _ptr(d), _ptr(w0), _ptr(w1), _ptr(rhs_vec), _ptr(out),
                          ctypes.byref(o), st, _stream()), "cr_solve")
@@ -304,7 +324,7 @@ def solve(plan: Plan, prob: Problem, d=None, w0=None, w1=None, rhs_vec=None, nrh
 
 def solve_batched(plans, probs, d=None, w0=None, w1=None, tol: float = 1e-6, maxiter: int = 20000,
                   prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 0, check_every: int = 16,
-                  out=None, use_graph: bool = True):
+                  out=None, use_graph: bool = True, precond: int = CR_PC_JACOBI):
     """Independent single-column problems (own plan each). d, w0, w1: lists of
     tensors (or None). Returns (list of s [nalm] complex128, [Stats])."""
     n = len(plans)
@@ -322,7 +342,7 @@ def solve_batched(plans, probs, d=None, w0=None, w1=None, tol: float = 1e-6, max
 
     hp = VP(*[pl.handle.value for pl in plans])
     pa = (_Problem * n)(*[pr._c() for pr in probs])
-    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every, int(use_graph))
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every, int(precond), int(use_graph))
     st = (_Stats * n)()
     _check(_lib.cr_solve_batched(hp, pa, n, arr(d), arr(w0), arr(w1), VP(*[_ptr(t).value for t in out]),
                                  ctypes.byref(o), st, _stream()), "cr_solve_batched")
@@ -358,11 +378,11 @@ class StepResult:
 def joint_step(plan: Plan, fid: Problem, d: torch.Tensor, chain: Chain, xi: float, u: float, w0: torch.Tensor,
                w1: torch.Tensor, sigma_lnq: float = 0.02, tol: float = 1e-6, maxiter: int = 10000,
                prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 50,
-               use_graph: bool = True) -> StepResult:
+               use_graph: bool = True, precond: int = CR_PC_JACOBI) -> StepResult:
     p = fid._c()
     c = _Chain(chain.q, chain.lnpi, _ptr(chain.ahat), _ptr(chain.fhat))
     dr = _Draws(xi, u, _ptr(w0), _ptr(w1), sigma_lnq)
-    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, 8, int(use_graph))
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, 8, int(precond), int(use_graph))
     r = _StepOut()
     _check(_lib.joint_cl_step(plan.handle, ctypes.byref(p), _ptr(d), ctypes.byref(c), ctypes.byref(dr),
                               ctypes.byref(o), ctypes.byref(r), _stream()), "joint_cl_step")
@@ -416,7 +436,7 @@ def grad_chi2(plan: Plan, prob: Problem, d: torch.Tensor, a: torch.Tensor):
 
 def grad_lnpi(plan: Plan, prob: Problem, d: torch.Tensor, w0, w1, edges, tol: float = 1e-10, maxiter: int = 20000,
               prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 0, check_every: int = 8,
-              use_graph: bool = True):
+              use_graph: bool = True, precond: int = CR_PC_JACOBI):
     """(dlnpi/dtheta [nbins] numpy, ln pi, [Stats x 3]) for per-bin log-amplitudes
     of C_l on [edges[k], edges[k+1])."""
     import numpy as np
@@ -426,7 +446,7 @@ def grad_lnpi(plan: Plan, prob: Problem, d: torch.Tensor, w0, w1, edges, tol: fl
     v = ctypes.c_double()
     st = (_Stats * 3)()
     p = prob._c()
-    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every, int(use_graph))
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every, int(precond), int(use_graph))
     _check(_lib.cr_grad_lnpi(plan.handle, ctypes.byref(p), _ptr(d), _ptr(w0), _ptr(w1), nb,
                              e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(o),
                              g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(v), st, _stream()),
@@ -440,6 +460,7 @@ def nalm(lmax: int, mmax: int | None = None) -> int:
 
 
 __all__ = ["Plan", "Problem", "Stats", "Chain", "StepResult", "synth", "adjoint", "analysis", "precond", "rhs",
+           "block_precond_build", "block_precond_apply", "CR_PC_JACOBI", "CR_PC_BLOCK",
            "apply", "solve", "solve_batched", "lnpi", "joint_step", "synth_grad", "synth_ad", "SynthFunction", "grad_chi2", "grad_lnpi",
            "CR_F64", "CR_MIXED", "CrshtError", "strerror", "EXPORTED"]
 _ = math

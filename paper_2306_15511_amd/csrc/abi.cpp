@@ -349,15 +349,35 @@ int true_residual(const crsht_plan* P, int nrhs, const double* ninv, const doubl
 // whose recursive residual meets tol is confirmed against the true FP64
 // residual and restarted from it if it does not; rel[] then holds the true
 // relative residuals. iters[] receives the iterations per column.
+// z = P r and the start of PCG (p = z, <r, z>, <r, r>, <b, b>) for the
+// Jacobi (pc false) or the block preconditioner
+int pcg_start(const crsht_plan* P, int nrhs, const double2* b, bool pc, hipStream_t s) {
+  Workspace const& w = P->w;
+  if (pc) CR_TRY(launch_pc_apply(P, nrhs, w.cg_r, w.cg_z, s));
+  CR_TRY(launch_cg_start(P, nrhs, b, w.cg_r, w.cg_z, w.cg_p, w.alm_a, s, pc));
+  return CR_OK;
+}
+
+// x += alpha p, r -= alpha q, z = P r; partials <r, z> (row 0), <r, r> (row 1)
+int pcg_update(const crsht_plan* P, int nrhs, bool pc, hipStream_t s) {
+  Workspace const& w = P->w;
+  CR_TRY(launch_cg_update(P, nrhs, w.cg_x, w.cg_r, w.cg_z, w.cg_p, w.cg_q, s, pc));
+  if (pc) {
+    CR_TRY(launch_pc_apply(P, nrhs, w.cg_r, w.cg_z, s));
+    CR_TRY(launch_pc_dots(P, nrhs, w.cg_r, w.cg_z, false, s));
+  }
+  return CR_OK;
+}
+
 int pcg_run(const crsht_plan* P, int nrhs, const double* ninv, const double2* b, double tol, int maxiter,
             int check_every, bool mixed, bool verify, std::vector<int>& iters, std::vector<double>& rel,
-            std::vector<int>& broke, hipStream_t s, bool use_graph = false) {
+            std::vector<int>& broke, hipStream_t s, bool use_graph = false, bool pc = false) {
   const int64_t na = vlen(P);
   const int nb = vec_reduce_blocks(P);
   Workspace const& w = P->w;
   CR_TRY(hipMemsetAsync(w.cg_x, 0, (size_t)nrhs * na * sizeof(double2), s));
   CR_TRY(hipMemcpyAsync(w.cg_r, b, (size_t)nrhs * na * sizeof(double2), hipMemcpyDeviceToDevice, s));
-  CR_TRY(launch_cg_start(P, nrhs, b, w.cg_r, w.cg_z, w.cg_p, w.alm_a, s));
+  CR_CHECK(pcg_start(P, nrhs, b, pc, s));
   CR_TRY(launch_cg_scalars(P, nrhs, 0, nb, tol, 0, s));
   CR_CHECK(read_scalars(P, nrhs, s));
 
@@ -372,13 +392,14 @@ int pcg_run(const crsht_plan* P, int nrhs, const double* ninv, const double2* b,
       key.kind = mixed ? 2 : 0;
       key.nrhs = nrhs;
       key.n = n;
+      key.pc = pc ? 1 : 0;
       key.ninv = ninv;
       key.tol = tol;
       CR_CHECK(run_block(P, key, use_graph, s, [&](hipStream_t q) -> int {
         for (int k = 0; k < n; ++k) {
           CR_CHECK(operator_core(P, nrhs, w.cg_p, w.alm_a, ninv, w.cg_q, q, mixed));
           CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, q));
-          CR_TRY(launch_cg_update(P, nrhs, w.cg_x, w.cg_r, w.cg_z, w.cg_p, w.cg_q, q));
+          CR_CHECK(pcg_update(P, nrhs, pc, q));
           CR_TRY(launch_cg_scalars(P, nrhs, 2, nb, tol, 0, q));
           CR_TRY(launch_cg_pupdate(P, nrhs, w.cg_z, w.cg_p, w.alm_a, q));
         }
@@ -409,7 +430,7 @@ int pcg_run(const crsht_plan* P, int nrhs, const double* ninv, const double2* b,
     }
     if (!restart) break;
     CR_CHECK(write_scalars(P, nrhs, s));
-    CR_TRY(launch_cg_start(P, nrhs, b, w.cg_r, w.cg_z, w.cg_p, w.alm_a, s));
+    CR_CHECK(pcg_start(P, nrhs, b, pc, s));
     CR_TRY(launch_cg_scalars(P, nrhs, 0, nb, tol, 1, s));
     CR_CHECK(read_scalars(P, nrhs, s));
   }
@@ -447,7 +468,8 @@ int fill_stats(int nrhs, double tol, const std::vector<int>& iters, const std::v
 // the search directions kept, so the Krylov space is not discarded. A column
 // stops when its true relative residual is at most tol.
 int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_opts* o, std::vector<int>& iters,
-                  std::vector<int>& refine, std::vector<double>& rel, std::vector<int>& broke, hipStream_t s) {
+                  std::vector<int>& refine, std::vector<double>& rel, std::vector<int>& broke, hipStream_t s,
+                  bool pc = false) {
   // PCG on the mixed-precision operator with FP64 vectors and reliable updates:
   // every time a column's recursive residual has fallen by inner_tol since its
   // last replacement (or claims convergence), r is replaced by the FP64 true
@@ -465,7 +487,7 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
   refine.assign(nrhs, 0);
   CR_TRY(hipMemsetAsync(w.cg_x, 0, (size_t)nrhs * na * sizeof(double2), s));
   CR_TRY(hipMemcpyAsync(w.cg_r, w.cg_b, (size_t)nrhs * na * sizeof(double2), hipMemcpyDeviceToDevice, s));
-  CR_TRY(launch_cg_start(P, nrhs, w.cg_b, w.cg_r, w.cg_z, w.cg_p, w.alm_a, s));
+  CR_CHECK(pcg_start(P, nrhs, w.cg_b, pc, s));
   CR_TRY(launch_cg_scalars(P, nrhs, 0, nb, tol, 0, s));
   CR_CHECK(read_scalars(P, nrhs, s));
   std::vector<double> last(nrhs, 1.0);   // true relative residual at the last replacement
@@ -505,7 +527,12 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
       // z = D^-1 r from the replaced residual, beta = <r,z>/<r,z>_prev; the
       // direction update stays pending (fused into the next operator)
       CR_CHECK(write_scalars(P, nrhs, s));
-      CR_TRY(launch_cg_replace(P, nrhs, w.cg_r, w.cg_z, s));
+      if (pc) {
+        CR_TRY(launch_pc_apply(P, nrhs, w.cg_r, w.cg_z, s));
+        CR_TRY(launch_pc_dots(P, nrhs, w.cg_r, w.cg_z, true, s));
+      } else {
+        CR_TRY(launch_cg_replace(P, nrhs, w.cg_r, w.cg_z, s));
+      }
       CR_TRY(launch_cg_scalars(P, nrhs, 3, nb, tol, 0, s));
     }
     bool any = false;
@@ -521,6 +548,7 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
     key.nrhs = nrhs;
     key.n = n;
     key.first_update = pending ? 1 : 0;
+    key.pc = pc ? 1 : 0;
     key.ninv = ninv;
     key.tol = tol;
     const bool first = pending;
@@ -528,7 +556,7 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
       for (int k = 0; k < n; ++k) {
         CR_CHECK(operator_core_cg(P, nrhs, k > 0 || first, ninv, w.cg_q, q));
         CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, q));
-        CR_TRY(launch_cg_update(P, nrhs, w.cg_x, w.cg_r, w.cg_z, w.cg_p, w.cg_q, q));
+        CR_CHECK(pcg_update(P, nrhs, pc, q));
         CR_TRY(launch_cg_scalars(P, nrhs, 2, nb, tol, 0, q));
       }
       return CR_OK;
@@ -553,9 +581,12 @@ int solve_core(const crsht_plan* P, const cr_problem* prob, double q, int nrhs, 
   if (!opts || !stats || !s_out) return CR_EINVAL;
   if (!(opts->tol > 0.0) || opts->maxiter < 1) return CR_EINVAL;
   if (opts->prec != CR_F64 && opts->prec != CR_MIXED) return CR_EINVAL;
+  if (opts->precond != CR_PC_JACOBI && opts->precond != CR_PC_BLOCK) return CR_EINVAL;
+  const bool pc = opts->precond == CR_PC_BLOCK;
+  if (pc && (!P->pc.built || P->ncomp != 1)) return CR_EINVAL;
   const int every = opts->check_every > 0 ? opts->check_every : 8;
   CR_CHECK(set_problem(P, prob, q, s));
-  CR_CHECK(compute_diag(P, prob->ninv, s));
+  if (!pc) CR_CHECK(compute_diag(P, prob->ninv, s));
   if (rhs)
     CR_TRY(launch_project(P, nrhs, C2(rhs), P->w.cg_b, s));
   else
@@ -563,10 +594,10 @@ int solve_core(const crsht_plan* P, const cr_problem* prob, double q, int nrhs, 
   std::vector<int> iters, refine, broke;
   std::vector<double> rel;
   if (opts->prec == CR_MIXED) {
-    CR_CHECK(solve_refined(P, nrhs, prob->ninv, opts, iters, refine, rel, broke, s));
+    CR_CHECK(solve_refined(P, nrhs, prob->ninv, opts, iters, refine, rel, broke, s, pc));
   } else {
     CR_CHECK(pcg_run(P, nrhs, prob->ninv, P->w.cg_b, opts->tol, opts->maxiter, every, false, true, iters, rel, broke,
-                     s, opts->use_graph != 0));
+                     s, opts->use_graph != 0, pc));
     refine.assign(nrhs, 0);
   }
   fill_stats(nrhs, opts->tol, iters, refine, rel, broke, stats);
@@ -642,6 +673,22 @@ extern "C" int cr_precond(const crsht_plan* P, const cr_problem* prob, double* d
   CR_CHECK(set_problem(P, prob, 1.0, s));
   CR_CHECK(compute_diag(P, prob->ninv, s));
   CR_TRY(hipMemcpyAsync(diag, P->w.diag, vlen(P) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return CR_OK;
+}
+
+extern "C" int cr_block_precond_build(crsht_plan* P, const cr_problem* prob, void* stream) {
+  CR_CHECK(check_plan(P, 1));
+  if (P->ncomp != 1) return CR_ENOTSUP;
+  hipStream_t s = S(stream);
+  CR_CHECK(set_problem(P, prob, 1.0, s));   // validates the spectrum, beam and lmin
+  return block_pc_build(P, prob->bl, prob->cl, prob->lmin, 1.0, prob->ninv, s);
+}
+
+extern "C" int cr_block_precond_apply(const crsht_plan* P, int nrhs, const double* r, double* z, void* stream) {
+  CR_CHECK(check_plan(P, nrhs));
+  if (!r || !z || r == z) return CR_EINVAL;
+  if (!P->pc.built) return CR_EINVAL;
+  CR_TRY(launch_pc_apply(P, nrhs, C2(r), C2(z), S(stream)));
   return CR_OK;
 }
 

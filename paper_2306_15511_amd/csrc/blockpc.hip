@@ -1,0 +1,374 @@
+// Per-m block preconditioner (paper App. A; the better preconditioner that
+// Sect. 4 names as the main lever on the cost of the solve).
+//
+// For a noise model that depends on latitude only, N^-1 in harmonic space is
+// diagonal in m and S^-1 + B Y^T N^-1 Y B is one dense (l, l') matrix per m.
+// For a general noise model the same matrices built from the ring sums of
+// N^-1 (averaged over each ring and its mirror, so that blocks couple only
+// l - l' even) form a symmetric positive definite preconditioner:
+//   M_mq[i, j] = delta_ij / C_l + b_l b_l' sum_p lambda_lm(z_p) lambda_l'm(z_p) W_p,
+// l = m + q + 2 i, l' = m + q + 2 j (q = parity of l - m), W_p = ring sum of
+// N^-1 over both rings of pair p (the same ring weights as the Jacobi
+// diagonal, whose entries are the diagonal of these blocks). Rows with
+// l < lmin are the identity.
+//
+// Set-up (once per noise model, beam and spectrum shape): the blocks are
+// grouped into buckets of equal padded size; per bucket the FP64 factor
+// L = [b_l lambda_lm(z_p) sqrt(W_p)] is written by the recurrence kernel, the
+// Gram matrix L L^T is formed with rocBLAS SYRK, the prior diagonal added,
+// and the inverse computed with rocSOLVER (Cholesky, then inverse from the
+// factor); the inverses are stored in FP32, full symmetric, per block.
+// Application (every PCG iteration): z_mq = M_mq^-1 r_mq for the real and
+// imaginary parts of every column, one workgroup per 256 rows of a block.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "internal.h"
+#include "devutil.h"
+
+namespace crsht {
+namespace {
+
+constexpr int kStartGroup = 16;   // start-table group of the Legendre recurrence
+constexpr int kNeverG = 0x7fffffff;
+constexpr int kPcRows = 256;      // rows of a block per application workgroup
+constexpr int kPcCols = 16;       // right-hand sides per application pass
+constexpr int kPcJ = 64;          // r values staged per LDS tile
+constexpr int kPad = 32;          // bucket granularity of the padded block size
+
+// L[i][p] = b_l kappa_lm mu_lm(z_p) sqrt(W_p) for the rows l = m + q + 2 i of
+// block blk (0 for l < lmin); the recurrence and its start state are those of
+// the transform kernels. L: [bucket block][npad][npairs], zeroed beforehand.
+__global__ __launch_bounds__(256) void k_pc_lambda(int lmax, int npairs, int lmin, const double* __restrict__ pair_z,
+                                                   const double* __restrict__ alpha,
+                                                   const double* __restrict__ kappa, const int* __restrict__ lst_g,
+                                                   const double2* __restrict__ lst_s,
+                                                   const int64_t* __restrict__ mstart,
+                                                   const double* __restrict__ ring_w, const double* __restrict__ bl,
+                                                   const int* __restrict__ blocks, const int* __restrict__ bm,
+                                                   const int* __restrict__ bq, int npad, double* __restrict__ L) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const int blk = blocks[blockIdx.y];
+  const int m = bm[blk], q = bq[blk];
+  double* __restrict__ Lb = L + (size_t)blockIdx.y * npad * npairs;
+  const double w = sqrt(ring_w[p]);
+  const size_t o = (size_t)m * npairs + p;
+  const int gs = lst_g[o];
+  const double2 s0 = lst_s[o];
+  const double z = pair_z[p];
+  const int64_t base = mstart[m];
+  const int nsteps = lmax - m + 1;
+  double v0 = 0.0, v1 = 0.0;
+  for (int st = 0; st < nsteps; ++st) {
+    if (st % kStartGroup == 0 && st / kStartGroup == gs) {
+      v0 = s0.x;
+      v1 = s0.y;
+    }
+    const double mu = fma(alpha[base + st] * z, v1, -v0);
+    v0 = v1;
+    v1 = mu;
+    if (st >= q && ((st - q) & 1) == 0) {
+      const int l = m + st;
+      if (l >= lmin) Lb[(size_t)((st - q) >> 1) * npairs + p] = bl[l] * kappa[base + st] * mu * w;
+    }
+  }
+}
+
+// After C = L L^T (lower triangle, column-major, npad x npad per block): the
+// prior 1/C_l on kept rows, the identity on rows l < lmin and on padding.
+__global__ void k_pc_fix(const int* __restrict__ blocks, const int* __restrict__ bm, const int* __restrict__ bq,
+                         const int* __restrict__ bn, int lmin, const double* __restrict__ sinv_l, int npad,
+                         double* __restrict__ C) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npad) return;
+  const int blk = blocks[blockIdx.y];
+  const int m = bm[blk], q = bq[blk], n = bn[blk];
+  double* c = C + (size_t)blockIdx.y * npad * npad + (size_t)i * npad + i;
+  const int l = m + q + 2 * i;
+  if (i >= n || l < lmin)
+    *c = 1.0;
+  else
+    *c += sinv_l[l];
+}
+
+// Inverse (lower triangle from potri) -> full symmetric FP32 n x n per block.
+__global__ void k_pc_store(const int* __restrict__ blocks, const int* __restrict__ bn,
+                           const int64_t* __restrict__ boff, int npad, const double* __restrict__ C,
+                           float* __restrict__ inv) {
+  const int blk = blocks[blockIdx.z];
+  const int n = bn[blk];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i >= n || j >= n) return;
+  const double* c = C + (size_t)blockIdx.z * npad * npad;
+  const double v = i >= j ? c[(size_t)j * npad + i] : c[(size_t)i * npad + j];
+  inv[boff[blk] + (size_t)j * n + i] = (float)v;
+}
+
+// z = M^-1 r on the rows [r0, r0 + kPcRows) of one block, all columns.
+// Thread i accumulates row i; M^-1 is symmetric, so row i is read as column i
+// (consecutive threads read consecutive floats). r values of the block are
+// staged in LDS (FP32) in tiles of kPcJ rows x kPcCols columns (re, im).
+__global__ __launch_bounds__(kPcRows) void k_pc_apply(int nrhs, int64_t vlen, const int64_t* __restrict__ mstart,
+                                                      const int* __restrict__ task_b, const int* __restrict__ task_r0,
+                                                      const int* __restrict__ bm, const int* __restrict__ bq,
+                                                      const int* __restrict__ bn, const int64_t* __restrict__ boff,
+                                                      const float* __restrict__ inv, const double2* __restrict__ r,
+                                                      double2* __restrict__ z) {
+  __shared__ __attribute__((aligned(16))) float rs[kPcJ][2 * kPcCols];
+  const int b = task_b[blockIdx.x];
+  const int n = bn[b];
+  const int i = task_r0[blockIdx.x] + threadIdx.x;
+  const bool live = i < n;
+  const int64_t e0 = mstart[bm[b]] + bq[b];       // element of row j: e0 + 2 j
+  const float* __restrict__ A = inv + boff[b];
+  for (int c0 = 0; c0 < nrhs; c0 += kPcCols) {
+    const int nc = min(kPcCols, nrhs - c0);
+    float acc[2 * kPcCols];
+#pragma unroll
+    for (int k = 0; k < 2 * kPcCols; ++k) acc[k] = 0.f;
+    for (int j0 = 0; j0 < n; j0 += kPcJ) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < kPcJ * kPcCols; e += kPcRows) {
+        const int jj = e % kPcJ, cc = e / kPcJ, j = j0 + jj;
+        double2 v = make_double2(0.0, 0.0);
+        if (cc < nc && j < n) v = r[(int64_t)(c0 + cc) * vlen + e0 + 2 * j];
+        rs[jj][2 * cc] = (float)v.x;
+        rs[jj][2 * cc + 1] = (float)v.y;
+      }
+      __syncthreads();
+      const int jn = min(kPcJ, n - j0);
+      if (live) {
+        const float* __restrict__ Aj = A + (size_t)j0 * n + i;
+        for (int jj = 0; jj < jn; ++jj) {
+          const float a = Aj[(size_t)jj * n];
+          const float4* rv = reinterpret_cast<const float4*>(&rs[jj][0]);
+#pragma unroll
+          for (int k = 0; k < kPcCols / 2; ++k) {
+            const float4 t = rv[k];
+            acc[4 * k + 0] = fmaf(a, t.x, acc[4 * k + 0]);
+            acc[4 * k + 1] = fmaf(a, t.y, acc[4 * k + 1]);
+            acc[4 * k + 2] = fmaf(a, t.z, acc[4 * k + 2]);
+            acc[4 * k + 3] = fmaf(a, t.w, acc[4 * k + 3]);
+          }
+        }
+      }
+    }
+    if (live)
+      for (int cc = 0; cc < nc; ++cc)
+        z[(int64_t)(c0 + cc) * vlen + e0 + 2 * i] = make_double2((double)acc[2 * cc], (double)acc[2 * cc + 1]);
+  }
+}
+
+// partial <r, z> (row 0) and, with rr, <r, r> (row 1) per column
+__global__ void k_pc_dots(int64_t vlen, const int* __restrict__ idx_m, const double2* __restrict__ r,
+                          const double2* __restrict__ z, int rr, double* __restrict__ partial, int npart) {
+  __shared__ double sh[256];
+  const int c = blockIdx.y;
+  double rz = 0.0, r2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < vlen; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ci = c * vlen + i;
+    const int m = idx_m[i];
+    const double2 rv = r[ci];
+    rz += wdot(m, rv, z[ci]);
+    if (rr) r2 += wdot(m, rv, rv);
+  }
+  rz = block_sum(rz, sh);
+  if (rr) r2 = block_sum(r2, sh);
+  if (threadIdx.x == 0) {
+    double* pa = partial + (size_t)c * npart * 4;
+    pa[blockIdx.x] = rz;
+    if (rr) pa[npart + blockIdx.x] = r2;
+  }
+}
+
+template <typename T>
+int dev_alloc(T** p, size_t n) {
+  *p = nullptr;
+  if (hipMalloc((void**)p, (n ? n : 1) * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    return CR_ENOMEM;
+  }
+  return CR_OK;
+}
+
+template <typename T>
+int dev_upload(T** p, const std::vector<T>& h) {
+  int rc = dev_alloc(p, h.size());
+  if (rc) return rc;
+  return hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) == hipSuccess ? CR_OK : CR_EDEVICE;
+}
+
+}  // namespace
+
+void block_pc_free(BlockPC& pc) {
+  void* ptrs[] = {pc.inv, pc.bm, pc.bq, pc.bn, pc.boff, pc.task_b, pc.task_r0};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  pc = BlockPC();
+}
+
+int block_pc_build(crsht_plan* P, const double* bl, const double* cl, int lmin, double q, const double* ninv,
+                   hipStream_t s) {
+  const Geometry& g = P->g;
+  const int lmax = g.lmax, mmax = g.mmax, np = g.npairs;
+  BlockPC& pc = P->pc;
+  block_pc_free(pc);
+  // blocks (m, parity) with their sizes, compact FP32 offsets, application tasks
+  std::vector<int> bm, bq, bn;
+  std::vector<int64_t> boff;
+  int64_t off = 0;
+  for (int m = 0; m <= mmax; ++m)
+    for (int qq = 0; qq < 2; ++qq) {
+      if (m + qq > lmax) continue;
+      const int n = (lmax - m - qq) / 2 + 1;
+      bm.push_back(m);
+      bq.push_back(qq);
+      bn.push_back(n);
+      boff.push_back(off);
+      off += (int64_t)n * n;
+    }
+  const int nb = (int)bm.size();
+  std::vector<int> tb, tr;
+  for (int b = 0; b < nb; ++b)
+    for (int r0 = 0; r0 < bn[b]; r0 += kPcRows) {
+      tb.push_back(b);
+      tr.push_back(r0);
+    }
+  int rc;
+  if ((rc = dev_upload(&pc.bm, bm)) || (rc = dev_upload(&pc.bq, bq)) || (rc = dev_upload(&pc.bn, bn)) ||
+      (rc = dev_upload(&pc.boff, boff)) || (rc = dev_upload(&pc.task_b, tb)) || (rc = dev_upload(&pc.task_r0, tr)) ||
+      (rc = dev_alloc(&pc.inv, (size_t)off))) {
+    block_pc_free(pc);
+    return rc;
+  }
+  pc.nblocks = nb;
+  pc.ntasks = (int)tb.size();
+  pc.inv_elems = off;
+
+  // per-l inputs on the device: b_l and the prior 1 / (q C_l)
+  std::vector<double> hb(lmax + 1), hs(lmax + 1, 0.0);
+  for (int l = 0; l <= lmax; ++l) {
+    hb[l] = bl[l];
+    if (l >= lmin) hs[l] = 1.0 / (q * cl[l]);
+  }
+  double *dbl = nullptr, *dsinv = nullptr, *L = nullptr, *C = nullptr;
+  int *dblocks = nullptr, *dinfo = nullptr;
+  rocblas_handle h = nullptr;
+  auto cleanup = [&]() {
+    if (h) (void)rocblas_destroy_handle(h);
+    void* ptrs[] = {dbl, dsinv, L, C, dblocks, dinfo};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+  };
+  // buckets of equal padded size, processed in batches bounded by memory
+  std::vector<std::vector<int>> buckets((lmax + 2) / kPad + 2);
+  for (int b = 0; b < nb; ++b) buckets[(bn[b] + kPad - 1) / kPad].push_back(b);
+  const size_t budget = (size_t)1 << 29;   // bytes of L per batch
+  size_t maxL = 0, maxC = 0, maxb = 0;
+  for (size_t k = 0; k < buckets.size(); ++k) {
+    if (buckets[k].empty()) continue;
+    const size_t npad = k * kPad;
+    const size_t per = std::max<size_t>(1, budget / (npad * np * sizeof(double)));
+    const size_t cnt = std::min(per, buckets[k].size());
+    maxL = std::max(maxL, cnt * npad * np);
+    maxC = std::max(maxC, cnt * npad * npad);
+    maxb = std::max(maxb, cnt);
+  }
+  if ((rc = dev_upload(&dbl, hb)) || (rc = dev_upload(&dsinv, hs)) || (rc = dev_alloc(&L, maxL)) ||
+      (rc = dev_alloc(&C, maxC)) || (rc = dev_alloc(&dblocks, maxb)) || (rc = dev_alloc(&dinfo, maxb))) {
+    cleanup();
+    block_pc_free(pc);
+    return rc;
+  }
+  if (rocblas_create_handle(&h) != rocblas_status_success || rocblas_set_stream(h, s) != rocblas_status_success) {
+    cleanup();
+    block_pc_free(pc);
+    return CR_EDEVICE;
+  }
+  // ring sums of N^-1 over both rings of each pair
+  if (launch_ring_weights(P, ninv, P->w.ring_w, s) != hipSuccess) {
+    cleanup();
+    block_pc_free(pc);
+    return CR_EDEVICE;
+  }
+  int status = CR_OK;
+  std::vector<int> hinfo;
+  for (size_t k = 0; k < buckets.size() && status == CR_OK; ++k) {
+    if (buckets[k].empty()) continue;   // (k = 0 is always empty: every block has n >= 1)
+    const int npad = (int)k * kPad;
+    const std::vector<int>& bl_k = buckets[k];
+    const size_t per = std::max<size_t>(1, budget / ((size_t)npad * np * sizeof(double)));
+    for (size_t a = 0; a < bl_k.size() && status == CR_OK; a += per) {
+      const int cnt = (int)std::min(per, bl_k.size() - a);
+      const std::vector<int> ids(bl_k.begin() + a, bl_k.begin() + a + cnt);
+      bool ok = hipMemcpyAsync(dblocks, ids.data(), cnt * sizeof(int), hipMemcpyHostToDevice, s) == hipSuccess;
+      ok = ok && hipMemsetAsync(L, 0, (size_t)cnt * npad * np * sizeof(double), s) == hipSuccess;
+      if (ok) {
+        hipLaunchKernelGGL(k_pc_lambda, dim3((np + 255) / 256, cnt), dim3(256), 0, s, lmax, np, lmin, P->t.pair_z,
+                           P->t.rec_alpha, P->t.rec_kappa, P->t.lst_g, P->t.lst_s, P->t.mstart, P->w.ring_w, dbl,
+                           dblocks, pc.bm, pc.bq, npad, L);
+        ok = hipGetLastError() == hipSuccess;
+      }
+      const double one = 1.0, zero = 0.0;
+      // C = L L^T: L is row-major [npad][np], i.e. column-major np x npad, so C = A^T A
+      ok = ok && rocblas_dsyrk_strided_batched(h, rocblas_fill_lower, rocblas_operation_transpose, npad, np, &one, L,
+                                               np, (rocblas_stride)npad * np, &zero, C, npad,
+                                               (rocblas_stride)npad * npad, cnt) == rocblas_status_success;
+      if (ok) {
+        hipLaunchKernelGGL(k_pc_fix, dim3((npad + 255) / 256, cnt), dim3(256), 0, s, dblocks, pc.bm, pc.bq, pc.bn,
+                           lmin, dsinv, npad, C);
+        ok = hipGetLastError() == hipSuccess;
+      }
+      ok = ok && rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, npad, C, npad, (rocblas_stride)npad * npad,
+                                                  dinfo, cnt) == rocblas_status_success;
+      hinfo.assign(cnt, 0);
+      ok = ok && hipMemcpyAsync(hinfo.data(), dinfo, cnt * sizeof(int), hipMemcpyDeviceToHost, s) == hipSuccess &&
+           hipStreamSynchronize(s) == hipSuccess;
+      if (!ok) {
+        status = CR_EDEVICE;
+        break;
+      }
+      for (int v : hinfo)
+        if (v != 0) status = CR_EINVAL;   // a block is not positive definite
+      if (status != CR_OK) break;
+      ok = rocsolver_dpotri_strided_batched(h, rocblas_fill_lower, npad, C, npad, (rocblas_stride)npad * npad, dinfo,
+                                            cnt) == rocblas_status_success;
+      if (ok) {
+        hipLaunchKernelGGL(k_pc_store, dim3((npad + 255) / 256, npad, cnt), dim3(256), 0, s, dblocks, pc.bn, pc.boff,
+                           npad, C, pc.inv);
+        ok = hipGetLastError() == hipSuccess;
+      }
+      ok = ok && hipStreamSynchronize(s) == hipSuccess;   // scratch is reused by the next batch
+      if (!ok) status = CR_EDEVICE;
+    }
+  }
+  cleanup();
+  if (status != CR_OK) {
+    block_pc_free(pc);
+    return status;
+  }
+  pc.built = true;
+  pc.lmin = lmin;
+  return CR_OK;
+}
+
+hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s) {
+  const BlockPC& pc = P->pc;
+  hipLaunchKernelGGL(k_pc_apply, dim3(pc.ntasks), dim3(kPcRows), 0, s, nrhs, vlen(P), P->t.mstart, pc.task_b,
+                     pc.task_r0, pc.bm, pc.bq, pc.bn, pc.boff, pc.inv, r, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_pc_dots(const crsht_plan* P, int nrhs, const double2* r, const double2* z, bool rr,
+                          hipStream_t s) {
+  const int nb = vec_reduce_blocks(P);
+  hipLaunchKernelGGL(k_pc_dots, dim3(nb, nrhs), dim3(256), 0, s, vlen(P), P->t.idx_mv, r, z, rr ? 1 : 0,
+                     P->w.partial, P->w.npart);
+  return hipGetLastError();
+}
+
+}  // namespace crsht

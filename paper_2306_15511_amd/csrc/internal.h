@@ -149,17 +149,32 @@ struct Timing {
 }  // namespace crsht
 
 namespace crsht {
+// Per-m block preconditioner (blockpc.hip): for each (m, parity q of l - m)
+// block of n rows l = m + q + 2 i, the FP32 inverse n x n (full symmetric) at
+// inv + boff[b]; application tasks cover kPcRows rows of one block each.
+struct BlockPC {
+  bool built = false;
+  int lmin = 0;
+  int nblocks = 0, ntasks = 0;
+  int64_t inv_elems = 0;
+  float* inv = nullptr;
+  int *bm = nullptr, *bq = nullptr, *bn = nullptr;
+  int64_t* boff = nullptr;
+  int *task_b = nullptr, *task_r0 = nullptr;
+};
+
 // identity of a captured PCG iteration block: replayed only for the same
 // launch sequence and arguments
 struct GraphKey {
   int kind = -1;            // 0: FP64 PCG block, 1: mixed PCG block
   int nrhs = 0, n = 0;      // columns, iterations in the block
   int first_update = 0;     // mixed: the block starts with a pending direction update
+  int pc = 0;               // block preconditioner in use
   const void* ninv = nullptr;
   double tol = 0.0;
   bool operator==(const GraphKey& o) const {
-    return kind == o.kind && nrhs == o.nrhs && n == o.n && first_update == o.first_update && ninv == o.ninv &&
-           tol == o.tol;
+    return kind == o.kind && nrhs == o.nrhs && n == o.n && first_update == o.first_update && pc == o.pc &&
+           ninv == o.ninv && tol == o.tol;
   }
 };
 }  // namespace crsht
@@ -169,6 +184,7 @@ struct crsht_plan {
   hipStream_t cap_stream = nullptr;     // stream used only to capture iteration blocks
   hipGraphExec_t graph_exec = nullptr;  // last captured block
   crsht::GraphKey graph_key;
+  crsht::BlockPC pc;                    // per-m block preconditioner (built on request)
   int ncomp = 1;
   int nrhs_max = 1;
   int device = 0;
@@ -270,6 +286,18 @@ hipError_t launch_rhs_finish_tqu(const crsht_plan* P, int nrhs, const double2* d
 hipError_t launch_diag_tqu(const crsht_plan* P, const double2* rawt, const double2* rawp, double* diag,
                            hipStream_t s);
 
+// ---- per-m block preconditioner (blockpc.hip) ----
+// build from b_l, C_l (host, scaled by q) and N^-1 (device); allocates the
+// plan's preconditioner storage; CR_EINVAL if a block is not positive definite
+int block_pc_build(crsht_plan* P, const double* bl, const double* cl, int lmin, double q, const double* ninv,
+                   hipStream_t s);
+void block_pc_free(BlockPC& pc);
+// z = M^-1 r per column (r, z: [nrhs][nalm])
+hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s);
+// partial <r, z> (row 0) and, with rr, <r, r> (row 1), nb = vec_reduce_blocks
+hipError_t launch_pc_dots(const crsht_plan* P, int nrhs, const double2* r, const double2* z, bool rr,
+                          hipStream_t s);
+
 // ---- vector kernels (vec.hip) ----
 // Reductions write per-block partial sums to w.partial (column c, row r at
 // partial[(c * 4 + r) * npart + block]) and a one-block kernel sums them.
@@ -295,12 +323,15 @@ hipError_t launch_map_axpby(int64_t n, double a, const double* x, double b, cons
                             hipStream_t s);
 hipError_t launch_alm_axpby(int64_t n, double a, const double2* x, double b, const double2* y, double2* out,
                             hipStream_t s);
+// zgiven: z already holds the preconditioned residual (block preconditioner)
 hipError_t launch_cg_start(const crsht_plan* P, int nrhs, const double2* b, const double2* r, double2* z,
-                           double2* p, double2* pt, hipStream_t s);
+                           double2* p, double2* pt, hipStream_t s, bool zgiven = false);
 hipError_t launch_cg_scalars(const crsht_plan* P, int nrhs, int what, int nb, double tol, int restart,
                              hipStream_t s);
+// noz == false: z = r / D with <r, z> in row 0; true: z untouched, row 0 = 0
+// (the block preconditioner and launch_pc_dots follow)
 hipError_t launch_cg_update(const crsht_plan* P, int nrhs, double2* x, double2* r, double2* z, const double2* p,
-                            const double2* q, hipStream_t s);
+                            const double2* q, hipStream_t s, bool noz = false);
 hipError_t launch_cg_replace(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s);
 hipError_t launch_cg_pupdate(const crsht_plan* P, int nrhs, const double2* z, double2* p, double2* pt,
                              hipStream_t s);

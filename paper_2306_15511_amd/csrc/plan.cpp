@@ -83,6 +83,7 @@ void free_plan_memory(crsht_plan* P) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (P->w.host_scal) (void)hipHostFree(P->w.host_scal);
+  crsht::block_pc_free(P->pc);
   if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
   P->graph_exec = nullptr;

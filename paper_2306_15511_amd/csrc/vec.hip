@@ -144,7 +144,7 @@ __global__ void k_cg_start(int64_t nalm, const int* __restrict__ idx_m, const do
                            const double* __restrict__ bk, const double2* __restrict__ b,
                            const double2* __restrict__ r, double2* __restrict__ z, double2* __restrict__ p,
                            double2* __restrict__ pt, double* __restrict__ partial, int npart,
-                           const double* __restrict__ scal) {
+                           const double* __restrict__ scal, int zgiven) {
   __shared__ double sh[kVecBlock];
   const int c = blockIdx.y;
   double rz = 0.0, rr = 0.0, bb = 0.0;
@@ -153,9 +153,14 @@ __global__ void k_cg_start(int64_t nalm, const int* __restrict__ idx_m, const do
       const int64_t ci = c * nalm + i;
       const int m = idx_m[i];
       const double2 rv = r[ci];
-      const double dinv = 1.0 / diag[i];
-      double2 zv = make_double2(rv.x * dinv, rv.y * dinv);
-      z[ci] = zv;
+      double2 zv;
+      if (zgiven) {
+        zv = z[ci];
+      } else {
+        const double dinv = 1.0 / diag[i];
+        zv = make_double2(rv.x * dinv, rv.y * dinv);
+        z[ci] = zv;
+      }
       p[ci] = zv;
       pt[ci] = make_double2(bk[i] * zv.x, bk[i] * zv.y);
       rz += wdot(m, rv, zv);
@@ -244,7 +249,7 @@ __global__ void k_cg_scalars(int what, int nb, const double* __restrict__ partia
 __global__ void k_cg_update(int64_t nalm, const int* __restrict__ idx_m, const double* __restrict__ diag,
                             const double* __restrict__ bk, double2* __restrict__ x, double2* __restrict__ r,
                             double2* __restrict__ z, const double2* __restrict__ p, const double2* __restrict__ q,
-                            double* __restrict__ partial, int npart, const double* __restrict__ scal) {
+                            double* __restrict__ partial, int npart, const double* __restrict__ scal, int noz) {
   __shared__ double sh[kVecBlock];
   const int c = blockIdx.y;
   const double* sc = scal + c * kScalSlots;
@@ -263,10 +268,12 @@ __global__ void k_cg_update(int64_t nalm, const int* __restrict__ idx_m, const d
       rv.y = fma(-a, qv.y, rv.y);
       x[ci] = xv;
       r[ci] = rv;
-      const double dinv = 1.0 / diag[i];
-      const double2 zv = make_double2(rv.x * dinv, rv.y * dinv);
-      z[ci] = zv;
-      rz += wdot(m, rv, zv);
+      if (!noz) {
+        const double dinv = 1.0 / diag[i];
+        const double2 zv = make_double2(rv.x * dinv, rv.y * dinv);
+        z[ci] = zv;
+        rz += wdot(m, rv, zv);
+      }
       rr += wdot(m, rv, rv);
     }
   }
@@ -569,10 +576,10 @@ hipError_t launch_alm_axpby(int64_t n, double a, const double2* x, double b, con
 }
 
 hipError_t launch_cg_start(const crsht_plan* P, int nrhs, const double2* b, const double2* r, double2* z,
-                           double2* p, double2* pt, hipStream_t s) {
+                           double2* p, double2* pt, hipStream_t s, bool zgiven) {
   const int nb = vec_reduce_blocks(P);
   hipLaunchKernelGGL(k_cg_start, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, P->w.diag,
-                     P->w.bk, b, r, z, p, pt, P->w.partial, P->w.npart, P->w.scal);
+                     P->w.bk, b, r, z, p, pt, P->w.partial, P->w.npart, P->w.scal, zgiven ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -598,10 +605,10 @@ hipError_t launch_diag(const crsht_plan* P, const double2* raw, double* diag, hi
 }
 
 hipError_t launch_cg_update(const crsht_plan* P, int nrhs, double2* x, double2* r, double2* z, const double2* p,
-                            const double2* q, hipStream_t s) {
+                            const double2* q, hipStream_t s, bool noz) {
   const int nb = vec_reduce_blocks(P);
   hipLaunchKernelGGL(k_cg_update, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, P->w.diag,
-                     P->w.bk, x, r, z, p, q, P->w.partial, P->w.npart, P->w.scal);
+                     P->w.bk, x, r, z, p, q, P->w.partial, P->w.npart, P->w.scal, noz ? 1 : 0);
   return hipGetLastError();
 }
 
