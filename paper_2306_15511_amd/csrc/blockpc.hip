@@ -19,7 +19,8 @@
 // and the inverse computed with rocSOLVER (Cholesky, then inverse from the
 // factor); the inverses are stored in FP32, full symmetric, per block.
 // Application (every PCG iteration): z_mq = M_mq^-1 r_mq for the real and
-// imaginary parts of every column, one workgroup per 256 rows of a block.
+// imaginary parts of every column on the matrix cores (FP32), one workgroup
+// per 256 rows of a block.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -34,10 +35,13 @@ namespace {
 
 constexpr int kStartGroup = 16;   // start-table group of the Legendre recurrence
 constexpr int kNeverG = 0x7fffffff;
-constexpr int kPcRows = 256;      // rows of a block per application workgroup
+constexpr int kPcRows = 256;      // rows of a block per application workgroup (8 wavefronts x 32)
 constexpr int kPcCols = 16;       // right-hand sides per application pass
-constexpr int kPcJ = 64;          // r values staged per LDS tile
+constexpr int kPcJ = 128;         // r rows staged per LDS tile
 constexpr int kPad = 32;          // bucket granularity of the padded block size
+
+// leading dimension (floats) of a stored inverse of n rows: 16-byte aligned rows
+__host__ __device__ __forceinline__ int pc_ld(int n) { return (n + 3) & ~3; }
 
 // L[i][p] = b_l kappa_lm mu_lm(z_p) sqrt(W_p) for the rows l = m + q + 2 i of
 // block blk (0 for l < lmin); the recurrence and its start state are those of
@@ -95,7 +99,8 @@ __global__ void k_pc_fix(const int* __restrict__ blocks, const int* __restrict__
     *c += sinv_l[l];
 }
 
-// Inverse (lower triangle from potri) -> full symmetric FP32 n x n per block.
+// Inverse (lower triangle from potri) -> full symmetric FP32 n x n per block
+// (leading dimension pc_ld(n)).
 __global__ void k_pc_store(const int* __restrict__ blocks, const int* __restrict__ bn,
                            const int64_t* __restrict__ boff, int npad, const double* __restrict__ C,
                            float* __restrict__ inv) {
@@ -105,34 +110,44 @@ __global__ void k_pc_store(const int* __restrict__ blocks, const int* __restrict
   if (i >= n || j >= n) return;
   const double* c = C + (size_t)blockIdx.z * npad * npad;
   const double v = i >= j ? c[(size_t)j * npad + i] : c[(size_t)i * npad + j];
-  inv[boff[blk] + (size_t)j * n + i] = (float)v;
+  inv[boff[blk] + (size_t)j * pc_ld(n) + i] = (float)v;
 }
 
-// z = M^-1 r on the rows [r0, r0 + kPcRows) of one block, all columns.
-// Thread i accumulates row i; M^-1 is symmetric, so row i is read as column i
-// (consecutive threads read consecutive floats). r values of the block are
-// staged in LDS (FP32) in tiles of kPcJ rows x kPcCols columns (re, im).
-__global__ __launch_bounds__(kPcRows) void k_pc_apply(int nrhs, int64_t vlen, const int64_t* __restrict__ mstart,
-                                                      const int* __restrict__ task_b, const int* __restrict__ task_r0,
-                                                      const int* __restrict__ bm, const int* __restrict__ bq,
-                                                      const int* __restrict__ bn, const int64_t* __restrict__ boff,
-                                                      const float* __restrict__ inv, const double2* __restrict__ r,
-                                                      double2* __restrict__ z) {
-  __shared__ __attribute__((aligned(16))) float rs[kPcJ][2 * kPcCols];
+// z = M^-1 r on the rows [r0, r0 + kPcRows) of one block, all columns, on
+// the matrix cores: wavefront w computes the 32-row tile i0 = r0 + 32 w of
+// Z = M^-1 R for 16 right-hand sides (32 real columns) with
+// v_mfma_f32_32x32x2_f32. Per LDS tile of kPcJ rows j of R (FP32, rows padded
+// to 33 floats so the staging writes spread over the banks), the two K
+// slots of an MFMA take j = j0 + t and j = j0 + kPcJ / 2 + t, so that every
+// lane reads its row of M^-1 (stored with a 16-byte aligned leading
+// dimension ld) as contiguous float4 runs.
+// MFMA 32x32x2 f32 lane layout: A[i][k] in lane i + 32 k, B[k][c] in lane
+// c + 32 k, D[i][c] in lane c + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4.
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+__global__ __launch_bounds__(kPcRows * 2) void k_pc_apply(int nrhs, int64_t vlen, const int64_t* __restrict__ mstart,
+                                                          const int* __restrict__ task_b,
+                                                          const int* __restrict__ task_r0, const int* __restrict__ bm,
+                                                          const int* __restrict__ bq, const int* __restrict__ bn,
+                                                          const int64_t* __restrict__ boff,
+                                                          const float* __restrict__ inv,
+                                                          const double2* __restrict__ r, double2* __restrict__ z) {
+  constexpr int kHalf = kPcJ / 2;
+  __shared__ float rs[kPcJ][33];
   const int b = task_b[blockIdx.x];
   const int n = bn[b];
-  const int i = task_r0[blockIdx.x] + threadIdx.x;
-  const bool live = i < n;
+  const int ld = pc_ld(n);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int il = lane & 31, kk = lane >> 5;
+  const int i0 = task_r0[blockIdx.x] + 32 * w;
+  const bool rowok = i0 + il < n;
   const int64_t e0 = mstart[bm[b]] + bq[b];       // element of row j: e0 + 2 j
-  const float* __restrict__ A = inv + boff[b];
+  const float* __restrict__ Arow = inv + boff[b] + (size_t)(rowok ? i0 + il : 0) * ld;
   for (int c0 = 0; c0 < nrhs; c0 += kPcCols) {
     const int nc = min(kPcCols, nrhs - c0);
-    float acc[2 * kPcCols];
-#pragma unroll
-    for (int k = 0; k < 2 * kPcCols; ++k) acc[k] = 0.f;
+    f32x16_t acc = {};
     for (int j0 = 0; j0 < n; j0 += kPcJ) {
       __syncthreads();
-      for (int e = threadIdx.x; e < kPcJ * kPcCols; e += kPcRows) {
+      for (int e = threadIdx.x; e < kPcJ * kPcCols; e += blockDim.x) {
         const int jj = e % kPcJ, cc = e / kPcJ, j = j0 + jj;
         double2 v = make_double2(0.0, 0.0);
         if (cc < nc && j < n) v = r[(int64_t)(c0 + cc) * vlen + e0 + 2 * j];
@@ -140,26 +155,36 @@ __global__ __launch_bounds__(kPcRows) void k_pc_apply(int nrhs, int64_t vlen, co
         rs[jj][2 * cc + 1] = (float)v.y;
       }
       __syncthreads();
-      const int jn = min(kPcJ, n - j0);
-      if (live) {
-        const float* __restrict__ Aj = A + (size_t)j0 * n + i;
-        for (int jj = 0; jj < jn; ++jj) {
-          const float a = Aj[(size_t)jj * n];
-          const float4* rv = reinterpret_cast<const float4*>(&rs[jj][0]);
+      if (i0 < n) {
+        const int jb = j0 + kk * kHalf;                 // this lane's K slot: rows jb .. jb + kHalf - 1
+        const float4* __restrict__ A4 = reinterpret_cast<const float4*>(Arow + jb);
 #pragma unroll
-          for (int k = 0; k < kPcCols / 2; ++k) {
-            const float4 t = rv[k];
-            acc[4 * k + 0] = fmaf(a, t.x, acc[4 * k + 0]);
-            acc[4 * k + 1] = fmaf(a, t.y, acc[4 * k + 1]);
-            acc[4 * k + 2] = fmaf(a, t.z, acc[4 * k + 2]);
-            acc[4 * k + 3] = fmaf(a, t.w, acc[4 * k + 3]);
+        for (int t0 = 0; t0 < kHalf; t0 += 16) {
+          float4 av[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int jp = jb + t0 + 4 * v;             // padding columns n .. ld - 1 hold zeros
+            av[v] = (rowok && jp < ld) ? A4[t0 / 4 + v] : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const float4 q4 = av[u / 4];
+            const float a = (u % 4 == 0) ? q4.x : (u % 4 == 1) ? q4.y : (u % 4 == 2) ? q4.z : q4.w;
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, rs[kk * kHalf + t0 + u][il], acc, 0, 0, 0);
           }
         }
       }
     }
-    if (live)
-      for (int cc = 0; cc < nc; ++cc)
-        z[(int64_t)(c0 + cc) * vlen + e0 + 2 * i] = make_double2((double)acc[2 * cc], (double)acc[2 * cc + 1]);
+    if (i0 < n) {
+      const int rhs = il >> 1, comp = il & 1;
+      if (rhs < nc) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int row = i0 + 8 * (q / 4) + 4 * kk + (q % 4);
+          if (row < n) reinterpret_cast<double*>(z + (int64_t)(c0 + rhs) * vlen + e0 + 2 * row)[comp] = acc[q];
+        }
+      }
+    }
   }
 }
 
@@ -229,7 +254,7 @@ int block_pc_build(crsht_plan* P, const double* bl, const double* cl, int lmin, 
       bq.push_back(qq);
       bn.push_back(n);
       boff.push_back(off);
-      off += (int64_t)n * n;
+      off += (int64_t)n * pc_ld(n);
     }
   const int nb = (int)bm.size();
   std::vector<int> tb, tr;
@@ -248,6 +273,11 @@ int block_pc_build(crsht_plan* P, const double* bl, const double* cl, int lmin, 
   pc.nblocks = nb;
   pc.ntasks = (int)tb.size();
   pc.inv_elems = off;
+  // padding columns n .. ld - 1 of every row stay zero (read by the application kernel)
+  if (hipMemsetAsync(pc.inv, 0, (size_t)off * sizeof(float), s) != hipSuccess) {
+    block_pc_free(pc);
+    return CR_EDEVICE;
+  }
 
   // per-l inputs on the device: b_l and the prior 1 / (q C_l)
   std::vector<double> hb(lmax + 1), hs(lmax + 1, 0.0);
@@ -358,7 +388,7 @@ int block_pc_build(crsht_plan* P, const double* bl, const double* cl, int lmin, 
 
 hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s) {
   const BlockPC& pc = P->pc;
-  hipLaunchKernelGGL(k_pc_apply, dim3(pc.ntasks), dim3(kPcRows), 0, s, nrhs, vlen(P), P->t.mstart, pc.task_b,
+  hipLaunchKernelGGL(k_pc_apply, dim3(pc.ntasks), dim3(kPcRows * 2), 0, s, nrhs, vlen(P), P->t.mstart, pc.task_b,
                      pc.task_r0, pc.bm, pc.bq, pc.bn, pc.boff, pc.inv, r, z);
   return hipGetLastError();
 }
