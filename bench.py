@@ -311,7 +311,7 @@ def main():
     # every launch of the tracked kernels (direct launches, no graph replay)
     crsht.timing_enable(plan, True)
     _, st = step()
-    tm = {k: crsht.timing_read(plan, k) for k in range(5)}
+    tm = {k: crsht.timing_read(plan, k) for k in range(6)}
     crsht.timing_enable(plan, False)
     print("kernel-timing step: iters %s" % [s.iters for s in st], file=sys.stderr, flush=True)
 
@@ -351,6 +351,11 @@ def main():
                 FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s", "legendre.hip")
     kinfo[1] = ("k_legendre_adj (FP64 VALU, whole transform)", "alu", sum((3 + 4 * g) * T for g in ga),
                 FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s", "legendre.hip")
+    if use_block:
+        # stored inverses (FP32, sum of n^2 over the (m, parity) blocks) + r read + z written
+        sn2 = sum(((lmax - m - q) // 2 + 1) ** 2 for m in range(lmax + 1) for q in (0, 1) if m + q <= lmax)
+        kinfo[5] = ("k_pc_apply (block preconditioner, FP32 MFMA)", "hbm",
+                    4 * sn2 + 2 * R * plan.vlen * 16, HBM_PEAK_GBS, "GB/s", "blockpc.hip")
     roofs = {}
     for kid, (name, bound, work, peak, unit, src) in kinfo.items():
         ms, nl = tm[kid]

@@ -324,7 +324,8 @@ int cr_grad_lnpi(const crsht_plan *plan, const cr_problem *prob, const double *d
  * pair of HIP events on the launch stream; 0 turns it off. Tracked kernels:
  * 0 = FP64 Legendre synthesis, 1 = FP64 Legendre adjoint (incl. the
  * preconditioner diagonal pass), 2 = ring (azimuthal FFT) pass,
- * 3 = bf16x3 MFMA Legendre synthesis, 4 = bf16x3 MFMA Legendre adjoint.
+ * 3 = bf16x3 MFMA Legendre synthesis, 4 = bf16x3 MFMA Legendre adjoint,
+ * 5 = block preconditioner application.
  * crsht_timing_read waits for the recorded events and returns the summed
  * duration (milliseconds) and the number of launches since enabling. */
 int crsht_timing_enable(const crsht_plan *plan, int on);

@@ -201,6 +201,7 @@ class Plan:
 
 KERNEL_LEGENDRE_SYNTH, KERNEL_LEGENDRE_ADJOINT, KERNEL_RING = 0, 1, 2
 KERNEL_MFMA_SYNTH, KERNEL_MFMA_ADJOINT = 3, 4
+KERNEL_BLOCK_PC = 5
 
 
 def timing_enable(plan: Plan, on: bool = True):

@@ -20,7 +20,7 @@
 // factor); the inverses are stored in FP32, full symmetric, per block.
 // Application (every PCG iteration): z_mq = M_mq^-1 r_mq for the real and
 // imaginary parts of every column on the matrix cores (FP32), one workgroup
-// per 256 rows of a block.
+// per 256 rows of a block (128 per wavefront).
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -35,9 +35,10 @@ namespace {
 
 constexpr int kStartGroup = 16;   // start-table group of the Legendre recurrence
 constexpr int kNeverG = 0x7fffffff;
-constexpr int kPcRows = 256;      // rows of a block per application workgroup (8 wavefronts x 32)
+constexpr int kPcWaves = 2;       // wavefronts per application workgroup
+constexpr int kPcRows = 128 * kPcWaves;   // rows of a block per application workgroup (128 per wavefront)
 constexpr int kPcCols = 16;       // right-hand sides per application pass
-constexpr int kPcJ = 128;         // r rows staged per LDS tile
+constexpr int kPcJ = 64;          // r rows staged per LDS tile
 constexpr int kPad = 32;          // bucket granularity of the padded block size
 
 // leading dimension (floats) of a stored inverse of n rows: 16-byte aligned rows
@@ -113,75 +114,106 @@ __global__ void k_pc_store(const int* __restrict__ blocks, const int* __restrict
   inv[boff[blk] + (size_t)j * pc_ld(n) + i] = (float)v;
 }
 
-// z = M^-1 r on the rows [r0, r0 + kPcRows) of one block, all columns, on
-// the matrix cores: wavefront w computes the 32-row tile i0 = r0 + 32 w of
-// Z = M^-1 R for 16 right-hand sides (32 real columns) with
-// v_mfma_f32_32x32x2_f32. Per LDS tile of kPcJ rows j of R (FP32, rows padded
-// to 33 floats so the staging writes spread over the banks), the two K
-// slots of an MFMA take j = j0 + t and j = j0 + kPcJ / 2 + t, so that every
-// lane reads its row of M^-1 (stored with a 16-byte aligned leading
-// dimension ld) as contiguous float4 runs.
+// z = M^-1 r for one block and 16 right-hand sides (32 real columns) on the
+// matrix cores (v_mfma_f32_32x32x2_f32). Wavefront w of a workgroup owns the
+// rows [i0, i0 + 128), i0 = r0 + 128 w. Per K step (rows j, j + 1 of the
+// symmetric M^-1) lane l of half h loads the float4 M^-1[j + h][i0 + 4 l ..
+// i0 + 4 l + 3], so one load instruction reads two contiguous 512-byte runs;
+// component v of it is the A operand of the v-th of four MFMAs whose 32 output
+// rows are i0 + 4 t + v (t = 0 .. 31), each with its own accumulator. The B
+// operand R[j + h][c] comes from an LDS tile of kPcJ rows j (FP32; rows padded
+// to 33 floats so the staging writes spread over the banks). The A loads of
+// the next kPcPre K steps are in flight while the current ones are multiplied.
 // MFMA 32x32x2 f32 lane layout: A[i][k] in lane i + 32 k, B[k][c] in lane
 // c + 32 k, D[i][c] in lane c + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4.
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
-__global__ __launch_bounds__(kPcRows * 2) void k_pc_apply(int nrhs, int64_t vlen, const int64_t* __restrict__ mstart,
-                                                          const int* __restrict__ task_b,
-                                                          const int* __restrict__ task_r0, const int* __restrict__ bm,
-                                                          const int* __restrict__ bq, const int* __restrict__ bn,
-                                                          const int64_t* __restrict__ boff,
-                                                          const float* __restrict__ inv,
-                                                          const double2* __restrict__ r, double2* __restrict__ z) {
-  constexpr int kHalf = kPcJ / 2;
+constexpr int kPcPre = 4;          // K steps per prefetch group
+__global__ __launch_bounds__(kPcWaves * 64) void k_pc_apply(int nrhs, int64_t vlen, const int64_t* __restrict__ mstart,
+                                                            const int* __restrict__ task_b,
+                                                            const int* __restrict__ task_r0,
+                                                            const int* __restrict__ bm, const int* __restrict__ bq,
+                                                            const int* __restrict__ bn,
+                                                            const int64_t* __restrict__ boff,
+                                                            const float* __restrict__ inv,
+                                                            const double2* __restrict__ r, double2* __restrict__ z) {
+  constexpr int kSteps = kPcJ / 2;                      // K steps per LDS tile
+  constexpr int kR = kPcJ * kPcCols / (kPcWaves * 64);  // residual values staged per thread and tile
+  static_assert(kSteps % kPcPre == 0, "tile must hold whole prefetch groups");
   __shared__ float rs[kPcJ][33];
   const int b = task_b[blockIdx.x];
   const int n = bn[b];
   const int ld = pc_ld(n);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int il = lane & 31, kk = lane >> 5;
-  const int i0 = task_r0[blockIdx.x] + 32 * w;
-  const bool rowok = i0 + il < n;
-  const int64_t e0 = mstart[bm[b]] + bq[b];       // element of row j: e0 + 2 j
-  const float* __restrict__ Arow = inv + boff[b] + (size_t)(rowok ? i0 + il : 0) * ld;
+  const int i0 = task_r0[blockIdx.x] + 128 * w;
+  const int ic = i0 + 4 * il;                           // first of this lane's 4 rows
+  const bool colok = ic < ld;                           // padding rows n .. ld - 1 hold zeros
+  const int64_t e0 = mstart[bm[b]] + bq[b];             // element of row j: e0 + 2 j
+  const float* __restrict__ Ab = inv + boff[b] + (colok ? ic : 0);
+  const int ntile = (n + kPcJ - 1) / kPcJ;
   for (int c0 = 0; c0 < nrhs; c0 += kPcCols) {
     const int nc = min(kPcCols, nrhs - c0);
-    f32x16_t acc = {};
-    for (int j0 = 0; j0 < n; j0 += kPcJ) {
-      __syncthreads();
-      for (int e = threadIdx.x; e < kPcJ * kPcCols; e += blockDim.x) {
-        const int jj = e % kPcJ, cc = e / kPcJ, j = j0 + jj;
-        double2 v = make_double2(0.0, 0.0);
-        if (cc < nc && j < n) v = r[(int64_t)(c0 + cc) * vlen + e0 + 2 * j];
-        rs[jj][2 * cc] = (float)v.x;
-        rs[jj][2 * cc + 1] = (float)v.y;
+    f32x16_t acc0 = {}, acc1 = {}, acc2 = {}, acc3 = {};
+    // groups of kPcPre K steps over all j; a new LDS tile every kSteps / kPcPre
+    // groups; the A operands of group G + 1 are requested before the products of G
+    constexpr int kGpt = kSteps / kPcPre;
+    const int ngrp = ntile * kGpt;
+    const bool live = colok && i0 < n;
+    float4 an[kPcPre];
+    auto fetch = [&](int G) {
+      const int jg = 2 * G * kPcPre + kk;
+#pragma unroll
+      for (int u = 0; u < kPcPre; ++u) {
+        const int j = jg + 2 * u;
+        an[u] = (live && j < n) ? *reinterpret_cast<const float4*>(Ab + (size_t)j * ld) : make_float4(0.f, 0.f, 0.f, 0.f);
       }
-      __syncthreads();
+    };
+    fetch(0);
+#pragma unroll 1
+    for (int G = 0; G < ngrp; ++G) {
+      const int g0 = G % kGpt;
+      if (g0 == 0) {
+        const int j0 = (G / kGpt) * kPcJ;
+        __syncthreads();                                // previous tile's products have read rs
+#pragma unroll
+        for (int k = 0; k < kR; ++k) {
+          const int e = threadIdx.x + k * kPcWaves * 64;
+          const int jj = e % kPcJ, cc = e / kPcJ, j = j0 + jj;
+          const double2 v = (cc < nc && j < n) ? r[(int64_t)(c0 + cc) * vlen + e0 + 2 * j] : make_double2(0.0, 0.0);
+          rs[jj][2 * cc] = (float)v.x;
+          rs[jj][2 * cc + 1] = (float)v.y;
+        }
+        __syncthreads();
+      }
+      float4 ac[kPcPre];
+#pragma unroll
+      for (int u = 0; u < kPcPre; ++u) ac[u] = an[u];
+      if (G + 1 < ngrp) fetch(G + 1);
       if (i0 < n) {
-        const int jb = j0 + kk * kHalf;                 // this lane's K slot: rows jb .. jb + kHalf - 1
-        const float4* __restrict__ A4 = reinterpret_cast<const float4*>(Arow + jb);
 #pragma unroll
-        for (int t0 = 0; t0 < kHalf; t0 += 16) {
-          float4 av[4];
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int jp = jb + t0 + 4 * v;             // padding columns n .. ld - 1 hold zeros
-            av[v] = (rowok && jp < ld) ? A4[t0 / 4 + v] : make_float4(0.f, 0.f, 0.f, 0.f);
-          }
-#pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const float4 q4 = av[u / 4];
-            const float a = (u % 4 == 0) ? q4.x : (u % 4 == 1) ? q4.y : (u % 4 == 2) ? q4.z : q4.w;
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, rs[kk * kHalf + t0 + u][il], acc, 0, 0, 0);
-          }
+        for (int u = 0; u < kPcPre; ++u) {
+          const float bval = rs[2 * (g0 * kPcPre + u) + kk][il];
+          acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[u].x, bval, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[u].y, bval, acc1, 0, 0, 0);
+          acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[u].z, bval, acc2, 0, 0, 0);
+          acc3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[u].w, bval, acc3, 0, 0, 0);
         }
       }
     }
     if (i0 < n) {
       const int rhs = il >> 1, comp = il & 1;
       if (rhs < nc) {
+        // row i0 + 16 kk + rr, rr = 4 (8 (q / 4) + q % 4) + v: one base pointer, constant offsets
+        const int ib = i0 + 16 * kk;
+        double* __restrict__ zb = reinterpret_cast<double*>(z + (int64_t)(c0 + rhs) * vlen + e0 + 2 * ib) + comp;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const int row = i0 + 8 * (q / 4) + 4 * kk + (q % 4);
-          if (row < n) reinterpret_cast<double*>(z + (int64_t)(c0 + rhs) * vlen + e0 + 2 * row)[comp] = acc[q];
+        for (int v = 0; v < 4; ++v) {
+          const f32x16_t a = v == 0 ? acc0 : v == 1 ? acc1 : v == 2 ? acc2 : acc3;
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const int rr = 4 * (8 * (q / 4) + (q % 4)) + v;
+            if (ib + rr < n) zb[4 * rr] = a[q];
+          }
         }
       }
     }
@@ -388,8 +420,10 @@ int block_pc_build(crsht_plan* P, const double* bl, const double* cl, int lmin, 
 
 hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s) {
   const BlockPC& pc = P->pc;
-  hipLaunchKernelGGL(k_pc_apply, dim3(pc.ntasks), dim3(kPcRows * 2), 0, s, nrhs, vlen(P), P->t.mstart, pc.task_b,
+  timing_begin(P, 5, s);
+  hipLaunchKernelGGL(k_pc_apply, dim3(pc.ntasks), dim3(kPcWaves * 64), 0, s, nrhs, vlen(P), P->t.mstart, pc.task_b,
                      pc.task_r0, pc.bm, pc.bq, pc.bn, pc.boff, pc.inv, r, z);
+  timing_end(P, 5, s);
   return hipGetLastError();
 }
 

@@ -135,8 +135,9 @@ enum ScalSlot {
 };
 
 // 0 FP64 Legendre synthesis, 1 FP64 Legendre adjoint, 2 ring pass,
-// 3 MFMA (bf16x3) Legendre synthesis, 4 MFMA Legendre adjoint
-constexpr int kTimedKernels = 5;
+// 3 MFMA (bf16x3) Legendre synthesis, 4 MFMA Legendre adjoint,
+// 5 block preconditioner application
+constexpr int kTimedKernels = 6;
 struct Timing {
   bool on = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events[kTimedKernels];
