@@ -84,3 +84,62 @@ def test_pcg_with_block_preconditioner():
 def wl_ninv(z, phi, nside):
     wl = ci.workload_masked_t(nside, 3 * nside - 1, cfg=1)
     return wl.ninv(z, phi)
+
+
+def test_tqu_blocks_equal_operator_entries():
+    # noise constant on rings, symmetric under z -> -z and zero on the polar
+    # cap rings (equatorial rings hold 4 nside pixels, so no m <= lmax aliases
+    # there): the T-T, E-E and B-B (l m, l' m) entries of the T+Q+U operator
+    # are exactly the blocks
+    from oracle import cr_tqu
+    from oracle.block_pc import BlockPreconditionerTQU
+    nside, lmax = 8, 23
+    wl = ci.workload_masked_t(nside, lmax, fwhm_arcmin=480.0, cfg=2)
+    z, phi = healpix.pixel_coords(nside)
+    nt = (np.abs(z) < 0.6) * (1.0 + z * z) / 40.0
+    P = cr_tqu.ProblemTQU(nside, lmax, ci.cl_tqu(lmax, wl.amp, 0.3), wl.bl(), nt, 0.5 * nt)
+    op = cr_tqu.CROperatorTQU(P)
+    pc = BlockPreconditionerTQU(op)
+    ls, ms = lm_arrays(lmax, lmax)
+    for m in (0, 1, 3, 8):
+        ii = pc.idx[m]
+        blocks = [np.linalg.inv(pc.inv[m][k]) for k in range(3)]
+        for jl in (2, 5, 11):
+            col = jl - m
+            if col < 0 or ls[ii[col]] < 2:
+                continue
+            for k in range(3):
+                x = np.zeros((3, ls.size), dtype=np.complex128)
+                x[k, ii[col]] = 1.0
+                y = op.apply(x)
+                got = y[k, ii].real
+                ref = blocks[k][:, col]
+                keep = ls[ii] >= 2
+                assert np.allclose(got[keep], ref[keep], rtol=1e-10, atol=1e-12 * np.abs(ref).max()), (m, jl, k)
+
+
+def test_tqu_block_pc_symmetric_and_cuts_iterations():
+    from oracle import cr_tqu
+    from oracle.block_pc import BlockPreconditionerTQU
+    nside = 8
+    lmax = 3 * nside - 1
+    wl = ci.workload_masked_t(nside, lmax, fwhm_arcmin=480.0, cfg=2)
+    z, phi = healpix.pixel_coords(nside)
+    nt = wl.ninv(z, phi)
+    P = cr_tqu.ProblemTQU(nside, lmax, ci.cl_tqu(lmax, wl.amp, 0.3), wl.bl(), nt, 0.5 * nt)
+    op = cr_tqu.CROperatorTQU(P)
+    pc = BlockPreconditionerTQU(op)
+    rng = np.random.default_rng(4)
+    x = op.project(np.stack([ci.white_alm(rng, lmax) for _ in range(3)]))
+    y = op.project(np.stack([ci.white_alm(rng, lmax) for _ in range(3)]))
+    a, c = op.dot(pc(x), y), op.dot(x, pc(y))
+    assert abs(a - c) <= 1e-10 * abs(a)
+    assert op.dot(pc(x), x) > 0
+    d = 30.0 * rng.standard_normal((3, op.sht.npix))
+    w0 = np.stack([ci.white_alm(rng, lmax) for _ in range(3)])
+    b = op.rhs(d, w0, rng.standard_normal((3, op.sht.npix)))
+    xj, sj = cr.pcg(op, b, 1e-8, 5000)
+    xb, sb = cr.pcg(op, b, 1e-8, 5000, precond=pc)
+    assert sb.converged and sj.converged
+    assert sb.iters * 4 < sj.iters, (sb.iters, sj.iters)
+    assert op.norm(xb - xj) <= 1e-6 * op.norm(xj)
