@@ -203,7 +203,7 @@ def main():
     ap.add_argument("--no-f64-compare", action="store_true")
     ap.add_argument("--workload", choices=["headline", "tqu", "batched64"], default="headline")
     ap.add_argument("--precond", choices=["block", "jacobi"], default=None,
-                    help="default: block (per-m blocks) for temperature, jacobi for tqu")
+                    help="default: block (per-m blocks, one set per component)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported "
@@ -252,7 +252,7 @@ def main():
         w0 = np.stack([ci.white_alm(ci.rng_for(2, c, ci.STREAM_W0), lmax) for c in range(R)])
         w1 = np.stack([ci.white_map(ci.rng_for(2, c, ci.STREAM_W1), wl.npix) for c in range(R)])
     prob = crsht.Problem(cl, bl, ninv, 2)
-    use_block = (args.precond or ("jacobi" if tqu else "block")) == "block"
+    use_block = (args.precond or "block") == "block"
     pc = crsht.CR_PC_BLOCK if use_block else crsht.CR_PC_JACOBI
     pc_setup_s = None
     if use_block:
@@ -352,10 +352,11 @@ def main():
     kinfo[1] = ("k_legendre_adj (FP64 VALU, whole transform)", "alu", sum((3 + 4 * g) * T for g in ga),
                 FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s", "legendre.hip")
     if use_block:
-        # stored inverses (FP32, sum of n^2 over the (m, parity) blocks) + r read + z written
+        # stored inverses (FP32, sum of n^2 over the (m, parity) blocks of
+        # every component) + r read + z written
         sn2 = sum(((lmax - m - q) // 2 + 1) ** 2 for m in range(lmax + 1) for q in (0, 1) if m + q <= lmax)
         kinfo[5] = ("k_pc_apply (block preconditioner, FP32 MFMA)", "hbm",
-                    4 * sn2 + 2 * R * plan.vlen * 16, HBM_PEAK_GBS, "GB/s", "blockpc.hip")
+                    4 * sn2 * nc + 2 * R * plan.vlen * 16, HBM_PEAK_GBS, "GB/s", "blockpc.hip")
     roofs = {}
     for kid, (name, bound, work, peak, unit, src) in kinfo.items():
         ms, nl = tm[kid]

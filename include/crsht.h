@@ -153,7 +153,7 @@ typedef struct {
   int check_every;     /* iterations between host convergence checks (>= 1; 0 = 8) */
   int precond;         /* CR_PC_JACOBI (0): the Jacobi diagonal of cr_precond, rebuilt by every solve;
                           CR_PC_BLOCK (1): the per-m block preconditioner stored in the plan by
-                          cr_block_precond_build (temperature plans; CR_EINVAL if none is built) */
+                          cr_block_precond_build (CR_EINVAL if none is built) */
   int use_graph;       /* 1: each block of check_every iterations is captured once as a HIP graph
                           (plan-owned, re-captured when nrhs, ninv, tol, precision or the block
                           length change) and replayed on `stream`; 0: every kernel is launched
@@ -193,12 +193,21 @@ int cr_precond(const crsht_plan *plan, const cr_problem *prob, double *diag, voi
  * by the next build). Built once per noise model, beam and spectrum shape,
  * it stays valid when the spectrum is rescaled (joint_cl_step): PCG only
  * needs a fixed symmetric positive definite preconditioner.
- * Temperature plans (CR_ENOTSUP for ncomp = 3); CR_EINVAL if a block is not
- * positive definite. Blocks until done. */
+ * ncomp = 3: three sets of blocks, one per component, three times the
+ * storage. T as above with N_T^-1 and (S^-1)_TT; E and B with the spin-2
+ * functions of the polarisation transforms,
+ *   M^E_mq[l, l'] = (S^-1)_EE,l delta_ll' + b_l b_l' sum_r (W_lm W_l'm + X_lm X_l'm)(z_r) W_P,r,
+ * M^B with (S^-1)_BB, W_P,r the mean of the Q and U ring sums (mirror
+ * averaged). The T-E prior coupling and the E-B coupling are left out, so
+ * the preconditioner is block diagonal per component (exact E-E and B-B
+ * m-blocks when the Q and U noise are equal and depend on latitude only).
+ * CR_EINVAL if a block is not positive definite (or lmin < 2 for ncomp = 3).
+ * Blocks until done. */
 int cr_block_precond_build(crsht_plan *plan, const cr_problem *prob, void *stream);
 
 /* z = M^-1 r with the stored block preconditioner, per column (the real and
- * imaginary parts alike). r, z: device [nrhs][nalm], distinct. Asynchronous. */
+ * imaginary parts alike). r, z: device [nrhs][ncomp][nalm], distinct.
+ * CR_EINVAL if none is built. Asynchronous. */
 int cr_block_precond_apply(const crsht_plan *plan, int nrhs, const double *r, double *z, void *stream);
 
 /* Right-hand side of eq. mapmakingeq: b = B Y^T N^-1 d + S^-1/2 w0 + B Y^T N^-1/2 w1,

@@ -583,7 +583,7 @@ int solve_core(const crsht_plan* P, const cr_problem* prob, double q, int nrhs, 
   if (opts->prec != CR_F64 && opts->prec != CR_MIXED) return CR_EINVAL;
   if (opts->precond != CR_PC_JACOBI && opts->precond != CR_PC_BLOCK) return CR_EINVAL;
   const bool pc = opts->precond == CR_PC_BLOCK;
-  if (pc && (!P->pc.built || P->ncomp != 1)) return CR_EINVAL;
+  if (pc && !P->pc.built) return CR_EINVAL;
   const int every = opts->check_every > 0 ? opts->check_every : 8;
   CR_CHECK(set_problem(P, prob, q, s));
   if (!pc) CR_CHECK(compute_diag(P, prob->ninv, s));
@@ -678,10 +678,10 @@ extern "C" int cr_precond(const crsht_plan* P, const cr_problem* prob, double* d
 
 extern "C" int cr_block_precond_build(crsht_plan* P, const cr_problem* prob, void* stream) {
   CR_CHECK(check_plan(P, 1));
-  if (P->ncomp != 1) return CR_ENOTSUP;
+  if (!prob || !prob->ninv) return CR_EINVAL;
   hipStream_t s = S(stream);
-  CR_CHECK(set_problem(P, prob, 1.0, s));   // validates the spectrum, beam and lmin
-  return block_pc_build(P, prob->bl, prob->cl, prob->lmin, 1.0, prob->ninv, s);
+  CR_CHECK(set_problem(P, prob, 1.0, s));   // validates the spectrum, beam and lmin; per-l arrays
+  return block_pc_build(P, prob->lmin, prob->ninv, s);
 }
 
 extern "C" int cr_block_precond_apply(const crsht_plan* P, int nrhs, const double* r, double* z, void* stream) {

@@ -12,15 +12,28 @@
 // diagonal, whose entries are the diagonal of these blocks). Rows with
 // l < lmin are the identity.
 //
+// T+Q+U plans hold three sets of blocks. T: as above with N_T^-1 and the TT
+// entry of S^-1. E and B share one Gram matrix built from the spin-2
+// functions W_lm, X_lm (the transforms' convention) and the mean of the Q and
+// U ring sums W_P,p:
+//   M^E_mq[i, j] = (S^-1)_EE,l delta_ij + b_l b_l' sum_p (W_lm W_l'm + X_lm X_l'm)(z_p) W_P,p,
+// M^B with (S^-1)_BB. For Q and U noise equal and depending on latitude only
+// these are the E-E and B-B m-blocks of the operator; the couplings left out
+// are T-E (prior) and E-B (l - l' odd), so the preconditioner stays block
+// diagonal per component, symmetric and positive definite.
+//
 // Set-up (once per noise model, beam and spectrum shape): the blocks are
 // grouped into buckets of equal padded size; per bucket the FP64 factor
-// L = [b_l lambda_lm(z_p) sqrt(W_p)] is written by the recurrence kernel, the
-// Gram matrix L L^T is formed with rocBLAS SYRK, the prior diagonal added,
-// and the inverse computed with rocSOLVER (Cholesky, then inverse from the
-// factor); the inverses are stored in FP32, full symmetric, per block.
-// Application (every PCG iteration): z_mq = M_mq^-1 r_mq for the real and
-// imaginary parts of every column on the matrix cores (FP32), one workgroup
-// per 256 rows of a block (128 per wavefront).
+// L = [b_l lambda_lm(z_p) sqrt(W_p)] (T), or [b_l W_lm sqrt(W_P,p) | b_l X_lm
+// sqrt(W_P,p)] (E and B, twice as many columns), is written by a recurrence
+// kernel, the Gram matrix L L^T is formed with rocBLAS SYRK, the prior
+// diagonal added, and the inverse computed with rocSOLVER (Cholesky, then
+// inverse from the factor); the inverses are stored in FP32, full symmetric,
+// per block.
+// Application (every PCG iteration): z_b = M_b^-1 r_b for the real and
+// imaginary parts of every column and every block of every component on the
+// matrix cores (FP32), one workgroup per 256 rows of a block (128 per
+// wavefront).
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -83,11 +96,71 @@ __global__ __launch_bounds__(256) void k_pc_lambda(int lmax, int npairs, int lmi
   }
 }
 
+// E/B factor of the same blocks: L[i][p] = b_l W_lm(z_p) sqrt(W_p) and
+// L[i][npairs + p] = b_l X_lm(z_p) sqrt(W_p), l = m + q + 2 i >= lmin, with
+//   W_lm = (-2 ((l - m^2)/s^2 + l (l - 1)/2) lambda_l + 2 z F_lm / s^2 lambda_{l-1}) / N_l,
+//   X_lm = -2 m / s^2 ((l - 1) z lambda_l - F_lm lambda_{l-1}) / N_l,
+// F_lm = sqrt((2l+1)/(2l-1) (l^2 - m^2)), N_l = sqrt((l-1) l (l+1) (l+2)),
+// s^2 = 1 - z^2, lambda_l = kappa_lm mu_lm from the scalar recurrence. Under
+// z -> -z, W_lm and X_lm change sign with opposite parities, so within one
+// block the products W W' and X X' are even and the pair sum of the ring
+// weights serves both rings. L: [bucket block][npad][2 npairs], zeroed.
+__global__ __launch_bounds__(256) void k_pc_spin(int lmax, int npairs, int lmin, const double* __restrict__ pair_z,
+                                                 const double* __restrict__ alpha,
+                                                 const double* __restrict__ kappa, const int* __restrict__ lst_g,
+                                                 const double2* __restrict__ lst_s,
+                                                 const int64_t* __restrict__ mstart,
+                                                 const double* __restrict__ ring_w, const double* __restrict__ bl,
+                                                 const int* __restrict__ blocks, const int* __restrict__ bm,
+                                                 const int* __restrict__ bq, int npad, double* __restrict__ L) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const int blk = blocks[blockIdx.y];
+  const int m = bm[blk], q = bq[blk];
+  double* __restrict__ Lb = L + (size_t)blockIdx.y * npad * 2 * npairs;
+  const double w = sqrt(ring_w[p]);
+  const size_t o = (size_t)m * npairs + p;
+  const int gs = lst_g[o];
+  const double2 s0 = lst_s[o];
+  const double z = pair_z[p];
+  const double is2 = 1.0 / ((1.0 - z) * (1.0 + z));
+  const double mm = (double)m;
+  const int64_t base = mstart[m];
+  const int nsteps = lmax - m + 1;
+  double v0 = 0.0, v1 = 0.0;
+  for (int st = 0; st < nsteps; ++st) {
+    if (st % kStartGroup == 0 && st / kStartGroup == gs) {
+      v0 = s0.x;
+      v1 = s0.y;
+    }
+    const double lprev = st > 0 ? kappa[base + st - 1] * v1 : 0.0;   // lambda_{l-1, m}
+    const double mu = fma(alpha[base + st] * z, v1, -v0);
+    v0 = v1;
+    v1 = mu;
+    if (st >= q && ((st - q) & 1) == 0) {
+      const int l = m + st;
+      if (l >= lmin && l >= 2) {
+        const double dl = (double)l;
+        const double lam = kappa[base + st] * mu;
+        const double f = sqrt((2.0 * dl + 1.0) / (2.0 * dl - 1.0) * (dl * dl - mm * mm));
+        const double nl = 1.0 / sqrt((dl - 1.0) * dl * (dl + 1.0) * (dl + 2.0));
+        const double W = (-2.0 * ((dl - mm * mm) * is2 + 0.5 * dl * (dl - 1.0)) * lam + 2.0 * z * f * is2 * lprev) * nl;
+        const double X = -2.0 * mm * is2 * ((dl - 1.0) * z * lam - f * lprev) * nl;
+        const double sc = bl[l] * w;
+        double* row = Lb + (size_t)((st - q) >> 1) * 2 * npairs;
+        row[p] = sc * W;
+        row[npairs + p] = sc * X;
+      }
+    }
+  }
+}
+
 // After C = L L^T (lower triangle, column-major, npad x npad per block): the
-// prior 1/C_l on kept rows, the identity on rows l < lmin and on padding.
+// prior sinv_l[sstride l] on kept rows, the identity on rows l < lmin and on
+// padding.
 __global__ void k_pc_fix(const int* __restrict__ blocks, const int* __restrict__ bm, const int* __restrict__ bq,
-                         const int* __restrict__ bn, int lmin, const double* __restrict__ sinv_l, int npad,
-                         double* __restrict__ C) {
+                         const int* __restrict__ bn, int lmin, const double* __restrict__ sinv_l, int sstride,
+                         int npad, double* __restrict__ C) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npad) return;
   const int blk = blocks[blockIdx.y];
@@ -97,7 +170,7 @@ __global__ void k_pc_fix(const int* __restrict__ blocks, const int* __restrict__
   if (i >= n || l < lmin)
     *c = 1.0;
   else
-    *c += sinv_l[l];
+    *c += sinv_l[(size_t)sstride * l];
 }
 
 // Inverse (lower triangle from potri) -> full symmetric FP32 n x n per block
@@ -128,10 +201,9 @@ __global__ void k_pc_store(const int* __restrict__ blocks, const int* __restrict
 // c + 32 k, D[i][c] in lane c + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4.
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 constexpr int kPcPre = 4;          // K steps per prefetch group
-__global__ __launch_bounds__(kPcWaves * 64) void k_pc_apply(int nrhs, int64_t vlen, const int64_t* __restrict__ mstart,
+__global__ __launch_bounds__(kPcWaves * 64) void k_pc_apply(int nrhs, int64_t vlen, const int64_t* __restrict__ be0,
                                                             const int* __restrict__ task_b,
                                                             const int* __restrict__ task_r0,
-                                                            const int* __restrict__ bm, const int* __restrict__ bq,
                                                             const int* __restrict__ bn,
                                                             const int64_t* __restrict__ boff,
                                                             const float* __restrict__ inv,
@@ -148,7 +220,7 @@ __global__ __launch_bounds__(kPcWaves * 64) void k_pc_apply(int nrhs, int64_t vl
   const int i0 = task_r0[blockIdx.x] + 128 * w;
   const int ic = i0 + 4 * il;                           // first of this lane's 4 rows
   const bool colok = ic < ld;                           // padding rows n .. ld - 1 hold zeros
-  const int64_t e0 = mstart[bm[b]] + bq[b];             // element of row j: e0 + 2 j
+  const int64_t e0 = be0[b];                            // element of row j: e0 + 2 j
   const float* __restrict__ Ab = inv + boff[b] + (colok ? ic : 0);
   const int ntile = (n + kPcJ - 1) / kPcJ;
   for (int c0 = 0; c0 < nrhs; c0 += kPcCols) {
@@ -262,33 +334,41 @@ int dev_upload(T** p, const std::vector<T>& h) {
 }  // namespace
 
 void block_pc_free(BlockPC& pc) {
-  void* ptrs[] = {pc.inv, pc.bm, pc.bq, pc.bn, pc.boff, pc.task_b, pc.task_r0};
+  void* ptrs[] = {pc.inv, pc.bm, pc.bq, pc.bn, pc.boff, pc.be0, pc.task_b, pc.task_r0};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   pc = BlockPC();
 }
 
-int block_pc_build(crsht_plan* P, const double* bl, const double* cl, int lmin, double q, const double* ninv,
-                   hipStream_t s) {
+int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
   const Geometry& g = P->g;
   const int lmax = g.lmax, mmax = g.mmax, np = g.npairs;
+  const int ncomp = P->ncomp;
   BlockPC& pc = P->pc;
   block_pc_free(pc);
-  // blocks (m, parity) with their sizes, compact FP32 offsets, application tasks
+  // blocks (component, m, parity), component-major: sizes, vector element of
+  // row 0, compact FP32 offsets; then the application tasks
   std::vector<int> bm, bq, bn;
-  std::vector<int64_t> boff;
+  std::vector<int64_t> boff, be0;
   int64_t off = 0;
-  for (int m = 0; m <= mmax; ++m)
-    for (int qq = 0; qq < 2; ++qq) {
-      if (m + qq > lmax) continue;
-      const int n = (lmax - m - qq) / 2 + 1;
-      bm.push_back(m);
-      bq.push_back(qq);
-      bn.push_back(n);
-      boff.push_back(off);
-      off += (int64_t)n * pc_ld(n);
+  for (int k = 0; k < ncomp; ++k) {
+    int64_t mst = 0;   // first element of m (m-major storage, l = m .. lmax)
+    for (int m = 0; m <= mmax; ++m) {
+      for (int qq = 0; qq < 2; ++qq) {
+        if (m + qq > lmax) continue;
+        const int n = (lmax - m - qq) / 2 + 1;
+        bm.push_back(m);
+        bq.push_back(qq);
+        bn.push_back(n);
+        be0.push_back((int64_t)k * g.nalm + mst + qq);
+        boff.push_back(off);
+        off += (int64_t)n * pc_ld(n);
+      }
+      mst += lmax - m + 1;
     }
+  }
   const int nb = (int)bm.size();
+  const int nbc = nb / ncomp;   // blocks per component; block b of component k is k nbc + b
   std::vector<int> tb, tr;
   for (int b = 0; b < nb; ++b)
     for (int r0 = 0; r0 < bn[b]; r0 += kPcRows) {
@@ -297,8 +377,8 @@ int block_pc_build(crsht_plan* P, const double* bl, const double* cl, int lmin, 
     }
   int rc;
   if ((rc = dev_upload(&pc.bm, bm)) || (rc = dev_upload(&pc.bq, bq)) || (rc = dev_upload(&pc.bn, bn)) ||
-      (rc = dev_upload(&pc.boff, boff)) || (rc = dev_upload(&pc.task_b, tb)) || (rc = dev_upload(&pc.task_r0, tr)) ||
-      (rc = dev_alloc(&pc.inv, (size_t)off))) {
+      (rc = dev_upload(&pc.boff, boff)) || (rc = dev_upload(&pc.be0, be0)) || (rc = dev_upload(&pc.task_b, tb)) ||
+      (rc = dev_upload(&pc.task_r0, tr)) || (rc = dev_alloc(&pc.inv, (size_t)off))) {
     block_pc_free(pc);
     return rc;
   }
@@ -311,37 +391,36 @@ int block_pc_build(crsht_plan* P, const double* bl, const double* cl, int lmin, 
     return CR_EDEVICE;
   }
 
-  // per-l inputs on the device: b_l and the prior 1 / (q C_l)
-  std::vector<double> hb(lmax + 1), hs(lmax + 1, 0.0);
-  for (int l = 0; l <= lmax; ++l) {
-    hb[l] = bl[l];
-    if (l >= lmin) hs[l] = 1.0 / (q * cl[l]);
-  }
-  double *dbl = nullptr, *dsinv = nullptr, *L = nullptr, *C = nullptr;
+  // per-l inputs left on the device by the problem set-up: b_l (row 2 of
+  // perl) and the priors (perl row 0 = 1/C_l; T+Q+U: sblk entries TT, EE, BB)
+  const double* dbl = P->w.perl + 2 * (lmax + 1);
+  double *L = nullptr, *C = nullptr;
   int *dblocks = nullptr, *dinfo = nullptr;
   rocblas_handle h = nullptr;
   auto cleanup = [&]() {
     if (h) (void)rocblas_destroy_handle(h);
-    void* ptrs[] = {dbl, dsinv, L, C, dblocks, dinfo};
+    void* ptrs[] = {L, C, dblocks, dinfo};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
   };
-  // buckets of equal padded size, processed in batches bounded by memory
+  // buckets of equal padded size (per component set), processed in batches
+  // bounded by memory; E and B batches hold cnt E blocks then cnt B blocks
   std::vector<std::vector<int>> buckets((lmax + 2) / kPad + 2);
-  for (int b = 0; b < nb; ++b) buckets[(bn[b] + kPad - 1) / kPad].push_back(b);
+  for (int b = 0; b < nbc; ++b) buckets[(bn[b] + kPad - 1) / kPad].push_back(b);
   const size_t budget = (size_t)1 << 29;   // bytes of L per batch
+  const int kmax = ncomp == 3 ? 2 : 1;     // columns of L per ring pair (E/B: W and X)
   size_t maxL = 0, maxC = 0, maxb = 0;
   for (size_t k = 0; k < buckets.size(); ++k) {
     if (buckets[k].empty()) continue;
     const size_t npad = k * kPad;
-    const size_t per = std::max<size_t>(1, budget / (npad * np * sizeof(double)));
+    const size_t per = std::max<size_t>(1, budget / (npad * np * kmax * sizeof(double)));
     const size_t cnt = std::min(per, buckets[k].size());
-    maxL = std::max(maxL, cnt * npad * np);
-    maxC = std::max(maxC, cnt * npad * npad);
-    maxb = std::max(maxb, cnt);
+    maxL = std::max(maxL, cnt * npad * np * kmax);
+    maxC = std::max(maxC, cnt * npad * npad * kmax);
+    maxb = std::max(maxb, cnt * kmax);
   }
-  if ((rc = dev_upload(&dbl, hb)) || (rc = dev_upload(&dsinv, hs)) || (rc = dev_alloc(&L, maxL)) ||
-      (rc = dev_alloc(&C, maxC)) || (rc = dev_alloc(&dblocks, maxb)) || (rc = dev_alloc(&dinfo, maxb))) {
+  if ((rc = dev_alloc(&L, maxL)) || (rc = dev_alloc(&C, maxC)) || (rc = dev_alloc(&dblocks, maxb)) ||
+      (rc = dev_alloc(&dinfo, maxb))) {
     cleanup();
     block_pc_free(pc);
     return rc;
@@ -351,61 +430,86 @@ int block_pc_build(crsht_plan* P, const double* bl, const double* cl, int lmin, 
     block_pc_free(pc);
     return CR_EDEVICE;
   }
-  // ring sums of N^-1 over both rings of each pair
-  if (launch_ring_weights(P, ninv, P->w.ring_w, s) != hipSuccess) {
-    cleanup();
-    block_pc_free(pc);
-    return CR_EDEVICE;
-  }
   int status = CR_OK;
   std::vector<int> hinfo;
-  for (size_t k = 0; k < buckets.size() && status == CR_OK; ++k) {
-    if (buckets[k].empty()) continue;   // (k = 0 is always empty: every block has n >= 1)
-    const int npad = (int)k * kPad;
-    const std::vector<int>& bl_k = buckets[k];
-    const size_t per = std::max<size_t>(1, budget / ((size_t)npad * np * sizeof(double)));
-    for (size_t a = 0; a < bl_k.size() && status == CR_OK; a += per) {
-      const int cnt = (int)std::min(per, bl_k.size() - a);
-      const std::vector<int> ids(bl_k.begin() + a, bl_k.begin() + a + cnt);
-      bool ok = hipMemcpyAsync(dblocks, ids.data(), cnt * sizeof(int), hipMemcpyHostToDevice, s) == hipSuccess;
-      ok = ok && hipMemsetAsync(L, 0, (size_t)cnt * npad * np * sizeof(double), s) == hipSuccess;
-      if (ok) {
-        hipLaunchKernelGGL(k_pc_lambda, dim3((np + 255) / 256, cnt), dim3(256), 0, s, lmax, np, lmin, P->t.pair_z,
-                           P->t.rec_alpha, P->t.rec_kappa, P->t.lst_g, P->t.lst_s, P->t.mstart, P->w.ring_w, dbl,
-                           dblocks, pc.bm, pc.bq, npad, L);
-        ok = hipGetLastError() == hipSuccess;
+  // pass 0: T (or the only component) with the ring sums of N^-1 (N_T^-1);
+  // pass 1 (T+Q+U): E and B with the mean of the Q and U ring sums
+  for (int pass = 0; pass < (ncomp == 3 ? 2 : 1) && status == CR_OK; ++pass) {
+    const bool spin = pass == 1;
+    const int kc = spin ? 2 : 1;   // L columns per pair
+    const int nset = spin ? 2 : 1;  // block sets sharing one Gram matrix (E, B)
+    const hipError_t we = spin ? launch_ring_weights(P, ninv + g.npix, P->w.ring_w, s, ninv + 2 * g.npix, 0.5)
+                               : launch_ring_weights(P, ninv, P->w.ring_w, s);
+    if (we != hipSuccess) {
+      status = CR_EDEVICE;
+      break;
+    }
+    for (size_t k = 0; k < buckets.size() && status == CR_OK; ++k) {
+      if (buckets[k].empty()) continue;   // (k = 0 is always empty: every block has n >= 1)
+      const int npad = (int)k * kPad;
+      const std::vector<int>& bl_k = buckets[k];
+      const size_t per = std::max<size_t>(1, budget / ((size_t)npad * np * kmax * sizeof(double)));
+      for (size_t a = 0; a < bl_k.size() && status == CR_OK; a += per) {
+        const int cnt = (int)std::min(per, bl_k.size() - a);
+        // global block ids: T pass k = 0; spin pass E (k = 1) then B (k = 2)
+        std::vector<int> ids;
+        for (int set = 0; set < nset; ++set)
+          for (int t = 0; t < cnt; ++t) ids.push_back((spin ? 1 + set : 0) * nbc + bl_k[a + t]);
+        const size_t lsz = (size_t)npad * np * kc, csz = (size_t)npad * npad;
+        bool ok = hipMemcpyAsync(dblocks, ids.data(), ids.size() * sizeof(int), hipMemcpyHostToDevice, s) ==
+                  hipSuccess;
+        ok = ok && hipMemsetAsync(L, 0, (size_t)cnt * lsz * sizeof(double), s) == hipSuccess;
+        if (ok) {
+          if (spin)
+            hipLaunchKernelGGL(k_pc_spin, dim3((np + 255) / 256, cnt), dim3(256), 0, s, lmax, np, lmin, P->t.pair_z,
+                               P->t.rec_alpha, P->t.rec_kappa, P->t.lst_g, P->t.lst_s, P->t.mstart, P->w.ring_w, dbl,
+                               dblocks, pc.bm, pc.bq, npad, L);
+          else
+            hipLaunchKernelGGL(k_pc_lambda, dim3((np + 255) / 256, cnt), dim3(256), 0, s, lmax, np, lmin,
+                               P->t.pair_z, P->t.rec_alpha, P->t.rec_kappa, P->t.lst_g, P->t.lst_s, P->t.mstart,
+                               P->w.ring_w, dbl, dblocks, pc.bm, pc.bq, npad, L);
+          ok = hipGetLastError() == hipSuccess;
+        }
+        const double one = 1.0, zero = 0.0;
+        // C = L L^T: L is row-major [npad][kc np], i.e. column-major (kc np) x npad, so C = A^T A
+        const int kdim = kc * np;
+        ok = ok && rocblas_dsyrk_strided_batched(h, rocblas_fill_lower, rocblas_operation_transpose, npad, kdim, &one,
+                                                 L, kdim, (rocblas_stride)lsz, &zero, C, npad,
+                                                 (rocblas_stride)csz, cnt) == rocblas_status_success;
+        // the B blocks start from the same Gram matrices
+        if (spin)
+          ok = ok && hipMemcpyAsync(C + (size_t)cnt * csz, C, (size_t)cnt * csz * sizeof(double),
+                                    hipMemcpyDeviceToDevice, s) == hipSuccess;
+        for (int set = 0; set < nset && ok; ++set) {
+          // prior: perl row 0 (temperature plans) or the sblk entry TT (0), EE (2), BB (3)
+          const double* prior = ncomp == 3 ? P->w.sblk + (spin ? 2 + set : 0) : P->w.perl;
+          hipLaunchKernelGGL(k_pc_fix, dim3((npad + 255) / 256, cnt), dim3(256), 0, s, dblocks + set * cnt, pc.bm,
+                             pc.bq, pc.bn, lmin, prior, ncomp == 3 ? 8 : 1, npad, C + (size_t)set * cnt * csz);
+          ok = hipGetLastError() == hipSuccess;
+        }
+        const int nbat = nset * cnt;
+        ok = ok && rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, npad, C, npad, (rocblas_stride)csz, dinfo,
+                                                    nbat) == rocblas_status_success;
+        hinfo.assign(nbat, 0);
+        ok = ok && hipMemcpyAsync(hinfo.data(), dinfo, nbat * sizeof(int), hipMemcpyDeviceToHost, s) == hipSuccess &&
+             hipStreamSynchronize(s) == hipSuccess;
+        if (!ok) {
+          status = CR_EDEVICE;
+          break;
+        }
+        for (int v : hinfo)
+          if (v != 0) status = CR_EINVAL;   // a block is not positive definite
+        if (status != CR_OK) break;
+        ok = rocsolver_dpotri_strided_batched(h, rocblas_fill_lower, npad, C, npad, (rocblas_stride)csz, dinfo,
+                                              nbat) == rocblas_status_success;
+        if (ok) {
+          hipLaunchKernelGGL(k_pc_store, dim3((npad + 255) / 256, npad, nbat), dim3(256), 0, s, dblocks, pc.bn,
+                             pc.boff, npad, C, pc.inv);
+          ok = hipGetLastError() == hipSuccess;
+        }
+        ok = ok && hipStreamSynchronize(s) == hipSuccess;   // scratch is reused by the next batch
+        if (!ok) status = CR_EDEVICE;
       }
-      const double one = 1.0, zero = 0.0;
-      // C = L L^T: L is row-major [npad][np], i.e. column-major np x npad, so C = A^T A
-      ok = ok && rocblas_dsyrk_strided_batched(h, rocblas_fill_lower, rocblas_operation_transpose, npad, np, &one, L,
-                                               np, (rocblas_stride)npad * np, &zero, C, npad,
-                                               (rocblas_stride)npad * npad, cnt) == rocblas_status_success;
-      if (ok) {
-        hipLaunchKernelGGL(k_pc_fix, dim3((npad + 255) / 256, cnt), dim3(256), 0, s, dblocks, pc.bm, pc.bq, pc.bn,
-                           lmin, dsinv, npad, C);
-        ok = hipGetLastError() == hipSuccess;
-      }
-      ok = ok && rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, npad, C, npad, (rocblas_stride)npad * npad,
-                                                  dinfo, cnt) == rocblas_status_success;
-      hinfo.assign(cnt, 0);
-      ok = ok && hipMemcpyAsync(hinfo.data(), dinfo, cnt * sizeof(int), hipMemcpyDeviceToHost, s) == hipSuccess &&
-           hipStreamSynchronize(s) == hipSuccess;
-      if (!ok) {
-        status = CR_EDEVICE;
-        break;
-      }
-      for (int v : hinfo)
-        if (v != 0) status = CR_EINVAL;   // a block is not positive definite
-      if (status != CR_OK) break;
-      ok = rocsolver_dpotri_strided_batched(h, rocblas_fill_lower, npad, C, npad, (rocblas_stride)npad * npad, dinfo,
-                                            cnt) == rocblas_status_success;
-      if (ok) {
-        hipLaunchKernelGGL(k_pc_store, dim3((npad + 255) / 256, npad, cnt), dim3(256), 0, s, dblocks, pc.bn, pc.boff,
-                           npad, C, pc.inv);
-        ok = hipGetLastError() == hipSuccess;
-      }
-      ok = ok && hipStreamSynchronize(s) == hipSuccess;   // scratch is reused by the next batch
-      if (!ok) status = CR_EDEVICE;
     }
   }
   cleanup();
@@ -421,8 +525,8 @@ int block_pc_build(crsht_plan* P, const double* bl, const double* cl, int lmin, 
 hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s) {
   const BlockPC& pc = P->pc;
   timing_begin(P, 5, s);
-  hipLaunchKernelGGL(k_pc_apply, dim3(pc.ntasks), dim3(kPcWaves * 64), 0, s, nrhs, vlen(P), P->t.mstart, pc.task_b,
-                     pc.task_r0, pc.bm, pc.bq, pc.bn, pc.boff, pc.inv, r, z);
+  hipLaunchKernelGGL(k_pc_apply, dim3(pc.ntasks), dim3(kPcWaves * 64), 0, s, nrhs, vlen(P), pc.be0, pc.task_b,
+                     pc.task_r0, pc.bn, pc.boff, pc.inv, r, z);
   timing_end(P, 5, s);
   return hipGetLastError();
 }

@@ -160,7 +160,8 @@ struct BlockPC {
   int64_t inv_elems = 0;
   float* inv = nullptr;
   int *bm = nullptr, *bq = nullptr, *bn = nullptr;
-  int64_t* boff = nullptr;
+  int64_t* boff = nullptr;   // first FP32 element of each stored inverse
+  int64_t* be0 = nullptr;    // vector element of row 0 of each block (component offset included)
   int *task_b = nullptr, *task_r0 = nullptr;
 };
 
@@ -288,12 +289,12 @@ hipError_t launch_diag_tqu(const crsht_plan* P, const double2* rawt, const doubl
                            hipStream_t s);
 
 // ---- per-m block preconditioner (blockpc.hip) ----
-// build from b_l, C_l (host, scaled by q) and N^-1 (device); allocates the
-// plan's preconditioner storage; CR_EINVAL if a block is not positive definite
-int block_pc_build(crsht_plan* P, const double* bl, const double* cl, int lmin, double q, const double* ninv,
-                   hipStream_t s);
+// build from the per-l arrays that set_problem left in the workspace (b_l
+// and the priors) and N^-1 (device, [ncomp][npix]); allocates the plan's
+// preconditioner storage; CR_EINVAL if a block is not positive definite
+int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s);
 void block_pc_free(BlockPC& pc);
-// z = M^-1 r per column (r, z: [nrhs][nalm])
+// z = M^-1 r per column (r, z: [nrhs][vlen])
 hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s);
 // partial <r, z> (row 0) and, with rr, <r, r> (row 1), nb = vec_reduce_blocks
 hipError_t launch_pc_dots(const crsht_plan* P, int nrhs, const double2* r, const double2* z, bool rr,

@@ -1,6 +1,7 @@
 """GPU parity of the per-m block preconditioner (cr_block_precond_build /
 cr_block_precond_apply) against the oracle's (oracle/block_pc.py), and of
-solves preconditioned with it (FP64, mixed, graph replay, many columns).
+solves preconditioned with it (FP64, mixed, graph replay, many columns), for
+temperature and T+Q+U plans.
 
 The stored inverses are FP32 and the application accumulates in FP32, so the
 preconditioner itself matches the oracle to about 2e-7 relative (bound
@@ -12,7 +13,7 @@ import torch
 
 import crinputs as ci
 from oracle import cr
-from oracle.block_pc import BlockPreconditioner
+from oracle.block_pc import BlockPreconditioner, BlockPreconditionerTQU
 from tests.gpu_helpers import masked_problem, real_rel, rel, tc
 
 pytestmark = pytest.mark.gpu
@@ -111,7 +112,59 @@ def test_block_preconditioner_errors():
     with pytest.raises(m.CrshtError):
         m.block_precond_apply(plan, r)
     plan3 = m.Plan(8, wl.lmax, ncomp=3)
-    with pytest.raises(m.CrshtError):          # temperature plans only
+    with pytest.raises(m.CrshtError):          # T+Q+U plans need lmin >= 2
         m.block_precond_build(plan3, m.Problem(np.stack([P.cl, P.cl, P.cl, 0 * P.cl]), P.bl,
-                                               tc(np.stack([P.ninv] * 3)), 2))
+                                               tc(np.stack([P.ninv] * 3)), 1))
     _ = rel
+
+
+def _tqu(nside):
+    from tests.test_gpu_tqu import _gpu_problem, _problem
+    wl, P, op = _problem(nside)
+    return P, op, _gpu_problem(_m(), P)
+
+
+@pytest.mark.parametrize("nside,nrhs", [(4, 1), (16, 2), (32, 17)])
+def test_tqu_apply_matches_oracle(nside, nrhs):
+    m = _m()
+    print("case tqu block pc apply", nside, nrhs, flush=True)
+    P, op, gp = _tqu(nside)
+    plan = m.Plan(nside, P.lmax, nrhs_max=nrhs, ncomp=3)
+    m.block_precond_build(plan, gp)
+    pc = BlockPreconditionerTQU(op)
+    rng = np.random.default_rng(nside + 7)
+    R = np.stack([op.project(np.stack([ci.white_alm(rng, P.lmax) for _ in range(3)])) for _ in range(nrhs)])
+    got = m.block_precond_apply(plan, tc(R)).cpu().numpy()
+    for c in range(nrhs):
+        ref = pc(R[c])
+        errs = [rel(got[c, k], ref[k]) for k in range(3)]
+        if c in (0, nrhs - 1):
+            print("col", c, "rel err T E B", ["%.2e" % e for e in errs], flush=True)
+        assert max(errs) < PC_TOL, (c, errs)
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_tqu_solve_with_block_preconditioner(prec):
+    from tests.test_gpu_tqu import _data, real_rel3
+    m = _m()
+    nside = 32
+    print("case tqu block pc solve", prec, flush=True)
+    P, op, gp = _tqu(nside)
+    plan = m.Plan(nside, P.lmax, nrhs_max=2, ncomp=3)
+    m.block_precond_build(plan, gp)
+    rng = np.random.default_rng(21)
+    d = np.stack([_data(rng, op, P) for _ in range(2)])
+    w0 = np.stack([np.stack([ci.white_alm(rng, P.lmax) for _ in range(3)]) for _ in range(2)])
+    w1 = rng.standard_normal((2, 3, op.sht.npix))
+    tol = 1e-8 if prec == "f64" else 1e-6
+    p = m.CR_F64 if prec == "f64" else m.CR_MIXED
+    s, st = m.solve(plan, gp, tc(d), tc(w0), tc(w1), nrhs=2, tol=tol, maxiter=20000, prec=p,
+                    precond=m.CR_PC_BLOCK)
+    sj, stj = m.solve(plan, gp, tc(d), tc(w0), tc(w1), nrhs=2, tol=tol, maxiter=20000, prec=p)
+    for c in range(2):
+        b = op.rhs(d[c], w0[c], w1[c])
+        res = real_rel3(op, op.apply(s.cpu().numpy()[c]), b)
+        print("col", c, "iters block", st[c].iters, "jacobi", stj[c].iters, "res %.2e" % res, flush=True)
+        assert st[c].status == 0
+        assert res <= 1.05 * tol
+        assert st[c].iters * 3 < stj[c].iters
