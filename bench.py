@@ -39,14 +39,19 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x
 BF16_MFMA_PEAK_TFLOPS = 2500.0     # dense
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of a kernel per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
-# runs of `paper_2306_15511_amd/kernel_probe.py operator --nrhs 16 --prec mixed`
-# at Nside 512, scaled by the same counters on a 1 GiB copy (FETCH x 2.0,
-# WRITE x 1.0); valid only while the kernel's source file hashes to `src`.
+# HBM traffic of a kernel per timed unit from rocprofv3 --pmc FETCH_SIZE /
+# WRITE_SIZE runs of `paper_2306_15511_amd/kernel_probe.py` (operator --nrhs 16
+# --prec mixed / f64; precond --nrhs 16) at Nside 512, scaled by the same
+# counters on a 1 GiB copy (FETCH x 2.0, WRITE x 1.0); valid only for the
+# 16-column temperature workload and while the kernel's source file hashes to
+# `src`.
 TRAFFIC = {
-    "k_adj_mfma": {"bytes": 959889818, "src": "4bb2b2ec354d97cb"},
-    "k_synth_mfma": {"bytes": 1321213952, "src": "4bb2b2ec354d97cb"},
-    "k_ring<RING_FUSED>": {"bytes": 851707494, "src": "b9fa70a40ebe481a"},   # one fused pass (4 class launches)
+    "k_adj_mfma": {"bytes": 959892986, "src": "5edbc0e441375b52"},
+    "k_synth_mfma": {"bytes": 1326284475, "src": "5edbc0e441375b52"},
+    "k_ring<RING_FUSED>": {"bytes": 4 * 212902664, "src": "664ab76c607be629"},   # one fused pass (4 class launches)
+    "k_legendre_synth": {"bytes": 2136106918, "src": "2d7bd3325ba00270"},        # one launch of 8 columns
+    "k_legendre_adj": {"bytes": 4 * 331719298, "src": "2d7bd3325ba00270"},       # one transform (4 launches)
+    "k_pc_apply": {"bytes": 5061436181, "src": "b78a7fbaff73a924"},
 }
 
 
@@ -364,7 +369,7 @@ def main():
             continue
         avg = ms / nl * 1e-3
         achieved = work / avg / (1e9 if unit == "GB/s" else 1e12)
-        tr = None if tqu else TRAFFIC.get(name.split(" ")[0])
+        tr = TRAFFIC.get(name.split(" ")[0]) if (not tqu and R == 16) else None
         traffic = None
         if tr is not None and tr["src"] == src_hash(src):
             traffic = tr["bytes"]

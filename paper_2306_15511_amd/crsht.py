@@ -170,10 +170,10 @@ class Plan:
         self.ncomp = int(info.ncomp)
         self.vlen = self.ncomp * self.nalm      # coefficients per column
         self.mlen = self.ncomp * self.npix      # map values per column
+        self.workspace_bytes = int(info.workspace_bytes)
 
     def alm_shape(self, nrhs: int):
         return (nrhs, self.nalm) if self.ncomp == 1 else (nrhs, self.ncomp, self.nalm)
-        self.workspace_bytes = int(info.workspace_bytes)
 
     @property
     def handle(self):
