@@ -262,6 +262,8 @@ hipError_t launch_ring(const crsht_plan* P, int nrhs, RingMode mode, const void*
 void ring_classes(const std::vector<int>& fft_len, std::vector<RingClass>& cls, std::vector<int>& pairs);
 // plan set-up: allow the dynamic LDS of the ring kernels the plan's classes need
 hipError_t ring_prepare(const crsht_plan* P);
+// once per plan: LDS limit of the FP64 matrix-core adjoint
+hipError_t legendre_prepare(const crsht_plan* P);
 size_t ring_lds_bytes(const crsht_plan* P, bool f32);
 
 // ---- spin-2 part of T+Q+U plans (pol.hip) ----

@@ -14,6 +14,8 @@
 // produces E (sum over even l-m) and O (odd l-m) per ring pair, the ring
 // kernel forms F_N = E + O and F_S = E - O; the adjoint consumes
 // G_N + G_S (even l-m) and G_N - G_S (odd l-m).
+#include <algorithm>
+
 #include "internal.h"
 
 namespace crsht {
@@ -335,6 +337,138 @@ __global__ __launch_bounds__(kAdjBlock) void k_legendre_adj(
   }
 }
 
+// ------------------------------------------------- adjoint on FP64 matrix cores
+// The adjoint sums raw[c](l) = sum_p mu_lm(z_p) G_c(p) are a contraction over
+// the ring pairs p, so the matrix cores can take the sum over p that the
+// vector kernel above does by cross-thread reduction. One block per m with
+// kAmWaves wavefronts; wavefront w owns the ring pairs 128 w .. 128 w + 127 as
+// two subsets of 64 (lane q: pairs 128 w + q and 128 w + 64 + q). Per chunk of
+// 32 l-steps, for each subset every lane runs the recurrence of its pair for
+// 32 steps and writes mu to the wavefront's own LDS rows (row = lane, 33
+// doubles: conflict-free reads of the operand below); the wavefront then
+// accumulates, with v_mfma_f64_16x16x4_f64 over 16 K-steps of 4 pairs,
+//   D_par[i][j] += sum_k mu(l0 + 2 i + par, p_k) G_par(p_k, j),
+// par = E (even l - m, G_N + G_S) and O (odd, G_N - G_S), j = 2 c + (re, im)
+// over up to 8 complex columns. The G operands of the wavefront's 128 pairs
+// stay in registers for the whole m. After both subsets the 8 wavefronts'
+// 16 x 16 tiles are summed through LDS in a fixed order (deterministic) and
+// the 32 l-steps x ncols results written. All products and sums are FP64.
+// FP64 MFMA 16x16x4 lane layout: A[i][k] in lane i + 16 k, B[k][j] in lane
+// j + 16 k, D[i][j] in lane j + 16 (i % 4), register i / 4.
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+constexpr int kAmWaves = 8;
+constexpr int kAmChunk = 32;     // l-steps per chunk: 16 rows of each parity
+constexpr int kAmRow = 33;       // LDS row stride (doubles) of the mu staging
+constexpr int kAmCols = 8;       // complex columns per launch (16 real MFMA columns)
+constexpr int kAmPairs = kAmWaves * 128;   // ring pairs one block covers
+
+__global__ __launch_bounds__(kAmWaves * 64) void k_legendre_adj_mfma(
+    int lmax, int mmax, int npairs, int ncols, const double* __restrict__ pair_z, const double* __restrict__ alpha,
+    const int* __restrict__ lst_g, const double2* __restrict__ lst_s, const int64_t* __restrict__ mstart,
+    const double2* __restrict__ geo, int64_t geo_stride, double2* __restrict__ out, int64_t out_stride) {
+  extern __shared__ double am_lds[];   // [kAmWaves][64][kAmRow]
+  const int m = block_to_m(blockIdx.x);
+  if (m > mmax) return;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  double* my = am_lds + (size_t)w * 64 * kAmRow;
+  const int64_t base = mstart[m];
+  const int nsteps = lmax - m + 1;
+
+  double z[2], v0[2], v1[2];
+  int gs[2];
+  double2 st[2];
+  int wmin = kNever;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int p = 128 * w + 64 * u + lane;
+    const bool ok = p < npairs;
+    const int pp = ok ? p : 0;
+    const size_t o = (size_t)m * npairs + pp;
+    z[u] = pair_z[pp];
+    v0[u] = 0.0;
+    v1[u] = 0.0;
+    gs[u] = ok ? lst_g[o] : kNever;
+    st[u] = lst_s[o];
+    wmin = min(wmin, gs[u]);
+  }
+  wmin = wave_min(wmin);   // first live group of this wavefront
+  // B operands: G_par(p, j) for p = 128 w + 64 u + 4 s + (lane / 16), j = lane % 16
+  const int kq = lane >> 4, jc = lane & 15, col = jc >> 1, ri = jc & 1;
+  double b[2][16][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int sk = 0; sk < 16; ++sk) {
+      const int p = 128 * w + 64 * u + 4 * sk + kq;
+      const bool ok = p < npairs && col < ncols;
+      const double* g =
+          reinterpret_cast<const double*>(geo + (ok ? col : 0) * geo_stride + ((size_t)(ok ? p : 0) * (mmax + 1) + m) * 2);
+      b[u][sk][0] = ok ? g[ri] : 0.0;
+      b[u][sk][1] = ok ? g[2 + ri] : 0.0;
+    }
+  const int ai = lane & 15;   // A row (l index within the parity) of this lane
+
+#pragma unroll 1
+  for (int l0 = 0; l0 < nsteps; l0 += kAmChunk) {
+    f64x4_t acc[2][2];
+#pragma unroll
+    for (int par = 0; par < 2; ++par) acc[par][0] = acc[par][1] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+    if (l0 / kGroup + 1 >= wmin) {   // the chunk reaches this wavefront's first live group
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+#pragma unroll
+        for (int sp = 0; sp < kAmChunk; ++sp) {
+          const int stp = l0 + sp;
+          if (sp % kGroup == 0 && stp / kGroup == gs[u]) {
+            v0[u] = st[u].x;
+            v1[u] = st[u].y;
+          }
+          double mu = 0.0;
+          if (stp < nsteps) {
+            mu = fma(alpha[base + stp] * z[u], v1[u], -v0[u]);
+            v0[u] = v1[u];
+            v1[u] = mu;
+          }
+          my[lane * kAmRow + sp] = mu;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int sk = 0; sk < 16; ++sk)
+#pragma unroll
+          for (int par = 0; par < 2; ++par) {
+            const double a = my[(4 * sk + kq) * kAmRow + 2 * ai + par];
+            acc[par][sk & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[u][sk][par], acc[par][sk & 1], 0, 0, 0);
+          }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+    // this wavefront's tiles into its own rows (its products have read them)
+#pragma unroll
+    for (int par = 0; par < 2; ++par)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) my[par * 256 + r * 64 + lane] = acc[par][0][r] + acc[par][1][r];
+    __syncthreads();
+    {
+      // thread t: column t / 64, l-step l0 + (t % 64) / 2, re/im t % 2 (coalesced stores)
+      const int c = t >> 6, sq = (t & 63) >> 1, rr = t & 1;
+      const int stp = l0 + sq;
+      if (c < ncols && stp < nsteps) {
+        const int par = sq & 1, i = sq >> 1;
+        const int idx = par * 256 + (i >> 2) * 64 + (2 * c + rr) + 16 * (i & 3);
+        double sum = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < kAmWaves; ++ww) sum += am_lds[(size_t)ww * 64 * kAmRow + idx];
+        reinterpret_cast<double*>(out + c * out_stride + base + stp)[rr] = sum;
+      }
+    }
+    __syncthreads();   // the rows are rewritten by the next chunk
+  }
+}
+
 int pick_nr(int n) { return n >= 8 ? 8 : n >= 4 ? 4 : n >= 2 ? 2 : 1; }
 
 template <int NR>
@@ -388,6 +522,13 @@ hipError_t adj_pass(const crsht_plan* P, const double2* geo, double2* out, bool 
 
 }  // namespace
 
+hipError_t legendre_prepare(const crsht_plan* P) {
+  (void)P;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_legendre_adj_mfma),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(kAmWaves * 64 * kAmRow * sizeof(double)));
+}
+
 hipError_t launch_legendre_start(const crsht_plan* P, hipStream_t s) {
   const Geometry& g = P->g;
   dim3 grid((g.npairs + 255) / 256, g.mmax + 1);
@@ -418,6 +559,19 @@ hipError_t launch_legendre_adjoint(const crsht_plan* P, int nrhs, const double2*
   hipError_t err = hipSuccess;
   if (diag) {
     err = adj_pass<1>(P, nullptr, raw, true, s);
+  } else if (nrhs >= 2 && P->g.npairs <= kAmPairs) {
+    // FP64 matrix cores, 8 columns per launch
+    const Geometry& g = P->g;
+    const int64_t geo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
+    const int nb = ((g.mmax + 1 + 31) / 32) * 32;
+    const size_t lds = (size_t)kAmWaves * 64 * kAmRow * sizeof(double);
+    for (int c0 = 0; c0 < nrhs && err == hipSuccess; c0 += kAmCols) {
+      const int nc = std::min(kAmCols, nrhs - c0);
+      hipLaunchKernelGGL(k_legendre_adj_mfma, dim3(nb), dim3(kAmWaves * 64), lds, s, g.lmax, g.mmax, g.npairs, nc,
+                         P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
+                         geo + (int64_t)c0 * geo_stride, geo_stride, raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm);
+      err = hipGetLastError();
+    }
   } else {
     const int64_t geo_stride = (int64_t)P->g.npairs * (P->g.mmax + 1) * 2;
     const int nr_cap = adj_max_nr(adj_rpt(P));

@@ -266,6 +266,7 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int ncomp, i
     crsht::ring_classes(pfft, P->ring_cls, rp);
     if ((rc = upload(&P->t.ring_pairs, rp, total))) return rc;
     if (crsht::ring_prepare(P) != hipSuccess) return CR_EDEVICE;
+    if (crsht::legendre_prepare(P) != hipSuccess) return CR_EDEVICE;
   }
   if ((rc = upload(&P->t.rec_alpha, alpha, total))) return rc;
   if ((rc = upload(&P->t.rec_kappa, kappa, total))) return rc;
