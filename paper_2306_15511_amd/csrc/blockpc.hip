@@ -213,6 +213,7 @@ __global__ __launch_bounds__(kPcWaves * 64) void k_pc_apply(int nrhs, int64_t vl
   static_assert(kSteps % kPcPre == 0, "tile must hold whole prefetch groups");
   __shared__ float rs[kPcJ][33];
   const int b = task_b[blockIdx.x];
+  if (b < 0) return;   // padding task (uniform per workgroup, before any barrier)
   const int n = bn[b];
   const int ld = pc_ld(n);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -369,11 +370,39 @@ int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
   }
   const int nb = (int)bm.size();
   const int nbc = nb / ncomp;   // blocks per component; block b of component k is k nbc + b
-  std::vector<int> tb, tr;
+  // Application tasks (block, first row), dealt to the 8 XCDs (workgroup i
+  // runs on XCD i mod 8): the tasks of both parity blocks of one (component,
+  // m) go to one XCD, so they share the residual lines they read and the
+  // result lines they write in that XCD's L2; units are placed largest first
+  // on the least loaded XCD, and within an XCD run largest first. Short XCD
+  // lists are padded with empty tasks (block -1).
+  constexpr int kXcd = 8;
+  std::vector<std::pair<double, int>> units;   // (cost, first block of the unit)
   for (int b = 0; b < nb; ++b)
-    for (int r0 = 0; r0 < bn[b]; r0 += kPcRows) {
-      tb.push_back(b);
-      tr.push_back(r0);
+    if (bq[b] == 0) {
+      double cost = (double)bn[b] * bn[b];
+      if (b + 1 < nb && bq[b + 1] == 1 && bm[b + 1] == bm[b]) cost += (double)bn[b + 1] * bn[b + 1];
+      units.push_back({cost, b});
+    }
+  std::stable_sort(units.begin(), units.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+  std::vector<std::vector<int>> xb(kXcd), xr(kXcd);
+  std::vector<double> load(kXcd, 0.0);
+  for (const auto& u : units) {
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[x] += u.first;
+    for (int b = u.second; b < nb && bm[b] == bm[u.second] && (b == u.second || bq[b] == 1); ++b)
+      for (int r0 = 0; r0 < bn[b]; r0 += kPcRows) {
+        xb[x].push_back(b);
+        xr[x].push_back(r0);
+      }
+  }
+  size_t per = 0;
+  for (int x = 0; x < kXcd; ++x) per = std::max(per, xb[x].size());
+  std::vector<int> tb(per * kXcd, -1), tr(per * kXcd, 0);
+  for (int x = 0; x < kXcd; ++x)
+    for (size_t k = 0; k < xb[x].size(); ++k) {
+      tb[k * kXcd + x] = xb[x][k];
+      tr[k * kXcd + x] = xr[x][k];
     }
   int rc;
   if ((rc = dev_upload(&pc.bm, bm)) || (rc = dev_upload(&pc.bq, bq)) || (rc = dev_upload(&pc.bn, bn)) ||
