@@ -51,7 +51,7 @@ struct Tables {
 
   // Legendre recurrence (scaled form mu_l = lambda_l / kappa_l):
   //   mu_m = lambda_mm, mu_{m-1} = 0, mu_l = alpha_lm z mu_{l-1} - mu_{l-2} for l > m
-  double* rec_alpha = nullptr;     // [nalm] alpha_lm (index of (l,m)); alpha_{m+1,m} = 1, alpha_mm unused
+  double* rec_alpha = nullptr;     // [nalm + 32] alpha_lm (index of (l,m)); alpha_{m+1,m} = 1, alpha_mm unused; 32 zeros after
   double* rec_kappa = nullptr;     // [nalm] kappa_lm, lambda_lm = kappa_lm mu_lm
   double* lmm_v = nullptr;         // [mmax+1][npairs] start value mantissa
   int* lmm_k = nullptr;            // [mmax+1][npairs] start scale index k <= 0

@@ -414,21 +414,23 @@ __global__ __launch_bounds__(kAmWaves * 64) void k_legendre_adj_mfma(
 #pragma unroll
     for (int par = 0; par < 2; ++par) acc[par][0] = acc[par][1] = f64x4_t{0.0, 0.0, 0.0, 0.0};
     if (l0 / kGroup + 1 >= wmin) {   // the chunk reaches this wavefront's first live group
+      // alpha of the chunk in one batch of loads. Past the last step of this
+      // m they are the next m's (or the table's zero padding): the rows of
+      // those l-steps only reach D rows whose outputs are not written.
+      double al[kAmChunk];
+#pragma unroll
+      for (int sp = 0; sp < kAmChunk; ++sp) al[sp] = alpha[base + l0 + sp];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
 #pragma unroll
         for (int sp = 0; sp < kAmChunk; ++sp) {
-          const int stp = l0 + sp;
-          if (sp % kGroup == 0 && stp / kGroup == gs[u]) {
+          if (sp % kGroup == 0 && (l0 + sp) / kGroup == gs[u]) {
             v0[u] = st[u].x;
             v1[u] = st[u].y;
           }
-          double mu = 0.0;
-          if (stp < nsteps) {
-            mu = fma(alpha[base + stp] * z[u], v1[u], -v0[u]);
-            v0[u] = v1[u];
-            v1[u] = mu;
-          }
+          const double mu = fma(al[sp] * z[u], v1[u], -v0[u]);
+          v0[u] = v1[u];
+          v1[u] = mu;
           my[lane * kAmRow + sp] = mu;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -268,6 +268,7 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int ncomp, i
     if (crsht::ring_prepare(P) != hipSuccess) return CR_EDEVICE;
     if (crsht::legendre_prepare(P) != hipSuccess) return CR_EDEVICE;
   }
+  alpha.resize(alpha.size() + 32, 0.0);   // readable past the last (l, m) by a whole chunk of 32 steps
   if ((rc = upload(&P->t.rec_alpha, alpha, total))) return rc;
   if ((rc = upload(&P->t.rec_kappa, kappa, total))) return rc;
   if ((rc = upload(&P->t.lmm_v, lv, total))) return rc;
