@@ -201,7 +201,8 @@ __global__ void k_pc_store(const int* __restrict__ blocks, const int* __restrict
 // c + 32 k, D[i][c] in lane c + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4.
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 constexpr int kPcPre = 4;          // K steps per prefetch group
-__global__ __launch_bounds__(kPcWaves * 64) void k_pc_apply(int nrhs, int64_t vlen, const int64_t* __restrict__ be0,
+// (three wavefronts per SIMD: 154 registers, more loads in flight per CU)
+__global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_pc_apply(int nrhs, int64_t vlen, const int64_t* __restrict__ be0,
                                                             const int* __restrict__ task_b,
                                                             const int* __restrict__ task_r0,
                                                             const int* __restrict__ bn,
