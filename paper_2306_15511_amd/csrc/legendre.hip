@@ -471,6 +471,106 @@ __global__ __launch_bounds__(kAmWaves * 64) void k_legendre_adj_mfma(
   }
 }
 
+// ----------------------------------------------- synthesis on FP64 matrix cores
+// The synthesis sums F_par(p, c) = sum_l mu_lm(z_p) a'_c(l) (par = parity of
+// l - m) are a contraction over l. One wavefront per (m, group of 64 ring
+// pairs); lane q runs the recurrence of pair 64 g + q. Per chunk of 32
+// l-steps the wavefront writes mu to its LDS tile (row = l-step, 72 doubles:
+// conflict-free operand reads) and accumulates, for each of its 4 tiles of 16
+// pairs and each parity, 4 K-steps of 4 l-steps on v_mfma_f64_16x16x4_f64:
+//   A[i][k] = mu(l0 + 2 (4 s + k) + par, pair 16 t + i),
+//   B[k][j] = a'_{j/2}(l0 + 2 (4 s + k) + par).(re, im),
+// up to 8 complex columns (16 real MFMA columns). The blocks of one m run on
+// one XCD (workgroup i runs on XCD i mod 8), so the coefficient lines they
+// all read stay in that L2. Chunks before the wavefront's first live start
+// group are skipped; all products and sums are FP64.
+constexpr int kSmRow = 72;       // LDS row stride (doubles) of the mu tile
+
+__global__ __launch_bounds__(64) void k_legendre_synth_mfma(
+    int lmax, int mmax, int npairs, int ncols, int ngroups, const double* __restrict__ pair_z,
+    const double* __restrict__ alpha, const int* __restrict__ lst_g, const double2* __restrict__ lst_s,
+    const int64_t* __restrict__ mstart, const double2* __restrict__ alms, int64_t alm_stride,
+    double2* __restrict__ eo, int64_t eo_stride) {
+  __shared__ double mu_s[kAmChunk * kSmRow];
+  const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+  const int g = q % ngroups, m = (q / ngroups) * 8 + xcd;
+  if (m > mmax) return;
+  const int lane = threadIdx.x;
+  const int p = 64 * g + lane;
+  const bool ok = p < npairs;
+  const int pp = ok ? p : 0;
+  const size_t o = (size_t)m * npairs + pp;
+  const double z = pair_z[pp];
+  const int gs = ok ? lst_g[o] : kNever;
+  const double2 st0 = lst_s[o];
+  const int gmin = wave_min(gs);
+  const int64_t base = mstart[m];
+  const int nsteps = lmax - m + 1;
+  const int kq = lane >> 4, jc = lane & 15, col = jc >> 1, ri = jc & 1;
+  const bool colok = col < ncols;
+  const double* __restrict__ acol = reinterpret_cast<const double*>(alms + (colok ? col : 0) * alm_stride + base) + ri;
+
+  f64x4_t acc[4][2];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t][0] = acc[t][1] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+  if (gmin != kNever) {
+    double v0 = 0.0, v1 = 0.0;
+#pragma unroll 1
+    for (int l0 = (gmin * kGroup / kAmChunk) * kAmChunk; l0 < nsteps; l0 += kAmChunk) {
+      double al[kAmChunk];   // past the last step: the next m's (or zero padding), times B = 0 below
+#pragma unroll
+      for (int sp = 0; sp < kAmChunk; ++sp) al[sp] = alpha[base + l0 + sp];
+      double b[2][4];
+#pragma unroll
+      for (int par = 0; par < 2; ++par)
+#pragma unroll
+        for (int sk = 0; sk < 4; ++sk) {
+          const int stp = l0 + 2 * (4 * sk + kq) + par;
+          b[par][sk] = (colok && stp < nsteps) ? acol[2 * stp] : 0.0;
+        }
+#pragma unroll
+      for (int sp = 0; sp < kAmChunk; ++sp) {
+        if (sp % kGroup == 0 && (l0 + sp) / kGroup == gs) {
+          v0 = st0.x;
+          v1 = st0.y;
+        }
+        const double mu = fma(al[sp] * z, v1, -v0);
+        v0 = v1;
+        v1 = mu;
+        mu_s[sp * kSmRow + lane] = mu;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int sk = 0; sk < 4; ++sk)
+#pragma unroll
+        for (int par = 0; par < 2; ++par)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const double a = mu_s[(2 * (4 * sk + kq) + par) * kSmRow + 16 * t + jc];
+            acc[t][par] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[par][sk], acc[t][par], 0, 0, 0);
+          }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  // D[i][j] in lane j + 16 (i % 4), register i / 4: pair 64 g + 16 t + i, column j / 2, re/im j % 2
+  if (!colok) return;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int pr = 64 * g + 16 * t + 4 * r + kq;
+      if (pr < npairs) {
+        double* dst = reinterpret_cast<double*>(eo + col * eo_stride + ((size_t)pr * (mmax + 1) + m) * 2) + ri;
+        dst[0] = acc[t][0][r];
+        dst[2] = acc[t][1][r];
+      }
+    }
+}
+
 int pick_nr(int n) { return n >= 8 ? 8 : n >= 4 ? 4 : n >= 2 ? 2 : 1; }
 
 template <int NR>
@@ -541,6 +641,23 @@ hipError_t launch_legendre_start(const crsht_plan* P, hipStream_t s) {
 
 hipError_t launch_legendre_synth(const crsht_plan* P, int nrhs, const double2* alms, double2* eo, hipStream_t s) {
   const int64_t eo_stride = (int64_t)P->g.npairs * (P->g.mmax + 1) * 2;
+  if (nrhs >= 2) {
+    // FP64 matrix cores, 8 columns per launch
+    const Geometry& g = P->g;
+    const int ngroups = (g.npairs + 63) / 64;
+    const int nb = 8 * ngroups * ((g.mmax + 1 + 7) / 8);
+    for (int c0 = 0; c0 < nrhs; c0 += kAmCols) {
+      const int nc = std::min(kAmCols, nrhs - c0);
+      timing_begin(P, 0, s);
+      hipLaunchKernelGGL(k_legendre_synth_mfma, dim3(nb), dim3(64), 0, s, g.lmax, g.mmax, g.npairs, nc, ngroups,
+                         P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
+                         alms + (int64_t)c0 * g.nalm, (int64_t)g.nalm, eo + (int64_t)c0 * eo_stride, eo_stride);
+      timing_end(P, 0, s);
+      const hipError_t err = hipGetLastError();
+      if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+  }
   for (int c0 = 0; c0 < nrhs;) {
     const int nr = pick_nr(nrhs - c0);
     const double2* a = alms + (int64_t)c0 * P->g.nalm;
