@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 
 # MI355X published peaks
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+FP64_MATRIX_PEAK_TFLOPS = 78.6     # dense FP64 MFMA (MI355X datasheet)
 BF16_MFMA_PEAK_TFLOPS = 2500.0     # dense
 HBM_PEAK_GBS = 8000.0
 
@@ -351,11 +352,19 @@ def main():
                     BF16_MFMA_PEAK_TFLOPS, "TFLOP/s", "legendre_mfma.hip")
     # FP64 Legendre kernels: the plain path, and in the mixed path the FP64
     # true residuals of the refinement and the right-hand side
-    gs, ga = groups(cs), groups(ca)
-    kinfo[0] = ("k_legendre_synth (FP64 VALU)", "alu", sum((3 + 4 * g) * T for g in gs) / len(gs),
-                FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s", "legendre.hip")
-    kinfo[1] = ("k_legendre_adj (FP64 VALU, whole transform)", "alu", sum((3 + 4 * g) * T for g in ga),
-                FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s", "legendre.hip")
+    # with two or more columns they run on the FP64 matrix cores in launches
+    # of up to 8 columns (FP64 vector units for a single column)
+    def fp64_groups(n):
+        return [min(8, n - c) for c in range(0, n, 8)] if n >= 2 else [1]
+    gs, ga = fp64_groups(cs), fp64_groups(ca)
+    f64m = cs >= 2
+    kinfo[0] = ("k_legendre_synth_mfma (FP64 MFMA Legendre synthesis)" if f64m else "k_legendre_synth (FP64 VALU)",
+                "mfma" if f64m else "alu", sum((3 + 4 * g) * T for g in gs) / len(gs),
+                FP64_MATRIX_PEAK_TFLOPS if f64m else FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s", "legendre.hip")
+    kinfo[1] = ("k_legendre_adj_mfma (FP64 MFMA Legendre adjoint, whole transform)" if ca >= 2
+                else "k_legendre_adj (FP64 VALU, whole transform)", "mfma" if ca >= 2 else "alu",
+                sum((3 + 4 * g) * T for g in ga),
+                FP64_MATRIX_PEAK_TFLOPS if ca >= 2 else FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s", "legendre.hip")
     if use_block:
         # stored inverses (FP32, sum of n^2 over the (m, parity) blocks of
         # every component) + r read + z written
