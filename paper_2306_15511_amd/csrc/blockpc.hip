@@ -49,7 +49,7 @@ namespace {
 constexpr int kStartGroup = 16;   // start-table group of the Legendre recurrence
 constexpr int kNeverG = 0x7fffffff;
 constexpr int kPcWaves = 2;       // wavefronts per application workgroup
-constexpr int kPcRows = 128 * kPcWaves;   // rows of a block per application workgroup (128 per wavefront)
+constexpr int kPcRows = 128;     // rows of each parity block per application workgroup
 constexpr int kPcCols = 16;       // right-hand sides per application pass
 constexpr int kPcJ = 64;          // r rows staged per LDS tile
 constexpr int kPad = 32;          // bucket granularity of the padded block size
@@ -187,44 +187,52 @@ __global__ void k_pc_store(const int* __restrict__ blocks, const int* __restrict
   inv[boff[blk] + (size_t)j * pc_ld(n) + i] = (float)v;
 }
 
-// z = M^-1 r for one block and 16 right-hand sides (32 real columns) on the
-// matrix cores (v_mfma_f32_32x32x2_f32). Wavefront w of a workgroup owns the
-// rows [i0, i0 + 128), i0 = r0 + 128 w. Per K step (rows j, j + 1 of the
-// symmetric M^-1) lane l of half h loads the float4 M^-1[j + h][i0 + 4 l ..
-// i0 + 4 l + 3], so one load instruction reads two contiguous 512-byte runs;
-// component v of it is the A operand of the v-th of four MFMAs whose 32 output
-// rows are i0 + 4 t + v (t = 0 .. 31), each with its own accumulator. The B
-// operand R[j + h][c] comes from an LDS tile of kPcJ rows j (FP32; rows padded
-// to 33 floats so the staging writes spread over the banks). The A loads of
-// the next kPcPre K steps are in flight while the current ones are multiplied.
+// z = M^-1 r for the two parity blocks of one m (one component) and 16
+// right-hand sides (32 real columns) on the matrix cores
+// (v_mfma_f32_32x32x2_f32). A workgroup takes rows [r0, r0 + 128) of both
+// blocks: wavefront w of block b_w (b_0: l - m even, b_1: odd, -1 if absent).
+// The two blocks' coefficients interleave in the vectors, so the workgroup
+// stages one contiguous residual range for both (coalesced loads) and both
+// wavefronts' results fill the same memory sectors close in time. Per K step
+// (rows j, j + 1 of the symmetric M^-1) lane l of half h loads the float4
+// M^-1[j + h][i0 + 4 l .. i0 + 4 l + 3], so one load instruction reads two
+// contiguous 512-byte runs; component v of it is the A operand of the v-th of
+// four MFMAs whose 32 output rows are i0 + 4 t + v (t = 0 .. 31), each with
+// its own accumulator. The B operand R[j + h][c] comes from an LDS tile of
+// kPcJ rows j per parity (FP32; rows padded to 33 floats so the staging
+// writes spread over the banks). The A loads of the next kPcPre K steps are in
+// flight while the current ones are multiplied.
 // MFMA 32x32x2 f32 lane layout: A[i][k] in lane i + 32 k, B[k][c] in lane
 // c + 32 k, D[i][c] in lane c + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4.
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 constexpr int kPcPre = 4;          // K steps per prefetch group
-// (three wavefronts per SIMD: 154 registers, more loads in flight per CU)
-__global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_pc_apply(int nrhs, int64_t vlen, const int64_t* __restrict__ be0,
-                                                            const int* __restrict__ task_b,
-                                                            const int* __restrict__ task_r0,
-                                                            const int* __restrict__ bn,
-                                                            const int64_t* __restrict__ boff,
-                                                            const float* __restrict__ inv,
-                                                            const double2* __restrict__ r, double2* __restrict__ z) {
-  constexpr int kSteps = kPcJ / 2;                      // K steps per LDS tile
-  constexpr int kR = kPcJ * kPcCols / (kPcWaves * 64);  // residual values staged per thread and tile
+// (three wavefronts per SIMD: more loads in flight per CU)
+__global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_pc_apply(
+    int nrhs, int64_t vlen, const int64_t* __restrict__ be0, const int* __restrict__ task_b,
+    const int* __restrict__ task_b1, const int* __restrict__ task_r0, const int* __restrict__ bn,
+    const int64_t* __restrict__ boff, const float* __restrict__ inv, const double2* __restrict__ r,
+    double2* __restrict__ z) {
+  constexpr int kSteps = kPcJ / 2;                          // K steps per LDS tile
+  constexpr int kR = 2 * kPcJ * kPcCols / (kPcWaves * 64);  // residual values staged per thread and tile
   static_assert(kSteps % kPcPre == 0, "tile must hold whole prefetch groups");
-  __shared__ float rs[kPcJ][33];
-  const int b = task_b[blockIdx.x];
-  if (b < 0) return;   // padding task (uniform per workgroup, before any barrier)
-  const int n = bn[b];
-  const int ld = pc_ld(n);
+  static_assert(kPcWaves == 2, "one wavefront per parity block");
+  __shared__ float rs[2][kPcJ][33];
+  const int b0 = task_b[blockIdx.x];
+  if (b0 < 0) return;   // padding task (uniform per workgroup, before any barrier)
+  const int b1 = task_b1[blockIdx.x];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int b = w == 0 ? b0 : b1;
+  const int n0 = bn[b0];                                    // the even block is the larger one
+  const int n1 = b1 >= 0 ? bn[b1] : 0;
+  const int n = w == 0 ? n0 : n1;
+  const int ld = pc_ld(n);
   const int il = lane & 31, kk = lane >> 5;
-  const int i0 = task_r0[blockIdx.x] + 128 * w;
-  const int ic = i0 + 4 * il;                           // first of this lane's 4 rows
-  const bool colok = ic < ld;                           // padding rows n .. ld - 1 hold zeros
-  const int64_t e0 = be0[b];                            // element of row j: e0 + 2 j
-  const float* __restrict__ Ab = inv + boff[b] + (colok ? ic : 0);
-  const int ntile = (n + kPcJ - 1) / kPcJ;
+  const int i0 = task_r0[blockIdx.x];
+  const int ic = i0 + 4 * il;                               // first of this lane's 4 rows
+  const bool colok = ic < ld;                               // padding rows n .. ld - 1 hold zeros
+  const int64_t e00 = be0[b0];                              // element of row j of block q: e00 + q + 2 j
+  const float* __restrict__ Ab = inv + (b >= 0 ? boff[b] : 0) + (colok ? ic : 0);
+  const int ntile = (n0 + kPcJ - 1) / kPcJ;
   for (int c0 = 0; c0 < nrhs; c0 += kPcCols) {
     const int nc = min(kPcCols, nrhs - c0);
     f32x16_t acc0 = {}, acc1 = {}, acc2 = {}, acc3 = {};
@@ -248,14 +256,17 @@ __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3
       const int g0 = G % kGpt;
       if (g0 == 0) {
         const int j0 = (G / kGpt) * kPcJ;
-        __syncthreads();                                // previous tile's products have read rs
+        __syncthreads();                                    // previous tile's products have read rs
 #pragma unroll
         for (int k = 0; k < kR; ++k) {
+          // consecutive threads read consecutive coefficients (both parities)
           const int e = threadIdx.x + k * kPcWaves * 64;
-          const int jj = e % kPcJ, cc = e / kPcJ, j = j0 + jj;
-          const double2 v = (cc < nc && j < n) ? r[(int64_t)(c0 + cc) * vlen + e0 + 2 * j] : make_double2(0.0, 0.0);
-          rs[jj][2 * cc] = (float)v.x;
-          rs[jj][2 * cc + 1] = (float)v.y;
+          const int ee = e % (2 * kPcJ), cc = e / (2 * kPcJ);
+          const int q = ee & 1, jj = ee >> 1, j = j0 + jj;
+          const bool in = cc < nc && j < (q ? n1 : n0);
+          const double2 v = in ? r[(int64_t)(c0 + cc) * vlen + e00 + 2 * j0 + ee] : make_double2(0.0, 0.0);
+          rs[q][jj][2 * cc] = (float)v.x;
+          rs[q][jj][2 * cc + 1] = (float)v.y;
         }
         __syncthreads();
       }
@@ -266,7 +277,7 @@ __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3
       if (i0 < n) {
 #pragma unroll
         for (int u = 0; u < kPcPre; ++u) {
-          const float bval = rs[2 * (g0 * kPcPre + u) + kk][il];
+          const float bval = rs[w][2 * (g0 * kPcPre + u) + kk][il];
           acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[u].x, bval, acc0, 0, 0, 0);
           acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[u].y, bval, acc1, 0, 0, 0);
           acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[u].z, bval, acc2, 0, 0, 0);
@@ -279,7 +290,7 @@ __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3
       if (rhs < nc) {
         // row i0 + 16 kk + rr, rr = 4 (8 (q / 4) + q % 4) + v: one base pointer, constant offsets
         const int ib = i0 + 16 * kk;
-        double* __restrict__ zb = reinterpret_cast<double*>(z + (int64_t)(c0 + rhs) * vlen + e0 + 2 * ib) + comp;
+        double* __restrict__ zb = reinterpret_cast<double*>(z + (int64_t)(c0 + rhs) * vlen + e00 + w + 2 * ib) + comp;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const f32x16_t a = v == 0 ? acc0 : v == 1 ? acc1 : v == 2 ? acc2 : acc3;
@@ -336,7 +347,7 @@ int dev_upload(T** p, const std::vector<T>& h) {
 }  // namespace
 
 void block_pc_free(BlockPC& pc) {
-  void* ptrs[] = {pc.inv, pc.bm, pc.bq, pc.bn, pc.boff, pc.be0, pc.task_b, pc.task_r0};
+  void* ptrs[] = {pc.inv, pc.bm, pc.bq, pc.bn, pc.boff, pc.be0, pc.task_b, pc.task_b1, pc.task_r0};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   pc = BlockPC();
@@ -371,43 +382,50 @@ int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
   }
   const int nb = (int)bm.size();
   const int nbc = nb / ncomp;   // blocks per component; block b of component k is k nbc + b
-  // Application tasks (block, first row), dealt to the 8 XCDs (workgroup i
-  // runs on XCD i mod 8): the tasks of both parity blocks of one (component,
-  // m) go to one XCD, so they share the residual lines they read and the
-  // result lines they write in that XCD's L2; units are placed largest first
-  // on the least loaded XCD, and within an XCD run largest first. Short XCD
-  // lists are padded with empty tasks (block -1).
+  // Application tasks (even block, odd block or -1, first row): one
+  // workgroup per 128 rows of both parity blocks of one (component, m),
+  // dealt to the 8 XCDs (workgroup i runs on XCD i mod 8) so that the tasks
+  // of one m share the residual lines they read and the result lines they
+  // write in that XCD's L2; units are placed largest first on the least
+  // loaded XCD, and within an XCD run largest first. Short XCD lists are
+  // padded with empty tasks (block -1).
   constexpr int kXcd = 8;
-  std::vector<std::pair<double, int>> units;   // (cost, first block of the unit)
+  struct Unit {
+    double cost;
+    int b0, b1;
+  };
+  std::vector<Unit> units;
   for (int b = 0; b < nb; ++b)
     if (bq[b] == 0) {
+      const int b1 = (b + 1 < nb && bq[b + 1] == 1 && bm[b + 1] == bm[b]) ? b + 1 : -1;
       double cost = (double)bn[b] * bn[b];
-      if (b + 1 < nb && bq[b + 1] == 1 && bm[b + 1] == bm[b]) cost += (double)bn[b + 1] * bn[b + 1];
-      units.push_back({cost, b});
+      if (b1 >= 0) cost += (double)bn[b1] * bn[b1];
+      units.push_back({cost, b, b1});
     }
-  std::stable_sort(units.begin(), units.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
-  std::vector<std::vector<int>> xb(kXcd), xr(kXcd);
+  std::stable_sort(units.begin(), units.end(), [](const Unit& x, const Unit& y) { return x.cost > y.cost; });
+  std::vector<std::vector<int>> xb(kXcd), xb1(kXcd), xr(kXcd);
   std::vector<double> load(kXcd, 0.0);
-  for (const auto& u : units) {
+  for (const Unit& u : units) {
     const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    load[x] += u.first;
-    for (int b = u.second; b < nb && bm[b] == bm[u.second] && (b == u.second || bq[b] == 1); ++b)
-      for (int r0 = 0; r0 < bn[b]; r0 += kPcRows) {
-        xb[x].push_back(b);
-        xr[x].push_back(r0);
-      }
+    load[x] += u.cost;
+    for (int r0 = 0; r0 < bn[u.b0]; r0 += kPcRows) {   // the even block has the most rows
+      xb[x].push_back(u.b0);
+      xb1[x].push_back(u.b1);
+      xr[x].push_back(r0);
+    }
   }
   size_t per = 0;
   for (int x = 0; x < kXcd; ++x) per = std::max(per, xb[x].size());
-  std::vector<int> tb(per * kXcd, -1), tr(per * kXcd, 0);
+  std::vector<int> tb(per * kXcd, -1), tb1(per * kXcd, -1), tr(per * kXcd, 0);
   for (int x = 0; x < kXcd; ++x)
     for (size_t k = 0; k < xb[x].size(); ++k) {
       tb[k * kXcd + x] = xb[x][k];
+      tb1[k * kXcd + x] = xb1[x][k];
       tr[k * kXcd + x] = xr[x][k];
     }
   int rc;
   if ((rc = dev_upload(&pc.bm, bm)) || (rc = dev_upload(&pc.bq, bq)) || (rc = dev_upload(&pc.bn, bn)) ||
-      (rc = dev_upload(&pc.boff, boff)) || (rc = dev_upload(&pc.be0, be0)) || (rc = dev_upload(&pc.task_b, tb)) ||
+      (rc = dev_upload(&pc.boff, boff)) || (rc = dev_upload(&pc.be0, be0)) || (rc = dev_upload(&pc.task_b, tb)) || (rc = dev_upload(&pc.task_b1, tb1)) ||
       (rc = dev_upload(&pc.task_r0, tr)) || (rc = dev_alloc(&pc.inv, (size_t)off))) {
     block_pc_free(pc);
     return rc;
@@ -556,7 +574,7 @@ hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, doub
   const BlockPC& pc = P->pc;
   timing_begin(P, 5, s);
   hipLaunchKernelGGL(k_pc_apply, dim3(pc.ntasks), dim3(kPcWaves * 64), 0, s, nrhs, vlen(P), pc.be0, pc.task_b,
-                     pc.task_r0, pc.bn, pc.boff, pc.inv, r, z);
+                     pc.task_b1, pc.task_r0, pc.bn, pc.boff, pc.inv, r, z);
   timing_end(P, 5, s);
   return hipGetLastError();
 }

@@ -152,7 +152,8 @@ struct Timing {
 namespace crsht {
 // Per-m block preconditioner (blockpc.hip): for each (m, parity q of l - m)
 // block of n rows l = m + q + 2 i, the FP32 inverse n x n (full symmetric) at
-// inv + boff[b]; application tasks cover kPcRows rows of one block each.
+// inv + boff[b]; application tasks cover 128 rows of both parity blocks of
+// one m (task_b: even block, task_b1: odd block or -1).
 struct BlockPC {
   bool built = false;
   int lmin = 0;
@@ -162,7 +163,7 @@ struct BlockPC {
   int *bm = nullptr, *bq = nullptr, *bn = nullptr;
   int64_t* boff = nullptr;   // first FP32 element of each stored inverse
   int64_t* be0 = nullptr;    // vector element of row 0 of each block (component offset included)
-  int *task_b = nullptr, *task_r0 = nullptr;
+  int *task_b = nullptr, *task_b1 = nullptr, *task_r0 = nullptr;
 };
 
 // identity of a captured PCG iteration block: replayed only for the same
