@@ -215,6 +215,7 @@ __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3
   constexpr int kSteps = kPcJ / 2;                          // K steps per LDS tile
   constexpr int kR = 2 * kPcJ * kPcCols / (kPcWaves * 64);  // residual values staged per thread and tile
   static_assert(kSteps % kPcPre == 0, "tile must hold whole prefetch groups");
+  static_assert(kR % 4 == 0, "residual staging in batches of 4");
   static_assert(kPcWaves == 2, "one wavefront per parity block");
   __shared__ float rs[2][kPcJ][33];
   const int b0 = task_b[blockIdx.x];
@@ -257,16 +258,27 @@ __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3
       if (g0 == 0) {
         const int j0 = (G / kGpt) * kPcJ;
         __syncthreads();                                    // previous tile's products have read rs
+        // consecutive threads read consecutive coefficients (both parities);
+        // in batches of 4 to bound the registers held by loads in flight
+#pragma unroll 1
+        for (int k0 = 0; k0 < kR; k0 += 4) {
+          double2 v[4];
 #pragma unroll
-        for (int k = 0; k < kR; ++k) {
-          // consecutive threads read consecutive coefficients (both parities)
-          const int e = threadIdx.x + k * kPcWaves * 64;
-          const int ee = e % (2 * kPcJ), cc = e / (2 * kPcJ);
-          const int q = ee & 1, jj = ee >> 1, j = j0 + jj;
-          const bool in = cc < nc && j < (q ? n1 : n0);
-          const double2 v = in ? r[(int64_t)(c0 + cc) * vlen + e00 + 2 * j0 + ee] : make_double2(0.0, 0.0);
-          rs[q][jj][2 * cc] = (float)v.x;
-          rs[q][jj][2 * cc + 1] = (float)v.y;
+          for (int k = 0; k < 4; ++k) {
+            const int e = threadIdx.x + (k0 + k) * kPcWaves * 64;
+            const int ee = e % (2 * kPcJ), cc = e / (2 * kPcJ);
+            const int q = ee & 1, j = j0 + (ee >> 1);
+            const bool in = cc < nc && j < (q ? n1 : n0);
+            v[k] = in ? r[(int64_t)(c0 + cc) * vlen + e00 + 2 * j0 + ee] : make_double2(0.0, 0.0);
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int e = threadIdx.x + (k0 + k) * kPcWaves * 64;
+            const int ee = e % (2 * kPcJ), cc = e / (2 * kPcJ);
+            const int q = ee & 1, jj = ee >> 1;
+            rs[q][jj][2 * cc] = (float)v[k].x;
+            rs[q][jj][2 * cc + 1] = (float)v[k].y;
+          }
         }
         __syncthreads();
       }

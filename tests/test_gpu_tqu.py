@@ -276,3 +276,82 @@ def test_tqu_nside512_sampled_rings_and_adjointness():
     from oracle.sht import dot
     rhs = sum(dot(a[k], ya[k], lmax, lmax) for k in range(3))
     assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(got) * np.linalg.norm(y)
+
+
+def test_tqu_nside1024_16_columns_sampled():
+    # the largest T+Q+U workload (Nside 1024, lmax 2047, 16 columns: 8 chains
+    # x mean and fluctuation): sampled rings of T, Q, U of the first and last
+    # column against the oracle (FP64 and mixed), adjointness of the transform
+    # pair and symmetry of the FP64 operator on two columns, and the block
+    # preconditioner (built at this size) symmetric and positive
+    m = _m()
+    from oracle import sht as osht, spin2
+    nside, lmax, ncol = 1024, 2047, 16
+    print("case tqu nside1024 x16", flush=True)
+    plan = m.Plan(nside, lmax, nrhs_max=ncol, ncomp=3)
+    rng = np.random.default_rng(1024)
+    ls, ms = ci.alm_lm_arrays(lmax)
+    a = (rng.standard_normal((ncol, 3, ls.size)) + 1j * rng.standard_normal((ncol, 3, ls.size))) / math.sqrt(2.0)
+    a[:, :, ls < 2] = 0.0
+    a[:, :, ms == 0] = a[:, :, ms == 0].real
+    da = tc(a)
+    del a
+    npix = 12 * nside * nside
+    rings = [0, 1, 700, 2047, 3000, 4094]
+    pol = spin2.PolSHT(nside, lmax)
+    R = pol.s.rings
+    cols = [0, ncol - 1]
+    # Q and U carry the 1/sin^2 cancellation of the spin-2 sums (module
+    # docstring): FP64 rounding u of the Legendre sums reaches Q, U amplified
+    # by up to 1/sin^2 (1.6e6 on the first ring here), so their bound on a
+    # ring is max(TOL, 8 u / sin^2); the mixed path is held to MIXED_TOL on
+    # rings with sin^2 > 0.01 (its polar-ring error is reported)
+    u = np.finfo(np.float64).eps / 2
+    for prec in (m.CR_F64, m.CR_MIXED):
+        got = m.synth(plan, da, prec=prec)
+        sel = {k: got[cols, :, int(R.first[k]):int(R.first[k]) + int(R.nphi[k])].cpu().numpy() for k in rings}
+        del got
+        worst = {}
+        for ci_, c in enumerate(cols):
+            ac = da[c].cpu().numpy()
+            rt = osht.synth_rings(pol.s, ac[0], rings)
+            rp = pol.synth_rings(ac[1], ac[2], rings)
+            for k in rings:
+                s2 = float(R.sin_theta[k]) ** 2
+                for comp, ref in ((0, rt[k]), (1, rp[k][0]), (2, rp[k][1])):
+                    e = rel(sel[k][ci_, comp], ref)
+                    worst[k] = max(worst.get(k, 0.0), e)
+                    if prec == m.CR_F64:
+                        tol = TOL if comp == 0 else max(TOL, 8 * u / s2)
+                        assert e < tol, (prec, c, k, comp, e, tol)
+                    elif s2 > 1e-2:
+                        assert e < MIXED_TOL, (prec, c, k, comp, e)
+        print("prec", prec, "worst rel error per sampled ring", {k: "%.1e" % v for k, v in worst.items()}, flush=True)
+    # adjointness and operator symmetry on two columns (FP64)
+    x = da[:2].contiguous()
+    y = torch.from_numpy(rng.standard_normal((2, 3, npix))).to(x.device)
+    ya = m.adjoint(plan, y)
+    sx = m.synth(plan, x)
+    lhs = float(torch.sum(sx * y))
+    mw = torch.from_numpy(np.where(ms == 0, 1.0, 2.0)).to(x.device)
+    rhs = float(torch.sum(mw * (x.real * ya.real + x.imag * ya.imag)))
+    assert abs(lhs - rhs) <= 1e-11 * float(torch.linalg.vector_norm(sx)) * float(torch.linalg.vector_norm(y))
+    wl = ci.workload_masked_t(nside, lmax, fwhm_arcmin=10.0, cfg=2)
+    z, phi = plan.pixel_coords()
+    nt = wl.ninv(z, phi)
+    gp = m.Problem(np.ascontiguousarray(ci.cl_tqu(lmax, wl.amp, 0.3)), wl.bl(),
+                   tc(np.stack([nt, nt / 2.0, nt / 2.0])), 2)
+    u = da[2:4].contiguous()
+    ax, au = m.apply(plan, gp, x), m.apply(plan, gp, u)
+    d1 = float(torch.sum(mw * (u.real * ax.real + u.imag * ax.imag)))
+    d2 = float(torch.sum(mw * (x.real * au.real + x.imag * au.imag)))
+    print("operator symmetry", d1, d2, flush=True)
+    assert abs(d1 - d2) <= 1e-10 * abs(d1)
+    m.block_precond_build(plan, gp)
+    px, pu = m.block_precond_apply(plan, x), m.block_precond_apply(plan, u)
+    e1 = float(torch.sum(mw * (u.real * px.real + u.imag * px.imag)))
+    e2 = float(torch.sum(mw * (x.real * pu.real + x.imag * pu.imag)))
+    ex = float(torch.sum(mw * (x.real * px.real + x.imag * px.imag)))
+    print("block preconditioner symmetry", e1, e2, "positivity", ex, flush=True)
+    assert abs(e1 - e2) <= 1e-5 * math.sqrt(abs(ex) * abs(float(torch.sum(mw * (u.real * pu.real + u.imag * pu.imag)))))
+    assert ex > 0
