@@ -202,6 +202,9 @@ def main():
     ap.add_argument("--nside", type=int, default=512)
     ap.add_argument("--lmax", type=int, default=None)
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--check-every", type=int, default=None,
+                    help="PCG iterations between host convergence checks (default 6 with the block "
+                         "preconditioner, 16 with Jacobi)")
     ap.add_argument("--inner-tol", type=float, default=1e-3,
                     help="mixed path: FP64 residual replacement each time the residual fell by this factor")
     ap.add_argument("--prec", choices=["f64", "mixed"], default="mixed")
@@ -259,6 +262,7 @@ def main():
         w1 = np.stack([ci.white_map(ci.rng_for(2, c, ci.STREAM_W1), wl.npix) for c in range(R)])
     prob = crsht.Problem(cl, bl, ninv, 2)
     use_block = (args.precond or "block") == "block"
+    ce = args.check_every or (6 if use_block else 16)
     pc = crsht.CR_PC_BLOCK if use_block else crsht.CR_PC_JACOBI
     pc_setup_s = None
     if use_block:
@@ -281,7 +285,7 @@ def main():
 
     def step():
         return crsht.solve(plan, prob, d, w0, w1, nrhs=R, tol=wl.tol, maxiter=20000, out=out,
-                           check_every=4 if use_block else 16, prec=prec, inner_tol=args.inner_tol, precond=pc)
+                           check_every=ce, prec=prec, inner_tol=args.inner_tol, precond=pc)
 
     f64_cmp = None
     if not args.no_f64_compare:
@@ -289,7 +293,7 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, st1 = crsht.solve(plan, prob, d[:1], w0[:1], w1[:1], nrhs=1, tol=wl.tol, maxiter=20000, out=out1,
-                             check_every=4 if use_block else 16, prec=crsht.CR_F64, precond=pc)
+                             check_every=ce, prec=crsht.CR_F64, precond=pc)
         torch.cuda.synchronize()
         t1 = time.perf_counter() - t0
         f64_cmp = {"form": "plain FP64 PCG, 1 column (column 0 of the batch), same preconditioner",

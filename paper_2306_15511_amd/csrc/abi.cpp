@@ -511,7 +511,15 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
       for (int c = 0; c < nrhs; ++c) {
         double* sc = P->w.host_scal + c * kScalSlots;
         if (sc[S_BREAK] != 0.0) continue;
-        sc[S_RESTART] = (trig[c] && rel[c] >= last[c]) ? 1.0 : 0.0;
+        // keep the direction only when the replacement corrects the
+        // recursive residual by a small relative amount; restart it when the
+        // true residual did not fall since the last replacement, or when it is
+        // far above the recursive one (the Krylov recurrences drifted: with a
+        // strong preconditioner and long blocks between checks the recursive
+        // residual can fall orders of magnitude below the reach of the
+        // low-precision operator, and beta from it would be meaningless)
+        const double rec = keep[(size_t)c * kScalSlots + S_REL];
+        sc[S_RESTART] = (trig[c] && (rel[c] >= last[c] || rel[c] > 4.0 * rec)) ? 1.0 : 0.0;
         last[c] = rel[c];
         refine[c] += 1;
         if (rel[c] <= tol) {

@@ -168,3 +168,29 @@ def test_tqu_solve_with_block_preconditioner(prec):
         assert st[c].status == 0
         assert res <= 1.05 * tol
         assert st[c].iters * 3 < stj[c].iters
+
+
+@pytest.mark.parametrize("check_every", [12, 16])
+def test_mixed_block_pc_long_blocks_between_checks(check_every):
+    # with the block preconditioner the recursive residual can fall far below
+    # what the mixed operator reaches within one block of iterations; the
+    # replacement must then restart the direction instead of taking beta from
+    # the drifted recursion (regression: this used to stagnate until maxiter)
+    m = _m()
+    nside, nrhs = 64, 4
+    print("case block pc long blocks", check_every, flush=True)
+    wl, P, op, d = masked_problem(nside)
+    plan = m.Plan(nside, wl.lmax, nrhs_max=nrhs)
+    gp = _gp(m, P)
+    m.block_precond_build(plan, gp)
+    rng = np.random.default_rng(65)
+    W0 = np.stack([ci.white_alm(rng, wl.lmax) for _ in range(nrhs)])
+    D = np.stack([d * (1.0 + 0.1 * c) for c in range(nrhs)])
+    s, st = m.solve(plan, gp, tc(D), tc(W0), None, nrhs=nrhs, tol=1e-6, maxiter=400, prec=m.CR_MIXED,
+                    precond=m.CR_PC_BLOCK, check_every=check_every)
+    x = s.cpu().numpy()
+    for c in range(nrhs):
+        res = real_rel(op, op.apply(x[c]), op.rhs(D[c], W0[c], None))
+        print("col %d iters %d refinements %d residual %.2e" % (c, st[c].iters, st[c].refinements, res), flush=True)
+        assert st[c].status == 0 and res <= 1.05e-6
+        assert st[c].iters <= 6 * check_every
