@@ -145,32 +145,49 @@ __global__ __launch_bounds__(256) void k_checkpoints(int lmax, int mmax, int npa
 // ------------------------------------------------------ synthesis operands
 // ab tiles: for each (m, chunk c of 32 steps), parity q, half h, the MFMA B
 // operand B[k][j] = f_idx * alm[rhs][idx], idx = (l = m + 32 c + 2 k + q, m),
-// j = 2 rhs + (re, im), in lane order (lane j + 32 (k/8) holds 8 bf16).
+// j = 2 rhs + (re, im), in lane order (lane j + 32 (k/8) holds 8 bf16). The
+// block reads each column's 32 steps coalesced (lane -> step) and stages
+// f * alm (float) in LDS as [q][rhs][comp][16 steps], from which each lane
+// reads its 8 steps contiguously.
 __global__ __launch_bounds__(64) void k_prep_synth(int lmax, int nrhs, const int64_t* __restrict__ mstart,
                                                    const int64_t* __restrict__ cstart, const double2* __restrict__ alm,
                                                    int64_t alm_stride, const double* __restrict__ f,
                                                    bf16x8* __restrict__ ab, int64_t ab_gstride) {
+  __shared__ __attribute__((aligned(16))) float st_lds[2][16][2][16];
   const int m = blockIdx.y, c = blockIdx.x, grp = blockIdx.z;   // group grp: right-hand sides 16 grp ..
+  nrhs -= 16 * grp;
+  alm += (int64_t)16 * grp * alm_stride;
+  ab += grp * ab_gstride;
   const int nsteps = lmax - m + 1;
   if (c * kSynChunk >= nsteps) return;
   const int lane = threadIdx.x;
-  const int j = lane & 31, kg = lane >> 5;
-  const int rhs = 16 * grp + (j >> 1), comp = j & 1;
   const int64_t base = mstart[m];
-  bf16x8* dst = ab + grp * ab_gstride + (size_t)(cstart[m] + c) * 4 * 64;
+  // element phase: lane -> step lane & 31, columns (lane >> 5) + 2 i
+  const int st = c * kSynChunk + (lane & 31);
+  const bool live = st < nsteps;
+  const double fv = live ? f[base + st] : 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int rhs = (lane >> 5) + 2 * i;
+    const double2 a = (rhs < nrhs && live) ? alm[rhs * alm_stride + base + st] : make_double2(0.0, 0.0);
+    const int q = (lane & 31) & 1, n = (lane & 31) >> 1;
+    st_lds[q][rhs][0][n] = to_f32(fv * a.x);
+    st_lds[q][rhs][1][n] = to_f32(fv * a.y);
+  }
+  __syncthreads();
+  // tile phase: lane j + 32 kg, j = 2 rhs + comp, holds steps 2 (8 kg + v) + q
+  const int j = lane & 31, kg = lane >> 5;
+  bf16x8* dst = ab + (size_t)(cstart[m] + c) * 4 * 64;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
+    const float* src = &st_lds[q][j >> 1][j & 1][8 * kg];
+    const float4 a4 = *reinterpret_cast<const float4*>(src), b4 = *reinterpret_cast<const float4*>(src + 4);
+    const float x[8] = {a4.x, a4.y, a4.z, a4.w, b4.x, b4.y, b4.z, b4.w};
     bf16x8 hi, lo;
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
-      const int st = c * kSynChunk + 2 * (8 * kg + v) + q;
-      double x = 0.0;
-      if (rhs < nrhs && st < nsteps) {
-        const double2 a = alm[rhs * alm_stride + base + st];
-        x = f[base + st] * (comp ? a.y : a.x);
-      }
       __bf16 h, l;
-      split_bf16((float)x, h, l);
+      split_bf16(x[v], h, l);
       hi[v] = h;
       lo[v] = l;
     }
