@@ -13,6 +13,17 @@ Steps of the move (the paper's enumerated algorithm, steps 2-4):
 Readings: the garbled middle term of pi is read as a^T S^-1 a^ (completing
 the square makes it exact); the prior is uniform in q, so the lognormal
 proposal contributes the Jacobian factor q'/q; ties ln u = ln A reject.
+
+The standard two-block Gibbs move (Sect. 2.2.1; the baseline the joint move
+is compared with) for the same one-parameter family is gibbs_step: q given
+the current sky from its inverse-gamma conditional, then the sky given q.
+
+Pins (tests/test_oracle_joint.py): the acceptance identity against the joint
+posterior of the dense model, the misread middle term breaking it, accept and
+reject paths; the Gibbs conditional's draws against a numerical integral of
+q^(-k/2) exp(-t/(2q)); both samplers' chains against the exact marginal
+posterior p(q | d) of a tiny masked problem (Gaussian likelihood of the
+observed pixels, brute force on a grid of q).
 """
 from __future__ import annotations
 
@@ -80,3 +91,36 @@ def joint_step(fid: Problem, d, state: ChainState, xi: float, u: float, w0_new, 
     fhat, _ = pcg(op, op.rhs(w0=w0_new, w1=w1_new), tol, maxiter)
     new = ChainState(q_new, ahat, fhat, lnpi(op, d, ahat, fhat))
     return new, StepResult(True, lnA, q_new, lp_new)
+
+
+# ------------------------------------------------------------ standard Gibbs
+def n_dof(lmax: int, lmin: int) -> int:
+    """Real degrees of freedom of a real field with lmin <= l <= lmax."""
+    return sum(2 * l + 1 for l in range(lmin, lmax + 1))
+
+
+def gibbs_shape(fid: Problem) -> float:
+    """Shape of the inverse-gamma conditional q | s under a uniform prior in q:
+    p(q | s) is proportional to q^(-k/2) exp(-t / (2 q)), i.e. shape k/2 - 1."""
+    return 0.5 * n_dof(fid.lmax, fid.lmin) - 1.0
+
+
+@dataclass
+class GibbsResult:
+    q_new: float
+    t: float
+
+
+def gibbs_step(fid: Problem, d, state: ChainState, g: float, w0_new, w1_new, tol: float, maxiter: int = 20000):
+    """One move of the standard two-block Gibbs sampler (Sect. 2.2.1) for
+    C_l(q) = q C_l^fid: q | s with s = a^ + f^ the current sky, t = s^T
+    S_fid^-1 s, q' = (t / 2) / g for g ~ Gamma(gibbs_shape, 1) supplied by the
+    caller; then s | q': the mean field and a fresh fluctuation at q'."""
+    op_fid = CROperator(fid)
+    s = state.ahat + state.fhat
+    t = op_fid.dot(s, op_fid.sinv * s)
+    q_new = 0.5 * t / g
+    op = CROperator(scaled_problem(fid, q_new))
+    ahat, _ = pcg(op, op.rhs(d=d), tol, maxiter)
+    fhat, _ = pcg(op, op.rhs(w0=w0_new, w1=w1_new), tol, maxiter)
+    return ChainState(q_new, ahat, fhat, lnpi(op, d, ahat, fhat)), GibbsResult(q_new, t)

@@ -80,3 +80,92 @@ def test_joint_step_accept_and_reject_paths():
     opn = cr.CROperator(joint.scaled_problem(P, s_acc.q))
     assert abs(s_acc.lnpi - joint.lnpi(opn, d, s_acc.ahat, s_acc.fhat)) < 1e-9 * abs(s_acc.lnpi)
     _ = rng
+
+
+def _tiny(nside=2, lmax=4):
+    wl = ci.workload_masked_t(nside, lmax)
+    z, phi = healpix.pixel_coords(nside)
+    ninv = wl.ninv(z, phi)
+    P = cr.Problem(nside, lmax, wl.cl(), wl.bl(), ninv)
+    op = cr.CROperator(P)
+    d = op.sht.synth(op.b * wl.signal()) + wl.noise(z, phi)
+    return wl, P, op, d
+
+
+def test_gibbs_conditional_parameters_against_numeric_density():
+    # q | s for a uniform prior in q: the density is p(s | q) of the real
+    # degrees of freedom (variance q C_l / W per coordinate, W = 1 for m = 0,
+    # 2 for m > 0), integrated numerically on a grid of q; the step's
+    # inverse-gamma (shape gibbs_shape, scale t/2) must have its moments
+    wl, P, op, d = _tiny(2, 3)
+    rng = np.random.default_rng(3)
+    st = joint.init_state(P, d, 1.0, ci.white_alm(rng, P.lmax), rng.standard_normal(d.size), 1e-12)
+    D = dense.DenseY(P.nside, P.lmax, lmin=2)
+    u = D.to_real(st.ahat + st.fhat)
+    var1 = D._per_dof(P.cl) / D.W
+    qs = np.exp(np.linspace(np.log(1e-3), np.log(1e3), 200001))
+    lp = np.array([-0.5 * np.sum(u * u / (q * var1)) - 0.5 * np.sum(np.log(q * var1)) for q in qs[::100]])
+    qg = qs[::100]
+    w = np.exp(lp - lp.max()) * qg                      # uniform prior in q on a log grid
+    mean = float(np.sum(w * qg) / np.sum(w))
+    var = float(np.sum(w * (qg - mean) ** 2) / np.sum(w))
+    _, r = joint.gibbs_step(P, d, st, 1.0, ci.white_alm(rng, P.lmax), rng.standard_normal(d.size), 1e-10)
+    a, b = joint.gibbs_shape(P), 0.5 * r.t
+    assert abs(b / (a - 1.0) - mean) < 2e-3 * mean
+    assert abs(b * b / ((a - 1.0) ** 2 * (a - 2.0)) - var) < 1e-2 * var
+    assert abs(r.q_new - b / 1.0) < 1e-12 * r.q_new      # g = 1
+
+
+def _iat(x, c=5.0):
+    """Integrated autocorrelation time (Sokal's automatic window)."""
+    x = np.asarray(x) - np.mean(x)
+    n = x.size
+    f = np.fft.rfft(x, 2 * n)
+    acf = np.fft.irfft(f * np.conj(f))[:n]
+    acf /= acf[0]
+    tau = 1.0
+    for m in range(1, n):
+        tau = 1.0 + 2.0 * np.sum(acf[1:m + 1])
+        if m >= c * tau:
+            break
+    return max(tau, 1.0)
+
+
+def test_joint_and_gibbs_chains_sample_exact_marginal_posterior():
+    # brute force on a tiny masked problem: p(q | d) from the Gaussian
+    # likelihood of the observed pixels, d ~ N(0, Y B S(q) B Y^T + N), on a
+    # grid of q; both samplers' chains must reproduce its mean within four
+    # standard errors (from the chains' own autocorrelation times)
+    wl, P, op, d = _tiny(2, 4)
+    D = dense.DenseY(P.nside, P.lmax, lmin=2)
+    obs = P.ninv > 0
+    Yo = D.Y[obs] * D._per_dof(P.bl)[None, :]
+    var1 = D._per_dof(P.cl) / D.W
+    def lnL(q):
+        C = (Yo * (q * var1)[None, :]) @ Yo.T + np.diag(1.0 / P.ninv[obs])
+        L = np.linalg.cholesky(C)
+        y = np.linalg.solve(L, d[obs])
+        return -0.5 * float(y @ y) - float(np.log(np.diag(L)).sum())
+    qs = np.exp(np.linspace(np.log(0.02), np.log(50.0), 3000))
+    lp = np.array([lnL(q) for q in qs])
+    w = np.exp(lp - lp.max()) * qs
+    exact = float(np.sum(w * qs) / np.sum(w))
+    rng = np.random.default_rng(5)
+    st0 = joint.init_state(P, d, 1.0, ci.white_alm(rng, P.lmax), rng.standard_normal(d.size), 1e-10)
+    alpha = joint.gibbs_shape(P)
+    for kind in ("joint", "gibbs"):
+        st, trace, acc = st0, [], 0
+        for _ in range(800):
+            w0n, w1n = ci.white_alm(rng, P.lmax), rng.standard_normal(d.size)
+            if kind == "joint":
+                st, r = joint.joint_step(P, d, st, rng.standard_normal(), rng.uniform(), w0n, w1n, 0.3, 1e-8)
+                acc += r.accepted
+            else:
+                st, r = joint.gibbs_step(P, d, st, rng.gamma(alpha), w0n, w1n, 1e-8)
+            trace.append(st.q)
+        x = np.array(trace[100:])
+        se = x.std() * math.sqrt(_iat(x) / x.size)
+        print(kind, "mean %.3f exact %.3f se %.3f accept %.2f" % (x.mean(), exact, se, acc / 800))
+        assert abs(x.mean() - exact) < 4.0 * se, (kind, x.mean(), exact, se)
+        if kind == "joint":
+            assert 0.2 < acc / 800 < 0.95
