@@ -286,10 +286,35 @@ typedef struct {
  * fluctuation by sqrt(q'/q); ln A = ln pi(q') - ln pi(q) + ln(q'/q) (uniform
  * prior in q; Gaussian proposal in ln q); accept iff ln u < ln A, and only then
  * solve a fresh fluctuation with draws->w0, w1 and update *state (q, lnpi,
- * ahat, fhat in place). Needs nrhs_max >= 1; uses the plan workspace.
+ * ahat, fhat in place). The mean-field solve starts from state->ahat (the
+ * mean field at q; the solve runs on the correction to the same tolerance
+ * relative to the right-hand side). Needs nrhs_max >= 1; uses the plan
+ * workspace.
  * `out` is host. Blocks until done. */
 int joint_cl_step(const crsht_plan *plan, const cr_problem *fid, const double *d, cr_chain *state,
                   const cr_draws *draws, const cr_opts *opts, cr_step_out *out, void *stream);
+
+typedef struct {
+  double q_new;        /* the drawn amplitude */
+  double t;            /* s^T S_fid^-1 s of the sky the draw conditioned on */
+  cr_stats mean_stats; /* mean-field solve at q_new */
+  cr_stats fluct_stats;/* fluctuation solve at q_new */
+} cr_gibbs_out;
+
+/* One move of the standard two-block Gibbs sampler (paper Sect. 2.2.1,
+ * standard CMB Gibbs sampling: amplitude given sky, then sky given
+ * amplitude), for the one-parameter family C_l(q) = q C_l^fid with a uniform
+ * prior in q — the baseline the joint move of joint_cl_step is compared with.
+ * With s = ahat + fhat the chain's current sky and t = s^T S_fid^-1 s over
+ * l >= lmin (real-field product), q | s is inverse gamma with shape
+ * alpha = k/2 - 1, k = sum_{l=lmin}^{lmax} (2l + 1), and scale t/2; the caller
+ * draws g ~ Gamma(alpha, 1) and the move sets q' = (t/2) / g. Then s | q':
+ * the mean field (warm-started from state->ahat) and a fresh fluctuation from
+ * w0, w1 (device; either may be NULL, not both), and ln pi of the new state.
+ * *state is updated in place; `out` is host. Temperature plans (CR_ENOTSUP
+ * for ncomp = 3). Blocks until done. */
+int gibbs_cl_step(const crsht_plan *plan, const cr_problem *fid, const double *d, cr_chain *state, double g,
+                  const double *w0, const double *w1, const cr_opts *opts, cr_gibbs_out *out, void *stream);
 
 /* Gradient of the synthesis for reverse-mode differentiation of a real
  * function L of the map: alm_grad = w_m Y^T map_grad with w_0 = 1 (Im of m = 0

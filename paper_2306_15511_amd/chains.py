@@ -1,0 +1,145 @@
+"""Chains of the joint amplitude / sky sampler and of the standard Gibbs
+sampler on one GPU (paper Sect. 2.2.1 and 2.2.2, for the one-parameter family
+C_l(q) = q C_l^fid with a uniform prior in q).
+
+Every move is one library call (joint_cl_step or gibbs_cl_step): the solves,
+ln pi and the accept test run on the GPU; this module only orders the moves
+of many chains, draws their random numbers on the host (numpy, so a run is
+reproducible from its seed) and reduces the traces to the diagnostics of the
+paper's comparison: the acceptance rate of the joint move and the integrated
+autocorrelation time of ln q. The mean-field solve of each move starts from
+the chain's previous mean field (warm start inside the library), and ln pi
+of the current state is carried in the chain (cached, never recomputed).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import Callable, Optional
+
+import numpy as np
+import torch
+
+from . import crsht
+
+
+def white_alm(rng: np.random.Generator, lmax: int) -> np.ndarray:
+    """Unit-variance draw of a real field's m >= 0 coefficients (m-major):
+    Re, Im ~ N(0, 1/2) for m > 0, real N(0, 1) for m = 0."""
+    ms = np.concatenate([np.full(lmax - m + 1, m) for m in range(lmax + 1)])
+    g = rng.standard_normal((2, ms.size))
+    out = (g[0] + 1j * g[1]) / math.sqrt(2.0)
+    out[ms == 0] = g[0][ms == 0]
+    return out
+
+
+def integrated_autocorr_time(x, c: float = 5.0) -> float:
+    """Integrated autocorrelation time 1 + 2 sum_k rho_k with Sokal's
+    automatic window (the smallest M with M >= c tau(M))."""
+    x = np.asarray(x, dtype=np.float64)
+    x = x - x.mean()
+    n = x.size
+    if n < 2 or not np.any(x):
+        return 1.0
+    f = np.fft.rfft(x, 2 * n)
+    acf = np.fft.irfft(f * np.conj(f))[:n]
+    acf /= acf[0]
+    tau = 1.0
+    for m in range(1, n):
+        tau = 1.0 + 2.0 * float(np.sum(acf[1:m + 1]))
+        if m >= c * tau:
+            break
+    return max(tau, 1.0)
+
+
+def scaled(fid: crsht.Problem, q: float) -> crsht.Problem:
+    return crsht.Problem(np.asarray(fid.cl) * q, fid.bl, fid.ninv, fid.lmin)
+
+
+def init_chain(plan: crsht.Plan, fid: crsht.Problem, d: torch.Tensor, q: float, w0: torch.Tensor,
+               w1: torch.Tensor, **solve_kw) -> crsht.Chain:
+    """State at amplitude q: mean field, fluctuation from (w0, w1), ln pi."""
+    p = scaled(fid, q)
+    ahat, _ = crsht.solve(plan, p, d, **solve_kw)
+    fhat, _ = crsht.solve(plan, p, None, w0, w1, **solve_kw)
+    ahat, fhat = ahat[0].clone(), fhat[0].clone()
+    return crsht.Chain(q, crsht.lnpi(plan, fid, q, d, ahat, fhat), ahat, fhat)
+
+
+@dataclass
+class ChainRun:
+    kind: str
+    q: np.ndarray            # [nchains, nsteps + 1] amplitude after each move (start first)
+    accepted: np.ndarray     # [nchains, nsteps] joint: accept flags; gibbs: all True
+    mean_iters: np.ndarray   # [nchains, nsteps] iterations of the mean-field solve
+    fluct_iters: np.ndarray  # [nchains, nsteps] iterations of the fluctuation solve (0 if rejected)
+    acceptance: np.ndarray   # [nchains]
+    iat: np.ndarray          # [nchains] integrated autocorrelation time of ln q (after burn-in)
+
+    def summary(self) -> dict:
+        return {"kind": self.kind, "chains": int(self.q.shape[0]), "steps": int(self.q.shape[1] - 1),
+                "acceptance": float(self.acceptance.mean()), "iat_lnq": float(self.iat.mean()),
+                "mean_iters": float(self.mean_iters.mean()), "q_mean": float(self.q[:, 1:].mean())}
+
+
+def default_draws(kind: str, lmax: int, npix: int, alpha: float, sigma_lnq: float, seed: int):
+    """Random numbers of each move in a fixed order (numpy Generator seeded
+    per chain): joint: xi, u, w0, w1; gibbs: g ~ Gamma(alpha, 1), w0, w1."""
+    rngs = {}
+
+    def draw(chain: int, step: int) -> dict:
+        rng = rngs.setdefault(chain, np.random.default_rng([seed, chain]))
+        out = {}
+        if kind == "joint":
+            out["xi"] = float(rng.standard_normal())
+            out["u"] = float(rng.uniform())
+        else:
+            out["g"] = float(rng.gamma(alpha))
+        out["w0"] = white_alm(rng, lmax)
+        out["w1"] = rng.standard_normal(npix)
+        return out
+
+    return draw
+
+
+def run_chains(plan: crsht.Plan, fid: crsht.Problem, d: torch.Tensor, chains: list, nsteps: int,
+               kind: str = "joint", sigma_lnq: float = 0.02, seed: int = 0, burn: int = 0,
+               draw: Optional[Callable[[int, int], dict]] = None, **solve_kw) -> ChainRun:
+    """Advance every chain (crsht.Chain, updated in place) by nsteps moves of
+    the joint sampler (kind "joint", Gaussian proposal of width sigma_lnq in
+    ln q) or of the standard Gibbs sampler (kind "gibbs"). draw(chain, step)
+    returns that move's random numbers (default: default_draws)."""
+    if kind not in ("joint", "gibbs"):
+        raise ValueError("kind must be 'joint' or 'gibbs'")
+    n = len(chains)
+    alpha = crsht.gibbs_shape(plan.lmax, fid.lmin)
+    if draw is None:
+        draw = default_draws(kind, plan.lmax, plan.npix, alpha, sigma_lnq, seed)
+    dev = d.device
+    q = np.zeros((n, nsteps + 1))
+    acc = np.zeros((n, nsteps), dtype=bool)
+    mi = np.zeros((n, nsteps), dtype=np.int64)
+    fi = np.zeros((n, nsteps), dtype=np.int64)
+    for c, ch in enumerate(chains):
+        q[c, 0] = ch.q
+    for s in range(nsteps):
+        for c, ch in enumerate(chains):
+            r = draw(c, s)
+            w0 = torch.from_numpy(np.ascontiguousarray(r["w0"])).to(dev)
+            w1 = torch.from_numpy(np.ascontiguousarray(r["w1"])).to(dev)
+            if kind == "joint":
+                res = crsht.joint_step(plan, fid, d, ch, r["xi"], r["u"], w0, w1, sigma_lnq=sigma_lnq, **solve_kw)
+                acc[c, s] = res.accepted
+            else:
+                res = crsht.gibbs_step(plan, fid, d, ch, r["g"], w0, w1, **solve_kw)
+                acc[c, s] = True
+            mi[c, s] = res.mean_stats.iters
+            fi[c, s] = res.fluct_stats.iters
+            q[c, s + 1] = ch.q
+    lnq = np.log(q[:, 1 + burn:])
+    iat = np.array([integrated_autocorr_time(x) for x in lnq])
+    return ChainRun(kind, q, acc, mi, fi, acc.mean(axis=1), iat)
+
+
+__all__ = ["white_alm", "integrated_autocorr_time", "scaled", "init_chain", "ChainRun", "default_draws",
+           "run_chains"]

@@ -68,6 +68,11 @@ class _StepOut(ctypes.Structure):
                 ("lnpi_new", ctypes.c_double), ("mean_stats", _Stats), ("fluct_stats", _Stats)]
 
 
+class _GibbsOut(ctypes.Structure):
+    _fields_ = [("q_new", ctypes.c_double), ("t", ctypes.c_double), ("mean_stats", _Stats),
+                ("fluct_stats", _Stats)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libcrsht.so is not built (%s); run python -m paper_2306_15511_amd.build" % LIB_PATH)
@@ -92,6 +97,8 @@ def _load():
         "cr_lnpi": ([P, ctypes.POINTER(_Problem), d, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp], i),
         "joint_cl_step": ([P, ctypes.POINTER(_Problem), vp, ctypes.POINTER(_Chain), ctypes.POINTER(_Draws),
                            ctypes.POINTER(_Opts), ctypes.POINTER(_StepOut), vp], i),
+        "gibbs_cl_step": ([P, ctypes.POINTER(_Problem), vp, ctypes.POINTER(_Chain), d, vp, vp,
+                           ctypes.POINTER(_Opts), ctypes.POINTER(_GibbsOut), vp], i),
         "cr_solve_batched": ([ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(_Problem), i,
                               ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                               ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
@@ -115,7 +122,7 @@ _lib = _load()
 
 EXPORTED = ("crsht_plan_create", "crsht_plan_destroy", "crsht_strerror", "crsht_plan_info", "crsht_pixel_coords",
             "sht_synth", "sht_synth_adjoint", "sht_analysis", "cr_precond", "cr_rhs", "cr_apply", "cr_solve",
-            "cr_lnpi", "joint_cl_step", "cr_solve_batched", "sht_synth_grad", "cr_grad_chi2", "cr_grad_lnpi",
+            "cr_lnpi", "joint_cl_step", "gibbs_cl_step", "cr_solve_batched", "sht_synth_grad", "cr_grad_chi2", "cr_grad_lnpi",
             "cr_block_precond_build", "cr_block_precond_apply", "crsht_timing_enable", "crsht_timing_read")
 
 
@@ -395,6 +402,40 @@ def joint_step(plan: Plan, fid: Problem, d: torch.Tensor, chain: Chain, xi: floa
     return StepResult(bool(r.accepted), r.lnA, r.q_new, r.lnpi_new, st(r.mean_stats), st(r.fluct_stats))
 
 
+@dataclass
+class GibbsResult:
+    q_new: float
+    t: float
+    mean_stats: Stats
+    fluct_stats: Stats
+
+
+def gibbs_shape(lmax: int, lmin: int = 2) -> float:
+    """Shape alpha = k/2 - 1 of the inverse-gamma amplitude conditional,
+    k = sum_{l=lmin}^{lmax} (2l + 1) real degrees of freedom."""
+    k = sum(2 * l + 1 for l in range(lmin, lmax + 1))
+    return 0.5 * k - 1.0
+
+
+def gibbs_step(plan: Plan, fid: Problem, d: torch.Tensor, chain: Chain, g: float, w0: torch.Tensor,
+               w1: torch.Tensor, tol: float = 1e-6, maxiter: int = 10000, prec: int = CR_F64,
+               inner_tol: float = 1e-2, max_refine: int = 50, use_graph: bool = True,
+               precond: int = CR_PC_JACOBI) -> GibbsResult:
+    """Standard Gibbs amplitude move (gibbs_cl_step); g ~ Gamma(gibbs_shape(lmax, lmin), 1)."""
+    p = fid._c()
+    c = _Chain(chain.q, chain.lnpi, _ptr(chain.ahat), _ptr(chain.fhat))
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, 8, int(precond), int(use_graph))
+    r = _GibbsOut()
+    _check(_lib.gibbs_cl_step(plan.handle, ctypes.byref(p), _ptr(d), ctypes.byref(c), float(g), _ptr(w0), _ptr(w1),
+                              ctypes.byref(o), ctypes.byref(r), _stream()), "gibbs_cl_step")
+    chain.q, chain.lnpi = c.q, c.lnpi
+
+    def st(s):
+        return Stats(s.status, s.iters, s.refinements, s.rel_resid_true)
+
+    return GibbsResult(r.q_new, r.t, st(r.mean_stats), st(r.fluct_stats))
+
+
 # ---------------------------------------------------------------- gradients
 def synth_grad(plan: Plan, map_grad: torch.Tensor, out: torch.Tensor | None = None, prec: int = CR_F64):
     """w_m Y^T map_grad (torch.autograd convention for the complex m >= 0 leaf)."""
@@ -462,6 +503,6 @@ def nalm(lmax: int, mmax: int | None = None) -> int:
 
 __all__ = ["Plan", "Problem", "Stats", "Chain", "StepResult", "synth", "adjoint", "analysis", "precond", "rhs",
            "block_precond_build", "block_precond_apply", "CR_PC_JACOBI", "CR_PC_BLOCK",
-           "apply", "solve", "solve_batched", "lnpi", "joint_step", "synth_grad", "synth_ad", "SynthFunction", "grad_chi2", "grad_lnpi",
+           "apply", "solve", "solve_batched", "lnpi", "joint_step", "gibbs_step", "gibbs_shape", "GibbsResult", "synth_grad", "synth_ad", "SynthFunction", "grad_chi2", "grad_lnpi",
            "CR_F64", "CR_MIXED", "CrshtError", "strerror", "EXPORTED"]
 _ = math

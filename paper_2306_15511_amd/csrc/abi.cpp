@@ -583,9 +583,13 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
   return CR_OK;
 }
 
+// x0 (device, one column, optional): warm start. The solve then runs on the
+// correction, A delta = b - A x0, to the tolerance tol ||b|| / ||b - A x0||,
+// and s_out = x0 + delta; stats report the correction's iterations and the
+// residual relative to ||b||.
 int solve_core(const crsht_plan* P, const cr_problem* prob, double q, int nrhs, const double* d, const double* w0,
                const double* w1, const double* rhs, double* s_out, const cr_opts* opts, cr_stats* stats,
-               hipStream_t s) {
+               hipStream_t s, const double* x0 = nullptr) {
   if (!opts || !stats || !s_out) return CR_EINVAL;
   if (!(opts->tol > 0.0) || opts->maxiter < 1) return CR_EINVAL;
   if (opts->prec != CR_F64 && opts->prec != CR_MIXED) return CR_EINVAL;
@@ -599,18 +603,54 @@ int solve_core(const crsht_plan* P, const cr_problem* prob, double q, int nrhs, 
     CR_TRY(launch_project(P, nrhs, C2(rhs), P->w.cg_b, s));
   else
     CR_CHECK(assemble_rhs(P, nrhs, prob->ninv, d, w0, w1, P->w.cg_b, s));
+  cr_opts o = *opts;
+  double r0 = 1.0;   // ||b - A x0|| / ||b||
+  const size_t vbytes = (size_t)nrhs * vlen(P) * sizeof(double2);
+  if (x0) {
+    if (nrhs != 1) return CR_EINVAL;
+    std::vector<double> rel0;
+    CR_TRY(launch_project(P, 1, C2(x0), P->w.cg_x, s));
+    CR_CHECK(true_residual(P, 1, prob->ninv, P->w.cg_x, P->w.cg_b, P->w.cg_r, rel0, s));
+    r0 = rel0[0];
+    if (r0 <= opts->tol) {   // the start already meets the tolerance
+      std::vector<int> zi(1, 0), zb(1, 0);
+      fill_stats(1, opts->tol, zi, zi, rel0, zb, stats);
+      CR_TRY(hipMemcpyAsync(s_out, P->w.cg_x, vbytes, hipMemcpyDeviceToDevice, s));
+      CR_TRY(hipStreamSynchronize(s));
+      return CR_OK;
+    }
+    CR_TRY(hipMemcpyAsync(P->w.cg_b, P->w.cg_r, vbytes, hipMemcpyDeviceToDevice, s));
+    o.tol = opts->tol / r0 * (1.0 - 1e-12);   // (so that the rescaled residual meets tol)
+  }
   std::vector<int> iters, refine, broke;
   std::vector<double> rel;
-  if (opts->prec == CR_MIXED) {
-    CR_CHECK(solve_refined(P, nrhs, prob->ninv, opts, iters, refine, rel, broke, s, pc));
+  if (o.prec == CR_MIXED) {
+    CR_CHECK(solve_refined(P, nrhs, prob->ninv, &o, iters, refine, rel, broke, s, pc));
   } else {
-    CR_CHECK(pcg_run(P, nrhs, prob->ninv, P->w.cg_b, opts->tol, opts->maxiter, every, false, true, iters, rel, broke,
-                     s, opts->use_graph != 0, pc));
+    CR_CHECK(pcg_run(P, nrhs, prob->ninv, P->w.cg_b, o.tol, o.maxiter, every, false, true, iters, rel, broke, s,
+                     o.use_graph != 0, pc));
     refine.assign(nrhs, 0);
   }
+  for (double& v : rel) v *= r0;
   fill_stats(nrhs, opts->tol, iters, refine, rel, broke, stats);
-  CR_TRY(hipMemcpyAsync(s_out, P->w.cg_x, (size_t)nrhs * vlen(P) * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  if (x0)
+    CR_TRY(launch_alm_axpby(vlen(P), 1.0, C2(x0), 1.0, P->w.cg_x, C2(s_out), s));
+  else
+    CR_TRY(hipMemcpyAsync(s_out, P->w.cg_x, vbytes, hipMemcpyDeviceToDevice, s));
   CR_TRY(hipStreamSynchronize(s));
+  return CR_OK;
+}
+
+// t = a^T S^-1 a (real-field product, the problem's current S^-1) into host *t
+int quad_sinv(const crsht_plan* P, const double2* a, double* t, hipStream_t s) {
+  const int npart = P->w.npart;
+  const int nba = std::min<int64_t>(npart, (P->g.nalm + 255) / 256);
+  double* pa = P->w.partial;
+  CR_TRY(hipMemsetAsync(pa, 0, 3 * (size_t)npart * sizeof(double), s));
+  CR_TRY(launch_alm_wquad(P, P->w.sinv, a, pa, nba, s));
+  CR_TRY(launch_sum_rows(P, 1, nba, s));
+  CR_CHECK(read_scalars(P, 1, s));
+  *t = P->w.host_scal[S_AUX0];
   return CR_OK;
 }
 
@@ -892,9 +932,9 @@ extern "C" int joint_cl_step(const crsht_plan* P, const cr_problem* fid, const d
   std::memset(out, 0, sizeof(*out));
   const double qn = state->q * std::exp(dr->sigma_lnq * dr->xi);
   out->q_new = qn;
-  // 1) mean field at q'
+  // 1) mean field at q', warm-started from the mean field at q
   double* ahat_n = reinterpret_cast<double*>(P->w.alm_c);
-  CR_CHECK(solve_core(P, fid, qn, 1, d, nullptr, nullptr, nullptr, ahat_n, opts, &out->mean_stats, s));
+  CR_CHECK(solve_core(P, fid, qn, 1, d, nullptr, nullptr, nullptr, ahat_n, opts, &out->mean_stats, s, state->ahat));
   // 2) rescaled fluctuation sqrt(q'/q) f
   const int64_t na = P->g.nalm;
   CR_TRY(launch_alm_axpby(na, std::sqrt(qn / state->q), C2(state->fhat), 0.0, nullptr, P->w.alm_d, s));
@@ -912,6 +952,39 @@ extern "C" int joint_cl_step(const crsht_plan* P, const cr_problem* fid, const d
   CR_CHECK(lnpi_terms(P, fid->ninv, d, P->w.alm_c, C2(state->fhat), t, s));
   state->q = qn;
   state->lnpi = -0.5 * (t[0] + t[1] + t[2]);
+  CR_TRY(hipStreamSynchronize(s));
+  return CR_OK;
+}
+
+extern "C" int gibbs_cl_step(const crsht_plan* P, const cr_problem* fid, const double* d, cr_chain* state, double g,
+                             const double* w0, const double* w1, const cr_opts* opts, cr_gibbs_out* out,
+                             void* stream) {
+  CR_CHECK(check_plan(P, 1));
+  if (P->ncomp != 1) return CR_ENOTSUP;
+  if (!fid || !d || !state || !opts || !out || !state->ahat || !state->fhat || (!w0 && !w1)) return CR_EINVAL;
+  if (!(g > 0.0) || !std::isfinite(g) || !(state->q > 0.0)) return CR_EINVAL;
+  hipStream_t s = S(stream);
+  std::memset(out, 0, sizeof(*out));
+  const int64_t na = P->g.nalm;
+  // 1) the current sky s = ahat + fhat and t = s^T S_fid^-1 s
+  CR_TRY(launch_alm_axpby(na, 1.0, C2(state->ahat), 1.0, C2(state->fhat), P->w.alm_d, s));
+  CR_CHECK(set_problem(P, fid, 1.0, s));
+  double t = 0.0;
+  CR_CHECK(quad_sinv(P, P->w.alm_d, &t, s));
+  if (!(t > 0.0) || !std::isfinite(t)) return CR_EINVAL;
+  // 2) q | s: inverse gamma (shape k/2 - 1, scale t/2), q' = (t/2) / g
+  const double qn = 0.5 * t / g;
+  out->t = t;
+  out->q_new = qn;
+  // 3) s | q': mean field (warm-started from the one at q) and a fresh fluctuation
+  CR_CHECK(solve_core(P, fid, qn, 1, d, nullptr, nullptr, nullptr, reinterpret_cast<double*>(P->w.alm_c), opts,
+                      &out->mean_stats, s, state->ahat));
+  CR_CHECK(solve_core(P, fid, qn, 1, nullptr, w0, w1, nullptr, state->fhat, opts, &out->fluct_stats, s));
+  CR_TRY(hipMemcpyAsync(state->ahat, P->w.alm_c, na * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  double tt[3];
+  CR_CHECK(lnpi_terms(P, fid->ninv, d, P->w.alm_c, C2(state->fhat), tt, s));
+  state->q = qn;
+  state->lnpi = -0.5 * (tt[0] + tt[1] + tt[2]);
   CR_TRY(hipStreamSynchronize(s));
   return CR_OK;
 }
