@@ -47,8 +47,8 @@ HBM_PEAK_GBS = 8000.0
 # 16-column temperature workload and while the kernel's source file hashes to
 # `src`.
 TRAFFIC = {
-    "k_adj_mfma": {"bytes": 959900960, "src": "5edbc0e441375b52"},
-    "k_synth_mfma": {"bytes": 1325138545, "src": "5edbc0e441375b52"},
+    "k_adj_mfma": {"bytes": 959896629, "src": "3c89991f0fac5560"},
+    "k_synth_mfma": {"bytes": 1324395064, "src": "3c89991f0fac5560"},
     "k_ring<RING_FUSED>": {"bytes": 4 * 212896371, "src": "664ab76c607be629"},   # one fused pass (4 class launches)
     "k_legendre_synth_mfma": {"bytes": 679984546, "src": "941a101a7a3fe1b5"},    # one launch of 8 columns
     "k_legendre_adj_mfma": {"bytes": 2 * 606666377, "src": "941a101a7a3fe1b5"},  # one transform (2 launches)
