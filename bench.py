@@ -211,12 +211,13 @@ def bench_batched(args):
 
 
 def bench_chains(args):
-    """Joint (C_l amplitude, sky) moves against standard Gibbs moves on the
-    headline sky (Nside 512, lmax 1535, hit-pattern noise, band mask, FWHM
-    10'): --chains chains advanced --steps moves each by both samplers (mixed
-    precision, per-m block preconditioner built once, warm-started mean
-    fields); one JSON line with moves/s of the joint sampler as `value` and
-    both samplers' acceptance, ln q autocorrelation time and iterations."""
+    """Joint (C_l amplitude, sky) moves against standard Gibbs moves and HMC
+    moves of ln q on the headline sky (Nside 512, lmax 1535, hit-pattern
+    noise, band mask, FWHM 10'): --chains chains advanced --steps moves each
+    by the three samplers (mixed precision, per-m block preconditioner built
+    once, warm-started mean fields); one JSON line with moves/s of the joint
+    sampler as `value` and every sampler's acceptance, ln q autocorrelation
+    time, moves per autocorrelation time per second and iterations."""
     import torch
     from paper_2306_15511_amd import chains, crsht
     import crinputs as ci
@@ -249,17 +250,38 @@ def bench_chains(args):
         dt = time.perf_counter() - t0
         out[kind] = dict(run.summary(), moves_per_s=args.chains * args.steps / dt, s=dt,
                          fluct_iters=float(run.fluct_iters.mean()))
+    # HMC on theta = ln q (one bin over every kept l): step from the target's
+    # curvature at the start (half its width), trajectories of three steps
+    edges = [2, lmax + 1]
+    rng = np.random.default_rng([11, 0])
+    ch = [chains.init_bin_chain(plan, fid, d, edges, [0.0], torch.from_numpy(chains.white_alm(rng, lmax)).to(dev),
+                                torch.from_numpy(rng.standard_normal(plan.npix)).to(dev), **kw)
+          for _ in range(args.chains)]
+    sig = float(chains.curvature_scale(plan, fid, d, ch[0], **kw)[0])
+    eps, nleap = 0.5 * sig, 3
+    chains.run_hmc(plan, fid, d, ch, args.warmup, eps, nleap, seed=1, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run = chains.run_hmc(plan, fid, d, ch, args.steps, eps, nleap, seed=2, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["hmc"] = dict(run.summary(), moves_per_s=args.chains * args.steps / dt, s=dt, eps=eps, nleap=nleap,
+                      width_lnq=sig, fluct_iters=float(run.fluct_iters.mean()))
+    for kind in out:
+        it = out[kind]["iat_theta"] if kind == "hmc" else out[kind]["iat_lnq"]
+        out[kind]["eff_moves_per_s"] = out[kind]["moves_per_s"] / it
     res = {
         "metric": "joint C_l-amplitude / sky moves/s (Nside 512, lmax 1535)",
         "value": out["joint"]["moves_per_s"], "unit": "moves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": out["joint"]["s"] / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3+f64" if args.prec == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": "%d chains, joint moves (sigma ln q 0.02) and standard Gibbs moves, T-only, Nside %d, "
+        "config": {"workload": "%d chains, joint moves (sigma ln q 0.02), standard Gibbs moves and HMC moves of ln q, "
+                               "T-only, Nside %d, "
                                "lmax %d, hit-pattern noise, |b|<20deg mask, FWHM 10', true residual %g, per-m block "
                                "preconditioner, warm-started mean fields" % (args.chains, nside, lmax, args.tol),
                    "chains": args.chains},
-        "joint": out["joint"], "gibbs": out["gibbs"],
+        "joint": out["joint"], "gibbs": out["gibbs"], "hmc": out["hmc"],
     }
     print(json.dumps(res))
 

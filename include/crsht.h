@@ -316,6 +316,68 @@ typedef struct {
 int gibbs_cl_step(const crsht_plan *plan, const cr_problem *fid, const double *d, cr_chain *state, double g,
                   const double *w0, const double *w1, const cr_opts *opts, cr_gibbs_out *out, void *stream);
 
+/* ln pi (Sect. 2.2.2, definition of pi(theta)) and its gradient in per-bin
+ * log-amplitudes theta_k (C_l -> C_l^fid exp(theta_k) for edges[k] <= l <
+ * edges[k+1]) at a fixed whitened fluctuation: the fluctuation f0, given at
+ * theta0, is carried to theta as f = exp((theta - theta0)/2) f0 per bin (the
+ * rescaling of the joint move), so that
+ *   d ln pi / d theta_k = 1/2 a^T S^-1_k a - 1/2 f^T B Y^T N^-1 Y B f_k
+ * with a the mean field at theta (it minimises chi^2 + a^T S^-1 a, so only the
+ * explicit S^-1 is differentiated; no adjoint solve). The mean-field solve
+ * starts from a0 (device [nalm], may be NULL) and its result goes to ahat
+ * (device [nalm], may be NULL). theta0, theta: host [nbins]; f0: device
+ * [nalm]; edges: host, nbins + 1 strictly increasing values in [0, lmax + 1];
+ * grad: host [nbins]; *lnpi host; stats: host, one entry (the mean-field
+ * solve). Temperature plans only. Blocks until done. */
+int cr_lnpi_grad_fixed(const crsht_plan *plan, const cr_problem *fid, const double *d, int nbins, const int *edges,
+                       const double *theta0, const double *theta, const double *f0, const double *a0,
+                       const cr_opts *opts, double *lnpi, double *grad, double *ahat, cr_stats *stats, void *stream);
+
+/* State of a chain over per-bin log-amplitudes (host struct, device vectors). */
+typedef struct {
+  int nbins;
+  const int *edges;    /* host, nbins + 1 bin edges in l */
+  double *theta;       /* host [nbins]: log-amplitudes, C_l = C_l^fid exp(theta_k) */
+  double lnpi;         /* ln pi of the current state */
+  double *ahat;        /* device [nalm]: mean field */
+  double *fhat;        /* device [nalm]: fluctuation */
+} cr_bin_chain;
+
+/* Randomness and tuning of one HMC move, drawn by the caller. */
+typedef struct {
+  const double *p0;    /* host [nbins]: momentum, standard normal */
+  double u;            /* uniform in (0,1): accept iff ln u < -(H_end - H_start) */
+  const double *w0;    /* device [nalm]: fresh w0 for the fluctuation after the move */
+  const double *w1;    /* device [npix]: fresh w1 */
+  double eps;          /* leapfrog step in theta (> 0) */
+  int nleap;           /* leapfrog steps (>= 1) */
+} cr_hmc_draws;
+
+typedef struct {
+  int accepted;
+  int status;          /* CR_OK, or the status of a mean-field solve that did not converge */
+  double dH;           /* H_end - H_start */
+  double lnpi_new;     /* ln pi at the end of the trajectory (rescaled fluctuation) */
+  int solves;          /* mean-field solves of the trajectory (nleap + 1) */
+  int iters;           /* their iterations, summed */
+  cr_stats fluct_stats;/* fresh fluctuation solve */
+} cr_hmc_out;
+
+/* One Hamiltonian Monte Carlo move of the per-bin log-amplitudes (the
+ * derivative-based sampler the paper's discussion points to, Sect. 4; the
+ * same target as the joint move: ln pi at a fixed whitened fluctuation, with
+ * a uniform prior in the amplitudes exp(theta_k), i.e. the potential
+ * U = -ln pi - sum_k theta_k and unit masses). nleap leapfrog steps of size
+ * eps from momentum p0, each with one warm-started mean-field solve and the
+ * gradient of cr_lnpi_grad_fixed; accept iff ln u < -(H_end - H_start). Then,
+ * accepted or not, a fresh fluctuation from w0, w1 at the amplitudes the move
+ * ends on (a draw of the whitened fluctuation given the amplitudes, which
+ * leaves the joint target invariant by itself) and ln pi of the new state;
+ * *state is updated in place (theta and ahat kept on rejection). `out` host.
+ * Temperature plans only. Blocks until done. */
+int hmc_cl_step(const crsht_plan *plan, const cr_problem *fid, const double *d, cr_bin_chain *state,
+                const cr_hmc_draws *draws, const cr_opts *opts, cr_hmc_out *out, void *stream);
+
 /* Gradient of the synthesis for reverse-mode differentiation of a real
  * function L of the map: alm_grad = w_m Y^T map_grad with w_0 = 1 (Im of m = 0
  * set to 0) and w_{m>0} = 2, i.e. dL/dRe a_lm + i dL/dIm a_lm for a complex

@@ -18,12 +18,19 @@ The standard two-block Gibbs move (Sect. 2.2.1; the baseline the joint move
 is compared with) for the same one-parameter family is gibbs_step: q given
 the current sky from its inverse-gamma conditional, then the sky given q.
 
+hmc_step is the derivative-based sampler Sect. 4 points to, on per-bin
+log-amplitudes: the joint move's target (ln pi at a fixed whitened
+fluctuation) explored by Hamiltonian trajectories, with the gradient of
+lnpi_grad_fixed.
+
 Pins (tests/test_oracle_joint.py): the acceptance identity against the joint
 posterior of the dense model, the misread middle term breaking it, accept and
 reject paths; the Gibbs conditional's draws against a numerical integral of
 q^(-k/2) exp(-t/(2q)); both samplers' chains against the exact marginal
 posterior p(q | d) of a tiny masked problem (Gaussian likelihood of the
-observed pixels, brute force on a grid of q).
+observed pixels, brute force on a grid of q); the fixed-fluctuation gradient
+against central differences of ln pi; the leapfrog energy error falling as
+eps^2; an HMC chain against the same exact posterior.
 """
 from __future__ import annotations
 
@@ -124,3 +131,86 @@ def gibbs_step(fid: Problem, d, state: ChainState, g: float, w0_new, w1_new, tol
     ahat, _ = pcg(op, op.rhs(d=d), tol, maxiter)
     fhat, _ = pcg(op, op.rhs(w0=w0_new, w1=w1_new), tol, maxiter)
     return ChainState(q_new, ahat, fhat, lnpi(op, d, ahat, fhat)), GibbsResult(q_new, t)
+
+
+# ------------------------------------------------ HMC over bin log-amplitudes
+def bin_factors(lmax: int, edges, x, c: float = 1.0) -> np.ndarray:
+    """Per-l factor exp(c x_k) on [edges[k], edges[k+1]), 1 elsewhere."""
+    f = np.ones(lmax + 1)
+    for k in range(len(edges) - 1):
+        f[edges[k]:edges[k + 1]] = math.exp(c * x[k])
+    return f
+
+
+def bin_problem(fid: Problem, edges, theta) -> Problem:
+    return Problem(fid.nside, fid.lmax, fid.cl * bin_factors(fid.lmax, edges, theta), fid.bl, fid.ninv, fid.lmin)
+
+
+def lnpi_grad_fixed(fid: Problem, d, edges, theta0, theta, f0, tol: float, maxiter: int = 20000):
+    """ln pi at the log-amplitudes theta with the fluctuation f0 (given at
+    theta0) carried along as exp((theta - theta0)/2) f0 per bin, and its
+    gradient: d ln pi/d theta_k = 1/2 a_k^T S^-1 a_k - 1/2 f_k^T M f, with
+    M = B Y^T N^-1 Y B (the mean field a is the minimiser of chi^2 + a^T S^-1 a,
+    so only the explicit S^-1 is differentiated). Returns (ln pi, grad, a)."""
+    op = CROperator(bin_problem(fid, edges, theta))
+    ahat, _ = pcg(op, op.rhs(d=d), tol, maxiter)
+    ls = op.ls
+    f = f0 * bin_factors(fid.lmax, edges, np.asarray(theta) - np.asarray(theta0), 0.5)[ls]
+    lp = lnpi(op, d, ahat, f)
+    Mf = op.apply_data_term(f)
+    grad = np.zeros(len(edges) - 1)
+    for k in range(len(edges) - 1):
+        sel = (ls >= edges[k]) & (ls < edges[k + 1])
+        ak, fk = ahat * sel, f * sel
+        grad[k] = 0.5 * op.dot(ak, op.sinv * ak) - 0.5 * op.dot(fk, Mf)
+    return lp, grad, ahat
+
+
+@dataclass
+class BinState:
+    theta: np.ndarray
+    ahat: np.ndarray
+    fhat: np.ndarray
+    lnpi: float
+
+
+def init_bin_state(fid: Problem, d, edges, theta, w0, w1, tol: float, maxiter: int = 20000) -> BinState:
+    op = CROperator(bin_problem(fid, edges, theta))
+    ahat, _ = pcg(op, op.rhs(d=d), tol, maxiter)
+    fhat, _ = pcg(op, op.rhs(w0=w0, w1=w1), tol, maxiter)
+    return BinState(np.array(theta, dtype=np.float64), ahat, fhat, lnpi(op, d, ahat, fhat))
+
+
+@dataclass
+class HmcResult:
+    accepted: bool
+    dH: float
+    lnpi_new: float
+
+
+def hmc_step(fid: Problem, d, edges, state: BinState, p0, u: float, w0_new, w1_new, eps: float, nleap: int,
+             tol: float, maxiter: int = 20000):
+    """Hamiltonian Monte Carlo move of the bin log-amplitudes at a fixed
+    whitened fluctuation: potential U = -ln pi - sum theta (uniform prior in
+    the amplitudes exp(theta_k)), unit masses, nleap leapfrog steps of size
+    eps from momentum p0; accept iff ln u < -(H_end - H_start); then, accepted
+    or not, a fresh fluctuation at the amplitudes the move ends on (a draw of
+    the whitened fluctuation given the amplitudes, which leaves the joint
+    target invariant by itself)."""
+    th0 = np.array(state.theta, dtype=np.float64)
+    p = np.array(p0, dtype=np.float64)
+    lp, g, ahat = lnpi_grad_fixed(fid, d, edges, th0, th0, state.fhat, tol, maxiter)
+    H0 = -lp - th0.sum() + 0.5 * float(p @ p)
+    p = p + 0.5 * eps * (g + 1.0)
+    th = th0.copy()
+    for i in range(nleap):
+        th = th + eps * p
+        lp, g, ahat = lnpi_grad_fixed(fid, d, edges, th0, th, state.fhat, tol, maxiter)
+        p = p + (1.0 if i + 1 < nleap else 0.5) * eps * (g + 1.0)
+    H1 = -lp - th.sum() + 0.5 * float(p @ p)
+    dH = H1 - H0
+    accepted = bool(np.isfinite(dH) and math.log(u) < -dH)
+    th_end, a_end = (th, ahat) if accepted else (th0, state.ahat)
+    op = CROperator(bin_problem(fid, edges, th_end))
+    fhat, _ = pcg(op, op.rhs(w0=w0_new, w1=w1_new), tol, maxiter)
+    return BinState(th_end, a_end, fhat, lnpi(op, d, a_end, fhat)), HmcResult(accepted, dH, lp)

@@ -1,8 +1,10 @@
 """Chains of the joint amplitude / sky sampler and of the standard Gibbs
 sampler on one GPU (paper Sect. 2.2.1 and 2.2.2, for the one-parameter family
-C_l(q) = q C_l^fid with a uniform prior in q).
+C_l(q) = q C_l^fid with a uniform prior in q), and of the Hamiltonian sampler
+of per-bin log-amplitudes (C_l = C_l^fid exp(theta_k) on bins in l, uniform
+prior in the amplitudes; the derivative-based sampler of Sect. 4).
 
-Every move is one library call (joint_cl_step or gibbs_cl_step): the solves,
+Every move is one library call (joint_cl_step, gibbs_cl_step or hmc_cl_step): the solves,
 ln pi and the accept test run on the GPU; this module only orders the moves
 of many chains, draws their random numbers on the host (numpy, so a run is
 reproducible from its seed) and reduces the traces to the diagnostics of the
@@ -141,5 +143,103 @@ def run_chains(plan: crsht.Plan, fid: crsht.Problem, d: torch.Tensor, chains: li
     return ChainRun(kind, q, acc, mi, fi, acc.mean(axis=1), iat)
 
 
+def bin_scaled(fid: crsht.Problem, edges, theta) -> crsht.Problem:
+    """fid with C_l exp(theta_k) on [edges[k], edges[k+1])."""
+    f = np.ones(len(fid.cl))
+    for k in range(len(edges) - 1):
+        f[edges[k]:edges[k + 1]] = math.exp(theta[k])
+    return crsht.Problem(np.asarray(fid.cl) * f, fid.bl, fid.ninv, fid.lmin)
+
+
+def init_bin_chain(plan: crsht.Plan, fid: crsht.Problem, d: torch.Tensor, edges, theta, w0: torch.Tensor,
+                   w1: torch.Tensor, **solve_kw) -> crsht.BinChain:
+    """State at the log-amplitudes theta: mean field, fluctuation, ln pi."""
+    p = bin_scaled(fid, edges, theta)
+    ahat, _ = crsht.solve(plan, p, d, **solve_kw)
+    fhat, _ = crsht.solve(plan, p, None, w0, w1, **solve_kw)
+    ahat, fhat = ahat[0].clone(), fhat[0].clone()
+    return crsht.BinChain(np.asarray(edges, dtype=np.int32), np.asarray(theta, dtype=np.float64).copy(),
+                          crsht.lnpi(plan, p, 1.0, d, ahat, fhat), ahat, fhat)
+
+
+def curvature_scale(plan: crsht.Plan, fid: crsht.Problem, d: torch.Tensor, chain: crsht.BinChain, h: float = 1e-3,
+                    **solve_kw) -> np.ndarray:
+    """Width of the HMC target along each bin, 1/sqrt(-d^2 ln pi/d theta_k^2),
+    from a forward difference of the fixed-fluctuation gradient at the chain's
+    state (nbins + 1 mean-field solves); a guide for the leapfrog step."""
+    th = np.asarray(chain.theta, dtype=np.float64)
+    g0 = crsht.lnpi_grad_fixed(plan, fid, d, chain.edges, th, th, chain.fhat, a0=chain.ahat, **solve_kw)[0]
+    out = np.zeros(th.size)
+    for k in range(th.size):
+        t1 = th.copy()
+        t1[k] += h
+        g1 = crsht.lnpi_grad_fixed(plan, fid, d, chain.edges, th, t1, chain.fhat, a0=chain.ahat, **solve_kw)[0]
+        c = -(g1[k] - g0[k]) / h
+        out[k] = 1.0 / math.sqrt(c) if c > 0 else float("inf")
+    return out
+
+
+@dataclass
+class HmcRun:
+    theta: np.ndarray        # [nchains, nsteps + 1, nbins] after each move (start first)
+    accepted: np.ndarray     # [nchains, nsteps]
+    dH: np.ndarray           # [nchains, nsteps] energy error of each trajectory
+    solves: np.ndarray       # [nchains, nsteps] mean-field solves of each trajectory
+    iters: np.ndarray        # [nchains, nsteps] their iterations, summed
+    fluct_iters: np.ndarray  # [nchains, nsteps]
+    acceptance: np.ndarray   # [nchains]
+    iat: np.ndarray          # [nchains, nbins] integrated autocorrelation time of theta_k (after burn-in)
+
+    def summary(self) -> dict:
+        return {"kind": "hmc", "chains": int(self.theta.shape[0]), "steps": int(self.theta.shape[1] - 1),
+                "bins": int(self.theta.shape[2]), "acceptance": float(self.acceptance.mean()),
+                "iat_theta": float(self.iat.mean()), "mean_iters_per_solve":
+                float(self.iters.sum() / max(self.solves.sum(), 1)), "abs_dH": float(np.abs(self.dH).mean())}
+
+
+def default_hmc_draws(nbins: int, lmax: int, npix: int, seed: int):
+    """Random numbers of each HMC move in a fixed order (numpy Generator
+    seeded per chain): momentum p0 [nbins], u, w0, w1."""
+    rngs = {}
+
+    def draw(chain: int, step: int) -> dict:
+        rng = rngs.setdefault(chain, np.random.default_rng([seed, chain, 1]))
+        return {"p0": rng.standard_normal(nbins), "u": float(rng.uniform()), "w0": white_alm(rng, lmax),
+                "w1": rng.standard_normal(npix)}
+
+    return draw
+
+
+def run_hmc(plan: crsht.Plan, fid: crsht.Problem, d: torch.Tensor, chains: list, nsteps: int, eps: float,
+            nleap: int, seed: int = 0, burn: int = 0, draw: Optional[Callable[[int, int], dict]] = None,
+            **solve_kw) -> HmcRun:
+    """Advance every chain (crsht.BinChain, updated in place) by nsteps HMC
+    moves of nleap leapfrog steps of size eps."""
+    n = len(chains)
+    nb = len(chains[0].edges) - 1
+    if draw is None:
+        draw = default_hmc_draws(nb, plan.lmax, plan.npix, seed)
+    dev = d.device
+    th = np.zeros((n, nsteps + 1, nb))
+    acc = np.zeros((n, nsteps), dtype=bool)
+    dh = np.zeros((n, nsteps))
+    sv = np.zeros((n, nsteps), dtype=np.int64)
+    it = np.zeros((n, nsteps), dtype=np.int64)
+    fi = np.zeros((n, nsteps), dtype=np.int64)
+    for c, ch in enumerate(chains):
+        th[c, 0] = ch.theta
+    for s in range(nsteps):
+        for c, ch in enumerate(chains):
+            r = draw(c, s)
+            w0 = torch.from_numpy(np.ascontiguousarray(r["w0"])).to(dev)
+            w1 = torch.from_numpy(np.ascontiguousarray(r["w1"])).to(dev)
+            res = crsht.hmc_step(plan, fid, d, ch, r["p0"], r["u"], w0, w1, eps, nleap, **solve_kw)
+            acc[c, s], dh[c, s], sv[c, s], it[c, s] = res.accepted, res.dH, res.solves, res.iters
+            fi[c, s] = res.fluct_stats.iters
+            th[c, s + 1] = ch.theta
+    iat = np.array([[integrated_autocorr_time(th[c, 1 + burn:, k]) for k in range(nb)] for c in range(n)])
+    return HmcRun(th, acc, dh, sv, it, fi, acc.mean(axis=1), iat)
+
+
 __all__ = ["white_alm", "integrated_autocorr_time", "scaled", "init_chain", "ChainRun", "default_draws",
-           "run_chains"]
+           "run_chains", "bin_scaled", "init_bin_chain", "curvature_scale", "HmcRun", "default_hmc_draws", "run_hmc"]

@@ -68,6 +68,23 @@ class _StepOut(ctypes.Structure):
                 ("lnpi_new", ctypes.c_double), ("mean_stats", _Stats), ("fluct_stats", _Stats)]
 
 
+class _BinChain(ctypes.Structure):
+    _fields_ = [("nbins", ctypes.c_int), ("edges", ctypes.POINTER(ctypes.c_int)),
+                ("theta", ctypes.POINTER(ctypes.c_double)), ("lnpi", ctypes.c_double), ("ahat", ctypes.c_void_p),
+                ("fhat", ctypes.c_void_p)]
+
+
+class _HmcDraws(ctypes.Structure):
+    _fields_ = [("p0", ctypes.POINTER(ctypes.c_double)), ("u", ctypes.c_double), ("w0", ctypes.c_void_p),
+                ("w1", ctypes.c_void_p), ("eps", ctypes.c_double), ("nleap", ctypes.c_int)]
+
+
+class _HmcOut(ctypes.Structure):
+    _fields_ = [("accepted", ctypes.c_int), ("status", ctypes.c_int), ("dH", ctypes.c_double),
+                ("lnpi_new", ctypes.c_double), ("solves", ctypes.c_int), ("iters", ctypes.c_int),
+                ("fluct_stats", _Stats)]
+
+
 class _GibbsOut(ctypes.Structure):
     _fields_ = [("q_new", ctypes.c_double), ("t", ctypes.c_double), ("mean_stats", _Stats),
                 ("fluct_stats", _Stats)]
@@ -97,6 +114,12 @@ def _load():
         "cr_lnpi": ([P, ctypes.POINTER(_Problem), d, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp], i),
         "joint_cl_step": ([P, ctypes.POINTER(_Problem), vp, ctypes.POINTER(_Chain), ctypes.POINTER(_Draws),
                            ctypes.POINTER(_Opts), ctypes.POINTER(_StepOut), vp], i),
+        "cr_lnpi_grad_fixed": ([P, ctypes.POINTER(_Problem), vp, i, ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), vp, vp,
+                                ctypes.POINTER(_Opts), ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double), vp, ctypes.POINTER(_Stats), vp], i),
+        "hmc_cl_step": ([P, ctypes.POINTER(_Problem), vp, ctypes.POINTER(_BinChain), ctypes.POINTER(_HmcDraws),
+                         ctypes.POINTER(_Opts), ctypes.POINTER(_HmcOut), vp], i),
         "gibbs_cl_step": ([P, ctypes.POINTER(_Problem), vp, ctypes.POINTER(_Chain), d, vp, vp,
                            ctypes.POINTER(_Opts), ctypes.POINTER(_GibbsOut), vp], i),
         "cr_solve_batched": ([ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(_Problem), i,
@@ -122,7 +145,8 @@ _lib = _load()
 
 EXPORTED = ("crsht_plan_create", "crsht_plan_destroy", "crsht_strerror", "crsht_plan_info", "crsht_pixel_coords",
             "sht_synth", "sht_synth_adjoint", "sht_analysis", "cr_precond", "cr_rhs", "cr_apply", "cr_solve",
-            "cr_lnpi", "joint_cl_step", "gibbs_cl_step", "cr_solve_batched", "sht_synth_grad", "cr_grad_chi2", "cr_grad_lnpi",
+            "cr_lnpi", "joint_cl_step", "gibbs_cl_step", "hmc_cl_step", "cr_lnpi_grad_fixed",
+            "cr_solve_batched", "sht_synth_grad", "cr_grad_chi2", "cr_grad_lnpi",
             "cr_block_precond_build", "cr_block_precond_apply", "crsht_timing_enable", "crsht_timing_read")
 
 
@@ -436,6 +460,86 @@ def gibbs_step(plan: Plan, fid: Problem, d: torch.Tensor, chain: Chain, g: float
     return GibbsResult(r.q_new, r.t, st(r.mean_stats), st(r.fluct_stats))
 
 
+@dataclass
+class BinChain:
+    """Chain over per-bin log-amplitudes theta (C_l = C_l^fid exp(theta_k) on
+    [edges[k], edges[k+1]))."""
+    edges: object            # host int array, nbins + 1
+    theta: object            # host float64 array, nbins (updated in place)
+    lnpi: float
+    ahat: torch.Tensor
+    fhat: torch.Tensor
+
+
+@dataclass
+class HmcResult:
+    accepted: bool
+    status: int
+    dH: float
+    lnpi_new: float
+    solves: int
+    iters: int
+    fluct_stats: Stats
+
+
+def _i32(a):
+    import numpy as np
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    import numpy as np
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def lnpi_grad_fixed(plan: Plan, fid: Problem, d: torch.Tensor, edges, theta0, theta, f0: torch.Tensor,
+                    a0: torch.Tensor | None = None, tol: float = 1e-10, maxiter: int = 20000, prec: int = CR_F64,
+                    inner_tol: float = 1e-2, max_refine: int = 50, check_every: int = 8, use_graph: bool = True,
+                    precond: int = CR_PC_JACOBI):
+    """(d ln pi / d theta [nbins] numpy, ln pi, mean field [nalm], Stats) at a
+    fixed whitened fluctuation (cr_lnpi_grad_fixed)."""
+    import numpy as np
+    e, t0, t1 = _i32(edges), _f64(theta0), _f64(theta)
+    nb = e.size - 1
+    g = np.zeros(nb)
+    v = ctypes.c_double()
+    st = (_Stats * 1)()
+    ahat = torch.empty(plan.alm_shape(1)[1:], dtype=torch.complex128, device=d.device)
+    p = fid._c()
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every, int(precond), int(use_graph))
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(_lib.cr_lnpi_grad_fixed(plan.handle, ctypes.byref(p), _ptr(d), nb,
+                                   e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), t0.ctypes.data_as(dp),
+                                   t1.ctypes.data_as(dp), _ptr(f0), _ptr(a0), ctypes.byref(o), ctypes.byref(v),
+                                   g.ctypes.data_as(dp), _ptr(ahat), st, _stream()), "cr_lnpi_grad_fixed")
+    return g, v.value, ahat, Stats(st[0].status, st[0].iters, st[0].refinements, st[0].rel_resid_true)
+
+
+def hmc_step(plan: Plan, fid: Problem, d: torch.Tensor, chain: BinChain, p0, u: float, w0: torch.Tensor,
+             w1: torch.Tensor, eps: float, nleap: int, tol: float = 1e-6, maxiter: int = 10000,
+             prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 50, use_graph: bool = True,
+             precond: int = CR_PC_JACOBI) -> HmcResult:
+    """One HMC move of the bin log-amplitudes (hmc_cl_step); chain.theta and
+    chain.lnpi are updated in place."""
+    e = _i32(chain.edges)
+    th = _f64(chain.theta)
+    pp = _f64(p0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    c = _BinChain(e.size - 1, e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), th.ctypes.data_as(dp), chain.lnpi,
+                  _ptr(chain.ahat), _ptr(chain.fhat))
+    dr = _HmcDraws(pp.ctypes.data_as(dp), u, _ptr(w0), _ptr(w1), eps, int(nleap))
+    p = fid._c()
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, 8, int(precond), int(use_graph))
+    r = _HmcOut()
+    _check(_lib.hmc_cl_step(plan.handle, ctypes.byref(p), _ptr(d), ctypes.byref(c), ctypes.byref(dr),
+                            ctypes.byref(o), ctypes.byref(r), _stream()), "hmc_cl_step")
+    chain.theta = th.copy()
+    chain.lnpi = c.lnpi
+    fs = r.fluct_stats
+    return HmcResult(bool(r.accepted), r.status, r.dH, r.lnpi_new, r.solves, r.iters,
+                     Stats(fs.status, fs.iters, fs.refinements, fs.rel_resid_true))
+
+
 # ---------------------------------------------------------------- gradients
 def synth_grad(plan: Plan, map_grad: torch.Tensor, out: torch.Tensor | None = None, prec: int = CR_F64):
     """w_m Y^T map_grad (torch.autograd convention for the complex m >= 0 leaf)."""
@@ -503,6 +607,7 @@ def nalm(lmax: int, mmax: int | None = None) -> int:
 
 __all__ = ["Plan", "Problem", "Stats", "Chain", "StepResult", "synth", "adjoint", "analysis", "precond", "rhs",
            "block_precond_build", "block_precond_apply", "CR_PC_JACOBI", "CR_PC_BLOCK",
-           "apply", "solve", "solve_batched", "lnpi", "joint_step", "gibbs_step", "gibbs_shape", "GibbsResult", "synth_grad", "synth_ad", "SynthFunction", "grad_chi2", "grad_lnpi",
+           "apply", "solve", "solve_batched", "lnpi", "joint_step", "gibbs_step", "gibbs_shape", "GibbsResult",
+           "BinChain", "HmcResult", "lnpi_grad_fixed", "hmc_step", "synth_grad", "synth_ad", "SynthFunction", "grad_chi2", "grad_lnpi",
            "CR_F64", "CR_MIXED", "CrshtError", "strerror", "EXPORTED"]
 _ = math

@@ -956,6 +956,151 @@ extern "C" int joint_cl_step(const crsht_plan* P, const cr_problem* fid, const d
   return CR_OK;
 }
 
+// ---- HMC move of per-bin log-amplitudes at fixed whitened fluctuation
+namespace {
+
+bool valid_bins(const crsht_plan* P, int nbins, const int* edges) {
+  if (nbins < 1 || nbins > P->g.lmax + 1 || !edges) return false;
+  for (int k = 0; k <= nbins; ++k) {
+    if (edges[k] < 0 || edges[k] > P->g.lmax + 1) return false;
+    if (k > 0 && edges[k] <= edges[k - 1]) return false;
+  }
+  return true;
+}
+
+// per-l factor exp(c * x_k) on [edges[k], edges[k+1]), 1 elsewhere
+void bin_factor(int lmax, int nbins, const int* edges, const double* x, double c, std::vector<double>& f) {
+  f.assign(lmax + 1, 1.0);
+  for (int k = 0; k < nbins; ++k)
+    for (int l = edges[k]; l < edges[k + 1]; ++l) f[l] = std::exp(c * x[k]);
+}
+
+// ln pi at the log-amplitudes theta (C_l -> C_l exp(theta_k) per bin) with the
+// fluctuation f0, given at theta0, rescaled by exp((theta - theta0)/2) per bin
+// (the whitened fluctuation S^-1/2 f held fixed), and its gradient in theta:
+//   d ln pi / d theta_k = 1/2 a^T S^-1_k a - 1/2 f^T M f_k,  M = B Y^T N^-1 Y B
+// (the mean field a minimises chi^2 + a^T S^-1 a, so it enters only through
+// the explicit S^-1; f_k changes as f_k / 2). The mean field (warm-started
+// from a0, which may alias w.alm_c) goes to w.alm_c, the rescaled
+// fluctuation to w.alm_d; edges are already in w.bin_edges.
+int lnpi_grad_u(const crsht_plan* P, const cr_problem* fid, const double* d, int nbins, const int* edges,
+                const double* theta0, const double* theta, const double* f0, const double* a0, const cr_opts* opts,
+                double* lnpi, double* grad, cr_stats* st, hipStream_t s) {
+  Workspace const& w = P->w;
+  const int lmax = P->g.lmax;
+  std::vector<double> fac, cl(lmax + 1), dth(nbins), lf;
+  bin_factor(lmax, nbins, edges, theta, 1.0, fac);
+  for (int l = 0; l <= lmax; ++l) cl[l] = fid->cl[l] * fac[l];
+  cr_problem pr = *fid;
+  pr.cl = cl.data();
+  CR_CHECK(solve_core(P, &pr, 1.0, 1, d, nullptr, nullptr, nullptr, reinterpret_cast<double*>(w.alm_c), opts, st, s,
+                      a0));
+  for (int k = 0; k < nbins; ++k) dth[k] = theta[k] - theta0[k];
+  bin_factor(lmax, nbins, edges, dth.data(), 0.5, lf);
+  CR_TRY(hipMemcpyAsync(w.lfac, lf.data(), (size_t)(lmax + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+  CR_TRY(launch_scale_per_l(P, C2(f0), w.lfac, w.alm_d, s));
+  double t[3];
+  CR_CHECK(lnpi_terms(P, fid->ninv, d, w.alm_c, w.alm_d, t, s));   // (synchronises: lf may go)
+  *lnpi = -0.5 * (t[0] + t[1] + t[2]);
+  CR_TRY(launch_scale_alm(P, 1, w.alm_d, w.bk, w.alm_a, s));
+  CR_CHECK(operator_core(P, 1, w.alm_d, w.alm_a, fid->ninv, w.cg_bin, s, false, false));
+  CR_TRY(launch_bin_grad(P, nbins, w.bin_edges, w.alm_c, w.alm_d, w.cg_bin, nullptr, w.bin_grad, s, 1));
+  CR_TRY(hipMemcpyAsync(grad, w.bin_grad, (size_t)nbins * sizeof(double), hipMemcpyDeviceToHost, s));
+  CR_TRY(hipStreamSynchronize(s));
+  return CR_OK;
+}
+
+}  // namespace
+
+extern "C" int cr_lnpi_grad_fixed(const crsht_plan* P, const cr_problem* fid, const double* d, int nbins,
+                                  const int* edges, const double* theta0, const double* theta, const double* f0,
+                                  const double* a0, const cr_opts* opts, double* lnpi, double* grad, double* ahat,
+                                  cr_stats* stats, void* stream) {
+  CR_CHECK(check_plan(P, 1));
+  if (P->ncomp != 1) return CR_ENOTSUP;
+  if (!fid || !d || !theta0 || !theta || !f0 || !opts || !lnpi || !grad || !stats) return CR_EINVAL;
+  if (!valid_bins(P, nbins, edges)) return CR_EINVAL;
+  hipStream_t s = S(stream);
+  CR_TRY(hipMemcpyAsync(P->w.bin_edges, edges, (size_t)(nbins + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  CR_CHECK(lnpi_grad_u(P, fid, d, nbins, edges, theta0, theta, f0, a0, opts, lnpi, grad, stats, s));
+  if (ahat)
+    CR_TRY(hipMemcpyAsync(ahat, P->w.alm_c, (size_t)P->g.nalm * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  CR_TRY(hipStreamSynchronize(s));
+  return CR_OK;
+}
+
+extern "C" int hmc_cl_step(const crsht_plan* P, const cr_problem* fid, const double* d, cr_bin_chain* st,
+                           const cr_hmc_draws* dr, const cr_opts* opts, cr_hmc_out* out, void* stream) {
+  CR_CHECK(check_plan(P, 1));
+  if (P->ncomp != 1) return CR_ENOTSUP;
+  if (!fid || !d || !st || !dr || !opts || !out || !st->theta || !st->ahat || !st->fhat || !dr->p0)
+    return CR_EINVAL;
+  if (!valid_bins(P, st->nbins, st->edges)) return CR_EINVAL;
+  if (!(dr->eps > 0.0) || !std::isfinite(dr->eps) || dr->nleap < 1 || !(dr->u > 0.0 && dr->u < 1.0))
+    return CR_EINVAL;
+  const int nb = st->nbins;
+  hipStream_t s = S(stream);
+  Workspace const& w = P->w;
+  std::memset(out, 0, sizeof(*out));
+  CR_TRY(hipMemcpyAsync(w.bin_edges, st->edges, (size_t)(nb + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  // potential U = -ln pi - sum theta (uniform prior in the amplitudes exp(theta_k)), dU = -grad - 1
+  std::vector<double> th0(st->theta, st->theta + nb), th(th0), p(dr->p0, dr->p0 + nb), g(nb);
+  double lp = 0.0;
+  cr_stats cs;
+  auto eval = [&](const double* a0) -> int {
+    CR_CHECK(lnpi_grad_u(P, fid, d, nb, st->edges, th0.data(), th.data(), st->fhat, a0, opts, &lp, g.data(), &cs,
+                         s));
+    out->iters += cs.iters;
+    out->solves += 1;
+    if (cs.status != CR_OK) out->status = cs.status;
+    return CR_OK;
+  };
+  auto U = [&]() {
+    double u = -lp;
+    for (int k = 0; k < nb; ++k) u -= th[k];
+    return u;
+  };
+  auto kin = [&]() {
+    double k2 = 0.0;
+    for (int k = 0; k < nb; ++k) k2 += 0.5 * p[k] * p[k];
+    return k2;
+  };
+  CR_CHECK(eval(st->ahat));
+  const double H0 = U() + kin();
+  // leapfrog: half step in p, nleap steps in theta, full steps in p between, half step at the end
+  for (int k = 0; k < nb; ++k) p[k] += 0.5 * dr->eps * (g[k] + 1.0);
+  for (int i = 0; i < dr->nleap; ++i) {
+    for (int k = 0; k < nb; ++k) th[k] += dr->eps * p[k];
+    CR_CHECK(eval(reinterpret_cast<const double*>(w.alm_c)));
+    const double c = (i + 1 < dr->nleap) ? 1.0 : 0.5;
+    for (int k = 0; k < nb; ++k) p[k] += c * dr->eps * (g[k] + 1.0);
+  }
+  const double H1 = U() + kin();
+  out->dH = H1 - H0;
+  out->lnpi_new = lp;
+  out->accepted = (std::isfinite(out->dH) && std::log(dr->u) < -out->dH) ? 1 : 0;
+  // then a fresh fluctuation at the amplitudes the move ends on (accepted or
+  // not: a draw of the fluctuation given the amplitudes leaves the joint
+  // target invariant on its own), and ln pi of the new state
+  if (!dr->w0 && !dr->w1) return CR_EINVAL;
+  const std::vector<double>& te = out->accepted ? th : th0;
+  std::vector<double> fac, cl(P->g.lmax + 1);
+  bin_factor(P->g.lmax, nb, st->edges, te.data(), 1.0, fac);
+  for (int l = 0; l <= P->g.lmax; ++l) cl[l] = fid->cl[l] * fac[l];
+  cr_problem pr = *fid;
+  pr.cl = cl.data();
+  CR_CHECK(solve_core(P, &pr, 1.0, 1, nullptr, dr->w0, dr->w1, nullptr, st->fhat, opts, &out->fluct_stats, s));
+  const int64_t na = P->g.nalm;
+  if (out->accepted)
+    CR_TRY(hipMemcpyAsync(st->ahat, w.alm_c, na * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  double t[3];
+  CR_CHECK(lnpi_terms(P, fid->ninv, d, C2(st->ahat), C2(st->fhat), t, s));
+  for (int k = 0; k < nb; ++k) st->theta[k] = te[k];
+  st->lnpi = -0.5 * (t[0] + t[1] + t[2]);
+  CR_TRY(hipStreamSynchronize(s));
+  return CR_OK;
+}
+
 extern "C" int gibbs_cl_step(const crsht_plan* P, const cr_problem* fid, const double* d, cr_chain* state, double g,
                              const double* w0, const double* w1, const cr_opts* opts, cr_gibbs_out* out,
                              void* stream) {

@@ -105,6 +105,7 @@ struct Workspace {
   int* bin_edges = nullptr;    // [lmax+2] multipole bin edges of a gradient call
   double* bin_part = nullptr;  // [lmax+1][kBinSlices][3] per-bin partial sums
   double* bin_grad = nullptr;  // [lmax+1] per-bin gradient
+  double* lfac = nullptr;      // [lmax+1] per-l factors (fluctuation rescaling of a bin move)
   void* mx_ab = nullptr;       // bf16 synthesis operand tiles (one group of kMixedCols columns)
   void* mx_ag = nullptr;       // bf16 adjoint operand tiles
   int npart = 0;
@@ -350,9 +351,14 @@ hipError_t launch_pix_wres(const crsht_plan* P, int nrhs, const double* ninv, co
 hipError_t launch_mweight(const crsht_plan* P, int nrhs, double2* a, hipStream_t s);
 // grad[k] = <a,S^-1_k a>/2 + <lam,S^-1/2_k w0>/2 - <lam,S^-1_k f> for the bins of
 // edges (device, nbins + 1 entries); w0 may be null
+// per-bin d ln pi / d theta_k; mode 0: at fixed w0, w1 (lam = A^-1 M f);
+// mode 1: at fixed whitened fluctuation (lam = M f, w0 unused)
 hipError_t launch_bin_grad(const crsht_plan* P, int nbins, const int* edges, const double2* ahat,
                            const double2* fhat, const double2* lam, const double2* w0, double* grad,
-                           hipStream_t s);
+                           hipStream_t s, int mode = 0);
+// out = fac_l[l] * in (one column of nalm coefficients)
+hipError_t launch_scale_per_l(const crsht_plan* P, const double2* in, const double* fac_l, double2* out,
+                              hipStream_t s);
 hipError_t launch_pix_wsq(const crsht_plan* P, const double* w, const double* x, const double* y, double* partial,
                           int nb, hipStream_t s);
 hipError_t launch_alm_wquad(const crsht_plan* P, const double* f, const double2* a, double* partial, int nb,

@@ -37,6 +37,16 @@ __global__ void k_scale(int64_t nalm, int nrhs, const double2* in, const double*
   }
 }
 
+// out = fac_l[l] * in per coefficient (one column)
+__global__ void k_scale_l(int64_t nalm, const int* __restrict__ idx_l, const double* __restrict__ fac_l,
+                          const double2* __restrict__ in, double2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nalm) return;
+  const double f = fac_l[idx_l[i]];
+  const double2 v = in[i];
+  out[i] = make_double2(f * v.x, f * v.y);
+}
+
 __global__ void k_ring_weights(int npairs, const int* __restrict__ nphi, const int64_t* __restrict__ fn,
                                const int64_t* __restrict__ fs, const double* __restrict__ ninv,
                                const double* __restrict__ ninv2, double scale, double* __restrict__ w) {
@@ -472,7 +482,7 @@ __global__ void k_bin_terms(int mmax, const int64_t* __restrict__ mstart, const 
                             const double* __restrict__ sinv, const double* __restrict__ sinvhalf,
                             const double2* __restrict__ ahat, const double2* __restrict__ fhat,
                             const double2* __restrict__ lam, const double2* __restrict__ w0,
-                            double* __restrict__ partial) {
+                            double* __restrict__ partial, int mode) {
   __shared__ double sh[kVecBlock];
   const int k = blockIdx.x, sl = blockIdx.y, S = gridDim.y;
   const int l0 = edges[k], l1 = edges[k + 1];
@@ -486,7 +496,7 @@ __global__ void k_bin_terms(int mmax, const int64_t* __restrict__ mstart, const 
       const double2 a = ahat[i], f = fhat[i], L = lam[i];
       const double si = sinv[i];
       t1 += si * wdot(m, a, a);
-      t3 += si * wdot(m, L, f);
+      t3 += (mode == 1 ? 1.0 : si) * wdot(m, L, f);
       if (w0) t2 += sinvhalf[i] * wdot(m, L, w0[i]);
     }
   }
@@ -501,8 +511,10 @@ __global__ void k_bin_terms(int mmax, const int64_t* __restrict__ mstart, const 
   }
 }
 
-// d ln pi / d theta_k = t1/2 + t2/2 - t3, slices summed in a fixed order
-__global__ void k_bin_grad(int nbins, int S, const double* __restrict__ partial, double* __restrict__ grad) {
+// d ln pi / d theta_k = t1/2 + t2/2 - t3 (mode 0: fixed w0, w1) or t1/2 - t3/2
+// (mode 1: fixed whitened fluctuation, lam = M f), slices summed in a fixed order
+__global__ void k_bin_grad(int nbins, int S, const double* __restrict__ partial, double* __restrict__ grad,
+                           int mode) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nbins) return;
   double t1 = 0.0, t2 = 0.0, t3 = 0.0;
@@ -512,7 +524,7 @@ __global__ void k_bin_grad(int nbins, int S, const double* __restrict__ partial,
     t2 += o[1];
     t3 += o[2];
   }
-  grad[k] = 0.5 * t1 + 0.5 * t2 - t3;
+  grad[k] = mode == 1 ? 0.5 * t1 - 0.5 * t3 : 0.5 * t1 + 0.5 * t2 - t3;
 }
 
 }  // namespace
@@ -666,12 +678,20 @@ hipError_t launch_mweight(const crsht_plan* P, int nrhs, double2* a, hipStream_t
 
 hipError_t launch_bin_grad(const crsht_plan* P, int nbins, const int* edges, const double2* ahat,
                            const double2* fhat, const double2* lam, const double2* w0, double* grad,
-                           hipStream_t s) {
+                           hipStream_t s, int mode) {
   hipLaunchKernelGGL(k_bin_terms, dim3(nbins, kBinSlices), dim3(kVecBlock), 0, s, P->g.mmax, P->t.mstart, edges,
-                     P->w.sinv, P->w.sinvhalf, ahat, fhat, lam, w0, P->w.bin_part);
+                     P->w.sinv, P->w.sinvhalf, ahat, fhat, lam, w0, P->w.bin_part, mode);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bin_grad, dim3((nbins + 63) / 64), dim3(64), 0, s, nbins, kBinSlices, P->w.bin_part, grad);
+  hipLaunchKernelGGL(k_bin_grad, dim3((nbins + 63) / 64), dim3(64), 0, s, nbins, kBinSlices, P->w.bin_part, grad,
+                     mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_per_l(const crsht_plan* P, const double2* in, const double* fac_l, double2* out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_l, dim3(nblocks(P->g.nalm)), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_l, fac_l, in,
+                     out);
   return hipGetLastError();
 }
 

@@ -117,3 +117,106 @@ def test_chain_driver_replays_oracle(kind):
     print(summ, flush=True)
     assert summ["steps"] == nsteps and 0.0 <= summ["acceptance"] <= 1.0 and summ["iat_lnq"] >= 1.0
     _ = math, torch
+
+
+# ------------------------------------------------ HMC over bin log-amplitudes
+def _bin_setup(edges, tol, seed):
+    m = _m()
+    wl, P, op, d = masked_problem(8)
+    plan = m.Plan(8, wl.lmax)
+    gp = m.Problem(P.cl, P.bl, tc(P.ninv), 2)
+    nb = len(edges) - 1
+    rng = np.random.default_rng([seed, nb])
+    st = joint.init_bin_state(P, d, edges, np.zeros(nb), ci.white_alm(rng, P.lmax), rng.standard_normal(P.ninv.size),
+                              tol)
+    return m, wl, P, d, plan, gp, st
+
+
+def _bin_chain(m, edges, st):
+    return m.BinChain(np.asarray(edges, dtype=np.int32), st.theta.copy(), st.lnpi, tc(st.ahat), tc(st.fhat))
+
+
+@pytest.mark.parametrize("warm", [False, True])
+def test_lnpi_grad_fixed_matches_oracle(warm):
+    tol = 1e-12
+    m = _m()
+    wl, P, op, d = masked_problem(8)
+    edges = [2, 6, 12, P.lmax + 1]
+    print("case lnpi_grad_fixed warm=%s" % warm, flush=True)
+    plan = m.Plan(8, wl.lmax)
+    gp = m.Problem(P.cl, P.bl, tc(P.ninv), 2)
+    rng = np.random.default_rng(31)
+    th0 = np.array([0.1, -0.05, 0.02])
+    st = joint.init_bin_state(P, d, edges, th0, ci.white_alm(rng, P.lmax), rng.standard_normal(P.ninv.size), tol)
+    th = th0 + np.array([0.03, -0.02, 0.04])
+    lp, g, ahat = joint.lnpi_grad_fixed(P, d, edges, th0, th, st.fhat, tol)
+    gg, glp, gahat, stats = m.lnpi_grad_fixed(plan, gp, tc(d), edges, th0, th, tc(st.fhat),
+                                              a0=tc(st.ahat) if warm else None, tol=tol)
+    print("grad gpu", gg, "oracle", g, "lnpi %.12e %.12e iters %d" % (glp, lp, stats.iters), flush=True)
+    assert stats.status == 0
+    assert np.all(np.abs(gg - g) <= 1e-8 * np.maximum(1.0, np.abs(g)))
+    assert abs(glp - lp) <= 1e-10 * abs(lp)
+    opb = cr.CROperator(joint.bin_problem(P, edges, th))
+    assert real_rel(opb, gahat.cpu().numpy(), ahat) < 1e-9
+
+
+@pytest.mark.parametrize("nbins", [1, 3])
+def test_hmc_step_matches_oracle(nbins):
+    # three moves with the same draws on both sides: accepted, rejected (a
+    # step size the trajectory cannot hold), accepted; theta, ln pi, the mean
+    # field and the refreshed fluctuation after each
+    tol = 1e-12
+    edges = [2, 24] if nbins == 1 else [2, 6, 12, 24]
+    m, wl, P, d, plan, gp, st = _bin_setup(edges, tol, 91)
+    assert P.lmax + 1 == 24
+    ch = _bin_chain(m, edges, st)
+    moves = [(0.02, 3), (0.1, 2) if nbins == 1 else (0.06, 2), (0.05, 3)]
+    flags = []
+    for s, (eps, nleap) in enumerate(moves):
+        print("case hmc step nbins=%d move %d eps %g nleap %d" % (nbins, s, eps, nleap), flush=True)
+        rng = np.random.default_rng([92, nbins, s])
+        p0, u = rng.standard_normal(nbins), float(rng.uniform())
+        w0n, w1n = ci.white_alm(rng, P.lmax), rng.standard_normal(P.ninv.size)
+        res = m.hmc_step(plan, gp, tc(d), ch, p0, u, tc(w0n), tc(w1n), eps, nleap, tol=tol)
+        st, r = joint.hmc_step(P, d, edges, st, p0, u, w0n, w1n, eps, nleap, tol)
+        print("dH gpu %.12e oracle %.12e accepted %s/%s solves %d iters %d" %
+              (res.dH, r.dH, res.accepted, r.accepted, res.solves, res.iters), flush=True)
+        flags.append(r.accepted)
+        assert res.accepted == r.accepted
+        assert abs(res.dH - r.dH) <= 1e-6 * max(1.0, abs(r.dH))
+        assert abs(res.lnpi_new - r.lnpi_new) <= 1e-9 * abs(r.lnpi_new)
+        assert res.status == 0 and res.fluct_stats.status == 0 and res.solves == nleap + 1
+        assert np.all(np.abs(ch.theta - st.theta) <= 1e-8)
+        assert abs(ch.lnpi - st.lnpi) <= 1e-9 * abs(st.lnpi)
+        opb = cr.CROperator(joint.bin_problem(P, edges, st.theta))
+        assert real_rel(opb, ch.ahat.cpu().numpy(), st.ahat) < 1e-8
+        assert real_rel(opb, ch.fhat.cpu().numpy(), st.fhat) < 1e-8
+    assert flags == [True, False, True]
+
+
+def test_hmc_chain_driver_replays_oracle():
+    from paper_2306_15511_amd import chains
+    tol = 1e-12
+    edges = [2, 8, 24]
+    m, wl, P, d, plan, gp, st = _bin_setup(edges, tol, 93)
+    print("case hmc chain driver", flush=True)
+    draws = {}
+
+    def draw(c, s):
+        if (c, s) not in draws:
+            rng = np.random.default_rng([94, c, s])
+            draws[(c, s)] = {"p0": rng.standard_normal(2), "u": float(rng.uniform()),
+                             "w0": ci.white_alm(rng, P.lmax), "w1": rng.standard_normal(P.ninv.size)}
+        return draws[(c, s)]
+
+    ch = _bin_chain(m, edges, st)
+    run = chains.run_hmc(plan, gp, tc(d), [ch], 3, 0.03, 3, draw=draw, tol=tol)
+    for s in range(3):
+        r = draw(0, s)
+        st, res = joint.hmc_step(P, d, edges, st, r["p0"], r["u"], r["w0"], r["w1"], 0.03, 3, tol)
+        assert bool(run.accepted[0, s]) == res.accepted
+        assert np.all(np.abs(run.theta[0, s + 1] - st.theta) <= 1e-8), s
+    assert abs(ch.lnpi - st.lnpi) <= 1e-9 * abs(st.lnpi)
+    summ = run.summary()
+    print(summ, flush=True)
+    assert summ["steps"] == 3 and summ["bins"] == 2 and 0.0 <= summ["acceptance"] <= 1.0

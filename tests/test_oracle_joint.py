@@ -169,3 +169,92 @@ def test_joint_and_gibbs_chains_sample_exact_marginal_posterior():
         assert abs(x.mean() - exact) < 4.0 * se, (kind, x.mean(), exact, se)
         if kind == "joint":
             assert 0.2 < acc / 800 < 0.95
+
+
+# ------------------------------------------------ HMC over bin log-amplitudes
+def test_fixed_fluctuation_gradient_against_central_differences():
+    # d ln pi / d theta_k at a fixed whitened fluctuation (f carried as
+    # exp((theta - theta0)/2) f0) against central differences of ln pi itself,
+    # on three bins; both terms of the gradient are far above the tolerance,
+    # so dropping either (or a wrong factor on the fluctuation term) fails
+    wl, P, op, d = _problem(4)
+    edges = [2, 4, 8, P.lmax + 1]
+    rng = np.random.default_rng(11)
+    th0 = np.array([0.1, -0.2, 0.05])
+    st = joint.init_bin_state(P, d, edges, th0, ci.white_alm(rng, P.lmax), rng.standard_normal(d.size), 1e-13)
+    th = th0 + np.array([0.3, -0.15, 0.2])
+    lp, g, ahat = joint.lnpi_grad_fixed(P, d, edges, th0, th, st.fhat, 1e-13)
+    h = 1e-4
+    fd = np.zeros(3)
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        lpp = joint.lnpi_grad_fixed(P, d, edges, th0, th + e, st.fhat, 1e-13)[0]
+        lpm = joint.lnpi_grad_fixed(P, d, edges, th0, th - e, st.fhat, 1e-13)[0]
+        fd[k] = (lpp - lpm) / (2 * h)
+    assert np.all(np.abs(g - fd) < 1e-6 * np.maximum(1.0, np.abs(fd))), (g, fd)
+    opb = cr.CROperator(joint.bin_problem(P, edges, th))
+    f = st.fhat * joint.bin_factors(P.lmax, edges, th - th0, 0.5)[opb.ls]
+    Mf = opb.apply_data_term(f)
+    for k in range(3):
+        sel = (opb.ls >= edges[k]) & (opb.ls < edges[k + 1])
+        assert 0.5 * opb.dot(ahat * sel, opb.sinv * ahat * sel) > 1e-3
+        assert 0.5 * opb.dot(f * sel, Mf) > 1e-3
+    # at theta = theta0 the carried fluctuation is f0 itself
+    assert abs(joint.lnpi_grad_fixed(P, d, edges, th0, th0, st.fhat, 1e-13)[0] - st.lnpi) < 1e-9 * abs(st.lnpi)
+
+
+def test_leapfrog_energy_error_falls_as_step_squared():
+    # fixed trajectory length, step halved: |dH| of the same trajectory falls
+    # by about four (second-order integrator); a wrong half step at either end
+    # or a gradient of the wrong sign makes it first order or divergent
+    wl, P, op, d = _tiny(2, 4)
+    edges = [2, 3, 5]
+    rng = np.random.default_rng(7)
+    st = joint.init_bin_state(P, d, edges, np.array([1.0, 0.6]), ci.white_alm(rng, P.lmax),
+                              rng.standard_normal(d.size), 1e-12)
+    p0 = np.array([0.7, -0.4])
+    w0n, w1n = ci.white_alm(rng, P.lmax), rng.standard_normal(d.size)
+    dh = [joint.hmc_step(P, d, edges, st, p0, 0.5, w0n, w1n, 0.4 / n, n, 1e-12)[1].dH for n in (4, 8, 16)]
+    assert abs(dh[0]) > 1e-4
+    for a, b in zip(dh, dh[1:]):
+        assert 3.0 < a / b < 5.0, dh
+
+
+def test_hmc_chain_samples_exact_marginal_posterior():
+    # two bins (l = 2; l = 3..4) of the tiny masked problem: the exact
+    # posterior of (theta_0, theta_1) from the Gaussian likelihood of the
+    # observed pixels with a uniform prior in the amplitudes exp(theta_k), on
+    # a grid; the HMC chain's means within four standard errors
+    wl, P, op, d = _tiny(2, 4)
+    edges = [2, 3, 5]
+    D = dense.DenseY(P.nside, P.lmax, lmin=2)
+    obs = P.ninv > 0
+    Yo = D.Y[obs] * D._per_dof(P.bl)[None, :]
+    var1 = D._per_dof(P.cl) / D.W
+    lsd = D._per_dof(np.arange(P.lmax + 1, dtype=np.float64))
+    t0, t1 = np.linspace(-4.0, 10.0, 141), np.linspace(-3.0, 4.0, 71)
+    lp = np.zeros((t0.size, t1.size))
+    for i, a0 in enumerate(t0):
+        for j, a1 in enumerate(t1):
+            C = (Yo * (var1 * np.where(lsd < 3, math.exp(a0), math.exp(a1)))[None, :]) @ Yo.T
+            L = np.linalg.cholesky(C + np.diag(1.0 / P.ninv[obs]))
+            y = np.linalg.solve(L, d[obs])
+            lp[i, j] = -0.5 * float(y @ y) - float(np.log(np.diag(L)).sum()) + a0 + a1
+    w = np.exp(lp - lp.max())
+    assert w[-1].sum() < 1e-5 * w.sum() and w[:, -1].sum() < 1e-5 * w.sum()
+    exact = [float((w.sum(1) * t0).sum() / w.sum()), float((w.sum(0) * t1).sum() / w.sum())]
+    rng = np.random.default_rng(5)
+    st = joint.init_bin_state(P, d, edges, np.zeros(2), ci.white_alm(rng, P.lmax), rng.standard_normal(d.size), 1e-10)
+    trace, acc = [], 0
+    for _ in range(300):
+        st, r = joint.hmc_step(P, d, edges, st, rng.standard_normal(2), rng.uniform(), ci.white_alm(rng, P.lmax),
+                               rng.standard_normal(d.size), 0.2, 3, 1e-8)
+        acc += r.accepted
+        trace.append(st.theta.copy())
+    x = np.array(trace[50:])
+    for k in range(2):
+        se = x[:, k].std() * math.sqrt(_iat(x[:, k]) / x.shape[0])
+        print(k, "mean %.3f exact %.3f se %.3f" % (x[:, k].mean(), exact[k], se))
+        assert abs(x[:, k].mean() - exact[k]) < 4.0 * se, (k, x[:, k].mean(), exact[k], se)
+    assert 0.5 < acc / 300 <= 1.0
