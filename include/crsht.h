@@ -140,6 +140,12 @@ typedef struct {
                           ncomp = 3: [3][npix] for T, Q, U (no Q-U noise correlation). */
   int lmin;            /* first constrained multipole, 0 <= lmin <= lmax (2 for C_0 = C_1 = 0);
                           ncomp = 3 requires lmin >= 2. */
+  const double *amp;   /* host, [nrhs] or NULL: column c of cr_rhs, cr_apply, cr_solve and
+                          cr_solve_batched solves with the spectrum amp[c] C_l (amp[c] > 0 and
+                          finite; NULL = 1 for every column), e.g. the right-hand sides of several
+                          chains at different amplitudes in one call. The preconditioners (Jacobi
+                          and block) stay those of C_l. Every other call taking a cr_problem
+                          requires NULL (CR_EINVAL otherwise). */
 } cr_problem;
 
 typedef struct {

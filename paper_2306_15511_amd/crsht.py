@@ -39,7 +39,7 @@ class _Info(ctypes.Structure):
 
 class _Problem(ctypes.Structure):
     _fields_ = [("cl", ctypes.POINTER(ctypes.c_double)), ("bl", ctypes.POINTER(ctypes.c_double)),
-                ("ninv", ctypes.c_void_p), ("lmin", ctypes.c_int)]
+                ("ninv", ctypes.c_void_p), ("lmin", ctypes.c_int), ("amp", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Opts(ctypes.Structure):
@@ -277,18 +277,24 @@ def analysis(plan: Plan, m: torch.Tensor, n_iter: int = 0, out: torch.Tensor | N
 class Problem:
     """cl, bl: host float64 arrays of lmax+1; ninv: device float64 [npix].
     Plans with ncomp = 3: cl [4, lmax+1] (TT, EE, BB, TE), ninv [3, npix]
-    (T, Q, U), lmin >= 2."""
+    (T, Q, U), lmin >= 2. amp: optional host float64 array, one amplitude
+    per column (column c solves with amp[c] C_l; rhs, apply and solve only)."""
     cl: object
     bl: object
     ninv: torch.Tensor
     lmin: int = 2
+    amp: object = None
 
     def _c(self, q: float = 1.0):
         import numpy as np
         self._cl = np.ascontiguousarray(self.cl, dtype=np.float64)
         self._bl = np.ascontiguousarray(self.bl, dtype=np.float64)
         dp = ctypes.POINTER(ctypes.c_double)
-        return _Problem(self._cl.ctypes.data_as(dp), self._bl.ctypes.data_as(dp), _ptr(self.ninv), self.lmin)
+        amp = None
+        if self.amp is not None:
+            self._amp = np.ascontiguousarray(self.amp, dtype=np.float64)
+            amp = self._amp.ctypes.data_as(dp)
+        return _Problem(self._cl.ctypes.data_as(dp), self._bl.ctypes.data_as(dp), _ptr(self.ninv), self.lmin, amp)
 
 
 @dataclass

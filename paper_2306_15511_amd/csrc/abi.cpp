@@ -90,10 +90,29 @@ int set_problem_tqu(const crsht_plan* P, const cr_problem* prob, double q, hipSt
   return CR_OK;
 }
 
-// ---- problem set-up: per-l factors for amplitude q (C_l -> q C_l)
-int set_problem(const crsht_plan* P, const cr_problem* prob, double q, hipStream_t s) {
+// per-column amplitudes of prob (columns 0..nrhs-1; nrhs = 0: the caller
+// takes none, so prob->amp must be NULL) into w.camp as (1/amp, 1/sqrt(amp)),
+// 1 for every column without one
+int set_columns(const crsht_plan* P, const cr_problem* prob, int nrhs, hipStream_t s) {
+  if (prob->amp && nrhs < 1) return CR_EINVAL;
+  std::vector<double2> f((size_t)P->nrhs_max, make_double2(1.0, 1.0));
+  if (prob->amp)
+    for (int c = 0; c < nrhs; ++c) {
+      const double a = prob->amp[c];
+      if (!(a > 0.0) || !std::isfinite(a)) return CR_EINVAL;
+      f[c] = make_double2(1.0 / a, 1.0 / std::sqrt(a));
+    }
+  CR_TRY(hipMemcpyAsync(P->w.camp, f.data(), f.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+  CR_TRY(hipStreamSynchronize(s));  // f (host vector) must outlive the copy
+  return CR_OK;
+}
+
+// ---- problem set-up: per-l factors for amplitude q (C_l -> q C_l); nrhs as
+// for set_columns
+int set_problem(const crsht_plan* P, const cr_problem* prob, double q, hipStream_t s, int nrhs = 0) {
   if (!prob || !prob->cl || !prob->bl || !prob->ninv) return CR_EINVAL;
   if (!(q > 0.0) || !std::isfinite(q)) return CR_EINVAL;
+  CR_CHECK(set_columns(P, prob, nrhs, s));
   if (P->ncomp == 3) return set_problem_tqu(P, prob, q, s);
   const int lmax = P->g.lmax;
   if (prob->lmin < 0 || prob->lmin > lmax) return CR_EINVAL;
@@ -597,7 +616,7 @@ int solve_core(const crsht_plan* P, const cr_problem* prob, double q, int nrhs, 
   const bool pc = opts->precond == CR_PC_BLOCK;
   if (pc && !P->pc.built) return CR_EINVAL;
   const int every = opts->check_every > 0 ? opts->check_every : 8;
-  CR_CHECK(set_problem(P, prob, q, s));
+  CR_CHECK(set_problem(P, prob, q, s, nrhs));
   if (!pc) CR_CHECK(compute_diag(P, prob->ninv, s));
   if (rhs)
     CR_TRY(launch_project(P, nrhs, C2(rhs), P->w.cg_b, s));
@@ -745,7 +764,7 @@ extern "C" int cr_rhs(const crsht_plan* P, const cr_problem* prob, int nrhs, con
   CR_CHECK(check_plan(P, nrhs));
   if (!b) return CR_EINVAL;
   hipStream_t s = S(stream);
-  CR_CHECK(set_problem(P, prob, 1.0, s));
+  CR_CHECK(set_problem(P, prob, 1.0, s, nrhs));
   return assemble_rhs(P, nrhs, prob->ninv, d, w0, w1, C2(b), s);
 }
 
@@ -755,7 +774,7 @@ extern "C" int cr_apply(const crsht_plan* P, const cr_problem* prob, int nrhs, c
   if (!x || !Ax) return CR_EINVAL;
   if (prec != CR_F64 && prec != CR_MIXED) return CR_EINVAL;
   hipStream_t s = S(stream);
-  CR_CHECK(set_problem(P, prob, 1.0, s));
+  CR_CHECK(set_problem(P, prob, 1.0, s, nrhs));
   CR_TRY(launch_project(P, nrhs, C2(x), P->w.cg_d, s));
   if (P->ncomp == 1) CR_TRY(launch_scale_alm(P, nrhs, P->w.cg_d, P->w.bk, P->w.alm_a, s));
   return operator_core(P, nrhs, P->w.cg_d, P->w.alm_a, prob->ninv, C2(Ax), s, prec == CR_MIXED);
@@ -889,6 +908,7 @@ extern "C" int cr_grad_lnpi(const crsht_plan* P, const cr_problem* prob, const d
                             const double* w1, int nbins, const int* edges, const cr_opts* opts, double* grad,
                             double* lnpi, cr_stats* stats, void* stream) {
   CR_CHECK(check_plan(P, 1));
+  if (prob && prob->amp) return CR_EINVAL;   // one spectrum per call
   if (P->ncomp != 1) return CR_ENOTSUP;
   if (!prob || !d || !edges || !opts || !grad || !lnpi || !stats) return CR_EINVAL;
   if (nbins < 1 || nbins > P->g.lmax + 1) return CR_EINVAL;
@@ -924,6 +944,7 @@ extern "C" int cr_grad_lnpi(const crsht_plan* P, const cr_problem* prob, const d
 extern "C" int joint_cl_step(const crsht_plan* P, const cr_problem* fid, const double* d, cr_chain* state,
                              const cr_draws* dr, const cr_opts* opts, cr_step_out* out, void* stream) {
   CR_CHECK(check_plan(P, 1));
+  if (fid && fid->amp) return CR_EINVAL;   // one spectrum per call
   if (P->ncomp != 1) return CR_ENOTSUP;
   if (!fid || !d || !state || !dr || !opts || !out || !state->ahat || !state->fhat) return CR_EINVAL;
   if (!(dr->sigma_lnq > 0.0) || !(dr->u > 0.0 && dr->u < 1.0) || !std::isfinite(dr->xi)) return CR_EINVAL;
@@ -1017,6 +1038,7 @@ extern "C" int cr_lnpi_grad_fixed(const crsht_plan* P, const cr_problem* fid, co
                                   const double* a0, const cr_opts* opts, double* lnpi, double* grad, double* ahat,
                                   cr_stats* stats, void* stream) {
   CR_CHECK(check_plan(P, 1));
+  if (fid && fid->amp) return CR_EINVAL;   // one spectrum per call
   if (P->ncomp != 1) return CR_ENOTSUP;
   if (!fid || !d || !theta0 || !theta || !f0 || !opts || !lnpi || !grad || !stats) return CR_EINVAL;
   if (!valid_bins(P, nbins, edges)) return CR_EINVAL;
@@ -1032,6 +1054,7 @@ extern "C" int cr_lnpi_grad_fixed(const crsht_plan* P, const cr_problem* fid, co
 extern "C" int hmc_cl_step(const crsht_plan* P, const cr_problem* fid, const double* d, cr_bin_chain* st,
                            const cr_hmc_draws* dr, const cr_opts* opts, cr_hmc_out* out, void* stream) {
   CR_CHECK(check_plan(P, 1));
+  if (fid && fid->amp) return CR_EINVAL;   // one spectrum per call
   if (P->ncomp != 1) return CR_ENOTSUP;
   if (!fid || !d || !st || !dr || !opts || !out || !st->theta || !st->ahat || !st->fhat || !dr->p0)
     return CR_EINVAL;
@@ -1105,6 +1128,7 @@ extern "C" int gibbs_cl_step(const crsht_plan* P, const cr_problem* fid, const d
                              const double* w0, const double* w1, const cr_opts* opts, cr_gibbs_out* out,
                              void* stream) {
   CR_CHECK(check_plan(P, 1));
+  if (fid && fid->amp) return CR_EINVAL;   // one spectrum per call
   if (P->ncomp != 1) return CR_ENOTSUP;
   if (!fid || !d || !state || !opts || !out || !state->ahat || !state->fhat || (!w0 && !w1)) return CR_EINVAL;
   if (!(g > 0.0) || !std::isfinite(g) || !(state->q > 0.0)) return CR_EINVAL;

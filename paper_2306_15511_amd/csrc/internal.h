@@ -106,6 +106,7 @@ struct Workspace {
   double* bin_part = nullptr;  // [lmax+1][kBinSlices][3] per-bin partial sums
   double* bin_grad = nullptr;  // [lmax+1] per-bin gradient
   double* lfac = nullptr;      // [lmax+1] per-l factors (fluctuation rescaling of a bin move)
+  double2* camp = nullptr;     // [nrhs_max] per-column (1/amp, 1/sqrt(amp)) of the problem's S^-1, S^-1/2
   void* mx_ab = nullptr;       // bf16 synthesis operand tiles (one group of kMixedCols columns)
   void* mx_ag = nullptr;       // bf16 adjoint operand tiles
   int npart = 0;

@@ -201,14 +201,15 @@ __device__ __forceinline__ void block3(const double* s, double2 t, double2 e, do
   ob = sc2(s[3], b);
 }
 
-// q = S^-1 p + dterm (3x3 blocks per l; S^-1 term omitted when sblk is null)
-// per column; partial <p, q> per block
+// q = camp[c].x S^-1 p + dterm (3x3 blocks per l; S^-1 term omitted when sblk
+// is null) per column c; partial <p, q> per block
 __global__ void k_cg_q_tqu(int64_t nalm, const int* __restrict__ idx_l, const int* __restrict__ idx_m,
-                           const double* __restrict__ sblk, const double2* __restrict__ p,
-                           const double2* __restrict__ dterm, double2* __restrict__ q, double* __restrict__ partial,
-                           int npart) {
+                           const double* __restrict__ sblk, const double2* __restrict__ camp,
+                           const double2* __restrict__ p, const double2* __restrict__ dterm, double2* __restrict__ q,
+                           double* __restrict__ partial, int npart) {
   __shared__ double sh[kVecT];
   const int c = blockIdx.y;
+  const double qa = camp[c].x;
   const int64_t base = (int64_t)c * 3 * nalm;
   double pq = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nalm; i += (int64_t)gridDim.x * blockDim.x) {
@@ -219,9 +220,9 @@ __global__ void k_cg_q_tqu(int64_t nalm, const int* __restrict__ idx_l, const in
     if (sblk) {
       double2 st, se, sb;
       block3(s, pt, pe, pb, st, se, sb);
-      qt = ad2(qt, st);
-      qe = ad2(qe, se);
-      qb = ad2(qb, sb);
+      qt = ad2(qt, sc2(qa, st));
+      qe = ad2(qe, sc2(qa, se));
+      qb = ad2(qb, sc2(qa, sb));
     }
     q[base + i] = qt;
     q[base + nalm + i] = qe;
@@ -232,10 +233,12 @@ __global__ void k_cg_q_tqu(int64_t nalm, const int* __restrict__ idx_l, const in
   if (threadIdx.x == 0) partial[(size_t)c * npart * 4 + blockIdx.x] = pq;
 }
 
-// out = dterm + S^-1/2 w0 (either may be null), Im of m = 0 set to 0
+// out = dterm + camp[c].y S^-1/2 w0 per column c (either term may be null),
+// Im of m = 0 set to 0
 __global__ void k_rhs_finish_tqu(int64_t nalm, int nrhs, const int* __restrict__ idx_l, const int* __restrict__ idx_m,
-                                 const double* __restrict__ sblk, const double2* __restrict__ dterm,
-                                 const double2* __restrict__ w0, double2* __restrict__ out) {
+                                 const double* __restrict__ sblk, const double2* __restrict__ camp,
+                                 const double2* __restrict__ dterm, const double2* __restrict__ w0,
+                                 double2* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nalm) return;
   const bool m0 = idx_m[i] == 0;
@@ -248,9 +251,10 @@ __global__ void k_rhs_finish_tqu(int64_t nalm, int nrhs, const int* __restrict__
     if (w0) {
       double2 a, b, d;
       block3(s, w0[base + i], w0[base + nalm + i], w0[base + 2 * nalm + i], a, b, d);
-      v[0] = ad2(v[0], a);
-      v[1] = ad2(v[1], b);
-      v[2] = ad2(v[2], d);
+      const double qh = camp[c].y;
+      v[0] = ad2(v[0], sc2(qh, a));
+      v[1] = ad2(v[1], sc2(qh, b));
+      v[2] = ad2(v[2], sc2(qh, d));
     }
     for (int k = 0; k < 3; ++k) {
       if (m0) v[k].y = 0.0;
@@ -353,14 +357,14 @@ hipError_t launch_cg_q_tqu(const crsht_plan* P, int nrhs, const double2* p, cons
                            hipStream_t s, bool prior) {
   const int nb = vec_reduce_blocks(P);
   hipLaunchKernelGGL(k_cg_q_tqu, dim3(nb, nrhs), dim3(kVecT), 0, s, P->g.nalm, P->t.idx_l, P->t.idx_m,
-                     prior ? P->w.sblk : nullptr, p, dterm, q, P->w.partial, P->w.npart);
+                     prior ? P->w.sblk : nullptr, P->w.camp, p, dterm, q, P->w.partial, P->w.npart);
   return hipGetLastError();
 }
 
 hipError_t launch_rhs_finish_tqu(const crsht_plan* P, int nrhs, const double2* dterm, const double2* w0,
                                  double2* out, hipStream_t s) {
   hipLaunchKernelGGL(k_rhs_finish_tqu, dim3(nblk(P->g.nalm)), dim3(kVecT), 0, s, P->g.nalm, nrhs, P->t.idx_l,
-                     P->t.idx_m, P->w.sblk, dterm, w0, out);
+                     P->t.idx_m, P->w.sblk, P->w.camp, dterm, w0, out);
   return hipGetLastError();
 }
 

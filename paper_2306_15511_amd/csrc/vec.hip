@@ -86,11 +86,13 @@ __global__ void k_pix_rhs(int64_t npix, int nrhs, int ncomp, const double* __res
   }
 }
 
-// out = bk * raw + sinvhalf * w0 (either may be absent), raw = the unscaled
-// adjoint Legendre sums of N^-1 d + N^-1/2 w1; Im of m = 0 forced to 0
+// out = bk * raw + sinvhalf * w0 (either may be absent; the S^-1/2 term of
+// column c scaled by camp[c].y), raw = the unscaled adjoint Legendre sums of
+// N^-1 d + N^-1/2 w1; Im of m = 0 forced to 0
 __global__ void k_rhs_finish(int64_t nalm, int nrhs, const int* __restrict__ idx_m, const double* __restrict__ bk,
-                             const double* __restrict__ sinvhalf, const double2* __restrict__ raw,
-                             const double2* __restrict__ w0, double2* __restrict__ out) {
+                             const double* __restrict__ sinvhalf, const double2* __restrict__ camp,
+                             const double2* __restrict__ raw, const double2* __restrict__ w0,
+                             double2* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nalm) return;
   const double sh = sinvhalf[i], b = bk[i];
@@ -101,8 +103,9 @@ __global__ void k_rhs_finish(int64_t nalm, int nrhs, const int* __restrict__ idx
     v.y *= b;
     if (w0) {
       const double2 w = w0[c * nalm + i];
-      v.x = fma(sh, w.x, v.x);
-      v.y = fma(sh, w.y, v.y);
+      const double shc = sh * camp[c].y;
+      v.x = fma(shc, w.x, v.x);
+      v.y = fma(shc, w.y, v.y);
     }
     if (m0) v.y = 0.0;
     out[c * nalm + i] = v;
@@ -340,16 +343,18 @@ __global__ void k_cg_pupdate(int64_t nalm, const double* __restrict__ bk, const 
   }
 }
 
-// q = sinv * p + bk * raw; partial <p, q>
+// q = camp[c].x sinv * p + bk * raw for column c; partial <p, q>
 __global__ void k_cg_q(int64_t nalm, const int* __restrict__ idx_m, const double* __restrict__ sinv,
-                       const double* __restrict__ bk, const double2* __restrict__ p, const double2* __restrict__ raw,
-                       double2* __restrict__ q, double* __restrict__ partial, int npart) {
+                       const double2* __restrict__ camp, const double* __restrict__ bk,
+                       const double2* __restrict__ p, const double2* __restrict__ raw, double2* __restrict__ q,
+                       double* __restrict__ partial, int npart) {
   __shared__ double sh[kVecBlock];
   const int c = blockIdx.y;
+  const double qa = camp[c].x;
   double pq = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nalm; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t ci = c * nalm + i;
-    const double si = sinv ? sinv[i] : 0.0, b = bk[i];
+    const double si = sinv ? qa * sinv[i] : 0.0, b = bk[i];
     const double2 pv = p[ci], rv = raw[ci];
     const double2 qv = make_double2(fma(si, pv.x, b * rv.x), fma(si, pv.y, b * rv.y));
     q[ci] = qv;
@@ -565,7 +570,7 @@ hipError_t launch_pix_rhs(const crsht_plan* P, int nrhs, const double* ninv, con
 hipError_t launch_rhs_finish(const crsht_plan* P, int nrhs, const double2* raw, const double2* w0, double2* out,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_rhs_finish, dim3(nblocks(P->g.nalm)), dim3(kVecBlock), 0, s, P->g.nalm, nrhs, P->t.idx_m,
-                     P->w.bk, P->w.sinvhalf, raw, w0, out);
+                     P->w.bk, P->w.sinvhalf, P->w.camp, raw, w0, out);
   return hipGetLastError();
 }
 
@@ -606,7 +611,7 @@ hipError_t launch_cg_q(const crsht_plan* P, int nrhs, const double2* p, const do
                        hipStream_t s, bool prior) {
   const int nb = vec_reduce_blocks(P);
   hipLaunchKernelGGL(k_cg_q, dim3(nb, nrhs), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_m,
-                     prior ? P->w.sinv : nullptr, P->w.bk, p, raw, q, P->w.partial, P->w.npart);
+                     prior ? P->w.sinv : nullptr, P->w.camp, P->w.bk, p, raw, q, P->w.partial, P->w.npart);
   return hipGetLastError();
 }
 

@@ -70,3 +70,33 @@ def test_strerror(lib):
     assert lib.crsht_strerror(0) == b"success"
     assert b"invalid" in lib.crsht_strerror(-1)
     assert lib.crsht_strerror(12345) == b"unknown status"
+
+
+def test_binding_struct_layouts_match_header(tmp_path):
+    # every struct the binding passes through the boundary has the size and
+    # field offsets the C compiler gives the header's declaration
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    from paper_2306_15511_amd import crsht
+    pairs = {"crsht_info": crsht._Info, "cr_problem": crsht._Problem, "cr_opts": crsht._Opts,
+             "cr_stats": crsht._Stats, "cr_chain": crsht._Chain, "cr_draws": crsht._Draws,
+             "cr_step_out": crsht._StepOut, "cr_gibbs_out": crsht._GibbsOut, "cr_bin_chain": crsht._BinChain,
+             "cr_hmc_draws": crsht._HmcDraws, "cr_hmc_out": crsht._HmcOut}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "crsht.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append('  printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            lines.append('  printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    for cname, py in pairs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert int(got["%s.%s" % (cname, fname)]) == getattr(py, fname).offset, (cname, fname)

@@ -132,3 +132,54 @@ def test_invalid_spectrum_rejected():
     with pytest.raises(m.CrshtError):
         m.solve(plan, gp, tc(d))
     _ = math, healpix
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_column_amplitudes(prec):
+    # per-column amplitudes (column c with C_l amp[c]): right-hand side and
+    # operator of every column against the oracle's problem at amp[c] C_l;
+    # solves (Jacobi, and the block preconditioner built at C_l) against the
+    # dense Cholesky solution at amp[c] C_l; the same columns without amp
+    # unchanged; a chain call given amplitudes is rejected
+    m = _m()
+    nside = 8
+    print("case column amplitudes", prec, flush=True)
+    wl, P, op, d = masked_problem(nside)
+    amp = np.array([0.8, 1.0, 1.25])
+    plan = m.Plan(nside, wl.lmax, nrhs_max=3)
+    gp = m.Problem(P.cl, P.bl, tc(P.ninv), P.lmin, amp)
+    rng = np.random.default_rng(21)
+    W0 = np.stack([ci.white_alm(rng, wl.lmax) for _ in range(3)])
+    W1 = np.stack([rng.standard_normal(P.ninv.size) for _ in range(3)])
+    D3 = np.stack([d, 0.5 * d, -d])
+    ops = [cr.CROperator(cr.Problem(nside, wl.lmax, P.cl * a, P.bl, P.ninv, P.lmin)) for a in amp]
+    Dd = dense.DenseY(nside, wl.lmax, lmin=2)
+    if prec == "f64":
+        got = m.rhs(plan, gp, tc(D3), tc(W0), tc(W1), nrhs=3).cpu().numpy()
+        X = np.stack([ci.white_alm(rng, wl.lmax) for _ in range(3)])
+        ax = m.apply(plan, gp, tc(X)).cpu().numpy()
+        for c in range(3):
+            assert rel(got[c], ops[c].rhs(D3[c], W0[c], W1[c])) < TOL
+            assert rel(ax[c], ops[c].apply(X[c])) < TOL
+    pr = m.CR_F64 if prec == "f64" else m.CR_MIXED
+    tol = 1e-12 if prec == "f64" else 1e-8
+    m.block_precond_build(plan, _gpu_problem(m, P))
+    for pc in (m.CR_PC_JACOBI, m.CR_PC_BLOCK):
+        s, st = m.solve(plan, gp, tc(D3), tc(W0), tc(W1), nrhs=3, tol=tol, prec=pr, precond=pc, max_refine=50)
+        print("precond", pc, "iters", [x.iters for x in st], flush=True)
+        for c in range(3):
+            ref = Dd.cr_solve(P.cl * amp[c], P.bl, P.ninv, ops[c].rhs(D3[c], W0[c], W1[c]))
+            assert st[c].status == 0
+            assert real_rel(ops[c], s.cpu().numpy()[c], ref) < (1e-9 if prec == "f64" else 1e-6)
+            x = s.cpu().numpy()[c]
+            assert real_rel(ops[c], ops[c].apply(x), ops[c].rhs(D3[c], W0[c], W1[c])) <= 1.5 * tol
+    # without amplitudes: every column at C_l
+    s0, _ = m.solve(plan, _gpu_problem(m, P), tc(D3), tc(W0), tc(W1), nrhs=3, tol=1e-12)
+    ref = Dd.cr_solve(P.cl, P.bl, P.ninv, op.rhs(D3[2], W0[2], W1[2]))
+    assert real_rel(op, s0.cpu().numpy()[2], ref) < 1e-9
+    ch = m.Chain(1.0, 0.0, tc(W0[0]), tc(W0[1]))
+    with pytest.raises(RuntimeError):
+        m.joint_step(plan, gp, tc(d), ch, 0.1, 0.5, tc(W0[0]), tc(W1[0]))
+    with pytest.raises(RuntimeError):
+        m.solve(plan, m.Problem(P.cl, P.bl, tc(P.ninv), P.lmin, np.array([1.0, -1.0, 1.0])), tc(D3), tc(W0),
+                tc(W1), nrhs=3, tol=1e-8)

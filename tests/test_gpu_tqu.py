@@ -355,3 +355,26 @@ def test_tqu_nside1024_16_columns_sampled():
     print("block preconditioner symmetry", e1, e2, "positivity", ex, flush=True)
     assert abs(e1 - e2) <= 1e-5 * math.sqrt(abs(ex) * abs(float(torch.sum(mw * (u.real * pu.real + u.imag * pu.imag)))))
     assert ex > 0
+
+
+def test_tqu_column_amplitudes():
+    # T+Q+U columns at amp[c] times all four spectra: solve against the
+    # oracle's PCG on the scaled problem
+    m = _m()
+    nside = 4
+    print("case tqu column amplitudes", flush=True)
+    wl, P, op = _problem(nside, 11)
+    amp = np.array([0.7, 1.4])
+    plan = m.Plan(nside, P.lmax, nrhs_max=2, ncomp=3)
+    gp = m.Problem(np.ascontiguousarray(P.cl), P.bl, tc(np.stack([P.ninv_t, P.ninv_p, P.ninv_p])), P.lmin, amp)
+    rng = np.random.default_rng(12)
+    d = np.stack([_data(rng, op, P) for _ in range(2)])
+    w0 = np.stack([np.stack([ci.white_alm(rng, P.lmax) for _ in range(3)]) for _ in range(2)])
+    w1 = rng.standard_normal((2, 3, op.sht.npix))
+    s, st = m.solve(plan, gp, tc(d), tc(w0), tc(w1), nrhs=2, tol=1e-13, maxiter=5000)
+    for c in range(2):
+        Pc = cr_tqu.ProblemTQU(nside, P.lmax, P.cl * amp[c], P.bl, P.ninv_t, P.ninv_p, P.lmin)
+        oc = cr_tqu.CROperatorTQU(Pc)
+        xo, info = cr.pcg(oc, oc.rhs(d[c], w0[c], w1[c]), 1e-13, 5000)
+        assert info.converged and st[c].status == 0
+        assert real_rel3(oc, s.cpu().numpy()[c], xo) < TOL
