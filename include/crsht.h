@@ -78,7 +78,12 @@ typedef struct crsht_plan crsht_plan;
  *   parts, and each product is formed as hi*hi + hi*lo + lo*hi on the matrix
  *   cores with float32 accumulation (relative error about 5e-6 per transform).
  *   Ring FFTs, CG vectors, dot products and scalars stay float64. In cr_solve
- *   it is the inner operator of float64 iterative refinement. */
+ *   it is the inner operator of float64 iterative refinement.
+ *   T+Q+U plans: Q and U come from Legendre sums that cancel near the poles
+ *   and are divided by sin^2(theta) (up to 1.6e6 on the first ring at Nside
+ *   1024), which amplifies the rounding of the mixed sums by as much; at
+ *   Nside >= 1024 the mixed solve does not reach 1e-6 (the inner iteration
+ *   stalls near 1e-4 and some columns diverge): use CR_F64 there. */
 typedef enum { CR_F64 = 0, CR_MIXED = 1 } cr_prec;
 
 /* Preconditioner of cr_solve (cr_opts.precond). */
@@ -234,6 +239,9 @@ int cr_apply(const crsht_plan *plan, const cr_problem *prob, int nrhs, const dou
  * field of eq. mean-field-map, w0 and w1 only the fluctuation of eq. fluc-map),
  * unless rhs is non-NULL (device [nrhs][nalm]), which is used as b directly.
  * s_out: device [nrhs][nalm]. stats: host, nrhs entries.
+ * With the environment variable CRSHT_PROGRESS = k > 0, every k-th host
+ * convergence check prints the iteration count and the largest recursive
+ * residual of the open columns to stderr (long solves).
  * Blocks until the solve has finished on `stream`. */
 int cr_solve(const crsht_plan *plan, const cr_problem *prob, int nrhs, const double *d, const double *w0,
              const double *w1, const double *rhs, double *s_out, const cr_opts *opts, cr_stats *stats,

@@ -7,6 +7,8 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <thread>
@@ -336,6 +338,35 @@ int read_scalars(const crsht_plan* P, int nrhs, hipStream_t s) {
   return CR_OK;
 }
 
+// Progress of long solves: with the environment variable CRSHT_PROGRESS set
+// to a positive integer k, every k-th host check of a PCG loop prints the
+// iteration count and the largest recursive residual of the unfinished
+// columns to stderr (read from the scalars the check has just copied back).
+int progress_every() {
+  static const int k = [] {
+    const char* e = std::getenv("CRSHT_PROGRESS");
+    const int v = e ? std::atoi(e) : 0;
+    return v > 0 ? v : 0;
+  }();
+  return k;
+}
+
+void report_progress(const crsht_plan* P, int nrhs, int it, int check, const char* what) {
+  const int k = progress_every();
+  if (k == 0 || check % k != 0) return;
+  double worst = 0.0;
+  int open = 0;
+  for (int c = 0; c < nrhs; ++c) {
+    const double* sc = P->w.host_scal + c * kScalSlots;
+    if (sc[S_DONE] != 0.0) continue;
+    ++open;
+    worst = std::max(worst, sc[S_REL]);
+  }
+  std::fprintf(stderr, "crsht %s: iteration %d, %d of %d columns open, largest recursive residual %.3e\n", what,
+               it, open, nrhs, worst);
+  std::fflush(stderr);
+}
+
 int write_scalars(const crsht_plan* P, int nrhs, hipStream_t s) {
   CR_TRY(hipMemcpyAsync(P->w.scal, P->w.host_scal, (size_t)nrhs * kScalSlots * sizeof(double),
                         hipMemcpyHostToDevice, s));
@@ -401,7 +432,7 @@ int pcg_run(const crsht_plan* P, int nrhs, const double* ninv, const double2* b,
   CR_CHECK(read_scalars(P, nrhs, s));
 
   rel.assign(nrhs, 0.0);
-  int it = 0;
+  int it = 0, checks = 0;
   for (;;) {
     bool all_done = true;
     for (int c = 0; c < nrhs; ++c) all_done &= P->w.host_scal[c * kScalSlots + S_DONE] != 0.0;
@@ -426,6 +457,7 @@ int pcg_run(const crsht_plan* P, int nrhs, const double* ninv, const double2* b,
       }));
       it += n;
       CR_CHECK(read_scalars(P, nrhs, s));
+      report_progress(P, nrhs, it, ++checks, "pcg");
       continue;
     }
     if (!verify) {
@@ -511,7 +543,7 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
   CR_CHECK(read_scalars(P, nrhs, s));
   std::vector<double> last(nrhs, 1.0);   // true relative residual at the last replacement
   rel.assign(nrhs, 1.0);
-  int it = 0, nrep = 0;
+  int it = 0, nrep = 0, checks = 0;
   bool pending = false;                  // direction update of the last iteration not yet applied
   for (;;) {
     bool need = false;
@@ -591,6 +623,7 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
     pending = true;
     it += n;
     CR_CHECK(read_scalars(P, nrhs, s));
+    report_progress(P, nrhs, it, ++checks, "mixed pcg");
   }
   iters.assign(nrhs, 0);
   broke.assign(nrhs, 0);

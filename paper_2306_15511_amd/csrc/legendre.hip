@@ -352,7 +352,10 @@ __global__ __launch_bounds__(kAdjBlock) void k_legendre_adj(
 // over up to 8 complex columns. The G operands of the wavefront's 128 pairs
 // stay in registers for the whole m. After both subsets the 8 wavefronts'
 // 16 x 16 tiles are summed through LDS in a fixed order (deterministic) and
-// the 32 l-steps x ncols results written. All products and sums are FP64.
+// the 32 l-steps x ncols results written. A block covers kAmPairs ring pairs
+// from p_off; grids with more pairs take one launch per kAmPairs, the later
+// ones adding to what the earlier wrote (accumulate = 1), in launch order.
+// All products and sums are FP64.
 // FP64 MFMA 16x16x4 lane layout: A[i][k] in lane i + 16 k, B[k][j] in lane
 // j + 16 k, D[i][j] in lane j + 16 (i % 4), register i / 4.
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
@@ -363,9 +366,10 @@ constexpr int kAmCols = 8;       // complex columns per launch (16 real MFMA col
 constexpr int kAmPairs = kAmWaves * 128;   // ring pairs one block covers
 
 __global__ __launch_bounds__(kAmWaves * 64) void k_legendre_adj_mfma(
-    int lmax, int mmax, int npairs, int ncols, const double* __restrict__ pair_z, const double* __restrict__ alpha,
-    const int* __restrict__ lst_g, const double2* __restrict__ lst_s, const int64_t* __restrict__ mstart,
-    const double2* __restrict__ geo, int64_t geo_stride, double2* __restrict__ out, int64_t out_stride) {
+    int lmax, int mmax, int npairs, int p_off, int accumulate, int ncols, const double* __restrict__ pair_z,
+    const double* __restrict__ alpha, const int* __restrict__ lst_g, const double2* __restrict__ lst_s,
+    const int64_t* __restrict__ mstart, const double2* __restrict__ geo, int64_t geo_stride, double2* __restrict__ out,
+    int64_t out_stride) {
   extern __shared__ double am_lds[];   // [kAmWaves][64][kAmRow]
   const int m = block_to_m(blockIdx.x);
   if (m > mmax) return;
@@ -380,7 +384,7 @@ __global__ __launch_bounds__(kAmWaves * 64) void k_legendre_adj_mfma(
   int wmin = kNever;
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    const int p = 128 * w + 64 * u + lane;
+    const int p = p_off + 128 * w + 64 * u + lane;
     const bool ok = p < npairs;
     const int pp = ok ? p : 0;
     const size_t o = (size_t)m * npairs + pp;
@@ -399,7 +403,7 @@ __global__ __launch_bounds__(kAmWaves * 64) void k_legendre_adj_mfma(
   for (int u = 0; u < 2; ++u)
 #pragma unroll
     for (int sk = 0; sk < 16; ++sk) {
-      const int p = 128 * w + 64 * u + 4 * sk + kq;
+      const int p = p_off + 128 * w + 64 * u + 4 * sk + kq;
       const bool ok = p < npairs && col < ncols;
       const double* g =
           reinterpret_cast<const double*>(geo + (ok ? col : 0) * geo_stride + ((size_t)(ok ? p : 0) * (mmax + 1) + m) * 2);
@@ -464,7 +468,8 @@ __global__ __launch_bounds__(kAmWaves * 64) void k_legendre_adj_mfma(
         double sum = 0.0;
 #pragma unroll
         for (int ww = 0; ww < kAmWaves; ++ww) sum += am_lds[(size_t)ww * 64 * kAmRow + idx];
-        reinterpret_cast<double*>(out + c * out_stride + base + stp)[rr] = sum;
+        double* o = reinterpret_cast<double*>(out + c * out_stride + base + stp) + rr;
+        *o = accumulate ? *o + sum : sum;
       }
     }
     __syncthreads();   // the rows are rewritten by the next chunk
@@ -678,18 +683,20 @@ hipError_t launch_legendre_adjoint(const crsht_plan* P, int nrhs, const double2*
   hipError_t err = hipSuccess;
   if (diag) {
     err = adj_pass<1>(P, nullptr, raw, true, s);
-  } else if (nrhs >= 2 && P->g.npairs <= kAmPairs) {
-    // FP64 matrix cores, 8 columns per launch
+  } else if (nrhs >= 2) {
+    // FP64 matrix cores, 8 columns and kAmPairs ring pairs per launch
     const Geometry& g = P->g;
     const int64_t geo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
     const int nb = ((g.mmax + 1 + 31) / 32) * 32;
     const size_t lds = (size_t)kAmWaves * 64 * kAmRow * sizeof(double);
     for (int c0 = 0; c0 < nrhs && err == hipSuccess; c0 += kAmCols) {
       const int nc = std::min(kAmCols, nrhs - c0);
-      hipLaunchKernelGGL(k_legendre_adj_mfma, dim3(nb), dim3(kAmWaves * 64), lds, s, g.lmax, g.mmax, g.npairs, nc,
-                         P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
-                         geo + (int64_t)c0 * geo_stride, geo_stride, raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm);
-      err = hipGetLastError();
+      for (int p0 = 0; p0 < g.npairs && err == hipSuccess; p0 += kAmPairs) {
+        hipLaunchKernelGGL(k_legendre_adj_mfma, dim3(nb), dim3(kAmWaves * 64), lds, s, g.lmax, g.mmax, g.npairs, p0,
+                           p0 > 0 ? 1 : 0, nc, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
+                           geo + (int64_t)c0 * geo_stride, geo_stride, raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm);
+        err = hipGetLastError();
+      }
     }
   } else {
     const int64_t geo_stride = (int64_t)P->g.npairs * (P->g.mmax + 1) * 2;

@@ -126,3 +126,32 @@ def test_invalid_arguments():
     with pytest.raises(m.CrshtError):
         m.synth(plan, a[:plan.nalm], prec=7)   # unknown precision
     _ = math
+
+
+def test_nside1024_adjoint_matrix_cores_two_pair_launches():
+    # Nside 1024 has 2048 ring pairs: the FP64 matrix-core adjoint (two or
+    # more columns) covers them in two launches, the second adding to the
+    # first. Against the single-column vector kernel, column by column, and
+    # adjointness with the synthesis of the same columns
+    m = _mod()
+    nside, lmax, n = 1024, 2047, 3
+    print("case nside1024 adjoint, 3 columns", flush=True)
+    plan = m.Plan(nside, lmax, nrhs_max=n)
+    rng = np.random.default_rng(1025)
+    npix = 12 * nside * nside
+    y = torch.from_numpy(rng.standard_normal((n, npix))).to("cuda:0")
+    got = m.adjoint(plan, y)
+    for c in range(n):
+        one = m.adjoint(plan, y[c:c + 1].contiguous())
+        e = float(torch.linalg.vector_norm(got[c] - one[0]) / torch.linalg.vector_norm(one[0]))
+        print("column", c, "matrix cores vs vector kernel", e, flush=True)
+        assert e < 1e-12
+    a = np.stack([ci.white_alm(rng, lmax) for _ in range(n)])
+    ls, ms = ci.alm_lm_arrays(lmax)
+    w = torch.from_numpy(np.where(ms == 0, 1.0, 2.0)).to("cuda:0")
+    da = tc(a)
+    sx = m.synth(plan, da)
+    for c in range(n):
+        lhs = float(torch.sum(sx[c] * y[c]))
+        rhs = float(torch.sum(w * (da[c].real * got[c].real + da[c].imag * got[c].imag)))
+        assert abs(lhs - rhs) <= 1e-12 * float(torch.linalg.vector_norm(sx[c])) * float(torch.linalg.vector_norm(y[c]))
