@@ -50,8 +50,8 @@ TRAFFIC = {
     "k_adj_mfma": {"bytes": 959896629, "src": "3c89991f0fac5560"},
     "k_synth_mfma": {"bytes": 1324395064, "src": "3c89991f0fac5560"},
     "k_ring<RING_FUSED>": {"bytes": 4 * 212896371, "src": "664ab76c607be629"},   # one fused pass (4 class launches)
-    "k_legendre_synth_mfma": {"bytes": 679984546, "src": "941a101a7a3fe1b5"},    # one launch of 8 columns
-    "k_legendre_adj_mfma": {"bytes": 2 * 606666377, "src": "941a101a7a3fe1b5"},  # one transform (2 launches)
+    "k_legendre_synth_mfma": {"bytes": 680437984, "src": "34e5a8a115b9d7fc"},    # one launch of 8 columns
+    "k_legendre_adj_mfma": {"bytes": 2 * 606571360, "src": "34e5a8a115b9d7fc"},  # one transform (2 launches)
     "k_pc_apply": {"bytes": 3539768550, "src": "53b332e687b51ce1"},
 }
 

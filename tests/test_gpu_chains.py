@@ -220,3 +220,15 @@ def test_hmc_chain_driver_replays_oracle():
     summ = run.summary()
     print(summ, flush=True)
     assert summ["steps"] == 3 and summ["bins"] == 2 and 0.0 <= summ["acceptance"] <= 1.0
+    # the step guide: widths of the target along each bin from the curvature
+    # of ln pi at a fixed fluctuation, against the oracle's second difference
+    sig = chains.curvature_scale(plan, gp, tc(d), ch, tol=tol)
+    h = 1e-3
+    for k in range(2):
+        e = np.zeros(2)
+        e[k] = h
+        g0 = joint.lnpi_grad_fixed(P, d, edges, st.theta, st.theta, st.fhat, tol)[1][k]
+        g1 = joint.lnpi_grad_fixed(P, d, edges, st.theta, st.theta + e, st.fhat, tol)[1][k]
+        ref = 1.0 / math.sqrt(-(g1 - g0) / h)
+        print("width bin %d gpu %.6e oracle %.6e" % (k, sig[k], ref), flush=True)
+        assert abs(sig[k] - ref) <= 1e-5 * ref
