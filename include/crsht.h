@@ -221,6 +221,18 @@ int cr_block_precond_build(crsht_plan *plan, const cr_problem *prob, void *strea
  * CR_EINVAL if none is built. Asynchronous. */
 int cr_block_precond_apply(const crsht_plan *plan, int nrhs, const double *r, double *z, void *stream);
 
+/* Unit Gaussian white draws for the random terms of eq. mapmakingeq on the
+ * device: w0 (device [nrhs][ncomp][nalm]) gets white a_lm of a real field
+ * (Re and Im of N(0, 1/2) for m > 0, real N(0, 1) for m = 0), w1 (device
+ * [nrhs][ncomp][npix]) standard normal pixels; either may be NULL, not both.
+ * Philox4x32-10 (Salmon et al. 2011) keyed by `seed`, with counter words
+ * (element, column | purpose << 31, counter lo, counter hi): every value
+ * depends only on (seed, counter, column, element), and w0 and w1 of one call
+ * are independent. Two standard normals per generator block by the
+ * Box-Muller transform of two 53-bit uniforms. Asynchronous. */
+int cr_white(const crsht_plan *plan, int nrhs, uint64_t seed, uint64_t counter, double *w0, double *w1,
+             void *stream);
+
 /* Right-hand side of eq. mapmakingeq: b = B Y^T N^-1 d + S^-1/2 w0 + B Y^T N^-1/2 w1,
  * restricted to l >= lmin. d, w1: device maps [nrhs][npix]; w0: device alm
  * [nrhs][nalm]; any of the three may be NULL (term omitted). b: device
@@ -307,6 +319,22 @@ typedef struct {
  * `out` is host. Blocks until done. */
 int joint_cl_step(const crsht_plan *plan, const cr_problem *fid, const double *d, cr_chain *state,
                   const cr_draws *draws, const cr_opts *opts, cr_step_out *out, void *stream);
+
+/* The joint move of joint_cl_step for nchains chains at once, sharing the
+ * data d: the mean fields at every chain's proposal q'_c = q_c exp(sigma_lnq
+ * xi[c]) are the columns of one solve (per-column amplitudes, each warm-started
+ * from the chain's mean field; the solve runs to the strictest column's
+ * correction tolerance), and the fresh fluctuations of the chains that accept
+ * are the columns of a second solve from w0, w1 (solved for every chain when
+ * any accepts; the columns of rejected chains are discarded). The decision of
+ * chain c is ln u[c] < ln A_c with ln A as in joint_cl_step. states: host
+ * [nchains], updated in place like joint_cl_step's state; xi, u: host
+ * [nchains]; w0: device [nchains][nalm]; w1: device [nchains][npix] (either
+ * may be NULL, not both); out: host [nchains]. nchains <= nrhs_max of the
+ * plan; fid->amp must be NULL. Temperature plans only. Blocks until done. */
+int joint_cl_step_batch(const crsht_plan *plan, const cr_problem *fid, const double *d, int nchains,
+                        cr_chain *states, const double *xi, const double *u, double sigma_lnq, const double *w0,
+                        const double *w1, const cr_opts *opts, cr_step_out *out, void *stream);
 
 typedef struct {
   double q_new;        /* the drawn amplitude */

@@ -104,15 +104,56 @@ def default_draws(kind: str, lmax: int, npix: int, alpha: float, sigma_lnq: floa
     return draw
 
 
+def device_draws(plan: crsht.Plan, kind: str, alpha: Optional[float] = None, seed: int = 0, nbins: int = 1):
+    """Like default_draws, with w0 and w1 drawn on the device (crsht.white:
+    Philox4x32-10 keyed by seed and chain, counter = step); the scalars (xi,
+    u; g; p0, u for kind "hmc") from a numpy Generator per chain."""
+    rngs = {}
+
+    def draw(chain: int, step: int) -> dict:
+        rng = rngs.setdefault(chain, np.random.default_rng([seed, chain, 2]))
+        out = {}
+        if kind == "joint":
+            out["xi"] = float(rng.standard_normal())
+            out["u"] = float(rng.uniform())
+        elif kind == "gibbs":
+            out["g"] = float(rng.gamma(alpha))
+        else:
+            out["p0"] = rng.standard_normal(nbins)
+            out["u"] = float(rng.uniform())
+        w0, w1 = crsht.white(plan, 1, (seed << 24) + chain, step)
+        out["w0"], out["w1"] = w0[0], w1[0]
+        return out
+
+    return draw
+
+
+def _on(x, dev) -> torch.Tensor:
+    if isinstance(x, torch.Tensor):
+        return x.to(dev)
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def _stack(xs, dev) -> torch.Tensor:
+    if isinstance(xs[0], torch.Tensor):
+        return torch.stack([x.to(dev) for x in xs]).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(np.stack(xs))).to(dev)
+
+
 def run_chains(plan: crsht.Plan, fid: crsht.Problem, d: torch.Tensor, chains: list, nsteps: int,
                kind: str = "joint", sigma_lnq: float = 0.02, seed: int = 0, burn: int = 0,
-               draw: Optional[Callable[[int, int], dict]] = None, **solve_kw) -> ChainRun:
+               draw: Optional[Callable[[int, int], dict]] = None, batched: bool = False, **solve_kw) -> ChainRun:
     """Advance every chain (crsht.Chain, updated in place) by nsteps moves of
     the joint sampler (kind "joint", Gaussian proposal of width sigma_lnq in
     ln q) or of the standard Gibbs sampler (kind "gibbs"). draw(chain, step)
-    returns that move's random numbers (default: default_draws)."""
+    returns that move's random numbers (default: default_draws). batched
+    (joint moves): every step moves all chains in one joint_cl_step_batch call
+    (the chains' solves as the columns of one solve; len(chains) <=
+    nrhs_max of the plan)."""
     if kind not in ("joint", "gibbs"):
         raise ValueError("kind must be 'joint' or 'gibbs'")
+    if batched and kind != "joint":
+        raise ValueError("batched moves are joint moves")
     n = len(chains)
     alpha = crsht.gibbs_shape(plan.lmax, fid.lmin)
     if draw is None:
@@ -125,10 +166,22 @@ def run_chains(plan: crsht.Plan, fid: crsht.Problem, d: torch.Tensor, chains: li
     for c, ch in enumerate(chains):
         q[c, 0] = ch.q
     for s in range(nsteps):
+        if batched:
+            rs = [draw(c, s) for c in range(n)]
+            w0 = _stack([r["w0"] for r in rs], dev)
+            w1 = _stack([r["w1"] for r in rs], dev)
+            res = crsht.joint_step_batch(plan, fid, d, chains, [r["xi"] for r in rs], [r["u"] for r in rs], w0, w1,
+                                         sigma_lnq=sigma_lnq, **solve_kw)
+            for c, ch in enumerate(chains):
+                acc[c, s] = res[c].accepted
+                mi[c, s] = res[c].mean_stats.iters
+                fi[c, s] = res[c].fluct_stats.iters
+                q[c, s + 1] = ch.q
+            continue
         for c, ch in enumerate(chains):
             r = draw(c, s)
-            w0 = torch.from_numpy(np.ascontiguousarray(r["w0"])).to(dev)
-            w1 = torch.from_numpy(np.ascontiguousarray(r["w1"])).to(dev)
+            w0 = _on(r["w0"], dev)
+            w1 = _on(r["w1"], dev)
             if kind == "joint":
                 res = crsht.joint_step(plan, fid, d, ch, r["xi"], r["u"], w0, w1, sigma_lnq=sigma_lnq, **solve_kw)
                 acc[c, s] = res.accepted
@@ -231,8 +284,8 @@ def run_hmc(plan: crsht.Plan, fid: crsht.Problem, d: torch.Tensor, chains: list,
     for s in range(nsteps):
         for c, ch in enumerate(chains):
             r = draw(c, s)
-            w0 = torch.from_numpy(np.ascontiguousarray(r["w0"])).to(dev)
-            w1 = torch.from_numpy(np.ascontiguousarray(r["w1"])).to(dev)
+            w0 = _on(r["w0"], dev)
+            w1 = _on(r["w1"], dev)
             res = crsht.hmc_step(plan, fid, d, ch, r["p0"], r["u"], w0, w1, eps, nleap, **solve_kw)
             acc[c, s], dh[c, s], sv[c, s], it[c, s] = res.accepted, res.dH, res.solves, res.iters
             fi[c, s] = res.fluct_stats.iters
@@ -242,4 +295,4 @@ def run_hmc(plan: crsht.Plan, fid: crsht.Problem, d: torch.Tensor, chains: list,
 
 
 __all__ = ["white_alm", "integrated_autocorr_time", "scaled", "init_chain", "ChainRun", "default_draws",
-           "run_chains", "bin_scaled", "init_bin_chain", "curvature_scale", "HmcRun", "default_hmc_draws", "run_hmc"]
+           "run_chains", "device_draws", "bin_scaled", "init_bin_chain", "curvature_scale", "HmcRun", "default_hmc_draws", "run_hmc"]

@@ -120,6 +120,10 @@ def _load():
                                 ctypes.POINTER(ctypes.c_double), vp, ctypes.POINTER(_Stats), vp], i),
         "hmc_cl_step": ([P, ctypes.POINTER(_Problem), vp, ctypes.POINTER(_BinChain), ctypes.POINTER(_HmcDraws),
                          ctypes.POINTER(_Opts), ctypes.POINTER(_HmcOut), vp], i),
+        "cr_white": ([P, i, ctypes.c_uint64, ctypes.c_uint64, vp, vp, vp], i),
+        "joint_cl_step_batch": ([P, ctypes.POINTER(_Problem), vp, i, ctypes.POINTER(_Chain),
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), d, vp, vp,
+                                 ctypes.POINTER(_Opts), ctypes.POINTER(_StepOut), vp], i),
         "gibbs_cl_step": ([P, ctypes.POINTER(_Problem), vp, ctypes.POINTER(_Chain), d, vp, vp,
                            ctypes.POINTER(_Opts), ctypes.POINTER(_GibbsOut), vp], i),
         "cr_solve_batched": ([ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(_Problem), i,
@@ -145,7 +149,7 @@ _lib = _load()
 
 EXPORTED = ("crsht_plan_create", "crsht_plan_destroy", "crsht_strerror", "crsht_plan_info", "crsht_pixel_coords",
             "sht_synth", "sht_synth_adjoint", "sht_analysis", "cr_precond", "cr_rhs", "cr_apply", "cr_solve",
-            "cr_lnpi", "joint_cl_step", "gibbs_cl_step", "hmc_cl_step", "cr_lnpi_grad_fixed",
+            "cr_white", "cr_lnpi", "joint_cl_step", "joint_cl_step_batch", "gibbs_cl_step", "hmc_cl_step", "cr_lnpi_grad_fixed",
             "cr_solve_batched", "sht_synth_grad", "cr_grad_chi2", "cr_grad_lnpi",
             "cr_block_precond_build", "cr_block_precond_apply", "crsht_timing_enable", "crsht_timing_read")
 
@@ -432,6 +436,49 @@ def joint_step(plan: Plan, fid: Problem, d: torch.Tensor, chain: Chain, xi: floa
     return StepResult(bool(r.accepted), r.lnA, r.q_new, r.lnpi_new, st(r.mean_stats), st(r.fluct_stats))
 
 
+def white(plan: Plan, nrhs: int, seed: int, counter: int, alm: bool = True, pix: bool = True,
+          device: torch.device | None = None):
+    """(w0 [nrhs, (3,) nalm] complex, w1 [nrhs, (3,) npix]) unit white draws on
+    the device (cr_white); either is None when not asked for."""
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    w0 = torch.empty(plan.alm_shape(nrhs), dtype=torch.complex128, device=dev) if alm else None
+    shape = (nrhs, 3, plan.npix) if plan.ncomp == 3 else (nrhs, plan.npix)
+    w1 = torch.empty(shape, dtype=torch.float64, device=dev) if pix else None
+    _check(_lib.cr_white(plan.handle, nrhs, seed & (2 ** 64 - 1), counter & (2 ** 64 - 1), _ptr(w0), _ptr(w1),
+                         _stream()), "cr_white")
+    return w0, w1
+
+
+def joint_step_batch(plan: Plan, fid: Problem, d: torch.Tensor, chains: list, xi, u, w0: torch.Tensor,
+                     w1: torch.Tensor, sigma_lnq: float = 0.02, tol: float = 1e-6, maxiter: int = 10000,
+                     prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 50, use_graph: bool = True,
+                     precond: int = CR_PC_JACOBI) -> list:
+    """Joint moves of several chains at once (joint_cl_step_batch); w0
+    [n, nalm] and w1 [n, npix] on the device; every chain updated in place."""
+    n = len(chains)
+    p = fid._c()
+    arr = (_Chain * n)(*[_Chain(c.q, c.lnpi, _ptr(c.ahat), _ptr(c.fhat)) for c in chains])
+    x, uu = _f64(xi), _f64(u)
+    if x.size != n or uu.size != n:
+        raise ValueError("xi and u need one entry per chain")
+    dp = ctypes.POINTER(ctypes.c_double)
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, 8, int(precond), int(use_graph))
+    outs = (_StepOut * n)()
+    _check(_lib.joint_cl_step_batch(plan.handle, ctypes.byref(p), _ptr(d), n, arr, x.ctypes.data_as(dp),
+                                    uu.ctypes.data_as(dp), sigma_lnq, _ptr(w0), _ptr(w1), ctypes.byref(o), outs,
+                                    _stream()), "joint_cl_step_batch")
+
+    def st(s_):
+        return Stats(s_.status, s_.iters, s_.refinements, s_.rel_resid_true)
+
+    res = []
+    for c, ch in enumerate(chains):
+        ch.q, ch.lnpi = arr[c].q, arr[c].lnpi
+        r = outs[c]
+        res.append(StepResult(bool(r.accepted), r.lnA, r.q_new, r.lnpi_new, st(r.mean_stats), st(r.fluct_stats)))
+    return res
+
+
 @dataclass
 class GibbsResult:
     q_new: float
@@ -613,7 +660,7 @@ def nalm(lmax: int, mmax: int | None = None) -> int:
 
 __all__ = ["Plan", "Problem", "Stats", "Chain", "StepResult", "synth", "adjoint", "analysis", "precond", "rhs",
            "block_precond_build", "block_precond_apply", "CR_PC_JACOBI", "CR_PC_BLOCK",
-           "apply", "solve", "solve_batched", "lnpi", "joint_step", "gibbs_step", "gibbs_shape", "GibbsResult",
+           "apply", "solve", "solve_batched", "lnpi", "white", "joint_step", "joint_step_batch", "gibbs_step", "gibbs_shape", "GibbsResult",
            "BinChain", "HmcResult", "lnpi_grad_fixed", "hmc_step", "synth_grad", "synth_ad", "SynthFunction", "grad_chi2", "grad_lnpi",
            "CR_F64", "CR_MIXED", "CrshtError", "strerror", "EXPORTED"]
 _ = math

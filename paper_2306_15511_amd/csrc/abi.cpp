@@ -635,10 +635,11 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
   return CR_OK;
 }
 
-// x0 (device, one column, optional): warm start. The solve then runs on the
-// correction, A delta = b - A x0, to the tolerance tol ||b|| / ||b - A x0||,
-// and s_out = x0 + delta; stats report the correction's iterations and the
-// residual relative to ||b||.
+// x0 (device, nrhs columns, optional; may alias s_out): warm start. The solve
+// then runs on the correction, A delta = b - A x0, to the tolerance
+// tol / max_c(||b - A x0|| / ||b||) (the strictest column's), and s_out =
+// x0 + delta; stats report the correction's iterations and the residual
+// relative to ||b||.
 int solve_core(const crsht_plan* P, const cr_problem* prob, double q, int nrhs, const double* d, const double* w0,
                const double* w1, const double* rhs, double* s_out, const cr_opts* opts, cr_stats* stats,
                hipStream_t s, const double* x0 = nullptr) {
@@ -656,23 +657,21 @@ int solve_core(const crsht_plan* P, const cr_problem* prob, double q, int nrhs, 
   else
     CR_CHECK(assemble_rhs(P, nrhs, prob->ninv, d, w0, w1, P->w.cg_b, s));
   cr_opts o = *opts;
-  double r0 = 1.0;   // ||b - A x0|| / ||b||
+  std::vector<double> r0(nrhs, 1.0);   // ||b - A x0|| / ||b|| per column
   const size_t vbytes = (size_t)nrhs * vlen(P) * sizeof(double2);
   if (x0) {
-    if (nrhs != 1) return CR_EINVAL;
-    std::vector<double> rel0;
-    CR_TRY(launch_project(P, 1, C2(x0), P->w.cg_x, s));
-    CR_CHECK(true_residual(P, 1, prob->ninv, P->w.cg_x, P->w.cg_b, P->w.cg_r, rel0, s));
-    r0 = rel0[0];
-    if (r0 <= opts->tol) {   // the start already meets the tolerance
-      std::vector<int> zi(1, 0), zb(1, 0);
-      fill_stats(1, opts->tol, zi, zi, rel0, zb, stats);
+    CR_TRY(launch_project(P, nrhs, C2(x0), P->w.cg_x, s));
+    CR_CHECK(true_residual(P, nrhs, prob->ninv, P->w.cg_x, P->w.cg_b, P->w.cg_r, r0, s));
+    const double rmax = *std::max_element(r0.begin(), r0.end());
+    if (rmax <= opts->tol) {   // the start already meets the tolerance
+      std::vector<int> zi(nrhs, 0), zb(nrhs, 0);
+      fill_stats(nrhs, opts->tol, zi, zi, r0, zb, stats);
       CR_TRY(hipMemcpyAsync(s_out, P->w.cg_x, vbytes, hipMemcpyDeviceToDevice, s));
       CR_TRY(hipStreamSynchronize(s));
       return CR_OK;
     }
     CR_TRY(hipMemcpyAsync(P->w.cg_b, P->w.cg_r, vbytes, hipMemcpyDeviceToDevice, s));
-    o.tol = opts->tol / r0 * (1.0 - 1e-12);   // (so that the rescaled residual meets tol)
+    o.tol = opts->tol / rmax * (1.0 - 1e-12);   // (so that the rescaled residuals meet tol)
   }
   std::vector<int> iters, refine, broke;
   std::vector<double> rel;
@@ -683,10 +682,10 @@ int solve_core(const crsht_plan* P, const cr_problem* prob, double q, int nrhs, 
                      o.use_graph != 0, pc));
     refine.assign(nrhs, 0);
   }
-  for (double& v : rel) v *= r0;
+  for (int c = 0; c < nrhs; ++c) rel[c] *= r0[c];
   fill_stats(nrhs, opts->tol, iters, refine, rel, broke, stats);
   if (x0)
-    CR_TRY(launch_alm_axpby(vlen(P), 1.0, C2(x0), 1.0, P->w.cg_x, C2(s_out), s));
+    CR_TRY(launch_alm_axpby((int64_t)nrhs * vlen(P), 1.0, C2(x0), 1.0, P->w.cg_x, C2(s_out), s));
   else
     CR_TRY(hipMemcpyAsync(s_out, P->w.cg_x, vbytes, hipMemcpyDeviceToDevice, s));
   CR_TRY(hipStreamSynchronize(s));
@@ -766,6 +765,14 @@ extern "C" int sht_analysis(const crsht_plan* P, int nrhs, const double* map, do
 }
 
 // ============================================================== CR system
+extern "C" int cr_white(const crsht_plan* P, int nrhs, uint64_t seed, uint64_t counter, double* w0, double* w1,
+                        void* stream) {
+  CR_CHECK(check_plan(P, nrhs));
+  if (!w0 && !w1) return CR_EINVAL;
+  CR_TRY(launch_white(P, nrhs * P->ncomp, seed, counter, reinterpret_cast<double2*>(w0), w1, S(stream)));
+  return CR_OK;
+}
+
 extern "C" int cr_precond(const crsht_plan* P, const cr_problem* prob, double* diag, void* stream) {
   CR_CHECK(check_plan(P, 1));
   if (!diag) return CR_EINVAL;
@@ -1006,6 +1013,77 @@ extern "C" int joint_cl_step(const crsht_plan* P, const cr_problem* fid, const d
   CR_CHECK(lnpi_terms(P, fid->ninv, d, P->w.alm_c, C2(state->fhat), t, s));
   state->q = qn;
   state->lnpi = -0.5 * (t[0] + t[1] + t[2]);
+  CR_TRY(hipStreamSynchronize(s));
+  return CR_OK;
+}
+
+extern "C" int joint_cl_step_batch(const crsht_plan* P, const cr_problem* fid, const double* d, int n,
+                                   cr_chain* st, const double* xi, const double* u, double sigma_lnq,
+                                   const double* w0, const double* w1, const cr_opts* opts, cr_step_out* out,
+                                   void* stream) {
+  CR_CHECK(check_plan(P, n));
+  if (P->ncomp != 1) return CR_ENOTSUP;
+  if (!fid || !d || !st || !xi || !u || !opts || !out || (!w0 && !w1)) return CR_EINVAL;
+  if (fid->amp) return CR_EINVAL;   // the move sets the columns' amplitudes itself
+  if (!(sigma_lnq > 0.0) || !std::isfinite(sigma_lnq)) return CR_EINVAL;
+  for (int c = 0; c < n; ++c) {
+    if (!st[c].ahat || !st[c].fhat || !(st[c].q > 0.0) || !std::isfinite(st[c].q) || !std::isfinite(st[c].lnpi))
+      return CR_EINVAL;
+    if (!(u[c] > 0.0 && u[c] < 1.0) || !std::isfinite(xi[c])) return CR_EINVAL;
+  }
+  hipStream_t s = S(stream);
+  Workspace const& w = P->w;
+  const int64_t na = P->g.nalm;
+  const size_t cb = (size_t)na * sizeof(double2);
+  std::memset(out, 0, (size_t)n * sizeof(cr_step_out));
+  std::vector<double> qn(n);
+  for (int c = 0; c < n; ++c) qn[c] = out[c].q_new = st[c].q * std::exp(sigma_lnq * xi[c]);
+  // 1) the data term B Y^T N^-1 d of the mean-field right-hand side does not
+  //    depend on the spectrum: one column, copied to every chain's
+  CR_CHECK(set_problem(P, fid, 1.0, s));
+  CR_CHECK(assemble_rhs(P, 1, fid->ninv, d, nullptr, nullptr, w.cg_bin, s));
+  for (int c = 1; c < n; ++c)
+    CR_TRY(hipMemcpyAsync(w.cg_bin + (size_t)c * na, w.cg_bin, cb, hipMemcpyDeviceToDevice, s));
+  // 2) mean fields at q'_c, one column per chain, warm-started from the chains' mean fields
+  for (int c = 0; c < n; ++c)
+    CR_TRY(hipMemcpyAsync(w.cg_xacc + (size_t)c * na, st[c].ahat, cb, hipMemcpyDeviceToDevice, s));
+  cr_problem pa = *fid;
+  pa.amp = qn.data();
+  std::vector<cr_stats> ms(n), fs(n);
+  CR_CHECK(solve_core(P, &pa, 1.0, n, nullptr, nullptr, nullptr, reinterpret_cast<const double*>(w.cg_bin),
+                      reinterpret_cast<double*>(w.cg_xacc), opts, ms.data(), s,
+                      reinterpret_cast<const double*>(w.cg_xacc)));
+  // 3) ln pi(q'_c) with the rescaled fluctuation, ln A, decisions. The
+  //    problem factors are those of the fiducial spectrum: the prior term is
+  //    divided by q'_c.
+  bool any = false;
+  double t[3];
+  for (int c = 0; c < n; ++c) {
+    out[c].mean_stats = ms[c];
+    CR_TRY(launch_alm_axpby(na, std::sqrt(qn[c] / st[c].q), C2(st[c].fhat), 0.0, nullptr, w.alm_d, s));
+    CR_CHECK(lnpi_terms(P, fid->ninv, d, w.cg_xacc + (size_t)c * na, w.alm_d, t, s));
+    out[c].lnpi_new = -0.5 * (t[0] + t[1] / qn[c] + t[2]);
+    out[c].lnA = out[c].lnpi_new - st[c].lnpi + std::log(qn[c] / st[c].q);
+    out[c].accepted = std::log(u[c]) < out[c].lnA ? 1 : 0;
+    any = any || out[c].accepted;
+  }
+  if (!any) return CR_OK;
+  // 4) fresh fluctuations at q'_c in one solve of every column (the columns of
+  //    rejected chains are computed alongside and discarded)
+  CR_CHECK(solve_core(P, &pa, 1.0, n, nullptr, w0, w1, nullptr, reinterpret_cast<double*>(w.cg_bin), opts, fs.data(),
+                      s));
+  // 5) accepted chains take the new mean field, fluctuation, amplitude and ln pi
+  for (int c = 0; c < n; ++c) {
+    if (!out[c].accepted) continue;
+    out[c].fluct_stats = fs[c];
+    const double2* a = w.cg_xacc + (size_t)c * na;
+    const double2* f = w.cg_bin + (size_t)c * na;
+    CR_TRY(hipMemcpyAsync(st[c].ahat, a, cb, hipMemcpyDeviceToDevice, s));
+    CR_TRY(hipMemcpyAsync(st[c].fhat, f, cb, hipMemcpyDeviceToDevice, s));
+    CR_CHECK(lnpi_terms(P, fid->ninv, d, a, f, t, s));
+    st[c].q = qn[c];
+    st[c].lnpi = -0.5 * (t[0] + t[1] / qn[c] + t[2]);
+  }
   CR_TRY(hipStreamSynchronize(s));
   return CR_OK;
 }

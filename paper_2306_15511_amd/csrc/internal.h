@@ -357,6 +357,10 @@ hipError_t launch_mweight(const crsht_plan* P, int nrhs, double2* a, hipStream_t
 hipError_t launch_bin_grad(const crsht_plan* P, int nbins, const int* edges, const double2* ahat,
                            const double2* fhat, const double2* lam, const double2* w0, double* grad,
                            hipStream_t s, int mode = 0);
+// Gaussian white draws (Philox4x32-10 + Box-Muller) of nrhs columns: w0
+// [nrhs][nalm] white a_lm of a real field, w1 [nrhs][npix]; either may be null
+hipError_t launch_white(const crsht_plan* P, int nrhs, uint64_t seed, uint64_t counter, double2* w0, double* w1,
+                        hipStream_t s);
 // out = fac_l[l] * in (one column of nalm coefficients)
 hipError_t launch_scale_per_l(const crsht_plan* P, const double2* in, const double* fac_l, double2* out,
                               hipStream_t s);

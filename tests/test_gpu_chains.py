@@ -80,13 +80,17 @@ def test_joint_mean_field_warm_start():
     assert real_rel(opn, ch.ahat.cpu().numpy(), cold[0].cpu().numpy()) < 1e-5
 
 
-@pytest.mark.parametrize("kind", ["joint", "gibbs"])
+@pytest.mark.parametrize("kind", ["joint", "gibbs", "joint_batched"])
 def test_chain_driver_replays_oracle(kind):
     from paper_2306_15511_amd import chains
     tol = 1e-12
     m, wl, P, d, plan, gp, st = _setup(8, tol)
     print("case chains", kind, flush=True)
     nchain, nsteps = 2, 4
+    batched = kind == "joint_batched"
+    kind = "joint" if batched else kind
+    if batched:
+        plan = m.Plan(8, wl.lmax, nrhs_max=nchain)
     alpha = joint.gibbs_shape(P)
     draws = {}
 
@@ -101,7 +105,8 @@ def test_chain_driver_replays_oracle(kind):
         return draws[(c, s)]
 
     gch = [_chain(m, st) for _ in range(nchain)]
-    run = chains.run_chains(plan, gp, tc(d), gch, nsteps, kind=kind, sigma_lnq=0.05, draw=draw, tol=tol)
+    run = chains.run_chains(plan, gp, tc(d), gch, nsteps, kind=kind, sigma_lnq=0.05, draw=draw, batched=batched,
+                            tol=tol)
     for c in range(nchain):
         ost = st
         for s in range(nsteps):
@@ -232,3 +237,44 @@ def test_hmc_chain_driver_replays_oracle():
         ref = 1.0 / math.sqrt(-(g1 - g0) / h)
         print("width bin %d gpu %.6e oracle %.6e" % (k, sig[k], ref), flush=True)
         assert abs(sig[k] - ref) <= 1e-5 * ref
+
+
+def test_joint_step_batch_matches_oracle():
+    # three chains at different amplitudes moved in one call: every chain's
+    # proposal, ln A, decision and new state against the oracle's joint move
+    # with the same numbers; one chain is forced to reject (u -> 1 with a
+    # large proposal), the others accept (u -> 0)
+    tol = 1e-12
+    m, wl, P, d, plan0, gp, st0 = _setup(8, tol)
+    print("case joint step batch", flush=True)
+    plan = m.Plan(8, wl.lmax, nrhs_max=3)
+    rng = np.random.default_rng(61)
+    states = []
+    for q in (0.9, 1.0, 1.2):
+        states.append(joint.init_state(P, d, q, ci.white_alm(rng, P.lmax), rng.standard_normal(P.ninv.size), tol))
+    xi = [0.3, 40.0, -0.5]
+    u = [0.5, 1.0 - 1e-12, 1e-300]
+    W0 = np.stack([ci.white_alm(rng, P.lmax) for _ in range(3)])
+    W1 = np.stack([rng.standard_normal(P.ninv.size) for _ in range(3)])
+    gch = [_chain(m, s_) for s_ in states]
+    res = m.joint_step_batch(plan, gp, tc(d), gch, xi, u, tc(W0), tc(W1), sigma_lnq=0.05, tol=tol)
+    flags = []
+    for c in range(3):
+        new, r = joint.joint_step(P, d, states[c], xi[c], u[c], W0[c], W1[c], 0.05, tol)
+        print("chain %d lnA gpu %.12e oracle %.12e accepted %s/%s iters %d/%d" % (
+            c, res[c].lnA, r.lnA, res[c].accepted, r.accepted, res[c].mean_stats.iters, res[c].fluct_stats.iters),
+            flush=True)
+        flags.append(r.accepted)
+        assert res[c].accepted == r.accepted
+        assert res[c].q_new == r.q_new
+        assert abs(res[c].lnA - r.lnA) <= 1e-7 * max(1.0, abs(states[c].lnpi))
+        assert abs(res[c].lnpi_new - r.lnpi_new) <= 1e-9 * abs(r.lnpi_new)
+        assert abs(gch[c].q - new.q) <= 1e-15 * new.q
+        assert abs(gch[c].lnpi - new.lnpi) <= 1e-9 * abs(new.lnpi)
+        opn = cr.CROperator(joint.scaled_problem(P, new.q))
+        assert real_rel(opn, gch[c].ahat.cpu().numpy(), new.ahat) < 1e-8
+        assert real_rel(opn, gch[c].fhat.cpu().numpy(), new.fhat) < 1e-8
+        assert res[c].mean_stats.status == 0
+    assert flags[1] is False and flags[2] is True
+    with pytest.raises(RuntimeError):   # more chains than the plan's columns
+        m.joint_step_batch(plan0, gp, tc(d), gch[:2], xi[:2], u[:2], tc(W0[:2]), tc(W1[:2]), tol=tol)
