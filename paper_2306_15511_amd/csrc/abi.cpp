@@ -727,6 +727,36 @@ int lnpi_terms(const crsht_plan* P, const double* ninv, const double* d, const d
   return CR_OK;
 }
 
+// lnpi_terms of n columns at once: ahat, fhat device [n][nalm]; the
+// syntheses of all columns in one launch each; t host [n][3]
+int lnpi_terms_batch(const crsht_plan* P, int n, const double* ninv, const double* d, const double2* ahat,
+                     const double2* fhat, double* t, hipStream_t s) {
+  const int npart = P->w.npart;
+  const int nbp = std::min<int64_t>(npart, (P->g.npix + 255) / 256);
+  const int nba = std::min<int64_t>(npart, (P->g.nalm + 255) / 256);
+  const int64_t na = P->g.nalm, np = P->g.npix;
+  double* pa = P->w.partial;
+  CR_TRY(hipMemsetAsync(pa, 0, 4 * (size_t)n * npart * sizeof(double), s));
+  CR_CHECK(synth_f64(P, n, ahat, P->w.bk, P->w.map_a, s));
+  for (int c = 0; c < n; ++c) {
+    double* pc = pa + (size_t)c * npart * 4;
+    CR_TRY(launch_pix_wsq(P, ninv, d, P->w.map_a + c * np, pc, nbp, s));
+    CR_TRY(launch_alm_wquad(P, P->w.sinv, ahat + c * na, pc + npart, nba, s));
+  }
+  CR_CHECK(synth_f64(P, n, fhat, P->w.bk, P->w.map_a, s));
+  for (int c = 0; c < n; ++c)
+    CR_TRY(launch_pix_wsq(P, ninv, P->w.map_a + c * np, nullptr, pa + (size_t)c * npart * 4 + 2 * npart, nbp, s));
+  CR_TRY(launch_sum_rows(P, n, std::max(nbp, nba), s));
+  CR_CHECK(read_scalars(P, n, s));
+  for (int c = 0; c < n; ++c) {
+    const double* sc = P->w.host_scal + c * kScalSlots;
+    t[3 * c] = sc[S_AUX0];
+    t[3 * c + 1] = sc[S_AUX1];
+    t[3 * c + 2] = sc[S_AUX2];
+  }
+  return CR_OK;
+}
+
 }  // namespace
 
 // ============================================================== transforms
@@ -1057,12 +1087,14 @@ extern "C" int joint_cl_step_batch(const crsht_plan* P, const cr_problem* fid, c
   //    problem factors are those of the fiducial spectrum: the prior term is
   //    divided by q'_c.
   bool any = false;
-  double t[3];
+  std::vector<double> t(3 * (size_t)n);
+  for (int c = 0; c < n; ++c)   // rescaled fluctuations into cg_bin (its right-hand sides are consumed)
+    CR_TRY(launch_alm_axpby(na, std::sqrt(qn[c] / st[c].q), C2(st[c].fhat), 0.0, nullptr,
+                            w.cg_bin + (size_t)c * na, s));
+  CR_CHECK(lnpi_terms_batch(P, n, fid->ninv, d, w.cg_xacc, w.cg_bin, t.data(), s));
   for (int c = 0; c < n; ++c) {
     out[c].mean_stats = ms[c];
-    CR_TRY(launch_alm_axpby(na, std::sqrt(qn[c] / st[c].q), C2(st[c].fhat), 0.0, nullptr, w.alm_d, s));
-    CR_CHECK(lnpi_terms(P, fid->ninv, d, w.cg_xacc + (size_t)c * na, w.alm_d, t, s));
-    out[c].lnpi_new = -0.5 * (t[0] + t[1] / qn[c] + t[2]);
+    out[c].lnpi_new = -0.5 * (t[3 * c] + t[3 * c + 1] / qn[c] + t[3 * c + 2]);
     out[c].lnA = out[c].lnpi_new - st[c].lnpi + std::log(qn[c] / st[c].q);
     out[c].accepted = std::log(u[c]) < out[c].lnA ? 1 : 0;
     any = any || out[c].accepted;
@@ -1072,17 +1104,16 @@ extern "C" int joint_cl_step_batch(const crsht_plan* P, const cr_problem* fid, c
   //    rejected chains are computed alongside and discarded)
   CR_CHECK(solve_core(P, &pa, 1.0, n, nullptr, w0, w1, nullptr, reinterpret_cast<double*>(w.cg_bin), opts, fs.data(),
                       s));
-  // 5) accepted chains take the new mean field, fluctuation, amplitude and ln pi
+  // 5) accepted chains take the new mean field, fluctuation, amplitude and ln
+  //    pi (evaluated for every column in one batch)
+  CR_CHECK(lnpi_terms_batch(P, n, fid->ninv, d, w.cg_xacc, w.cg_bin, t.data(), s));
   for (int c = 0; c < n; ++c) {
     if (!out[c].accepted) continue;
     out[c].fluct_stats = fs[c];
-    const double2* a = w.cg_xacc + (size_t)c * na;
-    const double2* f = w.cg_bin + (size_t)c * na;
-    CR_TRY(hipMemcpyAsync(st[c].ahat, a, cb, hipMemcpyDeviceToDevice, s));
-    CR_TRY(hipMemcpyAsync(st[c].fhat, f, cb, hipMemcpyDeviceToDevice, s));
-    CR_CHECK(lnpi_terms(P, fid->ninv, d, a, f, t, s));
+    CR_TRY(hipMemcpyAsync(st[c].ahat, w.cg_xacc + (size_t)c * na, cb, hipMemcpyDeviceToDevice, s));
+    CR_TRY(hipMemcpyAsync(st[c].fhat, w.cg_bin + (size_t)c * na, cb, hipMemcpyDeviceToDevice, s));
     st[c].q = qn[c];
-    st[c].lnpi = -0.5 * (t[0] + t[1] / qn[c] + t[2]);
+    st[c].lnpi = -0.5 * (t[3 * c] + t[3 * c + 1] / qn[c] + t[3 * c + 2]);
   }
   CR_TRY(hipStreamSynchronize(s));
   return CR_OK;
