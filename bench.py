@@ -225,7 +225,7 @@ def bench_chains(args):
     lmax = 3 * nside - 1 if args.lmax is None else args.lmax
     wl = ci.workload_masked_t(nside, lmax, fwhm_arcmin=10.0, cfg=2)
     dev = torch.device("cuda:0")
-    plan = crsht.Plan(nside, lmax, nrhs_max=max(1, args.chains))
+    plan = crsht.Plan(nside, lmax, nrhs_max=max(1, 2 * args.chains))
     z, phi = plan.pixel_coords()
     cl, bl = wl.cl(), wl.bl()
     ls, _ = ci.alm_lm_arrays(lmax)
@@ -238,7 +238,7 @@ def bench_chains(args):
               inner_tol=args.inner_tol, precond=crsht.CR_PC_BLOCK)
     out = {}
     for name, kind, batched in (("joint", "joint", False), ("joint_batched", "joint", True),
-                                ("gibbs", "gibbs", False)):
+                                ("gibbs", "gibbs", False), ("gibbs_batched", "gibbs", True)):
         rng = np.random.default_rng([11, 0])
         ch = [chains.init_chain(plan, fid, d, 1.0, torch.from_numpy(chains.white_alm(rng, lmax)).to(dev),
                                 torch.from_numpy(rng.standard_normal(plan.npix)).to(dev), **kw)
@@ -283,12 +283,13 @@ def bench_chains(args):
         "data": "synthetic",
         "config": {"workload": "%d chains, joint moves (sigma ln q 0.02; value: all chains moved in one batched "
                                "call per step, also one chain after another), standard Gibbs moves and HMC moves of "
-                               "ln q, T-only, Nside %d, "
+                               "ln q (Gibbs moves also batched), T-only, Nside %d, "
                                "lmax %d, hit-pattern noise, |b|<20deg mask, FWHM 10', true residual %g, per-m block "
                                "preconditioner, warm-started mean fields, w0 and w1 drawn on the device (Philox4x32-10)"
                                % (args.chains, nside, lmax, args.tol),
                    "chains": args.chains},
-        "joint": out["joint"], "joint_batched": out["joint_batched"], "gibbs": out["gibbs"], "hmc": out["hmc"],
+        "joint": out["joint"], "joint_batched": out["joint_batched"], "gibbs": out["gibbs"],
+        "gibbs_batched": out["gibbs_batched"], "hmc": out["hmc"],
     }
     print(json.dumps(res))
 

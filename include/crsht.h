@@ -358,6 +358,19 @@ typedef struct {
 int gibbs_cl_step(const crsht_plan *plan, const cr_problem *fid, const double *d, cr_chain *state, double g,
                   const double *w0, const double *w1, const cr_opts *opts, cr_gibbs_out *out, void *stream);
 
+/* The Gibbs move of gibbs_cl_step for nchains chains at once: q'_c from
+ * g[c] and chain c's sky, then one solve of 2 nchains columns: columns
+ * 0..nchains-1 the mean fields (warm-started from the chains' mean fields),
+ * columns nchains..2 nchains-1 the fluctuations from w0, w1, each column at
+ * its chain's amplitude (the columns of the mean-field and fluctuation terms
+ * of several chains, as in a multi-chain Gibbs sampler). states, g, out:
+ * host [nchains]; w0: device [nchains][nalm], w1: device [nchains][npix]
+ * (either may be NULL, not both). 2 nchains <= nrhs_max of the plan;
+ * fid->amp must be NULL. Temperature plans only. Blocks until done. */
+int gibbs_cl_step_batch(const crsht_plan *plan, const cr_problem *fid, const double *d, int nchains,
+                        cr_chain *states, const double *g, const double *w0, const double *w1, const cr_opts *opts,
+                        cr_gibbs_out *out, void *stream);
+
 /* ln pi (Sect. 2.2.2, definition of pi(theta)) and its gradient in per-bin
  * log-amplitudes theta_k (C_l -> C_l^fid exp(theta_k) for edges[k] <= l <
  * edges[k+1]) at a fixed whitened fluctuation: the fluctuation f0, given at

@@ -146,14 +146,14 @@ def run_chains(plan: crsht.Plan, fid: crsht.Problem, d: torch.Tensor, chains: li
     """Advance every chain (crsht.Chain, updated in place) by nsteps moves of
     the joint sampler (kind "joint", Gaussian proposal of width sigma_lnq in
     ln q) or of the standard Gibbs sampler (kind "gibbs"). draw(chain, step)
-    returns that move's random numbers (default: default_draws). batched
-    (joint moves): every step moves all chains in one joint_cl_step_batch call
-    (the chains' solves as the columns of one solve; len(chains) <=
-    nrhs_max of the plan)."""
+    returns that move's random numbers (default: default_draws). batched:
+    every step moves all chains in one joint_cl_step_batch or
+    gibbs_cl_step_batch call (the chains' solves as the columns of one
+    solve; len(chains) columns, 2 len(chains) for Gibbs moves, at most the
+    plan's nrhs_max)."""
     if kind not in ("joint", "gibbs"):
         raise ValueError("kind must be 'joint' or 'gibbs'")
-    if batched and kind != "joint":
-        raise ValueError("batched moves are joint moves")
+
     n = len(chains)
     alpha = crsht.gibbs_shape(plan.lmax, fid.lmin)
     if draw is None:
@@ -170,10 +170,13 @@ def run_chains(plan: crsht.Plan, fid: crsht.Problem, d: torch.Tensor, chains: li
             rs = [draw(c, s) for c in range(n)]
             w0 = _stack([r["w0"] for r in rs], dev)
             w1 = _stack([r["w1"] for r in rs], dev)
-            res = crsht.joint_step_batch(plan, fid, d, chains, [r["xi"] for r in rs], [r["u"] for r in rs], w0, w1,
-                                         sigma_lnq=sigma_lnq, **solve_kw)
+            if kind == "joint":
+                res = crsht.joint_step_batch(plan, fid, d, chains, [r["xi"] for r in rs], [r["u"] for r in rs], w0,
+                                             w1, sigma_lnq=sigma_lnq, **solve_kw)
+            else:
+                res = crsht.gibbs_step_batch(plan, fid, d, chains, [r["g"] for r in rs], w0, w1, **solve_kw)
             for c, ch in enumerate(chains):
-                acc[c, s] = res[c].accepted
+                acc[c, s] = res[c].accepted if kind == "joint" else True
                 mi[c, s] = res[c].mean_stats.iters
                 fi[c, s] = res[c].fluct_stats.iters
                 q[c, s + 1] = ch.q

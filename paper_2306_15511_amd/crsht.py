@@ -120,6 +120,9 @@ def _load():
                                 ctypes.POINTER(ctypes.c_double), vp, ctypes.POINTER(_Stats), vp], i),
         "hmc_cl_step": ([P, ctypes.POINTER(_Problem), vp, ctypes.POINTER(_BinChain), ctypes.POINTER(_HmcDraws),
                          ctypes.POINTER(_Opts), ctypes.POINTER(_HmcOut), vp], i),
+        "gibbs_cl_step_batch": ([P, ctypes.POINTER(_Problem), vp, i, ctypes.POINTER(_Chain),
+                                 ctypes.POINTER(ctypes.c_double), vp, vp, ctypes.POINTER(_Opts),
+                                 ctypes.POINTER(_GibbsOut), vp], i),
         "cr_white": ([P, i, ctypes.c_uint64, ctypes.c_uint64, vp, vp, vp], i),
         "joint_cl_step_batch": ([P, ctypes.POINTER(_Problem), vp, i, ctypes.POINTER(_Chain),
                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), d, vp, vp,
@@ -149,7 +152,7 @@ _lib = _load()
 
 EXPORTED = ("crsht_plan_create", "crsht_plan_destroy", "crsht_strerror", "crsht_plan_info", "crsht_pixel_coords",
             "sht_synth", "sht_synth_adjoint", "sht_analysis", "cr_precond", "cr_rhs", "cr_apply", "cr_solve",
-            "cr_white", "cr_lnpi", "joint_cl_step", "joint_cl_step_batch", "gibbs_cl_step", "hmc_cl_step", "cr_lnpi_grad_fixed",
+            "cr_white", "cr_lnpi", "joint_cl_step", "joint_cl_step_batch", "gibbs_cl_step", "gibbs_cl_step_batch", "hmc_cl_step", "cr_lnpi_grad_fixed",
             "cr_solve_batched", "sht_synth_grad", "cr_grad_chi2", "cr_grad_lnpi",
             "cr_block_precond_build", "cr_block_precond_apply", "crsht_timing_enable", "crsht_timing_read")
 
@@ -513,6 +516,35 @@ def gibbs_step(plan: Plan, fid: Problem, d: torch.Tensor, chain: Chain, g: float
     return GibbsResult(r.q_new, r.t, st(r.mean_stats), st(r.fluct_stats))
 
 
+def gibbs_step_batch(plan: Plan, fid: Problem, d: torch.Tensor, chains: list, g, w0: torch.Tensor,
+                     w1: torch.Tensor, tol: float = 1e-6, maxiter: int = 10000, prec: int = CR_F64,
+                     inner_tol: float = 1e-2, max_refine: int = 50, use_graph: bool = True,
+                     precond: int = CR_PC_JACOBI) -> list:
+    """Gibbs moves of several chains at once (gibbs_cl_step_batch); w0 [n,
+    nalm] and w1 [n, npix] on the device; every chain updated in place."""
+    n = len(chains)
+    p = fid._c()
+    arr = (_Chain * n)(*[_Chain(c.q, c.lnpi, _ptr(c.ahat), _ptr(c.fhat)) for c in chains])
+    gg = _f64(g)
+    if gg.size != n:
+        raise ValueError("g needs one entry per chain")
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, 8, int(precond), int(use_graph))
+    outs = (_GibbsOut * n)()
+    _check(_lib.gibbs_cl_step_batch(plan.handle, ctypes.byref(p), _ptr(d), n, arr,
+                                    gg.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(w0), _ptr(w1),
+                                    ctypes.byref(o), outs, _stream()), "gibbs_cl_step_batch")
+
+    def st(s_):
+        return Stats(s_.status, s_.iters, s_.refinements, s_.rel_resid_true)
+
+    res = []
+    for c, ch in enumerate(chains):
+        ch.q, ch.lnpi = arr[c].q, arr[c].lnpi
+        r = outs[c]
+        res.append(GibbsResult(r.q_new, r.t, st(r.mean_stats), st(r.fluct_stats)))
+    return res
+
+
 @dataclass
 class BinChain:
     """Chain over per-bin log-amplitudes theta (C_l = C_l^fid exp(theta_k) on
@@ -660,7 +692,7 @@ def nalm(lmax: int, mmax: int | None = None) -> int:
 
 __all__ = ["Plan", "Problem", "Stats", "Chain", "StepResult", "synth", "adjoint", "analysis", "precond", "rhs",
            "block_precond_build", "block_precond_apply", "CR_PC_JACOBI", "CR_PC_BLOCK",
-           "apply", "solve", "solve_batched", "lnpi", "white", "joint_step", "joint_step_batch", "gibbs_step", "gibbs_shape", "GibbsResult",
+           "apply", "solve", "solve_batched", "lnpi", "white", "joint_step", "joint_step_batch", "gibbs_step", "gibbs_step_batch", "gibbs_shape", "GibbsResult",
            "BinChain", "HmcResult", "lnpi_grad_fixed", "hmc_step", "synth_grad", "synth_ad", "SynthFunction", "grad_chi2", "grad_lnpi",
            "CR_F64", "CR_MIXED", "CrshtError", "strerror", "EXPORTED"]
 _ = math

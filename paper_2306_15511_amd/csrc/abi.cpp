@@ -1299,3 +1299,63 @@ extern "C" int gibbs_cl_step(const crsht_plan* P, const cr_problem* fid, const d
   CR_TRY(hipStreamSynchronize(s));
   return CR_OK;
 }
+
+extern "C" int gibbs_cl_step_batch(const crsht_plan* P, const cr_problem* fid, const double* d, int n, cr_chain* st,
+                                   const double* g, const double* w0, const double* w1, const cr_opts* opts,
+                                   cr_gibbs_out* out, void* stream) {
+  if (n < 1) return CR_EINVAL;
+  CR_CHECK(check_plan(P, 2 * n));
+  if (P->ncomp != 1) return CR_ENOTSUP;
+  if (!fid || !d || !st || !g || !opts || !out || (!w0 && !w1)) return CR_EINVAL;
+  if (fid->amp) return CR_EINVAL;   // the move sets the columns' amplitudes itself
+  for (int c = 0; c < n; ++c) {
+    if (!st[c].ahat || !st[c].fhat || !(st[c].q > 0.0) || !std::isfinite(st[c].q)) return CR_EINVAL;
+    if (!(g[c] > 0.0) || !std::isfinite(g[c])) return CR_EINVAL;
+  }
+  hipStream_t s = S(stream);
+  Workspace const& w = P->w;
+  const int64_t na = P->g.nalm;
+  const size_t cb = (size_t)na * sizeof(double2);
+  std::memset(out, 0, (size_t)n * sizeof(cr_gibbs_out));
+  // 1) q_c | s_c: t_c = s_c^T S_fid^-1 s_c of the current sky, q'_c = (t_c / 2) / g_c
+  CR_CHECK(set_problem(P, fid, 1.0, s));
+  std::vector<double> qn(2 * (size_t)n);
+  for (int c = 0; c < n; ++c) {
+    CR_TRY(launch_alm_axpby(na, 1.0, C2(st[c].ahat), 1.0, C2(st[c].fhat), w.alm_d, s));
+    double t = 0.0;
+    CR_CHECK(quad_sinv(P, w.alm_d, &t, s));
+    if (!(t > 0.0) || !std::isfinite(t)) return CR_EINVAL;
+    out[c].t = t;
+    out[c].q_new = qn[c] = qn[n + c] = 0.5 * t / g[c];
+  }
+  // 2) s_c | q'_c: columns 0..n-1 the mean fields (the data term, one column
+  //    copied; warm-started from the chains' mean fields), columns n..2n-1 the
+  //    fluctuations from w0, w1 (cold), all at their chain's amplitude
+  cr_problem pa = *fid;
+  pa.amp = qn.data();
+  CR_CHECK(assemble_rhs(P, 1, fid->ninv, d, nullptr, nullptr, w.cg_bin, s));
+  for (int c = 1; c < n; ++c)
+    CR_TRY(hipMemcpyAsync(w.cg_bin + (size_t)c * na, w.cg_bin, cb, hipMemcpyDeviceToDevice, s));
+  CR_CHECK(set_problem(P, &pa, 1.0, s, n));   // columns 0..n-1 at q'_c for the S^-1/2 w0 term
+  CR_CHECK(assemble_rhs(P, n, fid->ninv, nullptr, w0, w1, w.cg_bin + (size_t)n * na, s));
+  for (int c = 0; c < n; ++c)
+    CR_TRY(hipMemcpyAsync(w.cg_xacc + (size_t)c * na, st[c].ahat, cb, hipMemcpyDeviceToDevice, s));
+  CR_TRY(hipMemsetAsync(w.cg_xacc + (size_t)n * na, 0, (size_t)n * cb, s));
+  std::vector<cr_stats> ss(2 * (size_t)n);
+  CR_CHECK(solve_core(P, &pa, 1.0, 2 * n, nullptr, nullptr, nullptr, reinterpret_cast<const double*>(w.cg_bin),
+                      reinterpret_cast<double*>(w.cg_xacc), opts, ss.data(), s,
+                      reinterpret_cast<const double*>(w.cg_xacc)));
+  // 3) new states and ln pi of each (one batch)
+  std::vector<double> t(3 * (size_t)n);
+  CR_CHECK(lnpi_terms_batch(P, n, fid->ninv, d, w.cg_xacc, w.cg_xacc + (size_t)n * na, t.data(), s));
+  for (int c = 0; c < n; ++c) {
+    out[c].mean_stats = ss[c];
+    out[c].fluct_stats = ss[n + c];
+    CR_TRY(hipMemcpyAsync(st[c].ahat, w.cg_xacc + (size_t)c * na, cb, hipMemcpyDeviceToDevice, s));
+    CR_TRY(hipMemcpyAsync(st[c].fhat, w.cg_xacc + (size_t)(n + c) * na, cb, hipMemcpyDeviceToDevice, s));
+    st[c].q = qn[c];
+    st[c].lnpi = -0.5 * (t[3 * c] + t[3 * c + 1] / qn[c] + t[3 * c + 2]);
+  }
+  CR_TRY(hipStreamSynchronize(s));
+  return CR_OK;
+}

@@ -80,17 +80,17 @@ def test_joint_mean_field_warm_start():
     assert real_rel(opn, ch.ahat.cpu().numpy(), cold[0].cpu().numpy()) < 1e-5
 
 
-@pytest.mark.parametrize("kind", ["joint", "gibbs", "joint_batched"])
+@pytest.mark.parametrize("kind", ["joint", "gibbs", "joint_batched", "gibbs_batched"])
 def test_chain_driver_replays_oracle(kind):
     from paper_2306_15511_amd import chains
     tol = 1e-12
     m, wl, P, d, plan, gp, st = _setup(8, tol)
     print("case chains", kind, flush=True)
     nchain, nsteps = 2, 4
-    batched = kind == "joint_batched"
-    kind = "joint" if batched else kind
+    batched = kind.endswith("_batched")
+    kind = kind.replace("_batched", "")
     if batched:
-        plan = m.Plan(8, wl.lmax, nrhs_max=nchain)
+        plan = m.Plan(8, wl.lmax, nrhs_max=2 * nchain)
     alpha = joint.gibbs_shape(P)
     draws = {}
 
@@ -278,3 +278,34 @@ def test_joint_step_batch_matches_oracle():
     assert flags[1] is False and flags[2] is True
     with pytest.raises(RuntimeError):   # more chains than the plan's columns
         m.joint_step_batch(plan0, gp, tc(d), gch[:2], xi[:2], u[:2], tc(W0[:2]), tc(W1[:2]), tol=tol)
+
+
+def test_gibbs_step_batch_matches_oracle():
+    # three chains in one gibbs_cl_step_batch call (six columns: three mean
+    # fields, three fluctuations) against the oracle's Gibbs move of each
+    tol = 1e-12
+    m, wl, P, d, plan0, gp, st0 = _setup(8, tol)
+    print("case gibbs step batch", flush=True)
+    plan = m.Plan(8, wl.lmax, nrhs_max=6)
+    rng = np.random.default_rng(71)
+    states = [joint.init_state(P, d, q, ci.white_alm(rng, P.lmax), rng.standard_normal(P.ninv.size), tol)
+              for q in (0.9, 1.0, 1.2)]
+    alpha = joint.gibbs_shape(P)
+    g = [0.8 * alpha, alpha, 1.25 * alpha]
+    W0 = np.stack([ci.white_alm(rng, P.lmax) for _ in range(3)])
+    W1 = np.stack([rng.standard_normal(P.ninv.size) for _ in range(3)])
+    gch = [_chain(m, s_) for s_ in states]
+    res = m.gibbs_step_batch(plan, gp, tc(d), gch, g, tc(W0), tc(W1), tol=tol)
+    for c in range(3):
+        new, r = joint.gibbs_step(P, d, states[c], g[c], W0[c], W1[c], tol)
+        print("chain %d t gpu %.15e oracle %.15e q %.6f iters %d/%d" % (
+            c, res[c].t, r.t, r.q_new, res[c].mean_stats.iters, res[c].fluct_stats.iters), flush=True)
+        assert abs(res[c].t - r.t) <= 1e-12 * r.t
+        assert abs(res[c].q_new - r.q_new) <= 1e-12 * r.q_new and abs(gch[c].q - new.q) <= 1e-12 * new.q
+        assert abs(gch[c].lnpi - new.lnpi) <= 1e-9 * abs(new.lnpi)
+        opn = cr.CROperator(joint.scaled_problem(P, new.q))
+        assert real_rel(opn, gch[c].ahat.cpu().numpy(), new.ahat) < 1e-8
+        assert real_rel(opn, gch[c].fhat.cpu().numpy(), new.fhat) < 1e-8
+        assert res[c].mean_stats.status == 0 and res[c].fluct_stats.status == 0
+    with pytest.raises(RuntimeError):   # 2 x 3 columns do not fit a plan of 3
+        m.gibbs_step_batch(m.Plan(8, wl.lmax, nrhs_max=3), gp, tc(d), gch, g, tc(W0), tc(W1), tol=tol)
