@@ -433,6 +433,23 @@ typedef struct {
 int hmc_cl_step(const crsht_plan *plan, const cr_problem *fid, const double *d, cr_bin_chain *state,
                 const cr_hmc_draws *draws, const cr_opts *opts, cr_hmc_out *out, void *stream);
 
+/* The standard two-block Gibbs move (paper Sect. 2.2.1: amplitudes given the
+ * sky, then the sky given the amplitudes) for per-bin amplitudes A_b =
+ * exp(theta_b) of C_l = C_l^fid A_b on [edges[b], edges[b+1]) with uniform
+ * priors in the A_b: with s = ahat + fhat and t_b = s^T S_fid^-1 s summed
+ * over the bin (real-field product), A_b | s is inverse gamma with shape
+ * k_b/2 - 1 (k_b = sum over the bin of 2l + 1) and scale t_b/2; the caller
+ * draws g_b ~ Gamma(k_b/2 - 1, 1) (host [nbins]) and the move sets theta_b =
+ * ln((t_b/2) / g_b). Then the mean field (warm-started from state->ahat) and
+ * a fresh fluctuation from w0, w1 (device; either may be NULL, not both) at
+ * the new spectrum, and ln pi of the new state; *state updated in place.
+ * Bins must start at or above fid->lmin. t: host [nbins] or NULL (the t_b);
+ * stats: host [2] (mean field, fluctuation). Temperature plans only. Blocks
+ * until done. */
+int gibbs_bins_step(const crsht_plan *plan, const cr_problem *fid, const double *d, cr_bin_chain *state,
+                    const double *g, const double *w0, const double *w1, const cr_opts *opts, double *t,
+                    cr_stats *stats, void *stream);
+
 /* Gradient of the synthesis for reverse-mode differentiation of a real
  * function L of the map: alm_grad = w_m Y^T map_grad with w_0 = 1 (Im of m = 0
  * set to 0) and w_{m>0} = 2, i.e. dL/dRe a_lm + i dL/dIm a_lm for a complex

@@ -18,7 +18,9 @@ The standard two-block Gibbs move (Sect. 2.2.1; the baseline the joint move
 is compared with) for the same one-parameter family is gibbs_step: q given
 the current sky from its inverse-gamma conditional, then the sky given q.
 
-hmc_step is the derivative-based sampler Sect. 4 points to, on per-bin
+gibbs_bins_step is the standard Gibbs move for per-bin amplitudes (one
+inverse-gamma draw per bin given the sky). hmc_step is the derivative-based
+sampler Sect. 4 points to, on per-bin
 log-amplitudes: the joint move's target (ln pi at a fixed whitened
 fluctuation) explored by Hamiltonian trajectories, with the gradient of
 lnpi_grad_fixed.
@@ -214,3 +216,34 @@ def hmc_step(fid: Problem, d, edges, state: BinState, p0, u: float, w0_new, w1_n
     op = CROperator(bin_problem(fid, edges, th_end))
     fhat, _ = pcg(op, op.rhs(w0=w0_new, w1=w1_new), tol, maxiter)
     return BinState(th_end, a_end, fhat, lnpi(op, d, a_end, fhat)), HmcResult(accepted, dH, lp)
+
+
+# ------------------------------------------------ standard Gibbs over bins
+def bin_dof(lmin: int, edges) -> np.ndarray:
+    """Real degrees of freedom of each bin (l >= lmin)."""
+    return np.array([sum(2 * l + 1 for l in range(max(edges[k], lmin), edges[k + 1])) for k in range(len(edges) - 1)],
+                    dtype=np.float64)
+
+
+def gibbs_bins_shape(fid: Problem, edges) -> np.ndarray:
+    """Per-bin inverse-gamma shapes k_b/2 - 1 of A_b | s under uniform priors in
+    the amplitudes A_b = exp(theta_b)."""
+    return 0.5 * bin_dof(fid.lmin, edges) - 1.0
+
+
+def gibbs_bins_step(fid: Problem, d, edges, state: BinState, g, w0_new, w1_new, tol: float, maxiter: int = 20000):
+    """Standard two-block Gibbs move (Sect. 2.2.1) for per-bin amplitudes:
+    with s = a^ + f^ and t_b = sum over the bin of s^T S_fid^-1 s, each
+    A_b | s is inverse gamma (shape gibbs_bins_shape, scale t_b/2): A_b =
+    (t_b/2)/g_b for g_b ~ Gamma(shape_b, 1) from the caller; theta_b = ln A_b;
+    then the mean field and a fresh fluctuation at the new spectrum. Returns
+    (new state, t)."""
+    op_fid = CROperator(fid)
+    s = state.ahat + state.fhat
+    t = np.array([op_fid.dot(s * ((op_fid.ls >= edges[k]) & (op_fid.ls < edges[k + 1])), op_fid.sinv * s)
+                  for k in range(len(edges) - 1)])
+    theta = np.log(0.5 * t / np.asarray(g, dtype=np.float64))
+    op = CROperator(bin_problem(fid, edges, theta))
+    ahat, _ = pcg(op, op.rhs(d=d), tol, maxiter)
+    fhat, _ = pcg(op, op.rhs(w0=w0_new, w1=w1_new), tol, maxiter)
+    return BinState(theta, ahat, fhat, lnpi(op, d, ahat, fhat)), t

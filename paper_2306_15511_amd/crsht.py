@@ -123,6 +123,9 @@ def _load():
         "gibbs_cl_step_batch": ([P, ctypes.POINTER(_Problem), vp, i, ctypes.POINTER(_Chain),
                                  ctypes.POINTER(ctypes.c_double), vp, vp, ctypes.POINTER(_Opts),
                                  ctypes.POINTER(_GibbsOut), vp], i),
+        "gibbs_bins_step": ([P, ctypes.POINTER(_Problem), vp, ctypes.POINTER(_BinChain),
+                             ctypes.POINTER(ctypes.c_double), vp, vp, ctypes.POINTER(_Opts),
+                             ctypes.POINTER(ctypes.c_double), vp, vp], i),
         "cr_white": ([P, i, ctypes.c_uint64, ctypes.c_uint64, vp, vp, vp], i),
         "joint_cl_step_batch": ([P, ctypes.POINTER(_Problem), vp, i, ctypes.POINTER(_Chain),
                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), d, vp, vp,
@@ -152,7 +155,7 @@ _lib = _load()
 
 EXPORTED = ("crsht_plan_create", "crsht_plan_destroy", "crsht_strerror", "crsht_plan_info", "crsht_pixel_coords",
             "sht_synth", "sht_synth_adjoint", "sht_analysis", "cr_precond", "cr_rhs", "cr_apply", "cr_solve",
-            "cr_white", "cr_lnpi", "joint_cl_step", "joint_cl_step_batch", "gibbs_cl_step", "gibbs_cl_step_batch", "hmc_cl_step", "cr_lnpi_grad_fixed",
+            "cr_white", "cr_lnpi", "joint_cl_step", "joint_cl_step_batch", "gibbs_cl_step", "gibbs_cl_step_batch", "gibbs_bins_step", "hmc_cl_step", "cr_lnpi_grad_fixed",
             "cr_solve_batched", "sht_synth_grad", "cr_grad_chi2", "cr_grad_lnpi",
             "cr_block_precond_build", "cr_block_precond_apply", "crsht_timing_enable", "crsht_timing_read")
 
@@ -600,6 +603,36 @@ def lnpi_grad_fixed(plan: Plan, fid: Problem, d: torch.Tensor, edges, theta0, th
     return g, v.value, ahat, Stats(st[0].status, st[0].iters, st[0].refinements, st[0].rel_resid_true)
 
 
+def gibbs_bins_step(plan: Plan, fid: Problem, d: torch.Tensor, chain: BinChain, g, w0: torch.Tensor,
+                    w1: torch.Tensor, tol: float = 1e-6, maxiter: int = 10000, prec: int = CR_F64,
+                    inner_tol: float = 1e-2, max_refine: int = 50, use_graph: bool = True,
+                    precond: int = CR_PC_JACOBI):
+    """Standard Gibbs move of per-bin amplitudes (gibbs_bins_step): returns
+    (t [nbins] numpy, mean-field Stats, fluctuation Stats); chain.theta and
+    chain.lnpi updated in place."""
+    import numpy as np
+    e = _i32(chain.edges)
+    th = _f64(chain.theta)
+    gg = _f64(g)
+    nb = e.size - 1
+    if gg.size != nb:
+        raise ValueError("g needs one entry per bin")
+    dp = ctypes.POINTER(ctypes.c_double)
+    c = _BinChain(nb, e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), th.ctypes.data_as(dp), chain.lnpi,
+                  _ptr(chain.ahat), _ptr(chain.fhat))
+    t = np.zeros(nb)
+    sts = (_Stats * 2)()
+    p = fid._c()
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, 8, int(precond), int(use_graph))
+    _check(_lib.gibbs_bins_step(plan.handle, ctypes.byref(p), _ptr(d), ctypes.byref(c), gg.ctypes.data_as(dp),
+                                _ptr(w0), _ptr(w1), ctypes.byref(o), t.ctypes.data_as(dp), sts, _stream()),
+           "gibbs_bins_step")
+    chain.theta = th.copy()
+    chain.lnpi = c.lnpi
+    mk = [Stats(x.status, x.iters, x.refinements, x.rel_resid_true) for x in sts]
+    return t, mk[0], mk[1]
+
+
 def hmc_step(plan: Plan, fid: Problem, d: torch.Tensor, chain: BinChain, p0, u: float, w0: torch.Tensor,
              w1: torch.Tensor, eps: float, nleap: int, tol: float = 1e-6, maxiter: int = 10000,
              prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 50, use_graph: bool = True,
@@ -693,6 +726,6 @@ def nalm(lmax: int, mmax: int | None = None) -> int:
 __all__ = ["Plan", "Problem", "Stats", "Chain", "StepResult", "synth", "adjoint", "analysis", "precond", "rhs",
            "block_precond_build", "block_precond_apply", "CR_PC_JACOBI", "CR_PC_BLOCK",
            "apply", "solve", "solve_batched", "lnpi", "white", "joint_step", "joint_step_batch", "gibbs_step", "gibbs_step_batch", "gibbs_shape", "GibbsResult",
-           "BinChain", "HmcResult", "lnpi_grad_fixed", "hmc_step", "synth_grad", "synth_ad", "SynthFunction", "grad_chi2", "grad_lnpi",
+           "BinChain", "HmcResult", "lnpi_grad_fixed", "hmc_step", "gibbs_bins_step", "synth_grad", "synth_ad", "SynthFunction", "grad_chi2", "grad_lnpi",
            "CR_F64", "CR_MIXED", "CrshtError", "strerror", "EXPORTED"]
 _ = math

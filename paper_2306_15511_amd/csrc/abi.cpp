@@ -1266,6 +1266,54 @@ extern "C" int hmc_cl_step(const crsht_plan* P, const cr_problem* fid, const dou
   return CR_OK;
 }
 
+extern "C" int gibbs_bins_step(const crsht_plan* P, const cr_problem* fid, const double* d, cr_bin_chain* st,
+                               const double* g, const double* w0, const double* w1, const cr_opts* opts, double* t,
+                               cr_stats* stats, void* stream) {
+  CR_CHECK(check_plan(P, 1));
+  if (fid && fid->amp) return CR_EINVAL;   // one spectrum per call
+  if (P->ncomp != 1) return CR_ENOTSUP;
+  if (!fid || !d || !st || !g || !opts || !stats || !st->theta || !st->ahat || !st->fhat || (!w0 && !w1))
+    return CR_EINVAL;
+  if (!valid_bins(P, st->nbins, st->edges) || st->edges[0] < fid->lmin) return CR_EINVAL;
+  const int nb = st->nbins;
+  for (int k = 0; k < nb; ++k)
+    if (!(g[k] > 0.0) || !std::isfinite(g[k])) return CR_EINVAL;
+  hipStream_t s = S(stream);
+  Workspace const& w = P->w;
+  const int64_t na = P->g.nalm;
+  std::memset(stats, 0, 2 * sizeof(cr_stats));
+  // 1) per-bin t_b = s^T S_fid^-1 s over the bin, s = ahat + fhat
+  CR_CHECK(set_problem(P, fid, 1.0, s));
+  CR_TRY(launch_alm_axpby(na, 1.0, C2(st->ahat), 1.0, C2(st->fhat), w.alm_d, s));
+  CR_TRY(hipMemcpyAsync(w.bin_edges, st->edges, (size_t)(nb + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  CR_TRY(launch_bin_grad(P, nb, w.bin_edges, w.alm_d, w.alm_d, w.alm_d, nullptr, w.bin_grad, s, 2));
+  std::vector<double> tb(nb), th(nb);
+  CR_TRY(hipMemcpyAsync(tb.data(), w.bin_grad, (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, s));
+  CR_TRY(hipStreamSynchronize(s));
+  // 2) A_b | s inverse gamma (shape k_b/2 - 1, scale t_b/2): A_b = (t_b/2) / g_b
+  for (int k = 0; k < nb; ++k) {
+    if (!(tb[k] > 0.0) || !std::isfinite(tb[k])) return CR_EINVAL;
+    th[k] = std::log(0.5 * tb[k] / g[k]);
+    if (t) t[k] = tb[k];
+  }
+  // 3) s | A: mean field (warm-started) and a fresh fluctuation at the new spectrum
+  std::vector<double> fac, cl(P->g.lmax + 1);
+  bin_factor(P->g.lmax, nb, st->edges, th.data(), 1.0, fac);
+  for (int l = 0; l <= P->g.lmax; ++l) cl[l] = fid->cl[l] * fac[l];
+  cr_problem pr = *fid;
+  pr.cl = cl.data();
+  CR_CHECK(solve_core(P, &pr, 1.0, 1, d, nullptr, nullptr, nullptr, reinterpret_cast<double*>(w.alm_c), opts,
+                      &stats[0], s, st->ahat));
+  CR_CHECK(solve_core(P, &pr, 1.0, 1, nullptr, w0, w1, nullptr, st->fhat, opts, &stats[1], s));
+  CR_TRY(hipMemcpyAsync(st->ahat, w.alm_c, (size_t)na * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  double tt[3];
+  CR_CHECK(lnpi_terms(P, fid->ninv, d, w.alm_c, C2(st->fhat), tt, s));
+  for (int k = 0; k < nb; ++k) st->theta[k] = th[k];
+  st->lnpi = -0.5 * (tt[0] + tt[1] + tt[2]);
+  CR_TRY(hipStreamSynchronize(s));
+  return CR_OK;
+}
+
 extern "C" int gibbs_cl_step(const crsht_plan* P, const cr_problem* fid, const double* d, cr_chain* state, double g,
                              const double* w0, const double* w1, const cr_opts* opts, cr_gibbs_out* out,
                              void* stream) {

@@ -353,7 +353,8 @@ hipError_t launch_mweight(const crsht_plan* P, int nrhs, double2* a, hipStream_t
 // grad[k] = <a,S^-1_k a>/2 + <lam,S^-1/2_k w0>/2 - <lam,S^-1_k f> for the bins of
 // edges (device, nbins + 1 entries); w0 may be null
 // per-bin d ln pi / d theta_k; mode 0: at fixed w0, w1 (lam = A^-1 M f);
-// mode 1: at fixed whitened fluctuation (lam = M f, w0 unused)
+// mode 1: at fixed whitened fluctuation (lam = M f, w0 unused); mode 2: the
+// per-bin a^T S^-1_k a alone
 hipError_t launch_bin_grad(const crsht_plan* P, int nbins, const int* edges, const double2* ahat,
                            const double2* fhat, const double2* lam, const double2* w0, double* grad,
                            hipStream_t s, int mode = 0);

@@ -517,7 +517,8 @@ __global__ void k_bin_terms(int mmax, const int64_t* __restrict__ mstart, const 
 }
 
 // d ln pi / d theta_k = t1/2 + t2/2 - t3 (mode 0: fixed w0, w1) or t1/2 - t3/2
-// (mode 1: fixed whitened fluctuation, lam = M f), slices summed in a fixed order
+// (mode 1: fixed whitened fluctuation, lam = M f); mode 2: t1 alone (the
+// bin's a^T S^-1 a); slices summed in a fixed order
 __global__ void k_bin_grad(int nbins, int S, const double* __restrict__ partial, double* __restrict__ grad,
                            int mode) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -529,7 +530,7 @@ __global__ void k_bin_grad(int nbins, int S, const double* __restrict__ partial,
     t2 += o[1];
     t3 += o[2];
   }
-  grad[k] = mode == 1 ? 0.5 * t1 - 0.5 * t3 : 0.5 * t1 + 0.5 * t2 - t3;
+  grad[k] = mode == 2 ? t1 : mode == 1 ? 0.5 * t1 - 0.5 * t3 : 0.5 * t1 + 0.5 * t2 - t3;
 }
 
 }  // namespace

@@ -309,3 +309,36 @@ def test_gibbs_step_batch_matches_oracle():
         assert res[c].mean_stats.status == 0 and res[c].fluct_stats.status == 0
     with pytest.raises(RuntimeError):   # 2 x 3 columns do not fit a plan of 3
         m.gibbs_step_batch(m.Plan(8, wl.lmax, nrhs_max=3), gp, tc(d), gch, g, tc(W0), tc(W1), tol=tol)
+
+
+@pytest.mark.parametrize("nbins", [1, 3])
+def test_gibbs_bins_step_matches_oracle(nbins):
+    # per-bin t_b, the drawn log-amplitudes, ln pi and the new sky against the
+    # oracle's standard Gibbs move over bins with the same gamma variates and
+    # w0, w1 (two moves in a row)
+    tol = 1e-12
+    edges = [2, 24] if nbins == 1 else [2, 6, 12, 24]
+    m, wl, P, d, plan, gp, st = _bin_setup(edges, tol, 81)
+    print("case gibbs bins nbins=%d" % nbins, flush=True)
+    ch = _bin_chain(m, edges, st)
+    alpha = joint.gibbs_bins_shape(P, edges)
+    for s in range(2):
+        rng = np.random.default_rng([82, nbins, s])
+        g = rng.gamma(alpha)
+        w0n, w1n = ci.white_alm(rng, P.lmax), rng.standard_normal(P.ninv.size)
+        t, ms, fs = m.gibbs_bins_step(plan, gp, tc(d), ch, g, tc(w0n), tc(w1n), tol=tol)
+        st, tr = joint.gibbs_bins_step(P, d, edges, st, g, w0n, w1n, tol)
+        print("t gpu", t, "oracle", tr, "theta", st.theta, "iters %d/%d" % (ms.iters, fs.iters), flush=True)
+        # the first move starts from the oracle's state (t to rounding), the
+        # second from the GPU's own solves to 1e-12 (t to about that)
+        bound = 1e-12 if s == 0 else 1e-9
+        assert np.all(np.abs(t - tr) <= bound * tr)
+        assert np.all(np.abs(ch.theta - st.theta) <= bound)
+        assert abs(ch.lnpi - st.lnpi) <= 1e-9 * abs(st.lnpi)
+        opb = cr.CROperator(joint.bin_problem(P, edges, st.theta))
+        assert real_rel(opb, ch.ahat.cpu().numpy(), st.ahat) < 1e-8
+        assert real_rel(opb, ch.fhat.cpu().numpy(), st.fhat) < 1e-8
+        assert ms.status == 0 and fs.status == 0
+    bad = m.BinChain(np.array([0, 24], dtype=np.int32), np.zeros(1), ch.lnpi, ch.ahat, ch.fhat)
+    with pytest.raises(RuntimeError):   # a bin below lmin has no amplitude to draw
+        m.gibbs_bins_step(plan, gp, tc(d), bad, [1.0], tc(w0n), tc(w1n), tol=tol)

@@ -221,13 +221,11 @@ def test_leapfrog_energy_error_falls_as_step_squared():
         assert 3.0 < a / b < 5.0, dh
 
 
-def test_hmc_chain_samples_exact_marginal_posterior():
-    # two bins (l = 2; l = 3..4) of the tiny masked problem: the exact
-    # posterior of (theta_0, theta_1) from the Gaussian likelihood of the
-    # observed pixels with a uniform prior in the amplitudes exp(theta_k), on
-    # a grid; the HMC chain's means within four standard errors
-    wl, P, op, d = _tiny(2, 4)
-    edges = [2, 3, 5]
+def _two_bin_exact(P, d, edges):
+    """Exact posterior means of (theta_0, theta_1) of two bins on the tiny
+    masked problem: Gaussian likelihood of the observed pixels with C_l
+    exp(theta_b) on bin b, uniform priors in the amplitudes exp(theta_b),
+    on a grid."""
     D = dense.DenseY(P.nside, P.lmax, lmin=2)
     obs = P.ninv > 0
     Yo = D.Y[obs] * D._per_dof(P.bl)[None, :]
@@ -237,13 +235,23 @@ def test_hmc_chain_samples_exact_marginal_posterior():
     lp = np.zeros((t0.size, t1.size))
     for i, a0 in enumerate(t0):
         for j, a1 in enumerate(t1):
-            C = (Yo * (var1 * np.where(lsd < 3, math.exp(a0), math.exp(a1)))[None, :]) @ Yo.T
+            C = (Yo * (var1 * np.where(lsd < edges[1], math.exp(a0), math.exp(a1)))[None, :]) @ Yo.T
             L = np.linalg.cholesky(C + np.diag(1.0 / P.ninv[obs]))
             y = np.linalg.solve(L, d[obs])
             lp[i, j] = -0.5 * float(y @ y) - float(np.log(np.diag(L)).sum()) + a0 + a1
     w = np.exp(lp - lp.max())
     assert w[-1].sum() < 1e-5 * w.sum() and w[:, -1].sum() < 1e-5 * w.sum()
-    exact = [float((w.sum(1) * t0).sum() / w.sum()), float((w.sum(0) * t1).sum() / w.sum())]
+    return [float((w.sum(1) * t0).sum() / w.sum()), float((w.sum(0) * t1).sum() / w.sum())]
+
+
+def test_hmc_chain_samples_exact_marginal_posterior():
+    # two bins (l = 2; l = 3..4) of the tiny masked problem: the exact
+    # posterior of (theta_0, theta_1) from the Gaussian likelihood of the
+    # observed pixels with a uniform prior in the amplitudes exp(theta_k), on
+    # a grid; the HMC chain's means within four standard errors
+    wl, P, op, d = _tiny(2, 4)
+    edges = [2, 3, 5]
+    exact = _two_bin_exact(P, d, edges)
     rng = np.random.default_rng(5)
     st = joint.init_bin_state(P, d, edges, np.zeros(2), ci.white_alm(rng, P.lmax), rng.standard_normal(d.size), 1e-10)
     trace, acc = [], 0
@@ -258,3 +266,45 @@ def test_hmc_chain_samples_exact_marginal_posterior():
         print(k, "mean %.3f exact %.3f se %.3f" % (x[:, k].mean(), exact[k], se))
         assert abs(x[:, k].mean() - exact[k]) < 4.0 * se, (k, x[:, k].mean(), exact[k], se)
     assert 0.5 < acc / 300 <= 1.0
+
+
+# ------------------------------------------------ standard Gibbs over bins
+def test_bin_gibbs_conditional_parameters():
+    # per-bin t_b from the dense real coordinates of the sky (variance C_l / W
+    # per coordinate) against the step's, the shapes from the bins' real
+    # degrees of freedom, and A_b = (t_b / 2) / g_b
+    wl, P, op, d = _tiny(2, 4)
+    edges = [2, 3, 5]
+    rng = np.random.default_rng(13)
+    st = joint.init_bin_state(P, d, edges, np.array([0.2, -0.1]), ci.white_alm(rng, P.lmax),
+                              rng.standard_normal(d.size), 1e-12)
+    D = dense.DenseY(P.nside, P.lmax, lmin=2)
+    u = D.to_real(st.ahat + st.fhat)
+    var1 = D._per_dof(P.cl) / D.W
+    lsd = D._per_dof(np.arange(P.lmax + 1, dtype=np.float64))
+    tb = [float(np.sum((u * u / var1)[(lsd >= edges[k]) & (lsd < edges[k + 1])])) for k in range(2)]
+    kb = [int(np.sum((lsd >= edges[k]) & (lsd < edges[k + 1]))) for k in range(2)]
+    assert np.allclose(joint.gibbs_bins_shape(P, edges), 0.5 * np.array(kb) - 1.0)
+    g = np.array([1.7, 6.2])
+    new, t = joint.gibbs_bins_step(P, d, edges, st, g, ci.white_alm(rng, P.lmax), rng.standard_normal(d.size), 1e-10)
+    assert np.allclose(t, tb, rtol=1e-12)
+    assert np.allclose(np.exp(new.theta), 0.5 * np.array(tb) / g, rtol=1e-12)
+
+
+def test_bin_gibbs_chain_samples_exact_marginal_posterior():
+    wl, P, op, d = _tiny(2, 4)
+    edges = [2, 3, 5]
+    exact = _two_bin_exact(P, d, edges)
+    alpha = joint.gibbs_bins_shape(P, edges)
+    rng = np.random.default_rng(9)
+    st = joint.init_bin_state(P, d, edges, np.zeros(2), ci.white_alm(rng, P.lmax), rng.standard_normal(d.size), 1e-10)
+    trace = []
+    for _ in range(400):
+        st, _ = joint.gibbs_bins_step(P, d, edges, st, rng.gamma(alpha), ci.white_alm(rng, P.lmax),
+                                      rng.standard_normal(d.size), 1e-8)
+        trace.append(st.theta.copy())
+    x = np.array(trace[50:])
+    for k in range(2):
+        se = x[:, k].std() * math.sqrt(_iat(x[:, k]) / x.shape[0])
+        print(k, "mean %.3f exact %.3f se %.3f" % (x[:, k].mean(), exact[k], se))
+        assert abs(x[:, k].mean() - exact[k]) < 4.0 * se, (k, x[:, k].mean(), exact[k], se)
