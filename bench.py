@@ -17,7 +17,7 @@ replay each block of check_every PCG iterations as a captured HIP graph; the
 per-kernel launch times come from one extra step with HIP events around every
 launch of the tracked kernels.
 
-Prints one JSON line. --gpus N with N > 1 is refused: this build runs on one
+Prints one JSON line. --gpus N with N > 1 is refused: the benchmark runs on one
 GPU.
 """
 from __future__ import annotations
@@ -320,7 +320,7 @@ def main():
                     help="default: block (per-m blocks, one set per component)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; --gpus %d is not supported "
+        print("bench.py: the benchmark measures one GPU only; --gpus %d is not supported "
               "(independent chains would shard one per GPU with no communication)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched64":

@@ -64,7 +64,7 @@ enum {
   CR_EINVAL = -1,    /* invalid argument (sizes, NULL pointers, bad spectra) */
   CR_ENOMEM = -2,    /* device allocation failed at plan creation */
   CR_EDEVICE = -3,   /* a HIP runtime call or kernel launch failed */
-  CR_ENOTSUP = -4,   /* valid but not supported by this build */
+  CR_ENOTSUP = -4,   /* valid but not supported by this library */
   CR_NOCONV = 1,     /* maxiter reached; the last iterate is written */
   CR_BREAKDOWN = 2   /* <p, A p> <= 0 or non-finite; output undefined */
 };

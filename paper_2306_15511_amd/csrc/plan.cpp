@@ -405,7 +405,7 @@ extern "C" const char* crsht_strerror(int status) {
     case CR_EINVAL: return "invalid argument";
     case CR_ENOMEM: return "device allocation failed";
     case CR_EDEVICE: return "HIP runtime error";
-    case CR_ENOTSUP: return "not supported by this build";
+    case CR_ENOTSUP: return "not supported by this library";
     case CR_NOCONV: return "maximum iterations reached before the tolerance";
     case CR_BREAKDOWN: return "conjugate-gradient breakdown (non-positive or non-finite curvature)";
     default: return "unknown status";
