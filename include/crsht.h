@@ -276,7 +276,9 @@ int cr_solve_batched(const crsht_plan *const *plans, const cr_problem *probs, in
  * amplitude-scaled spectrum C_l(q) = q cl:
  *   ln pi = -1/2 (d - Y B a)^T N^-1 (d - Y B a) - 1/2 a^T S(q)^-1 a - 1/2 f^T B Y^T N^-1 Y B f
  * d: device map; ahat, fhat: device alm [nalm]. Result to *lnpi (host).
- * Temperature plans only (CR_ENOTSUP for ncomp = 3). Blocks until done. */
+ * T+Q+U plans: d [3][npix], ahat, fhat [3][nalm]; the chi^2 and fluctuation
+ * terms summed over T, Q, U with their N^-1, the prior with the 3x3 blocks of
+ * S(q)^-1. Blocks until done. */
 int cr_lnpi(const crsht_plan *plan, const cr_problem *fid, double q, const double *d, const double *ahat,
             const double *fhat, double *lnpi, void *stream);
 
@@ -307,7 +309,8 @@ typedef struct {
 } cr_step_out;
 
 /* One joint C_l-amplitude / sky move (paper Sect. 2.2.2, algorithm steps 2-4),
- * temperature plans (ncomp = 1; CR_ENOTSUP otherwise):
+ * temperature and T+Q+U plans (all four spectra scaled by q; states of
+ * [3][nalm] coefficients, maps [3][npix]):
  * propose q' = q exp(sigma xi); solve the mean field at q'; rescale the
  * fluctuation by sqrt(q'/q); ln A = ln pi(q') - ln pi(q) + ln(q'/q) (uniform
  * prior in q; Gaussian proposal in ln q); accept iff ln u < ln A, and only then

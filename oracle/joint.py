@@ -247,3 +247,41 @@ def gibbs_bins_step(fid: Problem, d, edges, state: BinState, g, w0_new, w1_new, 
     ahat, _ = pcg(op, op.rhs(d=d), tol, maxiter)
     fhat, _ = pcg(op, op.rhs(w0=w0_new, w1=w1_new), tol, maxiter)
     return BinState(theta, ahat, fhat, lnpi(op, d, ahat, fhat)), t
+
+
+# ------------------------------------------------ T+Q+U ln pi and joint move
+def lnpi_terms_tqu(op, d, ahat, fhat):
+    """(chi^2, a^T S^-1 a, f^T B^T N^-1 B f) of a T+Q+U problem
+    (oracle.cr_tqu.CROperatorTQU; maps [3][npix], alm [3][nalm])."""
+    n = op._ninv()
+    res = d - op.synth(op.b * op.project(ahat))
+    chi2 = float(np.sum(n * res * res))
+    a = op.project(ahat)
+    prior = op.dot(a, op._block(op.sinv_lm, a))
+    ff = op.synth(op.b * op.project(fhat))
+    return chi2, prior, float(np.sum(n * ff * ff))
+
+
+def lnpi_tqu(op, d, ahat, fhat) -> float:
+    return -0.5 * sum(lnpi_terms_tqu(op, d, ahat, fhat))
+
+
+def joint_step_tqu(fid, d, state: ChainState, xi: float, u: float, w0_new, w1_new, sigma_lnq: float, tol: float,
+                   maxiter: int = 20000):
+    """joint_step for a T+Q+U problem (all four spectra scaled by q)."""
+    from .cr_tqu import CROperatorTQU, ProblemTQU
+
+    def op_at(q):
+        return CROperatorTQU(ProblemTQU(fid.nside, fid.lmax, fid.cl * q, fid.bl, fid.ninv_t, fid.ninv_p, fid.lmin))
+
+    q_new = state.q * math.exp(sigma_lnq * xi)
+    op = op_at(q_new)
+    ahat, _ = pcg(op, op.rhs(d=d), tol, maxiter)
+    f_scaled = math.sqrt(q_new / state.q) * state.fhat
+    lp_new = lnpi_tqu(op, d, ahat, f_scaled)
+    lnA = lp_new - state.lnpi + math.log(q_new / state.q)
+    accepted = math.log(u) < lnA
+    if not accepted:
+        return state, StepResult(False, lnA, q_new, lp_new)
+    fhat, _ = pcg(op, op.rhs(w0=w0_new, w1=w1_new), tol, maxiter)
+    return ChainState(q_new, ahat, fhat, lnpi_tqu(op, d, ahat, fhat)), StepResult(True, lnA, q_new, lp_new)

@@ -706,8 +706,43 @@ int quad_sinv(const crsht_plan* P, const double2* a, double* t, hipStream_t s) {
 }
 
 // terms of ln pi into host t[3]: chi^2 of the mean field, a^T S^-1 a, f^T B^T N^-1 B f
+// T+Q+U: chi^2 and the fluctuation term summed over T, Q, U (maps
+// [3][npix], ninv [3][npix]); the prior with the 3x3 blocks of S^-1
+int lnpi_terms_tqu(const crsht_plan* P, const double* ninv, const double* d, const double2* ahat, const double2* fhat,
+                   double t[3], hipStream_t s) {
+  const int npart = P->w.npart;
+  const int nbp = std::min<int64_t>(npart, (P->g.npix + 255) / 256);
+  const int nba = std::min<int64_t>(npart, (P->g.nalm + 255) / 256);
+  const int64_t np = P->g.npix;
+  double* pa = P->w.partial;
+  auto sum3 = [&](int nb) -> double {
+    if (launch_sum_rows(P, 1, nb, s) != hipSuccess) return NAN;
+    if (read_scalars(P, 1, s) != CR_OK) return NAN;
+    return P->w.host_scal[S_AUX0] + P->w.host_scal[S_AUX1] + P->w.host_scal[S_AUX2];
+  };
+  // chi^2: rows 0..2 = T, Q, U
+  CR_TRY(hipMemsetAsync(pa, 0, 3 * (size_t)npart * sizeof(double), s));
+  CR_CHECK(synth_f64(P, 1, ahat, P->w.bl_keep, P->w.map_a, s));
+  for (int k = 0; k < 3; ++k)
+    CR_TRY(launch_pix_wsq(P, ninv + k * np, d + k * np, P->w.map_a + k * np, pa + k * npart, nbp, s));
+  t[0] = sum3(nbp);
+  // prior: row 0
+  CR_TRY(hipMemsetAsync(pa, 0, 3 * (size_t)npart * sizeof(double), s));
+  CR_TRY(launch_alm_wquad_tqu(P, ahat, pa, nba, s));
+  t[1] = sum3(nba);
+  // fluctuation term: rows 0..2 = T, Q, U
+  CR_TRY(hipMemsetAsync(pa, 0, 3 * (size_t)npart * sizeof(double), s));
+  CR_CHECK(synth_f64(P, 1, fhat, P->w.bl_keep, P->w.map_a, s));
+  for (int k = 0; k < 3; ++k)
+    CR_TRY(launch_pix_wsq(P, ninv + k * np, P->w.map_a + k * np, nullptr, pa + k * npart, nbp, s));
+  t[2] = sum3(nbp);
+  if (!std::isfinite(t[0]) || !std::isfinite(t[1]) || !std::isfinite(t[2])) return CR_EDEVICE;
+  return CR_OK;
+}
+
 int lnpi_terms(const crsht_plan* P, const double* ninv, const double* d, const double2* ahat, const double2* fhat,
                double t[3], hipStream_t s) {
+  if (P->ncomp == 3) return lnpi_terms_tqu(P, ninv, d, ahat, fhat, t, s);
   const int npart = P->w.npart;
   const int nbp = std::min<int64_t>(npart, (P->g.npix + 255) / 256);
   const int nba = std::min<int64_t>(npart, (P->g.nalm + 255) / 256);
@@ -910,7 +945,6 @@ extern "C" int cr_solve_batched(const crsht_plan* const* plans, const cr_problem
 extern "C" int cr_lnpi(const crsht_plan* P, const cr_problem* fid, double q, const double* d, const double* ahat,
                        const double* fhat, double* lnpi, void* stream) {
   CR_CHECK(check_plan(P, 1));
-  if (P->ncomp != 1) return CR_ENOTSUP;
   if (!d || !ahat || !fhat || !lnpi) return CR_EINVAL;
   hipStream_t s = S(stream);
   CR_CHECK(set_problem(P, fid, q, s));
@@ -1015,7 +1049,6 @@ extern "C" int joint_cl_step(const crsht_plan* P, const cr_problem* fid, const d
                              const cr_draws* dr, const cr_opts* opts, cr_step_out* out, void* stream) {
   CR_CHECK(check_plan(P, 1));
   if (fid && fid->amp) return CR_EINVAL;   // one spectrum per call
-  if (P->ncomp != 1) return CR_ENOTSUP;
   if (!fid || !d || !state || !dr || !opts || !out || !state->ahat || !state->fhat) return CR_EINVAL;
   if (!(dr->sigma_lnq > 0.0) || !(dr->u > 0.0 && dr->u < 1.0) || !std::isfinite(dr->xi)) return CR_EINVAL;
   if (!(state->q > 0.0) || !std::isfinite(state->lnpi)) return CR_EINVAL;
@@ -1027,7 +1060,7 @@ extern "C" int joint_cl_step(const crsht_plan* P, const cr_problem* fid, const d
   double* ahat_n = reinterpret_cast<double*>(P->w.alm_c);
   CR_CHECK(solve_core(P, fid, qn, 1, d, nullptr, nullptr, nullptr, ahat_n, opts, &out->mean_stats, s, state->ahat));
   // 2) rescaled fluctuation sqrt(q'/q) f
-  const int64_t na = P->g.nalm;
+  const int64_t na = vlen(P);   // coefficients of one state (3 nalm for T+Q+U)
   CR_TRY(launch_alm_axpby(na, std::sqrt(qn / state->q), C2(state->fhat), 0.0, nullptr, P->w.alm_d, s));
   // 3) ln pi(q') and ln A (problem factors are still those of q')
   double t[3];

@@ -358,6 +358,8 @@ hipError_t launch_mweight(const crsht_plan* P, int nrhs, double2* a, hipStream_t
 hipError_t launch_bin_grad(const crsht_plan* P, int nbins, const int* edges, const double2* ahat,
                            const double2* fhat, const double2* lam, const double2* w0, double* grad,
                            hipStream_t s, int mode = 0);
+// partials of a^T S^-1 a with the 3x3 blocks of a T+Q+U plan (nb blocks)
+hipError_t launch_alm_wquad_tqu(const crsht_plan* P, const double2* a, double* partial, int nb, hipStream_t s);
 // Gaussian white draws (Philox4x32-10 + Box-Muller) of nrhs columns: w0
 // [nrhs][nalm] white a_lm of a real field, w1 [nrhs][npix]; either may be null
 hipError_t launch_white(const crsht_plan* P, int nrhs, uint64_t seed, uint64_t counter, double2* w0, double* w1,

@@ -233,6 +233,23 @@ __global__ void k_cg_q_tqu(int64_t nalm, const int* __restrict__ idx_l, const in
   if (threadIdx.x == 0) partial[(size_t)c * npart * 4 + blockIdx.x] = pq;
 }
 
+// partial of a^T S^-1 a (3x3 blocks per l, real-field product) per block
+__global__ void k_alm_wquad_tqu(int64_t nalm, const int* __restrict__ idx_l, const int* __restrict__ idx_m,
+                                const double* __restrict__ sblk, const double2* __restrict__ a,
+                                double* __restrict__ partial) {
+  __shared__ double sh[kVecT];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nalm; i += (int64_t)gridDim.x * blockDim.x) {
+    const int m = idx_m[i];
+    const double2 t = a[i], e = a[nalm + i], b = a[2 * nalm + i];
+    double2 ot, oe, ob;
+    block3(sblk + 8 * idx_l[i], t, e, b, ot, oe, ob);
+    acc += wdot(m, t, ot) + wdot(m, e, oe) + wdot(m, b, ob);
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
 // out = dterm + camp[c].y S^-1/2 w0 per column c (either term may be null),
 // Im of m = 0 set to 0
 __global__ void k_rhs_finish_tqu(int64_t nalm, int nrhs, const int* __restrict__ idx_l, const int* __restrict__ idx_m,
@@ -350,6 +367,12 @@ hipError_t launch_pol_combine_adjoint(const crsht_plan* P, int nrhs, const doubl
 hipError_t launch_expand_tqu(const crsht_plan* P, const double* perl, hipStream_t s) {
   hipLaunchKernelGGL(k_expand_tqu, dim3(nblk(P->g.nalm)), dim3(kVecT), 0, s, P->g.nalm, P->g.lmax, P->t.idx_l,
                      P->t.rec_kappa, P->w.sblk, perl, P->w.sinv, P->w.sinvhalf, P->w.bk, P->w.bl_keep);
+  return hipGetLastError();
+}
+
+hipError_t launch_alm_wquad_tqu(const crsht_plan* P, const double2* a, double* partial, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_alm_wquad_tqu, dim3(nb), dim3(kVecT), 0, s, P->g.nalm, P->t.idx_l, P->t.idx_m, P->w.sblk, a,
+                     partial);
   return hipGetLastError();
 }
 

@@ -378,3 +378,45 @@ def test_tqu_column_amplitudes():
         xo, info = cr.pcg(oc, oc.rhs(d[c], w0[c], w1[c]), 1e-13, 5000)
         assert info.converged and st[c].status == 0
         assert real_rel3(oc, s.cpu().numpy()[c], xo) < TOL
+
+
+def test_tqu_lnpi_and_joint_step():
+    # ln pi of a T+Q+U state (at q = 1 and rescaled) and the joint move
+    # (accepted, then rejected) against the oracle with the same numbers
+    from oracle import joint
+    m = _m()
+    nside = 4
+    print("case tqu joint step", flush=True)
+    wl, P, op = _problem(nside, 11)
+    plan = m.Plan(nside, P.lmax, ncomp=3)
+    gp = _gpu_problem(m, P)
+    rng = np.random.default_rng(19)
+    d = _data(rng, op, P)
+    npix = op.sht.npix
+    w0 = np.stack([ci.white_alm(rng, P.lmax) for _ in range(3)])
+    w1 = rng.standard_normal((3, npix))
+    tol = 1e-12
+    a, _ = cr.pcg(op, op.rhs(d=d), 1e-13)
+    f, _ = cr.pcg(op, op.rhs(w0=w0, w1=w1), 1e-13)
+    lp = joint.lnpi_tqu(op, d, a, f)
+    assert abs(m.lnpi(plan, gp, 1.0, tc(d), tc(a), tc(f)) - lp) <= 1e-10 * abs(lp)
+    op13 = cr_tqu.CROperatorTQU(cr_tqu.ProblemTQU(nside, P.lmax, P.cl * 1.3, P.bl, P.ninv_t, P.ninv_p, P.lmin))
+    lp13 = joint.lnpi_tqu(op13, d, a, f)
+    assert abs(m.lnpi(plan, gp, 1.3, tc(d), tc(a), tc(f)) - lp13) <= 1e-10 * abs(lp13)
+    st = joint.ChainState(1.0, a, f, lp)
+    ch = m.Chain(1.0, lp, tc(a), tc(f))
+    for xi, u in ((0.4, 1e-300), (60.0, 1.0 - 1e-12)):
+        w0n = np.stack([ci.white_alm(rng, P.lmax) for _ in range(3)])
+        w1n = rng.standard_normal((3, npix))
+        res = m.joint_step(plan, gp, tc(d), ch, xi, u, tc(w0n), tc(w1n), sigma_lnq=0.05, tol=tol)
+        new, r = joint.joint_step_tqu(P, d, st, xi, u, w0n, w1n, 0.05, tol)
+        print("lnA gpu %.12e oracle %.12e accepted %s/%s" % (res.lnA, r.lnA, res.accepted, r.accepted), flush=True)
+        assert res.accepted == r.accepted
+        assert res.q_new == r.q_new
+        assert abs(res.lnA - r.lnA) <= 1e-7 * max(1.0, abs(st.lnpi))
+        assert abs(ch.q - new.q) <= 1e-15 * new.q and abs(ch.lnpi - new.lnpi) <= 1e-9 * abs(new.lnpi)
+        opn = cr_tqu.CROperatorTQU(cr_tqu.ProblemTQU(nside, P.lmax, P.cl * new.q, P.bl, P.ninv_t, P.ninv_p, P.lmin))
+        assert real_rel3(opn, ch.ahat.cpu().numpy(), new.ahat) < 1e-8
+        assert real_rel3(opn, ch.fhat.cpu().numpy(), new.fhat) < 1e-8
+        st = new
+    assert ch.q == st.q

@@ -308,3 +308,40 @@ def test_bin_gibbs_chain_samples_exact_marginal_posterior():
         se = x[:, k].std() * math.sqrt(_iat(x[:, k]) / x.shape[0])
         print(k, "mean %.3f exact %.3f se %.3f" % (x[:, k].mean(), exact[k], se))
         assert abs(x[:, k].mean() - exact[k]) < 4.0 * se, (k, x[:, k].mean(), exact[k], se)
+
+
+def test_tqu_lnpi_reduces_to_temperature_without_polarisation_data():
+    # with N_P^-1 = 0 and C^TE = 0 the E and B mean fields vanish and their
+    # fluctuations never reach the data term, so ln pi of T+Q+U equals the
+    # temperature ln pi of the same T problem; with polarisation data the
+    # extra terms are present (the reduction is not trivially met)
+    from oracle import cr_tqu
+    nside, lmax = 4, 11
+    wl = ci.workload_masked_t(nside, lmax)
+    z, phi = healpix.pixel_coords(nside)
+    nt = wl.ninv(z, phi)
+    cl = ci.cl_tqu(lmax, wl.amp, 0.0)
+    P3 = cr_tqu.ProblemTQU(nside, lmax, cl, wl.bl(), nt, np.zeros_like(nt))
+    op3 = cr_tqu.CROperatorTQU(P3)
+    P1 = cr.Problem(nside, lmax, cl[0], wl.bl(), nt)
+    op1 = cr.CROperator(P1)
+    rng = np.random.default_rng(4)
+    d3 = np.stack([op1.sht.synth(op1.b * wl.signal()) + wl.noise(z, phi), rng.standard_normal(nt.size),
+                   rng.standard_normal(nt.size)])
+    w0 = np.stack([ci.white_alm(rng, lmax) for _ in range(3)])
+    w1 = rng.standard_normal((3, nt.size))
+    a3, _ = cr.pcg(op3, op3.rhs(d=d3), 1e-13)
+    f3, _ = cr.pcg(op3, op3.rhs(w0=w0, w1=w1), 1e-13)
+    a1, _ = cr.pcg(op1, op1.rhs(d=d3[0]), 1e-13)
+    f1, _ = cr.pcg(op1, op1.rhs(w0=w0[0], w1=w1[0]), 1e-13)
+    assert np.max(np.abs(a3[1:])) < 1e-12 * np.max(np.abs(a3[0]))
+    # the fluctuation's E, B parts are prior draws: their prior term stays, so
+    # compare the terms: chi^2 and the data term of f equal, the prior of a equal
+    t3 = joint.lnpi_terms_tqu(op3, d3, a3, f3)
+    t1 = joint.lnpi_terms(op1, d3[0], a1, f1)
+    for x, y in zip(t3, t1):
+        assert abs(x - y) <= 1e-9 * max(1.0, abs(y)), (t3, t1)
+    P3p = cr_tqu.ProblemTQU(nside, lmax, cl, wl.bl(), nt, nt / 2.0)
+    op3p = cr_tqu.CROperatorTQU(P3p)
+    a3p, _ = cr.pcg(op3p, op3p.rhs(d=d3), 1e-13)
+    assert abs(joint.lnpi_terms_tqu(op3p, d3, a3p, f3)[0] - t1[0]) > 1e-3 * abs(t1[0])
