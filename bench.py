@@ -254,6 +254,8 @@ def bench_chains(args):
         dt = time.perf_counter() - t0
         out[name] = dict(run.summary(), moves_per_s=args.chains * args.steps / dt, s=dt,
                          fluct_iters=float(run.fluct_iters.mean()))
+        print("%s: %.1f moves/s, acceptance %.3f, iat ln q %.2f" % (name, out[name]["moves_per_s"],
+              out[name]["acceptance"], out[name]["iat_lnq"]), file=sys.stderr, flush=True)
     # HMC on theta = ln q (one bin over every kept l): step from the target's
     # curvature at the start (half its width), trajectories of three steps
     edges = [2, lmax + 1]
