@@ -230,9 +230,10 @@ def bench_chains(args):
     cl, bl = wl.cl(), wl.bl()
     ls, _ = ci.alm_lm_arrays(lmax)
     a = torch.from_numpy(bl[ls] * ci.signal_alm(ci.rng_for(2, 0, ci.STREAM_SIGNAL), cl, lmax)).to(dev)
-    d = crsht.synth(plan, a) + torch.from_numpy(wl.sigma_map(z, phi) *
+    ns = args.noise_scale   # noise level relative to the headline sky (N -> ns^2 N)
+    d = crsht.synth(plan, a) + torch.from_numpy(ns * wl.sigma_map(z, phi) *
                                                 ci.white_map(ci.rng_for(2, 0, ci.STREAM_NOISE), wl.npix)).to(dev)
-    fid = crsht.Problem(cl, bl, torch.from_numpy(wl.ninv(z, phi)).to(dev), 2)
+    fid = crsht.Problem(cl, bl, torch.from_numpy(wl.ninv(z, phi) / (ns * ns)).to(dev), 2)
     crsht.block_precond_build(plan, fid)
     kw = dict(tol=args.tol, prec=crsht.CR_MIXED if args.prec == "mixed" else crsht.CR_F64,
               inner_tol=args.inner_tol, precond=crsht.CR_PC_BLOCK)
@@ -287,8 +288,8 @@ def bench_chains(args):
                                "call per step, also one chain after another), standard Gibbs moves and HMC moves of "
                                "ln q (Gibbs moves also batched), T-only, Nside %d, "
                                "lmax %d, hit-pattern noise, |b|<20deg mask, FWHM 10', true residual %g, per-m block "
-                               "preconditioner, warm-started mean fields, w0 and w1 drawn on the device (Philox4x32-10)"
-                               % (args.chains, nside, lmax, args.tol),
+                               "preconditioner, warm-started mean fields, w0 and w1 drawn on the device (Philox4x32-10), "
+                               "noise x %g" % (args.chains, nside, lmax, args.tol, args.noise_scale),
                    "chains": args.chains},
         "joint": out["joint"], "joint_batched": out["joint_batched"], "gibbs": out["gibbs"],
         "gibbs_batched": out["gibbs_batched"], "hmc": out["hmc"],
@@ -315,6 +316,8 @@ def main():
     ap.add_argument("--no-f64-compare", action="store_true")
     ap.add_argument("--workload", choices=["headline", "tqu", "batched64", "chains"], default="headline")
     ap.add_argument("--chains", type=int, default=4, help="--workload chains: number of chains")
+    ap.add_argument("--noise-scale", type=float, default=1.0,
+                    help="--workload chains: noise standard deviation relative to the headline sky")
     ap.add_argument("--chain-columns", action="store_true",
                     help="headline/tqu: the columns are the mean-field and fluctuation systems of nrhs/2 chains, "
                          "each at its own amplitude q ~ U[0.8, 1.25] (one solve for all)")
