@@ -52,7 +52,7 @@ TRAFFIC = {
     "k_ring<RING_FUSED>": {"bytes": 4 * 212896371, "src": "664ab76c607be629"},   # one fused pass (4 class launches)
     "k_legendre_synth_mfma": {"bytes": 680437984, "src": "34e5a8a115b9d7fc"},    # one launch of 8 columns
     "k_legendre_adj_mfma": {"bytes": 2 * 606571360, "src": "34e5a8a115b9d7fc"},  # one transform (2 launches)
-    "k_pc_apply": {"bytes": 3539768550, "src": "53b332e687b51ce1"},
+    "k_pc_apply": {"bytes": 3086747669, "src": "b178efe54277f7b9"},
 }
 
 

@@ -297,20 +297,35 @@ __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3
         }
       }
     }
-    if (i0 < n) {
-      const int rhs = il >> 1, comp = il & 1;
-      if (rhs < nc) {
-        // row i0 + 16 kk + rr, rr = 4 (8 (q / 4) + q % 4) + v: one base pointer, constant offsets
-        const int ib = i0 + 16 * kk;
-        double* __restrict__ zb = reinterpret_cast<double*>(z + (int64_t)(c0 + rhs) * vlen + e00 + w + 2 * ib) + comp;
+    // results through LDS (the rs tile, free after the last products), 8
+    // columns at a time, then written as whole rows of both parities: the
+    // task's 256 interleaved coefficients of a column are contiguous
+    float* stage = &rs[0][0][0];   // [8 columns][256 coefficients][re, im]
+    const int rhs = il >> 1, comp = il & 1;
+    const int ib = i0 + 16 * kk;
+#pragma unroll 1
+    for (int h = 0; h < kPcCols; h += 8) {
+      __syncthreads();   // the products (or the previous half's writes) have read the tile
+      if (i0 < n && rhs >= h && rhs < h + 8) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const f32x16_t a = v == 0 ? acc0 : v == 1 ? acc1 : v == 2 ? acc2 : acc3;
 #pragma unroll
           for (int q = 0; q < 16; ++q) {
             const int rr = 4 * (8 * (q / 4) + (q % 4)) + v;
-            if (ib + rr < n) zb[4 * rr] = a[q];
+            stage[((rhs - h) * 256 + 2 * (ib - i0 + rr) + w) * 2 + comp] = a[q];
           }
+        }
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int k = 0; k < 8 * 256 / (kPcWaves * 64); ++k) {
+        const int idx = threadIdx.x + k * kPcWaves * 64;
+        const int cc = idx >> 8, er = idx & 255;
+        const int c = h + cc, q = er & 1, row = i0 + (er >> 1);
+        if (c < nc && row < (q ? n1 : n0)) {
+          const float* v = stage + idx * 2;
+          z[(int64_t)(c0 + c) * vlen + e00 + 2 * i0 + er] = make_double2((double)v[0], (double)v[1]);
         }
       }
     }
