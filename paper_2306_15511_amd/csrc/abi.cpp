@@ -1181,7 +1181,7 @@ void bin_factor(int lmax, int nbins, const int* edges, const double* x, double c
 // fluctuation to w.alm_d; edges are already in w.bin_edges.
 int lnpi_grad_u(const crsht_plan* P, const cr_problem* fid, const double* d, int nbins, const int* edges,
                 const double* theta0, const double* theta, const double* f0, const double* a0, const cr_opts* opts,
-                double* lnpi, double* grad, cr_stats* st, hipStream_t s) {
+                double* lnpi, double* grad, cr_stats* st, hipStream_t s, const double* rhs_d = nullptr) {
   Workspace const& w = P->w;
   const int lmax = P->g.lmax;
   std::vector<double> fac, cl(lmax + 1), dth(nbins), lf;
@@ -1189,8 +1189,10 @@ int lnpi_grad_u(const crsht_plan* P, const cr_problem* fid, const double* d, int
   for (int l = 0; l <= lmax; ++l) cl[l] = fid->cl[l] * fac[l];
   cr_problem pr = *fid;
   pr.cl = cl.data();
-  CR_CHECK(solve_core(P, &pr, 1.0, 1, d, nullptr, nullptr, nullptr, reinterpret_cast<double*>(w.alm_c), opts, st, s,
-                      a0));
+  // the mean-field right-hand side B Y^T N^-1 d does not depend on theta: rhs_d,
+  // when given, holds it (device, [nalm]) and spares its adjoint transform
+  CR_CHECK(solve_core(P, &pr, 1.0, 1, rhs_d ? nullptr : d, nullptr, nullptr, rhs_d,
+                      reinterpret_cast<double*>(w.alm_c), opts, st, s, a0));
   for (int k = 0; k < nbins; ++k) dth[k] = theta[k] - theta0[k];
   bin_factor(lmax, nbins, edges, dth.data(), 0.5, lf);
   CR_TRY(hipMemcpyAsync(w.lfac, lf.data(), (size_t)(lmax + 1) * sizeof(double), hipMemcpyHostToDevice, s));
@@ -1241,13 +1243,16 @@ extern "C" int hmc_cl_step(const crsht_plan* P, const cr_problem* fid, const dou
   Workspace const& w = P->w;
   std::memset(out, 0, sizeof(*out));
   CR_TRY(hipMemcpyAsync(w.bin_edges, st->edges, (size_t)(nb + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  // the mean-field right-hand side, the same at every point of the trajectory
+  CR_CHECK(set_problem(P, fid, 1.0, s));
+  CR_CHECK(assemble_rhs(P, 1, fid->ninv, d, nullptr, nullptr, w.cg_xacc, s));
   // potential U = -ln pi - sum theta (uniform prior in the amplitudes exp(theta_k)), dU = -grad - 1
   std::vector<double> th0(st->theta, st->theta + nb), th(th0), p(dr->p0, dr->p0 + nb), g(nb);
   double lp = 0.0;
   cr_stats cs;
   auto eval = [&](const double* a0) -> int {
-    CR_CHECK(lnpi_grad_u(P, fid, d, nb, st->edges, th0.data(), th.data(), st->fhat, a0, opts, &lp, g.data(), &cs,
-                         s));
+    CR_CHECK(lnpi_grad_u(P, fid, d, nb, st->edges, th0.data(), th.data(), st->fhat, a0, opts, &lp, g.data(), &cs, s,
+                         reinterpret_cast<const double*>(w.cg_xacc)));
     out->iters += cs.iters;
     out->solves += 1;
     if (cs.status != CR_OK) out->status = cs.status;
