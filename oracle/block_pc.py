@@ -48,10 +48,15 @@ class BlockPreconditioner:
         self.lmax, self.mmax = lmax, mmax
         ls, ms = lm_arrays(lmax, mmax)
         self.idx = [np.flatnonzero(ms == m) for m in range(mmax + 1)]   # l = m .. lmax
-        lam = [np.zeros((lmax - m + 1, R.nrings)) for m in range(mmax + 1)]
-        for l, row in lambda_rows(lmax, mmax, R.z, R.sin_theta):
-            for m in range(row.shape[0]):
-                lam[m][l - m] = row[m]
+        if getattr(sht, "fast", False):
+            # the same lambda_lm from the plain-C recurrence, one m at a time
+            from .clegendre import lambda_m
+            lam = [lambda_m(lmax, m, R.z, R.sin_theta) for m in range(mmax + 1)]
+        else:
+            lam = [np.zeros((lmax - m + 1, R.nrings)) for m in range(mmax + 1)]
+            for l, row in lambda_rows(lmax, mmax, R.z, R.sin_theta):
+                for m in range(row.shape[0]):
+                    lam[m][l - m] = row[m]
         self.blocks = []
         self.inv = []
         for m in range(mmax + 1):

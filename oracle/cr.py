@@ -15,7 +15,8 @@ Readings used here:
   B Y^T N^-1 Y B;
 * PCG starts from x0 = 0 and stops when the relative residual
   ||r|| / ||b|| (real-field norm) is at most tol; the recursively updated
-  residual is confirmed against the true residual b - A x before stopping
+  residual is replaced by the true residual b - A x every 50 iterations
+  (the search direction is kept), and confirmed against it before stopping
   (if it fails, the iteration restarts from the true residual).
 """
 from __future__ import annotations
@@ -105,10 +106,11 @@ class PCGInfo:
 
 
 def pcg(op, b: np.ndarray, tol: float, maxiter: int = 10000, precond=None,
-        x0: np.ndarray | None = None) -> tuple[np.ndarray, PCGInfo]:
+        x0: np.ndarray | None = None, replace_every: int = 50) -> tuple[np.ndarray, PCGInfo]:
     """Preconditioned conjugate gradients in the real-field inner product.
     precond: None (Jacobi diagonal of op), an array D (z = r / D) or a
-    callable r -> z (symmetric positive definite)."""
+    callable r -> z (symmetric positive definite). Every replace_every
+    iterations r is replaced by the true residual b - A x."""
     if callable(precond):
         apply_pc = precond
     else:
@@ -130,6 +132,8 @@ def pcg(op, b: np.ndarray, tol: float, maxiter: int = 10000, precond=None,
         x = x + alpha * p
         r = r - alpha * q
         it += 1
+        if replace_every and it % replace_every == 0:
+            r = b - op.apply(x)
         rel = op.norm(r) / bnorm
         hist.append(rel)
         if rel <= tol:

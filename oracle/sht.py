@@ -58,9 +58,14 @@ def dot(a: np.ndarray, c: np.ndarray, lmax: int, mmax: int) -> float:
 
 
 class SHT:
-    """Y and Y^T for one (nside, lmax, mmax)."""
+    """Y and Y^T for one (nside, lmax, mmax).
 
-    def __init__(self, nside: int, lmax: int, mmax: int | None = None):
+    fast=True evaluates the two Legendre sums with the plain-C loops of
+    ``clegendre`` (the same recurrence and sums, for the large workloads);
+    the azimuthal step is numpy's FFT either way."""
+
+    def __init__(self, nside: int, lmax: int, mmax: int | None = None, fast: bool = False):
+        self.fast = fast
         self.nside, self.lmax = nside, lmax
         self.mmax = lmax if mmax is None else mmax
         if self.mmax > lmax:
@@ -78,6 +83,9 @@ class SHT:
     def legendre_synth(self, alm: np.ndarray) -> np.ndarray:
         """F[m, r] = sum_l lambda_lm(z_r) a_lm (complex)."""
         R = self.rings
+        if self.fast:
+            from . import clegendre
+            return clegendre.legendre_synth(self.lmax, self.mmax, R.z, R.sin_theta, alm)
         F = np.zeros((self.mmax + 1, R.nrings), dtype=np.complex128)
         for l, lam in lambda_rows(self.lmax, self.mmax, R.z, R.sin_theta):
             top = lam.shape[0] - 1
@@ -87,6 +95,9 @@ class SHT:
     def legendre_adjoint(self, G: np.ndarray, square: bool = False) -> np.ndarray:
         """out_lm = sum_r lambda_lm(z_r) G[m, r] (lambda^2 if square)."""
         R = self.rings
+        if self.fast:
+            from . import clegendre
+            return clegendre.legendre_adjoint(self.lmax, self.mmax, R.z, R.sin_theta, G, square)
         out = np.zeros(self.nalm, dtype=np.complex128)
         for l, lam in lambda_rows(self.lmax, self.mmax, R.z, R.sin_theta):
             top = lam.shape[0] - 1
