@@ -545,6 +545,7 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
   rel.assign(nrhs, 1.0);
   int it = 0, nrep = 0, checks = 0;
   bool pending = false;                  // direction update of the last iteration not yet applied
+  bool fresh = false;                    // rel[] is the true residual of the current x
   for (;;) {
     bool need = false;
     std::vector<char> trig(nrhs, 0);
@@ -556,6 +557,7 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
     if (need && pending && nrep < maxref) {
       std::vector<double> keep(P->w.host_scal, P->w.host_scal + (size_t)nrhs * kScalSlots);
       CR_CHECK(true_residual(P, nrhs, ninv, w.cg_x, w.cg_b, w.cg_r, rel, s));
+      fresh = true;
       ++nrep;
       std::memcpy(P->w.host_scal, keep.data(), keep.size() * sizeof(double));
       bool cont = false;
@@ -596,9 +598,12 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
     }
     bool any = false;
     for (int c = 0; c < nrhs; ++c) any |= P->w.host_scal[c * kScalSlots + S_DONE] == 0.0;
-    if (!any) break;   // every column confirmed by its true residual (or broken down)
-    if (it >= o->maxiter) {
-      CR_CHECK(true_residual(P, nrhs, ninv, w.cg_x, w.cg_b, w.cg_r, rel, s));
+    if (!any || it >= o->maxiter) {
+      // every column stopped: confirmed by its true residual, broken down,
+      // out of iterations, or (once max_refine replacements are spent)
+      // stopped on its recursive residual; report the true residual of the x
+      // that is returned
+      if (!fresh) CR_CHECK(true_residual(P, nrhs, ninv, w.cg_x, w.cg_b, w.cg_r, rel, s));
       break;
     }
     const int n = std::min(every, o->maxiter - it);
@@ -621,6 +626,7 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
       return CR_OK;
     }));
     pending = true;
+    fresh = false;
     it += n;
     CR_CHECK(read_scalars(P, nrhs, s));
     report_progress(P, nrhs, it, ++checks, "mixed pcg");
@@ -1052,6 +1058,7 @@ extern "C" int joint_cl_step(const crsht_plan* P, const cr_problem* fid, const d
   if (!fid || !d || !state || !dr || !opts || !out || !state->ahat || !state->fhat) return CR_EINVAL;
   if (!(dr->sigma_lnq > 0.0) || !(dr->u > 0.0 && dr->u < 1.0) || !std::isfinite(dr->xi)) return CR_EINVAL;
   if (!(state->q > 0.0) || !std::isfinite(state->lnpi)) return CR_EINVAL;
+  if (!dr->w0 && !dr->w1) return CR_EINVAL;   // the fluctuation of an accepted move needs a random term
   hipStream_t s = S(stream);
   std::memset(out, 0, sizeof(*out));
   const double qn = state->q * std::exp(dr->sigma_lnq * dr->xi);
@@ -1070,7 +1077,6 @@ extern "C" int joint_cl_step(const crsht_plan* P, const cr_problem* fid, const d
   out->accepted = std::log(dr->u) < out->lnA ? 1 : 0;
   if (!out->accepted) return CR_OK;
   // 4) accepted: fresh fluctuation at q', then ln pi of the new state
-  if (!dr->w0 && !dr->w1) return CR_EINVAL;
   CR_CHECK(solve_core(P, fid, qn, 1, nullptr, dr->w0, dr->w1, nullptr, state->fhat, opts, &out->fluct_stats, s));
   CR_TRY(hipMemcpyAsync(state->ahat, P->w.alm_c, na * sizeof(double2), hipMemcpyDeviceToDevice, s));
   CR_CHECK(lnpi_terms(P, fid->ninv, d, P->w.alm_c, C2(state->fhat), t, s));
@@ -1238,6 +1244,7 @@ extern "C" int hmc_cl_step(const crsht_plan* P, const cr_problem* fid, const dou
   if (!valid_bins(P, st->nbins, st->edges)) return CR_EINVAL;
   if (!(dr->eps > 0.0) || !std::isfinite(dr->eps) || dr->nleap < 1 || !(dr->u > 0.0 && dr->u < 1.0))
     return CR_EINVAL;
+  if (!dr->w0 && !dr->w1) return CR_EINVAL;   // the fluctuation drawn after the move needs a random term
   const int nb = st->nbins;
   hipStream_t s = S(stream);
   Workspace const& w = P->w;
@@ -1285,7 +1292,6 @@ extern "C" int hmc_cl_step(const crsht_plan* P, const cr_problem* fid, const dou
   // then a fresh fluctuation at the amplitudes the move ends on (accepted or
   // not: a draw of the fluctuation given the amplitudes leaves the joint
   // target invariant on its own), and ln pi of the new state
-  if (!dr->w0 && !dr->w1) return CR_EINVAL;
   const std::vector<double>& te = out->accepted ? th : th0;
   std::vector<double> fac, cl(P->g.lmax + 1);
   bin_factor(P->g.lmax, nb, st->edges, te.data(), 1.0, fac);

@@ -385,6 +385,12 @@ int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
   const int lmax = g.lmax, mmax = g.mmax, np = g.npairs;
   const int ncomp = P->ncomp;
   BlockPC& pc = P->pc;
+  // a captured iteration block holds the old preconditioner's device
+  // addresses (inverses, tasks): drop it before they are freed, so that the
+  // next solve captures again with the new storage
+  if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
+  P->graph_exec = nullptr;
+  P->graph_key = GraphKey();
   block_pc_free(pc);
   // blocks (component, m, parity), component-major: sizes, vector element of
   // row 0, compact FP32 offsets; then the application tasks

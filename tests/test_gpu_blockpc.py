@@ -194,3 +194,33 @@ def test_mixed_block_pc_long_blocks_between_checks(check_every):
         print("col %d iters %d refinements %d residual %.2e" % (c, st[c].iters, st[c].refinements, res), flush=True)
         assert st[c].status == 0 and res <= 1.05e-6
         assert st[c].iters <= 6 * check_every
+
+
+def test_rebuild_with_new_noise_in_same_tensor_after_graph_solve():
+    # a captured iteration block holds the preconditioner's device storage;
+    # rebuilding it (new N^-1 written into the same tensor) must not replay
+    # the old graph on freed memory: the graph-replayed solve after the
+    # rebuild equals the directly launched one
+    m = _m()
+    nside = 16
+    print("case block pc rebuild after graph solve", flush=True)
+    wl, P, op, d = masked_problem(nside)
+    plan = m.Plan(nside, wl.lmax)
+    ninv = tc(P.ninv)
+    gp = m.Problem(P.cl, P.bl, ninv, 2)
+    m.block_precond_build(plan, gp)
+    w0, w1 = tc(wl.w0()), tc(wl.w1())
+    s1, st1 = m.solve(plan, gp, tc(d), w0, w1, tol=1e-10, maxiter=2000, precond=m.CR_PC_BLOCK, use_graph=True)
+    assert st1[0].status == 0
+    ninv.mul_(3.0)   # a new noise model in the same device tensor
+    m.block_precond_build(plan, gp)
+    s2, st2 = m.solve(plan, gp, tc(d), w0, w1, tol=1e-10, maxiter=2000, precond=m.CR_PC_BLOCK, use_graph=True)
+    s3, st3 = m.solve(plan, gp, tc(d), w0, w1, tol=1e-10, maxiter=2000, precond=m.CR_PC_BLOCK, use_graph=False)
+    assert st2[0].status == 0 and st3[0].status == 0
+    assert st2[0].iters == st3[0].iters
+    assert torch.equal(s2, s3)
+    P3 = cr.Problem(P.nside, P.lmax, P.cl, P.bl, 3.0 * P.ninv, P.lmin)
+    op3 = cr.CROperator(P3)
+    x = s2.cpu().numpy()[0]
+    b = op3.rhs(d, wl.w0(), wl.w1())
+    assert real_rel(op3, op3.apply(x), b) <= 1.5e-10
