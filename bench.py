@@ -5,20 +5,26 @@ Workload (temperature, HEALPix Nside 512, lmax 1535): C_l = A/(l(l+1)) with a
 100 uK pixel rms, Gaussian beam FWHM 10 arcmin, anisotropic white noise
 sigma_p = 30 uK / sqrt(h_p) with h_p = 1 + 4 sin^2(ecliptic-like latitude),
 N^-1 = 0 in the band |b| < 20 deg, data d = Y B a_true + n, fresh w0/w1 per
-column. One step = one full constrained-realization solve (right-hand side,
-Jacobi diagonal and all PCG iterations) to a true relative residual of 1e-6
-for `--nrhs` independent columns at once. The default is the batched
-mixed-precision form (16 columns, bf16x3 MFMA Legendre steps inside PCG with
-FP64 vectors, scalars and residual replacement); `--prec f64` runs the plain
-FP64 form. Unless `--no-f64-compare` is given, one plain FP64 single-column
-solve of column 0 is timed as well (reported beside the headline, never as
-`value`). Inputs are resident on the GPU before timing starts. The timed steps
-replay each block of check_every PCG iterations as a captured HIP graph; the
-per-kernel launch times come from one extra step with HIP events around every
-launch of the tracked kernels.
+column. One step = one full constrained-realization solve (right-hand side
+and all PCG iterations, per-m block preconditioner built once per noise model
+before the timed steps) to a true relative residual of 1e-6 for `--nrhs`
+independent columns at once. The default is the batched mixed-precision form
+(16 columns, bf16x3 MFMA Legendre steps inside PCG with FP64 vectors, scalars
+and residual replacement); `--prec f64` runs the plain FP64 form. Inputs are
+resident on the GPU before timing starts; the timed steps replay each block of
+check_every PCG iterations as a captured HIP graph; the per-kernel launch
+times come from one extra solve with HIP events around every launch of the
+tracked kernels.
 
-Prints one JSON line. --gpus N with N > 1 is refused: the benchmark runs on one
-GPU.
+Beside `value` the line carries, unless switched off: `forms` (the same solve
+as plain FP64 PCG at the same 16 columns, as mixed PCG at 1 column and as
+FP64 at 1 column, all to the same 1e-6 residual), `tqu_line` (T+Q+U, 2
+columns) and `cpu_baseline` (the oracle on the host cores).
+
+Other workloads: tqu, batched64 (64 uneven problems), chains (joint, Gibbs
+and HMC moves), and the counter-run probes probe-operator, probe-precond and
+copy. Prints one JSON line. --gpus N with N > 1 is refused: the benchmark
+runs on one GPU.
 """
 from __future__ import annotations
 
@@ -41,8 +47,8 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0     # dense
 HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of a kernel per timed unit from rocprofv3 --pmc FETCH_SIZE /
-# WRITE_SIZE runs of `paper_2306_15511_amd/kernel_probe.py` (operator --nrhs 16
-# --prec mixed / f64; precond --nrhs 16) at Nside 512, scaled by the same
+# WRITE_SIZE runs of this script's probe workloads (probe-operator --nrhs 16
+# --prec mixed / f64; probe-precond --nrhs 16) at Nside 512, scaled by the same
 # counters on a 1 GiB copy (FETCH x 2.0, WRITE x 1.0); valid only for the
 # 16-column temperature workload and while the kernel's source file hashes to
 # `src`.
@@ -70,73 +76,90 @@ def src_hash(rel: str) -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def cpu_baseline(wl, iters: int, iters_src: str, tqu: bool = False):
-    """Oracle (numpy FP64) SHT pair on a bounded sample: the Legendre and
-    azimuthal steps of one synthesis + adjoint restricted to every 16th ring,
-    scaled to the full ring count; solves/s = 1/(t_pair * iters). With tqu the
-    pair also carries the spin-2 part (W, X rows of oracle/spin2.py for E and
-    B, and the Q, U ring FFTs)."""
-    from oracle import sht as osht
-    from oracle import spin2
-    from oracle.legendre import lambda_rows
-    import crinputs as ci
-    S = osht.SHT(wl.nside, wl.lmax)
-    R = S.rings
-    nr = R.nrings
-    sel = np.arange(0, nr, 16)
-    nmap = 3 if tqu else 1
-    a = [ci.white_alm(np.random.default_rng(1 + k), wl.lmax) for k in range(nmap)]
-    x = [np.random.default_rng(20 + k).standard_normal(S.npix) for k in range(nmap)]
-    t0 = time.perf_counter()
-    z, st = R.z[sel], R.sin_theta[sel]
-    F = np.zeros((nmap, S.mmax + 1, sel.size), dtype=np.complex128)
-    for l, lam in lambda_rows(S.lmax, S.mmax, z, st):
-        top = lam.shape[0] - 1
-        F[0, :top + 1] += lam * a[0][S._idx(l, top)][:, None]
-    if tqu:
-        for l, W, X in spin2.wx_rows(S.lmax, S.mmax, z, st):
-            if l < 2:
-                continue
-            top = W.shape[0] - 1
-            e, b = a[1][S._idx(l, top)][:, None], a[2][S._idx(l, top)][:, None]
-            F[1, :top + 1] -= W * e + 1j * X * b
-            F[2, :top + 1] -= W * b - 1j * X * e
-    m = np.arange(S.mmax + 1)
-    G = np.empty_like(F)
-    for j, k in enumerate(sel):
-        n, f0 = int(R.nphi[k]), int(R.first[k])
-        for q in range(nmap):
-            c = np.zeros(n, dtype=np.complex128)
-            np.add.at(c, m % n, np.where(m == 0, 1.0, 2.0) * F[q, :, j] * np.exp(1j * m * R.phi0[k]))
-            _ = (n * np.fft.ifft(c)).real
-            Xf = np.fft.fft(x[q][f0:f0 + n])
-            G[q, :, j] = np.exp(-1j * m * R.phi0[k]) * Xf[m % n]
-    out = np.zeros((nmap, S.nalm), dtype=np.complex128)
-    for l, lam in lambda_rows(S.lmax, S.mmax, z, st):
-        top = lam.shape[0] - 1
-        out[0, S._idx(l, top)] = np.sum(lam * G[0, :top + 1], axis=1)
-    if tqu:
-        for l, W, X in spin2.wx_rows(S.lmax, S.mmax, z, st):
-            if l < 2:
-                continue
-            top = W.shape[0] - 1
-            i = S._idx(l, top)
-            out[1, i] = np.sum(-W * G[1, :top + 1] - 1j * X * G[2, :top + 1], axis=1)
-            out[2, i] = np.sum(1j * X * G[1, :top + 1] - W * G[2, :top + 1], axis=1)
-    t = time.perf_counter() - t0
-    t_pair = t * nr / sel.size
+def _oracle_threads() -> int:
     cores = len(os.sched_getaffinity(0))
-    try:
-        import threadpoolctl
-        used = max([d.get("num_threads", 1) for d in threadpoolctl.threadpool_info()] or [1])
-        cores = min(cores, used) if used else cores
-    except Exception:
-        pass
-    return {"value": 1.0 / (t_pair * max(iters, 1)), "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": "numpy FP64 oracle %sSHT pair (Legendre + FFT synthesis and adjoint) on %d of %d rings "
-                      "(%.1f s), scaled to all rings: %.1f s per SHT pair; solves/s = 1/(s per pair x %d "
-                      "iterations, %s)" % ("T+Q+U " if tqu else "", sel.size, nr, t, t_pair, iters, iters_src),
-            "sht_pairs_per_s": 1.0 / t_pair}
+    env = os.environ.get("OMP_NUM_THREADS")
+    return min(cores, int(env)) if env and env.isdigit() and int(env) > 0 else cores
+
+
+def cpu_baseline(wl, iters: int, iters_src: str, tqu: bool = False):
+    """The oracle on the host cores: one full SHT pair (synthesis + adjoint of
+    one field) at the benchmark's Nside and lmax, with the oracle's plain-C
+    Legendre sums and numpy FFTs; solves/s = 1/(s per pair x iterations).
+    With tqu the pair also carries the spin-2 part on a bounded sample (the
+    W, X rows of the numpy oracle on every 16th ring, scaled to all rings).
+    Beside it, one whole oracle solve (right-hand side, block preconditioner
+    set-up, PCG to 1e-6) of the same sky at Nside 128, lmax 383."""
+    from oracle import sht as osht
+    import crinputs as ci
+    S = osht.SHT(wl.nside, wl.lmax, fast=True)
+    a = ci.white_alm(np.random.default_rng(1), wl.lmax)
+    x = np.random.default_rng(20).standard_normal(S.npix)
+    t0 = time.perf_counter()
+    S.synth(a)
+    S.adjoint(x)
+    t_pair = time.perf_counter() - t0
+    sample = ("oracle SHT pair (plain-C Legendre sums + numpy FFT) at Nside %d, lmax %d, all %d rings: %.2f s"
+              % (wl.nside, wl.lmax, S.rings.nrings, t_pair))
+    if tqu:
+        t_pair = t_pair + _spin2_sample_time(wl)
+        sample += ("; T+Q+U: the T pair + the spin-2 rows of E, B (numpy oracle on every 16th ring, scaled) and "
+                   "the Q, U FFTs: %.2f s" % t_pair)
+    sample += "; solves/s = 1/(s per pair x %d iterations, %s)" % (iters, iters_src)
+    out = {"value": 1.0 / (t_pair * max(iters, 1)), "unit": "solves/s", "cores": _oracle_threads(), "kind": "oracle",
+           "sample": sample, "sht_pairs_per_s": 1.0 / t_pair}
+    if not tqu:
+        out["full_solve"] = _oracle_full_solve()
+    return out
+
+
+def _spin2_sample_time(wl) -> float:
+    """Seconds of the spin-2 part of one T+Q+U SHT pair in the oracle: the
+    (a_E, a_B) -> (Q, U) spectra of the numpy oracle on every 16th ring,
+    scaled to all rings, twice (synthesis and transpose use the same W, X
+    rows), plus the azimuthal FFTs of Q and U at full size."""
+    from oracle import spin2
+    import crinputs as ci
+    pol = spin2.PolSHT(wl.nside, wl.lmax)
+    R = pol.s.rings
+    sel = np.arange(0, R.nrings, 16)
+    aE, aB = (ci.white_alm(np.random.default_rng(2 + k), wl.lmax) for k in range(2))
+    t0 = time.perf_counter()
+    GQ, GU = pol.spectra(aE, aB, sel)
+    t_rows = (time.perf_counter() - t0) * R.nrings / sel.size
+    F = np.zeros((pol.mmax + 1, R.nrings), dtype=np.complex128)
+    x = np.random.default_rng(21).standard_normal(pol.npix)
+    t0 = time.perf_counter()
+    pol.s.phi_synth(F)
+    pol.s.phi_adjoint(x)
+    t_fft = time.perf_counter() - t0
+    return 2.0 * t_rows + 2.0 * t_fft
+
+
+def _oracle_full_solve(nside: int = 128) -> dict:
+    """One complete oracle constrained-realization solve (d, w0, w1 terms,
+    right-hand side, per-m block preconditioner, PCG to 1e-6) of the
+    benchmark's sky at a smaller Nside."""
+    from oracle import cr, healpix
+    from oracle import sht as osht
+    from oracle.block_pc import BlockPreconditioner
+    import crinputs as ci
+    wl = ci.workload_masked_t(nside, 3 * nside - 1, fwhm_arcmin=10.0 * 512 / nside, cfg=2)
+    z, phi = healpix.pixel_coords(nside)
+    t0 = time.perf_counter()
+    S = osht.SHT(nside, wl.lmax, fast=True)
+    P = cr.Problem(nside, wl.lmax, wl.cl(), wl.bl(), wl.ninv(z, phi))
+    op = cr.CROperator(P, S)
+    d = S.synth(op.b * wl.signal()) + wl.noise(z, phi)
+    t1 = time.perf_counter()
+    b = op.rhs(d, wl.w0(), wl.w1())
+    pc = BlockPreconditioner(op)
+    x, info = cr.pcg(op, b, 1e-6, 2000, precond=pc)
+    t2 = time.perf_counter()
+    return {"nside": nside, "lmax": wl.lmax, "s": t2 - t1, "solves_per_s": 1.0 / (t2 - t1), "iters": info.iters,
+            "rel_resid_true": info.rel_resid_true, "inputs_s": t1 - t0, "cores": _oracle_threads(),
+            "what": "oracle CR solve of the benchmark sky (hit pattern, |b|<20deg, FWHM 10' x 512/Nside): "
+                    "right-hand side + block preconditioner set-up + PCG to 1e-6, timed whole"}
 
 
 def bench_batched(args):
@@ -297,47 +320,62 @@ def bench_chains(args):
     print(json.dumps(res))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--nrhs", type=int, default=None, help="columns per solve (default 16; 2 for --workload tqu)")
-    ap.add_argument("--nside", type=int, default=512)
-    ap.add_argument("--lmax", type=int, default=None)
-    ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--check-every", type=int, default=None,
-                    help="PCG iterations between host convergence checks (default 6 with the block "
-                         "preconditioner, 16 with Jacobi)")
-    ap.add_argument("--inner-tol", type=float, default=None,
-                    help="mixed path: FP64 residual replacement each time the residual fell by this factor "
-                         "(default 1e-3; 1e-2 for --workload tqu, the faster setting measured for each)")
-    ap.add_argument("--prec", choices=["f64", "mixed"], default="mixed")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-f64-compare", action="store_true")
-    ap.add_argument("--workload", choices=["headline", "tqu", "batched64", "chains"], default="headline")
-    ap.add_argument("--chains", type=int, default=4, help="--workload chains: number of chains")
-    ap.add_argument("--noise-scale", type=float, default=1.0,
-                    help="--workload chains: noise standard deviation relative to the headline sky")
-    ap.add_argument("--chain-columns", action="store_true",
-                    help="headline/tqu: the columns are the mean-field and fluctuation systems of nrhs/2 chains, "
-                         "each at its own amplitude q ~ U[0.8, 1.25] (one solve for all)")
-    ap.add_argument("--precond", choices=["block", "jacobi"], default=None,
-                    help="default: block (per-m blocks, one set per component)")
-    args = ap.parse_args()
-    if args.inner_tol is None:
-        args.inner_tol = 1e-2 if args.workload == "tqu" else 1e-3
-    if args.gpus != 1:
-        print("bench.py: the benchmark measures one GPU only; --gpus %d is not supported "
-              "(independent chains would shard one per GPU with no communication)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
-    if args.workload == "batched64":
-        bench_batched(args)
+def probe(args):
+    """Short fixed workloads for hardware-counter runs (rocprofv3 --pmc):
+    probe-operator applies the CR operator --reps times on the benchmark sky
+    (FP64 or mixed, --nrhs columns, --ncomp 1 or 3); probe-precond builds the
+    per-m block preconditioner and applies it --reps times; copy copies a
+    float64 buffer of --mib MiB --reps times (calibration of FETCH_SIZE /
+    WRITE_SIZE against exact bytes)."""
+    import torch
+    dev = torch.device("cuda:0")
+    if args.workload == "copy":
+        n = args.mib * 1024 * 1024 // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(args.reps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("copied %d bytes x %d" % (n * 8, args.reps))
         return
-    if args.workload == "chains":
-        bench_chains(args)
-        return
+    import crinputs as ci
+    from paper_2306_15511_amd import crsht
+    nside = args.nside
+    lmax = 3 * nside - 1 if args.lmax is None else args.lmax
+    ncomp = args.ncomp
+    nrhs = args.nrhs or 16
+    wl = ci.workload_masked_t(nside, lmax, fwhm_arcmin=10.0, cfg=2)
+    plan = crsht.Plan(nside, lmax, nrhs_max=nrhs, ncomp=ncomp)
+    z, phi = plan.pixel_coords()
+    nt = wl.ninv(z, phi)
+    if ncomp == 3:
+        cl = np.ascontiguousarray(ci.cl_tqu(lmax, wl.amp, 0.3))
+        prob = crsht.Problem(cl, wl.bl(), torch.from_numpy(np.stack([nt, nt / 2.0, nt / 2.0])).to(dev), 2)
+    else:
+        prob = crsht.Problem(wl.cl(), wl.bl(), torch.from_numpy(nt).to(dev), 2)
+    rng = np.random.default_rng(0)
+    x = np.stack([ci.white_alm(rng, lmax) for _ in range(nrhs * ncomp)])
+    x = torch.from_numpy(x.reshape(plan.alm_shape(nrhs))).to(dev)
+    if args.workload == "probe-precond":
+        crsht.block_precond_build(plan, prob)
+        for _ in range(args.reps):
+            crsht.block_precond_apply(plan, x)
+        torch.cuda.synchronize()
+        print("applied block preconditioner x %d at nside %d, %d columns" % (args.reps, nside, nrhs))
+    else:
+        prec = crsht.CR_MIXED if args.prec == "mixed" else crsht.CR_F64
+        for _ in range(args.reps):
+            crsht.apply(plan, prob, x, prec=prec)
+        torch.cuda.synchronize()
+        print("applied operator x %d at nside %d, %d columns, %s" % (args.reps, nside, nrhs, args.prec))
+    plan.close()
 
+
+def solve_line(args, tqu: bool, R: int, steps: int, warmup: int, compare: bool, kernels: bool = True):
+    """One solve workload on the benchmark sky (T only, or T+Q+U with C^EE =
+    0.05 C^TT, C^BB = 0.005 C^TT, TE correlation 0.3, sigma_QU = sqrt(2)
+    sigma_T): inputs resident in HBM, `warmup` untimed and `steps` timed
+    solves of R columns. Returns the result dict (value = solves/s)."""
     import torch
     from paper_2306_15511_amd import crsht
     import crinputs as ci
@@ -346,12 +384,8 @@ def main():
     lmax = 3 * nside - 1 if args.lmax is None else args.lmax
     wl = ci.workload_masked_t(nside, lmax, fwhm_arcmin=10.0, cfg=2)
     wl.tol = args.tol
-    tqu = args.workload == "tqu"
-    if tqu and args.prec == "mixed" and nside >= 1024:
-        sys.exit("bench.py: the mixed T+Q+U solve does not converge to 1e-6 at Nside >= 1024 (polar Q/U "
-                 "cancellation amplifies the bf16x3 rounding by 1/sin^2 theta); run it with --prec f64")
+    inner_tol = args.inner_tol if args.inner_tol is not None else (1e-2 if tqu else 1e-3)
     nc = 3 if tqu else 1
-    R = args.nrhs if args.nrhs else (2 if tqu else 16)
     mixed = args.prec == "mixed"
     dev = torch.device("cuda:0")
     plan = crsht.Plan(nside, lmax, nrhs_max=R, ncomp=nc)
@@ -360,8 +394,6 @@ def main():
     ls, _ = ci.alm_lm_arrays(lmax)
     sig = wl.sigma_map(z, phi)
     if tqu:
-        # T+Q+U: C^EE = 0.05 C^TT, C^BB = 0.005 C^TT, TE correlation 0.3;
-        # sigma_QU = sqrt(2) sigma_T with the same hits and mask
         cl = ci.cl_tqu(lmax, wl.amp, 0.3)
         nt = wl.ninv(z, phi)
         ninv = torch.from_numpy(np.stack([nt, nt / 2.0, nt / 2.0])).to(dev)
@@ -413,52 +445,107 @@ def main():
 
     prec = crsht.CR_MIXED if mixed else crsht.CR_F64
 
-    def step():
-        return crsht.solve(plan, prob, d, w0, w1, nrhs=R, tol=wl.tol, maxiter=20000, out=out,
-                           check_every=ce, prec=prec, inner_tol=args.inner_tol, precond=pc)
+    def solve(n, p, o):
+        return crsht.solve(plan, prob if n == R else crsht.Problem(cl, bl, ninv, 2, None if amp is None else amp[:n]),
+                           d[:n], w0[:n], w1[:n], nrhs=n, tol=wl.tol, maxiter=20000, out=o, check_every=ce, prec=p,
+                           inner_tol=inner_tol, precond=pc)
 
-    f64_cmp = None
-    if not args.no_f64_compare:
-        out1 = torch.empty(plan.alm_shape(1), dtype=torch.complex128, device=dev)
+    def timed_form(n, p, reps, label):
+        """warm-up solve (captures the graphs) and `reps` timed solves of n columns"""
+        o = out[:n]
+        solve(n, p, o)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, st1 = crsht.solve(plan, prob, d[:1], w0[:1], w1[:1], nrhs=1, tol=wl.tol, maxiter=20000, out=out1,
-                             check_every=ce, prec=crsht.CR_F64, precond=pc)
+        for _ in range(reps):
+            _, st = solve(n, p, o)
         torch.cuda.synchronize()
-        t1 = time.perf_counter() - t0
-        f64_cmp = {"form": "plain FP64 PCG, 1 column (column 0 of the batch), same preconditioner",
-                   "solves_per_s": 1.0 / t1,
-                   "iters": st1[0].iters, "rel_resid_true": st1[0].rel_resid_true}
-        print("f64 single: %.3f s, iters %d, resid %.2e" % (t1, st1[0].iters, st1[0].rel_resid_true),
-              file=sys.stderr, flush=True)
+        t = (time.perf_counter() - t0) / reps
+        r = {"form": label, "nrhs": n, "solves_per_s": n / t, "ms_per_solve_call": t * 1e3,
+             "iters_per_solve": sum(x.iters for x in st) / n,
+             "rel_resid_true_max": max(x.rel_resid_true for x in st),
+             "all_converged": all(x.status == 0 for x in st)}
+        print("%s: %.2f solves/s, iters %s" % (label, r["solves_per_s"], [x.iters for x in st]), file=sys.stderr,
+              flush=True)
+        return r
 
-    for _ in range(args.warmup):
-        _, st = step()
-        print("warmup: iters %s resid %s" % ([s.iters for s in st], ["%.2e" % s.rel_resid_true for s in st]),
+    for _ in range(warmup):
+        _, st = solve(R, prec, out)
+        print("warmup: iters %s resid %s" % ([x.iters for x in st], ["%.2e" % x.rel_resid_true for x in st]),
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
-    for k in range(args.steps):
-        _, st = step()
+    for k in range(steps):
+        _, st = solve(R, prec, out)
         stats.append(st)
-        print("step %d: iters %s refinements %s resid %s" % (k, [s.iters for s in st], [s.refinements for s in st],
-                                                             ["%.2e" % s.rel_resid_true for s in st]),
+        print("step %d: iters %s refinements %s resid %s" % (k, [x.iters for x in st], [x.refinements for x in st],
+                                                             ["%.2e" % x.rel_resid_true for x in st]),
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    # per-kernel launch times: one more (untimed) step with HIP events around
-    # every launch of the tracked kernels (direct launches, no graph replay)
+    solves = steps * R
+    tot_iters = sum(sum(x.iters for x in st) for st in stats)
+    what = ("T+Q+U (spin-0 and spin-2) constrained-realization PCG solve, C^EE = 0.05 C^TT, C^BB = 0.005 C^TT, "
+            "TE correlation 0.3, sigma_QU = sqrt(2) sigma_T" if tqu else "T-only constrained-realization PCG solve")
+    res = {
+        "metric": "constrained-realization CG solves/s at Nside=512, lmax=1535; SHT pairs/s",
+        "value": solves / dt,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": dt / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3+f64" if mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s, Nside %d, lmax %d, hit-pattern noise, "
+                               "|b|<20deg mask, FWHM 10', true residual %g, %d columns per solve, %s"
+                               % (what, nside, lmax, wl.tol, R, "bf16x3 MFMA Legendre + FP64 vectors and residual "
+                                  "replacement" if mixed else "FP64"),
+                   "nside": nside, "lmax": lmax, "nrhs": R, "ncomp": nc, "tol": wl.tol, "inner_tol": inner_tol,
+                   "check_every": ce,
+                   "preconditioner": "per-m blocks (built once per noise model)" if use_block else "Jacobi",
+                   "precision": "CR_MIXED" if mixed else "CR_F64"},
+        "sht_pairs_per_s": tot_iters * nc / dt,
+        "iters_per_solve": tot_iters / solves,
+        "rel_resid_true_max": max(x.rel_resid_true for st in stats for x in st),
+        "all_converged": all(x.status == 0 for st in stats for x in st),
+    }
+    if tqu:
+        res["config"]["sht_pairs_note"] = "one SHT pair per field: 3 per T+Q+U column and iteration"
+    if amp is not None:
+        res["config"]["workload"] += ("; the columns are %d chains x (mean field, fluctuation), chain k at "
+                                      "C_l q_k, q_k ~ U[0.8, 1.25]" % (R // 2))
+        res["config"]["chain_amplitudes"] = [float(v) for v in amp[::2]]
+    if pc_setup_s is not None:
+        res["precond_setup_s"] = pc_setup_s
+    if kernels:
+        res.update(kernel_roofline(args, plan, lambda: solve(R, prec, out), nside, lmax, R, nc, mixed, use_block, tqu))
+    if compare:
+        # the comparison forms at the same residual, preconditioner and sky
+        forms = {}
+        if mixed:
+            forms["f64_same_columns"] = timed_form(R, crsht.CR_F64, 1, "plain FP64 PCG, %d columns" % R)
+            if R > 1:
+                forms["mixed_1_column"] = timed_form(1, crsht.CR_MIXED, 3, "mixed PCG, 1 column")
+        forms["f64_1_column"] = timed_form(1, crsht.CR_F64, 1, "plain FP64 PCG, 1 column")
+        res["forms"] = forms
+    plan.close()
+    return res
+
+
+def kernel_roofline(args, plan, one_solve, nside, lmax, R, nc, mixed, use_block, tqu):
+    """per-kernel launch times: one more (untimed) solve with HIP events
+    around every launch of the tracked kernels (direct launches, no graph
+    replay), and the roofline fraction of each against its algorithmic work"""
+    from paper_2306_15511_amd import crsht
     crsht.timing_enable(plan, True)
-    _, st = step()
+    _, st = one_solve()
     tm = {k: crsht.timing_read(plan, k) for k in range(6)}
     crsht.timing_enable(plan, False)
-    print("kernel-timing step: iters %s" % [s.iters for s in st], file=sys.stderr, flush=True)
-
-    solves = args.steps * R
-    sps = solves / dt
-    tot_iters = sum(sum(s.iters for s in st) for st in stats)
-
+    print("kernel-timing step: iters %s" % [x.iters for x in st], file=sys.stderr, flush=True)
     # algorithmic work per timed unit (one launch; an FP64 adjoint unit is a whole transform)
     T = legendre_triples(nside, lmax, lmax)
     # Legendre sums of one column (E and O, complex; float2 in the mixed path)
@@ -466,14 +553,6 @@ def main():
     # scalar Legendre columns per transform: a T+Q+U column is 9 in the
     # synthesis and 7 in the adjoint; the ring pass sees nc maps per column
     cs, ca = (9 * R, 7 * R) if tqu else (R, R)
-
-    def groups(n):
-        out = []
-        while n > 0:
-            out.append(pick_nr(n))
-            n -= out[-1]
-        return out
-
     kinfo = {
         2: ("k_ring<RING_FUSED> (azimuthal FFT pass, N^-1 fused)", "hbm",
             nc * R * 2 * eo_bytes + nc * plan.npix * 8, HBM_PEAK_GBS, "GB/s", "ring.hip"),
@@ -484,10 +563,11 @@ def main():
                     BF16_MFMA_PEAK_TFLOPS, "TFLOP/s", "legendre_mfma.hip")
         kinfo[4] = ("k_adj_mfma (bf16x3 MFMA Legendre adjoint)", "mfma", 4 * T * ca / -(-ca // 16),
                     BF16_MFMA_PEAK_TFLOPS, "TFLOP/s", "legendre_mfma.hip")
+
     # FP64 Legendre kernels: the plain path, and in the mixed path the FP64
-    # true residuals of the refinement and the right-hand side
-    # with two or more columns they run on the FP64 matrix cores in launches
-    # of up to 8 columns (FP64 vector units for a single column)
+    # true residuals of the refinement and the right-hand side; with two or
+    # more columns they run on the FP64 matrix cores in launches of up to 8
+    # columns (FP64 vector units for a single column)
     def fp64_groups(n):
         return [min(8, n - c) for c in range(0, n, 8)] if n >= 2 else [1]
     gs, ga = fp64_groups(cs), fp64_groups(ca)
@@ -522,50 +602,87 @@ def main():
     dom = max(roofs, key=lambda k: roofs[k]["total_ms"])
     roof = dict(roofs[dom])
     roof["kernel"] = dom
-    what = ("T+Q+U (spin-0 and spin-2) constrained-realization PCG solve, C^EE = 0.05 C^TT, C^BB = 0.005 C^TT, "
-            "TE correlation 0.3, sigma_QU = sqrt(2) sigma_T" if tqu else "T-only constrained-realization PCG solve")
-    res = {
-        "metric": "constrained-realization CG solves/s at Nside=512, lmax=1535; SHT pairs/s",
-        "value": sps,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "bf16x3+f64" if mixed else "f64",
-        "data": "synthetic",
-        "config": {"workload": "%s, Nside %d, lmax %d, hit-pattern noise, "
-                               "|b|<20deg mask, FWHM 10', true residual %g, %d columns per solve, %s"
-                               % (what, nside, lmax, wl.tol, R, "bf16x3 MFMA Legendre + FP64 vectors and residual "
-                                  "replacement" if mixed else "FP64"),
-                   "nside": nside, "lmax": lmax, "nrhs": R, "ncomp": nc, "tol": wl.tol, "inner_tol": args.inner_tol,
-                   "preconditioner": "per-m blocks (built once per noise model)" if use_block else "Jacobi",
-                   "precision": "CR_MIXED" if mixed else "CR_F64"},
-        "sht_pairs_per_s": tot_iters / dt,
-        "iters_per_solve": tot_iters / solves,
-        "rel_resid_true_max": max(s.rel_resid_true for st in stats for s in st),
-        "roofline": roof,
-        "kernels": roofs,
-    }
-    if amp is not None:
-        res["config"]["workload"] += ("; the columns are %d chains x (mean field, fluctuation), chain k at "
-                                      "C_l q_k, q_k ~ U[0.8, 1.25]" % (R // 2))
-        res["config"]["chain_amplitudes"] = [float(v) for v in amp[::2]]
-    if pc_setup_s is not None:
-        res["precond_setup_s"] = pc_setup_s
-    if f64_cmp is not None:
-        res["f64_single_column"] = f64_cmp
+    return {"roofline": roof, "kernels": roofs}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nrhs", type=int, default=None, help="columns per solve (default 16; 2 for --workload tqu)")
+    ap.add_argument("--nside", type=int, default=512)
+    ap.add_argument("--lmax", type=int, default=None)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--check-every", type=int, default=None,
+                    help="PCG iterations between host convergence checks (default 6 with the block "
+                         "preconditioner, 16 with Jacobi)")
+    ap.add_argument("--inner-tol", type=float, default=None,
+                    help="mixed path: FP64 residual replacement each time the residual fell by this factor "
+                         "(default 1e-3; 1e-2 for T+Q+U, the faster setting measured for each)")
+    ap.add_argument("--prec", choices=["f64", "mixed"], default="mixed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f64-compare", action="store_true",
+                    help="headline: skip the FP64 and single-column comparison forms")
+    ap.add_argument("--no-tqu-line", action="store_true", help="headline: skip the T+Q+U line")
+    ap.add_argument("--workload", choices=["headline", "tqu", "batched64", "chains", "probe-operator",
+                                           "probe-precond", "copy"], default="headline")
+    ap.add_argument("--chains", type=int, default=4, help="--workload chains: number of chains")
+    ap.add_argument("--noise-scale", type=float, default=1.0,
+                    help="--workload chains: noise standard deviation relative to the headline sky")
+    ap.add_argument("--chain-columns", action="store_true",
+                    help="headline/tqu: the columns are the mean-field and fluctuation systems of nrhs/2 chains, "
+                         "each at its own amplitude q ~ U[0.8, 1.25] (one solve for all)")
+    ap.add_argument("--precond", choices=["block", "jacobi"], default=None,
+                    help="default: block (per-m blocks, one set per component)")
+    ap.add_argument("--ncomp", type=int, choices=[1, 3], default=1, help="probe workloads: 3 = T+Q+U")
+    ap.add_argument("--reps", type=int, default=3, help="probe workloads: repetitions")
+    ap.add_argument("--mib", type=int, default=1024, help="copy: buffer size in MiB")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: the benchmark measures one GPU only; --gpus %d is not supported "
+              "(independent chains would shard one per GPU with no communication)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.workload in ("probe-operator", "probe-precond", "copy"):
+        probe(args)
+        return
+    if args.workload == "batched64":
+        if args.inner_tol is None:
+            args.inner_tol = 1e-3
+        bench_batched(args)
+        return
+    if args.workload == "chains":
+        if args.inner_tol is None:
+            args.inner_tol = 1e-3
+        bench_chains(args)
+        return
+    tqu = args.workload == "tqu"
+    if tqu and args.prec == "mixed" and args.nside >= 1024:
+        sys.exit("bench.py: the mixed T+Q+U solve does not converge to 1e-6 at Nside >= 1024 (polar Q/U "
+                 "cancellation amplifies the bf16x3 rounding by 1/sin^2 theta); run it with --prec f64")
+    R = args.nrhs if args.nrhs else (2 if tqu else 16)
+    res = solve_line(args, tqu, R, args.steps, args.warmup, compare=not args.no_f64_compare)
+    if not tqu and not args.no_tqu_line:
+        # the second line: T+Q+U, 2 columns, same sky (one warm-up, two timed solves)
+        t = solve_line(args, True, 2, 2, 1, compare=False, kernels=False)
+        res["tqu_line"] = {k: t[k] for k in ("value", "unit", "ms_per_step", "steps", "dtype", "config",
+                                             "sht_pairs_per_s", "iters_per_solve", "rel_resid_true_max",
+                                             "all_converged", "precond_setup_s") if k in t}
     if not args.no_cpu_baseline:
-        if f64_cmp is not None:
-            it, src = f64_cmp["iters"], "the FP64 GPU solve's count for column 0"
+        f1 = res.get("forms", {}).get("f64_1_column")
+        if f1 is not None:
+            it, src = int(round(f1["iters_per_solve"])), "the FP64 GPU solve's count for one column"
         else:
-            it, src = int(round(tot_iters / solves)), "the benchmarked solves' mean count"
-        res["cpu_baseline"] = cpu_baseline(wl, it, src, tqu)
+            it, src = int(round(res["iters_per_solve"])), "the benchmarked solves' mean count"
+        res["cpu_baseline"] = cpu_baseline(ci_workload(args), it, src, tqu)
     print(json.dumps(res))
-    plan.close()
+
+
+def ci_workload(args):
+    import crinputs as ci
+    nside = args.nside
+    lmax = 3 * nside - 1 if args.lmax is None else args.lmax
+    return ci.workload_masked_t(nside, lmax, fwhm_arcmin=10.0, cfg=2)
 
 
 if __name__ == "__main__":

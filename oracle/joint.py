@@ -70,11 +70,14 @@ class ChainState:
     lnpi: float
 
 
-def init_state(fid: Problem, d, q: float, w0, w1, tol: float, maxiter: int = 20000) -> ChainState:
-    """Algorithm step 1 with a fixed amplitude q instead of a Boltzmann code."""
-    op = CROperator(scaled_problem(fid, q))
-    ahat, _ = pcg(op, op.rhs(d=d), tol, maxiter)
-    fhat, _ = pcg(op, op.rhs(w0=w0, w1=w1), tol, maxiter)
+def init_state(fid: Problem, d, q: float, w0, w1, tol: float, maxiter: int = 20000, sht=None,
+               precond=None) -> ChainState:
+    """Algorithm step 1 with a fixed amplitude q instead of a Boltzmann code.
+    sht: the transforms to use (default: a new numpy SHT); precond: as for
+    pcg (None = the Jacobi diagonal)."""
+    op = CROperator(scaled_problem(fid, q), sht)
+    ahat, _ = pcg(op, op.rhs(d=d), tol, maxiter, precond=precond)
+    fhat, _ = pcg(op, op.rhs(w0=w0, w1=w1), tol, maxiter, precond=precond)
     return ChainState(q, ahat, fhat, lnpi(op, d, ahat, fhat))
 
 
@@ -87,17 +90,17 @@ class StepResult:
 
 
 def joint_step(fid: Problem, d, state: ChainState, xi: float, u: float, w0_new, w1_new,
-               sigma_lnq: float, tol: float, maxiter: int = 20000):
+               sigma_lnq: float, tol: float, maxiter: int = 20000, sht=None, precond=None):
     q_new = state.q * math.exp(sigma_lnq * xi)
-    op = CROperator(scaled_problem(fid, q_new))
-    ahat, _ = pcg(op, op.rhs(d=d), tol, maxiter)
+    op = CROperator(scaled_problem(fid, q_new), sht)
+    ahat, _ = pcg(op, op.rhs(d=d), tol, maxiter, precond=precond)
     f_scaled = math.sqrt(q_new / state.q) * state.fhat
     lp_new = lnpi(op, d, ahat, f_scaled)
     lnA = lp_new - state.lnpi + math.log(q_new / state.q)
     accepted = math.log(u) < lnA
     if not accepted:
         return state, StepResult(False, lnA, q_new, lp_new)
-    fhat, _ = pcg(op, op.rhs(w0=w0_new, w1=w1_new), tol, maxiter)
+    fhat, _ = pcg(op, op.rhs(w0=w0_new, w1=w1_new), tol, maxiter, precond=precond)
     new = ChainState(q_new, ahat, fhat, lnpi(op, d, ahat, fhat))
     return new, StepResult(True, lnA, q_new, lp_new)
 

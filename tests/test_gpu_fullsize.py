@@ -1,0 +1,194 @@
+"""GPU parity at the benchmarked and largest sizes, against the oracle with its
+plain-C Legendre sums (oracle/legendre_sums.c, pinned to the numpy oracle):
+
+* the benchmark's own solve (T only, Nside 512, lmax 1535, 16 columns,
+  CR_MIXED, per-m block preconditioner, host checks every 6 iterations, FP64
+  residual replacement every 1e-3 drop): the oracle evaluates the true
+  residual ||b - A x|| / ||b|| of two columns from its own A and b;
+* element-wise transforms at Nside 512 (FP64 matrix cores, FP64 vector
+  kernels, bf16x3 matrix cores) and the FP64 matrix-core adjoint at Nside
+  1024, whose 2048 ring pairs take two launches (the second adding to the
+  first);
+* the block preconditioner with blocks of up to 384 rows (Nside 256);
+* the plain FP64 workload of Nside 16 (full sky, uniform noise, FWHM 5 deg,
+  residual 1e-8) against the dense Cholesky solution;
+* the joint amplitude move on the masked hit-pattern sky at Nside 64 (both
+  sides with the block preconditioner), ln A to an absolute 1e-8.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import crinputs as ci
+from oracle import cr, dense, healpix, joint
+from oracle import sht as osht
+from oracle.block_pc import BlockPreconditioner
+from tests.gpu_helpers import real_rel, rel, tc
+
+pytestmark = pytest.mark.gpu
+MIXED_TOL = 2e-5
+
+
+def _m():
+    from paper_2306_15511_amd import crsht as m
+    return m
+
+
+def test_benchmark_solve_oracle_residual():
+    m = _m()
+    print("case benchmark solve: nside 512, lmax 1535, 16 columns, mixed, block pc", flush=True)
+    wl = ci.workload_headline_t()
+    nside, lmax, R = wl.nside, wl.lmax, 16
+    S = osht.SHT(nside, lmax, fast=True)
+    z, phi = healpix.pixel_coords(nside)
+    P = cr.Problem(nside, lmax, wl.cl(), wl.bl(), wl.ninv(z, phi))
+    op = cr.CROperator(P, S)
+    sig = wl.sigma_map(z, phi)
+    base = S.synth(op.b * wl.signal())
+    d = np.stack([base + sig * ci.white_map(ci.rng_for(2, c, ci.STREAM_NOISE), S.npix) for c in range(R)])
+    w0 = np.stack([ci.white_alm(ci.rng_for(2, c, ci.STREAM_W0), lmax) for c in range(R)])
+    w1 = np.stack([ci.white_map(ci.rng_for(2, c, ci.STREAM_W1), S.npix) for c in range(R)])
+    plan = m.Plan(nside, lmax, nrhs_max=R)
+    gp = m.Problem(P.cl, P.bl, tc(P.ninv), 2)
+    m.block_precond_build(plan, gp)
+    s, st = m.solve(plan, gp, tc(d), tc(w0), tc(w1), nrhs=R, tol=1e-6, maxiter=2000, check_every=6,
+                    prec=m.CR_MIXED, inner_tol=1e-3, precond=m.CR_PC_BLOCK)
+    x = s.cpu().numpy()
+    print("iterations", [t.iters for t in st], "replacements", [t.refinements for t in st], flush=True)
+    assert all(t.status == 0 for t in st)
+    for c in (0, R - 1):
+        b = op.rhs(d[c], w0[c], w1[c])
+        res = op.norm(b - op.apply(x[c])) / op.norm(b)
+        print("column %d: oracle residual %.3e, library residual %.3e" % (c, res, st[c].rel_resid_true), flush=True)
+        assert res <= 1e-6
+        assert abs(res - st[c].rel_resid_true) <= 1e-9
+    plan.close()
+
+
+def test_nside512_transforms_elementwise():
+    m = _m()
+    nside, lmax, n = 512, 1535, 2
+    print("case nside512 full transforms, 2 columns", flush=True)
+    S = osht.SHT(nside, lmax, fast=True)
+    rng = np.random.default_rng(5120)
+    A = np.stack([ci.white_alm(rng, lmax) for _ in range(n)])
+    X = rng.standard_normal((n, S.npix))
+    ref_map = [S.synth(A[c]) for c in range(n)]
+    ref_alm = [S.adjoint(X[c]) for c in range(n)]
+    plan = m.Plan(nside, lmax, nrhs_max=n)
+    dA, dX = tc(A), tc(X)
+    for name, prec, tol in (("fp64 matrix cores", m.CR_F64, 1e-10), ("bf16x3 matrix cores", m.CR_MIXED, MIXED_TOL)):
+        gm = m.synth(plan, dA, prec=prec).cpu().numpy()
+        ga = m.adjoint(plan, dX, prec=prec).cpu().numpy()
+        e = [rel(gm[c], ref_map[c]) for c in range(n)] + [rel(ga[c], ref_alm[c]) for c in range(n)]
+        print(name, "synthesis / adjoint rel errors", ["%.2e" % v for v in e], flush=True)
+        assert max(e) < tol
+    # one column: the FP64 vector kernels
+    gm = m.synth(plan, dA[:1].contiguous()).cpu().numpy()
+    ga = m.adjoint(plan, dX[:1].contiguous()).cpu().numpy()
+    e = (rel(gm[0], ref_map[0]), rel(ga[0], ref_alm[0]))
+    print("fp64 vector kernels", e, flush=True)
+    assert max(e) < 1e-10
+    plan.close()
+
+
+def test_nside1024_fp64_adjoint_two_launches_elementwise():
+    m = _m()
+    nside, lmax, n = 1024, 2047, 2
+    print("case nside1024 fp64 adjoint (two pair launches), 2 columns", flush=True)
+    S = osht.SHT(nside, lmax, fast=True)
+    rng = np.random.default_rng(10240)
+    X = rng.standard_normal((n, S.npix))
+    plan = m.Plan(nside, lmax, nrhs_max=n)
+    ga = m.adjoint(plan, tc(X)).cpu().numpy()
+    e = rel(ga[0], S.adjoint(X[0]))
+    print("fp64 matrix-core adjoint rel error %.2e" % e, flush=True)
+    assert e < 1e-10
+    plan.close()
+
+
+def test_block_preconditioner_large_blocks():
+    # blocks of up to 384 rows per parity (lmax 767): more than two LDS
+    # K-tiles and row offsets beyond the first 128-row task of an m
+    m = _m()
+    nside, nrhs = 256, 16
+    print("case block pc apply nside256 x16", flush=True)
+    wl = ci.workload_masked_t(nside)
+    z, phi = healpix.pixel_coords(nside)
+    P = cr.Problem(nside, wl.lmax, wl.cl(), wl.bl(), wl.ninv(z, phi))
+    op = cr.CROperator(P, osht.SHT(nside, wl.lmax, fast=True))
+    plan = m.Plan(nside, wl.lmax, nrhs_max=nrhs)
+    m.block_precond_build(plan, m.Problem(P.cl, P.bl, tc(P.ninv), 2))
+    pc = BlockPreconditioner(op)
+    rng = np.random.default_rng(256)
+    Rr = np.stack([op.project(ci.white_alm(rng, wl.lmax)) for _ in range(nrhs)])
+    got = m.block_precond_apply(plan, tc(Rr)).cpu().numpy()
+    worst = max(real_rel(op, got[c], pc(Rr[c])) for c in (0, 5, 15))
+    print("block pc max rel err %.3e" % worst, flush=True)
+    assert worst < 1e-5
+    plan.close()
+
+
+def test_plain_fp64_workload_nside16_against_dense():
+    # Nside 16, lmax 47, full sky, uniform white noise sigma 10 uK, FWHM 5 deg,
+    # one FP64 solve to residual 1e-8; and run to 1e-13 against the dense
+    # Cholesky solution to 1e-10
+    m = _m()
+    wl = ci.workload_plain_t(16)
+    z, phi = healpix.pixel_coords(16)
+    P = cr.Problem(16, wl.lmax, wl.cl(), wl.bl(), wl.ninv(z, phi))
+    op = cr.CROperator(P)
+    d = op.sht.synth(op.b * wl.signal()) + wl.noise(z, phi)
+    w0, w1 = wl.w0(), wl.w1()
+    b = op.rhs(d, w0, w1)
+    xd = dense.DenseY(16, wl.lmax, lmin=2).cr_solve(P.cl, P.bl, P.ninv, b)
+    plan = m.Plan(16, wl.lmax)
+    gp = m.Problem(P.cl, P.bl, tc(P.ninv), 2)
+    s, st = m.solve(plan, gp, tc(d), tc(w0), tc(w1), tol=wl.tol, maxiter=5000)
+    x = s.cpu().numpy()[0]
+    res = op.norm(b - op.apply(x)) / op.norm(b)
+    print("tol 1e-8: iters %d, oracle residual %.2e, distance to dense %.2e"
+          % (st[0].iters, res, real_rel(op, x, xd)), flush=True)
+    assert st[0].status == 0 and res <= wl.tol
+    s, st = m.solve(plan, gp, tc(d), tc(w0), tc(w1), tol=1e-13, maxiter=5000)
+    e = real_rel(op, s.cpu().numpy()[0], xd)
+    print("tol 1e-13: distance to dense %.2e" % e, flush=True)
+    assert e < 1e-10
+    plan.close()
+
+
+@pytest.mark.parametrize("xi,u", [(0.4, 0.95), (-0.3, 1e-12)])
+def test_joint_step_masked_nside64(xi, u):
+    m = _m()
+    nside, tol = 64, 1e-10
+    print("case joint step nside64", xi, u, flush=True)
+    wl = ci.workload_masked_t(nside)
+    z, phi = healpix.pixel_coords(nside)
+    S = osht.SHT(nside, wl.lmax, fast=True)
+    P = cr.Problem(nside, wl.lmax, wl.cl(), wl.bl(), wl.ninv(z, phi))
+    op = cr.CROperator(P, S)
+    d = S.synth(op.b * wl.signal()) + wl.noise(z, phi)
+    pc = BlockPreconditioner(op)
+    st = joint.init_state(P, d, 1.0, wl.w0(), wl.w1(), tol, sht=S, precond=pc)
+    rng = ci.rng_for(1, 64, ci.STREAM_MH)
+    w0n, w1n = ci.white_alm(rng, wl.lmax), rng.standard_normal(P.ninv.size)
+    plan = m.Plan(nside, wl.lmax)
+    gp = m.Problem(P.cl, P.bl, tc(P.ninv), 2)
+    m.block_precond_build(plan, gp)
+    ch = m.Chain(st.q, st.lnpi, tc(st.ahat), tc(st.fhat))
+    res = m.joint_step(plan, gp, tc(d), ch, xi, u, tc(w0n), tc(w1n), sigma_lnq=0.02, tol=tol,
+                       precond=m.CR_PC_BLOCK)
+    new, r = joint.joint_step(P, d, st, xi, u, w0n, w1n, 0.02, tol, sht=S, precond=pc)
+    print("lnA gpu %.12f oracle %.12f diff %.2e; accepted %s / %s" % (res.lnA, r.lnA, res.lnA - r.lnA,
+          res.accepted, r.accepted), flush=True)
+    assert abs(res.q_new - r.q_new) <= 1e-15 * r.q_new
+    assert abs(res.lnA - r.lnA) <= 1e-8 + 1e-13 * abs(r.lnpi_new)
+    assert res.accepted == r.accepted
+    assert abs(ch.lnpi - new.lnpi) <= 1e-8 * max(1.0, abs(new.lnpi))
+    opn = cr.CROperator(joint.scaled_problem(P, new.q), S)
+    assert real_rel(opn, ch.ahat.cpu().numpy(), new.ahat) < 1e-8
+    assert real_rel(opn, ch.fhat.cpu().numpy(), new.fhat) < 1e-8
+    plan.close()
+    _ = (math, torch)

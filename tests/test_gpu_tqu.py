@@ -262,14 +262,19 @@ def test_tqu_nside512_sampled_rings_and_adjointness():
     rings = [0, 1, 2, 37, 300, 511, 512, 900, 1023, 1500, 2045, 2046]
     ref = pol.synth_rings(a[1], a[2], rings)
     R = pol.s.rings
-    worst_m = 0.0
     for k in rings:
         f, n = int(R.first[k]), int(R.nphi[k])
+        # Q and U divide Legendre sums that cancel near the poles by
+        # sin^2 theta, which amplifies the mixed rounding (about 5e-8 of the
+        # cancelling terms, measured at Nside 1024) by 1/sin^2 theta
+        s2 = 1.0 - R.z[k] ** 2
+        bound_m = max(MIXED_TOL, 1e-7 / s2)
         for q in range(2):
             e = rel(got[1 + q, f:f + n], ref[k][q])
             assert e < TOL, (k, q, e)
-            worst_m = max(worst_m, rel(gm[1 + q, f:f + n], ref[k][q]))
-    print("mixed worst sampled-ring rel error", worst_m, flush=True)
+            em = rel(gm[1 + q, f:f + n], ref[k][q])
+            print("ring %d sin^2 %.2e: mixed rel error %.2e (bound %.2e)" % (k, s2, em, bound_m), flush=True)
+            assert em < bound_m, (k, q, em)
     y = rng.standard_normal((3, pol.npix))
     ya = m.adjoint(plan, tc(y)).cpu().numpy()
     lhs = float(np.sum(got * y))
@@ -413,7 +418,7 @@ def test_tqu_lnpi_and_joint_step():
         print("lnA gpu %.12e oracle %.12e accepted %s/%s" % (res.lnA, r.lnA, res.accepted, r.accepted), flush=True)
         assert res.accepted == r.accepted
         assert res.q_new == r.q_new
-        assert abs(res.lnA - r.lnA) <= 1e-7 * max(1.0, abs(st.lnpi))
+        assert abs(res.lnA - r.lnA) <= 1e-8 + 1e-13 * abs(r.lnpi_new)   # absolute: ln A decides the move
         assert abs(ch.q - new.q) <= 1e-15 * new.q and abs(ch.lnpi - new.lnpi) <= 1e-9 * abs(new.lnpi)
         opn = cr_tqu.CROperatorTQU(cr_tqu.ProblemTQU(nside, P.lmax, P.cl * new.q, P.bl, P.ninv_t, P.ninv_p, P.lmin))
         assert real_rel3(opn, ch.ahat.cpu().numpy(), new.ahat) < 1e-8
