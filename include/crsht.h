@@ -65,6 +65,7 @@ enum {
   CR_ENOMEM = -2,    /* device allocation failed at plan creation */
   CR_EDEVICE = -3,   /* a HIP runtime call or kernel launch failed */
   CR_ENOTSUP = -4,   /* valid but not supported by this library */
+  CR_ESCRATCH = -5,  /* sht_synth_noalloc: the call needs more than its static scratch */
   CR_NOCONV = 1,     /* maxiter reached; the last iterate is written */
   CR_BREAKDOWN = 2   /* <p, A p> <= 0 or non-finite; output undefined */
 };
@@ -122,6 +123,29 @@ int crsht_pixel_coords(const crsht_plan *plan, double *z_host, double *phi_host)
  * alm: device, [nrhs][nalm] complex; map: device, [nrhs][npix].
  * 1 <= nrhs <= nrhs_max. prec: CR_F64 or CR_MIXED. Asynchronous. */
 int sht_synth(const crsht_plan *plan, int nrhs, const double *alm, double *map, cr_prec prec, void *stream);
+
+/* Bytes of the file-scope device scratch of sht_synth_noalloc (one copy per
+ * GPU the library runs on, held until the process ends). */
+#define CRSHT_NOALLOC_SCRATCH_BYTES (96u << 20)
+
+/* sht_synth without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc. Same arguments, kernels and result as sht_synth
+ * (temperature plans only: CR_ENOTSUP for ncomp = 3). The transform's
+ * intermediate buffers (the scaled a_lm and the Legendre sums) live in a
+ * static device scratch of CRSHT_NOALLOC_SCRATCH_BYTES instead of the plan
+ * workspace; the call allocates nothing (no hipMalloc, no library routine
+ * that allocates). Needs CR_F64: nrhs (16 nalm + 32 npairs (mmax+1)) bytes
+ * (nalm term rounded up to 256), CR_MIXED: nrhs 16 npairs (mmax+1) bytes,
+ * else CR_ESCRATCH (Nside 512, lmax 1535: one FP64 or three mixed columns).
+ * The plan's device must be current (CR_EINVAL otherwise) and kernel timing
+ * off (CR_EINVAL). Every call on one GPU shares that GPU's scratch, which
+ * keeps the last call's contents: calls that overlap on one GPU (different
+ * streams or threads, any plans) race and must be serialised by the caller.
+ * The scratch's device address is looked up once per device at plan
+ * creation. Asynchronous. */
+int sht_synth_noalloc(const crsht_plan *plan, int nrhs, const double *alm, double *map, cr_prec prec,
+                      void *stream);
 
 /* Adjoint synthesis Y^T (the transpose; paper App. A pixel sums).
  * map: device [nrhs][npix]; alm: device [nrhs][nalm] complex. Asynchronous. */

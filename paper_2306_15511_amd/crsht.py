@@ -19,7 +19,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("CRSHT_LIB") or os.path.join(_HERE, "libcrsht.so")
 
-CR_OK, CR_EINVAL, CR_ENOMEM, CR_EDEVICE, CR_ENOTSUP = 0, -1, -2, -3, -4
+CR_OK, CR_EINVAL, CR_ENOMEM, CR_EDEVICE, CR_ENOTSUP, CR_ESCRATCH = 0, -1, -2, -3, -4, -5
 CR_NOCONV, CR_BREAKDOWN = 1, 2
 CR_F64, CR_MIXED = 0, 1
 CR_PC_JACOBI, CR_PC_BLOCK = 0, 1
@@ -102,6 +102,7 @@ def _load():
         "crsht_plan_info": ([P, ctypes.POINTER(_Info)], i),
         "crsht_pixel_coords": ([P, vp, vp], i),
         "sht_synth": ([P, i, vp, vp, i, vp], i),
+        "sht_synth_noalloc": ([P, i, vp, vp, i, vp], i),
         "sht_synth_adjoint": ([P, i, vp, vp, i, vp], i),
         "sht_analysis": ([P, i, vp, vp, i, vp], i),
         "cr_precond": ([P, ctypes.POINTER(_Problem), vp, vp], i),
@@ -154,7 +155,7 @@ def _load():
 _lib = _load()
 
 EXPORTED = ("crsht_plan_create", "crsht_plan_destroy", "crsht_strerror", "crsht_plan_info", "crsht_pixel_coords",
-            "sht_synth", "sht_synth_adjoint", "sht_analysis", "cr_precond", "cr_rhs", "cr_apply", "cr_solve",
+            "sht_synth", "sht_synth_noalloc", "sht_synth_adjoint", "sht_analysis", "cr_precond", "cr_rhs", "cr_apply", "cr_solve",
             "cr_white", "cr_lnpi", "joint_cl_step", "joint_cl_step_batch", "gibbs_cl_step", "gibbs_cl_step_batch", "gibbs_bins_step", "hmc_cl_step", "cr_lnpi_grad_fixed",
             "cr_solve_batched", "sht_synth_grad", "cr_grad_chi2", "cr_grad_lnpi",
             "cr_block_precond_build", "cr_block_precond_apply", "crsht_timing_enable", "crsht_timing_read")
@@ -263,6 +264,14 @@ def synth(plan: Plan, alm: torch.Tensor, out: torch.Tensor | None = None, prec: 
     if out is None:
         out = torch.empty(tuple(alm.shape[:-1]) + (plan.npix,), dtype=torch.float64, device=alm.device)
     _check(_lib.sht_synth(plan.handle, n, _ptr(alm), _ptr(out), prec, _stream()), "sht_synth")
+    return out
+
+
+def synth_noalloc(plan: Plan, alm: torch.Tensor, out: torch.Tensor, prec: int = CR_F64) -> torch.Tensor:
+    """sht_synth_noalloc: sht_synth with the library's static device scratch
+    (no allocation by the call); `out` is the caller's map tensor."""
+    n = _nrhs(alm, plan.vlen, torch.complex128)
+    _check(_lib.sht_synth_noalloc(plan.handle, n, _ptr(alm), _ptr(out), prec, _stream()), "sht_synth_noalloc")
     return out
 
 

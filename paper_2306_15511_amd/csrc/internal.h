@@ -305,6 +305,10 @@ hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, doub
 hipError_t launch_pc_dots(const crsht_plan* P, int nrhs, const double2* r, const double2* z, bool rr,
                           hipStream_t s);
 
+// ---- allocation-free synthesis (noalloc.hip) ----
+// device address of the static scratch on `device` (current), once per device
+int noalloc_setup(int device);
+
 // ---- vector kernels (vec.hip) ----
 // Reductions write per-block partial sums to w.partial (column c, row r at
 // partial[(c * 4 + r) * npart + block]) and a one-block kernel sums them.

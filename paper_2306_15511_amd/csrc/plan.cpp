@@ -388,6 +388,9 @@ extern "C" int crsht_plan_create(int nside, int lmax, int mmax, int ncomp, int n
     return rc;
   }
   P->workspace_bytes_ = (int64_t)total;
+  // device address of the allocation-free call's scratch on this device
+  // (once per device; a failure only disables sht_synth_noalloc)
+  (void)crsht::noalloc_setup(P->device);
   *out = P;
   return CR_OK;
 }
@@ -406,6 +409,7 @@ extern "C" const char* crsht_strerror(int status) {
     case CR_ENOMEM: return "device allocation failed";
     case CR_EDEVICE: return "HIP runtime error";
     case CR_ENOTSUP: return "not supported by this library";
+    case CR_ESCRATCH: return "the input needs more than the static scratch of the allocation-free call";
     case CR_NOCONV: return "maximum iterations reached before the tolerance";
     case CR_BREAKDOWN: return "conjugate-gradient breakdown (non-positive or non-finite curvature)";
     default: return "unknown status";
