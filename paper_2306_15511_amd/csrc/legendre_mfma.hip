@@ -264,34 +264,46 @@ __global__ __launch_bounds__(64) void k_pupdate_prep(int lmax, int nrhs, int64_t
 }
 
 // ----------------------------------------------------------------- synthesis
-// One wavefront per (m, block of 64 ring pairs): lane p runs the recurrence
-// of pair p for a chunk of 32 steps, writes mu (bf16 hi, lo; even and odd
-// steps apart) to an LDS tile [pair][k], then the wavefront multiplies the
-// two 32-pair M tiles by the chunk's ab tiles. Chunks before the first live
-// group of the 64 pairs are skipped.
+// One workgroup of 4 wavefronts per (4 consecutive m, block of 64 ring
+// pairs); wavefront w takes m = m0 + w. Lane p runs the recurrence of pair p
+// for a chunk of 32 steps, splits mu into bf16 hi and lo (even and odd steps
+// apart) in registers, then the wavefront multiplies the two 32-pair M tiles
+// by the chunk's ab tiles. Chunks before the first live group of the 64 pairs
+// are skipped. The sums of the 4 m leave through LDS as one 64-byte run
+// (m0 .. m0 + 3, E and O) per (column, pair) of the [column][pair][m][E, O]
+// layout, instead of 16-byte pieces per wavefront.
+constexpr int kSynWaves = 4;                       // m per workgroup
+constexpr int kSynRow = kSynWaves * 4;             // floats per (column, pair) run: [m][E.re, E.im, O.re, O.im]
+constexpr int kSynRhsStride = 32 * kSynRow + 2;    // floats per column in LDS (32 pairs), padded against bank conflicts
 template <int NG>
-__global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npairs, int nrhs,
-                                                   const double* __restrict__ pair_z, const double* __restrict__ alpha,
-                                                   const int* __restrict__ lst_g, const double2* __restrict__ lst_s,
-                                                   const int64_t* __restrict__ mstart,
-                                                   const int64_t* __restrict__ cstart,
-                                                   const bf16x8* __restrict__ ab, int64_t ab_gstride,
-                                                   float2* __restrict__ eo, int64_t eo_stride) {
+__global__ __launch_bounds__(256) void k_synth_mfma(int lmax, int mmax, int npairs, int nrhs,
+                                                    const double* __restrict__ pair_z, const double* __restrict__ alpha,
+                                                    const int* __restrict__ lst_g, const double2* __restrict__ lst_s,
+                                                    const int64_t* __restrict__ mstart,
+                                                    const int64_t* __restrict__ cstart,
+                                                    const bf16x8* __restrict__ ab, int64_t ab_gstride,
+                                                    float2* __restrict__ eo, int64_t eo_stride) {
+  // results of one pair half (32 pairs) of the 16 columns of a group
+  __shared__ __attribute__((aligned(16))) float res[16 * kSynRhsStride];
   const int npb = (npairs + 63) / 64;
   const int q8 = blockIdx.x >> 3;
-  const int m = xcd_m(q8 / npb, blockIdx.x & 7), pb = q8 % npb;
-  if (m > mmax) return;
-  const int lane = threadIdx.x;
+  // each XCD takes 4 consecutive m out of every 32 (xcd_m): the 4 m of one workgroup
+  const int m0 = xcd_m(4 * (q8 / npb), blockIdx.x & 7), pb = q8 % npb;
+  const int w = threadIdx.x >> 6;
+  const int m = m0 + w;
+  const bool mlive = m <= mmax;   // every wavefront stays for the barriers
+  const int lane = threadIdx.x & 63;
   const int p = pb * 64 + lane;
-  const bool valid = p < npairs;
-  const int pp = valid ? p : npairs - 1;
-  const size_t o = (size_t)m * npairs + pp;
+  const bool valid = p < npairs && mlive;
+  const int pp = p < npairs ? p : npairs - 1;
+  const int mm = mlive ? m : mmax;
+  const size_t o = (size_t)mm * npairs + pp;
   const double z = pair_z[pp];
   const int gs = valid ? lst_g[o] : kNever;
   const double2 s0 = lst_s[o];
   const int gmin = __builtin_amdgcn_readfirstlane(wave_min(gs));   // wave-uniform: scalar loop control
-  const int64_t base = mstart[m];
-  const int nsteps = lmax - m + 1;
+  const int64_t base = mstart[mm];
+  const int nsteps = lmax - mm + 1;
 
   f32x16 dE0[NG], dE1[NG], dO0[NG], dO1[NG];
 #pragma unroll
@@ -299,7 +311,7 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
   if (gmin != kNever) {
     const int nch = (nsteps + kSynChunk - 1) / kSynChunk;
     double v0 = 0.0, v1 = 0.0;
-    const bf16x8* abm = ab + (size_t)cstart[m] * 4 * 64 + lane;
+    const bf16x8* abm = ab + (size_t)cstart[mm] * 4 * 64 + lane;
     const int cfirst = (gmin * kGroup) / kSynChunk;
     for (int c = cfirst; c < nch; ++c) {
       // operands of this chunk, consumed after the recurrence (which hides
@@ -373,24 +385,40 @@ __global__ __launch_bounds__(64) void k_synth_mfma(int lmax, int mmax, int npair
       }
     }
   }
-  // D[i][j]: lane j + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4
+  // D[i][j]: lane j + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4, i the pair
+  // within the tile, j = 2 rhs + comp. Per group and pair half t the
+  // wavefronts put their values at res[rhs][pair][w][E.re, E.im, O.re, O.im];
+  // then the 64-byte run of each (rhs, pair) -- the 4 m of the workgroup,
+  // contiguous in eo -- is written by 4 consecutive threads, 16 bytes each,
+  // so that every store instruction covers whole runs.
   const int j = lane & 31;
   const int comp = j & 1;
+  const int nm = min(kSynWaves, mmax + 1 - m0);   // live m of the workgroup (>= 1)
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
-    const int rhs = 16 * g + (j >> 1);
-    if (rhs >= nrhs) continue;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int i = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+    for (int t = 0; t < 2; ++t) {
+      float* rw = res + (j >> 1) * kSynRhsStride + w * 4 + comp;
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int pr = pb * 64 + 32 * t + i;
-        if (pr >= npairs) continue;
-        float* dst = reinterpret_cast<float*>(eo + rhs * eo_stride + ((size_t)pr * (mmax + 1) + m) * 2);
-        dst[comp] = t ? dE1[g][r] : dE0[g][r];
-        dst[2 + comp] = t ? dO1[g][r] : dO0[g][r];
+      for (int r = 0; r < 16; ++r) {
+        const int i = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+        rw[i * kSynRow] = t ? dE1[g][r] : dE0[g][r];
+        rw[i * kSynRow + 2] = t ? dO1[g][r] : dO0[g][r];
       }
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 8; ++h) {
+        const int e = threadIdx.x + 256 * h;   // (run, u): 512 runs x 4 m
+        const int run = e >> 2, u = e & 3;
+        const int rl = run >> 5, pr = run & 31;
+        const int rhs = 16 * g + rl, pair = pb * 64 + 32 * t + pr;
+        if (u < nm && rhs < nrhs && pair < npairs) {
+          const float* src = res + rl * kSynRhsStride + pr * kSynRow + 4 * u;
+          float4* dst = reinterpret_cast<float4*>(eo + rhs * eo_stride + ((size_t)pair * (mmax + 1) + m0 + u) * 2);
+          *dst = make_float4(src[0], src[1], src[2], src[3]);
+        }
+      }
+      __syncthreads();
     }
   }
 }
@@ -678,10 +706,12 @@ void mixed_starts(const Geometry& g, std::vector<int64_t>& cst, std::vector<int6
     for (size_t q = 0; q < per[x].size(); ++q) order[(size_t)x * maxq + q] = per[x][q];
 }
 
+// workgroups of k_synth_mfma: per XCD one m quad out of every 32 m, times
+// the blocks of 64 ring pairs
 int synth_mfma_blocks(const Geometry& g) {
   const int npb = (g.npairs + 63) / 64;
-  const int jmax = (g.mmax + 32) / 32 * 4;   // m-slots per XCD covering m = 0..mmax
-  return 8 * jmax * npb;
+  const int nquad = (g.mmax + 32) / 32;   // quads per XCD covering m = 0..mmax
+  return 8 * nquad * npb;
 }
 
 hipError_t launch_checkpoints(const crsht_plan* P, hipStream_t s) {
@@ -702,11 +732,11 @@ hipError_t synth_mfma_launch(const crsht_plan* P, int nr, const bf16x8* ab, floa
   dim3 gs(synth_mfma_blocks(g));
   timing_begin(P, 3, s);
   if (launch_groups(nr) > 1)
-    hipLaunchKernelGGL(k_synth_mfma<2>, gs, dim3(64), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.pair_z,
+    hipLaunchKernelGGL(k_synth_mfma<2>, gs, dim3(256), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.pair_z,
                        P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.mx_cstart, ab, ab_group(g), eo,
                        eo_stride);
   else
-    hipLaunchKernelGGL(k_synth_mfma<1>, gs, dim3(64), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.pair_z,
+    hipLaunchKernelGGL(k_synth_mfma<1>, gs, dim3(256), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.pair_z,
                        P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.mx_cstart, ab, ab_group(g), eo,
                        eo_stride);
   timing_end(P, 3, s);
