@@ -41,10 +41,14 @@
  *     Pointers documented as "host" are host memory.
  *   - A plan owns its tables and workspace (allocated at creation, sized for
  *     nrhs_max columns); calls allocate nothing.
- *   - `stream` is a hipStream_t (NULL = the legacy default stream). Transforms
- *     and cr_apply are asynchronous on it. cr_solve, cr_lnpi and
- *     joint_cl_step synchronise `stream` (they read convergence scalars);
- *     their outputs are complete when they return.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream). Transforms,
+ *     cr_apply and cr_solve_async are asynchronous on it (cr_solve_async writes
+ *     its statistics to device memory). cr_solve, cr_lnpi, joint_cl_step and
+ *     the other chain moves synchronise `stream` (they read convergence
+ *     scalars back); their outputs are complete when they return.
+ *   - Calls allocate no device memory: plans own their workspace, staging
+ *     and streams; cr_block_precond_build (a set-up call, once per noise
+ *     model) allocates the preconditioner's storage.
  *   - A plan is not thread-safe: concurrent calls need distinct plans.
  *
  * Errors: functions return CR_OK (0) or a negative code detected before or
@@ -269,7 +273,7 @@ int cr_rhs(const crsht_plan *plan, const cr_problem *prob, int nrhs, const doubl
 int cr_apply(const crsht_plan *plan, const cr_problem *prob, int nrhs, const double *x, double *Ax,
              cr_prec prec, void *stream);
 
-/* Solve eq. mapmakingeq for nrhs independent columns by Jacobi-preconditioned
+/* Solve eq. mapmakingeq for nrhs independent columns by preconditioned
  * conjugate gradients (Shewchuk 1994) from s = 0. The right-hand side is
  * assembled as in cr_rhs from d, w0, w1 (NULL = omitted: d only gives the mean
  * field of eq. mean-field-map, w0 and w1 only the fluctuation of eq. fluc-map),
@@ -283,15 +287,46 @@ int cr_solve(const crsht_plan *plan, const cr_problem *prob, int nrhs, const dou
              const double *w1, const double *rhs, double *s_out, const cr_opts *opts, cr_stats *stats,
              void *stream);
 
+/* The solve of cr_solve, stream-ordered: the whole solve (right-hand side,
+ * PCG, FP64 residual replacements, final true residual) is enqueued on
+ * `stream` and the call returns at once; nothing waits on the host. The
+ * decisions the host loop of cr_solve takes from scalars it reads back (when
+ * to replace the residual, restart a direction, stop a column or the solve)
+ * are taken on the device by a small control kernel between sections whose
+ * kernels return at once once the solve has stopped. With opts->use_graph
+ * each block of check_every iterations is one replay of a captured graph.
+ * ceil(maxiter / check_every) blocks are enqueued, so maxiter should be near
+ * the expected count (blocks after convergence cost a few microseconds per
+ * kernel; the iteration count may exceed maxiter by less than check_every).
+ * CR_MIXED: the iterates of cr_solve; CR_F64: PCG with the FP64 operator whose
+ * residual is replaced by the true one when a column claims convergence.
+ * stats_dev: device memory for nrhs cr_stats, written by the last kernel of
+ * the solve: valid after the stream has been synchronised (or any later work
+ * on it). s_out: device [nrhs][nalm]. The per-call host data (spectra, beam,
+ * amplitudes) is copied through pinned staging slots of the plan: more than
+ * four calls enqueued ahead of the device wait for the oldest. Other
+ * arguments and errors as cr_solve (errors are detected before enqueueing).
+ * Consecutive calls on one plan must use one stream (they share the plan
+ * workspace); changing nrhs, tolerance, preconditioner or limits between
+ * calls re-captures the graphs after synchronising the device once. */
+int cr_solve_async(const crsht_plan *plan, const cr_problem *prob, int nrhs, const double *d, const double *w0,
+                   const double *w1, const double *rhs, double *s_out, const cr_opts *opts, cr_stats *stats_dev,
+                   void *stream);
+
 /* Many independent problems at once (each with its own plan, so Nside, lmax
  * and the noise model may all differ): problem i solves eq. mapmakingeq for
  * one column with plans[i], probs[i], d[i], w0[i], w1[i] (device; any of the
  * three arrays of pointers, or an entry, may be NULL = term omitted) into
  * s_out[i] (device [nalm_i]); stats: host [nprob]. The plans must be
- * distinct (each solve uses its plan's workspace). The library drives the
- * problems concurrently, largest first, each on a stream of its own, after
- * waiting for `stream`; all share `opts`. Returns the first error of any
- * problem (the others are still solved). Blocks until all are done. */
+ * distinct (each solve uses its plan's workspace) and on the current device.
+ * Every problem runs the device-driven solve of cr_solve_async on its plan's
+ * own stream (created with the plan), forked from `stream` by an event and
+ * joined back to it; its blocks of check_every iterations are replays of
+ * the plan's captured graph. No host threads and no streams are created per
+ * call: one host loop enqueues the next block of every problem that the
+ * device has not yet flagged as finished, keeping two blocks per problem in
+ * flight. All share `opts`. Returns the first error. Blocks until all are
+ * done. */
 int cr_solve_batched(const crsht_plan *const *plans, const cr_problem *probs, int nprob, const double *const *d,
                      const double *const *w0, const double *const *w1, double *const *s_out, const cr_opts *opts,
                      cr_stats *stats, void *stream);

@@ -112,6 +112,7 @@ def _load():
         "cr_apply": ([P, ctypes.POINTER(_Problem), i, vp, vp, i, vp], i),
         "cr_solve": ([P, ctypes.POINTER(_Problem), i, vp, vp, vp, vp, vp, ctypes.POINTER(_Opts),
                       ctypes.POINTER(_Stats), vp], i),
+        "cr_solve_async": ([P, ctypes.POINTER(_Problem), i, vp, vp, vp, vp, vp, ctypes.POINTER(_Opts), vp, vp], i),
         "cr_lnpi": ([P, ctypes.POINTER(_Problem), d, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp], i),
         "joint_cl_step": ([P, ctypes.POINTER(_Problem), vp, ctypes.POINTER(_Chain), ctypes.POINTER(_Draws),
                            ctypes.POINTER(_Opts), ctypes.POINTER(_StepOut), vp], i),
@@ -156,6 +157,7 @@ _lib = _load()
 
 EXPORTED = ("crsht_plan_create", "crsht_plan_destroy", "crsht_strerror", "crsht_plan_info", "crsht_pixel_coords",
             "sht_synth", "sht_synth_noalloc", "sht_synth_adjoint", "sht_analysis", "cr_precond", "cr_rhs", "cr_apply", "cr_solve",
+            "cr_solve_async",
             "cr_white", "cr_lnpi", "joint_cl_step", "joint_cl_step_batch", "gibbs_cl_step", "gibbs_cl_step_batch", "gibbs_bins_step", "hmc_cl_step", "cr_lnpi_grad_fixed",
             "cr_solve_batched", "sht_synth_grad", "cr_grad_chi2", "cr_grad_lnpi",
             "cr_block_precond_build", "cr_block_precond_apply", "crsht_timing_enable", "crsht_timing_read")
@@ -377,6 +379,34 @@ def solve(plan: Plan, prob: Problem, d=None, w0=None, w1=None, rhs_vec=None, nrh
     _check(_lib.cr_solve(plan.handle, ctypes.byref(p), nrhs, _ptr(d), _ptr(w0), _ptr(w1), _ptr(rhs_vec), _ptr(out),
                          ctypes.byref(o), st, _stream()), "cr_solve")
     return out, [Stats(s.status, s.iters, s.refinements, s.rel_resid_true) for s in st]
+
+
+def solve_async(plan: Plan, prob: Problem, d=None, w0=None, w1=None, rhs_vec=None, nrhs: int = 1,
+                tol: float = 1e-6, maxiter: int = 60, prec: int = CR_F64, inner_tol: float = 1e-2,
+                max_refine: int = 50, check_every: int = 6, out: torch.Tensor | None = None,
+                stats: torch.Tensor | None = None, use_graph: bool = True, precond: int = CR_PC_JACOBI):
+    """cr_solve_async: the whole solve enqueued on the current stream, nothing
+    waits. Returns (s, stats_dev) with stats_dev a device tensor of nrhs
+    cr_stats (24 bytes each, as uint8); read it with decode_stats after a
+    synchronisation."""
+    if out is None:
+        out = torch.empty(plan.alm_shape(nrhs), dtype=torch.complex128, device=prob.ninv.device)
+    if stats is None:
+        stats = torch.empty(nrhs * ctypes.sizeof(_Stats), dtype=torch.uint8, device=prob.ninv.device)
+    if stats.numel() < nrhs * ctypes.sizeof(_Stats):
+        raise ValueError("stats needs %d bytes" % (nrhs * ctypes.sizeof(_Stats)))
+    p = prob._c()
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every, int(precond), int(use_graph))
+    _check(_lib.cr_solve_async(plan.handle, ctypes.byref(p), nrhs, _ptr(d), _ptr(w0), _ptr(w1), _ptr(rhs_vec),
+                               _ptr(out), ctypes.byref(o), _ptr(stats), _stream()), "cr_solve_async")
+    return out, stats
+
+
+def decode_stats(stats: torch.Tensor, nrhs: int) -> list:
+    """Host copies of the cr_stats an asynchronous solve wrote to the device."""
+    raw = bytes(stats[:nrhs * ctypes.sizeof(_Stats)].cpu().numpy().tobytes())
+    arr = (_Stats * nrhs).from_buffer_copy(raw)
+    return [Stats(x.status, x.iters, x.refinements, x.rel_resid_true) for x in arr]
 
 
 def solve_batched(plans, probs, d=None, w0=None, w1=None, tol: float = 1e-6, maxiter: int = 20000,

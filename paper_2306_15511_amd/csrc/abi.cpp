@@ -49,11 +49,49 @@ int check_plan(const crsht_plan* P, int nrhs) {
   return CR_OK;
 }
 
+// Host data of one call (column amplitudes, per-l arrays) packed into the
+// plan's next pinned staging slot and copied on the call's stream. A slot is
+// reused only after the copies last enqueued from it have executed (its
+// event), so the call never synchronises its stream.
+struct Stager {
+  crsht_plan* P;
+  hipStream_t s;
+  int slot = 0;
+  size_t off = 0;
+  bool ok = true;
+  Stager(const crsht_plan* Pc, hipStream_t st) : P(const_cast<crsht_plan*>(Pc)), s(st) {
+    slot = P->stage_next;
+    P->stage_next = (P->stage_next + 1) % crsht_plan::kStageSlots;
+    if (P->stage_used[slot]) ok = hipEventSynchronize(P->stage_ev[slot]) == hipSuccess;
+  }
+  int put(void* dst, const void* src, size_t bytes) {
+    if (!ok) return CR_EDEVICE;
+    if (off + bytes > P->stage_bytes) return CR_EINVAL;
+    unsigned char* h = static_cast<unsigned char*>(P->stage_host[slot]) + off;
+    std::memcpy(h, src, bytes);
+    off = (off + bytes + 255) & ~size_t(255);
+    CR_TRY(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, s));
+    return CR_OK;
+  }
+  int done() {
+    if (!ok) return CR_EDEVICE;
+    if (recorded || off == 0) return CR_OK;
+    recorded = true;
+    P->stage_used[slot] = true;
+    CR_TRY(hipEventRecord(P->stage_ev[slot], s));
+    return CR_OK;
+  }
+  // copies may have been enqueued from the slot before an argument error:
+  // its event is recorded in any case
+  ~Stager() { (void)done(); }
+  bool recorded = false;
+};
+
 // ---- T+Q+U problem set-up: per-l 3x3 blocks of S^-1 and S^-1/2 (TT, TE and
 // EE coupled, BB apart, TB = EB = 0) for amplitude q. For the symmetric
 // positive definite 2x2 block M = [[a, b], [b, c]] of S^-1 the principal
 // square root is (M + sqrt(det M) I) / sqrt(tr M + 2 sqrt(det M)).
-int set_problem_tqu(const crsht_plan* P, const cr_problem* prob, double q, hipStream_t s) {
+int set_problem_tqu(const crsht_plan* P, const cr_problem* prob, double q, hipStream_t s, Stager& st) {
   const int lmax = P->g.lmax;
   if (prob->lmin < 2 || prob->lmin > lmax) return CR_EINVAL;   // E and B start at l = 2
   const double* tt = prob->cl;
@@ -85,17 +123,17 @@ int set_problem_tqu(const crsht_plan* P, const cr_problem* prob, double q, hipSt
     o[7] = 1.0 / std::sqrt(cbb);
     perl[3 * (lmax + 1) + l] = 1.0;
   }
-  CR_TRY(hipMemcpyAsync(P->w.perl, perl.data(), perl.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  CR_TRY(hipMemcpyAsync(P->w.sblk, blk.data(), blk.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  CR_CHECK(st.put(P->w.perl, perl.data(), perl.size() * sizeof(double)));
+  CR_CHECK(st.put(P->w.sblk, blk.data(), blk.size() * sizeof(double)));
+  CR_CHECK(st.done());
   CR_TRY(launch_expand_tqu(P, P->w.perl, s));
-  CR_TRY(hipStreamSynchronize(s));  // host vectors must outlive the copies
   return CR_OK;
 }
 
 // per-column amplitudes of prob (columns 0..nrhs-1; nrhs = 0: the caller
 // takes none, so prob->amp must be NULL) into w.camp as (1/amp, 1/sqrt(amp)),
 // 1 for every column without one
-int set_columns(const crsht_plan* P, const cr_problem* prob, int nrhs, hipStream_t s) {
+int set_columns(const crsht_plan* P, const cr_problem* prob, int nrhs, Stager& st) {
   if (prob->amp && nrhs < 1) return CR_EINVAL;
   std::vector<double2> f((size_t)P->nrhs_max, make_double2(1.0, 1.0));
   if (prob->amp)
@@ -104,9 +142,7 @@ int set_columns(const crsht_plan* P, const cr_problem* prob, int nrhs, hipStream
       if (!(a > 0.0) || !std::isfinite(a)) return CR_EINVAL;
       f[c] = make_double2(1.0 / a, 1.0 / std::sqrt(a));
     }
-  CR_TRY(hipMemcpyAsync(P->w.camp, f.data(), f.size() * sizeof(double2), hipMemcpyHostToDevice, s));
-  CR_TRY(hipStreamSynchronize(s));  // f (host vector) must outlive the copy
-  return CR_OK;
+  return st.put(P->w.camp, f.data(), f.size() * sizeof(double2));
 }
 
 // ---- problem set-up: per-l factors for amplitude q (C_l -> q C_l); nrhs as
@@ -114,8 +150,9 @@ int set_columns(const crsht_plan* P, const cr_problem* prob, int nrhs, hipStream
 int set_problem(const crsht_plan* P, const cr_problem* prob, double q, hipStream_t s, int nrhs = 0) {
   if (!prob || !prob->cl || !prob->bl || !prob->ninv) return CR_EINVAL;
   if (!(q > 0.0) || !std::isfinite(q)) return CR_EINVAL;
-  CR_CHECK(set_columns(P, prob, nrhs, s));
-  if (P->ncomp == 3) return set_problem_tqu(P, prob, q, s);
+  Stager st(P, s);
+  CR_CHECK(set_columns(P, prob, nrhs, st));
+  if (P->ncomp == 3) return set_problem_tqu(P, prob, q, s, st);
   const int lmax = P->g.lmax;
   if (prob->lmin < 0 || prob->lmin > lmax) return CR_EINVAL;
   if (!(q > 0.0) || !std::isfinite(q)) return CR_EINVAL;
@@ -131,9 +168,9 @@ int set_problem(const crsht_plan* P, const cr_problem* prob, double q, hipStream
     perl[(lmax + 1) + l] = 1.0 / std::sqrt(c);
     perl[3 * (lmax + 1) + l] = 1.0;
   }
-  CR_TRY(hipMemcpyAsync(P->w.perl, perl.data(), perl.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  CR_CHECK(st.put(P->w.perl, perl.data(), perl.size() * sizeof(double)));
+  CR_CHECK(st.done());
   CR_TRY(launch_expand(P, P->w.perl, s));
-  CR_TRY(hipStreamSynchronize(s));  // perl (host vector) must outlive the copy
   return CR_OK;
 }
 
@@ -641,6 +678,202 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
   return CR_OK;
 }
 
+// ====================================================== device-driven solve
+// The refined PCG of solve_refined enqueued as a whole, stream-ordered: the
+// decisions its host loop takes from the scalars it reads back are taken on
+// the device by k_dctl (dsolve.hip) between predicated sections. One
+// super-step = check, FP64 true residual (if a column asks for it), tail (z,
+// <r,z> and beta from the replaced residual), block of `every` iterations.
+// CR_F64 runs the same loop with the FP64 operator and replaces the residual
+// only when a column claims convergence (reliable-update PCG).
+struct DSolve {
+  const crsht_plan* P = nullptr;
+  int nrhs = 0;
+  const double* ninv = nullptr;
+  bool mixed = false, pc = false;
+  DctlArgs a{};
+  int steps = 0;   // super-steps enqueued: ceil(maxiter / every)
+};
+
+// sets the kernel predicate of the plan for the sections enqueued in its scope
+struct PredScope {
+  const crsht_plan* P;
+  PredScope(const crsht_plan* Pc, const int* p) : P(Pc) { P->pred = p; }
+  ~PredScope() { P->pred = nullptr; }
+};
+
+// r = b - A x in FP64; ||r||^2, ||b||^2 into the column scalars (no read-back)
+int true_residual_dev(const crsht_plan* P, int nrhs, const double* ninv, const double2* x, const double2* b,
+                      double2* r, hipStream_t s) {
+  if (P->ncomp == 1) CR_TRY(launch_scale_alm(P, nrhs, x, P->w.bk, P->w.alm_a, s));
+  CR_CHECK(operator_core(P, nrhs, x, P->w.alm_a, ninv, P->w.cg_q, s));
+  CR_TRY(launch_residual(P, nrhs, b, P->w.cg_q, r, s));
+  CR_TRY(launch_sum_rows(P, nrhs, vec_reduce_blocks(P), s));
+  return CR_OK;
+}
+
+int dsolve_setup(DSolve& d, const crsht_plan* P, const cr_problem* prob, int nrhs, const cr_opts* o) {
+  if (!prob || !o) return CR_EINVAL;
+  if (!prob->cl || !prob->bl || !prob->ninv) return CR_EINVAL;
+  if (!(o->tol > 0.0) || o->maxiter < 1) return CR_EINVAL;
+  if (o->prec != CR_F64 && o->prec != CR_MIXED) return CR_EINVAL;
+  if (o->precond != CR_PC_JACOBI && o->precond != CR_PC_BLOCK) return CR_EINVAL;
+  d.P = P;
+  d.nrhs = nrhs;
+  d.ninv = prob->ninv;
+  d.mixed = o->prec == CR_MIXED;
+  d.pc = o->precond == CR_PC_BLOCK;
+  if (d.pc && !P->pc.built) return CR_EINVAL;
+  d.a.nrhs = nrhs;
+  d.a.tol = o->tol;
+  d.a.itol = d.mixed ? ((o->inner_tol > 0.0 && o->inner_tol < 1.0) ? o->inner_tol : 1e-2) : 0.0;
+  d.a.maxref = o->max_refine > 0 ? o->max_refine : 1000;
+  d.a.maxiter = o->maxiter;
+  d.a.every = o->check_every > 0 ? o->check_every : 8;
+  d.a.f64 = d.mixed ? 0 : 1;
+  d.steps = (o->maxiter + d.a.every - 1) / d.a.every;
+  return CR_OK;
+}
+
+// check, FP64 true residual and (with tail) z, <r,z>, beta from it
+int dsolve_check_replace(const DSolve& d, hipStream_t q, bool tail) {
+  const crsht_plan* P = d.P;
+  Workspace const& w = P->w;
+  CR_TRY(launch_dctl(P, DC_CHECK, d.a, nullptr, q));
+  {
+    PredScope ps(P, w.ctl + C_SKIP_REPL);
+    CR_CHECK(true_residual_dev(P, d.nrhs, d.ninv, w.cg_x, w.cg_b, w.cg_r, q));
+  }
+  CR_TRY(launch_dctl(P, DC_AFTER_REPL, d.a, nullptr, q));
+  if (!tail) return CR_OK;
+  PredScope ps(P, w.ctl + C_SKIP_TAIL);
+  if (d.pc) {
+    CR_TRY(launch_pc_apply(P, d.nrhs, w.cg_r, w.cg_z, q));
+    CR_TRY(launch_pc_dots(P, d.nrhs, w.cg_r, w.cg_z, true, q));
+  } else {
+    CR_TRY(launch_cg_replace(P, d.nrhs, w.cg_r, w.cg_z, q));
+  }
+  CR_TRY(launch_cg_scalars(P, d.nrhs, 3, vec_reduce_blocks(P), d.a.tol, 0, q));
+  return CR_OK;
+}
+
+// one super-step; `first`: the block starts with the pending direction update
+int dsolve_step(const DSolve& d, bool first, hipStream_t q) {
+  const crsht_plan* P = d.P;
+  Workspace const& w = P->w;
+  const int nb = vec_reduce_blocks(P);
+  CR_CHECK(dsolve_check_replace(d, q, true));
+  CR_TRY(launch_dctl(P, DC_PRE_BLOCK, d.a, nullptr, q));
+  {
+    PredScope ps(P, w.ctl + C_SKIP_ITER);
+    for (int k = 0; k < d.a.every; ++k) {
+      const bool upd = k > 0 || first;
+      if (d.mixed) {
+        CR_CHECK(operator_core_cg(P, d.nrhs, upd, d.ninv, w.cg_q, q));
+      } else {
+        if (upd) CR_TRY(launch_cg_pupdate(P, d.nrhs, w.cg_z, w.cg_p, w.alm_a, q));
+        CR_CHECK(operator_core(P, d.nrhs, w.cg_p, w.alm_a, d.ninv, w.cg_q, q));
+      }
+      CR_TRY(launch_cg_scalars(P, d.nrhs, 1, nb, d.a.tol, 0, q));
+      CR_CHECK(pcg_update(P, d.nrhs, d.pc, q));
+      CR_TRY(launch_cg_scalars(P, d.nrhs, 2, nb, d.a.tol, 0, q));
+    }
+  }
+  CR_TRY(launch_dctl(P, DC_AFTER_BLOCK, d.a, nullptr, q));
+  return CR_OK;
+}
+
+// captured super-steps (first block, later blocks), kept with their key;
+// returns whether they are to be replayed
+int dsolve_graphs(const DSolve& d, bool use_graph, bool* graphs) {
+  crsht_plan* P = const_cast<crsht_plan*>(d.P);
+  *graphs = false;
+  if (!use_graph || P->timing.on || !P->cap_stream) return CR_OK;
+  GraphKey key;
+  key.kind = d.mixed ? 3 : 4;
+  key.nrhs = d.nrhs;
+  key.n = d.a.every;
+  key.pc = d.pc ? 1 : 0;
+  key.ninv = d.ninv;
+  key.tol = d.a.tol;
+  key.itol = d.a.itol;
+  key.maxref = d.a.maxref;
+  key.maxiter = d.a.maxiter;
+  if (!(P->dgraph[0] && P->dgraph[1] && P->dgraph_key == key)) {
+    if (P->dgraph[0] || P->dgraph[1]) {
+      // replays of the old graphs may still be queued on some stream
+      CR_TRY(hipDeviceSynchronize());
+      for (auto& gx : P->dgraph) {
+        if (gx) (void)hipGraphExecDestroy(gx);
+        gx = nullptr;
+      }
+    }
+    P->dgraph_key = GraphKey();
+    for (int f = 0; f < 2; ++f) {
+      CR_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+      const int rc = dsolve_step(d, f == 1, P->cap_stream);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(P->cap_stream, &g);
+      if (rc != CR_OK || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc != CR_OK ? rc : CR_EDEVICE;
+      }
+      hipGraphExec_t ex = nullptr;
+      const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) return CR_EDEVICE;
+      P->dgraph[f] = ex;
+    }
+    P->dgraph_key = key;
+  }
+  *graphs = true;
+  return CR_OK;
+}
+
+int dsolve_launch(const DSolve& d, int k, bool graphs, hipStream_t s) {
+  if (graphs) {
+    CR_TRY(hipGraphLaunch(d.P->dgraph[k > 0 ? 1 : 0], s));
+    return CR_OK;
+  }
+  return dsolve_step(d, k > 0, s);
+}
+
+// problem set-up, right-hand side, x = 0, r = b and the start of PCG
+int dsolve_prologue(const DSolve& d, const cr_problem* prob, const double* dm, const double* w0, const double* w1,
+                    const double* rhs, hipStream_t s) {
+  const crsht_plan* P = d.P;
+  Workspace const& w = P->w;
+  const size_t vbytes = (size_t)d.nrhs * vlen(P) * sizeof(double2);
+  CR_CHECK(set_problem(P, prob, 1.0, s, d.nrhs));
+  if (!d.pc) CR_CHECK(compute_diag(P, prob->ninv, s));
+  if (rhs)
+    CR_TRY(launch_project(P, d.nrhs, C2(rhs), w.cg_b, s));
+  else
+    CR_CHECK(assemble_rhs(P, d.nrhs, prob->ninv, dm, w0, w1, w.cg_b, s));
+  CR_TRY(hipMemsetAsync(w.cg_x, 0, vbytes, s));
+  CR_TRY(hipMemcpyAsync(w.cg_r, w.cg_b, vbytes, hipMemcpyDeviceToDevice, s));
+  CR_CHECK(pcg_start(P, d.nrhs, w.cg_b, d.pc, s));
+  CR_TRY(launch_cg_scalars(P, d.nrhs, 0, vec_reduce_blocks(P), d.a.tol, 0, s));
+  CR_TRY(launch_dctl(P, DC_INIT, d.a, nullptr, s));
+  return CR_OK;
+}
+
+// the last check, the FP64 true residual of the returned x (unless current),
+// the statistics and x
+int dsolve_epilogue(const DSolve& d, double* s_out, void* stats_dev, hipStream_t s) {
+  const crsht_plan* P = d.P;
+  Workspace const& w = P->w;
+  CR_CHECK(dsolve_check_replace(d, s, false));
+  CR_TRY(launch_dctl(P, DC_FINAL_PRE, d.a, nullptr, s));
+  {
+    PredScope ps(P, w.ctl + C_SKIP_FINAL);
+    CR_CHECK(true_residual_dev(P, d.nrhs, d.ninv, w.cg_x, w.cg_b, w.cg_r, s));
+  }
+  CR_TRY(launch_dctl(P, DC_FINAL_POST, d.a, stats_dev, s));
+  CR_TRY(hipMemcpyAsync(s_out, w.cg_x, (size_t)d.nrhs * vlen(P) * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  return CR_OK;
+}
+
 // x0 (device, nrhs columns, optional; may alias s_out): warm start. The solve
 // then runs on the correction, A delta = b - A x0, to the tolerance
 // tol / max_c(||b - A x0|| / ||b||) (the strictest column's), and s_out =
@@ -898,6 +1131,23 @@ extern "C" int cr_solve(const crsht_plan* P, const cr_problem* prob, int nrhs, c
   return solve_core(P, prob, 1.0, nrhs, d, w0, w1, rhs, s_out, opts, stats, S(stream));
 }
 
+extern "C" int cr_solve_async(const crsht_plan* P, const cr_problem* prob, int nrhs, const double* d,
+                              const double* w0, const double* w1, const double* rhs, double* s_out,
+                              const cr_opts* opts, cr_stats* stats_dev, void* stream) {
+  CR_CHECK(check_plan(P, nrhs));
+  if (!s_out || !stats_dev) return CR_EINVAL;
+  DSolve ds;
+  CR_CHECK(dsolve_setup(ds, P, prob, nrhs, opts));
+  hipStream_t s = S(stream);
+  bool graphs = false;
+  CR_CHECK(dsolve_graphs(ds, opts->use_graph != 0, &graphs));
+  CR_CHECK(dsolve_prologue(ds, prob, d, w0, w1, rhs, s));
+  for (int k = 0; k < ds.steps; ++k) CR_CHECK(dsolve_launch(ds, k, graphs, s));
+  CR_CHECK(dsolve_epilogue(ds, s_out, stats_dev, s));
+  CR_TRY(hipGetLastError());
+  return CR_OK;
+}
+
 extern "C" int cr_solve_batched(const crsht_plan* const* plans, const cr_problem* probs, int nprob,
                                 const double* const* d, const double* const* w0, const double* const* w1,
                                 double* const* s_out, const cr_opts* opts, cr_stats* stats, void* stream) {
@@ -908,44 +1158,72 @@ extern "C" int cr_solve_batched(const crsht_plan* const* plans, const cr_problem
     for (int j = 0; j < i; ++j)
       if (plans[j] == plans[i]) return CR_EINVAL;   // each problem needs its own workspace
   }
-  // the caller's stream has produced the inputs
-  CR_TRY(hipStreamSynchronize(S(stream)));
-  std::vector<hipStream_t> st(nprob, nullptr);
-  int rc = CR_OK;
-  for (int i = 0; i < nprob && rc == CR_OK; ++i) {
-    if (hipSetDevice(plans[i]->device) != hipSuccess || hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking) != hipSuccess)
-      rc = CR_EDEVICE;
+  int dev = -1;
+  CR_TRY(hipGetDevice(&dev));
+  for (int i = 0; i < nprob; ++i)
+    if (plans[i]->device != dev) return CR_EINVAL;
+  hipStream_t s = S(stream);
+  std::vector<DSolve> ds(nprob);
+  std::vector<char> graphs(nprob, 0);
+  for (int i = 0; i < nprob; ++i) {
+    CR_CHECK(dsolve_setup(ds[i], plans[i], &probs[i], 1, opts));
+    bool g = false;
+    CR_CHECK(dsolve_graphs(ds[i], opts->use_graph != 0, &g));
+    graphs[i] = g ? 1 : 0;
   }
-  if (rc == CR_OK) {
-    // largest problems first; a pool of host workers, each driving one
-    // problem's PCG on that problem's stream, keeps several solves in flight
-    std::vector<int> order(nprob);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return plans[a]->g.npix * (int64_t)plans[a]->g.lmax >
-                                                plans[b]->g.npix * (int64_t)plans[b]->g.lmax; });
-    std::vector<int> res(nprob, CR_OK);
-    std::atomic<int> next{0};
-    auto worker = [&]() {
-      for (int k; (k = next.fetch_add(1)) < nprob;) {
-        const int i = order[k];
-        if (hipSetDevice(plans[i]->device) != hipSuccess) {
-          res[i] = CR_EDEVICE;
+  // largest problems first
+  std::vector<int> order(nprob);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return plans[a]->g.npix * (int64_t)plans[a]->g.lmax > plans[b]->g.npix * (int64_t)plans[b]->g.lmax;
+  });
+  // every problem on its plan's stream, after the caller's stream has
+  // produced the inputs
+  for (int i : order) {
+    const crsht_plan* P = plans[i];
+    CR_TRY(hipEventRecord(P->ev_fork, s));
+    CR_TRY(hipStreamWaitEvent(P->exec_stream, P->ev_fork, 0));
+    *reinterpret_cast<volatile int*>(P->w.host_exited) = 0;
+    CR_CHECK(dsolve_prologue(ds[i], &probs[i], d ? d[i] : nullptr, w0 ? w0[i] : nullptr, w1 ? w1[i] : nullptr,
+                             nullptr, P->exec_stream));
+  }
+  // blocks of every problem until its solve has stopped: block r of a
+  // problem is enqueued once its block r - 2 has run (two in flight) and the
+  // device has not yet flagged the problem as stopped
+  std::vector<char> stopped(nprob, 0);
+  const int R = crsht_plan::kRoundEvents;
+  for (int r = 0;; ++r) {
+    bool any = false;
+    for (int i : order) {
+      if (stopped[i]) continue;
+      const crsht_plan* P = plans[i];
+      if (r >= ds[i].steps) {
+        stopped[i] = 1;
+        continue;
+      }
+      if (r >= 2) {
+        CR_TRY(hipEventSynchronize(P->ev_round[(r - 2) % R]));
+        if (*reinterpret_cast<volatile int*>(P->w.host_exited) != 0) {
+          stopped[i] = 1;
           continue;
         }
-        res[i] = solve_core(plans[i], &probs[i], 1.0, 1, d ? d[i] : nullptr, w0 ? w0[i] : nullptr,
-                            w1 ? w1[i] : nullptr, nullptr, s_out[i], opts, &stats[i], st[i]);
       }
-    };
-    const int nw = std::min(nprob, kBatchWorkers);
-    std::vector<std::thread> pool;
-    for (int k = 0; k < nw; ++k) pool.emplace_back(worker);
-    for (auto& t : pool) t.join();
-    for (int i = 0; i < nprob && rc == CR_OK; ++i) rc = res[i];
+      CR_CHECK(dsolve_launch(ds[i], r, graphs[i] != 0, P->exec_stream));
+      CR_TRY(hipEventRecord(P->ev_round[r % R], P->exec_stream));
+      any = true;
+    }
+    if (!any) break;
   }
-  for (hipStream_t x : st)
-    if (x) (void)hipStreamDestroy(x);
-  return rc;
+  for (int i : order) {
+    const crsht_plan* P = plans[i];
+    CR_CHECK(dsolve_epilogue(ds[i], s_out[i], P->w.dstats, P->exec_stream));
+    CR_TRY(hipEventRecord(P->ev_join, P->exec_stream));
+    CR_TRY(hipStreamWaitEvent(s, P->ev_join, 0));
+  }
+  CR_TRY(hipStreamSynchronize(s));
+  for (int i = 0; i < nprob; ++i)
+    CR_TRY(hipMemcpy(&stats[i], plans[i]->w.dstats, sizeof(cr_stats), hipMemcpyDeviceToHost));
+  return CR_OK;
 }
 
 extern "C" int cr_lnpi(const crsht_plan* P, const cr_problem* fid, double q, const double* d, const double* ahat,

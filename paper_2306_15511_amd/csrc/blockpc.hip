@@ -211,7 +211,8 @@ __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3
     int nrhs, int64_t vlen, const int64_t* __restrict__ be0, const int* __restrict__ task_b,
     const int* __restrict__ task_b1, const int* __restrict__ task_r0, const int* __restrict__ bn,
     const int64_t* __restrict__ boff, const float* __restrict__ inv, const double2* __restrict__ r,
-    double2* __restrict__ z) {
+    double2* __restrict__ z, const int* __restrict__ pred) {
+  if (pred && *pred) return;
   constexpr int kSteps = kPcJ / 2;                          // K steps per LDS tile
   constexpr int kR = 2 * kPcJ * kPcCols / (kPcWaves * 64);  // residual values staged per thread and tile
   static_assert(kSteps % kPcPre == 0, "tile must hold whole prefetch groups");
@@ -334,7 +335,9 @@ __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3
 
 // partial <r, z> (row 0) and, with rr, <r, r> (row 1) per column
 __global__ void k_pc_dots(int64_t vlen, const int* __restrict__ idx_m, const double2* __restrict__ r,
-                          const double2* __restrict__ z, int rr, double* __restrict__ partial, int npart) {
+                          const double2* __restrict__ z, int rr, double* __restrict__ partial, int npart,
+                          const int* __restrict__ pred) {
+  if (pred && *pred) return;
   __shared__ double sh[256];
   const int c = blockIdx.y;
   double rz = 0.0, r2 = 0.0;
@@ -391,6 +394,11 @@ int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
   if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
   P->graph_exec = nullptr;
   P->graph_key = GraphKey();
+  for (auto& gx : P->dgraph) {
+    if (gx) (void)hipGraphExecDestroy(gx);
+    gx = nullptr;
+  }
+  P->dgraph_key = GraphKey();
   block_pc_free(pc);
   // blocks (component, m, parity), component-major: sizes, vector element of
   // row 0, compact FP32 offsets; then the application tasks
@@ -607,7 +615,7 @@ hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, doub
   const BlockPC& pc = P->pc;
   timing_begin(P, 5, s);
   hipLaunchKernelGGL(k_pc_apply, dim3(pc.ntasks), dim3(kPcWaves * 64), 0, s, nrhs, vlen(P), pc.be0, pc.task_b,
-                     pc.task_b1, pc.task_r0, pc.bn, pc.boff, pc.inv, r, z);
+                     pc.task_b1, pc.task_r0, pc.bn, pc.boff, pc.inv, r, z, P->pred);
   timing_end(P, 5, s);
   return hipGetLastError();
 }
@@ -616,7 +624,7 @@ hipError_t launch_pc_dots(const crsht_plan* P, int nrhs, const double2* r, const
                           hipStream_t s) {
   const int nb = vec_reduce_blocks(P);
   hipLaunchKernelGGL(k_pc_dots, dim3(nb, nrhs), dim3(256), 0, s, vlen(P), P->t.idx_mv, r, z, rr ? 1 : 0,
-                     P->w.partial, P->w.npart);
+                     P->w.partial, P->w.npart, P->pred);
   return hipGetLastError();
 }
 

@@ -107,12 +107,15 @@ struct Workspace {
   double* bin_grad = nullptr;  // [lmax+1] per-bin gradient
   double* lfac = nullptr;      // [lmax+1] per-l factors (fluctuation rescaling of a bin move)
   double2* camp = nullptr;     // [nrhs_max] per-column (1/amp, 1/sqrt(amp)) of the problem's S^-1, S^-1/2
+  int* ctl = nullptr;          // [kCtlSlots] control block of a device-driven solve
+  int* host_exited = nullptr;  // pinned, device-visible: set to 1 by the device once the solve has stopped
+  void* dstats = nullptr;      // [nrhs_max] cr_stats written by a device-driven solve (cr_solve_batched)
   void* mx_ab = nullptr;       // bf16 synthesis operand tiles (one group of kMixedCols columns)
   void* mx_ag = nullptr;       // bf16 adjoint operand tiles
   int npart = 0;
 };
 
-constexpr int kScalSlots = 16;
+constexpr int kScalSlots = 24;
 constexpr int kBinSlices = 16;   // m slices per multipole bin in the gradient reductions
 constexpr int kMixedCols = 32;   // MFMA N: 16 right-hand sides (re, im) per column group
 constexpr int kMaxGroups = 2;    // column groups sharing one recurrence pass of an MFMA synthesis launch
@@ -134,6 +137,39 @@ enum ScalSlot {
   S_AUX1 = 12,
   S_AUX2 = 13,
   S_RESTART = 14,  // host flag: the next replacement restarts the direction (beta = 0)
+  // device-driven solve (dsolve.hip): per-column state of the refinement
+  S_TRIG = 15,     // the column asked for the current residual replacement
+  S_LAST = 16,     // true relative residual at the last replacement (1 before the first)
+  S_REFINE = 17,   // residual replacements of the column
+  S_TRUE = 18,     // last true relative residual
+};
+
+// Control block of a device-driven solve (int32, plan workspace w.ctl).
+// The C_SKIP_* words are the predicates of the enqueued sections: the
+// kernels of a section return at once while their word is non-zero.
+enum CtlSlot {
+  C_SKIP_ITER = 0,   // block of PCG iterations (all columns finished or the solve exited)
+  C_SKIP_REPL = 1,   // FP64 true residual of a replacement (not needed at this check)
+  C_SKIP_TAIL = 2,   // z, <r,z> and beta from the replaced residual
+  C_SKIP_FINAL = 3,  // FP64 true residual at exit (the last one is current)
+  C_IT = 4,          // iterations done
+  C_NREP = 5,        // replacements done
+  C_FRESH = 6,       // the true residuals are those of the current x
+  C_PENDING = 7,     // a direction update is pending (after the first block)
+  C_EXITED = 8,      // the solve has stopped; later sections are skipped
+  kCtlSlots = 16
+};
+// modes of the control kernel k_dctl
+enum DctlMode { DC_INIT = 0, DC_CHECK = 1, DC_AFTER_REPL = 2, DC_PRE_BLOCK = 3, DC_AFTER_BLOCK = 4, DC_FINAL_PRE = 5,
+                DC_FINAL_POST = 6 };
+struct DctlArgs {
+  int nrhs;
+  double tol;        // target relative true residual
+  double itol;       // replacement each time the recursive residual fell by this factor (0: at convergence only)
+  int maxref;        // maximum replacements
+  int maxiter;       // iterations
+  int every;         // iterations per enqueued block
+  int f64;           // stats report no replacements (plain FP64 form)
 };
 
 // 0 FP64 Legendre synthesis, 1 FP64 Legendre adjoint, 2 ring pass,
@@ -177,15 +213,41 @@ struct GraphKey {
   int pc = 0;               // block preconditioner in use
   const void* ninv = nullptr;
   double tol = 0.0;
+  double itol = 0.0;        // device-driven solve: replacement factor, replacement and iteration limits
+  int maxref = 0, maxiter = 0;
   bool operator==(const GraphKey& o) const {
     return kind == o.kind && nrhs == o.nrhs && n == o.n && first_update == o.first_update && pc == o.pc &&
-           ninv == o.ninv && tol == o.tol;
+           ninv == o.ninv && tol == o.tol && itol == o.itol && maxref == o.maxref && maxiter == o.maxiter;
   }
 };
 }  // namespace crsht
 
 struct crsht_plan {
   crsht::Geometry g;
+  // predicate of the solve kernels: while non-null, every kernel of the PCG
+  // loop (operator, preconditioner, vector updates, reductions) returns at
+  // once when *pred != 0. Set only while a device-driven solve enqueues its
+  // predicated sections (dsolve.hip); null otherwise.
+  mutable const int* pred = nullptr;
+  // pinned staging of the per-call host data (spectra, beam, column
+  // amplitudes): slot k is reused only after the copies last enqueued from it
+  // have run (event k), so no call has to synchronise its stream
+  static constexpr int kStageSlots = 4;
+  void* stage_host[kStageSlots] = {};
+  hipEvent_t stage_ev[kStageSlots] = {};
+  bool stage_used[kStageSlots] = {};
+  int stage_next = 0;
+  size_t stage_bytes = 0;
+  // captured super-steps of the device-driven solve (first block, later blocks)
+  hipGraphExec_t dgraph[2] = {};
+  crsht::GraphKey dgraph_key;
+  // cr_solve_batched: the plan's problem runs on its own stream (created with
+  // the plan), forked from and joined to the caller's stream by events; a
+  // ring of events paces the enqueued blocks against the device
+  hipStream_t exec_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  static constexpr int kRoundEvents = 3;
+  hipEvent_t ev_round[kRoundEvents] = {};
   hipStream_t cap_stream = nullptr;     // stream used only to capture iteration blocks
   hipGraphExec_t graph_exec = nullptr;  // last captured block
   crsht::GraphKey graph_key;
@@ -308,6 +370,10 @@ hipError_t launch_pc_dots(const crsht_plan* P, int nrhs, const double2* r, const
 // ---- allocation-free synthesis (noalloc.hip) ----
 // device address of the static scratch on `device` (current), once per device
 int noalloc_setup(int device);
+
+// ---- device-driven solve control (dsolve.hip) ----
+// stats: device cr_stats [nrhs] (written by DC_FINAL_POST), may be null for other modes
+hipError_t launch_dctl(const crsht_plan* P, int mode, const DctlArgs& a, void* stats_dev, hipStream_t s);
 
 // ---- vector kernels (vec.hip) ----
 // Reductions write per-block partial sums to w.partial (column c, row r at

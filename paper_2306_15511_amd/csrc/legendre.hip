@@ -103,7 +103,9 @@ template <int NR>
 __global__ __launch_bounds__(kSynthBlock) void k_legendre_synth(
     int lmax, int mmax, int npairs, const double* __restrict__ pair_z, const double* __restrict__ alpha,
     const int* __restrict__ lst_g, const double2* __restrict__ lst_s, const int64_t* __restrict__ mstart,
-    const double2* __restrict__ alms, int64_t alm_stride, double2* __restrict__ eo, int64_t eo_stride) {
+    const double2* __restrict__ alms, int64_t alm_stride, double2* __restrict__ eo, int64_t eo_stride,
+    const int* __restrict__ pred) {
+  if (pred && *pred) return;
   __shared__ double s_al[2][kChunk];
   __shared__ double2 s_a[2][NR][kChunk];
   const int lane = threadIdx.x;
@@ -230,7 +232,8 @@ __global__ __launch_bounds__(kAdjBlock) void k_legendre_adj(
     int lmax, int mmax, int npairs, const double* __restrict__ pair_z, const double* __restrict__ alpha,
     const int* __restrict__ lst_g, const double2* __restrict__ lst_s, const int64_t* __restrict__ mstart,
     const double2* __restrict__ geo, int64_t geo_stride, const double* __restrict__ ringw,
-    double2* __restrict__ out, int64_t out_stride) {
+    double2* __restrict__ out, int64_t out_stride, const int* __restrict__ pred) {
+  if (pred && *pred) return;
   constexpr int C = kAdjOutputs / (2 * NR);          // l steps per reduction chunk (divides kGroup)
   constexpr int TPO = kAdjBlock / kAdjOutputs;        // threads per reduced output
   extern __shared__ double s_al[];                    // [lmax+1] alpha of this m
@@ -369,7 +372,8 @@ __global__ __launch_bounds__(kAmWaves * 64) void k_legendre_adj_mfma(
     int lmax, int mmax, int npairs, int p_off, int accumulate, int ncols, const double* __restrict__ pair_z,
     const double* __restrict__ alpha, const int* __restrict__ lst_g, const double2* __restrict__ lst_s,
     const int64_t* __restrict__ mstart, const double2* __restrict__ geo, int64_t geo_stride, double2* __restrict__ out,
-    int64_t out_stride) {
+    int64_t out_stride, const int* __restrict__ pred) {
+  if (pred && *pred) return;
   extern __shared__ double am_lds[];   // [kAmWaves][64][kAmRow]
   const int m = block_to_m(blockIdx.x);
   if (m > mmax) return;
@@ -495,7 +499,8 @@ __global__ __launch_bounds__(64) void k_legendre_synth_mfma(
     int lmax, int mmax, int npairs, int ncols, int ngroups, const double* __restrict__ pair_z,
     const double* __restrict__ alpha, const int* __restrict__ lst_g, const double2* __restrict__ lst_s,
     const int64_t* __restrict__ mstart, const double2* __restrict__ alms, int64_t alm_stride,
-    double2* __restrict__ eo, int64_t eo_stride) {
+    double2* __restrict__ eo, int64_t eo_stride, const int* __restrict__ pred) {
+  if (pred && *pred) return;
   __shared__ double mu_s[kAmChunk * kSmRow];
   const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
   const int g = q % ngroups, m = (q / ngroups) * 8 + xcd;
@@ -585,7 +590,8 @@ hipError_t synth_pass(const crsht_plan* P, const double2* alms, double2* eo, hip
   const int64_t eo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
   timing_begin(P, 0, s);
   hipLaunchKernelGGL(k_legendre_synth<NR>, grid, dim3(kSynthBlock), 0, s, g.lmax, g.mmax, g.npairs, P->t.pair_z,
-                     P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, alms, (int64_t)g.nalm, eo, eo_stride);
+                     P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, alms, (int64_t)g.nalm, eo, eo_stride,
+                     P->pred);
   timing_end(P, 0, s);
   return hipGetLastError();
 }
@@ -599,11 +605,11 @@ hipError_t adj_pass_rpt(const crsht_plan* P, const double2* geo, double2* out, b
   if (diag)
     hipLaunchKernelGGL((k_legendre_adj<NR, RPT, MODE_DIAG>), dim3(nb), dim3(kAdjBlock), lds, s, g.lmax, g.mmax,
                        g.npairs, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, geo, geo_stride,
-                       P->w.ring_w, out, (int64_t)g.nalm);
+                       P->w.ring_w, out, (int64_t)g.nalm, P->pred);
   else
     hipLaunchKernelGGL((k_legendre_adj<NR, RPT, MODE_RAW>), dim3(nb), dim3(kAdjBlock), lds, s, g.lmax, g.mmax,
                        g.npairs, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, geo, geo_stride,
-                       P->w.ring_w, out, (int64_t)g.nalm);
+                       P->w.ring_w, out, (int64_t)g.nalm, P->pred);
   return hipGetLastError();
 }
 
@@ -656,7 +662,8 @@ hipError_t launch_legendre_synth(const crsht_plan* P, int nrhs, const double2* a
       timing_begin(P, 0, s);
       hipLaunchKernelGGL(k_legendre_synth_mfma, dim3(nb), dim3(64), 0, s, g.lmax, g.mmax, g.npairs, nc, ngroups,
                          P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
-                         alms + (int64_t)c0 * g.nalm, (int64_t)g.nalm, eo + (int64_t)c0 * eo_stride, eo_stride);
+                         alms + (int64_t)c0 * g.nalm, (int64_t)g.nalm, eo + (int64_t)c0 * eo_stride, eo_stride,
+                         P->pred);
       timing_end(P, 0, s);
       const hipError_t err = hipGetLastError();
       if (err != hipSuccess) return err;
@@ -694,7 +701,8 @@ hipError_t launch_legendre_adjoint(const crsht_plan* P, int nrhs, const double2*
       for (int p0 = 0; p0 < g.npairs && err == hipSuccess; p0 += kAmPairs) {
         hipLaunchKernelGGL(k_legendre_adj_mfma, dim3(nb), dim3(kAmWaves * 64), lds, s, g.lmax, g.mmax, g.npairs, p0,
                            p0 > 0 ? 1 : 0, nc, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
-                           geo + (int64_t)c0 * geo_stride, geo_stride, raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm);
+                           geo + (int64_t)c0 * geo_stride, geo_stride, raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm,
+                           P->pred);
         err = hipGetLastError();
       }
     }

@@ -152,7 +152,9 @@ __global__ __launch_bounds__(256) void k_checkpoints(int lmax, int mmax, int npa
 __global__ __launch_bounds__(64) void k_prep_synth(int lmax, int nrhs, const int64_t* __restrict__ mstart,
                                                    const int64_t* __restrict__ cstart, const double2* __restrict__ alm,
                                                    int64_t alm_stride, const double* __restrict__ f,
-                                                   bf16x8* __restrict__ ab, int64_t ab_gstride) {
+                                                   bf16x8* __restrict__ ab, int64_t ab_gstride,
+                                                   const int* __restrict__ pred) {
+  if (pred && *pred) return;
   __shared__ __attribute__((aligned(16))) float st_lds[2][16][2][16];
   const int m = blockIdx.y, c = blockIdx.x, grp = blockIdx.z;   // group grp: right-hand sides 16 grp ..
   nrhs -= 16 * grp;
@@ -205,7 +207,9 @@ __global__ __launch_bounds__(64) void k_pupdate_prep(int lmax, int nrhs, int64_t
                                                      const int64_t* __restrict__ cstart, const double* __restrict__ bk,
                                                      const double2* __restrict__ z, double2* __restrict__ p,
                                                      const double* __restrict__ scal, int update,
-                                                     bf16x8* __restrict__ ab, int64_t ab_gstride) {
+                                                     bf16x8* __restrict__ ab, int64_t ab_gstride,
+                                                     const int* __restrict__ pred) {
+  if (pred && *pred) return;
   __shared__ __attribute__((aligned(16))) float st_lds[2][16][2][16];
   const int m = blockIdx.y, c = blockIdx.x, grp = blockIdx.z;   // group grp: right-hand sides 16 grp ..
   nrhs -= 16 * grp;
@@ -282,7 +286,9 @@ __global__ __launch_bounds__(256) void k_synth_mfma(int lmax, int mmax, int npai
                                                     const int64_t* __restrict__ mstart,
                                                     const int64_t* __restrict__ cstart,
                                                     const bf16x8* __restrict__ ab, int64_t ab_gstride,
-                                                    float2* __restrict__ eo, int64_t eo_stride) {
+                                                    float2* __restrict__ eo, int64_t eo_stride,
+                                                    const int* __restrict__ pred) {
+  if (pred && *pred) return;
   // results of one pair half (32 pairs) of the 16 columns of a group
   __shared__ __attribute__((aligned(16))) float res[16 * kSynRhsStride];
   const int npb = (npairs + 63) / 64;
@@ -433,7 +439,9 @@ __global__ __launch_bounds__(256) void k_synth_mfma(int lmax, int mmax, int npai
 constexpr int kPrepM = 8;                       // m per block
 constexpr int kPrepMS = 2 * 16 * 2 * 16 + 8;   // floats per m in LDS ([q][rhs][comp][pair], padded)
 __global__ __launch_bounds__(256) void k_prep_adj(int mmax, int npairs, int nrhs, const float2* __restrict__ geo,
-                                                  int64_t geo_stride, bf16x8* __restrict__ ag, int64_t ag_gstride) {
+                                                  int64_t geo_stride, bf16x8* __restrict__ ag, int64_t ag_gstride,
+                                                  const int* __restrict__ pred) {
+  if (pred && *pred) return;
   __shared__ __attribute__((aligned(16))) float G[kPrepM * kPrepMS];
   const int kb = blockIdx.x, m0 = blockIdx.y * kPrepM, grp = blockIdx.z;   // right-hand sides 16 grp ..
   nrhs -= 16 * grp;
@@ -534,7 +542,9 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
                                                   const int* __restrict__ tile_m, const int* __restrict__ order,
                                                   int maxq, const double2* __restrict__ ckpt,
                                                   const bf16x8* __restrict__ ag, int64_t ag_gstride,
-                                                  double2* __restrict__ out, int64_t out_stride) {
+                                                  double2* __restrict__ out, int64_t out_stride,
+                                                  const int* __restrict__ pred) {
+  if (pred && *pred) return;
   // per wavefront: [q][h][32 steps][kRowB bytes]; reused for the partial results
   __shared__ __attribute__((aligned(16))) unsigned char lds[kAdjWaves][2][2][32][kRowB];
   const int tid = order[(blockIdx.x & 7) * maxq + (blockIdx.x >> 3)];   // tiles of one m stay on one XCD
@@ -734,11 +744,11 @@ hipError_t synth_mfma_launch(const crsht_plan* P, int nr, const bf16x8* ab, floa
   if (launch_groups(nr) > 1)
     hipLaunchKernelGGL(k_synth_mfma<2>, gs, dim3(256), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.pair_z,
                        P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.mx_cstart, ab, ab_group(g), eo,
-                       eo_stride);
+                       eo_stride, P->pred);
   else
     hipLaunchKernelGGL(k_synth_mfma<1>, gs, dim3(256), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.pair_z,
                        P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.mx_cstart, ab, ab_group(g), eo,
-                       eo_stride);
+                       eo_stride, P->pred);
   timing_end(P, 3, s);
   return hipGetLastError();
 }
@@ -754,7 +764,7 @@ hipError_t launch_legendre_synth_mixed(const crsht_plan* P, int nrhs, const doub
     const int nr = min(nrhs - c0, per);
     dim3 gp((g.lmax + kSynChunk) / kSynChunk, g.mmax + 1, launch_groups(nr));
     hipLaunchKernelGGL(k_prep_synth, gp, dim3(64), 0, s, g.lmax, nr, P->t.mstart, P->t.mx_cstart,
-                       alm + (int64_t)c0 * g.nalm, (int64_t)g.nalm, f, ab, ab_group(g));
+                       alm + (int64_t)c0 * g.nalm, (int64_t)g.nalm, f, ab, ab_group(g), P->pred);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = synth_mfma_launch(P, nr, ab, eo + (int64_t)c0 * eo_stride, eo_stride, s);
@@ -774,7 +784,7 @@ hipError_t launch_legendre_synth_mixed_cg(const crsht_plan* P, int nrhs, const d
     dim3 gp((g.lmax + kSynChunk) / kSynChunk, g.mmax + 1, launch_groups(nr));
     hipLaunchKernelGGL(k_pupdate_prep, gp, dim3(64), 0, s, g.lmax, nr, g.nalm, P->t.mstart, P->t.mx_cstart,
                        P->w.bk, z + (int64_t)c0 * g.nalm, p + (int64_t)c0 * g.nalm,
-                       P->w.scal + (int64_t)c0 * kScalSlots, update ? 1 : 0, ab, ab_group(g));
+                       P->w.scal + (int64_t)c0 * kScalSlots, update ? 1 : 0, ab, ab_group(g), P->pred);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = synth_mfma_launch(P, nr, ab, eo + (int64_t)c0 * eo_stride, eo_stride, s);
@@ -796,7 +806,7 @@ hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const fl
     const int nr = min(nrhs - c0, per);
     dim3 gp((g.npairs + 15) / 16, (g.mmax + kPrepM) / kPrepM, launch_groups(nr));
     hipLaunchKernelGGL(k_prep_adj, gp, dim3(256), 0, s, g.mmax, g.npairs, nr, geo + (int64_t)c0 * geo_stride,
-                       geo_stride, ag, ag_group(g));
+                       geo_stride, ag, ag_group(g), P->pred);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     timing_begin(P, 4, s);
@@ -804,12 +814,12 @@ hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const fl
       hipLaunchKernelGGL(k_adj_mfma<2>, dim3(8u * (unsigned)P->t.mx_maxq), dim3(kAdjWaves * 64), 0, s, g.lmax,
                          g.mmax, g.npairs, nr, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
                          P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_order, P->t.mx_maxq, P->t.mx_ckpt,
-                         (const bf16x8*)ag, ag_group(g), raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm);
+                         (const bf16x8*)ag, ag_group(g), raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm, P->pred);
     else
       hipLaunchKernelGGL(k_adj_mfma<1>, dim3(8u * (unsigned)P->t.mx_maxq), dim3(kAdjWaves * 64), 0, s, g.lmax,
                          g.mmax, g.npairs, nr, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
                          P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_order, P->t.mx_maxq, P->t.mx_ckpt,
-                         (const bf16x8*)ag, ag_group(g), raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm);
+                         (const bf16x8*)ag, ag_group(g), raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm, P->pred);
     timing_end(P, 4, s);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

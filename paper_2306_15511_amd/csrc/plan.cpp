@@ -79,13 +79,32 @@ void free_plan_memory(crsht_plan* P) {
                   P->w.mx_ab, P->w.mx_ag,
                   P->t.idx_l, P->t.idx_m, P->w.eo, P->w.geo, P->w.alm_a, P->w.alm_b, P->w.cg_x, P->w.cg_r, P->t.idx_mv, P->w.bl_keep, P->w.sblk,
                   P->w.cg_z, P->w.cg_p, P->w.cg_q, P->w.cg_b, P->w.cg_d, P->w.alm_c, P->w.alm_d, P->w.map_a, P->w.ring_w,
-                  P->w.diag, P->w.sinv, P->w.sinvhalf, P->w.bk, P->w.perl, P->w.partial, P->w.scal};
+                  P->w.diag, P->w.sinv, P->w.sinvhalf, P->w.bk, P->w.perl, P->w.partial, P->w.scal, P->w.ctl,
+                  P->w.dstats};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (P->w.host_scal) (void)hipHostFree(P->w.host_scal);
+  if (P->w.host_exited) (void)hipHostFree(P->w.host_exited);
+  for (int k = 0; k < crsht_plan::kStageSlots; ++k) {
+    if (P->stage_host[k]) (void)hipHostFree(P->stage_host[k]);
+    if (P->stage_ev[k]) (void)hipEventDestroy(P->stage_ev[k]);
+    P->stage_host[k] = nullptr;
+    P->stage_ev[k] = nullptr;
+  }
+  for (auto& gx : P->dgraph) {
+    if (gx) (void)hipGraphExecDestroy(gx);
+    gx = nullptr;
+  }
   crsht::block_pc_free(P->pc);
   if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+  if (P->exec_stream) (void)hipStreamDestroy(P->exec_stream);
+  P->exec_stream = nullptr;
+  hipEvent_t* evs[] = {&P->ev_fork, &P->ev_join, &P->ev_round[0], &P->ev_round[1], &P->ev_round[2]};
+  for (hipEvent_t* e : evs) {
+    if (*e) (void)hipEventDestroy(*e);
+    *e = nullptr;
+  }
   P->graph_exec = nullptr;
   P->cap_stream = nullptr;
 }
@@ -357,9 +376,46 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int ncomp, i
     return CR_ENOMEM;
   }
   if (hipMemset(w.scal, 0, R * crsht::kScalSlots * sizeof(double)) != hipSuccess) return CR_EDEVICE;
+  if ((rc = dalloc(&w.ctl, (size_t)crsht::kCtlSlots, total))) return rc;
+  if (hipMemset(w.ctl, 0, crsht::kCtlSlots * sizeof(int)) != hipSuccess) return CR_EDEVICE;
+  // device-visible pinned word polled by the batched driver (coherent: the
+  // host reads it while kernels may still write it)
+  if (hipHostMalloc((void**)&w.host_exited, 64, hipHostMallocCoherent) != hipSuccess) {
+    w.host_exited = nullptr;
+    return CR_ENOMEM;
+  }
+  *w.host_exited = 1;
+  // pinned staging slots for the per-call host data: column amplitudes, the
+  // per-l arrays and (T+Q+U) the 3x3 spectra blocks
+  P->stage_bytes = 16 * (size_t)R + 12 * sizeof(double) * (size_t)(lmax + 1) + 1024;
+  for (int k = 0; k < crsht_plan::kStageSlots; ++k) {
+    if (hipHostMalloc(&P->stage_host[k], P->stage_bytes, hipHostMallocDefault) != hipSuccess) {
+      P->stage_host[k] = nullptr;
+      return CR_ENOMEM;
+    }
+    if (hipEventCreateWithFlags(&P->stage_ev[k], hipEventDisableTiming) != hipSuccess) {
+      P->stage_ev[k] = nullptr;
+      return CR_EDEVICE;
+    }
+  }
   if (hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     P->cap_stream = nullptr;
     return CR_EDEVICE;
+  }
+  if (hipStreamCreateWithFlags(&P->exec_stream, hipStreamNonBlocking) != hipSuccess) {
+    P->exec_stream = nullptr;
+    return CR_EDEVICE;
+  }
+  hipEvent_t* evs[] = {&P->ev_fork, &P->ev_join, &P->ev_round[0], &P->ev_round[1], &P->ev_round[2]};
+  for (hipEvent_t* e : evs)
+    if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
+      *e = nullptr;
+      return CR_EDEVICE;
+    }
+  {
+    unsigned char* ds = nullptr;
+    if ((rc = dalloc(&ds, R * sizeof(cr_stats), total))) return rc;
+    w.dstats = ds;
   }
   return CR_OK;
 }

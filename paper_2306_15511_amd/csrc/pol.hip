@@ -58,7 +58,8 @@ __device__ __forceinline__ void st2(float2* p, double2 v) { *p = make_float2((fl
 __global__ void k_pol_prep_synth(int64_t nalm, int nrhs, const int* __restrict__ idx_l,
                                  const int* __restrict__ idx_m, const double* __restrict__ kappa,
                                  const double* __restrict__ f, const double2* __restrict__ alm,
-                                 double2* __restrict__ out) {
+                                 double2* __restrict__ out, const int* __restrict__ pred) {
+  if (pred && *pred) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nalm) return;
   const int l = idx_l[i], m = idx_m[i];
@@ -87,7 +88,8 @@ __global__ void k_pol_prep_synth(int64_t nalm, int nrhs, const int* __restrict__
 // written over group columns 1 (Q) and 2 (U). eo: [groups][9][pairs][mmax+1][2].
 template <class V>
 __global__ void k_pol_combine_synth(int npairs, int mmax, int nrhs, const double* __restrict__ pair_z, V* eo,
-                                    int64_t col_stride) {
+                                    int64_t col_stride, const int* __restrict__ pred) {
+  if (pred && *pred) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)npairs * (mmax + 1)) return;
   const int p = (int)(t / (mmax + 1)), m = (int)(t % (mmax + 1));
@@ -131,7 +133,8 @@ __global__ void k_pol_combine_synth(int npairs, int mmax, int nrhs, const double
 // factor c swaps E and O). geo: [groups][7][pairs][mmax+1][2].
 template <class V>
 __global__ void k_pol_pre_adjoint(int npairs, int mmax, int nrhs, const double* __restrict__ pair_z, V* geo,
-                                  int64_t col_stride) {
+                                  int64_t col_stride, const int* __restrict__ pred) {
+  if (pred && *pred) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)npairs * (mmax + 1)) return;
   const int p = (int)(t / (mmax + 1));
@@ -156,7 +159,8 @@ __global__ void k_pol_pre_adjoint(int npairs, int mmax, int nrhs, const double* 
 __global__ void k_pol_combine_adjoint(int64_t nalm, int nrhs, const int* __restrict__ idx_l,
                                       const int* __restrict__ idx_m, const double* __restrict__ kappa,
                                       const double* __restrict__ f, const double2* __restrict__ raw,
-                                      double2* __restrict__ out) {
+                                      double2* __restrict__ out, const int* __restrict__ pred) {
+  if (pred && *pred) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nalm) return;
   const int l = idx_l[i], m = idx_m[i];
@@ -206,7 +210,8 @@ __device__ __forceinline__ void block3(const double* s, double2 t, double2 e, do
 __global__ void k_cg_q_tqu(int64_t nalm, const int* __restrict__ idx_l, const int* __restrict__ idx_m,
                            const double* __restrict__ sblk, const double2* __restrict__ camp,
                            const double2* __restrict__ p, const double2* __restrict__ dterm, double2* __restrict__ q,
-                           double* __restrict__ partial, int npart) {
+                           double* __restrict__ partial, int npart, const int* __restrict__ pred) {
+  if (pred && *pred) return;
   __shared__ double sh[kVecT];
   const int c = blockIdx.y;
   const double qa = camp[c].x;
@@ -327,7 +332,7 @@ int nblk(int64_t n) { return (int)((n + kVecT - 1) / kVecT); }
 hipError_t launch_pol_prep_synth(const crsht_plan* P, int nrhs, const double2* alm, const double* f, double2* out,
                                  hipStream_t s) {
   hipLaunchKernelGGL(k_pol_prep_synth, dim3(nblk(P->g.nalm)), dim3(kVecT), 0, s, P->g.nalm, nrhs, P->t.idx_l,
-                     P->t.idx_m, P->t.rec_kappa, f, alm, out);
+                     P->t.idx_m, P->t.rec_kappa, f, alm, out, P->pred);
   return hipGetLastError();
 }
 
@@ -337,10 +342,10 @@ hipError_t launch_pol_combine_synth(const crsht_plan* P, int nrhs, void* eo, boo
   const int64_t cs = n * 2;
   if (f32)
     hipLaunchKernelGGL(k_pol_combine_synth<float2>, dim3(nblk(n)), dim3(kVecT), 0, s, g.npairs, g.mmax, nrhs,
-                       P->t.pair_z, (float2*)eo, cs);
+                       P->t.pair_z, (float2*)eo, cs, P->pred);
   else
     hipLaunchKernelGGL(k_pol_combine_synth<double2>, dim3(nblk(n)), dim3(kVecT), 0, s, g.npairs, g.mmax, nrhs,
-                       P->t.pair_z, (double2*)eo, cs);
+                       P->t.pair_z, (double2*)eo, cs, P->pred);
   return hipGetLastError();
 }
 
@@ -350,17 +355,17 @@ hipError_t launch_pol_pre_adjoint(const crsht_plan* P, int nrhs, void* geo, bool
   const int64_t cs = n * 2;
   if (f32)
     hipLaunchKernelGGL(k_pol_pre_adjoint<float2>, dim3(nblk(n)), dim3(kVecT), 0, s, g.npairs, g.mmax, nrhs,
-                       P->t.pair_z, (float2*)geo, cs);
+                       P->t.pair_z, (float2*)geo, cs, P->pred);
   else
     hipLaunchKernelGGL(k_pol_pre_adjoint<double2>, dim3(nblk(n)), dim3(kVecT), 0, s, g.npairs, g.mmax, nrhs,
-                       P->t.pair_z, (double2*)geo, cs);
+                       P->t.pair_z, (double2*)geo, cs, P->pred);
   return hipGetLastError();
 }
 
 hipError_t launch_pol_combine_adjoint(const crsht_plan* P, int nrhs, const double2* raw, const double* f,
                                       double2* out, hipStream_t s) {
   hipLaunchKernelGGL(k_pol_combine_adjoint, dim3(nblk(P->g.nalm)), dim3(kVecT), 0, s, P->g.nalm, nrhs, P->t.idx_l,
-                     P->t.idx_m, P->t.rec_kappa, f, raw, out);
+                     P->t.idx_m, P->t.rec_kappa, f, raw, out, P->pred);
   return hipGetLastError();
 }
 
@@ -380,7 +385,7 @@ hipError_t launch_cg_q_tqu(const crsht_plan* P, int nrhs, const double2* p, cons
                            hipStream_t s, bool prior) {
   const int nb = vec_reduce_blocks(P);
   hipLaunchKernelGGL(k_cg_q_tqu, dim3(nb, nrhs), dim3(kVecT), 0, s, P->g.nalm, P->t.idx_l, P->t.idx_m,
-                     prior ? P->w.sblk : nullptr, P->w.camp, p, dterm, q, P->w.partial, P->w.npart);
+                     prior ? P->w.sblk : nullptr, P->w.camp, p, dterm, q, P->w.partial, P->w.npart, P->pred);
   return hipGetLastError();
 }
 

@@ -482,7 +482,9 @@ __global__ __launch_bounds__(NT) void k_ring(Tables T, int nside, int mmax, int 
                                               const V* __restrict__ chirp, const V* __restrict__ kern,
                                               const V* __restrict__ eo, int64_t eo_stride, double* __restrict__ map,
                                               int64_t map_stride, const double* __restrict__ ninv,
-                                              V* __restrict__ geo, int64_t geo_stride, RingCols rc) {
+                                              V* __restrict__ geo, int64_t geo_stride, RingCols rc,
+                                              const int* __restrict__ pred) {
+  if (pred && *pred) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   V* buf = reinterpret_cast<V*>(lds_raw);
   // spectrum scratch of small rings (blockDim x 8 reals) in the upper half
@@ -557,7 +559,7 @@ hipError_t ring_launch(const crsht_plan* P, int nrhs, const V* eo, double* map, 
   do {                                                                                                          \
     hipLaunchKernelGGL((k_ring<V, MODE, NT>), dim3(nb), dim3(nt), lds, s, P->t, g.nside, g.mmax, g.fft_max,      \
                        P->t.ring_pairs + rc.off, rc.count, nrhs, rc.L, tw, chirp, kern, eo, stride, map,         \
-                       (int64_t)g.npix, ninv, geo, stride, cols);                                               \
+                       (int64_t)g.npix, ninv, geo, stride, cols, P->pred);                                      \
   } while (0)
     if (nt <= 512)
       CRSHT_RING_LAUNCH(512);

@@ -27,7 +27,9 @@ __global__ void k_expand(int64_t nalm, const int* __restrict__ idx_l, const doub
 }
 
 // out = f * in per column (in and out may be the same array)
-__global__ void k_scale(int64_t nalm, int nrhs, const double2* in, const double* __restrict__ f, double2* out) {
+__global__ void k_scale(int64_t nalm, int nrhs, const double2* in, const double* __restrict__ f, double2* out,
+                        const int* __restrict__ pred) {
+  if (pred && *pred) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nalm) return;
   const double s = f[i];
@@ -114,7 +116,8 @@ __global__ void k_rhs_finish(int64_t nalm, int nrhs, const int* __restrict__ idx
 
 // out = x on kept modes (sinv > 0), 0 elsewhere, Im of m = 0 set to 0
 __global__ void k_project(int64_t nalm, int nrhs, const int* __restrict__ idx_m, const double* __restrict__ sinv,
-                          const double2* __restrict__ x, double2* __restrict__ out) {
+                          const double2* __restrict__ x, double2* __restrict__ out, const int* __restrict__ pred) {
+  if (pred && *pred) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nalm) return;
   const bool keep = sinv[i] > 0.0;
@@ -157,7 +160,8 @@ __global__ void k_cg_start(int64_t nalm, const int* __restrict__ idx_m, const do
                            const double* __restrict__ bk, const double2* __restrict__ b,
                            const double2* __restrict__ r, double2* __restrict__ z, double2* __restrict__ p,
                            double2* __restrict__ pt, double* __restrict__ partial, int npart,
-                           const double* __restrict__ scal, int zgiven) {
+                           const double* __restrict__ scal, int zgiven, const int* __restrict__ pred) {
+  if (pred && *pred) return;
   __shared__ double sh[kVecBlock];
   const int c = blockIdx.y;
   double rz = 0.0, rr = 0.0, bb = 0.0;
@@ -195,7 +199,8 @@ __global__ void k_cg_start(int64_t nalm, const int* __restrict__ idx_m, const do
 // sums partial[c][slot-row][0..nb) into scal; what = 0: start, 1: alpha, 2: beta,
 // 3: residual replacement
 __global__ void k_cg_scalars(int what, int nb, const double* __restrict__ partial, int npart,
-                             double* __restrict__ scal, double tol, int restart) {
+                             double* __restrict__ scal, double tol, int restart, const int* __restrict__ pred) {
+  if (pred && *pred) return;
   __shared__ double sh[kVecBlock];
   const int c = blockIdx.x;
   const double* pa = partial + (size_t)c * npart * 4;
@@ -262,7 +267,9 @@ __global__ void k_cg_scalars(int what, int nb, const double* __restrict__ partia
 __global__ void k_cg_update(int64_t nalm, const int* __restrict__ idx_m, const double* __restrict__ diag,
                             const double* __restrict__ bk, double2* __restrict__ x, double2* __restrict__ r,
                             double2* __restrict__ z, const double2* __restrict__ p, const double2* __restrict__ q,
-                            double* __restrict__ partial, int npart, const double* __restrict__ scal, int noz) {
+                            double* __restrict__ partial, int npart, const double* __restrict__ scal, int noz,
+                            const int* __restrict__ pred) {
+  if (pred && *pred) return;
   __shared__ double sh[kVecBlock];
   const int c = blockIdx.y;
   const double* sc = scal + c * kScalSlots;
@@ -302,7 +309,8 @@ __global__ void k_cg_update(int64_t nalm, const int* __restrict__ idx_m, const d
 // residual replacement: z = r / D; partial <r,z>, <r,r> (p untouched)
 __global__ void k_cg_replace(int64_t nalm, const int* __restrict__ idx_m, const double* __restrict__ diag,
                              const double2* __restrict__ r, double2* __restrict__ z, double* __restrict__ partial,
-                             int npart) {
+                             int npart, const int* __restrict__ pred) {
+  if (pred && *pred) return;
   __shared__ double sh[kVecBlock];
   const int c = blockIdx.y;
   double rz = 0.0, rr = 0.0;
@@ -327,7 +335,9 @@ __global__ void k_cg_replace(int64_t nalm, const int* __restrict__ idx_m, const 
 
 // p = z + beta p; pt = bk p
 __global__ void k_cg_pupdate(int64_t nalm, const double* __restrict__ bk, const double2* __restrict__ z,
-                             double2* __restrict__ p, double2* __restrict__ pt, const double* __restrict__ scal) {
+                             double2* __restrict__ p, double2* __restrict__ pt, const double* __restrict__ scal,
+                             const int* __restrict__ pred) {
+  if (pred && *pred) return;
   const int c = blockIdx.y;
   const double* sc = scal + c * kScalSlots;
   if (sc[S_DONE] != 0.0) return;
@@ -347,7 +357,8 @@ __global__ void k_cg_pupdate(int64_t nalm, const double* __restrict__ bk, const 
 __global__ void k_cg_q(int64_t nalm, const int* __restrict__ idx_m, const double* __restrict__ sinv,
                        const double2* __restrict__ camp, const double* __restrict__ bk,
                        const double2* __restrict__ p, const double2* __restrict__ raw, double2* __restrict__ q,
-                       double* __restrict__ partial, int npart) {
+                       double* __restrict__ partial, int npart, const int* __restrict__ pred) {
+  if (pred && *pred) return;
   __shared__ double sh[kVecBlock];
   const int c = blockIdx.y;
   const double qa = camp[c].x;
@@ -375,7 +386,8 @@ __global__ void k_diag(int64_t nalm, const double* __restrict__ sinv, const doub
 // r = b - Ax; partial <r,r> into row 1 (row 0: <r,r> as well)
 __global__ void k_residual(int64_t nalm, const int* __restrict__ idx_m, const double2* __restrict__ b,
                            const double2* __restrict__ ax, double2* __restrict__ r, double* __restrict__ partial,
-                           int npart) {
+                           int npart, const int* __restrict__ pred) {
+  if (pred && *pred) return;
   __shared__ double sh[kVecBlock];
   const int c = blockIdx.y;
   double rr = 0.0, bb = 0.0;
@@ -399,7 +411,9 @@ __global__ void k_residual(int64_t nalm, const int* __restrict__ idx_m, const do
 }
 
 // sum rows 0, 1, 2 of the partials of column c into scal[c][AUX0..AUX2]
-__global__ void k_sum_rows(int nb, const double* __restrict__ partial, int npart, double* __restrict__ scal) {
+__global__ void k_sum_rows(int nb, const double* __restrict__ partial, int npart, double* __restrict__ scal,
+                           const int* __restrict__ pred) {
+  if (pred && *pred) return;
   __shared__ double sh[kVecBlock];
   const int c = blockIdx.x;
   const double* pa = partial + (size_t)c * npart * 4;
@@ -550,7 +564,7 @@ hipError_t launch_expand(const crsht_plan* P, const double* perl, hipStream_t s)
 
 hipError_t launch_scale_alm(const crsht_plan* P, int nrhs, const double2* in, const double* f, double2* out,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_scale, dim3(nblocks(P->g.nalm)), dim3(kVecBlock), 0, s, P->g.nalm, nrhs, in, f, out);
+  hipLaunchKernelGGL(k_scale, dim3(nblocks(P->g.nalm)), dim3(kVecBlock), 0, s, P->g.nalm, nrhs, in, f, out, P->pred);
   return hipGetLastError();
 }
 
@@ -577,7 +591,7 @@ hipError_t launch_rhs_finish(const crsht_plan* P, int nrhs, const double2* raw, 
 
 hipError_t launch_project(const crsht_plan* P, int nrhs, const double2* x, double2* out, hipStream_t s) {
   hipLaunchKernelGGL(k_project, dim3(nblocks(vlen(P))), dim3(kVecBlock), 0, s, vlen(P), nrhs, P->t.idx_mv,
-                     P->w.sinv, x, out);
+                     P->w.sinv, x, out, P->pred);
   return hipGetLastError();
 }
 
@@ -597,14 +611,14 @@ hipError_t launch_cg_start(const crsht_plan* P, int nrhs, const double2* b, cons
                            double2* p, double2* pt, hipStream_t s, bool zgiven) {
   const int nb = vec_reduce_blocks(P);
   hipLaunchKernelGGL(k_cg_start, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, P->w.diag,
-                     P->w.bk, b, r, z, p, pt, P->w.partial, P->w.npart, P->w.scal, zgiven ? 1 : 0);
+                     P->w.bk, b, r, z, p, pt, P->w.partial, P->w.npart, P->w.scal, zgiven ? 1 : 0, P->pred);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_scalars(const crsht_plan* P, int nrhs, int what, int nb, double tol, int restart,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_cg_scalars, dim3(nrhs), dim3(kVecBlock), 0, s, what, nb, P->w.partial, P->w.npart,
-                     P->w.scal, tol, restart);
+                     P->w.scal, tol, restart, P->pred);
   return hipGetLastError();
 }
 
@@ -612,7 +626,7 @@ hipError_t launch_cg_q(const crsht_plan* P, int nrhs, const double2* p, const do
                        hipStream_t s, bool prior) {
   const int nb = vec_reduce_blocks(P);
   hipLaunchKernelGGL(k_cg_q, dim3(nb, nrhs), dim3(kVecBlock), 0, s, P->g.nalm, P->t.idx_m,
-                     prior ? P->w.sinv : nullptr, P->w.camp, P->w.bk, p, raw, q, P->w.partial, P->w.npart);
+                     prior ? P->w.sinv : nullptr, P->w.camp, P->w.bk, p, raw, q, P->w.partial, P->w.npart, P->pred);
   return hipGetLastError();
 }
 
@@ -626,14 +640,14 @@ hipError_t launch_cg_update(const crsht_plan* P, int nrhs, double2* x, double2* 
                             const double2* q, hipStream_t s, bool noz) {
   const int nb = vec_reduce_blocks(P);
   hipLaunchKernelGGL(k_cg_update, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, P->w.diag,
-                     P->w.bk, x, r, z, p, q, P->w.partial, P->w.npart, P->w.scal, noz ? 1 : 0);
+                     P->w.bk, x, r, z, p, q, P->w.partial, P->w.npart, P->w.scal, noz ? 1 : 0, P->pred);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_replace(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s) {
   const int nb = vec_reduce_blocks(P);
   hipLaunchKernelGGL(k_cg_replace, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, P->w.diag, r, z,
-                     P->w.partial, P->w.npart);
+                     P->w.partial, P->w.npart, P->pred);
   return hipGetLastError();
 }
 
@@ -641,7 +655,7 @@ hipError_t launch_cg_pupdate(const crsht_plan* P, int nrhs, const double2* z, do
                              hipStream_t s) {
   const int nb = vec_reduce_blocks(P);
   hipLaunchKernelGGL(k_cg_pupdate, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->w.bk, z, p, pt,
-                     P->w.scal);
+                     P->w.scal, P->pred);
   return hipGetLastError();
 }
 
@@ -649,12 +663,12 @@ hipError_t launch_residual(const crsht_plan* P, int nrhs, const double2* b, cons
                            hipStream_t s) {
   const int nb = vec_reduce_blocks(P);
   hipLaunchKernelGGL(k_residual, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, b, ax, r,
-                     P->w.partial, P->w.npart);
+                     P->w.partial, P->w.npart, P->pred);
   return hipGetLastError();
 }
 
 hipError_t launch_sum_rows(const crsht_plan* P, int nrhs, int nb, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_rows, dim3(nrhs), dim3(kVecBlock), 0, s, nb, P->w.partial, P->w.npart, P->w.scal);
+  hipLaunchKernelGGL(k_sum_rows, dim3(nrhs), dim3(kVecBlock), 0, s, nb, P->w.partial, P->w.npart, P->w.scal, P->pred);
   return hipGetLastError();
 }
 

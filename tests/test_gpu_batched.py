@@ -1,11 +1,14 @@
 """GPU checks of the batched driver cr_solve_batched: independent problems of
 different Nside, amplitude, white-noise level and band mask (the recipe of
 the 64-problem batched workload, at sizes the oracle solves quickly) against
-single solves (identical results) and the oracle."""
+single device-driven solves of the same problems (cr_solve_async: identical
+results and iteration counts), against cr_solve in mixed precision (the same
+refinement decisions, taken on the host there), and against the oracle."""
 import math
 
 import numpy as np
 import pytest
+import torch
 
 import crinputs as ci
 from oracle import cr, healpix
@@ -49,11 +52,16 @@ def test_batched_matches_single_and_oracle():
     out, st = m.solve_batched(plans, probs, D, W0, W1, tol=1e-10)
     for j, (wl, P, op, d, w0, w1) in enumerate(cases):
         assert st[j].status == 0 and st[j].rel_resid_true <= 1e-10, (j, st[j])
-        single, st1 = m.solve(plans[j], probs[j], D[j], W0[j], W1[j], tol=1e-10, check_every=16)
+        single, sd = m.solve_async(plans[j], probs[j], D[j], W0[j], W1[j], tol=1e-10, maxiter=20000,
+                                   check_every=16)
+        torch.cuda.synchronize()
+        st1 = m.decode_stats(sd, 1)
         assert np.array_equal(out[j].cpu().numpy(), single.cpu().numpy()[0]), j
         assert st1[0].iters == st[j].iters
         ref, _ = cr.pcg(op, op.rhs(d=d, w0=w0, w1=w1), 1e-12)
         assert real_rel(op, out[j].cpu().numpy(), ref) < 1e-7, j
+        b = op.rhs(d=d, w0=w0, w1=w1)
+        assert op.norm(b - op.apply(out[j].cpu().numpy())) / op.norm(b) <= 1.5e-10, j
 
 
 def test_batched_mixed_precision_and_missing_terms():
@@ -74,6 +82,12 @@ def test_batched_mixed_precision_and_missing_terms():
         print("problem %d nside %d: iters %d replacements %d oracle residual %.2e" % (
             j, ns[j], st[j].iters, st[j].refinements, res), flush=True)
         assert res <= 1.5e-6
+        # the host-driven mixed solve takes the same decisions from the same scalars
+        single, st1 = m.solve(plans[j], probs[j], D[j], None, None, tol=1e-6, prec=m.CR_MIXED, check_every=16)
+        e = real_rel(op, x, single.cpu().numpy()[0])
+        print("   vs cr_solve: iters %d / %d, rel diff %.2e" % (st[j].iters, st1[0].iters, e), flush=True)
+        assert st1[0].iters == st[j].iters and st1[0].refinements == st[j].refinements
+        assert e <= 1e-12
 
 
 def test_batched_rejects_shared_plan():
