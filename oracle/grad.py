@@ -120,3 +120,48 @@ def harmonic_lnpi_modes(C, b, nl, r, w0, w1):
     c2 = (w1.real ** 2 + w1.imag ** 2) * nl * b * b * C * C
     fl = b * b * (c0 + c1 + c2) / (nl * D * D)
     return -0.5 * (mean + fl)
+
+
+# ------------------------------------------------------------------- T+Q+U
+# The same derivative for a sky (a_T, a_E, a_B) with the 3x3 spectrum blocks
+# of Sect. 2.2.2 (oracle/cr_tqu.py), each block scaled as a whole per bin:
+# C_l(theta) = C_l^fid exp(theta_k) for l in bin k, so S^-1 and S^-1/2 of the
+# bin scale by exp(-theta_k) and exp(-theta_k / 2) and the three terms keep
+# their form with the blocks: dL/dtheta_k = 1/2 a^T S^-1_k a + 1/2 lambda^T
+# S^-1/2_k w0 - lambda^T S^-1_k f, lambda = A^-1 M f (one adjoint solve).
+def scaled_problem_tqu(fid, edges: np.ndarray, theta: np.ndarray):
+    from .cr_tqu import ProblemTQU
+    cl = np.array(fid.cl, dtype=np.float64, copy=True)
+    for k in range(edges.size - 1):
+        cl[:, edges[k]:edges[k + 1]] *= math.exp(theta[k])
+    return ProblemTQU(fid.nside, fid.lmax, cl, fid.bl, fid.ninv_t, fid.ninv_p, fid.lmin)
+
+
+def grad_lnpi_tqu(fid, d, w0, w1, edges: np.ndarray, theta=None, tol: float = 1e-12, maxiter: int = 20000):
+    """(dL/dtheta, L) at theta (default 0) for a T+Q+U problem (ProblemTQU);
+    d, w1 maps [3][npix], w0 [3][nalm]."""
+    from .cr_tqu import CROperatorTQU
+    from .joint import lnpi_tqu
+    theta = np.zeros(edges.size - 1) if theta is None else np.asarray(theta, dtype=np.float64)
+    op = CROperatorTQU(scaled_problem_tqu(fid, edges, theta))
+    ahat, _ = pcg(op, op.rhs(d=d), tol, maxiter)
+    fhat, _ = pcg(op, op.rhs(w0=w0, w1=w1), tol, maxiter)
+    lam, _ = pcg(op, op.apply_data_term(fhat), tol, maxiter)
+    w0p = op.project(w0)
+    masks = bin_masks(op.ls, edges)
+    g = np.empty(len(masks))
+    for k, mk in enumerate(masks):
+        t1 = op.dot(ahat, mk[None, :] * op._block(op.sinv_lm, ahat))
+        t2 = op.dot(lam, mk[None, :] * op._block(op.sinvh_lm, w0p))
+        t3 = op.dot(lam, mk[None, :] * op._block(op.sinv_lm, fhat))
+        g[k] = 0.5 * t1 + 0.5 * t2 - t3
+    return g, lnpi_tqu(op, d, ahat, fhat)
+
+
+def lnpi_at_tqu(fid, d, w0, w1, edges: np.ndarray, theta, tol: float = 1e-12, maxiter: int = 20000) -> float:
+    from .cr_tqu import CROperatorTQU
+    from .joint import lnpi_tqu
+    op = CROperatorTQU(scaled_problem_tqu(fid, edges, np.asarray(theta, dtype=np.float64)))
+    ahat, _ = pcg(op, op.rhs(d=d), tol, maxiter)
+    fhat, _ = pcg(op, op.rhs(w0=w0, w1=w1), tol, maxiter)
+    return lnpi_tqu(op, d, ahat, fhat)
