@@ -423,6 +423,11 @@ def solve_line(args, tqu: bool, R: int, steps: int, warmup: int, compare: bool, 
         w0[0::2] = 0.0
         w1[0::2] = 0.0
     prob = crsht.Problem(cl, bl, ninv, 2, amp)
+    tuning = None
+    if not args.no_tune:
+        # tile shapes for this plan, column count and precision (set-up, like the preconditioner)
+        tuning = crsht.autotune(plan, R, crsht.CR_MIXED if args.prec == "mixed" else crsht.CR_F64)
+        print("tile shapes: %s" % tuning, file=sys.stderr, flush=True)
     use_block = (args.precond or "block") == "block"
     ce = args.check_every or (6 if use_block else 16)
     pc = crsht.CR_PC_BLOCK if use_block else crsht.CR_PC_JACOBI
@@ -521,6 +526,8 @@ def solve_line(args, tqu: bool, R: int, steps: int, warmup: int, compare: bool, 
         res["config"]["chain_amplitudes"] = [float(v) for v in amp[::2]]
     if pc_setup_s is not None:
         res["precond_setup_s"] = pc_setup_s
+    if tuning is not None:
+        res["tile_shapes"] = tuning
     if kernels:
         res.update(kernel_roofline(args, plan, lambda: solve(R, prec, out), nside, lmax, R, nc, mixed, use_block, tqu))
     if compare:
@@ -625,6 +632,8 @@ def main():
     ap.add_argument("--no-f64-compare", action="store_true",
                     help="headline: skip the FP64 and single-column comparison forms")
     ap.add_argument("--no-tqu-line", action="store_true", help="headline: skip the T+Q+U line")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default tile shapes (no crsht_autotune before the timed steps)")
     ap.add_argument("--workload", choices=["headline", "tqu", "batched64", "chains", "probe-operator",
                                            "probe-precond", "copy"], default="headline")
     ap.add_argument("--chains", type=int, default=4, help="--workload chains: number of chains")

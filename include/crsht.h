@@ -548,6 +548,37 @@ int cr_grad_lnpi(const crsht_plan *plan, const cr_problem *prob, const double *d
                  const double *w1, int nbins, const int *edges, const cr_opts *opts, double *grad,
                  double *lnpi, cr_stats *stats, void *stream);
 
+/* Tile shapes chosen at run time by the library's autotuner. Each plan
+ * starts with the default shapes; crsht_autotune measures the candidates on
+ * the plan's own workspace for nrhs columns in precision prec and keeps the
+ * fastest (results do not depend on the shapes: the same arithmetic per
+ * element, in the same order). The choices:
+ *   ring_div[k]: the ring pass (azimuthal FFTs with N^-1 fused) of FFT-length
+ *     class k runs fft_len[k] / ring_div[k] threads per workgroup (8 or 4;
+ *     4 only for classes of length >= 1024),
+ *   f64_synth_cols, f64_adj_cols: complex columns per launch of the FP64
+ *     matrix-core Legendre synthesis and adjoint (2, 4 or 8).
+ * With the environment variable CRSHT_TUNE_CACHE naming a file, the choices
+ * are looked up there first, keyed by device architecture, nside, lmax,
+ * mmax, ncomp, nrhs and precision, and new measurements are appended.
+ * Captured iteration graphs of the plan are dropped when its shapes change.
+ * Synchronises the device. */
+typedef struct {
+  int nclasses;            /* ring FFT-length classes of the plan */
+  int fft_len[8];          /* their lengths */
+  int ring_div[8];         /* points per thread divisor per class (8 or 4) */
+  int f64_synth_cols;      /* 2, 4 or 8 */
+  int f64_adj_cols;        /* 2, 4 or 8 */
+  int from_cache;          /* crsht_autotune: 1 = read from CRSHT_TUNE_CACHE, 0 = measured */
+  double ms_default;       /* crsht_autotune (measured): the tuned kernels with the default shapes */
+  double ms_tuned;         /* ... with the chosen shapes */
+} crsht_tuning;
+int crsht_autotune(crsht_plan *plan, int nrhs, cr_prec prec, crsht_tuning *out, void *stream);
+/* the plan's current shapes */
+int crsht_get_tuning(const crsht_plan *plan, crsht_tuning *out);
+/* set shapes explicitly (validated as above; CR_EINVAL otherwise) */
+int crsht_set_tuning(crsht_plan *plan, const crsht_tuning *in);
+
 /* Per-kernel timing for measurement (not needed for computation).
  * crsht_timing_enable(plan, 1) synchronises the device, clears the counters
  * and makes the library bracket every launch of the tracked kernels with a

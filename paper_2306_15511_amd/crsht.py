@@ -53,6 +53,12 @@ class _Stats(ctypes.Structure):
                 ("rel_resid_true", ctypes.c_double)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("nclasses", ctypes.c_int), ("fft_len", ctypes.c_int * 8), ("ring_div", ctypes.c_int * 8),
+                ("f64_synth_cols", ctypes.c_int), ("f64_adj_cols", ctypes.c_int), ("from_cache", ctypes.c_int),
+                ("ms_default", ctypes.c_double), ("ms_tuned", ctypes.c_double)]
+
+
 class _Chain(ctypes.Structure):
     _fields_ = [("q", ctypes.c_double), ("lnpi", ctypes.c_double), ("ahat", ctypes.c_void_p),
                 ("fhat", ctypes.c_void_p)]
@@ -143,6 +149,9 @@ def _load():
         "cr_grad_lnpi": ([P, ctypes.POINTER(_Problem), vp, vp, vp, i, ctypes.POINTER(ctypes.c_int),
                           ctypes.POINTER(_Opts), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(_Stats), vp], i),
+        "crsht_autotune": ([P, i, i, ctypes.POINTER(_Tuning), vp], i),
+        "crsht_get_tuning": ([P, ctypes.POINTER(_Tuning)], i),
+        "crsht_set_tuning": ([P, ctypes.POINTER(_Tuning)], i),
         "crsht_timing_enable": ([P, i], i),
         "crsht_timing_read": ([P, i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], i),
     }
@@ -160,7 +169,8 @@ EXPORTED = ("crsht_plan_create", "crsht_plan_destroy", "crsht_strerror", "crsht_
             "cr_solve_async",
             "cr_white", "cr_lnpi", "joint_cl_step", "joint_cl_step_batch", "gibbs_cl_step", "gibbs_cl_step_batch", "gibbs_bins_step", "hmc_cl_step", "cr_lnpi_grad_fixed",
             "cr_solve_batched", "sht_synth_grad", "cr_grad_chi2", "cr_grad_lnpi",
-            "cr_block_precond_build", "cr_block_precond_apply", "crsht_timing_enable", "crsht_timing_read")
+            "cr_block_precond_build", "cr_block_precond_apply", "crsht_timing_enable", "crsht_timing_read",
+            "crsht_autotune", "crsht_get_tuning", "crsht_set_tuning")
 
 
 def lib():
@@ -258,6 +268,42 @@ def timing_read(plan: Plan, kernel: int):
     n = ctypes.c_int64()
     _check(_lib.crsht_timing_read(plan.handle, kernel, ctypes.byref(ms), ctypes.byref(n)), "crsht_timing_read")
     return ms.value, n.value
+
+
+# ---------------------------------------------------------------- tile shapes
+def _tuning_dict(t: _Tuning) -> dict:
+    n = t.nclasses
+    return {"fft_len": list(t.fft_len[:n]), "ring_div": list(t.ring_div[:n]), "f64_synth_cols": t.f64_synth_cols,
+            "f64_adj_cols": t.f64_adj_cols, "from_cache": bool(t.from_cache), "ms_default": t.ms_default,
+            "ms_tuned": t.ms_tuned}
+
+
+def autotune(plan: Plan, nrhs: int, prec: int = CR_F64) -> dict:
+    """crsht_autotune: measure (or read from CRSHT_TUNE_CACHE) and keep the
+    fastest tile shapes of the plan for nrhs columns in precision prec."""
+    t = _Tuning()
+    _check(_lib.crsht_autotune(plan.handle, nrhs, prec, ctypes.byref(t), _stream()), "crsht_autotune")
+    return _tuning_dict(t)
+
+
+def get_tuning(plan: Plan) -> dict:
+    t = _Tuning()
+    _check(_lib.crsht_get_tuning(plan.handle, ctypes.byref(t)), "crsht_get_tuning")
+    return _tuning_dict(t)
+
+
+def set_tuning(plan: Plan, ring_div=None, f64_synth_cols: int | None = None, f64_adj_cols: int | None = None):
+    """crsht_set_tuning: force shapes (unspecified fields keep their values)."""
+    t = _Tuning()
+    _check(_lib.crsht_get_tuning(plan.handle, ctypes.byref(t)), "crsht_get_tuning")
+    if ring_div is not None:
+        for k, v in enumerate(ring_div):
+            t.ring_div[k] = int(v)
+    if f64_synth_cols is not None:
+        t.f64_synth_cols = int(f64_synth_cols)
+    if f64_adj_cols is not None:
+        t.f64_adj_cols = int(f64_adj_cols)
+    _check(_lib.crsht_set_tuning(plan.handle, ctypes.byref(t)), "crsht_set_tuning")
 
 
 # ---------------------------------------------------------------- transforms

@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -1297,7 +1298,6 @@ extern "C" int cr_grad_lnpi(const crsht_plan* P, const cr_problem* prob, const d
                             double* lnpi, cr_stats* stats, void* stream) {
   CR_CHECK(check_plan(P, 1));
   if (prob && prob->amp) return CR_EINVAL;   // one spectrum per call
-  if (P->ncomp != 1) return CR_ENOTSUP;
   if (!prob || !d || !edges || !opts || !grad || !lnpi || !stats) return CR_EINVAL;
   if (nbins < 1 || nbins > P->g.lmax + 1) return CR_EINVAL;
   for (int k = 0; k <= nbins; ++k) {
@@ -1319,7 +1319,19 @@ extern "C" int cr_grad_lnpi(const crsht_plan* P, const cr_problem* prob, const d
                       reinterpret_cast<double*>(w.cg_xacc), opts, &stats[2], s));
   // per-bin terms (problem factors sinv, sinvhalf are those of prob)
   CR_TRY(hipMemcpyAsync(w.bin_edges, edges, (size_t)(nbins + 1) * sizeof(int), hipMemcpyHostToDevice, s));
-  CR_TRY(launch_bin_grad(P, nbins, w.bin_edges, w.alm_c, w.alm_d, w.cg_xacc, w0 ? C2(w0) : nullptr, w.bin_grad, s));
+  if (P->ncomp == 3) {
+    // the 3x3 blocks: S^-1 a (cg_r), S^-1/2 w0 (cg_z), S^-1 f (cg_p), then per-bin dots
+    const int64_t nv = vlen(P);
+    CR_TRY(hipMemsetAsync(w.alm_b, 0, (size_t)nv * sizeof(double2), s));
+    CR_TRY(launch_cg_q_tqu(P, 1, w.alm_c, w.alm_b, w.cg_r, s, true));
+    CR_TRY(launch_cg_q_tqu(P, 1, w.alm_d, w.alm_b, w.cg_p, s, true));
+    if (w0) CR_TRY(launch_rhs_finish_tqu(P, 1, nullptr, C2(w0), w.cg_z, s));
+    CR_TRY(launch_bin_grad_dots(P, nbins, w.bin_edges, w.alm_c, w.cg_r, w0 ? w.cg_xacc : nullptr,
+                                w0 ? w.cg_z : nullptr, w.cg_xacc, w.cg_p, w.bin_grad, s));
+  } else {
+    CR_TRY(launch_bin_grad(P, nbins, w.bin_edges, w.alm_c, w.alm_d, w.cg_xacc, w0 ? C2(w0) : nullptr, w.bin_grad,
+                           s));
+  }
   CR_TRY(hipMemcpyAsync(grad, w.bin_grad, (size_t)nbins * sizeof(double), hipMemcpyDeviceToHost, s));
   CR_TRY(hipStreamSynchronize(s));
   double t[3];
@@ -1727,5 +1739,232 @@ extern "C" int gibbs_cl_step_batch(const crsht_plan* P, const cr_problem* fid, c
     st[c].lnpi = -0.5 * (t[3 * c] + t[3 * c + 1] / qn[c] + t[3 * c + 2]);
   }
   CR_TRY(hipStreamSynchronize(s));
+  return CR_OK;
+}
+
+// ================================================================ autotuner
+namespace {
+
+void fill_tuning(const crsht_plan* P, crsht_tuning* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->nclasses = (int)std::min<size_t>(P->ring_cls.size(), kMaxRingClasses);
+  for (int k = 0; k < 8; ++k) {
+    o->fft_len[k] = k < o->nclasses ? P->ring_cls[k].L : 0;
+    o->ring_div[k] = k < o->nclasses ? (k < kMaxRingClasses ? P->tune.ring_div[k] : 8) : 0;
+  }
+  o->f64_synth_cols = P->tune.f64_synth_cols;
+  o->f64_adj_cols = P->tune.f64_adj_cols;
+}
+
+bool valid_cols(int c) { return c == 2 || c == 4 || c == 8; }
+
+int apply_tuning(crsht_plan* P, const crsht_tuning* in) {
+  if (!valid_cols(in->f64_synth_cols) || !valid_cols(in->f64_adj_cols)) return CR_EINVAL;
+  Tuning t;
+  const int nc = (int)std::min<size_t>(P->ring_cls.size(), kMaxRingClasses);
+  for (int k = 0; k < nc; ++k) {
+    const int d = in->ring_div[k];
+    if (d != 8 && d != 4) return CR_EINVAL;
+    if (d == 4 && P->ring_cls[k].L < 1024) return CR_EINVAL;
+    t.ring_div[k] = d;
+  }
+  t.f64_synth_cols = in->f64_synth_cols;
+  t.f64_adj_cols = in->f64_adj_cols;
+  // captured graphs hold the launch shapes: drop them (after any replays)
+  CR_TRY(hipDeviceSynchronize());
+  if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
+  P->graph_exec = nullptr;
+  P->graph_key = GraphKey();
+  for (auto& gx : P->dgraph) {
+    if (gx) (void)hipGraphExecDestroy(gx);
+    gx = nullptr;
+  }
+  P->dgraph_key = GraphKey();
+  P->tune = t;
+  return CR_OK;
+}
+
+// mean milliseconds of `reps` runs of f on s (after one untimed run)
+template <class F>
+int time_ms(hipStream_t s, int reps, F f, double* ms) {
+  hipEvent_t a = nullptr, b = nullptr;
+  CR_TRY(hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return CR_EDEVICE;
+  }
+  int rc = f();
+  if (rc == CR_OK && hipEventRecord(a, s) != hipSuccess) rc = CR_EDEVICE;
+  for (int r = 0; r < reps && rc == CR_OK; ++r) rc = f();
+  if (rc == CR_OK && hipEventRecord(b, s) != hipSuccess) rc = CR_EDEVICE;
+  float t = 0.f;
+  if (rc == CR_OK && (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&t, a, b) != hipSuccess))
+    rc = CR_EDEVICE;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *ms = (double)t / reps;
+  return rc;
+}
+
+std::string tune_key(const crsht_plan* P, int nrhs, cr_prec prec) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, P->device) == hipSuccess) arch = prop.gcnArchName;
+  for (char& c : arch)
+    if (c == ' ') c = '_';
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "crsht-tune-1 %s %d %d %d %d %d %d", arch.c_str(), P->g.nside, P->g.lmax,
+                P->g.mmax, P->ncomp, nrhs, (int)prec);
+  return buf;
+}
+
+bool cache_lookup(const char* path, const std::string& key, crsht_tuning* t) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[1024];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    const size_t kl = key.size();
+    if (std::strncmp(line, key.c_str(), kl) != 0 || line[kl] != ' ') continue;
+    crsht_tuning c = *t;
+    int* d = c.ring_div;
+    if (std::sscanf(line + kl, " %d %d %d %d %d %d %d %d %d %d", &d[0], &d[1], &d[2], &d[3], &d[4], &d[5], &d[6],
+                    &d[7], &c.f64_synth_cols, &c.f64_adj_cols) == 10) {
+      *t = c;   // the last matching line wins
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const char* path, const std::string& key, const crsht_tuning& t) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  const int* d = t.ring_div;
+  std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d\n", key.c_str(), d[0], d[1], d[2], d[3], d[4], d[5], d[6], d[7],
+               t.f64_synth_cols, t.f64_adj_cols);
+  std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" int crsht_get_tuning(const crsht_plan* P, crsht_tuning* out) {
+  if (!P || !out) return CR_EINVAL;
+  fill_tuning(P, out);
+  return CR_OK;
+}
+
+extern "C" int crsht_set_tuning(crsht_plan* P, const crsht_tuning* in) {
+  if (!P || !in) return CR_EINVAL;
+  return apply_tuning(P, in);
+}
+
+// Measures the candidate shapes on the plan's workspace: the fused ring pass
+// (N^-1 between the transforms, the form inside PCG) in the given precision,
+// one class at a time (coordinate search), and the FP64 matrix-core Legendre
+// synthesis and adjoint for every columns-per-launch choice.
+extern "C" int crsht_autotune(crsht_plan* P, int nrhs, cr_prec prec, crsht_tuning* out, void* stream) {
+  CR_CHECK(check_plan(P, nrhs));
+  if (!out) return CR_EINVAL;
+  if (prec != CR_F64 && prec != CR_MIXED) return CR_EINVAL;
+  if (P->timing.on) return CR_EINVAL;
+  hipStream_t s = S(stream);
+  const bool f32 = prec == CR_MIXED;
+  const std::string key = tune_key(P, nrhs, prec);
+  const char* path = std::getenv("CRSHT_TUNE_CACHE");
+  crsht_tuning t;
+  fill_tuning(P, &t);
+  if (path && *path && cache_lookup(path, key, &t)) {
+    CR_CHECK(apply_tuning(P, &t));
+    fill_tuning(P, out);
+    out->from_cache = 1;
+    return CR_OK;
+  }
+  // default shapes as the starting point; the inputs are the workspace's
+  // contents after zero fills (the timings do not depend on the values)
+  crsht_tuning cur;
+  fill_tuning(P, &cur);
+  for (int k = 0; k < cur.nclasses; ++k) cur.ring_div[k] = 8;
+  cur.f64_synth_cols = cur.f64_adj_cols = 8;
+  CR_CHECK(apply_tuning(P, &cur));
+  Workspace const& w = P->w;
+  const int ncomp = P->ncomp;
+  const int cs = ncomp == 3 ? 9 * nrhs : nrhs, ca = ncomp == 3 ? 7 * nrhs : nrhs;   // Legendre columns
+  const size_t eo_bytes = (size_t)cs * P->g.npairs * (P->g.mmax + 1) * 2 * sizeof(double2);
+  const size_t geo_bytes = (size_t)ca * P->g.npairs * (P->g.mmax + 1) * 2 * sizeof(double2);
+  CR_TRY(hipMemsetAsync(w.eo, 0, eo_bytes, s));
+  CR_TRY(hipMemsetAsync(w.geo, 0, geo_bytes, s));
+  CR_TRY(hipMemsetAsync(w.alm_a, 0, (size_t)cs * P->g.nalm * sizeof(double2), s));
+  CR_TRY(hipMemsetAsync(w.map_a, 0, (size_t)ncomp * P->g.npix * sizeof(double), s));
+  const double* ninv = w.map_a;
+  auto ring = [&]() -> int {
+    if (ncomp == 3)
+      CR_TRY(launch_ring(P, 3 * nrhs, RING_FUSED, w.eo, nullptr, ninv, w.geo, f32, s, tqu_cols(P)));
+    else
+      CR_TRY(launch_ring(P, nrhs, RING_FUSED, w.eo, nullptr, ninv, w.geo, f32, s));
+    return CR_OK;
+  };
+  auto syn = [&]() -> int {
+    CR_TRY(launch_legendre_synth(P, cs, w.alm_a, w.eo, s));
+    return CR_OK;
+  };
+  auto adj = [&]() -> int {
+    CR_TRY(launch_legendre_adjoint(P, ca, w.geo, w.alm_b, false, s));
+    return CR_OK;
+  };
+  const int reps = 3;
+  double t_ring = 0, t_syn = 0, t_adj = 0;
+  CR_CHECK(time_ms(s, reps, ring, &t_ring));
+  if (cs >= 2) CR_CHECK(time_ms(s, reps, syn, &t_syn));
+  if (ca >= 2) CR_CHECK(time_ms(s, reps, adj, &t_adj));
+  const double t_default = t_ring + t_syn + t_adj;
+  for (int k = 0; k < cur.nclasses; ++k) {
+    if (P->ring_cls[k].L < 1024) continue;
+    crsht_tuning c = cur;
+    c.ring_div[k] = 4;
+    CR_CHECK(apply_tuning(P, &c));
+    double tt = 0;
+    CR_CHECK(time_ms(s, reps, ring, &tt));
+    if (tt < 0.97 * t_ring) {
+      cur = c;
+      t_ring = tt;
+    }
+  }
+  const int cands[3] = {4, 2, 8};
+  if (cs >= 2) {
+    for (int v : cands) {
+      if (v == cur.f64_synth_cols || v > cs) continue;
+      crsht_tuning c = cur;
+      c.f64_synth_cols = v;
+      CR_CHECK(apply_tuning(P, &c));
+      double tt = 0;
+      CR_CHECK(time_ms(s, reps, syn, &tt));
+      if (tt < 0.97 * t_syn) {
+        cur = c;
+        t_syn = tt;
+      }
+    }
+  }
+  if (ca >= 2) {
+    for (int v : cands) {
+      if (v == cur.f64_adj_cols || v > ca) continue;
+      crsht_tuning c = cur;
+      c.f64_adj_cols = v;
+      CR_CHECK(apply_tuning(P, &c));
+      double tt = 0;
+      CR_CHECK(time_ms(s, reps, adj, &tt));
+      if (tt < 0.97 * t_adj) {
+        cur = c;
+        t_adj = tt;
+      }
+    }
+  }
+  CR_CHECK(apply_tuning(P, &cur));
+  if (path && *path) cache_store(path, key, cur);
+  fill_tuning(P, out);
+  out->from_cache = 0;
+  out->ms_default = t_default;
+  out->ms_tuned = t_ring + t_syn + t_adj;
   return CR_OK;
 }

@@ -78,6 +78,17 @@ struct RingClass {
   int L = 0, off = 0, count = 0;
 };
 
+// Run-time tile choices of a plan (crsht_autotune): threads per workgroup of
+// the ring pass per FFT-length class (L / ring_div[k], ring_div 8 or 4), and
+// complex columns per launch of the FP64 matrix-core Legendre kernels (2, 4
+// or 8). The defaults are the shapes the kernels were written around.
+constexpr int kMaxRingClasses = 8;
+struct Tuning {
+  int ring_div[kMaxRingClasses] = {8, 8, 8, 8, 8, 8, 8, 8};
+  int f64_synth_cols = 8;
+  int f64_adj_cols = 8;
+};
+
 // Workspace, allocated once at plan creation for nrhs_max columns.
 struct Workspace {
   double2* eo = nullptr;       // [nrhs][npairs][mmax+1][2]  (E, O) Legendre sums (float2 in the mixed path)
@@ -259,6 +270,7 @@ struct crsht_plan {
   crsht::Tables t;
   crsht::Workspace w;
   crsht::Timing timing;
+  crsht::Tuning tune;
   std::vector<crsht::RingClass> ring_cls;
   // host copies used for argument checks and bookkeeping
   std::vector<int> h_nphi;
@@ -330,6 +342,8 @@ hipError_t ring_prepare(const crsht_plan* P);
 // once per plan: LDS limit of the FP64 matrix-core adjoint
 hipError_t legendre_prepare(const crsht_plan* P);
 size_t ring_lds_bytes(const crsht_plan* P, bool f32);
+// threads per workgroup of ring class k under the plan's tuning
+int ring_class_threads(const crsht_plan* P, int k);
 
 // ---- spin-2 part of T+Q+U plans (pol.hip) ----
 // alm [nrhs][3][nalm] (times f per element, may be null) -> 9 scalar
@@ -428,6 +442,12 @@ hipError_t launch_mweight(const crsht_plan* P, int nrhs, double2* a, hipStream_t
 hipError_t launch_bin_grad(const crsht_plan* P, int nbins, const int* edges, const double2* ahat,
                            const double2* fhat, const double2* lam, const double2* w0, double* grad,
                            hipStream_t s, int mode = 0);
+// d ln pi / d theta_k = <x1,y1>_k/2 + <x2,y2>_k/2 - <x3,y3>_k per bin over all
+// components (T+Q+U: x1 = a, y1 = S^-1 a, x2 = lam, y2 = S^-1/2 w0, x3 = lam,
+// y3 = S^-1 f); x2 or y2 may be null
+hipError_t launch_bin_grad_dots(const crsht_plan* P, int nbins, const int* edges, const double2* x1,
+                                const double2* y1, const double2* x2, const double2* y2, const double2* x3,
+                                const double2* y3, double* grad, hipStream_t s);
 // partials of a^T S^-1 a with the 3x3 blocks of a T+Q+U plan (nb blocks)
 hipError_t launch_alm_wquad_tqu(const crsht_plan* P, const double2* a, double* partial, int nb, hipStream_t s);
 // Gaussian white draws (Philox4x32-10 + Box-Muller) of nrhs columns: w0

@@ -657,8 +657,9 @@ hipError_t launch_legendre_synth(const crsht_plan* P, int nrhs, const double2* a
     const Geometry& g = P->g;
     const int ngroups = (g.npairs + 63) / 64;
     const int nb = 8 * ngroups * ((g.mmax + 1 + 7) / 8);
-    for (int c0 = 0; c0 < nrhs; c0 += kAmCols) {
-      const int nc = std::min(kAmCols, nrhs - c0);
+    const int cpl = std::max(1, std::min(kAmCols, P->tune.f64_synth_cols));
+    for (int c0 = 0; c0 < nrhs; c0 += cpl) {
+      const int nc = std::min(cpl, nrhs - c0);
       timing_begin(P, 0, s);
       hipLaunchKernelGGL(k_legendre_synth_mfma, dim3(nb), dim3(64), 0, s, g.lmax, g.mmax, g.npairs, nc, ngroups,
                          P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
@@ -696,8 +697,9 @@ hipError_t launch_legendre_adjoint(const crsht_plan* P, int nrhs, const double2*
     const int64_t geo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
     const int nb = ((g.mmax + 1 + 31) / 32) * 32;
     const size_t lds = (size_t)kAmWaves * 64 * kAmRow * sizeof(double);
-    for (int c0 = 0; c0 < nrhs && err == hipSuccess; c0 += kAmCols) {
-      const int nc = std::min(kAmCols, nrhs - c0);
+    const int cpl = std::max(1, std::min(kAmCols, P->tune.f64_adj_cols));
+    for (int c0 = 0; c0 < nrhs && err == hipSuccess; c0 += cpl) {
+      const int nc = std::min(cpl, nrhs - c0);
       for (int p0 = 0; p0 < g.npairs && err == hipSuccess; p0 += kAmPairs) {
         hipLaunchKernelGGL(k_legendre_adj_mfma, dim3(nb), dim3(kAmWaves * 64), lds, s, g.lmax, g.mmax, g.npairs, p0,
                            p0 > 0 ? 1 : 0, nc, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,

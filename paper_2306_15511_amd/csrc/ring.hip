@@ -538,7 +538,12 @@ __global__ __launch_bounds__(NT) void k_ring(Tables T, int nside, int mmax, int 
   write_geo(geop, buf, q, mmax);
 }
 
-int ring_threads(int Lc) { return Lc / 8 < 64 ? 64 : Lc / 8; }
+// threads of a class of FFT length Lc with Lc / div points per thread
+// (the kernels need at least Lc / 8 threads)
+int ring_threads(int Lc, int div = 8) {
+  const int t = Lc / (div < 8 ? div : 8);
+  return t < 64 ? 64 : t > 1024 ? 1024 : t;
+}
 
 template <class V>
 size_t ring_lds(int Lc) {
@@ -550,9 +555,10 @@ hipError_t ring_launch(const crsht_plan* P, int nrhs, const V* eo, double* map, 
                        const V* tw, const V* chirp, const V* kern, RingCols cols, hipStream_t s) {
   const Geometry& g = P->g;
   const int64_t stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
-  for (const RingClass& rc : P->ring_cls) {
+  for (size_t k = 0; k < P->ring_cls.size(); ++k) {
+    const RingClass& rc = P->ring_cls[k];
     const size_t lds = ring_lds<V>(rc.L);
-    const int nt = ring_threads(rc.L);
+    const int nt = ring_class_threads(P, (int)k);
     const int64_t items = (int64_t)rc.count * nrhs;
     const unsigned nb = (unsigned)((items + 7) / 8 * 8);
 #define CRSHT_RING_LAUNCH(NT)                                                                                   \
@@ -587,14 +593,26 @@ hipError_t ring_allow_lds(const crsht_plan* P) {
   for (const RingClass& rc : P->ring_cls) {
     const size_t lds = ring_lds<V>(rc.L);
     if (lds <= 65536) continue;
-    const void* f = ring_threads(rc.L) <= 512 ? (const void*)k_ring<V, MODE, 512> : (const void*)k_ring<V, MODE, 1024>;
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+    // either instantiation may serve the class (tuned threads per workgroup)
+    for (const void* f : {(const void*)k_ring<V, MODE, 512>, (const void*)k_ring<V, MODE, 1024>}) {
+      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
 
 }  // namespace
+
+// Classes above 512 hold rings of exactly their FFT length L (n > L/4), so
+// with L/4 threads the spectrum still takes its one-thread-per-frequency path
+// (the small-ring path with scratch of blockDim x 8 reals needs blockDim <=
+// L/8): only those classes may take L/4 threads.
+int ring_class_threads(const crsht_plan* P, int k) {
+  const int L = P->ring_cls[k].L;
+  const int div = (k < kMaxRingClasses && L >= 1024 && P->tune.ring_div[k] == 4) ? 4 : 8;
+  return ring_threads(L, div);
+}
 
 hipError_t ring_prepare(const crsht_plan* P) {
   hipError_t e;
