@@ -542,8 +542,10 @@ int cr_grad_chi2(const crsht_plan *plan, const cr_problem *prob, int nrhs, const
  * adjoint). d: device map; w0: device alm [nalm] or NULL; w1: device map or
  * NULL; edges: host, nbins + 1 strictly increasing values in [0, lmax + 1];
  * grad: host [nbins]; *lnpi (host) receives L. Needs nrhs_max >= 1; uses the
- * plan workspace. Temperature plans only (CR_ENOTSUP for ncomp = 3). Blocks
- * until done. */
+ * plan workspace. T+Q+U plans (ncomp = 3): d, w1 hold [3][npix], w0 [3][nalm],
+ * and bin k scales the whole 3x3 block (TT, TE, EE, BB) of each l in the bin,
+ * so S^-1_k, S^-1/2_k are the blocks' inverse and inverse square root scaled
+ * alike. Blocks until done. */
 int cr_grad_lnpi(const crsht_plan *plan, const cr_problem *prob, const double *d, const double *w0,
                  const double *w1, int nbins, const int *edges, const cr_opts *opts, double *grad,
                  double *lnpi, cr_stats *stats, void *stream);

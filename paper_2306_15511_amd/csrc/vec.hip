@@ -530,6 +530,42 @@ __global__ void k_bin_terms(int mmax, const int64_t* __restrict__ mstart, const 
   }
 }
 
+// per-bin real-field dots of vectors of ncomp blocks of nalm coefficients
+// (T+Q+U gradient): t1 = <x1, y1>_k, t2 = <x2, y2>_k (x2 or y2 null: 0),
+// t3 = <x3, y3>_k over the coefficients of bin k of every block
+__global__ void k_bin_dots3(int mmax, int64_t nalm, int ncomp, const int64_t* __restrict__ mstart,
+                            const int* __restrict__ edges, const double2* __restrict__ x1,
+                            const double2* __restrict__ y1, const double2* __restrict__ x2,
+                            const double2* __restrict__ y2, const double2* __restrict__ x3,
+                            const double2* __restrict__ y3, double* __restrict__ partial) {
+  __shared__ double sh[kVecBlock];
+  const int k = blockIdx.x, sl = blockIdx.y, S = gridDim.y;
+  const int l0 = edges[k], l1 = edges[k + 1];
+  double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+  const int mtop = min(mmax, l1 - 1);
+  for (int m = sl; m <= mtop; m += S) {
+    const int lo = max(l0, m);
+    for (int c = 0; c < ncomp; ++c) {
+      const int64_t base = c * nalm + mstart[m] - m;
+      for (int l = lo + threadIdx.x; l < l1; l += blockDim.x) {
+        const int64_t i = base + l;
+        t1 += wdot(m, x1[i], y1[i]);
+        if (x2 && y2) t2 += wdot(m, x2[i], y2[i]);
+        t3 += wdot(m, x3[i], y3[i]);
+      }
+    }
+  }
+  t1 = block_sum(t1, sh);
+  t2 = block_sum(t2, sh);
+  t3 = block_sum(t3, sh);
+  if (threadIdx.x == 0) {
+    double* o = partial + ((size_t)k * S + sl) * 3;
+    o[0] = t1;
+    o[1] = t2;
+    o[2] = t3;
+  }
+}
+
 // d ln pi / d theta_k = t1/2 + t2/2 - t3 (mode 0: fixed w0, w1) or t1/2 - t3/2
 // (mode 1: fixed whitened fluctuation, lam = M f); mode 2: t1 alone (the
 // bin's a^T S^-1 a); slices summed in a fixed order
@@ -705,6 +741,17 @@ hipError_t launch_bin_grad(const crsht_plan* P, int nbins, const int* edges, con
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bin_grad, dim3((nbins + 63) / 64), dim3(64), 0, s, nbins, kBinSlices, P->w.bin_part, grad,
                      mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_grad_dots(const crsht_plan* P, int nbins, const int* edges, const double2* x1,
+                                const double2* y1, const double2* x2, const double2* y2, const double2* x3,
+                                const double2* y3, double* grad, hipStream_t s) {
+  hipLaunchKernelGGL(k_bin_dots3, dim3(nbins, kBinSlices), dim3(kVecBlock), 0, s, P->g.mmax, P->g.nalm, P->ncomp,
+                     P->t.mstart, edges, x1, y1, x2, y2, x3, y3, P->w.bin_part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bin_grad, dim3((nbins + 63) / 64), dim3(64), 0, s, nbins, kBinSlices, P->w.bin_part, grad, 0);
   return hipGetLastError();
 }
 
