@@ -278,8 +278,9 @@ def bench_chains(args):
         dt = time.perf_counter() - t0
         out[name] = dict(run.summary(), moves_per_s=args.chains * args.steps / dt, s=dt,
                          fluct_iters=float(run.fluct_iters.mean()))
-        print("%s: %.1f moves/s, acceptance %.3f, iat ln q %.2f" % (name, out[name]["moves_per_s"],
-              out[name]["acceptance"], out[name]["iat_lnq"]), file=sys.stderr, flush=True)
+        print("%s: %.1f moves/s, acceptance %.3f, iat ln q %.2f, correlation length %.1f"
+              % (name, out[name]["moves_per_s"], out[name]["acceptance"], out[name]["iat_lnq"],
+                 out[name]["corr_len_lnq"]), file=sys.stderr, flush=True)
     # HMC on theta = ln q (one bin over every kept l): step from the target's
     # curvature at the start (half its width), trajectories of three steps
     edges = [2, lmax + 1]
@@ -666,9 +667,6 @@ def main():
         bench_chains(args)
         return
     tqu = args.workload == "tqu"
-    if tqu and args.prec == "mixed" and args.nside >= 1024:
-        sys.exit("bench.py: the mixed T+Q+U solve does not converge to 1e-6 at Nside >= 1024 (polar Q/U "
-                 "cancellation amplifies the bf16x3 rounding by 1/sin^2 theta); run it with --prec f64")
     R = args.nrhs if args.nrhs else (2 if tqu else 16)
     res = solve_line(args, tqu, R, args.steps, args.warmup, compare=not args.no_f64_compare)
     if not tqu and not args.no_tqu_line:

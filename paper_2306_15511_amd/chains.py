@@ -54,6 +54,30 @@ def integrated_autocorr_time(x, c: float = 5.0) -> float:
     return max(tau, 1.0)
 
 
+def autocorrelation(x) -> np.ndarray:
+    """zeta(Delta) for Delta = 0 .. n-1 (Sect. 5, Markov chain correlation
+    length): the mean over the n - Delta available pairs (i, i + Delta) of the
+    product of the chain values standardised by the chain's own mean and
+    standard deviation."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.size
+    sd = x.std()
+    if n < 2 or sd == 0.0:
+        return np.ones(max(n, 1))
+    y = (x - x.mean()) / sd
+    f = np.fft.rfft(y, 2 * n)
+    sums = np.fft.irfft(f * np.conj(f), 2 * n)[:n]
+    return sums / np.arange(n, 0, -1)
+
+
+def correlation_length(x, threshold: float = 0.1) -> int:
+    """The paper's overall correlation length: the first lag Delta with
+    zeta(Delta) < threshold (0.1); the chain length if there is none."""
+    z = autocorrelation(x)
+    below = np.nonzero(z < threshold)[0]
+    return int(below[0]) if below.size else int(z.size)
+
+
 def scaled(fid: crsht.Problem, q: float) -> crsht.Problem:
     return crsht.Problem(np.asarray(fid.cl) * q, fid.bl, fid.ninv, fid.lmin)
 
@@ -77,10 +101,12 @@ class ChainRun:
     fluct_iters: np.ndarray  # [nchains, nsteps] iterations of the fluctuation solve (0 if rejected)
     acceptance: np.ndarray   # [nchains]
     iat: np.ndarray          # [nchains] integrated autocorrelation time of ln q (after burn-in)
+    corr_len: np.ndarray     # [nchains] first lag with zeta(lag) < 0.1 of ln q (after burn-in)
 
     def summary(self) -> dict:
         return {"kind": self.kind, "chains": int(self.q.shape[0]), "steps": int(self.q.shape[1] - 1),
                 "acceptance": float(self.acceptance.mean()), "iat_lnq": float(self.iat.mean()),
+                "corr_len_lnq": float(self.corr_len.mean()),
                 "mean_iters": float(self.mean_iters.mean()), "q_mean": float(self.q[:, 1:].mean())}
 
 
@@ -196,7 +222,8 @@ def run_chains(plan: crsht.Plan, fid: crsht.Problem, d: torch.Tensor, chains: li
             q[c, s + 1] = ch.q
     lnq = np.log(q[:, 1 + burn:])
     iat = np.array([integrated_autocorr_time(x) for x in lnq])
-    return ChainRun(kind, q, acc, mi, fi, acc.mean(axis=1), iat)
+    cl = np.array([correlation_length(x) for x in lnq])
+    return ChainRun(kind, q, acc, mi, fi, acc.mean(axis=1), iat, cl)
 
 
 def bin_scaled(fid: crsht.Problem, edges, theta) -> crsht.Problem:
@@ -245,11 +272,13 @@ class HmcRun:
     fluct_iters: np.ndarray  # [nchains, nsteps]
     acceptance: np.ndarray   # [nchains]
     iat: np.ndarray          # [nchains, nbins] integrated autocorrelation time of theta_k (after burn-in)
+    corr_len: np.ndarray     # [nchains, nbins] first lag with zeta(lag) < 0.1 of theta_k (after burn-in)
 
     def summary(self) -> dict:
         return {"kind": "hmc", "chains": int(self.theta.shape[0]), "steps": int(self.theta.shape[1] - 1),
                 "bins": int(self.theta.shape[2]), "acceptance": float(self.acceptance.mean()),
-                "iat_theta": float(self.iat.mean()), "mean_iters_per_solve":
+                "iat_theta": float(self.iat.mean()), "corr_len_theta": float(self.corr_len.mean()),
+                "mean_iters_per_solve":
                 float(self.iters.sum() / max(self.solves.sum(), 1)), "abs_dH": float(np.abs(self.dH).mean())}
 
 
@@ -294,8 +323,9 @@ def run_hmc(plan: crsht.Plan, fid: crsht.Problem, d: torch.Tensor, chains: list,
             fi[c, s] = res.fluct_stats.iters
             th[c, s + 1] = ch.theta
     iat = np.array([[integrated_autocorr_time(th[c, 1 + burn:, k]) for k in range(nb)] for c in range(n)])
-    return HmcRun(th, acc, dh, sv, it, fi, acc.mean(axis=1), iat)
+    cl = np.array([[correlation_length(th[c, 1 + burn:, k]) for k in range(nb)] for c in range(n)])
+    return HmcRun(th, acc, dh, sv, it, fi, acc.mean(axis=1), iat, cl)
 
 
-__all__ = ["white_alm", "integrated_autocorr_time", "scaled", "init_chain", "ChainRun", "default_draws",
-           "run_chains", "device_draws", "bin_scaled", "init_bin_chain", "curvature_scale", "HmcRun", "default_hmc_draws", "run_hmc"]
+__all__ = ["white_alm", "integrated_autocorr_time", "autocorrelation", "correlation_length", "scaled", "init_chain",
+           "ChainRun", "default_draws", "run_chains", "device_draws", "bin_scaled", "init_bin_chain", "curvature_scale", "HmcRun", "default_hmc_draws", "run_hmc"]

@@ -1,7 +1,12 @@
 """CPU pins of the chain driver's host-side pieces: the integrated
-autocorrelation time against the closed form of an AR(1) process, the white
-a_lm draw's layout and variances, and the per-bin spectrum scaling."""
+autocorrelation time and the correlation length (first lag with zeta < 0.1)
+against the closed forms of an AR(1) process, zeta against its definition
+summed pair by pair, the white a_lm draw's layout and variances, and the
+per-bin spectrum scaling."""
+import math
+
 import numpy as np
+from scipy.signal import lfilter
 
 from paper_2306_15511_amd import chains
 
@@ -44,3 +49,28 @@ def test_bin_scaled_spectrum():
     want[2:5] *= 2.0
     want[5:8] *= 0.5
     assert np.allclose(np.asarray(out.cl), want)
+
+
+def _ar1(rng, rho, n):
+    e = rng.standard_normal(n) * math.sqrt(1.0 - rho * rho)
+    return lfilter([1.0], [1.0, -rho], e)
+
+
+def test_autocorrelation_matches_pairwise_definition():
+    # zeta(D) = mean over i of (x_i - mu)(x_{i+D} - mu) / sigma^2, written out
+    x = _ar1(np.random.default_rng(7), 0.6, 300) + 3.0
+    mu, sd = x.mean(), x.std()
+    want = [np.mean([(x[i] - mu) * (x[i + d] - mu) for i in range(x.size - d)]) / sd ** 2 for d in range(x.size)]
+    assert np.allclose(chains.autocorrelation(x), want, rtol=0, atol=1e-12)
+
+
+def test_correlation_length_of_ar1():
+    # zeta(D) = rho^D: the first D with rho^D < 0.1 is 4 for rho = 0.5
+    # (0.125, 0.0625), 7 for rho = 0.7 (0.118, 0.082) and 11 for rho = 0.8
+    # (0.107, 0.086); the estimate's standard deviation at 1e6 samples is
+    # about 0.002 (Bartlett), well inside those gaps; white noise: 1
+    rng = np.random.default_rng(11)
+    for rho, want in ((0.5, 4), (0.7, 7), (0.8, 11)):
+        assert chains.correlation_length(_ar1(rng, rho, 1_000_000)) == want, rho
+    assert chains.correlation_length(rng.standard_normal(100_000)) == 1
+    assert chains.correlation_length(np.ones(10)) == 10
