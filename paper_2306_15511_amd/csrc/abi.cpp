@@ -35,8 +35,6 @@ namespace {
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-constexpr int kBatchWorkers = 16;   // host threads driving problems of one batched solve
-
 const double2* C2(const double* p) { return reinterpret_cast<const double2*>(p); }
 double2* C2(double* p) { return reinterpret_cast<double2*>(p); }
 // the Legendre-sum buffers hold float2 values in the mixed-precision path
@@ -186,27 +184,46 @@ RingCols tqu_cols(const crsht_plan* P) {
 }
 
 // Legendre sums and Q, U spectra of f * (a_T, a_E, a_B) (f per coefficient,
-// null = 1) into w.eo; scratch w.alm_a
+// null = 1) into w.eo; scratch w.alm_a (and w.pol in the mixed form, whose
+// polar ring pairs take FP64 sums and an FP64 combination)
 int tqu_spectra(const crsht_plan* P, int nrhs, const double2* alm, const double* f, hipStream_t s, bool mixed) {
   Workspace const& w = P->w;
   CR_TRY(launch_pol_prep_synth(P, nrhs, alm, f, w.alm_a, s));
-  if (mixed)
+  if (mixed) {
     CR_TRY(launch_legendre_synth_mixed(P, 9 * nrhs, w.alm_a, nullptr, F2(w.eo), s));
-  else
-    CR_TRY(launch_legendre_synth(P, 9 * nrhs, w.alm_a, w.eo, s));
-  CR_TRY(launch_pol_combine_synth(P, nrhs, w.eo, mixed, s));
+    CR_TRY(launch_pol_combine_synth(P, nrhs, w.eo, true, s));
+    if (P->npol > 0) {
+      const int64_t pst = (int64_t)P->npol * (P->g.mmax + 1) * 2;
+      CR_TRY(launch_legendre_synth_pairs(P, 9 * nrhs, w.alm_a, w.pol, pst, P->npol, s));
+      CR_TRY(launch_pol_combine_synth(P, nrhs, w.pol, false, s, P->npol));
+      CR_TRY(launch_polar_spectra_to_f32(P, nrhs, w.pol, F2(w.eo), s));
+    }
+    return CR_OK;
+  }
+  CR_TRY(launch_legendre_synth(P, 9 * nrhs, w.alm_a, w.eo, s));
+  CR_TRY(launch_pol_combine_synth(P, nrhs, w.eo, false, s));
   return CR_OK;
 }
 
 // f * (a_T, a_E, a_B) from the azimuthal adjoints in w.geo (T, Q, U in group
-// columns 0..2); scratch w.alm_b
+// columns 0..2); scratch w.alm_b (and w.pol in the mixed form: the polar ring
+// pairs' adjoints move to FP64 and take FP64 Legendre sums added to the
+// mixed sums of the other pairs)
 int tqu_from_geo(const crsht_plan* P, int nrhs, const double* f, double2* out, hipStream_t s, bool mixed) {
   Workspace const& w = P->w;
-  CR_TRY(launch_pol_pre_adjoint(P, nrhs, w.geo, mixed, s));
-  if (mixed)
+  if (mixed) {
+    if (P->npol > 0) CR_TRY(launch_polar_geo_to_f64(P, nrhs, F2(w.geo), w.pol, s));
+    CR_TRY(launch_pol_pre_adjoint(P, nrhs, w.geo, true, s));
     CR_TRY(launch_legendre_adjoint_mixed(P, 7 * nrhs, F2(w.geo), w.alm_b, s));
-  else
+    if (P->npol > 0) {
+      const int64_t pst = (int64_t)P->npol * (P->g.mmax + 1) * 2;
+      CR_TRY(launch_pol_pre_adjoint(P, nrhs, w.pol, false, s, P->npol));
+      CR_TRY(launch_legendre_adjoint_pairs(P, 7 * nrhs, w.pol, pst, P->npol, true, w.alm_b, s));
+    }
+  } else {
+    CR_TRY(launch_pol_pre_adjoint(P, nrhs, w.geo, false, s));
     CR_TRY(launch_legendre_adjoint(P, 7 * nrhs, w.geo, w.alm_b, false, s));
+  }
   CR_TRY(launch_pol_combine_adjoint(P, nrhs, w.alm_b, f, out, s));
   return CR_OK;
 }

@@ -123,11 +123,16 @@ struct Workspace {
   void* dstats = nullptr;      // [nrhs_max] cr_stats written by a device-driven solve (cr_solve_batched)
   void* mx_ab = nullptr;       // bf16 synthesis operand tiles (one group of kMixedCols columns)
   void* mx_ag = nullptr;       // bf16 adjoint operand tiles
+  double2* pol = nullptr;      // T+Q+U: [nrhs][9][npol][mmax+1][2] FP64 Legendre sums of the polar ring pairs
   int npart = 0;
 };
 
 constexpr int kScalSlots = 24;
 constexpr int kBinSlices = 16;   // m slices per multipole bin in the gradient reductions
+// T+Q+U mixed transforms: ring pairs with sin^2 theta below this take FP64
+// Legendre sums (their Q, U spectra divide cancelling sums by sin^2 theta,
+// which magnifies the split-bf16 rounding by up to 3 Nside^2)
+constexpr double kPolarSin2 = 0.01;
 constexpr int kMixedCols = 32;   // MFMA N: 16 right-hand sides (re, im) per column group
 constexpr int kMaxGroups = 2;    // column groups sharing one recurrence pass of an MFMA synthesis launch
 constexpr int kAdjGroups = 1;    // column groups per MFMA adjoint launch
@@ -264,6 +269,9 @@ struct crsht_plan {
   crsht::GraphKey graph_key;
   crsht::BlockPC pc;                    // per-m block preconditioner (built on request)
   int ncomp = 1;
+  // T+Q+U: ring pairs [0, npol) (sin^2 theta below kPolarSin2) take FP64
+  // Legendre sums in the mixed transforms
+  int npol = 0;
   int nrhs_max = 1;
   int device = 0;
   int64_t workspace_bytes_ = 0;
@@ -296,6 +304,13 @@ hipError_t launch_legendre_start(const crsht_plan* P, hipStream_t s);
 // whatever diagonal factor the caller folds in).
 hipError_t launch_legendre_synth(const crsht_plan* P, int nrhs, const double2* alms, double2* eo,
                                  hipStream_t s);
+// FP64 matrix-core sums over the ring pairs [0, plim) only (eo / geo hold plim
+// pairs per column, column stride in complex entries; nrhs columns of any
+// count); the adjoint adds to raw when accumulate.
+hipError_t launch_legendre_synth_pairs(const crsht_plan* P, int nrhs, const double2* alms, double2* eo,
+                                       int64_t eo_stride, int plim, hipStream_t s);
+hipError_t launch_legendre_adjoint_pairs(const crsht_plan* P, int nrhs, const double2* geo, int64_t geo_stride,
+                                         int plim, bool accumulate, double2* raw, hipStream_t s);
 // Adjoint: raw[c][idx(l,m)] = sum_p mu_lm(z_p) * (G_E or G_O by parity)[c][p][m]
 // (no kappa, no other factor). diag: raw[idx].x = sum_p mu_lm(z_p)^2 W_p with
 // W_p = w.ring_w[p] (the preconditioner pass; geo unused, one column).
@@ -351,9 +366,19 @@ int ring_class_threads(const crsht_plan* P, int k);
 hipError_t launch_pol_prep_synth(const crsht_plan* P, int nrhs, const double2* alm, const double* f, double2* out,
                                  hipStream_t s);
 // Legendre sums of the 9 columns -> Q, U spectra over group columns 1, 2
-hipError_t launch_pol_combine_synth(const crsht_plan* P, int nrhs, void* eo, bool f32, hipStream_t s);
+// (npairs < 0: all ring pairs; else a buffer of the first npairs pairs)
+hipError_t launch_pol_combine_synth(const crsht_plan* P, int nrhs, void* eo, bool f32, hipStream_t s,
+                                    int npairs = -1);
 // azimuthal adjoints of Q, U (group columns 1, 2 of 7) -> weighted copies in 3..6
-hipError_t launch_pol_pre_adjoint(const crsht_plan* P, int nrhs, void* geo, bool f32, hipStream_t s);
+hipError_t launch_pol_pre_adjoint(const crsht_plan* P, int nrhs, void* geo, bool f32, hipStream_t s,
+                                  int npairs = -1);
+// polar ring pairs [0, npol) of the mixed T+Q+U transforms (FP64 in w.pol):
+// T, Q, U spectra of the polar pairs -> float2 eo (group columns 0..2 of 9)
+hipError_t launch_polar_spectra_to_f32(const crsht_plan* P, int nrhs, const double2* pol64, float2* eo,
+                                       hipStream_t s);
+// float2 azimuthal adjoints T, Q, U of the polar pairs -> FP64 pol64 (group
+// columns 0..2 of 7), and those float2 entries set to 0
+hipError_t launch_polar_geo_to_f64(const crsht_plan* P, int nrhs, float2* geo, double2* pol64, hipStream_t s);
 // raw Legendre adjoints [nrhs][7][nalm] -> f * (a_T, a_E, a_B) [nrhs][3][nalm]
 hipError_t launch_pol_combine_adjoint(const crsht_plan* P, int nrhs, const double2* raw, const double* f,
                                       double2* out, hipStream_t s);

@@ -369,7 +369,7 @@ constexpr int kAmCols = 8;       // complex columns per launch (16 real MFMA col
 constexpr int kAmPairs = kAmWaves * 128;   // ring pairs one block covers
 
 __global__ __launch_bounds__(kAmWaves * 64) void k_legendre_adj_mfma(
-    int lmax, int mmax, int npairs, int p_off, int accumulate, int ncols, const double* __restrict__ pair_z,
+    int lmax, int mmax, int npairs, int plim, int p_off, int accumulate, int ncols, const double* __restrict__ pair_z,
     const double* __restrict__ alpha, const int* __restrict__ lst_g, const double2* __restrict__ lst_s,
     const int64_t* __restrict__ mstart, const double2* __restrict__ geo, int64_t geo_stride, double2* __restrict__ out,
     int64_t out_stride, const int* __restrict__ pred) {
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(kAmWaves * 64) void k_legendre_adj_mfma(
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int p = p_off + 128 * w + 64 * u + lane;
-    const bool ok = p < npairs;
+    const bool ok = p < plim;   // pairs below plim only (tables have npairs per m)
     const int pp = ok ? p : 0;
     const size_t o = (size_t)m * npairs + pp;
     z[u] = pair_z[pp];
@@ -400,6 +400,12 @@ __global__ __launch_bounds__(kAmWaves * 64) void k_legendre_adj_mfma(
     wmin = min(wmin, gs[u]);
   }
   wmin = wave_min(wmin);   // first live group of this wavefront
+  __shared__ int wmin_s[kAmWaves];
+  if (lane == 0) wmin_s[w] = wmin;
+  __syncthreads();
+  int bmin = kNever;   // first live group of the workgroup
+#pragma unroll
+  for (int ww = 0; ww < kAmWaves; ++ww) bmin = min(bmin, wmin_s[ww]);
   // B operands: G_par(p, j) for p = 128 w + 64 u + 4 s + (lane / 16), j = lane % 16
   const int kq = lane >> 4, jc = lane & 15, col = jc >> 1, ri = jc & 1;
   double b[2][16][2];
@@ -408,7 +414,7 @@ __global__ __launch_bounds__(kAmWaves * 64) void k_legendre_adj_mfma(
 #pragma unroll
     for (int sk = 0; sk < 16; ++sk) {
       const int p = p_off + 128 * w + 64 * u + 4 * sk + kq;
-      const bool ok = p < npairs && col < ncols;
+      const bool ok = p < plim && col < ncols;
       const double* g =
           reinterpret_cast<const double*>(geo + (ok ? col : 0) * geo_stride + ((size_t)(ok ? p : 0) * (mmax + 1) + m) * 2);
       b[u][sk][0] = ok ? g[ri] : 0.0;
@@ -418,6 +424,7 @@ __global__ __launch_bounds__(kAmWaves * 64) void k_legendre_adj_mfma(
 
 #pragma unroll 1
   for (int l0 = 0; l0 < nsteps; l0 += kAmChunk) {
+    if (accumulate && l0 / kGroup + 1 < bmin) continue;   // no live pair: the sums would add zeros
     f64x4_t acc[2][2];
 #pragma unroll
     for (int par = 0; par < 2; ++par) acc[par][0] = acc[par][1] = f64x4_t{0.0, 0.0, 0.0, 0.0};
@@ -496,7 +503,7 @@ __global__ __launch_bounds__(kAmWaves * 64) void k_legendre_adj_mfma(
 constexpr int kSmRow = 72;       // LDS row stride (doubles) of the mu tile
 
 __global__ __launch_bounds__(64) void k_legendre_synth_mfma(
-    int lmax, int mmax, int npairs, int ncols, int ngroups, const double* __restrict__ pair_z,
+    int lmax, int mmax, int npairs, int plim, int ncols, int ngroups, const double* __restrict__ pair_z,
     const double* __restrict__ alpha, const int* __restrict__ lst_g, const double2* __restrict__ lst_s,
     const int64_t* __restrict__ mstart, const double2* __restrict__ alms, int64_t alm_stride,
     double2* __restrict__ eo, int64_t eo_stride, const int* __restrict__ pred) {
@@ -507,7 +514,7 @@ __global__ __launch_bounds__(64) void k_legendre_synth_mfma(
   if (m > mmax) return;
   const int lane = threadIdx.x;
   const int p = 64 * g + lane;
-  const bool ok = p < npairs;
+  const bool ok = p < plim;   // pairs [0, plim) of the npairs (tables have npairs per m)
   const int pp = ok ? p : 0;
   const size_t o = (size_t)m * npairs + pp;
   const double z = pair_z[pp];
@@ -573,7 +580,7 @@ __global__ __launch_bounds__(64) void k_legendre_synth_mfma(
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int pr = 64 * g + 16 * t + 4 * r + kq;
-      if (pr < npairs) {
+      if (pr < plim) {
         double* dst = reinterpret_cast<double*>(eo + col * eo_stride + ((size_t)pr * (mmax + 1) + m) * 2) + ri;
         dst[0] = acc[t][0][r];
         dst[2] = acc[t][1][r];
@@ -661,7 +668,8 @@ hipError_t launch_legendre_synth(const crsht_plan* P, int nrhs, const double2* a
     for (int c0 = 0; c0 < nrhs; c0 += cpl) {
       const int nc = std::min(cpl, nrhs - c0);
       timing_begin(P, 0, s);
-      hipLaunchKernelGGL(k_legendre_synth_mfma, dim3(nb), dim3(64), 0, s, g.lmax, g.mmax, g.npairs, nc, ngroups,
+      hipLaunchKernelGGL(k_legendre_synth_mfma, dim3(nb), dim3(64), 0, s, g.lmax, g.mmax, g.npairs, g.npairs, nc,
+                         ngroups,
                          P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
                          alms + (int64_t)c0 * g.nalm, (int64_t)g.nalm, eo + (int64_t)c0 * eo_stride, eo_stride,
                          P->pred);
@@ -685,6 +693,45 @@ hipError_t launch_legendre_synth(const crsht_plan* P, int nrhs, const double2* a
   return hipSuccess;
 }
 
+// FP64 matrix-core Legendre sums of the ring pairs [0, plim) only, for the
+// polar rings of the T+Q+U mixed path: eo / geo hold plim pairs per column
+// (stride eo_stride / geo_stride complex entries); the adjoint adds its sums
+// to raw (accumulate) or writes them. nrhs >= 2.
+hipError_t launch_legendre_synth_pairs(const crsht_plan* P, int nrhs, const double2* alms, double2* eo,
+                                       int64_t eo_stride, int plim, hipStream_t s) {
+  const Geometry& g = P->g;
+  const int ngroups = (plim + 63) / 64;
+  const int nb = 8 * ngroups * ((g.mmax + 1 + 7) / 8);
+  for (int c0 = 0; c0 < nrhs; c0 += kAmCols) {
+    const int nc = std::min(kAmCols, nrhs - c0);
+    hipLaunchKernelGGL(k_legendre_synth_mfma, dim3(nb), dim3(64), 0, s, g.lmax, g.mmax, g.npairs, plim, nc, ngroups,
+                       P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, alms + (int64_t)c0 * g.nalm,
+                       (int64_t)g.nalm, eo + (int64_t)c0 * eo_stride, eo_stride, P->pred);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_legendre_adjoint_pairs(const crsht_plan* P, int nrhs, const double2* geo, int64_t geo_stride,
+                                         int plim, bool accumulate, double2* raw, hipStream_t s) {
+  const Geometry& g = P->g;
+  const int nb = ((g.mmax + 1 + 31) / 32) * 32;
+  const size_t lds = (size_t)kAmWaves * 64 * kAmRow * sizeof(double);
+  for (int c0 = 0; c0 < nrhs; c0 += kAmCols) {
+    const int nc = std::min(kAmCols, nrhs - c0);
+    for (int p0 = 0; p0 < plim; p0 += kAmPairs) {
+      hipLaunchKernelGGL(k_legendre_adj_mfma, dim3(nb), dim3(kAmWaves * 64), lds, s, g.lmax, g.mmax, g.npairs, plim,
+                         p0, (accumulate || p0 > 0) ? 1 : 0, nc, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s,
+                         P->t.mstart, geo + (int64_t)c0 * geo_stride, geo_stride, raw + (int64_t)c0 * g.nalm,
+                         (int64_t)g.nalm, P->pred);
+      const hipError_t err = hipGetLastError();
+      if (err != hipSuccess) return err;
+    }
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_legendre_adjoint(const crsht_plan* P, int nrhs, const double2* geo, double2* raw, bool diag,
                                    hipStream_t s) {
   timing_begin(P, 1, s);
@@ -701,8 +748,8 @@ hipError_t launch_legendre_adjoint(const crsht_plan* P, int nrhs, const double2*
     for (int c0 = 0; c0 < nrhs && err == hipSuccess; c0 += cpl) {
       const int nc = std::min(cpl, nrhs - c0);
       for (int p0 = 0; p0 < g.npairs && err == hipSuccess; p0 += kAmPairs) {
-        hipLaunchKernelGGL(k_legendre_adj_mfma, dim3(nb), dim3(kAmWaves * 64), lds, s, g.lmax, g.mmax, g.npairs, p0,
-                           p0 > 0 ? 1 : 0, nc, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
+        hipLaunchKernelGGL(k_legendre_adj_mfma, dim3(nb), dim3(kAmWaves * 64), lds, s, g.lmax, g.mmax, g.npairs,
+                           g.npairs, p0, p0 > 0 ? 1 : 0, nc, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
                            geo + (int64_t)c0 * geo_stride, geo_stride, raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm,
                            P->pred);
         err = hipGetLastError();

@@ -76,7 +76,7 @@ void free_plan_memory(crsht_plan* P) {
                   P->t.pair_fft_len, P->t.pair_bs_off, P->t.pair_bk_off, P->t.bs_chirp, P->t.bs_kern,
                   P->t.twiddle, P->t.bs_chirp32, P->t.bs_kern32, P->t.twiddle32, P->t.ring_pairs, P->t.rec_alpha, P->t.rec_kappa, P->t.lmm_v, P->t.lmm_k, P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.ones,
                   P->t.mx_cstart, P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_order, P->t.mx_ckpt, P->w.cg_xacc, P->w.cg_bin, P->w.bin_edges, P->w.bin_part, P->w.bin_grad, P->w.lfac, P->w.camp,
-                  P->w.mx_ab, P->w.mx_ag,
+                  P->w.mx_ab, P->w.mx_ag, P->w.pol,
                   P->t.idx_l, P->t.idx_m, P->w.eo, P->w.geo, P->w.alm_a, P->w.alm_b, P->w.cg_x, P->w.cg_r, P->t.idx_mv, P->w.bl_keep, P->w.sblk,
                   P->w.cg_z, P->w.cg_p, P->w.cg_q, P->w.cg_b, P->w.cg_d, P->w.alm_c, P->w.alm_d, P->w.map_a, P->w.ring_w,
                   P->w.diag, P->w.sinv, P->w.sinvhalf, P->w.bk, P->w.perl, P->w.partial, P->w.scal, P->w.ctl,
@@ -343,6 +343,14 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int ncomp, i
     if ((rc = dalloc(a, C * na, total))) return rc;
   if ((rc = dalloc(&w.cg_xacc, C * na, total))) return rc;
   if ((rc = dalloc(&w.cg_bin, C * na, total))) return rc;
+  if (ncomp == 3) {
+    // polar ring pairs (a prefix: pairs run from the north pole towards the
+    // equator), whose spin-2 spectra divide Legendre sums by sin^2 theta
+    int npol = 0;
+    while (npol < np && (1.0 - pz[npol]) * (1.0 + pz[npol]) < crsht::kPolarSin2) ++npol;
+    P->npol = npol;
+    if (npol > 0 && (rc = dalloc(&w.pol, R * ceo * (size_t)npol * (size_t)(mmax + 1) * 2, total))) return rc;
+  }
   {
     unsigned char *ab = nullptr, *ag = nullptr;
     if ((rc = dalloc(&ab, (size_t)crsht::mixed_ab_bytes(g), total))) return rc;

@@ -327,6 +327,45 @@ __global__ void k_expand_tqu(int64_t nalm, int lmax, const int* __restrict__ idx
 
 int nblk(int64_t n) { return (int)((n + kVecT - 1) / kVecT); }
 
+
+// ---- polar rings of the mixed path: ring pairs [0, npol), whose Q and U
+// divide cancelling Legendre sums by sin^2 theta, are summed in FP64 in
+// buffers of npol pairs per column (pol64: [nrhs][ncol][npol][mmax+1][2])
+// next to the float2 buffers of all pairs ([nrhs][ncol][npairs][mmax+1][2]).
+// T, Q, U spectra (group columns 0..2) of the polar pairs: FP64 -> float2
+__global__ void k_polar_spectra_to_f32(int npol, int mmax, int nrhs, const double2* __restrict__ pol64,
+                                       int64_t col64, float2* __restrict__ eo, int64_t col32,
+                                       const int* __restrict__ pred) {
+  if (pred && *pred) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (pair, m, E/O) entry of a column
+  const int64_t n = (int64_t)npol * (mmax + 1) * 2;
+  if (t >= n) return;
+  for (int c = 0; c < nrhs; ++c)
+    for (int k = 0; k < 3; ++k) {
+      const double2 v = pol64[((int64_t)c * 9 + k) * col64 + t];
+      eo[((int64_t)c * 9 + k) * col32 + t] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+// azimuthal adjoints T, Q, U (group columns 0..2) of the polar pairs:
+// float2 -> FP64, and those float2 entries set to 0 (the weighted copies that
+// the pre-adjoint step then derives from them are 0 as well)
+__global__ void k_polar_geo_to_f64(int npol, int mmax, int nrhs, float2* __restrict__ geo, int64_t col32,
+                                   double2* __restrict__ pol64, int64_t col64, const int* __restrict__ pred) {
+  if (pred && *pred) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)npol * (mmax + 1) * 2;
+  if (t >= n) return;
+  for (int c = 0; c < nrhs; ++c) {
+    for (int k = 0; k < 3; ++k) {
+      float2* gk = geo + ((int64_t)c * 7 + k) * col32 + t;
+      const float2 v = *gk;
+      pol64[((int64_t)c * 7 + k) * col64 + t] = make_double2((double)v.x, (double)v.y);
+      *gk = make_float2(0.f, 0.f);
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_pol_prep_synth(const crsht_plan* P, int nrhs, const double2* alm, const double* f, double2* out,
@@ -336,28 +375,32 @@ hipError_t launch_pol_prep_synth(const crsht_plan* P, int nrhs, const double2* a
   return hipGetLastError();
 }
 
-hipError_t launch_pol_combine_synth(const crsht_plan* P, int nrhs, void* eo, bool f32, hipStream_t s) {
+hipError_t launch_pol_combine_synth(const crsht_plan* P, int nrhs, void* eo, bool f32, hipStream_t s, int npairs) {
   const Geometry& g = P->g;
-  const int64_t n = (int64_t)g.npairs * (g.mmax + 1);
+  const int np = npairs < 0 ? g.npairs : npairs;
+  const int64_t n = (int64_t)np * (g.mmax + 1);
   const int64_t cs = n * 2;
+  if (n == 0) return hipSuccess;
   if (f32)
-    hipLaunchKernelGGL(k_pol_combine_synth<float2>, dim3(nblk(n)), dim3(kVecT), 0, s, g.npairs, g.mmax, nrhs,
+    hipLaunchKernelGGL(k_pol_combine_synth<float2>, dim3(nblk(n)), dim3(kVecT), 0, s, np, g.mmax, nrhs,
                        P->t.pair_z, (float2*)eo, cs, P->pred);
   else
-    hipLaunchKernelGGL(k_pol_combine_synth<double2>, dim3(nblk(n)), dim3(kVecT), 0, s, g.npairs, g.mmax, nrhs,
+    hipLaunchKernelGGL(k_pol_combine_synth<double2>, dim3(nblk(n)), dim3(kVecT), 0, s, np, g.mmax, nrhs,
                        P->t.pair_z, (double2*)eo, cs, P->pred);
   return hipGetLastError();
 }
 
-hipError_t launch_pol_pre_adjoint(const crsht_plan* P, int nrhs, void* geo, bool f32, hipStream_t s) {
+hipError_t launch_pol_pre_adjoint(const crsht_plan* P, int nrhs, void* geo, bool f32, hipStream_t s, int npairs) {
   const Geometry& g = P->g;
-  const int64_t n = (int64_t)g.npairs * (g.mmax + 1);
+  const int np = npairs < 0 ? g.npairs : npairs;
+  const int64_t n = (int64_t)np * (g.mmax + 1);
   const int64_t cs = n * 2;
+  if (n == 0) return hipSuccess;
   if (f32)
-    hipLaunchKernelGGL(k_pol_pre_adjoint<float2>, dim3(nblk(n)), dim3(kVecT), 0, s, g.npairs, g.mmax, nrhs,
+    hipLaunchKernelGGL(k_pol_pre_adjoint<float2>, dim3(nblk(n)), dim3(kVecT), 0, s, np, g.mmax, nrhs,
                        P->t.pair_z, (float2*)geo, cs, P->pred);
   else
-    hipLaunchKernelGGL(k_pol_pre_adjoint<double2>, dim3(nblk(n)), dim3(kVecT), 0, s, g.npairs, g.mmax, nrhs,
+    hipLaunchKernelGGL(k_pol_pre_adjoint<double2>, dim3(nblk(n)), dim3(kVecT), 0, s, np, g.mmax, nrhs,
                        P->t.pair_z, (double2*)geo, cs, P->pred);
   return hipGetLastError();
 }
@@ -403,4 +446,27 @@ hipError_t launch_diag_tqu(const crsht_plan* P, const double2* rawt, const doubl
   return hipGetLastError();
 }
 
+
+hipError_t launch_polar_spectra_to_f32(const crsht_plan* P, int nrhs, const double2* pol64, float2* eo,
+                                       hipStream_t s) {
+  const Geometry& g = P->g;
+  const int npol = P->npol;
+  const int64_t n = (int64_t)npol * (g.mmax + 1) * 2;
+  const int64_t col64 = n, col32 = (int64_t)g.npairs * (g.mmax + 1) * 2;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_polar_spectra_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, npol, g.mmax, nrhs,
+                     pol64, col64, eo, col32, P->pred);
+  return hipGetLastError();
+}
+
+hipError_t launch_polar_geo_to_f64(const crsht_plan* P, int nrhs, float2* geo, double2* pol64, hipStream_t s) {
+  const Geometry& g = P->g;
+  const int npol = P->npol;
+  const int64_t n = (int64_t)npol * (g.mmax + 1) * 2;
+  const int64_t col64 = n, col32 = (int64_t)g.npairs * (g.mmax + 1) * 2;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_polar_geo_to_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, npol, g.mmax, nrhs, geo,
+                     col32, pol64, col64, P->pred);
+  return hipGetLastError();
+}
 }  // namespace crsht

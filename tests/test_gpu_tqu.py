@@ -20,6 +20,10 @@ from tests.gpu_helpers import rel, tc
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
 MIXED_TOL = 1e-4
+# Q, U on rings with sin^2 theta < 0.01 in the mixed path: FP64 Legendre sums
+# and combination, then FP32 spectra and FP32 ring FFT (a few float roundings
+# of the ring's own scale)
+POLAR_TOL = 1e-5
 
 
 def _m():
@@ -148,8 +152,10 @@ def test_tqu_solve_oracle_residual(nside):
         assert abs(res - st[c].rel_resid_true) < 1e-10
 
 
-@pytest.mark.parametrize("nside", [8, 32])
+@pytest.mark.parametrize("nside", [8, 16, 32, 64])
 def test_tqu_mixed_transforms(nside):
+    # Nside 8: no ring pair with sin^2 theta < 0.01; 16, 32, 64: 1, 3, 7
+    # polar pairs take FP64 Legendre sums inside the mixed transforms
     m = _m()
     print("case tqu mixed transforms nside", nside, flush=True)
     wl, P, op = _problem(nside)
@@ -165,6 +171,15 @@ def test_tqu_mixed_transforms(nside):
     errs += [rel(ga[k], ra[k]) for k in range(3)]
     print("mixed rel errors (T, Q, U maps; T, E, B alm)", errs, flush=True)
     assert max(errs) < MIXED_TOL
+    # the polar rings (FP64 sums, FP32 ring FFT) on their own
+    R = op.sht.rings
+    for k in range(R.z.size):
+        if R.sin_theta[k] ** 2 >= 0.01:
+            continue
+        f, n = int(R.first[k]), int(R.nphi[k])
+        for c in (1, 2):
+            e = rel(got[c, f:f + n], ref[c, f:f + n])
+            assert e < POLAR_TOL, (k, c, e)
 
 
 def test_tqu_mixed_solve_oracle_residual():
@@ -265,12 +280,12 @@ def test_tqu_nside512_sampled_rings_and_adjointness():
     for k in rings:
         f, n = int(R.first[k]), int(R.nphi[k])
         # Q and U divide Legendre sums that cancel near the poles by
-        # sin^2 theta, which amplifies the mixed rounding on the polar rings:
-        # measured 1.7e-5 / sin theta on ring 0, 1.1e-5 / sin theta on rings
-        # 1, 2 and 9e-6 / sin theta on ring 37 (the cancelling sums shrink as
-        # sin theta); bound 3e-5 / sin theta, and 1e-4 away from the poles
+        # sin^2 theta, which amplifies split-bf16 rounding there (measured
+        # 1.7e-5 / sin theta on ring 0 and 9e-6 / sin theta on ring 37 with
+        # bf16x3 sums on every ring): rings with sin^2 < 0.01 take FP64 sums
+        # (POLAR_TOL), the others keep the 1e-4 bound
         s2 = 1.0 - R.z[k] ** 2
-        bound_m = max(MIXED_TOL, 3e-5 / np.sqrt(s2))
+        bound_m = POLAR_TOL if s2 < 0.01 else MIXED_TOL
         for q in range(2):
             e = rel(got[1 + q, f:f + n], ref[k][q])
             assert e < TOL, (k, q, e)
@@ -312,7 +327,7 @@ def test_tqu_nside1024_16_columns_sampled():
     # docstring): FP64 rounding u of the Legendre sums reaches Q, U amplified
     # by up to 1/sin^2 (1.6e6 on the first ring here), so their bound on a
     # ring is max(TOL, 8 u / sin^2); the mixed path is held to MIXED_TOL on
-    # rings with sin^2 > 0.01 (its polar-ring error is reported)
+    # rings with sin^2 > 0.01 and to POLAR_TOL on the others (FP64 sums)
     u = np.finfo(np.float64).eps / 2
     for prec in (m.CR_F64, m.CR_MIXED):
         got = m.synth(plan, da, prec=prec)
@@ -333,6 +348,8 @@ def test_tqu_nside1024_16_columns_sampled():
                         assert e < tol, (prec, c, k, comp, e, tol)
                     elif s2 > 1e-2:
                         assert e < MIXED_TOL, (prec, c, k, comp, e)
+                    else:
+                        assert e < POLAR_TOL, (prec, c, k, comp, e)
         print("prec", prec, "worst rel error per sampled ring", {k: "%.1e" % v for k, v in worst.items()}, flush=True)
     # adjointness and operator symmetry on two columns (FP64)
     x = da[:2].contiguous()
@@ -362,6 +379,66 @@ def test_tqu_nside1024_16_columns_sampled():
     print("block preconditioner symmetry", e1, e2, "positivity", ex, flush=True)
     assert abs(e1 - e2) <= 1e-5 * math.sqrt(abs(ex) * abs(float(torch.sum(mw * (u.real * pu.real + u.imag * pu.imag)))))
     assert ex > 0
+
+
+def test_tqu_nside1024_16_columns_mixed_solve():
+    # the largest T+Q+U workload end to end: Nside 1024, lmax 2047, 16 columns
+    # (8 chains x mean field and fluctuation), split-bf16 Legendre sums with
+    # FP64 polar rings inside FP64 residual replacement, block preconditioner,
+    # relative residual 1e-6. The residual of the returned solution is taken
+    # again with the FP64 operator and right-hand side entry points.
+    m = _m()
+    nside, lmax, R = 1024, 2047, 16
+    print("case tqu nside1024 x16 mixed solve", flush=True)
+    plan = m.Plan(nside, lmax, nrhs_max=R, ncomp=3)
+    wl = ci.workload_masked_t(nside, lmax, fwhm_arcmin=10.0, cfg=2)
+    z, phi = plan.pixel_coords()
+    nt = wl.ninv(z, phi)
+    sig = torch.from_numpy(wl.sigma_map(z, phi)).cuda()
+    cl = np.ascontiguousarray(ci.cl_tqu(lmax, wl.amp, 0.3))
+    bl = wl.bl()
+    gp = m.Problem(cl, bl, tc(np.stack([nt, nt / 2.0, nt / 2.0])), 2)
+    ls, _ = ci.alm_lm_arrays(lmax)
+    # columns 2k (mean field: data, no white terms) and 2k+1 (fluctuation:
+    # white terms only), 8 sky draws
+    A = np.zeros((R, 3, ls.size), dtype=np.complex128)
+    for c in range(0, R, 2):
+        A[c] = bl[ls] * ci.signal_alm_tqu(ci.rng_for(4, c, ci.STREAM_SIGNAL), cl, lmax)
+    d = m.synth(plan, tc(A))
+    del A
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1024)
+    qu = torch.tensor([1.0, 2 ** 0.5, 2 ** 0.5], dtype=torch.float64, device="cuda").view(3, 1)
+    for c in range(0, R, 2):
+        d[c] += qu * sig * torch.randn((3, sig.numel()), generator=g, dtype=torch.float64, device="cuda")
+    d[1::2] = 0.0
+    w0 = torch.zeros(plan.alm_shape(R), dtype=torch.complex128, device="cuda")
+    w1 = torch.zeros((R, 3, sig.numel()), dtype=torch.float64, device="cuda")
+    for c in range(1, R, 2):
+        for k in range(3):
+            w0[c, k] = tc(ci.white_alm(ci.rng_for(4, c, ci.STREAM_W0 + 10 * k), lmax))
+        w1[c] = torch.randn((3, sig.numel()), generator=g, dtype=torch.float64, device="cuda")
+    m.block_precond_build(plan, gp)
+    import time
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st = m.solve(plan, gp, d, w0, w1, nrhs=R, tol=1e-6, maxiter=3000, prec=m.CR_MIXED, inner_tol=1e-2,
+                    precond=m.CR_PC_BLOCK, check_every=6)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print("mixed solve %.2f s, iters %s, refinements %s, rel true residual max %.2e"
+          % (dt, [s.iters for s in st], [s.refinements for s in st], max(s.rel_resid_true for s in st)), flush=True)
+    assert all(s.status == 0 for s in st)
+    b = m.rhs(plan, gp, d, w0, w1, nrhs=R)
+    del d, w0, w1
+    r = b - m.apply(plan, gp, x)
+    _, ms = ci.alm_lm_arrays(lmax)
+    mw = torch.from_numpy(np.where(ms == 0, 1.0, 2.0)).cuda()
+    for c in range(R):
+        nr = float(torch.sum(mw * (r[c].real ** 2 + r[c].imag ** 2)).sqrt())
+        nb = float(torch.sum(mw * (b[c].real ** 2 + b[c].imag ** 2)).sqrt())
+        assert nr <= 1.05e-6 * nb, (c, nr / nb)
+        assert abs(nr / nb - st[c].rel_resid_true) <= 1e-8, (c, nr / nb, st[c].rel_resid_true)
 
 
 def test_tqu_column_amplitudes():
