@@ -85,6 +85,24 @@ __device__ __forceinline__ void split8(const float* x, int q, bf16x8& hi, bf16x8
   lo = __builtin_bit_cast(bf16x8, l4);
 }
 
+// bf16 hi / lo vectors of x[0..7], as split8
+__device__ __forceinline__ void split8c(const float* x, bf16x8& hi, bf16x8& lo) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 h4, l4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float a = x[2 * i], b = x[2 * i + 1];
+    const unsigned hp = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){a, b}, bf16x2));
+    const float ha = __uint_as_float(hp << 16), hb = __uint_as_float(hp & 0xffff0000u);
+    h4[i] = hp;
+    l4[i] = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){a - ha, b - hb}, bf16x2));
+  }
+  hi = __builtin_bit_cast(bf16x8, h4);
+  lo = __builtin_bit_cast(bf16x8, l4);
+}
+
 // v_permlane32_swap per dword: t0 = (lanes 0-31: k0 own, lanes 32-63: k1 of
 // lane - 32), t1 = (lanes 0-31: k0 of lane + 32, lanes 32-63: k1 own)
 // (lane layout checked on the device)
@@ -494,42 +512,55 @@ __global__ __launch_bounds__(256) void k_prep_adj(int mmax, int npairs, int nrhs
 // One block (4 wavefronts) per (m, tile of 64 steps). Wavefront w covers the
 // ring pairs [w * per, (w + 1) * per) in rounds of 64: lane p loads the
 // checkpointed recurrence state of its pair at the tile start, runs the 64
-// steps, and writes mu (bf16 hi, lo) into an LDS tile [step][pair]; then
+// steps and writes mu as FP32 into an LDS tile [q][step / 2][pair]; then
 // R_q[col][n] += sum over 4 blocks of 16 pairs of G_q^T (ag) x mu_q, for the
-// 32 even (q = 0) and 32 odd (q = 1) steps. The 4 partial results are summed
-// in LDS and written as raw FP64 sums out[rhs][idx(l, m)].
-constexpr int kRowB = 64 * 2;   // bytes per LDS row: 64 pairs of bf16
-// 16-byte chunk of 8 pairs, XOR-swizzled by the row so that the 32 rows read by
-// one B-fragment load fall on different LDS banks
-__device__ __forceinline__ int swz(int row, int chunk) { return ((chunk ^ (row & 7)) << 4); }
+// 32 even (q = 0) and 32 odd (q = 1) steps, with the bf16 hi / lo split of mu
+// taken when the operand is read (two values per conversion). The 4 partial
+// results are summed in LDS and written as raw FP64 sums out[rhs][idx(l, m)].
+// The tile's alpha are staged once per block in LDS and read as broadcasts.
+constexpr int kRowF = 64;   // floats per LDS row: 64 pairs
+// float offset of pair p in row n: 16-byte chunks XOR-swizzled by the row so
+// that the 8 rows read by one group of lanes of a B-fragment load fall on
+// different LDS banks
+__device__ __forceinline__ int swzf(int n, int p) { return ((((p >> 2) ^ (n & 7)) << 2) | (p & 3)); }
 
-// One tile of the recurrence for this lane's ring pair: mu (bf16 hi, lo) of
-// the 64 steps into the wavefront's LDS tile [q][h][step / 2][pair]. The
-// start state is injected by selects at the 16-step group boundaries; with
-// TAIL, steps at or past slim give mu = 0.
-template <bool TAIL>
-__device__ __forceinline__ void adj_tile_steps(unsigned char* my, int lane, int st0, int slim, int gs, double2 s0,
-                                               double z, double v0, double v1, int av_lo, int av_hi) {
-  const int cb0 = (lane & 7) * 2;
-  for (int g = 0; g < kAdjTile / kGroup; ++g) {
-    const bool inj = st0 / kGroup + g == gs;
-    v0 = inj ? s0.x : v0;
-    v1 = inj ? s0.y : v1;
+// One tile of the recurrence for this lane's ring pair: mu (FP32) of the 64
+// steps into the wavefront's LDS tile [q][step / 2][pair]. The start state is
+// injected by selects at the 16-step group boundaries. Past the last step of
+// m (alpha = 0 there) the values are finite and reach only output steps that
+// are not written. The alpha of the next 8 steps are read while 8 steps run.
+__device__ __forceinline__ void adj_tile_steps(float* my, const double2* al, int lane, int st0, int gs, double2 s0,
+                                               double z, double v0, double v1) {
+  constexpr int kB = 8;   // steps per alpha batch
+  int off[8];             // swizzled offset of this lane's pair in rows n with n % 8 = r
 #pragma unroll
-    for (int j = 0; j < kGroup; ++j) {
-      const int s = g * kGroup + j;
-      const double a = __hiloint2double(__builtin_amdgcn_readlane(av_hi, s), __builtin_amdgcn_readlane(av_lo, s));
-      double mu = fma(a * z, v1, -v0);
-      if (TAIL) mu = s < slim ? mu : 0.0;
+  for (int r = 0; r < 8; ++r) off[r] = swzf(r, lane);
+  double2 ac[kB / 2], an[kB / 2];
+#pragma unroll
+  for (int i = 0; i < kB / 2; ++i) ac[i] = al[i];
+#pragma unroll
+  for (int b = 0; b < kAdjTile / kB; ++b) {
+    if (b + 1 < kAdjTile / kB) {
+#pragma unroll
+      for (int i = 0; i < kB / 2; ++i) an[i] = al[(b + 1) * (kB / 2) + i];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if ((b * kB) % kGroup == 0) {
+      const bool inj = (st0 + b * kB) / kGroup == gs;
+      v0 = inj ? s0.x : v0;
+      v1 = inj ? s0.y : v1;
+    }
+#pragma unroll
+    for (int j = 0; j < kB; ++j) {
+      const double a = (j & 1) ? ac[j >> 1].y : ac[j >> 1].x;
+      const double mu = fma(a * z, v1, -v0);
       v0 = v1;
       v1 = mu;
-      __bf16 h, l;
-      split_bf16(to_f32(mu), h, l);
-      const int q = j & 1, n = s >> 1;
-      const int cb = swz(n, lane >> 3) + cb0;
-      *reinterpret_cast<__bf16*>(my + ((q * 2 + 0) * 32 + n) * kRowB + cb) = h;
-      *reinterpret_cast<__bf16*>(my + ((q * 2 + 1) * 32 + n) * kRowB + cb) = l;
+      const int s = b * kB + j, q = s & 1, n = s >> 1;   // row n of parity q
+      my[(q * 32 + n) * kRowF + off[n & 7]] = to_f32(mu);
     }
+#pragma unroll
+    for (int i = 0; i < kB / 2; ++i) ac[i] = an[i];
   }
 }
 
@@ -545,8 +576,9 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
                                                   double2* __restrict__ out, int64_t out_stride,
                                                   const int* __restrict__ pred) {
   if (pred && *pred) return;
-  // per wavefront: [q][h][32 steps][kRowB bytes]; reused for the partial results
-  __shared__ __attribute__((aligned(16))) unsigned char lds[kAdjWaves][2][2][32][kRowB];
+  // per wavefront: FP32 [q][32 steps][kRowF pairs]; reused for the partial results
+  __shared__ __attribute__((aligned(16))) float lds[kAdjWaves][2][32][kRowF];
+  __shared__ double2 al[kAdjTile / 2];   // alpha of the tile's steps (0 past the last step)
   const int tid = order[(blockIdx.x & 7) * maxq + (blockIdx.x >> 3)];   // tiles of one m stay on one XCD
   if (tid < 0) return;
   const int m = tile_m[tid];
@@ -555,13 +587,17 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
   const int64_t base = mstart[m];
   const int nsteps = lmax - m + 1;
   const int st0 = T * kAdjTile;
+  const int slim = min(kAdjTile, nsteps - st0);
+  if (threadIdx.x < kAdjTile)
+    reinterpret_cast<double*>(al)[threadIdx.x] = (int)threadIdx.x < slim ? alpha[base + st0 + threadIdx.x] : 0.0;
+  __syncthreads();
   const int nkb = (npairs + 15) / 16;
   const int per = ((npairs + kAdjWaves * 64 - 1) / (kAdjWaves * 64)) * 64;   // pairs per wavefront
   f32x16 dE[NG], dO[NG];
 #pragma unroll
   for (int g = 0; g < NG; ++g) dE[g] = dO[g] = f32x16{};
   const int row = lane & 31, kg = lane >> 5;
-  unsigned char* my = &lds[w][0][0][0][0];
+  float* my = &lds[w][0][0][0];
 
   // per-pair data of a round (start group, z, start state, checkpoint)
   struct PairData {
@@ -599,19 +635,10 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
 #pragma unroll
         for (int u = 0; u < 4; ++u) aq[kb][u] = a[u * 64 + lane];
       }
+      __builtin_amdgcn_sched_barrier(0);   // keep the operand loads ahead of the recurrence
       const double z = cur.z;
       const double2 s0 = cur.s0;
-      double v0 = cur.ck.x, v1 = cur.ck.y;
-      // alpha of the tile: lane s holds alpha of step s (one coalesced load),
-      // broadcast per step by readlane (no scalar loads, which would wait on
-      // the LDS counter behind the tile writes)
-      const int slim = min(kAdjTile, nsteps - st0);
-      const double av = lane < slim ? alpha[base + st0 + lane] : 0.0;
-      const int av_lo = __double2loint(av), av_hi = __double2hiint(av);
-      if (slim == kAdjTile)
-        adj_tile_steps<false>(my, lane, st0, slim, gs, s0, z, v0, v1, av_lo, av_hi);
-      else
-        adj_tile_steps<true>(my, lane, st0, slim, gs, s0, z, v0, v1, av_lo, av_hi);
+      adj_tile_steps(my, al, lane, st0, gs, s0, z, cur.ck.x, cur.ck.y);
       // the tile is private to this wavefront and LDS accesses of one
       // wavefront complete in order: a compiler barrier suffices
       __builtin_amdgcn_wave_barrier();
@@ -628,16 +655,21 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
             for (int u = 0; u < 4; ++u) aq[kb][u] = a[u * 64 + lane];
           }
         }
+        // blocks of 16 pairs past the last pair: their mu are 0 (no start
+        // state, zero checkpoint), so the clamped operands add nothing
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
-          const int gkb = r0 / 16 + kb;
-          if (gkb >= nkb) break;
           // B[k][n] = mu(pair 16 kb + k, step pair n): lane n + 32 (k/8) reads 8 pairs of row n
-          const int off = swz(row, 2 * kb + kg);
-          const bf16x8 bEh = *reinterpret_cast<const bf16x8*>(my + ((0 * 2 + 0) * 32 + row) * kRowB + off);
-          const bf16x8 bEl = *reinterpret_cast<const bf16x8*>(my + ((0 * 2 + 1) * 32 + row) * kRowB + off);
-          const bf16x8 bOh = *reinterpret_cast<const bf16x8*>(my + ((1 * 2 + 0) * 32 + row) * kRowB + off);
-          const bf16x8 bOl = *reinterpret_cast<const bf16x8*>(my + ((1 * 2 + 1) * 32 + row) * kRowB + off);
+          const int p0 = 16 * kb + 8 * kg;
+          float xe[8], xo[8];
+          *reinterpret_cast<float4*>(xe) = *reinterpret_cast<const float4*>(my + row * kRowF + swzf(row, p0));
+          *reinterpret_cast<float4*>(xe + 4) = *reinterpret_cast<const float4*>(my + row * kRowF + swzf(row, p0 + 4));
+          *reinterpret_cast<float4*>(xo) = *reinterpret_cast<const float4*>(my + (32 + row) * kRowF + swzf(row, p0));
+          *reinterpret_cast<float4*>(xo + 4) =
+              *reinterpret_cast<const float4*>(my + (32 + row) * kRowF + swzf(row, p0 + 4));
+          bf16x8 bEh, bEl, bOh, bOl;
+          split8c(xe, bEh, bEl);
+          split8c(xo, bOh, bOl);
           dE[g] = mfma3(aq[kb][0], aq[kb][1], bEh, bEl, dE[g]);
           dO[g] = mfma3(aq[kb][2], aq[kb][3], bOh, bOl, dO[g]);
         }
@@ -645,11 +677,17 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
       __builtin_amdgcn_wave_barrier();
     }
     cur = nxt;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      // the accumulators stay in AGPRs across rounds (no copies around the recurrence)
+      asm volatile("" : "+a"(dE[g]));
+      asm volatile("" : "+a"(dO[g]));
+    }
   }
   // one block-wide barrier, reached once by every wavefront; each wavefront
   // reuses its own tile area for its partial result red[w][q][r][lane]
   // (NG x 8 KiB of the wavefront's 16 KiB tile area)
-  float* redw = reinterpret_cast<float*>(my);
+  float* redw = my;
 #pragma unroll
   for (int g = 0; g < NG; ++g)
 #pragma unroll
@@ -664,7 +702,7 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
     float acc = 0.f;
 #pragma unroll
     for (int ww = 0; ww < kAdjWaves; ++ww)
-      acc += reinterpret_cast<const float*>(&lds[ww][0][0][0][0])[((2 * g + q) * 16 + r) * 64 + ln];
+      acc += (&lds[ww][0][0][0])[((2 * g + q) * 16 + r) * 64 + ln];
     const int c = 8 * (r / 4) + 4 * (ln >> 5) + (r % 4);
     const int n = ln & 31;
     const int rhs = 16 * g + (c >> 1), comp = c & 1;
