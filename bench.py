@@ -53,12 +53,12 @@ HBM_PEAK_GBS = 8000.0
 # 16-column temperature workload and while the kernel's source file hashes to
 # `src`.
 TRAFFIC = {
-    "k_adj_mfma": {"bytes": 959896629, "src": "3c89991f0fac5560"},
-    "k_synth_mfma": {"bytes": 1324395064, "src": "3c89991f0fac5560"},
-    "k_ring<RING_FUSED>": {"bytes": 4 * 212896371, "src": "664ab76c607be629"},   # one fused pass (4 class launches)
-    "k_legendre_synth_mfma": {"bytes": 680437984, "src": "34e5a8a115b9d7fc"},    # one launch of 8 columns
-    "k_legendre_adj_mfma": {"bytes": 2 * 606571360, "src": "34e5a8a115b9d7fc"},  # one transform (2 launches)
-    "k_pc_apply": {"bytes": 3086747669, "src": "b178efe54277f7b9"},
+    "k_adj_mfma": {"bytes": 959810560, "src": "446b7d20a3644d9d"},
+    "k_synth_mfma": {"bytes": 696782848, "src": "446b7d20a3644d9d"},
+    "k_ring<float2, RING_FUSED>": {"bytes": 851464192, "src": "1095a43175397d24"},   # one pass (4 class launches)
+    "k_legendre_synth_mfma": {"bytes": 680593408, "src": "74e6c305f36a5103"},    # one launch of 8 columns
+    "k_legendre_adj_mfma": {"bytes": 2 * 606706688, "src": "74e6c305f36a5103"},  # one transform (2 launches)
+    "k_pc_apply": {"bytes": 3080813568, "src": "93eb7917d57ed236"},
 }
 
 
@@ -551,19 +551,23 @@ def kernel_roofline(args, plan, one_solve, nside, lmax, R, nc, mixed, use_block,
     from paper_2306_15511_amd import crsht
     crsht.timing_enable(plan, True)
     _, st = one_solve()
-    tm = {k: crsht.timing_read(plan, k) for k in range(6)}
+    tm = {k: crsht.timing_read(plan, k) for k in range(7)}
     crsht.timing_enable(plan, False)
     print("kernel-timing step: iters %s" % [x.iters for x in st], file=sys.stderr, flush=True)
     # algorithmic work per timed unit (one launch; an FP64 adjoint unit is a whole transform)
     T = legendre_triples(nside, lmax, lmax)
-    # Legendre sums of one column (E and O, complex; float2 in the mixed path)
-    eo_bytes = 2 * nside * (lmax + 1) * 2 * (8 if mixed else 16)
+    # Legendre sums of one column (E and O, complex): float2 in the mixed
+    # operator's ring pass, double2 in the FP64 one (the FP64 operator, and the
+    # true residuals of the mixed path)
+    eo32 = 2 * nside * (lmax + 1) * 2 * 8
     # scalar Legendre columns per transform: a T+Q+U column is 9 in the
     # synthesis and 7 in the adjoint; the ring pass sees nc maps per column
     cs, ca = (9 * R, 7 * R) if tqu else (R, R)
     kinfo = {
-        2: ("k_ring<RING_FUSED> (azimuthal FFT pass, N^-1 fused)", "hbm",
-            nc * R * 2 * eo_bytes + nc * plan.npix * 8, HBM_PEAK_GBS, "GB/s", "ring.hip"),
+        2: ("k_ring<float2, RING_FUSED> (azimuthal FFT pass, N^-1 fused, FP32)", "hbm",
+            nc * R * 2 * eo32 + nc * plan.npix * 8, HBM_PEAK_GBS, "GB/s", "ring.hip"),
+        6: ("k_ring<double2, RING_FUSED> (azimuthal FFT pass, N^-1 fused, FP64)", "hbm",
+            nc * R * 2 * 2 * eo32 + nc * plan.npix * 8, HBM_PEAK_GBS, "GB/s", "ring.hip"),
     }
     if mixed:
         # average work per launch: columns go in launches of at most 16
@@ -600,7 +604,7 @@ def kernel_roofline(args, plan, one_solve, nside, lmax, R, nc, mixed, use_block,
             continue
         avg = ms / nl * 1e-3
         achieved = work / avg / (1e9 if unit == "GB/s" else 1e12)
-        tr = TRAFFIC.get(name.split(" ")[0]) if (not tqu and R == 16) else None
+        tr = TRAFFIC.get(name.split(" (")[0]) if (not tqu and R == 16 and nside == 512) else None
         traffic = None
         if tr is not None and tr["src"] == src_hash(src):
             traffic = tr["bytes"]

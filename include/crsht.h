@@ -586,9 +586,11 @@ int crsht_set_tuning(crsht_plan *plan, const crsht_tuning *in);
  * and makes the library bracket every launch of the tracked kernels with a
  * pair of HIP events on the launch stream; 0 turns it off. Tracked kernels:
  * 0 = FP64 Legendre synthesis, 1 = FP64 Legendre adjoint (incl. the
- * preconditioner diagonal pass), 2 = ring (azimuthal FFT) pass,
- * 3 = bf16x3 MFMA Legendre synthesis, 4 = bf16x3 MFMA Legendre adjoint,
- * 5 = block preconditioner application.
+ * preconditioner diagonal pass), 2 = fused ring pass (azimuthal FFTs with
+ * N^-1, FP32: the mixed operator), 3 = bf16x3 MFMA Legendre synthesis,
+ * 4 = bf16x3 MFMA Legendre adjoint, 5 = block preconditioner application,
+ * 6 = fused ring pass in FP64 (the FP64 operator). Ring passes of a lone
+ * synthesis or adjoint are not tracked.
  * crsht_timing_read waits for the recorded events and returns the summed
  * duration (milliseconds) and the number of launches since enabling. */
 int crsht_timing_enable(const crsht_plan *plan, int on);

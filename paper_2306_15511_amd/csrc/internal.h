@@ -188,10 +188,10 @@ struct DctlArgs {
   int f64;           // stats report no replacements (plain FP64 form)
 };
 
-// 0 FP64 Legendre synthesis, 1 FP64 Legendre adjoint, 2 ring pass,
-// 3 MFMA (bf16x3) Legendre synthesis, 4 MFMA Legendre adjoint,
-// 5 block preconditioner application
-constexpr int kTimedKernels = 6;
+// 0 FP64 Legendre synthesis, 1 FP64 Legendre adjoint, 2 fused ring pass
+// (FP32, mixed path), 3 MFMA (bf16x3) Legendre synthesis, 4 MFMA Legendre
+// adjoint, 5 block preconditioner application, 6 fused ring pass (FP64)
+constexpr int kTimedKernels = 7;
 struct Timing {
   bool on = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events[kTimedKernels];

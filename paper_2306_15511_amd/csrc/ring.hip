@@ -132,26 +132,41 @@ __device__ __forceinline__ void dft_reg(V (&v)[R], bool inv) {
   for (int i = 0; i < R; ++i) v[i] = t[i];
 }
 
-// one in-place Stockham pass of radix R over N points with stride Ns
-// (Govindaraju et al. 2008 formulation). tw: exp(-2 pi i q / fmax), q < fmax.
-// Blocks have at least N/8 threads, so a thread handles at most J = 8/R
-// butterflies; all inputs are read into registers before the barrier that
-// precedes the writes, which makes the pass in place. The twiddles w^r of a
-// butterfly come from one table load w and products (at most six roundings).
+// one in-place Stockham pass of radix R over N = 2^lN points with stride
+// Ns = 2^lNs (Govindaraju et al. 2008 formulation). tw: exp(-2 pi i q / fmax),
+// q < fmax = 2^lf. Blocks have at least N/8 threads, so a thread handles at
+// most J = 8/R butterflies; all inputs are read into registers before the
+// barrier that precedes the writes, which makes the pass in place. The
+// twiddles w^r of a butterfly come from one table load w and products (at
+// most six roundings). All lengths are powers of two, so the index
+// arithmetic is shifts and masks, and the padded LDS offsets of a
+// butterfly's R points are one padded base plus multiples of a padded
+// stride (exact when the stride is 1 or a multiple of 16).
 template <int R, class V>
-__device__ __forceinline__ void stockham_pass(V* x, int N, int Ns, const V* __restrict__ tw, int fmax, bool inv) {
+__device__ __forceinline__ void stockham_pass(V* x, int lN, int lNs, const V* __restrict__ tw, int lf, bool inv) {
   constexpr int J = R >= 8 ? 1 : 8 / R;
-  const int nt = N / R;
+  constexpr int lR = R == 16 ? 4 : R == 8 ? 3 : R == 4 ? 2 : 1;
+  const int nt = 1 << (lN - lR);
+  const int Ns = 1 << lNs;
+  const bool in_strided = nt >= 16;                  // pad(j + r nt) = pad(j) + r (nt + nt / 16)
+  const int in_stride = nt + (nt >> 4);
+  const int out_stride = Ns == 1 ? 1 : Ns + (Ns >> 4);   // Ns = 1 or a multiple of 16
   V v[J][R];
 #pragma unroll
   for (int u = 0; u < J; ++u) {
     const int j = threadIdx.x + u * blockDim.x;
     if (j < nt) {
+      if (in_strided) {
+        const int pj = pad(j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[u][r] = x[pad(j + r * nt)];
-      if (Ns > 1) {
-        const int k = j % Ns;
-        V w1 = tw[k * (fmax / (Ns * R))];
+        for (int r = 0; r < R; ++r) v[u][r] = x[pj + r * in_stride];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[u][r] = x[pad(j + r * nt)];
+      }
+      if (lNs > 0) {
+        const int k = j & (Ns - 1);
+        V w1 = tw[k << (lf - lNs - lR)];
         if (inv) w1.y = -w1.y;
         const V w2 = cmul(w1, w1);
         const V w3 = cmul(w2, w1);
@@ -173,29 +188,31 @@ __device__ __forceinline__ void stockham_pass(V* x, int N, int Ns, const V* __re
   for (int u = 0; u < J; ++u) {
     const int j = threadIdx.x + u * blockDim.x;
     if (j < nt) {
-      const int k = j % Ns;
-      const int base = (j / Ns) * Ns * R + k;
+      const int k = j & (Ns - 1);
+      const int pb = pad(((j >> lNs) << (lNs + lR)) + k);
 #pragma unroll
-      for (int r = 0; r < R; ++r) x[pad(base + r * Ns)] = v[u][r];
+      for (int r = 0; r < R; ++r) x[pb + r * out_stride] = v[u][r];
     }
   }
   lds_barrier();
 }
 
-// length-N (power of two, N <= 8 blockDim) DFT in place, natural order
+// length-N (power of two, N <= 8 blockDim) DFT in place, natural order;
+// fmax = 2^lf entries in the twiddle table
 template <class V>
-__device__ __forceinline__ void fft_pow2(V* x, int N, const V* __restrict__ tw, int fmax, bool inv) {
+__device__ __forceinline__ void fft_pow2(V* x, int N, const V* __restrict__ tw, int lf, bool inv) {
   lds_barrier();
-  int b = ilog2(N);
-  int Ns = 1;
+  const int lN = ilog2(N);
+  int b = lN;
+  int lNs = 0;
   while (b >= 4) {
-    stockham_pass<16>(x, N, Ns, tw, fmax, inv);
-    Ns *= 16;
+    stockham_pass<16>(x, lN, lNs, tw, lf, inv);
+    lNs += 4;
     b -= 4;
   }
-  if (b == 3) stockham_pass<8>(x, N, Ns, tw, fmax, inv);
-  else if (b == 2) stockham_pass<4>(x, N, Ns, tw, fmax, inv);
-  else if (b == 1) stockham_pass<2>(x, N, Ns, tw, fmax, inv);
+  if (b == 3) stockham_pass<8>(x, lN, lNs, tw, lf, inv);
+  else if (b == 2) stockham_pass<4>(x, lN, lNs, tw, lf, inv);
+  else if (b == 1) stockham_pass<2>(x, lN, lNs, tw, lf, inv);
 }
 
 template <class V>
@@ -227,23 +244,23 @@ __device__ __forceinline__ PairInfo<V> pair_info(const Tables& T, int p, int nsi
   return q;
 }
 
-// e^{i k phi0} with phi0 = pi / den (den = 0 means phi0 = 0); k reduced
-// exactly modulo 2 den before the trigonometric call.
+// e^{i k phi0} with phi0 = pi / den (den = 0 means phi0 = 0), for 0 <= k < n:
+// on every ring den = n (polar caps) or den = n = 4 nside (belt), so k / den
+// already lies in [0, 2) and needs no reduction before the trigonometric call.
 __device__ __forceinline__ double2 phase_of(double2*, int k, int den) {
   if (den == 0) return make_double2(1.0, 0.0);
-  const int r = k % (2 * den);
   double s, c;
-  sincospi((double)r / (double)den, &s, &c);
+  sincospi((double)k / (double)den, &s, &c);
   return make_double2(c, s);
 }
 __device__ __forceinline__ float2 phase_of(float2*, int k, int den) {
   if (den == 0) return make_float2(1.0f, 0.0f);
-  const int r = k % (2 * den);
   float s, c;
-  sincospif((float)r / (float)den, &s, &c);
+  sincospif((float)k / (float)den, &s, &c);
   return make_float2(c, s);
 }
 template <class V> __device__ __forceinline__ V phase(int k, int den) { return phase_of((V*)nullptr, k, den); }
+
 
 template <class V> __device__ __forceinline__ Re<V> sign_pow(Re<V> sigma, int e) {
   return (sigma < Re<V>(0) && (e & 1)) ? Re<V>(-1) : Re<V>(1);
@@ -415,16 +432,16 @@ __device__ __forceinline__ void kern_mul(V* buf, const PairInfo<V>& q) {
 // Z_j = map_N[j] + i map_S[j] for j < n, left in buf[0..n) (natural order)
 template <class V>
 __device__ void ring_inverse(V* buf, Re<V>* scratch, const PairInfo<V>& q, const V* __restrict__ eo, int mmax,
-                             const V* __restrict__ tw, int fmax) {
+                             const V* __restrict__ tw, int lf) {
   spectrum(buf, scratch, q, eo, mmax);
   if (!q.blue) {
-    fft_pow2(buf, q.n, tw, fmax, true);
+    fft_pow2(buf, q.n, tw, lf, true);
   } else {
     // IDFT(h) = conj(DFT(conj h)); DFT by chirp-z
     for (int j = q.n + threadIdx.x; j < q.L; j += blockDim.x) buf[pad(j)] = zero<V>();
-    fft_pow2(buf, q.L, tw, fmax, false);
+    fft_pow2(buf, q.L, tw, lf, false);
     kern_mul(buf, q);
-    fft_pow2(buf, q.L, tw, fmax, true);
+    fft_pow2(buf, q.L, tw, lf, true);
     for (int j = threadIdx.x; j < q.n; j += blockDim.x) buf[pad(j)] = conj2(cmul(buf[pad(j)], q.chirp[j]));
     lds_barrier();
   }
@@ -434,15 +451,15 @@ __device__ void ring_inverse(V* buf, Re<V>* scratch, const PairInfo<V>& q, const
 // except that Bluestein rings leave X_k / c_k (the final chirp factor is
 // applied where the spectrum is read, in write_geo)
 template <class V>
-__device__ void ring_forward(V* buf, const PairInfo<V>& q, const V* __restrict__ tw, int fmax) {
+__device__ void ring_forward(V* buf, const PairInfo<V>& q, const V* __restrict__ tw, int lf) {
   if (!q.blue) {
-    fft_pow2(buf, q.n, tw, fmax, false);
+    fft_pow2(buf, q.n, tw, lf, false);
   } else {
     for (int j = threadIdx.x; j < q.L; j += blockDim.x)
       buf[pad(j)] = j < q.n ? cmul(buf[pad(j)], q.chirp[j]) : zero<V>();
-    fft_pow2(buf, q.L, tw, fmax, false);
+    fft_pow2(buf, q.L, tw, lf, false);
     kern_mul(buf, q);
-    fft_pow2(buf, q.L, tw, fmax, true);
+    fft_pow2(buf, q.L, tw, lf, true);
   }
 }
 
@@ -495,6 +512,7 @@ __global__ __launch_bounds__(NT) void k_ring(Tables T, int nside, int mmax, int 
   if (g >= npc * nrhs) return;
   const int p = pairs[g / nrhs], c = g % nrhs;
   const PairInfo<V> q = pair_info<V>(T, p, nside, chirp, kern);
+  const int lf = ilog2(fmax);   // the twiddle table has fmax = 2^lf entries
   // logical column c = component kc of group gq (T+Q+U plans: 3 maps per group)
   const int gq = c / rc.group, kc = c % rc.group;
   const V* __restrict__ eop = eo + ((int64_t)gq * rc.eo_cols + kc) * eo_stride + (size_t)p * (mmax + 1) * 2;
@@ -503,7 +521,7 @@ __global__ __launch_bounds__(NT) void k_ring(Tables T, int nside, int mmax, int 
   if (ninv) ninv += kc * rc.ninv_stride;
 
   if (MODE == RING_FUSED) {
-    ring_inverse(buf, scratch, q, eop, mmax, tw, fmax);
+    ring_inverse(buf, scratch, q, eop, mmax, tw, lf);
     // N^-1 of the ring (n <= 8 blockDim): all loads issued before the products
     constexpr int U = 8;
     Re<V> wn[U], ws[U];
@@ -522,7 +540,7 @@ __global__ __launch_bounds__(NT) void k_ring(Tables T, int nside, int mmax, int 
       }
     }
   } else if (MODE == RING_SYNTH) {
-    ring_inverse(buf, scratch, q, eop, mmax, tw, fmax);
+    ring_inverse(buf, scratch, q, eop, mmax, tw, lf);
     for (int j = threadIdx.x; j < q.n; j += blockDim.x) {
       const V Z = buf[pad(j)];
       mp[q.fn + j] = (double)Z.x;
@@ -533,7 +551,7 @@ __global__ __launch_bounds__(NT) void k_ring(Tables T, int nside, int mmax, int 
     for (int j = threadIdx.x; j < q.n; j += blockDim.x)
       buf[pad(j)] = mk<V>((Re<V>)mp[q.fn + j], q.equator ? Re<V>(0) : (Re<V>)mp[q.fs + j]);
   }
-  ring_forward(buf, q, tw, fmax);
+  ring_forward(buf, q, tw, lf);
   lds_barrier();
   write_geo(geop, buf, q, mmax);
 }
@@ -655,7 +673,9 @@ size_t ring_lds_bytes(const crsht_plan* P, bool f32) {
 
 hipError_t launch_ring(const crsht_plan* P, int nrhs, RingMode mode, const void* eo, double* map,
                        const double* ninv, void* geo, bool f32, hipStream_t s, RingCols cols) {
-  timing_begin(P, 2, s);
+  // timed: the fused operator passes, FP32 (id 2) and FP64 (id 6) apart
+  const int tid = mode == RING_FUSED ? (f32 ? 2 : 6) : -1;
+  timing_begin(P, tid, s);
   hipError_t e;
   if (f32)
     e = ring_mode<float2>(P, nrhs, mode, (const float2*)eo, map, ninv, (float2*)geo, P->t.twiddle32, P->t.bs_chirp32,
@@ -663,7 +683,7 @@ hipError_t launch_ring(const crsht_plan* P, int nrhs, RingMode mode, const void*
   else
     e = ring_mode<double2>(P, nrhs, mode, (const double2*)eo, map, ninv, (double2*)geo, P->t.twiddle, P->t.bs_chirp,
                            P->t.bs_kern, cols, s);
-  timing_end(P, 2, s);
+  timing_end(P, tid, s);
   return e;
 }
 
