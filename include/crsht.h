@@ -93,6 +93,8 @@ typedef enum { CR_F64 = 0, CR_MIXED = 1 } cr_prec;
 
 /* Preconditioner of cr_solve (cr_opts.precond). */
 enum { CR_PC_JACOBI = 0, CR_PC_BLOCK = 1 };
+/* cr_opts.terms */
+enum { CR_SUM = 0, CR_SEPARATE = 4 };
 
 /* Create a plan for HEALPix resolution nside (power of two not required,
  * 1 <= nside <= 1024; larger nside returns CR_ENOTSUP), band limit lmax >= 0 and mmax (<= lmax; pass -1 for
@@ -198,6 +200,11 @@ typedef struct {
                           length change) and replayed on `stream`; 0: every kernel is launched
                           directly. Results are identical either way. Ignored while kernel timing
                           is enabled. */
+  int terms;           /* read by cr_solve only. CR_SUM (0): one solution per column for the sum of
+                          the given terms; CR_SEPARATE: per column the mean field (d term, eq.
+                          mean-field-map) and the fluctuation (w0 and w1 terms, eq. fluc-map) as
+                          two solutions, solved together as 2 nrhs columns (needs 2 nrhs <=
+                          nrhs_max, d and at least one of w0, w1 non-NULL, rhs NULL) */
 } cr_opts;
 
 typedef struct {
@@ -278,7 +285,11 @@ int cr_apply(const crsht_plan *plan, const cr_problem *prob, int nrhs, const dou
  * assembled as in cr_rhs from d, w0, w1 (NULL = omitted: d only gives the mean
  * field of eq. mean-field-map, w0 and w1 only the fluctuation of eq. fluc-map),
  * unless rhs is non-NULL (device [nrhs][nalm]), which is used as b directly.
- * s_out: device [nrhs][nalm]. stats: host, nrhs entries.
+ * s_out: device [nrhs][nalm]. stats: host, nrhs entries. With opts->terms =
+ * CR_SEPARATE: s_out [nrhs][2][ncomp][nalm] (mean field, then fluctuation, of
+ * each column; the sum is the CR_SUM solution up to the tolerance) and stats
+ * 2 nrhs entries in the same order; cr_problem.amp[c] applies to both
+ * solutions of column c.
  * With the environment variable CRSHT_PROGRESS = k > 0, every k-th host
  * convergence check prints the iteration count and the largest recursive
  * residual of the open columns to stderr (long solves).
@@ -305,8 +316,9 @@ int cr_solve(const crsht_plan *plan, const cr_problem *prob, int nrhs, const dou
  * on it). s_out: device [nrhs][nalm]. The per-call host data (spectra, beam,
  * amplitudes) is copied through pinned staging slots of the plan: more than
  * four calls enqueued ahead of the device wait for the oldest. Other
- * arguments and errors as cr_solve (errors are detected before enqueueing).
- * Consecutive calls on one plan must use one stream (they share the plan
+ * arguments and errors as cr_solve (errors are detected before enqueueing;
+ * opts->terms must be CR_SUM). Consecutive calls on one plan must use one
+ * stream (they share the plan
  * workspace); changing nrhs, tolerance, preconditioner or limits between
  * calls re-captures the graphs after synchronising the device once. */
 int cr_solve_async(const crsht_plan *plan, const cr_problem *prob, int nrhs, const double *d, const double *w0,

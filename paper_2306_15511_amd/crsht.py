@@ -23,6 +23,7 @@ CR_OK, CR_EINVAL, CR_ENOMEM, CR_EDEVICE, CR_ENOTSUP, CR_ESCRATCH = 0, -1, -2, -3
 CR_NOCONV, CR_BREAKDOWN = 1, 2
 CR_F64, CR_MIXED = 0, 1
 CR_PC_JACOBI, CR_PC_BLOCK = 0, 1
+CR_SUM, CR_SEPARATE = 0, 4
 
 
 class CrshtError(RuntimeError):
@@ -45,7 +46,7 @@ class _Problem(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("prec", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("precond", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("use_graph", ctypes.c_int), ("terms", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -414,14 +415,19 @@ def apply(plan: Plan, prob: Problem, x: torch.Tensor, prec: int = CR_F64) -> tor
 def solve(plan: Plan, prob: Problem, d=None, w0=None, w1=None, rhs_vec=None, nrhs: int = 1, tol: float = 1e-6,
           maxiter: int = 10000, prec: int = CR_F64, inner_tol: float = 1e-2, max_refine: int = 50,
           check_every: int = 8, out: torch.Tensor | None = None, use_graph: bool = True,
-          precond: int = CR_PC_JACOBI):
+          precond: int = CR_PC_JACOBI, terms: int = CR_SUM):
     """Returns (s [nrhs, nalm] complex128 ([nrhs, 3, nalm] for ncomp = 3), [Stats]).
-    use_graph: replay each block of check_every iterations as a captured HIP graph."""
+    use_graph: replay each block of check_every iterations as a captured HIP graph.
+    terms = CR_SEPARATE: s [nrhs, 2, ...] (mean field, fluctuation) and 2 nrhs Stats."""
+    nsol = 2 * nrhs if terms == CR_SEPARATE else nrhs
     if out is None:
-        out = torch.empty(plan.alm_shape(nrhs), dtype=torch.complex128, device=prob.ninv.device)
+        shape = plan.alm_shape(nrhs)
+        if terms == CR_SEPARATE:
+            shape = (nrhs, 2) + tuple(shape[1:])
+        out = torch.empty(shape, dtype=torch.complex128, device=prob.ninv.device)
     p = prob._c()
-    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every, int(precond), int(use_graph))
-    st = (_Stats * nrhs)()
+    o = _Opts(tol, maxiter, prec, inner_tol, max_refine, check_every, int(precond), int(use_graph), int(terms))
+    st = (_Stats * nsol)()
     _check(_lib.cr_solve(plan.handle, ctypes.byref(p), nrhs, _ptr(d), _ptr(w0), _ptr(w1), _ptr(rhs_vec), _ptr(out),
                          ctypes.byref(o), st, _stream()), "cr_solve")
     return out, [Stats(s.status, s.iters, s.refinements, s.rel_resid_true) for s in st]

@@ -736,6 +736,7 @@ int dsolve_setup(DSolve& d, const crsht_plan* P, const cr_problem* prob, int nrh
   if (!(o->tol > 0.0) || o->maxiter < 1) return CR_EINVAL;
   if (o->prec != CR_F64 && o->prec != CR_MIXED) return CR_EINVAL;
   if (o->precond != CR_PC_JACOBI && o->precond != CR_PC_BLOCK) return CR_EINVAL;
+  if (o->terms != CR_SUM) return CR_EINVAL;   // separate outputs: cr_solve only
   d.P = P;
   d.nrhs = nrhs;
   d.ninv = prob->ninv;
@@ -1142,10 +1143,43 @@ extern "C" int cr_apply(const crsht_plan* P, const cr_problem* prob, int nrhs, c
   return operator_core(P, nrhs, P->w.cg_d, P->w.alm_a, prob->ninv, C2(Ax), s, prec == CR_MIXED);
 }
 
+// CR_SEPARATE: the right-hand sides of the d term and of the w0, w1 terms of
+// every column, assembled as two blocks of nrhs columns and interleaved into
+// s_out (mean field, fluctuation per column), solved as 2 nrhs columns with
+// the amplitudes repeated; the solution overwrites its right-hand side.
+int solve_separate(const crsht_plan* P, const cr_problem* prob, int nrhs, const double* d, const double* w0,
+                   const double* w1, double* s_out, const cr_opts* opts, cr_stats* stats, hipStream_t s) {
+  if (!prob || !opts || !stats || !s_out || !d || (!w0 && !w1)) return CR_EINVAL;
+  if (2 * nrhs > P->nrhs_max) return CR_EINVAL;
+  Workspace const& w = P->w;
+  const size_t vb = (size_t)vlen(P) * sizeof(double2);
+  CR_CHECK(set_problem(P, prob, 1.0, s, nrhs));
+  CR_CHECK(assemble_rhs(P, nrhs, prob->ninv, d, nullptr, nullptr, w.cg_xacc, s));
+  CR_CHECK(assemble_rhs(P, nrhs, prob->ninv, nullptr, w0, w1, w.cg_bin, s));
+  CR_TRY(hipMemcpy2DAsync(s_out, 2 * vb, w.cg_xacc, vb, vb, nrhs, hipMemcpyDeviceToDevice, s));
+  CR_TRY(hipMemcpy2DAsync(reinterpret_cast<char*>(s_out) + vb, 2 * vb, w.cg_bin, vb, vb, nrhs,
+                          hipMemcpyDeviceToDevice, s));
+  cr_problem p2 = *prob;
+  std::vector<double> amp2;
+  if (prob->amp) {
+    amp2.resize(2 * (size_t)nrhs);
+    for (int c = 0; c < nrhs; ++c) amp2[2 * c] = amp2[2 * c + 1] = prob->amp[c];
+    p2.amp = amp2.data();
+  }
+  cr_opts o = *opts;
+  o.terms = CR_SUM;
+  return solve_core(P, &p2, 1.0, 2 * nrhs, nullptr, nullptr, nullptr, s_out, s_out, &o, stats, s);
+}
+
 extern "C" int cr_solve(const crsht_plan* P, const cr_problem* prob, int nrhs, const double* d, const double* w0,
                         const double* w1, const double* rhs, double* s_out, const cr_opts* opts, cr_stats* stats,
                         void* stream) {
   CR_CHECK(check_plan(P, nrhs));
+  if (opts && opts->terms == CR_SEPARATE) {
+    if (rhs) return CR_EINVAL;
+    return solve_separate(P, prob, nrhs, d, w0, w1, s_out, opts, stats, S(stream));
+  }
+  if (opts && opts->terms != CR_SUM) return CR_EINVAL;
   return solve_core(P, prob, 1.0, nrhs, d, w0, w1, rhs, s_out, opts, stats, S(stream));
 }
 

@@ -95,6 +95,50 @@ def test_batched_columns_independent():
         assert real_rel(op, s.cpu().numpy()[c], ref) < 1e-9
 
 
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_separate_terms(prec):
+    # CR_SEPARATE: per column the mean field (d term) and the fluctuation (w0,
+    # w1 terms) as two solutions; each against the oracle's dense solution of
+    # its own right-hand side (FP64) or the oracle-evaluated residual (mixed),
+    # with per-column amplitudes applied to both; their sum solves the full
+    # right-hand side
+    m = _m()
+    nside = 8
+    print("case separate terms", prec, flush=True)
+    wl, P, op, d = masked_problem(nside)
+    plan = m.Plan(nside, wl.lmax, nrhs_max=4)
+    amp = np.array([1.0, 1.7])
+    gp = m.Problem(P.cl, P.bl, tc(P.ninv), P.lmin, amp)
+    rng = np.random.default_rng(13)
+    W0 = np.stack([ci.white_alm(rng, wl.lmax) for _ in range(2)])
+    W1 = np.stack([rng.standard_normal(P.ninv.size) for _ in range(2)])
+    D2 = np.stack([d, -0.5 * d])
+    pr = m.CR_F64 if prec == "f64" else m.CR_MIXED
+    tol = 1e-12 if prec == "f64" else 1e-8
+    s, st = m.solve(plan, gp, tc(D2), tc(W0), tc(W1), nrhs=2, tol=tol, prec=pr, terms=m.CR_SEPARATE)
+    assert tuple(s.shape[:2]) == (2, 2) and len(st) == 4
+    s = s.cpu().numpy()
+    Dd = dense.DenseY(nside, wl.lmax, lmin=2)
+    for c in range(2):
+        cl_c = P.cl * amp[c]
+        opc = cr.CROperator(cr.Problem(P.nside, P.lmax, cl_c, P.bl, P.ninv, P.lmin))
+        bs = (opc.rhs(D2[c], None, None), opc.rhs(None, W0[c], W1[c]))
+        for k, b in enumerate(bs):
+            assert st[2 * c + k].status == 0
+            if prec == "f64":
+                ref = Dd.cr_solve(cl_c, P.bl, P.ninv, b)
+                assert real_rel(opc, s[c, k], ref) < 1e-9, (c, k)
+            else:
+                res = real_rel(opc, opc.apply(s[c, k]), b)
+                assert res <= 1.05e-8, (c, k, res)
+        full = opc.rhs(D2[c], W0[c], W1[c])
+        nb = [math.sqrt(opc.dot(b, b)) for b in bs]
+        bound = 1.05 * tol * (nb[0] + nb[1]) / math.sqrt(opc.dot(full, full))
+        assert real_rel(opc, opc.apply(s[c, 0] + s[c, 1]), full) <= bound
+    with pytest.raises(m.CrshtError):   # 2 nrhs columns must fit the plan
+        m.solve(plan, gp, tc(np.stack([d] * 3)), tc(np.stack([W0[0]] * 3)), None, nrhs=3, terms=m.CR_SEPARATE)
+
+
 def test_fully_masked_gives_prior_draw():
     m = _m()
     nside = 8
