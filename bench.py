@@ -540,8 +540,37 @@ def solve_line(args, tqu: bool, R: int, steps: int, warmup: int, compare: bool, 
                 forms["mixed_1_column"] = timed_form(1, crsht.CR_MIXED, 3, "mixed PCG, 1 column")
         forms["f64_1_column"] = timed_form(1, crsht.CR_F64, 1, "plain FP64 PCG, 1 column")
         res["forms"] = forms
+        res["transforms"] = transform_rates(plan, R, nc, lmax, dev)
     plan.close()
     return res
+
+
+def transform_rates(plan, R: int, nc: int, lmax: int, dev):
+    """SHT pairs/s (synthesis + adjoint of R columns, inputs resident) per
+    precision: FP64, bf16x3 (the PCG inner operator) and bf16x6 (the
+    user-visible reduced-precision transforms)."""
+    import torch
+    from paper_2306_15511_amd import crsht
+    import crinputs as ci
+    rng = np.random.default_rng([7, R])
+    a = np.stack([ci.white_alm(rng, lmax) for _ in range(R * nc)]).reshape(plan.alm_shape(R))
+    A = torch.from_numpy(a).to(dev)
+    mp = crsht.synth(plan, A)
+    al = torch.empty_like(A)
+    out = {}
+    for name, prec in (("f64", crsht.CR_F64), ("bf16x3", crsht.CR_MIXED), ("bf16x6", crsht.CR_BF16X6)):
+        crsht.synth(plan, A, out=mp, prec=prec)
+        crsht.adjoint(plan, mp, out=al, prec=prec)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            crsht.synth(plan, A, out=mp, prec=prec)
+            crsht.adjoint(plan, mp, out=al, prec=prec)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"ms_per_pair_call": dt * 1e3, "sht_pairs_per_s": R * nc / dt}
+    return out
 
 
 def kernel_roofline(args, plan, one_solve, nside, lmax, R, nc, mixed, use_block, tqu):

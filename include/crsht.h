@@ -76,20 +76,25 @@ enum {
 
 typedef struct crsht_plan crsht_plan;
 
-/* Arithmetic of the Legendre contraction.
- * CR_F64: float64 throughout (vector ALU).
- * CR_MIXED: the lambda_lm recurrence stays float64; recurrence values and
- *   a_lm / ring coefficients are rounded to float and split into bf16 hi + lo
- *   parts, and each product is formed as hi*hi + hi*lo + lo*hi on the matrix
- *   cores with float32 accumulation (relative error about 5e-6 per transform).
- *   Ring FFTs, CG vectors, dot products and scalars stay float64. In cr_solve
- *   it is the inner operator of float64 iterative refinement.
- *   T+Q+U plans: Q and U come from Legendre sums that cancel near the poles
- *   and are divided by sin^2(theta) (up to 1.6e6 on the first ring at Nside
- *   1024), which amplifies the rounding of the mixed sums by as much; at
- *   Nside >= 1024 the mixed solve does not reach 1e-6 (the inner iteration
- *   stalls near 1e-4 and some columns diverge): use CR_F64 there. */
-typedef enum { CR_F64 = 0, CR_MIXED = 1 } cr_prec;
+/* Arithmetic of the transforms.
+ * CR_F64: float64 throughout (FP64 matrix cores for two or more columns,
+ *   vector ALU for one).
+ * CR_MIXED (bf16x3): the lambda_lm recurrence stays float64; recurrence
+ *   values and a_lm / ring coefficients are rounded to float and split into
+ *   bf16 hi + lo parts, and each product is formed as hi*hi + hi*lo + lo*hi on
+ *   the matrix cores with float32 accumulation (relative error about 5e-6 per
+ *   transform); the ring FFTs run in float32; CG vectors, dot products and
+ *   scalars stay float64. In cr_solve it is the inner operator of float64
+ *   iterative refinement. T+Q+U plans: Q and U come from Legendre sums that
+ *   cancel near the poles and are divided by sin^2(theta), so the ring pairs
+ *   with sin^2(theta) < 0.01 take float64 Legendre sums (the rounding of the
+ *   others is amplified by at most 100).
+ * CR_BF16X6: user-visible transforms (sht_synth, sht_synth_adjoint,
+ *   sht_synth_grad, cr_apply) to about 1e-7: the same kernels with three bf16
+ *   parts per operand (hi, mid, lo; the float value to 2^-24) and the six
+ *   products of total order <= 2, float32 accumulation and float32 ring FFTs.
+ *   Not a cr_solve precision (CR_EINVAL there). */
+typedef enum { CR_F64 = 0, CR_MIXED = 1, CR_BF16X6 = 3 } cr_prec;
 
 /* Preconditioner of cr_solve (cr_opts.precond). */
 enum { CR_PC_JACOBI = 0, CR_PC_BLOCK = 1 };

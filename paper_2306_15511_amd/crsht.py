@@ -21,7 +21,7 @@ LIB_PATH = os.environ.get("CRSHT_LIB") or os.path.join(_HERE, "libcrsht.so")
 
 CR_OK, CR_EINVAL, CR_ENOMEM, CR_EDEVICE, CR_ENOTSUP, CR_ESCRATCH = 0, -1, -2, -3, -4, -5
 CR_NOCONV, CR_BREAKDOWN = 1, 2
-CR_F64, CR_MIXED = 0, 1
+CR_F64, CR_MIXED, CR_BF16X6 = 0, 1, 3
 CR_PC_JACOBI, CR_PC_BLOCK = 0, 1
 CR_SUM, CR_SEPARATE = 0, 4
 

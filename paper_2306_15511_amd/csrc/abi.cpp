@@ -1053,20 +1053,31 @@ int lnpi_terms_batch(const crsht_plan* P, int n, const double* ninv, const doubl
 }  // namespace
 
 // ============================================================== transforms
+// precisions of the user-visible transforms; CR_BF16X6 runs the mixed
+// kernels with three bf16 parts per operand for the duration of the call
+bool transform_prec(cr_prec prec) { return prec == CR_F64 || prec == CR_MIXED || prec == CR_BF16X6; }
+struct SplitScope {
+  const crsht_plan* P;
+  SplitScope(const crsht_plan* p, cr_prec prec) : P(p) { P->mx_split = prec == CR_BF16X6 ? 3 : 2; }
+  ~SplitScope() { P->mx_split = 2; }
+};
+
 extern "C" int sht_synth(const crsht_plan* P, int nrhs, const double* alm, double* map, cr_prec prec,
                          void* stream) {
   CR_CHECK(check_plan(P, nrhs));
   if (!alm || !map) return CR_EINVAL;
-  if (prec != CR_F64 && prec != CR_MIXED) return CR_EINVAL;
-  return synth_f64(P, nrhs, C2(alm), P->t.rec_kappa, map, S(stream), prec == CR_MIXED);
+  if (!transform_prec(prec)) return CR_EINVAL;
+  SplitScope sc(P, prec);
+  return synth_f64(P, nrhs, C2(alm), P->t.rec_kappa, map, S(stream), prec != CR_F64);
 }
 
 extern "C" int sht_synth_adjoint(const crsht_plan* P, int nrhs, const double* map, double* alm, cr_prec prec,
                                  void* stream) {
   CR_CHECK(check_plan(P, nrhs));
   if (!alm || !map) return CR_EINVAL;
-  if (prec != CR_F64 && prec != CR_MIXED) return CR_EINVAL;
-  return adjoint_f64(P, nrhs, map, C2(alm), S(stream), prec == CR_MIXED);
+  if (!transform_prec(prec)) return CR_EINVAL;
+  SplitScope sc(P, prec);
+  return adjoint_f64(P, nrhs, map, C2(alm), S(stream), prec != CR_F64);
 }
 
 extern "C" int sht_analysis(const crsht_plan* P, int nrhs, const double* map, double* alm, int n_iter,
@@ -1135,12 +1146,13 @@ extern "C" int cr_apply(const crsht_plan* P, const cr_problem* prob, int nrhs, c
                         cr_prec prec, void* stream) {
   CR_CHECK(check_plan(P, nrhs));
   if (!x || !Ax) return CR_EINVAL;
-  if (prec != CR_F64 && prec != CR_MIXED) return CR_EINVAL;
+  if (!transform_prec(prec)) return CR_EINVAL;
   hipStream_t s = S(stream);
   CR_CHECK(set_problem(P, prob, 1.0, s, nrhs));
   CR_TRY(launch_project(P, nrhs, C2(x), P->w.cg_d, s));
   if (P->ncomp == 1) CR_TRY(launch_scale_alm(P, nrhs, P->w.cg_d, P->w.bk, P->w.alm_a, s));
-  return operator_core(P, nrhs, P->w.cg_d, P->w.alm_a, prob->ninv, C2(Ax), s, prec == CR_MIXED);
+  SplitScope sc(P, prec);
+  return operator_core(P, nrhs, P->w.cg_d, P->w.alm_a, prob->ninv, C2(Ax), s, prec != CR_F64);
 }
 
 // CR_SEPARATE: the right-hand sides of the d term and of the w0, w1 terms of
@@ -1294,9 +1306,12 @@ extern "C" int sht_synth_grad(const crsht_plan* P, int nrhs, const double* map_g
                               cr_prec prec, void* stream) {
   CR_CHECK(check_plan(P, nrhs));
   if (!map_grad || !alm_grad) return CR_EINVAL;
-  if (prec != CR_F64 && prec != CR_MIXED) return CR_EINVAL;
+  if (!transform_prec(prec)) return CR_EINVAL;
   hipStream_t s = S(stream);
-  CR_CHECK(adjoint_f64(P, nrhs, map_grad, C2(alm_grad), s, prec == CR_MIXED));
+  {
+    SplitScope sc(P, prec);
+    CR_CHECK(adjoint_f64(P, nrhs, map_grad, C2(alm_grad), s, prec != CR_F64));
+  }
   CR_TRY(launch_mweight(P, nrhs, C2(alm_grad), s));
   return CR_OK;
 }

@@ -245,6 +245,10 @@ struct crsht_plan {
   // once when *pred != 0. Set only while a device-driven solve enqueues its
   // predicated sections (dsolve.hip); null otherwise.
   mutable const int* pred = nullptr;
+  // bf16 parts per operand of the mixed Legendre transforms: 2 (bf16x3
+  // products, the PCG inner operator) or 3 (bf16x6, the CR_BF16X6 transforms);
+  // set only for the duration of a CR_BF16X6 call
+  mutable int mx_split = 2;
   // pinned staging of the per-call host data (spectra, beam, column
   // amplitudes): slot k is reused only after the copies last enqueued from it
   // have run (event k), so no call has to synchronise its stream

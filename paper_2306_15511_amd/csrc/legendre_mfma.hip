@@ -103,6 +103,36 @@ __device__ __forceinline__ void split8c(const float* x, bf16x8& hi, bf16x8& lo) 
   lo = __builtin_bit_cast(bf16x8, l4);
 }
 
+// bf16 hi / mid / lo vectors of x[0..7] (three parts: x - hi - mid - lo is
+// below 2^-24 |x|), two values per conversion
+__device__ __forceinline__ void split8c3(const float* x, bf16x8& hi, bf16x8& mid, bf16x8& lo) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 h4, m4, l4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float a = x[2 * i], b = x[2 * i + 1];
+    const unsigned hp = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){a, b}, bf16x2));
+    const float ra = a - __uint_as_float(hp << 16), rb = b - __uint_as_float(hp & 0xffff0000u);
+    const unsigned mp = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){ra, rb}, bf16x2));
+    const float sa = ra - __uint_as_float(mp << 16), sb = rb - __uint_as_float(mp & 0xffff0000u);
+    h4[i] = hp;
+    m4[i] = mp;
+    l4[i] = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){sa, sb}, bf16x2));
+  }
+  hi = __builtin_bit_cast(bf16x8, h4);
+  mid = __builtin_bit_cast(bf16x8, m4);
+  lo = __builtin_bit_cast(bf16x8, l4);
+}
+
+// NS bf16 parts of the 8 values x[0..7] (NS = 2: hi, lo; 3: hi, mid, lo)
+template <int NS>
+__device__ __forceinline__ void split_parts(const float* x, bf16x8 (&pt)[NS]) {
+  if constexpr (NS == 2) split8c(x, pt[0], pt[1]);
+  else split8c3(x, pt[0], pt[1], pt[2]);
+}
+
 // v_permlane32_swap per dword: t0 = (lanes 0-31: k0 own, lanes 32-63: k1 of
 // lane - 32), t1 = (lanes 0-31: k0 of lane + 32, lanes 32-63: k1 own)
 // (lane layout checked on the device)
@@ -125,6 +155,23 @@ __device__ __forceinline__ f32x16 mfma3(bf16x8 ah, bf16x8 al, bf16x8 bh, bf16x8 
   d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, d, 0, 0, 0);
   d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, d, 0, 0, 0);
   return d;
+}
+
+// split products: NS = 2 (bf16x3): hi hi + hi lo + lo hi; NS = 3 (bf16x6):
+// the six products of parts whose orders add up to at most 2
+template <int NS>
+__device__ __forceinline__ f32x16 mfma_parts(const bf16x8 (&a)[NS], const bf16x8 (&b)[NS], f32x16 d) {
+  if constexpr (NS == 2) {
+    return mfma3(a[0], a[1], b[0], b[1], d);
+  } else {
+    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[0], d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[1], d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[0], d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[2], d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[1], d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[0], d, 0, 0, 0);
+    return d;
+  }
 }
 
 // ------------------------------------------------------------- checkpoints
@@ -167,6 +214,7 @@ __global__ __launch_bounds__(256) void k_checkpoints(int lmax, int mmax, int npa
 // block reads each column's 32 steps coalesced (lane -> step) and stages
 // f * alm (float) in LDS as [q][rhs][comp][16 steps], from which each lane
 // reads its 8 steps contiguously.
+template <int NS>
 __global__ __launch_bounds__(64) void k_prep_synth(int lmax, int nrhs, const int64_t* __restrict__ mstart,
                                                    const int64_t* __restrict__ cstart, const double2* __restrict__ alm,
                                                    int64_t alm_stride, const double* __restrict__ f,
@@ -197,22 +245,16 @@ __global__ __launch_bounds__(64) void k_prep_synth(int lmax, int nrhs, const int
   __syncthreads();
   // tile phase: lane j + 32 kg, j = 2 rhs + comp, holds steps 2 (8 kg + v) + q
   const int j = lane & 31, kg = lane >> 5;
-  bf16x8* dst = ab + (size_t)(cstart[m] + c) * 4 * 64;
+  bf16x8* dst = ab + (size_t)(cstart[m] + c) * (2 * NS) * 64;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const float* src = &st_lds[q][j >> 1][j & 1][8 * kg];
     const float4 a4 = *reinterpret_cast<const float4*>(src), b4 = *reinterpret_cast<const float4*>(src + 4);
     const float x[8] = {a4.x, a4.y, a4.z, a4.w, b4.x, b4.y, b4.z, b4.w};
-    bf16x8 hi, lo;
+    bf16x8 pt[NS];
+    split_parts<NS>(x, pt);
 #pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      __bf16 h, l;
-      split_bf16(x[v], h, l);
-      hi[v] = h;
-      lo[v] = l;
-    }
-    dst[(q * 2 + 0) * 64 + lane] = hi;
-    dst[(q * 2 + 1) * 64 + lane] = lo;
+    for (int u = 0; u < NS; ++u) dst[(q * NS + u) * 64 + lane] = pt[u];
   }
 }
 
@@ -297,7 +339,7 @@ __global__ __launch_bounds__(64) void k_pupdate_prep(int lmax, int nrhs, int64_t
 constexpr int kSynWaves = 4;                       // m per workgroup
 constexpr int kSynRow = kSynWaves * 4;             // floats per (column, pair) run: [m][E.re, E.im, O.re, O.im]
 constexpr int kSynRhsStride = 32 * kSynRow + 2;    // floats per column in LDS (32 pairs), padded against bank conflicts
-template <int NG>
+template <int NG, int NS>
 __global__ __launch_bounds__(256) void k_synth_mfma(int lmax, int mmax, int npairs, int nrhs,
                                                     const double* __restrict__ pair_z, const double* __restrict__ alpha,
                                                     const int* __restrict__ lst_g, const double2* __restrict__ lst_s,
@@ -335,19 +377,20 @@ __global__ __launch_bounds__(256) void k_synth_mfma(int lmax, int mmax, int npai
   if (gmin != kNever) {
     const int nch = (nsteps + kSynChunk - 1) / kSynChunk;
     double v0 = 0.0, v1 = 0.0;
-    const bf16x8* abm = ab + (size_t)cstart[mm] * 4 * 64 + lane;
+    const bf16x8* abm = ab + (size_t)cstart[mm] * (2 * NS) * 64 + lane;
     const int cfirst = (gmin * kGroup) / kSynChunk;
     for (int c = cfirst; c < nch; ++c) {
       // operands of this chunk, consumed after the recurrence (which hides
       // their latency)
-      bf16x8 bEh[NG], bEl[NG], bOh[NG], bOl[NG];
+      bf16x8 bE[NG][NS], bO[NG][NS];
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
-        const bf16x8* src = abm + g * ab_gstride + (size_t)c * 256;
-        bEh[g] = src[0];
-        bEl[g] = src[64];
-        bOh[g] = src[128];
-        bOl[g] = src[192];
+        const bf16x8* src = abm + g * ab_gstride + (size_t)c * (2 * NS * 64);
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+          bE[g][u] = src[u * 64];
+          bO[g][u] = src[(NS + u) * 64];
+        }
       }
       const int st0 = c * kSynChunk;
       float mu32[kSynChunk];
@@ -386,26 +429,38 @@ __global__ __launch_bounds__(256) void k_synth_mfma(int lmax, int mmax, int npai
           mu32[s] = to_f32(mu);
         }
       }
-      bf16x8 eh[2], el[2], oh[2], ol[2];
+      bf16x8 e[2][NS], o[2][NS];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        split8(mu32 + 16 * h, 0, eh[h], el[h]);
-        split8(mu32 + 16 * h, 1, oh[h], ol[h]);
+        if constexpr (NS == 2) {
+          split8(mu32 + 16 * h, 0, e[h][0], e[h][1]);
+          split8(mu32 + 16 * h, 1, o[h][0], o[h][1]);
+        } else {
+          float xe[8], xo[8];
+#pragma unroll
+          for (int v = 0; v < 8; ++v) {
+            xe[v] = mu32[16 * h + 2 * v];
+            xo[v] = mu32[16 * h + 2 * v + 1];
+          }
+          split_parts<NS>(xe, e[h]);
+          split_parts<NS>(xo, o[h]);
+        }
       }
       // A fragments (lane row + 32 kg holds A[row][8 kg .. 8 kg + 7] of M tile t,
       // pairs 32 t + row): lane p owns all 16 k of its pair, so one
       // permlane32 swap of (k 0..7, k 8..15) gives both tiles' fragments
-      bf16x8 aEh0, aEh1, aEl0, aEl1, aOh0, aOh1, aOl0, aOl1;
-      swap_halves(eh[0], eh[1], aEh0, aEh1);
-      swap_halves(el[0], el[1], aEl0, aEl1);
-      swap_halves(oh[0], oh[1], aOh0, aOh1);
-      swap_halves(ol[0], ol[1], aOl0, aOl1);
+      bf16x8 aE0[NS], aE1[NS], aO0[NS], aO1[NS];
+#pragma unroll
+      for (int u = 0; u < NS; ++u) {
+        swap_halves(e[0][u], e[1][u], aE0[u], aE1[u]);
+        swap_halves(o[0][u], o[1][u], aO0[u], aO1[u]);
+      }
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
-        dE0[g] = mfma3(aEh0, aEl0, bEh[g], bEl[g], dE0[g]);
-        dE1[g] = mfma3(aEh1, aEl1, bEh[g], bEl[g], dE1[g]);
-        dO0[g] = mfma3(aOh0, aOl0, bOh[g], bOl[g], dO0[g]);
-        dO1[g] = mfma3(aOh1, aOl1, bOh[g], bOl[g], dO1[g]);
+        dE0[g] = mfma_parts<NS>(aE0, bE[g], dE0[g]);
+        dE1[g] = mfma_parts<NS>(aE1, bE[g], dE1[g]);
+        dO0[g] = mfma_parts<NS>(aO0, bO[g], dO0[g]);
+        dO1[g] = mfma_parts<NS>(aO1, bO[g], dO1[g]);
       }
     }
   }
@@ -456,6 +511,7 @@ __global__ __launch_bounds__(256) void k_synth_mfma(int lmax, int mmax, int npai
 // operand vectors are written contiguously.
 constexpr int kPrepM = 8;                       // m per block
 constexpr int kPrepMS = 2 * 16 * 2 * 16 + 8;   // floats per m in LDS ([q][rhs][comp][pair], padded)
+template <int NS>
 __global__ __launch_bounds__(256) void k_prep_adj(int mmax, int npairs, int nrhs, const float2* __restrict__ geo,
                                                   int64_t geo_stride, bf16x8* __restrict__ ag, int64_t ag_gstride,
                                                   const int* __restrict__ pred) {
@@ -494,17 +550,11 @@ __global__ __launch_bounds__(256) void k_prep_adj(int mmax, int npairs, int nrhs
     const float* src = G + mm * kPrepMS + q * 512 + c * 16 + kg * 8;
     const float4 lo4 = *reinterpret_cast<const float4*>(src), hi4 = *reinterpret_cast<const float4*>(src + 4);
     const float x[8] = {lo4.x, lo4.y, lo4.z, lo4.w, hi4.x, hi4.y, hi4.z, hi4.w};
-    bf16x8 h8, l8;
+    bf16x8 pt[NS];
+    split_parts<NS>(x, pt);
+    bf16x8* dst = ag + ((size_t)m * nkb + kb) * (2 * NS) * 64;
 #pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      __bf16 h, l;
-      split_bf16(x[v], h, l);
-      h8[v] = h;
-      l8[v] = l;
-    }
-    bf16x8* dst = ag + ((size_t)m * nkb + kb) * 4 * 64;
-    dst[(q * 2 + 0) * 64 + lane] = h8;
-    dst[(q * 2 + 1) * 64 + lane] = l8;
+    for (int u = 0; u < NS; ++u) dst[(q * NS + u) * 64 + lane] = pt[u];
   }
 }
 
@@ -564,7 +614,7 @@ __device__ __forceinline__ void adj_tile_steps(float* my, const double2* al, int
   }
 }
 
-template <int NG>
+template <int NG, int NS>
 __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs, int nrhs,
                                                   const double* __restrict__ pair_z, const double* __restrict__ alpha,
                                                   const int* __restrict__ lst_g, const double2* __restrict__ lst_s,
@@ -627,13 +677,13 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
     // skip the round when no pair becomes live before the end of the tile
     if (wave_min(gs) <= (st0 + kAdjTile - 1) / kGroup) {
       // G operands of the round's 4 blocks of 16 pairs, issued before the recurrence
-      bf16x8 aq[4][4];
+      bf16x8 aq[4][2][NS];   // [block of 16 pairs][parity][part]
 #pragma unroll
       for (int kb = 0; kb < 4; ++kb) {
         const int gkb = min(r0 / 16 + kb, nkb - 1);
-        const bf16x8* a = ag + ((size_t)m * nkb + gkb) * 4 * 64;
+        const bf16x8* a = ag + ((size_t)m * nkb + gkb) * (2 * NS) * 64;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) aq[kb][u] = a[u * 64 + lane];
+        for (int u = 0; u < 2 * NS; ++u) aq[kb][u / NS][u % NS] = a[u * 64 + lane];
       }
       __builtin_amdgcn_sched_barrier(0);   // keep the operand loads ahead of the recurrence
       const double z = cur.z;
@@ -650,9 +700,9 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
 #pragma unroll
           for (int kb = 0; kb < 4; ++kb) {
             const int gkb = min(r0 / 16 + kb, nkb - 1);
-            const bf16x8* a = ag + g * ag_gstride + ((size_t)m * nkb + gkb) * 4 * 64;
+            const bf16x8* a = ag + g * ag_gstride + ((size_t)m * nkb + gkb) * (2 * NS) * 64;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) aq[kb][u] = a[u * 64 + lane];
+            for (int u = 0; u < 2 * NS; ++u) aq[kb][u / NS][u % NS] = a[u * 64 + lane];
           }
         }
         // blocks of 16 pairs past the last pair: their mu are 0 (no start
@@ -667,11 +717,11 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
           *reinterpret_cast<float4*>(xo) = *reinterpret_cast<const float4*>(my + (32 + row) * kRowF + swzf(row, p0));
           *reinterpret_cast<float4*>(xo + 4) =
               *reinterpret_cast<const float4*>(my + (32 + row) * kRowF + swzf(row, p0 + 4));
-          bf16x8 bEh, bEl, bOh, bOl;
-          split8c(xe, bEh, bEl);
-          split8c(xo, bOh, bOl);
-          dE[g] = mfma3(aq[kb][0], aq[kb][1], bEh, bEl, dE[g]);
-          dO[g] = mfma3(aq[kb][2], aq[kb][3], bOh, bOl, dO[g]);
+          bf16x8 bE[NS], bO[NS];
+          split_parts<NS>(xe, bE);
+          split_parts<NS>(xo, bO);
+          dE[g] = mfma_parts<NS>(aq[kb][0], bE, dE[g]);
+          dO[g] = mfma_parts<NS>(aq[kb][1], bO, dO[g]);
         }
       }
       __builtin_amdgcn_wave_barrier();
@@ -729,8 +779,10 @@ int64_t mixed_adj_tiles(const Geometry& g) {
 // buffers for kMaxGroups groups
 int64_t ab_group(const Geometry& g) { return mixed_synth_chunks(g) * 4 * 64; }
 int64_t ag_group(const Geometry& g) { return (int64_t)(g.mmax + 1) * ((g.npairs + 15) / 16) * 4 * 64; }
+// (the bf16x6 form takes one group with three parts instead of two: 3/4 of
+// the synthesis buffer of kMaxGroups = 2 groups, 3/2 of the adjoint buffer)
 int64_t mixed_ab_bytes(const Geometry& g) { return kMaxGroups * ab_group(g) * 16; }
-int64_t mixed_ag_bytes(const Geometry& g) { return kAdjGroups * ag_group(g) * 16; }
+int64_t mixed_ag_bytes(const Geometry& g) { return kAdjGroups * ag_group(g) * 16 * 3 / 2; }
 void mixed_starts(const Geometry& g, std::vector<int64_t>& cst, std::vector<int64_t>& tst, std::vector<int>& tm,
                   std::vector<int>& order, int& maxq) {
   cst.assign(g.mmax + 2, 0);
@@ -774,19 +826,22 @@ hipError_t launch_checkpoints(const crsht_plan* P, hipStream_t s) {
 // (kMixedCols / 2); the recurrence of a launch is shared by all its columns.
 int launch_groups(int nr) { return (nr + kMixedCols / 2 - 1) / (kMixedCols / 2); }
 
-hipError_t synth_mfma_launch(const crsht_plan* P, int nr, const bf16x8* ab, float2* eo, int64_t eo_stride,
+hipError_t synth_mfma_launch(const crsht_plan* P, int nr, int ns, const bf16x8* ab, float2* eo, int64_t eo_stride,
                              hipStream_t s) {
   const Geometry& g = P->g;
   dim3 gs(synth_mfma_blocks(g));
   timing_begin(P, 3, s);
-  if (launch_groups(nr) > 1)
-    hipLaunchKernelGGL(k_synth_mfma<2>, gs, dim3(256), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.pair_z,
-                       P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.mx_cstart, ab, ab_group(g), eo,
-                       eo_stride, P->pred);
+#define CRSHT_SYNTH_LAUNCH(NG, NS)                                                                                \
+  hipLaunchKernelGGL((k_synth_mfma<NG, NS>), gs, dim3(256), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.pair_z,      \
+                     P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.mx_cstart, ab, ab_group(g), eo,    \
+                     eo_stride, P->pred)
+  if (ns == 3)
+    CRSHT_SYNTH_LAUNCH(1, 3);
+  else if (launch_groups(nr) > 1)
+    CRSHT_SYNTH_LAUNCH(2, 2);
   else
-    hipLaunchKernelGGL(k_synth_mfma<1>, gs, dim3(256), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.pair_z,
-                       P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.mx_cstart, ab, ab_group(g), eo,
-                       eo_stride, P->pred);
+    CRSHT_SYNTH_LAUNCH(1, 2);
+#undef CRSHT_SYNTH_LAUNCH
   timing_end(P, 3, s);
   return hipGetLastError();
 }
@@ -795,22 +850,28 @@ hipError_t launch_legendre_synth_mixed(const crsht_plan* P, int nrhs, const doub
                                        float2* eo, hipStream_t s) {
   if (!f) f = P->t.ones;
   const Geometry& g = P->g;
+  const int ns = P->mx_split == 3 ? 3 : 2;
   const int64_t eo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
   bf16x8* ab = reinterpret_cast<bf16x8*>(P->w.mx_ab);
-  const int per = kMaxGroups * (kMixedCols / 2);
+  const int per = (ns == 3 ? 1 : kMaxGroups) * (kMixedCols / 2);
   for (int c0 = 0; c0 < nrhs; c0 += per) {
     const int nr = min(nrhs - c0, per);
     dim3 gp((g.lmax + kSynChunk) / kSynChunk, g.mmax + 1, launch_groups(nr));
-    hipLaunchKernelGGL(k_prep_synth, gp, dim3(64), 0, s, g.lmax, nr, P->t.mstart, P->t.mx_cstart,
-                       alm + (int64_t)c0 * g.nalm, (int64_t)g.nalm, f, ab, ab_group(g), P->pred);
+    if (ns == 3)
+      hipLaunchKernelGGL(k_prep_synth<3>, gp, dim3(64), 0, s, g.lmax, nr, P->t.mstart, P->t.mx_cstart,
+                         alm + (int64_t)c0 * g.nalm, (int64_t)g.nalm, f, ab, ab_group(g), P->pred);
+    else
+      hipLaunchKernelGGL(k_prep_synth<2>, gp, dim3(64), 0, s, g.lmax, nr, P->t.mstart, P->t.mx_cstart,
+                         alm + (int64_t)c0 * g.nalm, (int64_t)g.nalm, f, ab, ab_group(g), P->pred);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = synth_mfma_launch(P, nr, ab, eo + (int64_t)c0 * eo_stride, eo_stride, s);
+    e = synth_mfma_launch(P, nr, ns, ab, eo + (int64_t)c0 * eo_stride, eo_stride, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
+// (the PCG inner operator: bf16x3 always)
 hipError_t launch_legendre_synth_mixed_cg(const crsht_plan* P, int nrhs, const double2* z, double2* p, bool update,
                                           float2* eo, hipStream_t s) {
   const Geometry& g = P->g;
@@ -825,7 +886,7 @@ hipError_t launch_legendre_synth_mixed_cg(const crsht_plan* P, int nrhs, const d
                        P->w.scal + (int64_t)c0 * kScalSlots, update ? 1 : 0, ab, ab_group(g), P->pred);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = synth_mfma_launch(P, nr, ab, eo + (int64_t)c0 * eo_stride, eo_stride, s);
+    e = synth_mfma_launch(P, nr, 2, ab, eo + (int64_t)c0 * eo_stride, eo_stride, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -834,6 +895,7 @@ hipError_t launch_legendre_synth_mixed_cg(const crsht_plan* P, int nrhs, const d
 hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const float2* geo, double2* raw,
                                          hipStream_t s) {
   const Geometry& g = P->g;
+  const int ns = P->mx_split == 3 ? 3 : 2;
   const int64_t geo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
   bf16x8* ag = reinterpret_cast<bf16x8*>(P->w.mx_ag);
   // one column group per adjoint launch: two groups raise the register use
@@ -842,22 +904,26 @@ hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const fl
   const int per = kAdjGroups * (kMixedCols / 2);
   for (int c0 = 0; c0 < nrhs; c0 += per) {
     const int nr = min(nrhs - c0, per);
-    dim3 gp((g.npairs + 15) / 16, (g.mmax + kPrepM) / kPrepM, launch_groups(nr));
-    hipLaunchKernelGGL(k_prep_adj, gp, dim3(256), 0, s, g.mmax, g.npairs, nr, geo + (int64_t)c0 * geo_stride,
-                       geo_stride, ag, ag_group(g), P->pred);
+    dim3 gp((g.npairs + 15) / 16, (g.mmax + kPrepM) / kPrepM, 1);
+    if (ns == 3)
+      hipLaunchKernelGGL(k_prep_adj<3>, gp, dim3(256), 0, s, g.mmax, g.npairs, nr, geo + (int64_t)c0 * geo_stride,
+                         geo_stride, ag, ag_group(g), P->pred);
+    else
+      hipLaunchKernelGGL(k_prep_adj<2>, gp, dim3(256), 0, s, g.mmax, g.npairs, nr, geo + (int64_t)c0 * geo_stride,
+                         geo_stride, ag, ag_group(g), P->pred);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     timing_begin(P, 4, s);
-    if (launch_groups(nr) > 1)
-      hipLaunchKernelGGL(k_adj_mfma<2>, dim3(8u * (unsigned)P->t.mx_maxq), dim3(kAdjWaves * 64), 0, s, g.lmax,
-                         g.mmax, g.npairs, nr, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
-                         P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_order, P->t.mx_maxq, P->t.mx_ckpt,
-                         (const bf16x8*)ag, ag_group(g), raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm, P->pred);
+#define CRSHT_ADJ_LAUNCH(NS)                                                                                       \
+  hipLaunchKernelGGL((k_adj_mfma<1, NS>), dim3(8u * (unsigned)P->t.mx_maxq), dim3(kAdjWaves * 64), 0, s, g.lmax,   \
+                     g.mmax, g.npairs, nr, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,        \
+                     P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_order, P->t.mx_maxq, P->t.mx_ckpt, (const bf16x8*)ag, \
+                     ag_group(g), raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm, P->pred)
+    if (ns == 3)
+      CRSHT_ADJ_LAUNCH(3);
     else
-      hipLaunchKernelGGL(k_adj_mfma<1>, dim3(8u * (unsigned)P->t.mx_maxq), dim3(kAdjWaves * 64), 0, s, g.lmax,
-                         g.mmax, g.npairs, nr, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
-                         P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_order, P->t.mx_maxq, P->t.mx_ckpt,
-                         (const bf16x8*)ag, ag_group(g), raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm, P->pred);
+      CRSHT_ADJ_LAUNCH(2);
+#undef CRSHT_ADJ_LAUNCH
     timing_end(P, 4, s);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -6,7 +6,7 @@ plain-C Legendre sums (oracle/legendre_sums.c, pinned to the numpy oracle):
   residual replacement every 1e-3 drop): the oracle evaluates the true
   residual ||b - A x|| / ||b|| of two columns from its own A and b;
 * element-wise transforms at Nside 512 (FP64 matrix cores, FP64 vector
-  kernels, bf16x3 matrix cores) and the FP64 matrix-core adjoint at Nside
+  kernels, bf16x3 and bf16x6 matrix cores) and the FP64 matrix-core adjoint at Nside
   1024, whose 2048 ring pairs take two launches (the second adding to the
   first);
 * the block preconditioner with blocks of up to 384 rows (Nside 256);
@@ -79,7 +79,8 @@ def test_nside512_transforms_elementwise():
     ref_alm = [S.adjoint(X[c]) for c in range(n)]
     plan = m.Plan(nside, lmax, nrhs_max=n)
     dA, dX = tc(A), tc(X)
-    for name, prec, tol in (("fp64 matrix cores", m.CR_F64, 1e-10), ("bf16x3 matrix cores", m.CR_MIXED, MIXED_TOL)):
+    for name, prec, tol in (("fp64 matrix cores", m.CR_F64, 1e-10), ("bf16x3 matrix cores", m.CR_MIXED, MIXED_TOL),
+                            ("bf16x6 matrix cores", m.CR_BF16X6, 1e-6)):
         gm = m.synth(plan, dA, prec=prec).cpu().numpy()
         ga = m.adjoint(plan, dX, prec=prec).cpu().numpy()
         e = [rel(gm[c], ref_map[c]) for c in range(n)] + [rel(ga[c], ref_alm[c]) for c in range(n)]

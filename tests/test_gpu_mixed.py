@@ -1,5 +1,6 @@
 """GPU checks of the mixed-precision (bf16x3 MFMA, FP32 accumulation) Legendre
-step and of FP64 iterative refinement around it.
+step, of the bf16x6 user-visible transforms and of FP64 iterative refinement
+around the bf16x3 operator.
 
 The mixed transforms are an approximation with no closed form for their error
 (parity unpinned beyond the FP64 oracle): the measured relative error against
@@ -42,6 +43,67 @@ def test_mixed_transforms_against_oracle(nside, lmax, nrhs):
         worst = max(worst, e1, e2)
     print("mixed transform max rel err %.3e" % worst, flush=True)
     assert worst < MIXED_TOL
+
+
+# CR_BF16X6 (three bf16 parts per operand, six products): user-visible
+# transforms held to 1e-6 of the FP64 oracle (the contract of the user-visible
+# reduced-precision transforms; measured about 1e-7, the float32 inputs and
+# ring FFTs)
+BF16X6_TOL = 1e-6
+
+
+@pytest.mark.parametrize("nside,lmax,nrhs", [(4, 11, 1), (8, 23, 3), (32, 95, 2), (64, 191, 17), (128, 383, 1),
+                                             (6, 17, 2)])
+def test_bf16x6_transforms_against_oracle(nside, lmax, nrhs):
+    m = _m()
+    print("case bf16x6", nside, lmax, nrhs, flush=True)
+    plan = m.Plan(nside, lmax, nrhs_max=nrhs)
+    S = osht.SHT(nside, lmax)
+    rng = np.random.default_rng(100 + nside + nrhs)
+    A = np.stack([ci.white_alm(rng, lmax) for _ in range(nrhs)])
+    X = rng.standard_normal((nrhs, S.npix))
+    gm = m.synth(plan, tc(A), prec=m.CR_BF16X6).cpu().numpy()
+    ga = m.adjoint(plan, tc(X), prec=m.CR_BF16X6).cpu().numpy()
+    worst = 0.0
+    for c in range(nrhs):
+        worst = max(worst, rel(gm[c], S.synth(A[c])), rel(ga[c], S.adjoint(X[c])))
+    print("bf16x6 transform max rel err %.3e" % worst, flush=True)
+    assert worst < BF16X6_TOL
+    # the bf16x3 form afterwards is unchanged by the bf16x6 call (the split
+    # count is set for the call only)
+    g3 = m.synth(plan, tc(A), prec=m.CR_MIXED).cpu().numpy()
+    assert max(rel(g3[c], S.synth(A[c])) for c in range(nrhs)) > 3 * worst
+
+
+def test_bf16x6_operator_and_tqu():
+    m = _m()
+    nside = 32
+    wl, P, op, d = masked_problem(nside)
+    plan = m.Plan(nside, wl.lmax, nrhs_max=2)
+    gp = m.Problem(P.cl, P.bl, tc(P.ninv), 2)
+    rng = np.random.default_rng(14)
+    X = np.stack([op.project(ci.white_alm(rng, wl.lmax)) for _ in range(2)])
+    got = m.apply(plan, gp, tc(X), prec=m.CR_BF16X6).cpu().numpy()
+    for c in range(2):
+        e = real_rel(op, got[c], op.apply(X[c]))
+        print("bf16x6 operator rel err %.3e" % e, flush=True)
+        assert e < BF16X6_TOL
+    # T+Q+U: T, Q, U maps and T, E, B coefficients (the spin-2 combination
+    # divides by sin^2 theta >= 0.01 off the FP64 polar rings)
+    from oracle import cr_tqu
+    lmax = wl.lmax
+    Pt = cr_tqu.ProblemTQU(nside, lmax, ci.cl_tqu(lmax, wl.amp, 0.3), wl.bl(), P.ninv, P.ninv / 2.0)
+    opt = cr_tqu.CROperatorTQU(Pt)
+    a = opt.project(np.stack([ci.white_alm(rng, lmax) for _ in range(3)]))
+    plan3 = m.Plan(nside, lmax, ncomp=3)
+    gm = m.synth(plan3, tc(a), prec=m.CR_BF16X6).cpu().numpy()
+    ref = opt.synth(a)
+    M = rng.standard_normal((3, opt.sht.npix))
+    ga = m.adjoint(plan3, tc(M), prec=m.CR_BF16X6).cpu().numpy()
+    ra = opt.adjoint(M)
+    errs = [rel(gm[k], ref[k]) for k in range(3)] + [rel(ga[k], ra[k]) for k in range(3)]
+    print("bf16x6 T+Q+U rel errors", ["%.2e" % v for v in errs], flush=True)
+    assert max(errs) < 1e-5
 
 
 def test_mixed_operator_against_oracle():
