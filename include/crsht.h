@@ -605,7 +605,8 @@ int crsht_set_tuning(crsht_plan *plan, const crsht_tuning *in);
  * 0 = FP64 Legendre synthesis, 1 = FP64 Legendre adjoint (incl. the
  * preconditioner diagonal pass), 2 = fused ring pass (azimuthal FFTs with
  * N^-1, FP32: the mixed operator), 3 = bf16x3 MFMA Legendre synthesis,
- * 4 = bf16x3 MFMA Legendre adjoint, 5 = block preconditioner application,
+ * 4 = bf16x3 MFMA Legendre adjoint (bf16x6 launches are not tracked),
+ * 5 = block preconditioner application,
  * 6 = fused ring pass in FP64 (the FP64 operator). Ring passes of a lone
  * synthesis or adjoint are not tracked.
  * crsht_timing_read waits for the recorded events and returns the summed

@@ -430,11 +430,26 @@ int write_scalars(const crsht_plan* P, int nrhs, hipStream_t s) {
 }
 
 // true relative residual ||b - A x|| / ||b|| per column into rel[]; leaves r = b - A x
+// precisions of the user-visible transforms; CR_BF16X6 runs the mixed
+// kernels with three bf16 parts per operand for the duration of the call
+bool transform_prec(cr_prec prec) { return prec == CR_F64 || prec == CR_MIXED || prec == CR_BF16X6; }
+struct SplitScope {
+  const crsht_plan* P;
+  SplitScope(const crsht_plan* p, cr_prec prec) : P(p) { P->mx_split = prec == CR_BF16X6 ? 3 : 2; }
+  ~SplitScope() { P->mx_split = 2; }
+};
+
+// r = b - A x and the relative residuals; A in FP64, or (low) with the bf16x6
+// operator (about 5e-7 of ||A x||: for intermediate residual replacements
+// far above the tolerance)
 int true_residual(const crsht_plan* P, int nrhs, const double* ninv, const double2* x, const double2* b,
-                  double2* r, std::vector<double>& rel, hipStream_t s) {
+                  double2* r, std::vector<double>& rel, hipStream_t s, bool low = false) {
   const int64_t na = P->g.nalm;
   if (P->ncomp == 1) CR_TRY(launch_scale_alm(P, nrhs, x, P->w.bk, P->w.alm_a, s));
-  CR_CHECK(operator_core(P, nrhs, x, P->w.alm_a, ninv, P->w.cg_q, s));
+  {
+    SplitScope sc(P, low ? CR_BF16X6 : CR_F64);
+    CR_CHECK(operator_core(P, nrhs, x, P->w.alm_a, ninv, P->w.cg_q, s, low));
+  }
   CR_TRY(launch_residual(P, nrhs, b, P->w.cg_q, r, s));
   const int nb = vec_reduce_blocks(P);
   CR_TRY(launch_sum_rows(P, nrhs, nb, s));
@@ -610,9 +625,19 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
       if (sc[S_DONE] != 0.0 || sc[S_REL] <= itol * last[c]) need = true, trig[c] = 1;
     }
     if (need && pending && nrep < maxref) {
+      // an intermediate replacement, while no column claims convergence and
+      // every open column's residual is far above the reach of the bf16x6
+      // operator, takes that operator; the others (and every decision on
+      // convergence) take FP64
+      bool low = true;
+      for (int c = 0; c < nrhs; ++c) {
+        const double* sc = P->w.host_scal + c * kScalSlots;
+        if (sc[S_BREAK] != 0.0 || rel[c] <= tol) continue;
+        if (sc[S_DONE] != 0.0 || sc[S_REL] < kLowReplaceFloor) low = false;
+      }
       std::vector<double> keep(P->w.host_scal, P->w.host_scal + (size_t)nrhs * kScalSlots);
-      CR_CHECK(true_residual(P, nrhs, ninv, w.cg_x, w.cg_b, w.cg_r, rel, s));
-      fresh = true;
+      CR_CHECK(true_residual(P, nrhs, ninv, w.cg_x, w.cg_b, w.cg_r, rel, s, low));
+      fresh = !low;
       ++nrep;
       std::memcpy(P->w.host_scal, keep.data(), keep.size() * sizeof(double));
       bool cont = false;
@@ -630,7 +655,7 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
         sc[S_RESTART] = (trig[c] && (rel[c] >= last[c] || rel[c] > 4.0 * rec)) ? 1.0 : 0.0;
         last[c] = rel[c];
         refine[c] += 1;
-        if (rel[c] <= tol) {
+        if (rel[c] <= tol && !low) {
           sc[S_DONE] = 1.0;
         } else if (it < o->maxiter) {
           sc[S_DONE] = 0.0;
@@ -722,9 +747,12 @@ struct PredScope {
 
 // r = b - A x in FP64; ||r||^2, ||b||^2 into the column scalars (no read-back)
 int true_residual_dev(const crsht_plan* P, int nrhs, const double* ninv, const double2* x, const double2* b,
-                      double2* r, hipStream_t s) {
+                      double2* r, hipStream_t s, bool low = false) {
   if (P->ncomp == 1) CR_TRY(launch_scale_alm(P, nrhs, x, P->w.bk, P->w.alm_a, s));
-  CR_CHECK(operator_core(P, nrhs, x, P->w.alm_a, ninv, P->w.cg_q, s));
+  {
+    SplitScope sc(P, low ? CR_BF16X6 : CR_F64);
+    CR_CHECK(operator_core(P, nrhs, x, P->w.alm_a, ninv, P->w.cg_q, s, low));
+  }
   CR_TRY(launch_residual(P, nrhs, b, P->w.cg_q, r, s));
   CR_TRY(launch_sum_rows(P, nrhs, vec_reduce_blocks(P), s));
   return CR_OK;
@@ -762,6 +790,10 @@ int dsolve_check_replace(const DSolve& d, hipStream_t q, bool tail) {
   {
     PredScope ps(P, w.ctl + C_SKIP_REPL);
     CR_CHECK(true_residual_dev(P, d.nrhs, d.ninv, w.cg_x, w.cg_b, w.cg_r, q));
+  }
+  if (d.mixed) {
+    PredScope ps(P, w.ctl + C_SKIP_REPL_LOW);
+    CR_CHECK(true_residual_dev(P, d.nrhs, d.ninv, w.cg_x, w.cg_b, w.cg_r, q, true));
   }
   CR_TRY(launch_dctl(P, DC_AFTER_REPL, d.a, nullptr, q));
   if (!tail) return CR_OK;
@@ -1053,14 +1085,6 @@ int lnpi_terms_batch(const crsht_plan* P, int n, const double* ninv, const doubl
 }  // namespace
 
 // ============================================================== transforms
-// precisions of the user-visible transforms; CR_BF16X6 runs the mixed
-// kernels with three bf16 parts per operand for the duration of the call
-bool transform_prec(cr_prec prec) { return prec == CR_F64 || prec == CR_MIXED || prec == CR_BF16X6; }
-struct SplitScope {
-  const crsht_plan* P;
-  SplitScope(const crsht_plan* p, cr_prec prec) : P(p) { P->mx_split = prec == CR_BF16X6 ? 3 : 2; }
-  ~SplitScope() { P->mx_split = 2; }
-};
 
 extern "C" int sht_synth(const crsht_plan* P, int nrhs, const double* alm, double* map, cr_prec prec,
                          void* stream) {

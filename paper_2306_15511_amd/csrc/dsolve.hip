@@ -43,26 +43,36 @@ __global__ __launch_bounds__(kCtlThreads) void k_dctl(int mode, DctlArgs a, doub
     // a replacement is due when a column (not broken, not yet confirmed)
     // claims convergence or its recursive residual has fallen by itol since
     // its last replacement; only after the first block and within max_refine
+    // An intermediate replacement -- no open column claims convergence and
+    // every open column's recursive residual is at least kLowReplaceFloor --
+    // uses the bf16x6 operator (mixed form only); the others FP64.
     const bool exited = ctl[C_EXITED] != 0;
-    bool need = false;
+    bool need = false, high = false;
     for (int c = t; c < a.nrhs; c += kCtlThreads) {
       double* sc = scal + c * kScalSlots;
       bool trig = false;
-      if (!exited && sc[S_BREAK] == 0.0 && sc[S_TRUE] > a.tol)
+      if (!exited && sc[S_BREAK] == 0.0 && sc[S_TRUE] > a.tol) {
         trig = sc[S_DONE] != 0.0 || sc[S_REL] <= a.itol * sc[S_LAST];
+        high |= sc[S_DONE] != 0.0 || sc[S_REL] < kLowReplaceFloor;
+      }
       sc[S_TRIG] = trig ? 1.0 : 0.0;
       need |= trig;
     }
     need = block_any(need);
+    high = block_any(high);
     if (t == 0) {
       const bool go = !exited && need && ctl[C_PENDING] != 0 && ctl[C_NREP] < a.maxref;
-      ctl[C_SKIP_REPL] = go ? 0 : 1;
+      const bool low = go && !high && a.f64 == 0;
+      ctl[C_SKIP_REPL] = (go && !low) ? 0 : 1;
+      ctl[C_SKIP_REPL_LOW] = low ? 0 : 1;
+      ctl[C_LOW] = low ? 1 : 0;
       ctl[C_SKIP_TAIL] = go ? 0 : 1;
     }
     return;
   }
   if (mode == DC_AFTER_REPL) {
-    if (ctl[C_SKIP_REPL] != 0) return;
+    if (ctl[C_SKIP_REPL] != 0 && ctl[C_SKIP_REPL_LOW] != 0) return;
+    const bool low = ctl[C_LOW] != 0;   // a bf16x6 residual decides no convergence
     // the true residuals (k_sum_rows: AUX0 = ||b - Ax||^2, AUX1 = ||b||^2);
     // keep the direction only when the replacement corrects the recursive
     // residual by a small amount, restart it when the true residual did not
@@ -78,7 +88,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_dctl(int mode, DctlArgs a, doub
       sc[S_RESTART] = (sc[S_TRIG] != 0.0 && (rel >= sc[S_LAST] || rel > 4.0 * rec)) ? 1.0 : 0.0;
       sc[S_LAST] = rel;
       sc[S_REFINE] += 1.0;
-      if (rel <= a.tol) {
+      if (rel <= a.tol && !low) {
         sc[S_DONE] = 1.0;
       } else if (it < a.maxiter) {
         sc[S_DONE] = 0.0;
@@ -90,7 +100,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_dctl(int mode, DctlArgs a, doub
     cont = block_any(cont);
     if (t == 0) {
       ctl[C_NREP] += 1;
-      ctl[C_FRESH] = 1;
+      ctl[C_FRESH] = low ? 0 : 1;
       if (!cont) {
         ctl[C_EXITED] = 1;
         ctl[C_SKIP_TAIL] = 1;

@@ -173,8 +173,14 @@ enum CtlSlot {
   C_FRESH = 6,       // the true residuals are those of the current x
   C_PENDING = 7,     // a direction update is pending (after the first block)
   C_EXITED = 8,      // the solve has stopped; later sections are skipped
+  C_SKIP_REPL_LOW = 9,  // residual of a replacement with the bf16x6 operator (not needed at this check)
+  C_LOW = 10,        // the last replacement used the bf16x6 operator
   kCtlSlots = 16
 };
+// mixed refinement: an intermediate residual replacement (no column claims
+// convergence, every open column's recursive residual at least this) uses
+// the bf16x6 operator (relative error about 5e-7) instead of FP64
+constexpr double kLowReplaceFloor = 5e-5;
 // modes of the control kernel k_dctl
 enum DctlMode { DC_INIT = 0, DC_CHECK = 1, DC_AFTER_REPL = 2, DC_PRE_BLOCK = 3, DC_AFTER_BLOCK = 4, DC_FINAL_PRE = 5,
                 DC_FINAL_POST = 6 };

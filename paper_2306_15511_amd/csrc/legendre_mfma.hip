@@ -830,7 +830,8 @@ hipError_t synth_mfma_launch(const crsht_plan* P, int nr, int ns, const bf16x8* 
                              hipStream_t s) {
   const Geometry& g = P->g;
   dim3 gs(synth_mfma_blocks(g));
-  timing_begin(P, 3, s);
+  const int tid = ns == 3 ? -1 : 3;   // timed: the bf16x3 launches
+  timing_begin(P, tid, s);
 #define CRSHT_SYNTH_LAUNCH(NG, NS)                                                                                \
   hipLaunchKernelGGL((k_synth_mfma<NG, NS>), gs, dim3(256), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.pair_z,      \
                      P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.mx_cstart, ab, ab_group(g), eo,    \
@@ -842,7 +843,7 @@ hipError_t synth_mfma_launch(const crsht_plan* P, int nr, int ns, const bf16x8* 
   else
     CRSHT_SYNTH_LAUNCH(1, 2);
 #undef CRSHT_SYNTH_LAUNCH
-  timing_end(P, 3, s);
+  timing_end(P, tid, s);
   return hipGetLastError();
 }
 
@@ -913,7 +914,7 @@ hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const fl
                          geo_stride, ag, ag_group(g), P->pred);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    timing_begin(P, 4, s);
+    timing_begin(P, ns == 3 ? -1 : 4, s);   // timed: the bf16x3 launches
 #define CRSHT_ADJ_LAUNCH(NS)                                                                                       \
   hipLaunchKernelGGL((k_adj_mfma<1, NS>), dim3(8u * (unsigned)P->t.mx_maxq), dim3(kAdjWaves * 64), 0, s, g.lmax,   \
                      g.mmax, g.npairs, nr, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,        \
@@ -924,7 +925,7 @@ hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const fl
     else
       CRSHT_ADJ_LAUNCH(2);
 #undef CRSHT_ADJ_LAUNCH
-    timing_end(P, 4, s);
+    timing_end(P, ns == 3 ? -1 : 4, s);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
