@@ -527,6 +527,8 @@ def solve_line(args, tqu: bool, R: int, steps: int, warmup: int, compare: bool, 
         res["config"]["chain_amplitudes"] = [float(v) for v in amp[::2]]
     if pc_setup_s is not None:
         res["precond_setup_s"] = pc_setup_s
+        pb, nb, nh = plan.precond_info()
+        res["precond_storage"] = {"bytes": pb, "blocks": nb, "fp16_blocks": nh}
     if tuning is not None:
         res["tile_shapes"] = tuning
     if kernels:
@@ -621,11 +623,12 @@ def kernel_roofline(args, plan, one_solve, nside, lmax, R, nc, mixed, use_block,
                 sum((3 + 4 * g) * T for g in ga),
                 FP64_MATRIX_PEAK_TFLOPS if ca >= 2 else FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s", "legendre.hip")
     if use_block:
-        # stored inverses (FP32, sum of n^2 over the (m, parity) blocks of
-        # every component) + r read + z written
-        sn2 = sum(((lmax - m - q) // 2 + 1) ** 2 for m in range(lmax + 1) for q in (0, 1) if m + q <= lmax)
-        kinfo[5] = ("k_pc_apply (block preconditioner, FP32 MFMA)", "hbm",
-                    4 * sn2 * nc + 2 * R * plan.vlen * 16, HBM_PEAK_GBS, "GB/s", "blockpc.hip")
+        # the n x n entries of the stored scaled inverses (FP16 or FP32 per
+        # block, as the build chose) + their FP32 diagonal scales + r read +
+        # z written
+        pcb = plan.precond_info()[0]
+        kinfo[5] = ("k_pc_apply (block preconditioner, FP16/FP32 storage, FP32 MFMA)", "hbm",
+                    pcb + 4 * plan.vlen + 2 * R * plan.vlen * 16, HBM_PEAK_GBS, "GB/s", "blockpc.hip")
     roofs = {}
     for kid, (name, bound, work, peak, unit, src) in kinfo.items():
         ms, nl = tm[kid]

@@ -121,6 +121,10 @@ typedef struct {
   int nside, lmax, mmax, ncomp, nrhs_max, nrings;
   int64_t npix, nalm;
   int64_t workspace_bytes;   /* device memory owned by the plan */
+  int64_t precond_bytes;     /* bytes of the n x n entries of the stored
+                                block-preconditioner inverses, each read once
+                                per cr_block_precond_apply (0 if none is built) */
+  int precond_blocks, precond_half_blocks;   /* blocks stored, of which in FP16 */
 } crsht_info;
 
 /* Fill *info (host). */
@@ -239,9 +243,15 @@ int cr_precond(const crsht_plan *plan, const cr_problem *prob, double *diag, voi
  * l < lmin are the identity) is formed in FP64, inverted by Cholesky
  * factorisation (rocBLAS SYRK for the Gram matrices, rocSOLVER potrf/potri
  * for the factorisation and inverse, on blocks padded to multiples of 32
- * with the identity) and stored in FP32, full symmetric, in the plan (about
- * 2 (lmax + 1)^3 / 3 bytes; allocated by this call, freed with the plan or
- * by the next build). Built once per noise model, beam and spectrum shape,
+ * with the identity) and stored full symmetric in the plan as
+ * S C S, S = diag(M^-1)^1/2 (FP32), C with a unit diagonal in FP16 where a
+ * Cholesky factorisation of fl16(C) - 2 ||fl16(C) - C||_F I succeeds (the
+ * rounding then keeps C positive definite and moves the eigenvalues of the
+ * preconditioned operator by less than a factor 2, in practice by a few per
+ * cent), else in FP32 (low-m blocks of a masked sky); storage about
+ * 2 (lmax + 1)^3 / 3 bytes, crsht_info.precond_bytes of it read per
+ * application; allocated by this call, freed with the plan or by the next
+ * build. Built once per noise model, beam and spectrum shape,
  * it stays valid when the spectrum is rescaled (joint_cl_step): PCG only
  * needs a fixed symmetric positive definite preconditioner.
  * ncomp = 3: three sets of blocks, one per component, three times the

@@ -35,7 +35,8 @@ class CrshtError(RuntimeError):
 class _Info(ctypes.Structure):
     _fields_ = [("nside", ctypes.c_int), ("lmax", ctypes.c_int), ("mmax", ctypes.c_int), ("ncomp", ctypes.c_int),
                 ("nrhs_max", ctypes.c_int), ("nrings", ctypes.c_int), ("npix", ctypes.c_int64),
-                ("nalm", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
+                ("nalm", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64), ("precond_bytes", ctypes.c_int64),
+                ("precond_blocks", ctypes.c_int), ("precond_half_blocks", ctypes.c_int)]
 
 
 class _Problem(ctypes.Structure):
@@ -226,6 +227,13 @@ class Plan:
         self.vlen = self.ncomp * self.nalm      # coefficients per column
         self.mlen = self.ncomp * self.npix      # map values per column
         self.workspace_bytes = int(info.workspace_bytes)
+
+    def precond_info(self):
+        """(bytes of the stored block-preconditioner inverses one application
+        reads, blocks, blocks stored in FP16); zeros if none is built."""
+        info = _Info()
+        _check(_lib.crsht_plan_info(self._h, ctypes.byref(info)), "crsht_plan_info")
+        return int(info.precond_bytes), int(info.precond_blocks), int(info.precond_half_blocks)
 
     def alm_shape(self, nrhs: int):
         return (nrhs, self.nalm) if self.ncomp == 1 else (nrhs, self.ncomp, self.nalm)

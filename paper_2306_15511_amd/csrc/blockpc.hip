@@ -28,16 +28,18 @@
 // sqrt(W_P,p)] (E and B, twice as many columns), is written by a recurrence
 // kernel, the Gram matrix L L^T is formed with rocBLAS SYRK, the prior
 // diagonal added, and the inverse computed with rocSOLVER (Cholesky, then
-// inverse from the factor); the inverses are stored in FP32, full symmetric,
-// per block.
+// inverse from the factor); the inverses are stored Jacobi-scaled, full
+// symmetric, per block in FP16 where that provably keeps them positive
+// definite, else in FP32 (see k_pc_store).
 // Application (every PCG iteration): z_b = M_b^-1 r_b for the real and
 // imaginary parts of every column and every block of every component on the
-// matrix cores (FP32), one workgroup per 256 rows of a block (128 per
-// wavefront).
+// matrix cores (FP32 products), one workgroup per 128 rows of both parity
+// blocks of one m (one wavefront each).
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "internal.h"
@@ -173,83 +175,148 @@ __global__ void k_pc_fix(const int* __restrict__ blocks, const int* __restrict__
     *c += sinv_l[(size_t)sstride * l];
 }
 
-// Inverse (lower triangle from potri) -> full symmetric FP32 n x n per block
-// (leading dimension pc_ld(n)).
+// Storage of an inverse: with S = diag(sqrt(M^-1_ii)), the Jacobi-scaled
+// C = S^-1 M^-1 S^-1 has a unit diagonal and, M^-1 being positive definite,
+// entries in [-1, 1]; the plan keeps S per vector element (FP32) and C per
+// block, full symmetric, n rows of pc_ld(n) entries at the block's float
+// offset boff, in FP32 or, where rounding to FP16 provably keeps it positive
+// definite with room to spare, in FP16 (half the bytes the application
+// streams on every iteration). Test of a block: with E = fl16(C) - C,
+// ||E||_2 <= ||E||_F, so if fl16(C) - kHalfMargin ||E||_F I is still positive
+// definite (a Cholesky factorisation of it succeeds), the smallest
+// eigenvalue of C exceeds (kHalfMargin - 1) ||E||_F >= ||E||_2: the rounding
+// moves every eigenvalue of the preconditioned operator by a factor within
+// (1 - d, 1 + d), d = ||E||_2 / lambda_min(C) < 1 / (kHalfMargin - 1), and
+// in practice (||E||_2 ~ ||E||_F / 10 for these blocks) by a few per cent.
+// Low-m blocks of a masked sky, whose smallest eigenvalues of C fall to
+// 1e-5 (well-measured modes), stay in FP32.
+constexpr double kHalfMargin = 2.0;
+
+// From the inverse (lower triangle from potri, npad x npad column-major per
+// batch entry): the FP32 scaled block and S; the lower triangle of
+// fl16(C) (padding: the identity) in T for the positivity test, and
+// ||fl16(C) - C||_F^2 summed into err2 per batch entry.
 __global__ void k_pc_store(const int* __restrict__ blocks, const int* __restrict__ bn,
-                           const int64_t* __restrict__ boff, int npad, const double* __restrict__ C,
-                           float* __restrict__ inv) {
+                           const int64_t* __restrict__ boff, const int64_t* __restrict__ be0, int npad,
+                           const double* __restrict__ C, float* __restrict__ inv, float* __restrict__ scale,
+                           double* __restrict__ T, double* __restrict__ err2) {
+  __shared__ double sh[256];
   const int blk = blocks[blockIdx.z];
   const int n = bn[blk];
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
-  if (i >= n || j >= n) return;
   const double* c = C + (size_t)blockIdx.z * npad * npad;
-  const double v = i >= j ? c[(size_t)j * npad + i] : c[(size_t)i * npad + j];
-  inv[boff[blk] + (size_t)j * pc_ld(n) + i] = (float)v;
+  double* t = T + (size_t)blockIdx.z * npad * npad;
+  double e2 = 0.0;
+  if (i < npad) {
+    if (i < n && j < n) {
+      const double v = i >= j ? c[(size_t)j * npad + i] : c[(size_t)i * npad + j];
+      const double si = sqrt(c[(size_t)i * npad + i]), sj = sqrt(c[(size_t)j * npad + j]);
+      const double cs = v / (si * sj);
+      const double h = (double)(_Float16)cs;
+      inv[boff[blk] + (size_t)j * pc_ld(n) + i] = (float)cs;
+      if (i == j) scale[be0[blk] + 2 * (int64_t)i] = (float)si;
+      if (i >= j) t[(size_t)j * npad + i] = h;
+      e2 = (h - cs) * (h - cs);
+    } else if (i >= j) {
+      t[(size_t)j * npad + i] = i == j ? 1.0 : 0.0;
+    }
+  }
+  e2 = block_sum(e2, sh);
+  if (threadIdx.x == 0 && e2 > 0.0) atomicAdd(err2 + blockIdx.z, e2);
 }
 
-// z = M^-1 r for the two parity blocks of one m (one component) and 16
-// right-hand sides (32 real columns) on the matrix cores
+// T_ii -= kHalfMargin ||E||_F on the block's rows (not the padding)
+__global__ void k_pc_shift(const int* __restrict__ blocks, const int* __restrict__ bn, int npad,
+                           const double* __restrict__ err2, double* __restrict__ T) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= bn[blocks[blockIdx.y]]) return;
+  T[(size_t)blockIdx.y * npad * npad + (size_t)i * npad + i] -= kHalfMargin * sqrt(err2[blockIdx.y]);
+}
+
+// Blocks whose test factorisation succeeded: FP16 over the front half of
+// their FP32 storage (rows of pc_ld(n) halves, padding columns zero), and
+// the per-block flag.
+__global__ void k_pc_half(const int* __restrict__ blocks, const int* __restrict__ bn,
+                          const int64_t* __restrict__ boff, int npad, const double* __restrict__ C,
+                          const int* __restrict__ info, float* __restrict__ inv, int* __restrict__ bhalf) {
+  const int blk = blocks[blockIdx.z];
+  const int n = bn[blk], ld = pc_ld(n);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  const bool half = info[blockIdx.z] == 0;
+  if (i == 0 && j == 0) bhalf[blk] = half ? 1 : 0;
+  if (!half || i >= ld || j >= n) return;
+  _Float16 h = (_Float16)0.0f;
+  if (i < n) {
+    const double* c = C + (size_t)blockIdx.z * npad * npad;
+    const double v = i >= j ? c[(size_t)j * npad + i] : c[(size_t)i * npad + j];
+    const double si = sqrt(c[(size_t)i * npad + i]), sj = sqrt(c[(size_t)j * npad + j]);
+    h = (_Float16)(v / (si * sj));
+  }
+  reinterpret_cast<_Float16*>(inv + boff[blk])[(size_t)j * ld + i] = h;
+}
+
+// z = M^-1 r = S C S r for the two parity blocks of one m (one component)
+// and 16 right-hand sides (32 real columns) on the matrix cores
 // (v_mfma_f32_32x32x2_f32). A workgroup takes rows [r0, r0 + 128) of both
 // blocks: wavefront w of block b_w (b_0: l - m even, b_1: odd, -1 if absent).
 // The two blocks' coefficients interleave in the vectors, so the workgroup
 // stages one contiguous residual range for both (coalesced loads) and both
 // wavefronts' results fill the same memory sectors close in time. Per K step
-// (rows j, j + 1 of the symmetric M^-1) lane l of half h loads the float4
-// M^-1[j + h][i0 + 4 l .. i0 + 4 l + 3], so one load instruction reads two
-// contiguous 512-byte runs; component v of it is the A operand of the v-th of
-// four MFMAs whose 32 output rows are i0 + 4 t + v (t = 0 .. 31), each with
-// its own accumulator. The B operand R[j + h][c] comes from an LDS tile of
-// kPcJ rows j per parity (FP32; rows padded to 33 floats so the staging
-// writes spread over the banks). The A loads of the next kPcPre K steps are in
-// flight while the current ones are multiplied.
+// (rows j, j + 1 of the symmetric C) lane l of half h loads the four
+// C[j + h][i0 + 4 l .. i0 + 4 l + 3] (FP32 or FP16 per block, a
+// wavefront-uniform choice), so one load instruction reads two contiguous
+// 512-byte (FP16: 256-byte) runs; component v of it (as FP32) is the A
+// operand of the v-th of four MFMAs whose 32 output rows are i0 + 4 t + v
+// (t = 0 .. 31), each with its own accumulator. The B operand R[j + h][c]
+// comes from an LDS tile of kPcJ rows j per parity (FP32 S r; rows padded to
+// 33 floats so the staging writes spread over the banks). The A loads of the
+// next prefetch group (kPcPre K steps; twice as many for FP16) are in flight
+// while the current ones are multiplied; the results are scaled by S as they
+// are written.
 // MFMA 32x32x2 f32 lane layout: A[i][k] in lane i + 32 k, B[k][c] in lane
 // c + 32 k, D[i][c] in lane c + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4.
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef _Float16 f16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 constexpr int kPcPre = 4;          // K steps per prefetch group
-// (three wavefronts per SIMD: more loads in flight per CU)
-__global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_pc_apply(
-    int nrhs, int64_t vlen, const int64_t* __restrict__ be0, const int* __restrict__ task_b,
-    const int* __restrict__ task_b1, const int* __restrict__ task_r0, const int* __restrict__ bn,
-    const int64_t* __restrict__ boff, const float* __restrict__ inv, const double2* __restrict__ r,
-    double2* __restrict__ z, const int* __restrict__ pred) {
-  if (pred && *pred) return;
+
+// One wavefront's part of k_pc_apply: rows [i0, i0 + 128) of its block
+// (FP16 or FP32 storage) against the staged residual tiles, then the
+// results. The A operands stay in their storage type while in flight and are
+// widened to FP32 at the products.
+template <bool H16>
+__device__ __forceinline__ void pc_apply_wave(const typename std::conditional<H16, _Float16, float>::type* __restrict__ Ab,
+                                              int nrhs, int64_t vlen, const float* __restrict__ scale,
+                                              const double2* __restrict__ r, double2* __restrict__ z,
+                                              float (*rs)[kPcJ][33], int w, int il, int kk, int n, int n0, int n1,
+                                              int ld, int i0, int64_t e00) {
+  using Vec = typename std::conditional<H16, f16x4_t, f32x4_t>::type;
+  // K steps per prefetch group: twice as many for FP16, the same bytes in flight
+  constexpr int kPre = H16 ? 2 * kPcPre : kPcPre;
+  static_assert((kPcJ / 2) % kPre == 0, "tile must hold whole prefetch groups");
   constexpr int kSteps = kPcJ / 2;                          // K steps per LDS tile
   constexpr int kR = 2 * kPcJ * kPcCols / (kPcWaves * 64);  // residual values staged per thread and tile
-  static_assert(kSteps % kPcPre == 0, "tile must hold whole prefetch groups");
-  static_assert(kR % 4 == 0, "residual staging in batches of 4");
-  static_assert(kPcWaves == 2, "one wavefront per parity block");
-  __shared__ float rs[2][kPcJ][33];
-  const int b0 = task_b[blockIdx.x];
-  if (b0 < 0) return;   // padding task (uniform per workgroup, before any barrier)
-  const int b1 = task_b1[blockIdx.x];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int b = w == 0 ? b0 : b1;
-  const int n0 = bn[b0];                                    // the even block is the larger one
-  const int n1 = b1 >= 0 ? bn[b1] : 0;
-  const int n = w == 0 ? n0 : n1;
-  const int ld = pc_ld(n);
-  const int il = lane & 31, kk = lane >> 5;
-  const int i0 = task_r0[blockIdx.x];
-  const int ic = i0 + 4 * il;                               // first of this lane's 4 rows
-  const bool colok = ic < ld;                               // padding rows n .. ld - 1 hold zeros
-  const int64_t e00 = be0[b0];                              // element of row j of block q: e00 + q + 2 j
-  const float* __restrict__ Ab = inv + (b >= 0 ? boff[b] : 0) + (colok ? ic : 0);
   const int ntile = (n0 + kPcJ - 1) / kPcJ;
   for (int c0 = 0; c0 < nrhs; c0 += kPcCols) {
     const int nc = min(kPcCols, nrhs - c0);
     f32x16_t acc0 = {}, acc1 = {}, acc2 = {}, acc3 = {};
-    // groups of kPcPre K steps over all j; a new LDS tile every kSteps / kPcPre
+    // groups of kPre K steps over all j; a new LDS tile every kSteps / kPre
     // groups; the A operands of group G + 1 are requested before the products of G
-    constexpr int kGpt = kSteps / kPcPre;
+    constexpr int kGpt = kSteps / kPre;
     const int ngrp = ntile * kGpt;
-    const bool live = colok && i0 < n;
-    float4 an[kPcPre];
+    // Loads without per-lane conditions (a branch around each load defeats
+    // the overlap of the next group's loads with this group's products):
+    // rows j >= n read row n - 1 and lanes past the padded row width read
+    // columns 0 .. 3, all finite entries whose products meet zero B operands
+    // (rows j >= n of the staged tile) or land in output rows never written.
+    Vec an[kPre] = {};
     auto fetch = [&](int G) {
-      const int jg = 2 * G * kPcPre + kk;
+      if (i0 >= n) return;   // wavefront-uniform: no rows of this block here
+      const int jg = 2 * G * kPre + kk;
 #pragma unroll
-      for (int u = 0; u < kPcPre; ++u) {
-        const int j = jg + 2 * u;
-        an[u] = (live && j < n) ? *reinterpret_cast<const float4*>(Ab + (size_t)j * ld) : make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int u = 0; u < kPre; ++u) {
+        const int j = min(jg + 2 * u, n - 1);
+        an[u] = *reinterpret_cast<const Vec*>(Ab + (size_t)j * ld);
       }
     };
     fetch(0);
@@ -264,6 +331,7 @@ __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3
 #pragma unroll 1
         for (int k0 = 0; k0 < kR; k0 += 4) {
           double2 v[4];
+          float sv[4];
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             const int e = threadIdx.x + (k0 + k) * kPcWaves * 64;
@@ -271,30 +339,31 @@ __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3
             const int q = ee & 1, j = j0 + (ee >> 1);
             const bool in = cc < nc && j < (q ? n1 : n0);
             v[k] = in ? r[(int64_t)(c0 + cc) * vlen + e00 + 2 * j0 + ee] : make_double2(0.0, 0.0);
+            sv[k] = in ? scale[e00 + 2 * j0 + ee] : 0.f;
           }
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             const int e = threadIdx.x + (k0 + k) * kPcWaves * 64;
             const int ee = e % (2 * kPcJ), cc = e / (2 * kPcJ);
             const int q = ee & 1, jj = ee >> 1;
-            rs[q][jj][2 * cc] = (float)v[k].x;
-            rs[q][jj][2 * cc + 1] = (float)v[k].y;
+            rs[q][jj][2 * cc] = (float)(v[k].x * sv[k]);
+            rs[q][jj][2 * cc + 1] = (float)(v[k].y * sv[k]);
           }
         }
         __syncthreads();
       }
-      float4 ac[kPcPre];
+      Vec ac[kPre];
 #pragma unroll
-      for (int u = 0; u < kPcPre; ++u) ac[u] = an[u];
+      for (int u = 0; u < kPre; ++u) ac[u] = an[u];
       if (G + 1 < ngrp) fetch(G + 1);
       if (i0 < n) {
 #pragma unroll
-        for (int u = 0; u < kPcPre; ++u) {
-          const float bval = rs[w][2 * (g0 * kPcPre + u) + kk][il];
-          acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[u].x, bval, acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[u].y, bval, acc1, 0, 0, 0);
-          acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[u].z, bval, acc2, 0, 0, 0);
-          acc3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[u].w, bval, acc3, 0, 0, 0);
+        for (int u = 0; u < kPre; ++u) {
+          const float bval = rs[w][2 * (g0 * kPre + u) + kk][il];
+          acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32((float)ac[u][0], bval, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32((float)ac[u][1], bval, acc1, 0, 0, 0);
+          acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32((float)ac[u][2], bval, acc2, 0, 0, 0);
+          acc3 = __builtin_amdgcn_mfma_f32_32x32x2f32((float)ac[u][3], bval, acc3, 0, 0, 0);
         }
       }
     }
@@ -326,11 +395,49 @@ __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3
         const int c = h + cc, q = er & 1, row = i0 + (er >> 1);
         if (c < nc && row < (q ? n1 : n0)) {
           const float* v = stage + idx * 2;
-          z[(int64_t)(c0 + c) * vlen + e00 + 2 * i0 + er] = make_double2((double)v[0], (double)v[1]);
+          const double sr = (double)scale[e00 + 2 * i0 + er];
+          z[(int64_t)(c0 + c) * vlen + e00 + 2 * i0 + er] = make_double2(sr * (double)v[0], sr * (double)v[1]);
         }
       }
     }
   }
+}
+
+// (three wavefronts per SIMD: more loads in flight per CU)
+__global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_pc_apply(
+    int nrhs, int64_t vlen, const int64_t* __restrict__ be0, const int* __restrict__ task_b,
+    const int* __restrict__ task_b1, const int* __restrict__ task_r0, const int* __restrict__ bn,
+    const int64_t* __restrict__ boff, const int* __restrict__ bhalf, const float* __restrict__ inv,
+    const float* __restrict__ scale, const double2* __restrict__ r, double2* __restrict__ z,
+    const int* __restrict__ pred) {
+  if (pred && *pred) return;
+  constexpr int kSteps = kPcJ / 2;                          // K steps per LDS tile
+  constexpr int kR = 2 * kPcJ * kPcCols / (kPcWaves * 64);  // residual values staged per thread and tile
+  static_assert(kSteps % kPcPre == 0, "tile must hold whole prefetch groups");
+  static_assert(kR % 4 == 0, "residual staging in batches of 4");
+  static_assert(kPcWaves == 2, "one wavefront per parity block");
+  __shared__ float rs[2][kPcJ][33];
+  const int b0 = task_b[blockIdx.x];
+  if (b0 < 0) return;   // padding task (uniform per workgroup, before any barrier)
+  const int b1 = task_b1[blockIdx.x];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int b = w == 0 ? b0 : b1;
+  const int n0 = bn[b0];                                    // the even block is the larger one
+  const int n1 = b1 >= 0 ? bn[b1] : 0;
+  const int n = w == 0 ? n0 : n1;
+  const int ld = pc_ld(n);
+  const int il = lane & 31, kk = lane >> 5;
+  const int i0 = task_r0[blockIdx.x];
+  const int ic = i0 + 4 * il;                               // first of this lane's 4 rows
+  const bool colok = ic < ld;                               // padding columns n .. ld - 1 hold zeros
+  const int64_t e00 = be0[b0];                              // element of row j of block q: e00 + q + 2 j
+  const float* __restrict__ base = inv + (b >= 0 ? boff[b] : 0);
+  // the two wavefronts may take different storage types; both pass the same barriers
+  if (b >= 0 && bhalf[b])
+    pc_apply_wave<true>(reinterpret_cast<const _Float16*>(base) + (colok ? ic : 0), nrhs, vlen, scale, r, z, rs,
+                        w, il, kk, n, n0, n1, ld, i0, e00);
+  else
+    pc_apply_wave<false>(base + (colok ? ic : 0), nrhs, vlen, scale, r, z, rs, w, il, kk, n, n0, n1, ld, i0, e00);
 }
 
 // partial <r, z> (row 0) and, with rr, <r, r> (row 1) per column
@@ -377,7 +484,7 @@ int dev_upload(T** p, const std::vector<T>& h) {
 }  // namespace
 
 void block_pc_free(BlockPC& pc) {
-  void* ptrs[] = {pc.inv, pc.bm, pc.bq, pc.bn, pc.boff, pc.be0, pc.task_b, pc.task_b1, pc.task_r0};
+  void* ptrs[] = {pc.inv, pc.scale, pc.bhalf, pc.bm, pc.bq, pc.bn, pc.boff, pc.be0, pc.task_b, pc.task_b1, pc.task_r0};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   pc = BlockPC();
@@ -467,7 +574,8 @@ int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
   int rc;
   if ((rc = dev_upload(&pc.bm, bm)) || (rc = dev_upload(&pc.bq, bq)) || (rc = dev_upload(&pc.bn, bn)) ||
       (rc = dev_upload(&pc.boff, boff)) || (rc = dev_upload(&pc.be0, be0)) || (rc = dev_upload(&pc.task_b, tb)) || (rc = dev_upload(&pc.task_b1, tb1)) ||
-      (rc = dev_upload(&pc.task_r0, tr)) || (rc = dev_alloc(&pc.inv, (size_t)off))) {
+      (rc = dev_upload(&pc.task_r0, tr)) || (rc = dev_alloc(&pc.inv, (size_t)off)) ||
+      (rc = dev_alloc(&pc.scale, (size_t)ncomp * g.nalm)) || (rc = dev_alloc(&pc.bhalf, (size_t)nb))) {
     block_pc_free(pc);
     return rc;
   }
@@ -475,7 +583,8 @@ int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
   pc.ntasks = (int)tb.size();
   pc.inv_elems = off;
   // padding columns n .. ld - 1 of every row stay zero (read by the application kernel)
-  if (hipMemsetAsync(pc.inv, 0, (size_t)off * sizeof(float), s) != hipSuccess) {
+  if (hipMemsetAsync(pc.inv, 0, (size_t)off * sizeof(float), s) != hipSuccess ||
+      hipMemsetAsync(pc.bhalf, 0, (size_t)nb * sizeof(int), s) != hipSuccess) {
     block_pc_free(pc);
     return CR_EDEVICE;
   }
@@ -483,12 +592,12 @@ int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
   // per-l inputs left on the device by the problem set-up: b_l (row 2 of
   // perl) and the priors (perl row 0 = 1/C_l; T+Q+U: sblk entries TT, EE, BB)
   const double* dbl = P->w.perl + 2 * (lmax + 1);
-  double *L = nullptr, *C = nullptr;
-  int *dblocks = nullptr, *dinfo = nullptr;
+  double *L = nullptr, *C = nullptr, *T = nullptr, *err2 = nullptr;
+  int *dblocks = nullptr, *dinfo = nullptr, *dinfo2 = nullptr;
   rocblas_handle h = nullptr;
   auto cleanup = [&]() {
     if (h) (void)rocblas_destroy_handle(h);
-    void* ptrs[] = {L, C, dblocks, dinfo};
+    void* ptrs[] = {L, C, T, err2, dblocks, dinfo, dinfo2};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
   };
@@ -508,8 +617,9 @@ int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
     maxC = std::max(maxC, cnt * npad * npad * kmax);
     maxb = std::max(maxb, cnt * kmax);
   }
-  if ((rc = dev_alloc(&L, maxL)) || (rc = dev_alloc(&C, maxC)) || (rc = dev_alloc(&dblocks, maxb)) ||
-      (rc = dev_alloc(&dinfo, maxb))) {
+  if ((rc = dev_alloc(&L, maxL)) || (rc = dev_alloc(&C, maxC)) || (rc = dev_alloc(&T, maxC)) ||
+      (rc = dev_alloc(&err2, maxb)) || (rc = dev_alloc(&dblocks, maxb)) || (rc = dev_alloc(&dinfo, maxb)) ||
+      (rc = dev_alloc(&dinfo2, maxb))) {
     cleanup();
     block_pc_free(pc);
     return rc;
@@ -591,9 +701,21 @@ int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
         if (status != CR_OK) break;
         ok = rocsolver_dpotri_strided_batched(h, rocblas_fill_lower, npad, C, npad, (rocblas_stride)csz, dinfo,
                                               nbat) == rocblas_status_success;
+        // FP32 scaled storage, then the FP16 test (a Cholesky factorisation of
+        // fl16(C) - kHalfMargin ||E||_F I) and FP16 storage where it succeeds
+        ok = ok && hipMemsetAsync(err2, 0, (size_t)nbat * sizeof(double), s) == hipSuccess;
         if (ok) {
           hipLaunchKernelGGL(k_pc_store, dim3((npad + 255) / 256, npad, nbat), dim3(256), 0, s, dblocks, pc.bn,
-                             pc.boff, npad, C, pc.inv);
+                             pc.boff, pc.be0, npad, C, pc.inv, pc.scale, T, err2);
+          hipLaunchKernelGGL(k_pc_shift, dim3((npad + 255) / 256, nbat), dim3(256), 0, s, dblocks, pc.bn, npad,
+                             err2, T);
+          ok = hipGetLastError() == hipSuccess;
+        }
+        ok = ok && rocsolver_dpotrf_strided_batched(h, rocblas_fill_lower, npad, T, npad, (rocblas_stride)csz,
+                                                    dinfo2, nbat) == rocblas_status_success;
+        if (ok) {
+          hipLaunchKernelGGL(k_pc_half, dim3((npad + 255) / 256, npad, nbat), dim3(256), 0, s, dblocks, pc.bn,
+                             pc.boff, npad, C, dinfo2, pc.inv, pc.bhalf);
           ok = hipGetLastError() == hipSuccess;
         }
         ok = ok && hipStreamSynchronize(s) == hipSuccess;   // scratch is reused by the next batch
@@ -606,6 +728,18 @@ int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
     block_pc_free(pc);
     return status;
   }
+  // bytes of the n x n entries of the stored inverses (one application reads each once)
+  std::vector<int> hh(nb);
+  if (hipMemcpy(hh.data(), pc.bhalf, nb * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+    block_pc_free(pc);
+    return CR_EDEVICE;
+  }
+  pc.stored_bytes = 0;
+  pc.nhalf = 0;
+  for (int b = 0; b < nb; ++b) {
+    pc.stored_bytes += (int64_t)bn[b] * bn[b] * (hh[b] ? 2 : 4);
+    pc.nhalf += hh[b] ? 1 : 0;
+  }
   pc.built = true;
   pc.lmin = lmin;
   return CR_OK;
@@ -615,7 +749,7 @@ hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, doub
   const BlockPC& pc = P->pc;
   timing_begin(P, 5, s);
   hipLaunchKernelGGL(k_pc_apply, dim3(pc.ntasks), dim3(kPcWaves * 64), 0, s, nrhs, vlen(P), pc.be0, pc.task_b,
-                     pc.task_b1, pc.task_r0, pc.bn, pc.boff, pc.inv, r, z, P->pred);
+                     pc.task_b1, pc.task_r0, pc.bn, pc.boff, pc.bhalf, pc.inv, pc.scale, r, z, P->pred);
   timing_end(P, 5, s);
   return hipGetLastError();
 }

@@ -211,17 +211,23 @@ struct Timing {
 
 namespace crsht {
 // Per-m block preconditioner (blockpc.hip): for each (m, parity q of l - m)
-// block of n rows l = m + q + 2 i, the FP32 inverse n x n (full symmetric) at
-// inv + boff[b]; application tasks cover 128 rows of both parity blocks of
-// one m (task_b: even block, task_b1: odd block or -1).
+// block of n rows l = m + q + 2 i, the inverse M^-1 = S C S with S =
+// diag(sqrt(M^-1_ii)): C (unit diagonal, |C_ij| <= 1) stored in FP16, full
+// symmetric, at inv + boff[b], and sqrt(M^-1_ii) in FP32 per vector element
+// (scale); application tasks cover 128 rows of both parity blocks of one m
+// (task_b: even block, task_b1: odd block or -1).
 struct BlockPC {
   bool built = false;
   int lmin = 0;
   int nblocks = 0, ntasks = 0;
-  int64_t inv_elems = 0;
-  float* inv = nullptr;
+  int64_t inv_elems = 0;     // floats of storage (every block sized for FP32)
+  int64_t stored_bytes = 0;  // bytes of the n x n entries of the stored inverses
+  int nhalf = 0;             // blocks stored in FP16
+  float* inv = nullptr;      // Jacobi-scaled inverses, FP32 or FP16 per block
+  float* scale = nullptr;    // [ncomp * nalm] sqrt of the inverse's diagonal, per vector element
+  int* bhalf = nullptr;      // per block: 1 if stored in FP16
   int *bm = nullptr, *bq = nullptr, *bn = nullptr;
-  int64_t* boff = nullptr;   // first FP32 element of each stored inverse
+  int64_t* boff = nullptr;   // float offset of each stored inverse
   int64_t* be0 = nullptr;    // vector element of row 0 of each block (component offset included)
   int *task_b = nullptr, *task_b1 = nullptr, *task_r0 = nullptr;
 };

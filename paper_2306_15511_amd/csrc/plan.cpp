@@ -491,6 +491,9 @@ extern "C" int crsht_plan_info(const crsht_plan* P, crsht_info* info) {
   info->npix = P->g.npix;
   info->nalm = P->g.nalm;
   info->workspace_bytes = P->workspace_bytes_;
+  info->precond_bytes = P->pc.built ? P->pc.stored_bytes : 0;
+  info->precond_blocks = P->pc.built ? P->pc.nblocks : 0;
+  info->precond_half_blocks = P->pc.built ? P->pc.nhalf : 0;
   return CR_OK;
 }
 

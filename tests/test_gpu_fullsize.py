@@ -128,7 +128,7 @@ def test_block_preconditioner_large_blocks():
     got = m.block_precond_apply(plan, tc(Rr)).cpu().numpy()
     worst = max(real_rel(op, got[c], pc(Rr[c])) for c in (0, 5, 15))
     print("block pc max rel err %.3e" % worst, flush=True)
-    assert worst < 1e-5
+    assert worst < 2e-3   # FP16 storage (where the factorisation test allows) of the unit-diagonal scaled inverses
     plan.close()
 
 
