@@ -326,23 +326,30 @@ __device__ __forceinline__ void pc_apply_wave(const typename std::conditional<H1
       if (g0 == 0) {
         const int j0 = (G / kGpt) * kPcJ;
         __syncthreads();                                    // previous tile's products have read rs
-        // consecutive threads read consecutive coefficients (both parities);
-        // in batches of 4 to bound the registers held by loads in flight
+        // consecutive threads read consecutive coefficients (both parities),
+        // in batches of kStage to bound the registers held by loads in
+        // flight; the loads carry no per-lane condition (elements outside the
+        // blocks or columns read element e00 of column c0 and are zeroed by
+        // their scale factor), so each batch's loads are in flight together
+        constexpr int kStage = 4;
+        static_assert(kR % kStage == 0, "whole staging batches");
 #pragma unroll 1
-        for (int k0 = 0; k0 < kR; k0 += 4) {
-          double2 v[4];
-          float sv[4];
+        for (int k0 = 0; k0 < kR; k0 += kStage) {
+          double2 v[kStage];
+          float sv[kStage];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
+          for (int k = 0; k < kStage; ++k) {
             const int e = threadIdx.x + (k0 + k) * kPcWaves * 64;
             const int ee = e % (2 * kPcJ), cc = e / (2 * kPcJ);
             const int q = ee & 1, j = j0 + (ee >> 1);
             const bool in = cc < nc && j < (q ? n1 : n0);
-            v[k] = in ? r[(int64_t)(c0 + cc) * vlen + e00 + 2 * j0 + ee] : make_double2(0.0, 0.0);
-            sv[k] = in ? scale[e00 + 2 * j0 + ee] : 0.f;
+            const int64_t el = in ? e00 + 2 * j0 + ee : e00;
+            v[k] = r[(int64_t)(c0 + (in ? cc : 0)) * vlen + el];
+            sv[k] = scale[el];
+            sv[k] = in ? sv[k] : 0.f;
           }
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
+          for (int k = 0; k < kStage; ++k) {
             const int e = threadIdx.x + (k0 + k) * kPcWaves * 64;
             const int ee = e % (2 * kPcJ), cc = e / (2 * kPcJ);
             const int q = ee & 1, jj = ee >> 1;
@@ -388,14 +395,23 @@ __device__ __forceinline__ void pc_apply_wave(const typename std::conditional<H1
         }
       }
       __syncthreads();
+      // this thread's coefficients are the same for every column: their
+      // scales are read once, without per-lane conditions
+      constexpr int kOut = 8 * 256 / (kPcWaves * 64);
+      float so[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int er = (threadIdx.x + t * kPcWaves * 64) & 255, q = er & 1, row = i0 + (er >> 1);
+        so[t] = scale[row < (q ? n1 : n0) ? e00 + 2 * i0 + er : e00];
+      }
 #pragma unroll 4
-      for (int k = 0; k < 8 * 256 / (kPcWaves * 64); ++k) {
+      for (int k = 0; k < kOut; ++k) {
         const int idx = threadIdx.x + k * kPcWaves * 64;
         const int cc = idx >> 8, er = idx & 255;
         const int c = h + cc, q = er & 1, row = i0 + (er >> 1);
         if (c < nc && row < (q ? n1 : n0)) {
           const float* v = stage + idx * 2;
-          const double sr = (double)scale[e00 + 2 * i0 + er];
+          const double sr = (double)so[k & 1];
           z[(int64_t)(c0 + c) * vlen + e00 + 2 * i0 + er] = make_double2(sr * (double)v[0], sr * (double)v[1]);
         }
       }
