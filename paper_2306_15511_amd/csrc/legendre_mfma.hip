@@ -285,25 +285,39 @@ __global__ __launch_bounds__(64) void k_pupdate_prep(int lmax, int nrhs, int64_t
   const int st = c * kSynChunk + (lane & 31);
   const bool live = st < nsteps;
   const double f = live ? bk[base + st] : 0.0;
+  // every load first and without per-lane conditions (a load under one is
+  // waited for at once): elements outside the chunk or the columns read the
+  // m's first element of column 0, and their values are not used
+  double2 pv[8], zv[8];
+  double done[8], beta[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int rhs = (lane >> 5) + 2 * i;
-    double2 pv = make_double2(0.0, 0.0);
+    const bool ok = rhs < nrhs && live;
+    const int64_t e = ok ? rhs * nalm + base + st : base;
+    pv[i] = p[e];
+    if (update) {
+      zv[i] = z[e];
+      const double* sc = scal + (ok ? rhs : 0) * kScalSlots;
+      done[i] = sc[S_DONE];
+      beta[i] = sc[S_BETA];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int rhs = (lane >> 5) + 2 * i;
+    double2 v = make_double2(0.0, 0.0);
     if (rhs < nrhs && live) {
-      const int64_t e = rhs * nalm + base + st;
-      pv = p[e];
-      const double* sc = scal + rhs * kScalSlots;
-      if (update && sc[S_DONE] == 0.0) {
-        const double beta = sc[S_BETA];
-        const double2 zv = z[e];
-        pv.x = fma(beta, pv.x, zv.x);
-        pv.y = fma(beta, pv.y, zv.y);
-        p[e] = pv;
+      v = pv[i];
+      if (update && done[i] == 0.0) {
+        v.x = fma(beta[i], v.x, zv[i].x);
+        v.y = fma(beta[i], v.y, zv[i].y);
+        p[rhs * nalm + base + st] = v;
       }
     }
     const int q = (lane & 31) & 1, n = (lane & 31) >> 1;
-    st_lds[q][rhs][0][n] = to_f32(f * pv.x);
-    st_lds[q][rhs][1][n] = to_f32(f * pv.y);
+    st_lds[q][rhs][0][n] = to_f32(f * v.x);
+    st_lds[q][rhs][1][n] = to_f32(f * v.y);
   }
   __syncthreads();
   // tile phase: lane j + 32 kg, j = 2 rhs + comp, holds steps 2 (8 kg + v) + q

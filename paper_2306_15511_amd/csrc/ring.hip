@@ -152,6 +152,14 @@ __device__ __forceinline__ void stockham_pass(V* x, int lN, int lNs, const V* __
   const int in_stride = nt + (nt >> 4);
   const int out_stride = Ns == 1 ? 1 : Ns + (Ns >> 4);   // Ns = 1 or a multiple of 16
   V v[J][R];
+  // twiddle loads first, for every u and without per-lane conditions (a
+  // load under one is waited for at once), so their latency overlaps the
+  // LDS reads
+  V wl[J];
+  if (lNs > 0) {
+#pragma unroll
+    for (int u = 0; u < J; ++u) wl[u] = tw[((threadIdx.x + u * blockDim.x) & (Ns - 1)) << (lf - lNs - lR)];
+  }
 #pragma unroll
   for (int u = 0; u < J; ++u) {
     const int j = threadIdx.x + u * blockDim.x;
@@ -165,8 +173,7 @@ __device__ __forceinline__ void stockham_pass(V* x, int lN, int lNs, const V* __
         for (int r = 0; r < R; ++r) v[u][r] = x[pad(j + r * nt)];
       }
       if (lNs > 0) {
-        const int k = j & (Ns - 1);
-        V w1 = tw[k << (lf - lNs - lR)];
+        V w1 = wl[u];
         if (inv) w1.y = -w1.y;
         const V w2 = cmul(w1, w1);
         const V w3 = cmul(w2, w1);
@@ -522,21 +529,24 @@ __global__ __launch_bounds__(NT) void k_ring(Tables T, int nside, int mmax, int 
 
   if (MODE == RING_FUSED) {
     ring_inverse(buf, scratch, q, eop, mmax, tw, lf);
-    // N^-1 of the ring (n <= 8 blockDim): all loads issued before the products
+    // N^-1 of the ring (n <= 8 blockDim): all loads issued before the
+    // products, without per-lane conditions (indices past the ring read its
+    // first pixel; the values are not used)
     constexpr int U = 8;
-    Re<V> wn[U], ws[U];
+    double wn[U], ws[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int j = threadIdx.x + u * blockDim.x;
-      wn[u] = j < q.n ? (Re<V>)ninv[q.fn + j] : Re<V>(0);
-      ws[u] = (j < q.n && !q.equator) ? (Re<V>)ninv[q.fs + j] : Re<V>(0);
+      const int jj = j < q.n ? j : 0;
+      wn[u] = ninv[q.fn + jj];
+      ws[u] = ninv[(q.equator ? q.fn : q.fs) + jj];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int j = threadIdx.x + u * blockDim.x;
       if (j < q.n) {
         const V Z = buf[pad(j)];
-        buf[pad(j)] = mk<V>(Z.x * wn[u], Z.y * ws[u]);
+        buf[pad(j)] = mk<V>(Z.x * (Re<V>)wn[u], q.equator ? Re<V>(0) : Z.y * (Re<V>)ws[u]);
       }
     }
   } else if (MODE == RING_SYNTH) {
