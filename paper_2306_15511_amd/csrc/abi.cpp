@@ -478,13 +478,16 @@ int pcg_start(const crsht_plan* P, int nrhs, const double2* b, bool pc, hipStrea
   return CR_OK;
 }
 
-// x += alpha p, r -= alpha q, z = P r; partials <r, z> (row 0), <r, r> (row 1)
-int pcg_update(const crsht_plan* P, int nrhs, bool pc, hipStream_t s) {
+// x += alpha p, r -= alpha q, z = P r; <r, z>, <r, r> and beta (the block
+// preconditioner sums its own <r, z> partials as it writes z)
+int pcg_update(const crsht_plan* P, int nrhs, bool pc, int nb, double tol, hipStream_t s) {
   Workspace const& w = P->w;
   CR_TRY(launch_cg_update(P, nrhs, w.cg_x, w.cg_r, w.cg_z, w.cg_p, w.cg_q, s, pc));
   if (pc) {
-    CR_TRY(launch_pc_apply(P, nrhs, w.cg_r, w.cg_z, s));
-    CR_TRY(launch_pc_dots(P, nrhs, w.cg_r, w.cg_z, false, s));
+    CR_TRY(launch_pc_apply(P, nrhs, w.cg_r, w.cg_z, s, true));
+    CR_TRY(launch_cg_scalars(P, nrhs, 2, nb, tol, 0, s, P->pc.part, P->pc.ntasks));
+  } else {
+    CR_TRY(launch_cg_scalars(P, nrhs, 2, nb, tol, 0, s));
   }
   return CR_OK;
 }
@@ -519,8 +522,7 @@ int pcg_run(const crsht_plan* P, int nrhs, const double* ninv, const double2* b,
         for (int k = 0; k < n; ++k) {
           CR_CHECK(operator_core(P, nrhs, w.cg_p, w.alm_a, ninv, w.cg_q, q, mixed));
           CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, q));
-          CR_CHECK(pcg_update(P, nrhs, pc, q));
-          CR_TRY(launch_cg_scalars(P, nrhs, 2, nb, tol, 0, q));
+          CR_CHECK(pcg_update(P, nrhs, pc, nb, tol, q));
           CR_TRY(launch_cg_pupdate(P, nrhs, w.cg_z, w.cg_p, w.alm_a, q));
         }
         return CR_OK;
@@ -700,8 +702,7 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
       for (int k = 0; k < n; ++k) {
         CR_CHECK(operator_core_cg(P, nrhs, k > 0 || first, ninv, w.cg_q, q));
         CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, q));
-        CR_CHECK(pcg_update(P, nrhs, pc, q));
-        CR_TRY(launch_cg_scalars(P, nrhs, 2, nb, tol, 0, q));
+        CR_CHECK(pcg_update(P, nrhs, pc, nb, tol, q));
       }
       return CR_OK;
     }));
@@ -826,8 +827,7 @@ int dsolve_step(const DSolve& d, bool first, hipStream_t q) {
         CR_CHECK(operator_core(P, d.nrhs, w.cg_p, w.alm_a, d.ninv, w.cg_q, q));
       }
       CR_TRY(launch_cg_scalars(P, d.nrhs, 1, nb, d.a.tol, 0, q));
-      CR_CHECK(pcg_update(P, d.nrhs, d.pc, q));
-      CR_TRY(launch_cg_scalars(P, d.nrhs, 2, nb, d.a.tol, 0, q));
+      CR_CHECK(pcg_update(P, d.nrhs, d.pc, nb, d.a.tol, q));
     }
   }
   CR_TRY(launch_dctl(P, DC_AFTER_BLOCK, d.a, nullptr, q));

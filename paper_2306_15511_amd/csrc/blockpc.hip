@@ -289,7 +289,9 @@ __device__ __forceinline__ void pc_apply_wave(const typename std::conditional<H1
                                               int nrhs, int64_t vlen, const float* __restrict__ scale,
                                               const double2* __restrict__ r, double2* __restrict__ z,
                                               float (*rs)[kPcJ][33], int w, int il, int kk, int n, int n0, int n1,
-                                              int ld, int i0, int64_t e00) {
+                                              int ld, int i0, int64_t e00, double* __restrict__ part,
+                                              int pstride, double wt, double* red) {
+  const int lane = threadIdx.x & 63;
   using Vec = typename std::conditional<H16, f16x4_t, f32x4_t>::type;
   // K steps per prefetch group: twice as many for FP16, the same bytes in flight
   constexpr int kPre = H16 ? 2 * kPcPre : kPcPre;
@@ -404,16 +406,58 @@ __device__ __forceinline__ void pc_apply_wave(const typename std::conditional<H1
         const int er = (threadIdx.x + t * kPcWaves * 64) & 255, q = er & 1, row = i0 + (er >> 1);
         so[t] = scale[row < (q ? n1 : n0) ? e00 + 2 * i0 + er : e00];
       }
-#pragma unroll 4
-      for (int k = 0; k < kOut; ++k) {
-        const int idx = threadIdx.x + k * kPcWaves * 64;
-        const int cc = idx >> 8, er = idx & 255;
-        const int c = h + cc, q = er & 1, row = i0 + (er >> 1);
-        if (c < nc && row < (q ? n1 : n0)) {
-          const float* v = stage + idx * 2;
-          const double sr = (double)so[k & 1];
-          z[(int64_t)(c0 + c) * vlen + e00 + 2 * i0 + er] = make_double2(sr * (double)v[0], sr * (double)v[1]);
+      // thread t writes coefficients t and t + 128 of columns h .. h + 7;
+      // with part, it also sums their terms of <r, z> per column (r loaded
+      // in batches, without per-lane conditions)
+      double rzp[8];
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) rzp[cc] = 0.0;
+      constexpr int kOb = 2;
+#pragma unroll
+      for (int k0 = 0; k0 < kOut; k0 += kOb) {
+        double2 rv[kOb];
+        if (part) {
+#pragma unroll
+          for (int k = 0; k < kOb; ++k) {
+            const int idx = threadIdx.x + (k0 + k) * kPcWaves * 64;
+            const int cc = idx >> 8, er = idx & 255;
+            const int c = h + cc, q = er & 1, row = i0 + (er >> 1);
+            const bool in = c < nc && row < (q ? n1 : n0);
+            rv[k] = r[(int64_t)(c0 + (in ? c : 0)) * vlen + (in ? e00 + 2 * i0 + er : e00)];
+          }
         }
+#pragma unroll
+        for (int k = 0; k < kOb; ++k) {
+          const int idx = threadIdx.x + (k0 + k) * kPcWaves * 64;
+          const int cc = idx >> 8, er = idx & 255;
+          const int c = h + cc, q = er & 1, row = i0 + (er >> 1);
+          if (c < nc && row < (q ? n1 : n0)) {
+            const float* v = stage + idx * 2;
+            const double sr = (double)so[k & 1];
+            const double2 zv = make_double2(sr * (double)v[0], sr * (double)v[1]);
+            z[(int64_t)(c0 + c) * vlen + e00 + 2 * i0 + er] = zv;
+            if (part) rzp[(k0 + k) >> 1] += fma(rv[k].x, zv.x, rv[k].y * zv.y);
+          }
+        }
+      }
+      if (part) {
+        // per column: sum over the wavefront (fixed butterfly order), then
+        // over the two wavefronts; weight 1 for m = 0, 2 otherwise
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+          double v = rzp[cc];
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+          rzp[cc] = v;
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int cc = 0; cc < 8; ++cc) red[w * 8 + cc] = rzp[cc];
+        }
+        __syncthreads();
+        if (threadIdx.x < 8 && h + (int)threadIdx.x < nc)
+          part[(int64_t)(c0 + h + threadIdx.x) * pstride + blockIdx.x] =
+              wt * (red[threadIdx.x] + red[8 + threadIdx.x]);
       }
     }
   }
@@ -424,8 +468,8 @@ __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3
     int nrhs, int64_t vlen, const int64_t* __restrict__ be0, const int* __restrict__ task_b,
     const int* __restrict__ task_b1, const int* __restrict__ task_r0, const int* __restrict__ bn,
     const int64_t* __restrict__ boff, const int* __restrict__ bhalf, const float* __restrict__ inv,
-    const float* __restrict__ scale, const double2* __restrict__ r, double2* __restrict__ z,
-    const int* __restrict__ pred) {
+    const float* __restrict__ scale, const int* __restrict__ bm, const double2* __restrict__ r,
+    double2* __restrict__ z, double* __restrict__ part, int pstride, const int* __restrict__ pred) {
   if (pred && *pred) return;
   constexpr int kSteps = kPcJ / 2;                          // K steps per LDS tile
   constexpr int kR = 2 * kPcJ * kPcCols / (kPcWaves * 64);  // residual values staged per thread and tile
@@ -433,8 +477,13 @@ __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3
   static_assert(kR % 4 == 0, "residual staging in batches of 4");
   static_assert(kPcWaves == 2, "one wavefront per parity block");
   __shared__ float rs[2][kPcJ][33];
+  __shared__ double red[2 * 8];
   const int b0 = task_b[blockIdx.x];
-  if (b0 < 0) return;   // padding task (uniform per workgroup, before any barrier)
+  if (b0 < 0) {   // padding task (uniform per workgroup, before any barrier): zero partials
+    if (part)
+      for (int c = threadIdx.x; c < nrhs; c += blockDim.x) part[(int64_t)c * pstride + blockIdx.x] = 0.0;
+    return;
+  }
   const int b1 = task_b1[blockIdx.x];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int b = w == 0 ? b0 : b1;
@@ -448,12 +497,14 @@ __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3
   const bool colok = ic < ld;                               // padding columns n .. ld - 1 hold zeros
   const int64_t e00 = be0[b0];                              // element of row j of block q: e00 + q + 2 j
   const float* __restrict__ base = inv + (b >= 0 ? boff[b] : 0);
+  const double wt = bm[b0] == 0 ? 1.0 : 2.0;               // real-field inner product weight of m
   // the two wavefronts may take different storage types; both pass the same barriers
   if (b >= 0 && bhalf[b])
     pc_apply_wave<true>(reinterpret_cast<const _Float16*>(base) + (colok ? ic : 0), nrhs, vlen, scale, r, z, rs,
-                        w, il, kk, n, n0, n1, ld, i0, e00);
+                        w, il, kk, n, n0, n1, ld, i0, e00, part, pstride, wt, red);
   else
-    pc_apply_wave<false>(base + (colok ? ic : 0), nrhs, vlen, scale, r, z, rs, w, il, kk, n, n0, n1, ld, i0, e00);
+    pc_apply_wave<false>(base + (colok ? ic : 0), nrhs, vlen, scale, r, z, rs, w, il, kk, n, n0, n1, ld, i0, e00,
+                         part, pstride, wt, red);
 }
 
 // partial <r, z> (row 0) and, with rr, <r, r> (row 1) per column
@@ -500,7 +551,8 @@ int dev_upload(T** p, const std::vector<T>& h) {
 }  // namespace
 
 void block_pc_free(BlockPC& pc) {
-  void* ptrs[] = {pc.inv, pc.scale, pc.bhalf, pc.bm, pc.bq, pc.bn, pc.boff, pc.be0, pc.task_b, pc.task_b1, pc.task_r0};
+  void* ptrs[] = {pc.inv, pc.scale, pc.bhalf, pc.part, pc.bm, pc.bq, pc.bn, pc.boff, pc.be0, pc.task_b, pc.task_b1,
+                  pc.task_r0};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   pc = BlockPC();
@@ -591,7 +643,8 @@ int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
   if ((rc = dev_upload(&pc.bm, bm)) || (rc = dev_upload(&pc.bq, bq)) || (rc = dev_upload(&pc.bn, bn)) ||
       (rc = dev_upload(&pc.boff, boff)) || (rc = dev_upload(&pc.be0, be0)) || (rc = dev_upload(&pc.task_b, tb)) || (rc = dev_upload(&pc.task_b1, tb1)) ||
       (rc = dev_upload(&pc.task_r0, tr)) || (rc = dev_alloc(&pc.inv, (size_t)off)) ||
-      (rc = dev_alloc(&pc.scale, (size_t)ncomp * g.nalm)) || (rc = dev_alloc(&pc.bhalf, (size_t)nb))) {
+      (rc = dev_alloc(&pc.scale, (size_t)ncomp * g.nalm)) || (rc = dev_alloc(&pc.bhalf, (size_t)nb)) ||
+      (rc = dev_alloc(&pc.part, (size_t)P->nrhs_max * tb.size()))) {
     block_pc_free(pc);
     return rc;
   }
@@ -761,11 +814,12 @@ int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
   return CR_OK;
 }
 
-hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s) {
+hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s, bool dots) {
   const BlockPC& pc = P->pc;
   timing_begin(P, 5, s);
   hipLaunchKernelGGL(k_pc_apply, dim3(pc.ntasks), dim3(kPcWaves * 64), 0, s, nrhs, vlen(P), pc.be0, pc.task_b,
-                     pc.task_b1, pc.task_r0, pc.bn, pc.boff, pc.bhalf, pc.inv, pc.scale, r, z, P->pred);
+                     pc.task_b1, pc.task_r0, pc.bn, pc.boff, pc.bhalf, pc.inv, pc.scale, pc.bm, r, z,
+                     dots ? pc.part : nullptr, pc.ntasks, P->pred);
   timing_end(P, 5, s);
   return hipGetLastError();
 }

@@ -226,6 +226,7 @@ struct BlockPC {
   float* inv = nullptr;      // Jacobi-scaled inverses, FP32 or FP16 per block
   float* scale = nullptr;    // [ncomp * nalm] sqrt of the inverse's diagonal, per vector element
   int* bhalf = nullptr;      // per block: 1 if stored in FP16
+  double* part = nullptr;    // [nrhs_max][ntasks] partials of <r, z> written by the application
   int *bm = nullptr, *bq = nullptr, *bn = nullptr;
   int64_t* boff = nullptr;   // float offset of each stored inverse
   int64_t* be0 = nullptr;    // vector element of row 0 of each block (component offset included)
@@ -417,7 +418,9 @@ hipError_t launch_diag_tqu(const crsht_plan* P, const double2* rawt, const doubl
 int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s);
 void block_pc_free(BlockPC& pc);
 // z = M^-1 r per column (r, z: [nrhs][vlen])
-hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s);
+// with dots, also the per-task partials of <r, z> into pc.part ([nrhs][ntasks])
+hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s,
+                           bool dots = false);
 // partial <r, z> (row 0) and, with rr, <r, r> (row 1), nb = vec_reduce_blocks
 hipError_t launch_pc_dots(const crsht_plan* P, int nrhs, const double2* r, const double2* z, bool rr,
                           hipStream_t s);
@@ -458,10 +461,12 @@ hipError_t launch_alm_axpby(int64_t n, double a, const double2* x, double b, con
 // zgiven: z already holds the preconditioned residual (block preconditioner)
 hipError_t launch_cg_start(const crsht_plan* P, int nrhs, const double2* b, const double2* r, double2* z,
                            double2* p, double2* pt, hipStream_t s, bool zgiven = false);
+// part0 (optional): row 0 (<r, z>) comes from part0[c * n0 + i], i < n0,
+// instead of the block partials (the block preconditioner's own partials)
 hipError_t launch_cg_scalars(const crsht_plan* P, int nrhs, int what, int nb, double tol, int restart,
-                             hipStream_t s);
+                             hipStream_t s, const double* part0 = nullptr, int n0 = 0);
 // noz == false: z = r / D with <r, z> in row 0; true: z untouched, row 0 = 0
-// (the block preconditioner and launch_pc_dots follow)
+// (the block preconditioner follows, with its own <r, z> partials)
 hipError_t launch_cg_update(const crsht_plan* P, int nrhs, double2* x, double2* r, double2* z, const double2* p,
                             const double2* q, hipStream_t s, bool noz = false);
 hipError_t launch_cg_replace(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s);

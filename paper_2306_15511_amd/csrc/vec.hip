@@ -199,7 +199,8 @@ __global__ void k_cg_start(int64_t nalm, const int* __restrict__ idx_m, const do
 // sums partial[c][slot-row][0..nb) into scal; what = 0: start, 1: alpha, 2: beta,
 // 3: residual replacement
 __global__ void k_cg_scalars(int what, int nb, const double* __restrict__ partial, int npart,
-                             double* __restrict__ scal, double tol, int restart, const int* __restrict__ pred) {
+                             double* __restrict__ scal, double tol, int restart, const double* __restrict__ part0,
+                             int n0, const int* __restrict__ pred) {
   if (pred && *pred) return;
   __shared__ double sh[kVecBlock];
   const int c = blockIdx.x;
@@ -207,12 +208,14 @@ __global__ void k_cg_scalars(int what, int nb, const double* __restrict__ partia
   double* sc = scal + c * kScalSlots;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-    s0 += pa[i];
+    if (!part0) s0 += pa[i];
     if (what != 1) {
       s1 += pa[npart + i];
       s2 += pa[2 * npart + i];
     }
   }
+  if (part0)
+    for (int i = threadIdx.x; i < n0; i += blockDim.x) s0 += part0[(size_t)c * n0 + i];
   s0 = block_sum(s0, sh);
   s1 = block_sum(s1, sh);
   s2 = block_sum(s2, sh);
@@ -652,9 +655,9 @@ hipError_t launch_cg_start(const crsht_plan* P, int nrhs, const double2* b, cons
 }
 
 hipError_t launch_cg_scalars(const crsht_plan* P, int nrhs, int what, int nb, double tol, int restart,
-                             hipStream_t s) {
+                             hipStream_t s, const double* part0, int n0) {
   hipLaunchKernelGGL(k_cg_scalars, dim3(nrhs), dim3(kVecBlock), 0, s, what, nb, P->w.partial, P->w.npart,
-                     P->w.scal, tol, restart, P->pred);
+                     P->w.scal, tol, restart, part0, n0, P->pred);
   return hipGetLastError();
 }
 
