@@ -53,12 +53,12 @@ HBM_PEAK_GBS = 8000.0
 # 16-column temperature workload and while the kernel's source file hashes to
 # `src`.
 TRAFFIC = {
-    "k_adj_mfma": {"bytes": 959810560, "src": "446b7d20a3644d9d"},
-    "k_synth_mfma": {"bytes": 696782848, "src": "446b7d20a3644d9d"},
-    "k_ring<float2, RING_FUSED>": {"bytes": 851464192, "src": "1095a43175397d24"},   # one pass (4 class launches)
+    "k_adj_mfma": {"bytes": 959810048, "src": "60fc0ea3cc5df5e4"},
+    "k_synth_mfma": {"bytes": 697151488, "src": "60fc0ea3cc5df5e4"},
+    "k_ring<float2, RING_FUSED>": {"bytes": 851797888, "src": "bd3b18c2827acee1"},   # one pass (4 class launches)
     "k_legendre_synth_mfma": {"bytes": 680593408, "src": "74e6c305f36a5103"},    # one launch of 8 columns
     "k_legendre_adj_mfma": {"bytes": 2 * 606706688, "src": "74e6c305f36a5103"},  # one transform (2 launches)
-    "k_pc_apply": {"bytes": 3080813568, "src": "93eb7917d57ed236"},
+    "k_pc_apply": {"bytes": 2382975339, "src": "bd48ba1ba3245378"},
 }
 
 
