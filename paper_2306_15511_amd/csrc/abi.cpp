@@ -263,16 +263,21 @@ int operator_core(const crsht_plan* P, int nrhs, const double2* x, const double2
 // A p inside the mixed-precision PCG: with update, first p = z + beta p per
 // column (fused with the MFMA operand preparation). out = sinv * p + bk *
 // (Y^T N^-1 Y)(bk p); block partials of <p, out> in row 0.
-int operator_core_cg(const crsht_plan* P, int nrhs, bool update, const double* ninv, double2* out, hipStream_t s) {
+// and alpha = <r, z> / <p, q> (the T form sums the adjoint's own <p, q>
+// partials)
+int operator_core_cg(const crsht_plan* P, int nrhs, bool update, const double* ninv, double2* out, int nb, double tol,
+                     hipStream_t s) {
   Workspace const& w = P->w;
   if (P->ncomp == 3) {
     if (update) CR_TRY(launch_cg_pupdate(P, nrhs, w.cg_z, w.cg_p, w.alm_a, s));
-    return operator_core_tqu(P, nrhs, w.cg_p, ninv, out, s, true, true);
+    CR_CHECK(operator_core_tqu(P, nrhs, w.cg_p, ninv, out, s, true, true));
+    CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, s));
+    return CR_OK;
   }
   CR_TRY(launch_legendre_synth_mixed_cg(P, nrhs, w.cg_z, w.cg_p, update, F2(w.eo), s));
   CR_TRY(launch_ring(P, nrhs, RING_FUSED, w.eo, nullptr, ninv, w.geo, true, s));
-  CR_TRY(launch_legendre_adjoint_mixed(P, nrhs, F2(w.geo), w.alm_b, s));
-  CR_TRY(launch_cg_q(P, nrhs, w.cg_p, w.alm_b, out, s));
+  CR_TRY(launch_legendre_adjoint_mixed_q(P, nrhs, F2(w.geo), w.cg_p, out, s));
+  CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, s, w.adj_part, (int)P->t.mx_ntiles));
   return CR_OK;
 }
 
@@ -700,8 +705,7 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
     const bool first = pending;
     CR_CHECK(run_block(P, key, o->use_graph != 0, s, [&](hipStream_t q) -> int {
       for (int k = 0; k < n; ++k) {
-        CR_CHECK(operator_core_cg(P, nrhs, k > 0 || first, ninv, w.cg_q, q));
-        CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, q));
+        CR_CHECK(operator_core_cg(P, nrhs, k > 0 || first, ninv, w.cg_q, nb, tol, q));
         CR_CHECK(pcg_update(P, nrhs, pc, nb, tol, q));
       }
       return CR_OK;
@@ -821,12 +825,12 @@ int dsolve_step(const DSolve& d, bool first, hipStream_t q) {
     for (int k = 0; k < d.a.every; ++k) {
       const bool upd = k > 0 || first;
       if (d.mixed) {
-        CR_CHECK(operator_core_cg(P, d.nrhs, upd, d.ninv, w.cg_q, q));
+        CR_CHECK(operator_core_cg(P, d.nrhs, upd, d.ninv, w.cg_q, nb, d.a.tol, q));
       } else {
         if (upd) CR_TRY(launch_cg_pupdate(P, d.nrhs, w.cg_z, w.cg_p, w.alm_a, q));
         CR_CHECK(operator_core(P, d.nrhs, w.cg_p, w.alm_a, d.ninv, w.cg_q, q));
+        CR_TRY(launch_cg_scalars(P, d.nrhs, 1, nb, d.a.tol, 0, q));
       }
-      CR_TRY(launch_cg_scalars(P, d.nrhs, 1, nb, d.a.tol, 0, q));
       CR_CHECK(pcg_update(P, d.nrhs, d.pc, nb, d.a.tol, q));
     }
   }

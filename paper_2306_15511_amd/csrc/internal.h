@@ -123,6 +123,7 @@ struct Workspace {
   void* dstats = nullptr;      // [nrhs_max] cr_stats written by a device-driven solve (cr_solve_batched)
   void* mx_ab = nullptr;       // bf16 synthesis operand tiles (one group of kMixedCols columns)
   void* mx_ag = nullptr;       // bf16 adjoint operand tiles
+  double* adj_part = nullptr;  // [nrhs_max][mixed adjoint tiles] partials of <p, q> (fused adjoint)
   double2* pol = nullptr;      // T+Q+U: [nrhs][9][npol][mmax+1][2] FP64 Legendre sums of the polar ring pairs
   int npart = 0;
 };
@@ -351,6 +352,10 @@ hipError_t launch_legendre_synth_mixed_cg(const crsht_plan* P, int nrhs, const d
                                           float2* eo, hipStream_t s);
 // raw sums as launch_legendre_adjoint (non-diag) from float2 geo, bf16x3 /
 // FP32 accumulation
+// T plans, PCG: the bf16x3 adjoint fused with q = camp.x sinv p + bk raw and
+// the per-tile partials of <p, q> (w.adj_part, [nrhs][t.mx_ntiles])
+hipError_t launch_legendre_adjoint_mixed_q(const crsht_plan* P, int nrhs, const float2* geo, const double2* p,
+                                           double2* q, hipStream_t s);
 hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const float2* geo, double2* raw,
                                          hipStream_t s);
 

@@ -638,6 +638,9 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
                                                   int maxq, const double2* __restrict__ ckpt,
                                                   const bf16x8* __restrict__ ag, int64_t ag_gstride,
                                                   double2* __restrict__ out, int64_t out_stride,
+                                                  const double2* __restrict__ qp, const double* __restrict__ sinv,
+                                                  const double2* __restrict__ camp, const double* __restrict__ bk,
+                                                  double* __restrict__ part, int64_t ntiles,
                                                   const int* __restrict__ pred) {
   if (pred && *pred) return;
   // per wavefront: FP32 [q][32 steps][kRowF pairs]; reused for the partial results
@@ -748,6 +751,32 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
       asm volatile("" : "+a"(dO[g]));
     }
   }
+  // PCG form: the operands of q (p, S^-1, B, the column amplitudes) are
+  // loaded now, without per-lane conditions (out-of-range elements read the
+  // tile's first coefficient of column 0), so that their latency overlaps the
+  // reduction below. Thread (w, lane) handles component w & 1 of columns
+  // 4 k + 2 (lane >> 5) + (w >> 1), k = 0..3, at steps 2 (lane & 31) + q.
+  double qpv[4][2], qsi[2], qbk[2], qca[4];
+  if (qp) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int st = st0 + 2 * (lane & 31) + q;
+      const int64_t i = base + (st < nsteps ? st : st0);
+      qsi[q] = sinv ? sinv[i] : 0.0;
+      qbk[q] = bk[i];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int rhs = 4 * k + 2 * (lane >> 5) + (w >> 1);
+        const bool ok = rhs < nrhs && st < nsteps;
+        qpv[k][q] = reinterpret_cast<const double*>(qp + (ok ? rhs : 0) * out_stride + (ok ? i : base + st0))[w & 1];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int rhs = 4 * k + 2 * (lane >> 5) + (w >> 1);
+      qca[k] = camp[rhs < nrhs ? rhs : 0].x;
+    }
+  }
   // one block-wide barrier, reached once by every wavefront; each wavefront
   // reuses its own tile area for its partial result red[w][q][r][lane]
   // (NG x 8 KiB of the wavefront's 16 KiB tile area)
@@ -761,18 +790,70 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
     }
   __syncthreads();
   // D[c][n] at lane n + 32 ((c/4)%2), register 4 (c/8) + c%4; sum the wavefronts
-  for (int e = threadIdx.x; e < NG * 2 * 16 * 64; e += blockDim.x) {
-    const int g = e / (2 * 16 * 64), q = (e / (16 * 64)) % 2, r = (e / 64) % 16, ln = e % 64;
-    float acc = 0.f;
+  if (!qp) {
+    for (int e = threadIdx.x; e < NG * 2 * 16 * 64; e += blockDim.x) {
+      const int g = e / (2 * 16 * 64), q = (e / (16 * 64)) % 2, r = (e / 64) % 16, ln = e % 64;
+      float acc = 0.f;
 #pragma unroll
-    for (int ww = 0; ww < kAdjWaves; ++ww)
-      acc += (&lds[ww][0][0][0])[((2 * g + q) * 16 + r) * 64 + ln];
-    const int c = 8 * (r / 4) + 4 * (ln >> 5) + (r % 4);
-    const int n = ln & 31;
-    const int rhs = 16 * g + (c >> 1), comp = c & 1;
-    const int st = st0 + 2 * n + q;
-    if (rhs < nrhs && st < nsteps)
-      reinterpret_cast<double*>(out + rhs * out_stride + base + st)[comp] = (double)acc;
+      for (int ww = 0; ww < kAdjWaves; ++ww)
+        acc += (&lds[ww][0][0][0])[((2 * g + q) * 16 + r) * 64 + ln];
+      const int c = 8 * (r / 4) + 4 * (ln >> 5) + (r % 4);
+      const int n = ln & 31;
+      const int rhs = 16 * g + (c >> 1), comp = c & 1;
+      const int st = st0 + 2 * n + q;
+      if (rhs < nrhs && st < nsteps)
+        reinterpret_cast<double*>(out + rhs * out_stride + base + st)[comp] = (double)acc;
+    }
+    return;
+  }
+  // PCG form (one column group): q = camp.x sinv p + bk raw, component by
+  // component, and the tile's partial of <p, q>
+  static_assert(NG == 1 && kAdjWaves == 4, "PCG form: one column group, four wavefronts");
+  const int ln = lane, comp = w & 1;
+  const int n = ln & 31;
+  double pz[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) pz[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int rhs = 4 * k + 2 * (ln >> 5) + (w >> 1);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int r = w + 4 * k;
+      float acc = 0.f;
+#pragma unroll
+      for (int ww = 0; ww < kAdjWaves; ++ww) acc += (&lds[ww][0][0][0])[(q * 16 + r) * 64 + ln];
+      const int st = st0 + 2 * n + q;
+      if (rhs < nrhs && st < nsteps) {
+        const double qv = fma(qca[k] * qsi[q], qpv[k][q], qbk[q] * (double)acc);
+        reinterpret_cast<double*>(out + rhs * out_stride + base + st)[comp] = qv;
+        pz[k] = fma(qpv[k][q], qv, pz[k]);
+      }
+    }
+  }
+  // sums over the 32 lanes of each half wavefront (fixed butterfly order),
+  // then the two components; weight 1 for m = 0, 2 otherwise
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double v = pz[k];
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    pz[k] = v;
+  }
+  __syncthreads();   // the tile area is read above; its start holds the sums below
+  double* red = reinterpret_cast<double*>(&lds[0][0][0][0]);   // [w][half][k]
+  if ((ln & 31) == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[(w * 2 + (ln >> 5)) * 4 + k] = pz[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    const int rhs = threadIdx.x;
+    const int k = rhs >> 2, half = (rhs >> 1) & 1, wg = rhs & 1;
+    if (rhs < nrhs) {
+      const double v = red[((2 * wg + 0) * 2 + half) * 4 + k] + red[((2 * wg + 1) * 2 + half) * 4 + k];
+      part[rhs * ntiles + tid] = (m == 0 ? 1.0 : 2.0) * v;
+    }
   }
 }
 
@@ -933,13 +1014,41 @@ hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const fl
   hipLaunchKernelGGL((k_adj_mfma<1, NS>), dim3(8u * (unsigned)P->t.mx_maxq), dim3(kAdjWaves * 64), 0, s, g.lmax,   \
                      g.mmax, g.npairs, nr, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,        \
                      P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_order, P->t.mx_maxq, P->t.mx_ckpt, (const bf16x8*)ag, \
-                     ag_group(g), raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm, P->pred)
+                     ag_group(g), raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm, nullptr, nullptr, nullptr, nullptr, \
+                     nullptr, 0, P->pred)
     if (ns == 3)
       CRSHT_ADJ_LAUNCH(3);
     else
       CRSHT_ADJ_LAUNCH(2);
 #undef CRSHT_ADJ_LAUNCH
     timing_end(P, ns == 3 ? -1 : 4, s);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_legendre_adjoint_mixed_q(const crsht_plan* P, int nrhs, const float2* geo, const double2* p,
+                                           double2* q, hipStream_t s) {
+  const Geometry& g = P->g;
+  const int64_t geo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
+  bf16x8* ag = reinterpret_cast<bf16x8*>(P->w.mx_ag);
+  const int per = kAdjGroups * (kMixedCols / 2);
+  for (int c0 = 0; c0 < nrhs; c0 += per) {
+    const int nr = min(nrhs - c0, per);
+    dim3 gp((g.npairs + 15) / 16, (g.mmax + kPrepM) / kPrepM, 1);
+    hipLaunchKernelGGL(k_prep_adj<2>, gp, dim3(256), 0, s, g.mmax, g.npairs, nr, geo + (int64_t)c0 * geo_stride,
+                       geo_stride, ag, ag_group(g), P->pred);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    timing_begin(P, 4, s);
+    hipLaunchKernelGGL((k_adj_mfma<1, 2>), dim3(8u * (unsigned)P->t.mx_maxq), dim3(kAdjWaves * 64), 0, s, g.lmax,
+                       g.mmax, g.npairs, nr, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
+                       P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_order, P->t.mx_maxq, P->t.mx_ckpt, (const bf16x8*)ag,
+                       ag_group(g), q + (int64_t)c0 * g.nalm, (int64_t)g.nalm, p + (int64_t)c0 * g.nalm,
+                       (const double*)P->w.sinv, (const double2*)P->w.camp + c0, (const double*)P->w.bk,
+                       P->w.adj_part + (int64_t)c0 * P->t.mx_ntiles, P->t.mx_ntiles, P->pred);
+    timing_end(P, 4, s);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

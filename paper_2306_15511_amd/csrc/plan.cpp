@@ -76,7 +76,7 @@ void free_plan_memory(crsht_plan* P) {
                   P->t.pair_fft_len, P->t.pair_bs_off, P->t.pair_bk_off, P->t.bs_chirp, P->t.bs_kern,
                   P->t.twiddle, P->t.bs_chirp32, P->t.bs_kern32, P->t.twiddle32, P->t.ring_pairs, P->t.rec_alpha, P->t.rec_kappa, P->t.lmm_v, P->t.lmm_k, P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.ones,
                   P->t.mx_cstart, P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_order, P->t.mx_ckpt, P->w.cg_xacc, P->w.cg_bin, P->w.bin_edges, P->w.bin_part, P->w.bin_grad, P->w.lfac, P->w.camp,
-                  P->w.mx_ab, P->w.mx_ag, P->w.pol,
+                  P->w.mx_ab, P->w.mx_ag, P->w.adj_part, P->w.pol,
                   P->t.idx_l, P->t.idx_m, P->w.eo, P->w.geo, P->w.alm_a, P->w.alm_b, P->w.cg_x, P->w.cg_r, P->t.idx_mv, P->w.bl_keep, P->w.sblk,
                   P->w.cg_z, P->w.cg_p, P->w.cg_q, P->w.cg_b, P->w.cg_d, P->w.alm_c, P->w.alm_d, P->w.map_a, P->w.ring_w,
                   P->w.diag, P->w.sinv, P->w.sinvhalf, P->w.bk, P->w.perl, P->w.partial, P->w.scal, P->w.ctl,
@@ -357,6 +357,7 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int ncomp, i
     w.mx_ab = ab;
     if ((rc = dalloc(&ag, (size_t)crsht::mixed_ag_bytes(g), total))) return rc;
     w.mx_ag = ag;
+    if ((rc = dalloc(&w.adj_part, R * (size_t)P->t.mx_ntiles, total))) return rc;
   }
   if ((rc = dalloc(&w.alm_c, C * (size_t)g.nalm, total))) return rc;
   if ((rc = dalloc(&w.alm_d, C * (size_t)g.nalm, total))) return rc;
