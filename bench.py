@@ -627,7 +627,7 @@ def kernel_roofline(args, plan, one_solve, nside, lmax, R, nc, mixed, use_block,
         # block, as the build chose) + their FP32 diagonal scales + r read +
         # z written
         pcb = plan.precond_info()[0]
-        kinfo[5] = ("k_pc_apply (block preconditioner, FP16/FP32 storage, FP32 MFMA)", "hbm",
+        kinfo[5] = ("k_pc_apply (block preconditioner, FP16 blocks on FP16 MFMA, FP32 blocks on FP32 MFMA)", "hbm",
                     pcb + 4 * plan.vlen + 2 * R * plan.vlen * 16, HBM_PEAK_GBS, "GB/s", "blockpc.hip")
     roofs = {}
     for kid, (name, bound, work, peak, unit, src) in kinfo.items():

@@ -49,7 +49,6 @@ namespace crsht {
 namespace {
 
 constexpr int kStartGroup = 16;   // start-table group of the Legendre recurrence
-constexpr int kNeverG = 0x7fffffff;
 constexpr int kPcWaves = 2;       // wavefronts per application workgroup
 constexpr int kPcRows = 128;     // rows of each parity block per application workgroup
 constexpr int kPcCols = 16;       // right-hand sides per application pass
@@ -233,92 +232,219 @@ __global__ void k_pc_shift(const int* __restrict__ blocks, const int* __restrict
   T[(size_t)blockIdx.y * npad * npad + (size_t)i * npad + i] -= kHalfMargin * sqrt(err2[blockIdx.y]);
 }
 
-// Blocks whose test factorisation succeeded: FP16 over the front half of
-// their FP32 storage (rows of pc_ld(n) halves, padding columns zero), and
-// the per-block flag.
+// Blocks whose test factorisation succeeded: C in FP16 in the operand order
+// of v_mfma_f32_32x32x16_f16, and the per-block flag. Tiles of 32 rows x 16
+// columns (1 KiB) in row-tile-major order, ceil(n/32) x ceil(n/16) per block
+// from element boff16; in a tile, lane l = i % 32 + 32 ((j % 16) / 8) holds
+// the 8 entries C[i][16 tj + 8 (l / 32) + e], e = 0..7, contiguously (zeros
+// past n), so every operand load of a wavefront is one contiguous 1 KiB run.
+__host__ __device__ __forceinline__ int pc_tiles_i(int n) { return (n + 31) / 32; }
+__host__ __device__ __forceinline__ int pc_tiles_j(int n) { return (n + 15) / 16; }
 __global__ void k_pc_half(const int* __restrict__ blocks, const int* __restrict__ bn,
-                          const int64_t* __restrict__ boff, int npad, const double* __restrict__ C,
-                          const int* __restrict__ info, float* __restrict__ inv, int* __restrict__ bhalf) {
+                          const int64_t* __restrict__ boff16, int npad, const double* __restrict__ C,
+                          const int* __restrict__ info, _Float16* __restrict__ inv16, int* __restrict__ bhalf) {
   const int blk = blocks[blockIdx.z];
-  const int n = bn[blk], ld = pc_ld(n);
+  const int n = bn[blk], ntj = pc_tiles_j(n);
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
   const bool half = info[blockIdx.z] == 0;
   if (i == 0 && j == 0) bhalf[blk] = half ? 1 : 0;
-  if (!half || i >= ld || j >= n) return;
+  if (!half || i >= 32 * pc_tiles_i(n) || j >= 16 * ntj) return;
   _Float16 h = (_Float16)0.0f;
-  if (i < n) {
+  if (i < n && j < n) {
     const double* c = C + (size_t)blockIdx.z * npad * npad;
     const double v = i >= j ? c[(size_t)j * npad + i] : c[(size_t)i * npad + j];
     const double si = sqrt(c[(size_t)i * npad + i]), sj = sqrt(c[(size_t)j * npad + j]);
     h = (_Float16)(v / (si * sj));
   }
-  reinterpret_cast<_Float16*>(inv + boff[blk])[(size_t)j * ld + i] = h;
+  const int lane = (i & 31) + 32 * ((j & 15) >> 3);
+  inv16[boff16[blk] + (((int64_t)(i >> 5) * ntj + (j >> 4)) * 64 + lane) * 8 + (j & 7)] = h;
 }
 
 // z = M^-1 r = S C S r for the two parity blocks of one m (one component)
-// and 16 right-hand sides (32 real columns) on the matrix cores
-// (v_mfma_f32_32x32x2_f32). A workgroup takes rows [r0, r0 + 128) of both
-// blocks: wavefront w of block b_w (b_0: l - m even, b_1: odd, -1 if absent).
-// The two blocks' coefficients interleave in the vectors, so the workgroup
-// stages one contiguous residual range for both (coalesced loads) and both
-// wavefronts' results fill the same memory sectors close in time. Per K step
-// (rows j, j + 1 of the symmetric C) lane l of half h loads the four
-// C[j + h][i0 + 4 l .. i0 + 4 l + 3] (FP32 or FP16 per block, a
-// wavefront-uniform choice), so one load instruction reads two contiguous
-// 512-byte (FP16: 256-byte) runs; component v of it (as FP32) is the A
-// operand of the v-th of four MFMAs whose 32 output rows are i0 + 4 t + v
-// (t = 0 .. 31), each with its own accumulator. The B operand R[j + h][c]
-// comes from an LDS tile of kPcJ rows j per parity (FP32 S r; rows padded to
-// 33 floats so the staging writes spread over the banks). The A loads of the
-// next prefetch group (kPcPre K steps; twice as many for FP16) are in flight
-// while the current ones are multiplied; the results are scaled by S as they
-// are written.
-// MFMA 32x32x2 f32 lane layout: A[i][k] in lane i + 32 k, B[k][c] in lane
-// c + 32 k, D[i][c] in lane c + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4.
+// and 16 right-hand sides (32 real columns) on the matrix cores. A
+// workgroup takes rows [r0, r0 + 128) of both blocks: wavefront w of block
+// b_w (b_0: l - m even, b_1: odd, -1 if absent). The two blocks'
+// coefficients interleave in the vectors, so the workgroup stages one
+// contiguous residual range for both (coalesced loads) into an LDS tile of
+// kPcJ rows j per parity (FP32 S r; rows padded to 33 floats so the staging
+// writes spread over the banks), and both wavefronts' results fill the same
+// memory sectors close in time. Each wavefront takes the path of its block's
+// storage (both pass the same barriers):
+// - FP32 blocks (v_mfma_f32_32x32x2_f32): per K step (rows j, j + 1 of the
+//   symmetric C) lane l of half h loads the float4 C[j + h][i0 + 4 l ..
+//   i0 + 4 l + 3], so one load instruction reads two contiguous 512-byte
+//   runs; component v is the A operand of the v-th of four MFMAs whose 32
+//   output rows are i0 + 4 t + v (t = 0 .. 31), each with its own
+//   accumulator; the loads of the next kPcPre K steps are in flight while
+//   the current ones are multiplied.
+// - FP16 blocks (v_mfma_f32_32x32x16_f16): per K step of 16 columns the four
+//   32-row tiles of the task are four contiguous 1 KiB loads (the storage is
+//   in operand order, see k_pc_half) and feed one MFMA each with the staged
+//   S r as the B operand, split into two FP16 parts (hi + lo, 22 bits) after
+//   scaling by a power of two per column: the running maximum of |S r| over
+//   the steps seen so far sets the exponent, and the accumulators are
+//   rescaled (by a power of two, exactly) whenever it grows. The products of
+//   a K step take an eighth of the FP32 path's matrix-core time.
+// The results are scaled by S (and the FP16 path's exponent) as they are
+// written. MFMA lane layouts: 32x32x2 f32: A[i][k] in lane i + 32 k, B[k][c]
+// in lane c + 32 k; 32x32x16 f16: A[i][k] in lane i + 32 (k / 8), element
+// k % 8, B[k][c] in lane c + 32 (k / 8), element k % 8; both: D[i][c] in
+// lane c + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4.
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
-typedef _Float16 f16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
-constexpr int kPcPre = 4;          // K steps per prefetch group
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+constexpr int kPcPre = 4;          // K steps per prefetch group (FP32 path)
+constexpr int kPcR = 2 * kPcJ * kPcCols / (kPcWaves * 64);   // residual values staged per thread and tile
+constexpr int kF16Shift = 140;     // FP16 path: S r x 2^(kF16Shift - e) < 2^14, e the biased exponent of its maximum
 
-// One wavefront's part of k_pc_apply: rows [i0, i0 + 128) of its block
-// (FP16 or FP32 storage) against the staged residual tiles, then the
-// results. The A operands stay in their storage type while in flight and are
-// widened to FP32 at the products.
-template <bool H16>
-__device__ __forceinline__ void pc_apply_wave(const typename std::conditional<H16, _Float16, float>::type* __restrict__ Ab,
-                                              int nrhs, int64_t vlen, const float* __restrict__ scale,
-                                              const double2* __restrict__ r, double2* __restrict__ z,
-                                              float (*rs)[kPcJ][33], int w, int il, int kk, int n, int n0, int n1,
-                                              int ld, int i0, int64_t e00, double* __restrict__ part,
-                                              int pstride, double wt, double* red) {
+// one residual tile, rows [j0, j0 + kPcJ) of both parities: consecutive
+// threads read consecutive coefficients, in batches of kStage to bound the
+// registers held by loads in flight; the loads carry no per-lane condition
+// (elements outside the blocks or columns read element e00 of column c0 and
+// are zeroed by their scale factor), so each batch's loads are in flight
+// together
+__device__ __forceinline__ void pc_stage(float (*rs)[kPcJ][33], int j0, int c0, int nc, int n0, int n1,
+                                         int64_t vlen, int64_t e00, const double2* __restrict__ r,
+                                         const float* __restrict__ scale) {
+  constexpr int kStage = 4;
+  static_assert(kPcR % kStage == 0, "whole staging batches");
+#pragma unroll 1
+  for (int k0 = 0; k0 < kPcR; k0 += kStage) {
+    double2 v[kStage];
+    float sv[kStage];
+#pragma unroll
+    for (int k = 0; k < kStage; ++k) {
+      const int e = threadIdx.x + (k0 + k) * kPcWaves * 64;
+      const int ee = e % (2 * kPcJ), cc = e / (2 * kPcJ);
+      const int q = ee & 1, j = j0 + (ee >> 1);
+      const bool in = cc < nc && j < (q ? n1 : n0);
+      const int64_t el = in ? e00 + 2 * j0 + ee : e00;
+      v[k] = r[(int64_t)(c0 + (in ? cc : 0)) * vlen + el];
+      sv[k] = scale[el];
+      sv[k] = in ? sv[k] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < kStage; ++k) {
+      const int e = threadIdx.x + (k0 + k) * kPcWaves * 64;
+      const int ee = e % (2 * kPcJ), cc = e / (2 * kPcJ);
+      const int q = ee & 1, jj = ee >> 1;
+      rs[q][jj][2 * cc] = (float)(v[k].x * sv[k]);
+      rs[q][jj][2 * cc + 1] = (float)(v[k].y * sv[k]);
+    }
+  }
+}
+
+// results through LDS (the rs tile, free after the last products), 8
+// columns at a time, then written as whole rows of both parities (the
+// task's 256 interleaved coefficients of a column are contiguous); fill(stage,
+// h) writes this wavefront's results of columns h .. h + 7 as
+// stage[column - h][2 (row - i0) + w][re, im]. With part, the per-task
+// partials of <r, z>.
+template <class Fill>
+__device__ __forceinline__ void pc_output(Fill&& fill, float (*rs)[kPcJ][33], int c0, int nc, int n0, int n1, int i0,
+                                          int64_t vlen, int64_t e00, const float* __restrict__ scale,
+                                          const double2* __restrict__ r, double2* __restrict__ z,
+                                          double* __restrict__ part, int pstride, double wt, double* red, int w,
+                                          int lane) {
+  float* stage = &rs[0][0][0];   // [8 columns][256 coefficients][re, im]
+#pragma unroll 1
+  for (int h = 0; h < kPcCols; h += 8) {
+    __syncthreads();   // the products (or the previous half's writes) have read the tile
+    fill(stage, h);
+    __syncthreads();
+    // this thread's coefficients are the same for every column: their
+    // scales are read once, without per-lane conditions
+    constexpr int kOut = 8 * 256 / (kPcWaves * 64);
+    float so[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int er = (threadIdx.x + t * kPcWaves * 64) & 255, q = er & 1, row = i0 + (er >> 1);
+      so[t] = scale[row < (q ? n1 : n0) ? e00 + 2 * i0 + er : e00];
+    }
+    // thread t writes coefficients t and t + 128 of columns h .. h + 7;
+    // with part, it also sums their terms of <r, z> per column (r loaded
+    // in batches, without per-lane conditions)
+    double rzp[8];
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) rzp[cc] = 0.0;
+    constexpr int kOb = 2;
+#pragma unroll
+    for (int k0 = 0; k0 < kOut; k0 += kOb) {
+      double2 rv[kOb];
+      if (part) {
+#pragma unroll
+        for (int k = 0; k < kOb; ++k) {
+          const int idx = threadIdx.x + (k0 + k) * kPcWaves * 64;
+          const int cc = idx >> 8, er = idx & 255;
+          const int c = h + cc, q = er & 1, row = i0 + (er >> 1);
+          const bool in = c < nc && row < (q ? n1 : n0);
+          rv[k] = r[(int64_t)(c0 + (in ? c : 0)) * vlen + (in ? e00 + 2 * i0 + er : e00)];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kOb; ++k) {
+        const int idx = threadIdx.x + (k0 + k) * kPcWaves * 64;
+        const int cc = idx >> 8, er = idx & 255;
+        const int c = h + cc, q = er & 1, row = i0 + (er >> 1);
+        if (c < nc && row < (q ? n1 : n0)) {
+          const float* v = stage + idx * 2;
+          const double sr = (double)so[k & 1];
+          const double2 zv = make_double2(sr * (double)v[0], sr * (double)v[1]);
+          z[(int64_t)(c0 + c) * vlen + e00 + 2 * i0 + er] = zv;
+          if (part) rzp[(k0 + k) >> 1] += fma(rv[k].x, zv.x, rv[k].y * zv.y);
+        }
+      }
+    }
+    if (part) {
+      // per column: sum over the wavefront (fixed butterfly order), then
+      // over the two wavefronts; weight 1 for m = 0, 2 otherwise
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) {
+        double v = rzp[cc];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        rzp[cc] = v;
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) red[w * 8 + cc] = rzp[cc];
+      }
+      __syncthreads();
+      if (threadIdx.x < 8 && h + (int)threadIdx.x < nc)
+        part[(int64_t)(c0 + h + threadIdx.x) * pstride + blockIdx.x] = wt * (red[threadIdx.x] + red[8 + threadIdx.x]);
+    }
+  }
+}
+
+// FP32 path of one wavefront: rows [i0, i0 + 128) of its block. Loads
+// without per-lane conditions (a branch around each load defeats the overlap
+// of the next group's loads with this group's products): rows j >= n read
+// row n - 1 and lanes past the padded row width read columns 0 .. 3, all
+// finite entries whose products meet zero B operands (rows j >= n of the
+// staged tile) or land in output rows never written.
+__device__ __forceinline__ void pc_apply_wave32(const float* __restrict__ Ab, int nrhs, int64_t vlen,
+                                                const float* __restrict__ scale, const double2* __restrict__ r,
+                                                double2* __restrict__ z, float (*rs)[kPcJ][33], int w, int il,
+                                                int kk, int n, int n0, int n1, int ld, int i0, int64_t e00,
+                                                double* __restrict__ part, int pstride, double wt, double* red) {
   const int lane = threadIdx.x & 63;
-  using Vec = typename std::conditional<H16, f16x4_t, f32x4_t>::type;
-  // K steps per prefetch group: twice as many for FP16, the same bytes in flight
-  constexpr int kPre = H16 ? 2 * kPcPre : kPcPre;
-  static_assert((kPcJ / 2) % kPre == 0, "tile must hold whole prefetch groups");
-  constexpr int kSteps = kPcJ / 2;                          // K steps per LDS tile
-  constexpr int kR = 2 * kPcJ * kPcCols / (kPcWaves * 64);  // residual values staged per thread and tile
+  constexpr int kSteps = kPcJ / 2;   // K steps per LDS tile
+  constexpr int kGpt = kSteps / kPcPre;
   const int ntile = (n0 + kPcJ - 1) / kPcJ;
   for (int c0 = 0; c0 < nrhs; c0 += kPcCols) {
     const int nc = min(kPcCols, nrhs - c0);
     f32x16_t acc0 = {}, acc1 = {}, acc2 = {}, acc3 = {};
-    // groups of kPre K steps over all j; a new LDS tile every kSteps / kPre
-    // groups; the A operands of group G + 1 are requested before the products of G
-    constexpr int kGpt = kSteps / kPre;
+    // groups of kPcPre K steps over all j; a new LDS tile every kGpt groups;
+    // the A operands of group G + 1 are requested before the products of G
     const int ngrp = ntile * kGpt;
-    // Loads without per-lane conditions (a branch around each load defeats
-    // the overlap of the next group's loads with this group's products):
-    // rows j >= n read row n - 1 and lanes past the padded row width read
-    // columns 0 .. 3, all finite entries whose products meet zero B operands
-    // (rows j >= n of the staged tile) or land in output rows never written.
-    Vec an[kPre] = {};
+    f32x4_t an[kPcPre] = {};
     auto fetch = [&](int G) {
       if (i0 >= n) return;   // wavefront-uniform: no rows of this block here
-      const int jg = 2 * G * kPre + kk;
+      const int jg = 2 * G * kPcPre + kk;
 #pragma unroll
-      for (int u = 0; u < kPre; ++u) {
+      for (int u = 0; u < kPcPre; ++u) {
         const int j = min(jg + 2 * u, n - 1);
-        an[u] = *reinterpret_cast<const Vec*>(Ab + (size_t)j * ld);
+        an[u] = *reinterpret_cast<const f32x4_t*>(Ab + (size_t)j * ld);
       }
     };
     fetch(0);
@@ -326,140 +452,132 @@ __device__ __forceinline__ void pc_apply_wave(const typename std::conditional<H1
     for (int G = 0; G < ngrp; ++G) {
       const int g0 = G % kGpt;
       if (g0 == 0) {
-        const int j0 = (G / kGpt) * kPcJ;
-        __syncthreads();                                    // previous tile's products have read rs
-        // consecutive threads read consecutive coefficients (both parities),
-        // in batches of kStage to bound the registers held by loads in
-        // flight; the loads carry no per-lane condition (elements outside the
-        // blocks or columns read element e00 of column c0 and are zeroed by
-        // their scale factor), so each batch's loads are in flight together
-        constexpr int kStage = 4;
-        static_assert(kR % kStage == 0, "whole staging batches");
-#pragma unroll 1
-        for (int k0 = 0; k0 < kR; k0 += kStage) {
-          double2 v[kStage];
-          float sv[kStage];
-#pragma unroll
-          for (int k = 0; k < kStage; ++k) {
-            const int e = threadIdx.x + (k0 + k) * kPcWaves * 64;
-            const int ee = e % (2 * kPcJ), cc = e / (2 * kPcJ);
-            const int q = ee & 1, j = j0 + (ee >> 1);
-            const bool in = cc < nc && j < (q ? n1 : n0);
-            const int64_t el = in ? e00 + 2 * j0 + ee : e00;
-            v[k] = r[(int64_t)(c0 + (in ? cc : 0)) * vlen + el];
-            sv[k] = scale[el];
-            sv[k] = in ? sv[k] : 0.f;
-          }
-#pragma unroll
-          for (int k = 0; k < kStage; ++k) {
-            const int e = threadIdx.x + (k0 + k) * kPcWaves * 64;
-            const int ee = e % (2 * kPcJ), cc = e / (2 * kPcJ);
-            const int q = ee & 1, jj = ee >> 1;
-            rs[q][jj][2 * cc] = (float)(v[k].x * sv[k]);
-            rs[q][jj][2 * cc + 1] = (float)(v[k].y * sv[k]);
-          }
-        }
+        __syncthreads();   // previous tile's products have read rs
+        pc_stage(rs, (G / kGpt) * kPcJ, c0, nc, n0, n1, vlen, e00, r, scale);
         __syncthreads();
       }
-      Vec ac[kPre];
+      f32x4_t ac[kPcPre];
 #pragma unroll
-      for (int u = 0; u < kPre; ++u) ac[u] = an[u];
+      for (int u = 0; u < kPcPre; ++u) ac[u] = an[u];
       if (G + 1 < ngrp) fetch(G + 1);
       if (i0 < n) {
 #pragma unroll
-        for (int u = 0; u < kPre; ++u) {
-          const float bval = rs[w][2 * (g0 * kPre + u) + kk][il];
-          acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32((float)ac[u][0], bval, acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32((float)ac[u][1], bval, acc1, 0, 0, 0);
-          acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32((float)ac[u][2], bval, acc2, 0, 0, 0);
-          acc3 = __builtin_amdgcn_mfma_f32_32x32x2f32((float)ac[u][3], bval, acc3, 0, 0, 0);
+        for (int u = 0; u < kPcPre; ++u) {
+          const float bval = rs[w][2 * (g0 * kPcPre + u) + kk][il];
+          acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[u][0], bval, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[u][1], bval, acc1, 0, 0, 0);
+          acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[u][2], bval, acc2, 0, 0, 0);
+          acc3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[u][3], bval, acc3, 0, 0, 0);
         }
       }
     }
-    // results through LDS (the rs tile, free after the last products), 8
-    // columns at a time, then written as whole rows of both parities: the
-    // task's 256 interleaved coefficients of a column are contiguous
-    float* stage = &rs[0][0][0];   // [8 columns][256 coefficients][re, im]
     const int rhs = il >> 1, comp = il & 1;
-    const int ib = i0 + 16 * kk;
+    pc_output(
+        [&](float* stage, int h) {
+          if (i0 < n && rhs >= h && rhs < h + 8) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const f32x16_t a = v == 0 ? acc0 : v == 1 ? acc1 : v == 2 ? acc2 : acc3;
+#pragma unroll
+              for (int q = 0; q < 16; ++q) {
+                // row i of accumulator v is i0 + 4 i + v, i = 8 (q / 4) + 4 kk + q % 4
+                const int ro = 4 * (8 * (q / 4) + 4 * kk + (q % 4)) + v;
+                stage[((rhs - h) * 256 + 2 * ro + w) * 2 + comp] = a[q];
+              }
+            }
+          }
+        },
+        rs, c0, nc, n0, n1, i0, vlen, e00, scale, r, z, part, pstride, wt, red, w, lane);
+  }
+}
+
+// FP16 path of one wavefront: rows [i0, i0 + 128) of its block, i.e. the
+// four row tiles i0 / 32 .. i0 / 32 + 3 (clamped to the block's last tile;
+// rows past the block are never written). At: the block's first tile of row
+// tile i0 / 32, plus this lane's 8 entries. Steps past the block's last
+// column tile read that tile again and meet zero B operands.
+__device__ __forceinline__ void pc_apply_wave16(const _Float16* __restrict__ At, int ntj, int ntr, int nrhs,
+                                                int64_t vlen, const float* __restrict__ scale,
+                                                const double2* __restrict__ r, double2* __restrict__ z,
+                                                float (*rs)[kPcJ][33], int w, int il, int kk, int n, int n0,
+                                                int n1, int i0, int64_t e00, double* __restrict__ part,
+                                                int pstride, double wt, double* red) {
+  const int lane = threadIdx.x & 63;
+  constexpr int kSpt = kPcJ / 16;   // K steps of 16 columns per LDS tile
+  const int nst = ((n0 + kPcJ - 1) / kPcJ) * kSpt;
+  for (int c0 = 0; c0 < nrhs; c0 += kPcCols) {
+    const int nc = min(kPcCols, nrhs - c0);
+    f32x16_t acc[4] = {};
+    int eb = 0;   // biased exponent of the running max of |S r| of this lane's column
+    f16x8_t an[4] = {};
+    auto fetch = [&](int st) {
+      if (i0 >= n) return;   // wavefront-uniform: no rows of this block here
+      const int tj = min(st, ntj - 1);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        an[t] = *reinterpret_cast<const f16x8_t*>(At + ((size_t)min(t, ntr - 1) * ntj + tj) * 512);
+    };
+    fetch(0);
 #pragma unroll 1
-    for (int h = 0; h < kPcCols; h += 8) {
-      __syncthreads();   // the products (or the previous half's writes) have read the tile
-      if (i0 < n && rhs >= h && rhs < h + 8) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const f32x16_t a = v == 0 ? acc0 : v == 1 ? acc1 : v == 2 ? acc2 : acc3;
-#pragma unroll
-          for (int q = 0; q < 16; ++q) {
-            const int rr = 4 * (8 * (q / 4) + (q % 4)) + v;
-            stage[((rhs - h) * 256 + 2 * (ib - i0 + rr) + w) * 2 + comp] = a[q];
-          }
-        }
-      }
-      __syncthreads();
-      // this thread's coefficients are the same for every column: their
-      // scales are read once, without per-lane conditions
-      constexpr int kOut = 8 * 256 / (kPcWaves * 64);
-      float so[2];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int er = (threadIdx.x + t * kPcWaves * 64) & 255, q = er & 1, row = i0 + (er >> 1);
-        so[t] = scale[row < (q ? n1 : n0) ? e00 + 2 * i0 + er : e00];
-      }
-      // thread t writes coefficients t and t + 128 of columns h .. h + 7;
-      // with part, it also sums their terms of <r, z> per column (r loaded
-      // in batches, without per-lane conditions)
-      double rzp[8];
-#pragma unroll
-      for (int cc = 0; cc < 8; ++cc) rzp[cc] = 0.0;
-      constexpr int kOb = 2;
-#pragma unroll
-      for (int k0 = 0; k0 < kOut; k0 += kOb) {
-        double2 rv[kOb];
-        if (part) {
-#pragma unroll
-          for (int k = 0; k < kOb; ++k) {
-            const int idx = threadIdx.x + (k0 + k) * kPcWaves * 64;
-            const int cc = idx >> 8, er = idx & 255;
-            const int c = h + cc, q = er & 1, row = i0 + (er >> 1);
-            const bool in = c < nc && row < (q ? n1 : n0);
-            rv[k] = r[(int64_t)(c0 + (in ? c : 0)) * vlen + (in ? e00 + 2 * i0 + er : e00)];
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < kOb; ++k) {
-          const int idx = threadIdx.x + (k0 + k) * kPcWaves * 64;
-          const int cc = idx >> 8, er = idx & 255;
-          const int c = h + cc, q = er & 1, row = i0 + (er >> 1);
-          if (c < nc && row < (q ? n1 : n0)) {
-            const float* v = stage + idx * 2;
-            const double sr = (double)so[k & 1];
-            const double2 zv = make_double2(sr * (double)v[0], sr * (double)v[1]);
-            z[(int64_t)(c0 + c) * vlen + e00 + 2 * i0 + er] = zv;
-            if (part) rzp[(k0 + k) >> 1] += fma(rv[k].x, zv.x, rv[k].y * zv.y);
-          }
-        }
-      }
-      if (part) {
-        // per column: sum over the wavefront (fixed butterfly order), then
-        // over the two wavefronts; weight 1 for m = 0, 2 otherwise
-#pragma unroll
-        for (int cc = 0; cc < 8; ++cc) {
-          double v = rzp[cc];
-#pragma unroll
-          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-          rzp[cc] = v;
-        }
-        if (lane == 0) {
-#pragma unroll
-          for (int cc = 0; cc < 8; ++cc) red[w * 8 + cc] = rzp[cc];
-        }
+    for (int st = 0; st < nst; ++st) {
+      const int s0 = st % kSpt;
+      if (s0 == 0) {
+        __syncthreads();   // previous tile's products have read rs
+        pc_stage(rs, (st / kSpt) * kPcJ, c0, nc, n0, n1, vlen, e00, r, scale);
         __syncthreads();
-        if (threadIdx.x < 8 && h + (int)threadIdx.x < nc)
-          part[(int64_t)(c0 + h + threadIdx.x) * pstride + blockIdx.x] =
-              wt * (red[threadIdx.x] + red[8 + threadIdx.x]);
+      }
+      f16x8_t ac[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) ac[t] = an[t];
+      if (st + 1 < nst) fetch(st + 1);
+      if (i0 < n) {
+        // B operand: column il of S r at rows 16 s0 + 8 kk + e, e = 0..7
+        float v[8];
+        float mx = 0.f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          v[e] = rs[w][16 * s0 + 8 * kk + e][il];
+          mx = fmaxf(mx, fabsf(v[e]));
+        }
+        mx = fmaxf(mx, __shfl_xor(mx, 32));   // lanes il and il + 32 hold the same column
+        const int ebn = (__float_as_int(mx) >> 23) & 0xff;
+        if (ebn > eb) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[t][q] = ldexpf(acc[t][q], eb - ebn);
+          eb = ebn;
+        }
+        f16x8_t bh, bl;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float y = ldexpf(v[e], kF16Shift - eb);
+          const _Float16 hi = (_Float16)y;
+          bh[e] = hi;
+          bl[e] = (_Float16)(y - (float)hi);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ac[t], bh, acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ac[t], bl, acc[t], 0, 0, 0);
+        }
       }
     }
+    const int rhs = il >> 1, comp = il & 1;
+    pc_output(
+        [&](float* stage, int h) {
+          if (i0 < n && rhs >= h && rhs < h + 8) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+              for (int q = 0; q < 16; ++q) {
+                // row i of tile t is i0 + 32 t + i, i = 8 (q / 4) + 4 kk + q % 4
+                const int ro = 32 * t + 8 * (q / 4) + 4 * kk + (q % 4);
+                stage[((rhs - h) * 256 + 2 * ro + w) * 2 + comp] = ldexpf(acc[t][q], eb - kF16Shift);
+              }
+          }
+        },
+        rs, c0, nc, n0, n1, i0, vlen, e00, scale, r, z, part, pstride, wt, red, w, lane);
   }
 }
 
@@ -468,13 +586,12 @@ __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3
     int nrhs, int64_t vlen, const int64_t* __restrict__ be0, const int* __restrict__ task_b,
     const int* __restrict__ task_b1, const int* __restrict__ task_r0, const int* __restrict__ bn,
     const int64_t* __restrict__ boff, const int* __restrict__ bhalf, const float* __restrict__ inv,
-    const float* __restrict__ scale, const int* __restrict__ bm, const double2* __restrict__ r,
-    double2* __restrict__ z, double* __restrict__ part, int pstride, const int* __restrict__ pred) {
+    const int64_t* __restrict__ boff16, const _Float16* __restrict__ inv16, const float* __restrict__ scale,
+    const int* __restrict__ bm, const double2* __restrict__ r, double2* __restrict__ z,
+    double* __restrict__ part, int pstride, const int* __restrict__ pred) {
   if (pred && *pred) return;
-  constexpr int kSteps = kPcJ / 2;                          // K steps per LDS tile
-  constexpr int kR = 2 * kPcJ * kPcCols / (kPcWaves * 64);  // residual values staged per thread and tile
-  static_assert(kSteps % kPcPre == 0, "tile must hold whole prefetch groups");
-  static_assert(kR % 4 == 0, "residual staging in batches of 4");
+  static_assert((kPcJ / 2) % kPcPre == 0, "tile must hold whole prefetch groups");
+  static_assert(kPcJ % 16 == 0, "tile must hold whole 16-column steps");
   static_assert(kPcWaves == 2, "one wavefront per parity block");
   __shared__ float rs[2][kPcJ][33];
   __shared__ double red[2 * 8];
@@ -490,21 +607,22 @@ __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3
   const int n0 = bn[b0];                                    // the even block is the larger one
   const int n1 = b1 >= 0 ? bn[b1] : 0;
   const int n = w == 0 ? n0 : n1;
-  const int ld = pc_ld(n);
   const int il = lane & 31, kk = lane >> 5;
   const int i0 = task_r0[blockIdx.x];
-  const int ic = i0 + 4 * il;                               // first of this lane's 4 rows
-  const bool colok = ic < ld;                               // padding columns n .. ld - 1 hold zeros
   const int64_t e00 = be0[b0];                              // element of row j of block q: e00 + q + 2 j
-  const float* __restrict__ base = inv + (b >= 0 ? boff[b] : 0);
   const double wt = bm[b0] == 0 ? 1.0 : 2.0;               // real-field inner product weight of m
-  // the two wavefronts may take different storage types; both pass the same barriers
-  if (b >= 0 && bhalf[b])
-    pc_apply_wave<true>(reinterpret_cast<const _Float16*>(base) + (colok ? ic : 0), nrhs, vlen, scale, r, z, rs,
-                        w, il, kk, n, n0, n1, ld, i0, e00, part, pstride, wt, red);
-  else
-    pc_apply_wave<false>(base + (colok ? ic : 0), nrhs, vlen, scale, r, z, rs, w, il, kk, n, n0, n1, ld, i0, e00,
-                         part, pstride, wt, red);
+  if (b >= 0 && bhalf[b]) {
+    const int ntj = pc_tiles_j(n);
+    const int ntr = pc_tiles_i(n) - i0 / 32;               // row tiles of this task in the block (>= 1)
+    pc_apply_wave16(inv16 + boff16[b] + (size_t)(i0 / 32) * ntj * 512 + lane * 8, ntj, ntr, nrhs, vlen, scale, r,
+                    z, rs, w, il, kk, n, n0, n1, i0, e00, part, pstride, wt, red);
+  } else {
+    const int ld = pc_ld(n);
+    const int ic = i0 + 4 * il;                             // first of this lane's 4 rows
+    const bool colok = ic < ld;                             // padding columns n .. ld - 1 hold zeros
+    pc_apply_wave32(inv + (b >= 0 ? boff[b] : 0) + (colok ? ic : 0), nrhs, vlen, scale, r, z, rs, w, il, kk, n,
+                    n0, n1, ld, i0, e00, part, pstride, wt, red);
+  }
 }
 
 // partial <r, z> (row 0) and, with rr, <r, r> (row 1) per column
@@ -551,8 +669,8 @@ int dev_upload(T** p, const std::vector<T>& h) {
 }  // namespace
 
 void block_pc_free(BlockPC& pc) {
-  void* ptrs[] = {pc.inv, pc.scale, pc.bhalf, pc.part, pc.bm, pc.bq, pc.bn, pc.boff, pc.be0, pc.task_b, pc.task_b1,
-                  pc.task_r0};
+  void* ptrs[] = {pc.inv, pc.inv16, pc.boff16, pc.scale, pc.bhalf, pc.part, pc.bm, pc.bq, pc.bn, pc.boff, pc.be0,
+                  pc.task_b, pc.task_b1, pc.task_r0};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   pc = BlockPC();
@@ -578,8 +696,8 @@ int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
   // blocks (component, m, parity), component-major: sizes, vector element of
   // row 0, compact FP32 offsets; then the application tasks
   std::vector<int> bm, bq, bn;
-  std::vector<int64_t> boff, be0;
-  int64_t off = 0;
+  std::vector<int64_t> boff, be0, boff16;
+  int64_t off = 0, off16 = 0;
   for (int k = 0; k < ncomp; ++k) {
     int64_t mst = 0;   // first element of m (m-major storage, l = m .. lmax)
     for (int m = 0; m <= mmax; ++m) {
@@ -592,6 +710,8 @@ int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
         be0.push_back((int64_t)k * g.nalm + mst + qq);
         boff.push_back(off);
         off += (int64_t)n * pc_ld(n);
+        boff16.push_back(off16);
+        off16 += (int64_t)512 * pc_tiles_i(n) * pc_tiles_j(n);
       }
       mst += lmax - m + 1;
     }
@@ -643,6 +763,7 @@ int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
   if ((rc = dev_upload(&pc.bm, bm)) || (rc = dev_upload(&pc.bq, bq)) || (rc = dev_upload(&pc.bn, bn)) ||
       (rc = dev_upload(&pc.boff, boff)) || (rc = dev_upload(&pc.be0, be0)) || (rc = dev_upload(&pc.task_b, tb)) || (rc = dev_upload(&pc.task_b1, tb1)) ||
       (rc = dev_upload(&pc.task_r0, tr)) || (rc = dev_alloc(&pc.inv, (size_t)off)) ||
+      (rc = dev_upload(&pc.boff16, boff16)) || (rc = dev_alloc(&pc.inv16, (size_t)off16)) ||
       (rc = dev_alloc(&pc.scale, (size_t)ncomp * g.nalm)) || (rc = dev_alloc(&pc.bhalf, (size_t)nb)) ||
       (rc = dev_alloc(&pc.part, (size_t)P->nrhs_max * tb.size()))) {
     block_pc_free(pc);
@@ -784,7 +905,7 @@ int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
                                                     dinfo2, nbat) == rocblas_status_success;
         if (ok) {
           hipLaunchKernelGGL(k_pc_half, dim3((npad + 255) / 256, npad, nbat), dim3(256), 0, s, dblocks, pc.bn,
-                             pc.boff, npad, C, dinfo2, pc.inv, pc.bhalf);
+                             pc.boff16, npad, C, dinfo2, pc.inv16, pc.bhalf);
           ok = hipGetLastError() == hipSuccess;
         }
         ok = ok && hipStreamSynchronize(s) == hipSuccess;   // scratch is reused by the next batch
@@ -818,7 +939,7 @@ hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, doub
   const BlockPC& pc = P->pc;
   timing_begin(P, 5, s);
   hipLaunchKernelGGL(k_pc_apply, dim3(pc.ntasks), dim3(kPcWaves * 64), 0, s, nrhs, vlen(P), pc.be0, pc.task_b,
-                     pc.task_b1, pc.task_r0, pc.bn, pc.boff, pc.bhalf, pc.inv, pc.scale, pc.bm, r, z,
+                     pc.task_b1, pc.task_r0, pc.bn, pc.boff, pc.bhalf, pc.inv, pc.boff16, pc.inv16, pc.scale, pc.bm, r, z,
                      dots ? pc.part : nullptr, pc.ntasks, P->pred);
   timing_end(P, 5, s);
   return hipGetLastError();

@@ -224,7 +224,9 @@ struct BlockPC {
   int64_t inv_elems = 0;     // floats of storage (every block sized for FP32)
   int64_t stored_bytes = 0;  // bytes of the n x n entries of the stored inverses
   int nhalf = 0;             // blocks stored in FP16
-  float* inv = nullptr;      // Jacobi-scaled inverses, FP32 or FP16 per block
+  float* inv = nullptr;      // Jacobi-scaled inverses of the FP32 blocks ([n][pc_ld(n)] at float offset boff)
+  _Float16* inv16 = nullptr; // those of the FP16 blocks in MFMA operand tiles (from element boff16)
+  int64_t* boff16 = nullptr; // element offset of each block's FP16 tiles
   float* scale = nullptr;    // [ncomp * nalm] sqrt of the inverse's diagonal, per vector element
   int* bhalf = nullptr;      // per block: 1 if stored in FP16
   double* part = nullptr;    // [nrhs_max][ntasks] partials of <r, z> written by the application
