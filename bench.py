@@ -51,14 +51,14 @@ HBM_PEAK_GBS = 8000.0
 # --prec mixed / f64; probe-precond --nrhs 16) at Nside 512, scaled by the same
 # counters on a 1 GiB copy (FETCH x 2.0, WRITE x 1.0); valid only for the
 # 16-column temperature workload and while the kernel's source file hashes to
-# `src`.
+# `src`. (k_adj_mfma has none: the probe runs its plain form, the solve its
+# PCG form, which also reads p and writes q.)
 TRAFFIC = {
-    "k_adj_mfma": {"bytes": 959810048, "src": "60fc0ea3cc5df5e4"},
-    "k_synth_mfma": {"bytes": 697151488, "src": "60fc0ea3cc5df5e4"},
-    "k_ring<float2, RING_FUSED>": {"bytes": 851797888, "src": "bd3b18c2827acee1"},   # one pass (4 class launches)
+    "k_synth_mfma": {"bytes": 699248576, "src": "cdd511f347359444"},
+    "k_ring<float2, RING_FUSED>": {"bytes": 851798528, "src": "bd3b18c2827acee1"},   # one pass (4 class launches)
     "k_legendre_synth_mfma": {"bytes": 680593408, "src": "74e6c305f36a5103"},    # one launch of 8 columns
     "k_legendre_adj_mfma": {"bytes": 2 * 606706688, "src": "74e6c305f36a5103"},  # one transform (2 launches)
-    "k_pc_apply": {"bytes": 2382975339, "src": "bd48ba1ba3245378"},
+    "k_pc_apply": {"bytes": 2286730421, "src": "afb34cda84ace42e"},
 }
 
 
@@ -604,7 +604,7 @@ def kernel_roofline(args, plan, one_solve, nside, lmax, R, nc, mixed, use_block,
         # average work per launch: columns go in launches of at most 16
         kinfo[3] = ("k_synth_mfma (bf16x3 MFMA Legendre synthesis)", "mfma", 4 * T * cs / -(-cs // 16),
                     BF16_MFMA_PEAK_TFLOPS, "TFLOP/s", "legendre_mfma.hip")
-        kinfo[4] = ("k_adj_mfma (bf16x3 MFMA Legendre adjoint)", "mfma", 4 * T * ca / -(-ca // 16),
+        kinfo[4] = ("k_adj_mfma (bf16x3 MFMA Legendre adjoint; in the solve also q and <p, q>)", "mfma", 4 * T * ca / -(-ca // 16),
                     BF16_MFMA_PEAK_TFLOPS, "TFLOP/s", "legendre_mfma.hip")
 
     # FP64 Legendre kernels: the plain path, and in the mixed path the FP64

@@ -198,11 +198,15 @@ __global__ void k_cg_start(int64_t nalm, const int* __restrict__ idx_m, const do
 
 // sums partial[c][slot-row][0..nb) into scal; what = 0: start, 1: alpha, 2: beta,
 // 3: residual replacement
-__global__ void k_cg_scalars(int what, int nb, const double* __restrict__ partial, int npart,
-                             double* __restrict__ scal, double tol, int restart, const double* __restrict__ part0,
-                             int n0, const int* __restrict__ pred) {
+// (kScalBlock threads: the per-task and per-tile partials of the block
+// preconditioner and the fused adjoint number several thousand per column)
+constexpr int kScalBlock = 1024;
+__global__ __launch_bounds__(kScalBlock) void k_cg_scalars(int what, int nb, const double* __restrict__ partial,
+                                                           int npart, double* __restrict__ scal, double tol,
+                                                           int restart, const double* __restrict__ part0, int n0,
+                                                           const int* __restrict__ pred) {
   if (pred && *pred) return;
-  __shared__ double sh[kVecBlock];
+  __shared__ double sh[kScalBlock];
   const int c = blockIdx.x;
   const double* pa = partial + (size_t)c * npart * 4;
   double* sc = scal + c * kScalSlots;
@@ -656,7 +660,7 @@ hipError_t launch_cg_start(const crsht_plan* P, int nrhs, const double2* b, cons
 
 hipError_t launch_cg_scalars(const crsht_plan* P, int nrhs, int what, int nb, double tol, int restart,
                              hipStream_t s, const double* part0, int n0) {
-  hipLaunchKernelGGL(k_cg_scalars, dim3(nrhs), dim3(kVecBlock), 0, s, what, nb, P->w.partial, P->w.npart,
+  hipLaunchKernelGGL(k_cg_scalars, dim3(nrhs), dim3(kScalBlock), 0, s, what, nb, P->w.partial, P->w.npart,
                      P->w.scal, tol, restart, part0, n0, P->pred);
   return hipGetLastError();
 }
