@@ -105,6 +105,36 @@ def test_storage_precision_choice():
     plan.close()
 
 
+def test_fp16_products_scale_free():
+    """The FP16 products take S r in two FP16 parts after scaling each column
+    by a power of two from its running maximum: columns whose magnitudes
+    differ by 1e+-30 from each other (and a zero column, and one whose large
+    entries sit only in the last rows) give the oracle's result to the same
+    relative accuracy, and scaling a column by a power of two scales its
+    result exactly."""
+    m = _m()
+    nside, nrhs = 64, 6
+    print("case block pc fp16 products scale", nside, flush=True)
+    wl, P, op, d = masked_problem(nside)
+    plan = m.Plan(nside, wl.lmax, nrhs_max=nrhs)
+    m.block_precond_build(plan, _gp(m, P))
+    pc = BlockPreconditioner(op)
+    rng = np.random.default_rng(11)
+    base = op.project(ci.white_alm(rng, wl.lmax))
+    tail = base.copy()
+    ls = ci.alm_lm_arrays(wl.lmax)[0]
+    tail[ls < wl.lmax - 20] *= 1e-12   # the large entries only at the highest l
+    R = np.stack([base, base * 1e30, base * 1e-30, np.zeros_like(base), tail, base * 2.0 ** 40])
+    got = m.block_precond_apply(plan, tc(R)).cpu().numpy()
+    for c in (0, 1, 2, 4):
+        err = real_rel(op, got[c], pc(R[c]))
+        print("column %d rel err %.3e" % (c, err), flush=True)
+        assert err < PC_TOL
+    assert np.all(got[3] == 0.0)
+    assert np.array_equal(got[5], got[0] * 2.0 ** 40)
+    plan.close()
+
+
 @pytest.mark.parametrize("nside", [8, 32])
 def test_fp64_solve_with_block_preconditioner(nside):
     m = _m()
