@@ -285,6 +285,11 @@ struct crsht_plan {
   static constexpr int kRoundEvents = 3;
   hipEvent_t ev_round[kRoundEvents] = {};
   hipStream_t cap_stream = nullptr;     // stream used only to capture iteration blocks
+  // ring passes: the FFT-length classes after the first run on these
+  // streams, forked from and joined back to the caller's stream
+  static constexpr int kRingAux = 3;
+  hipStream_t ring_aux[kRingAux] = {};
+  hipEvent_t ring_fork = nullptr, ring_join[kRingAux] = {};
   hipGraphExec_t graph_exec = nullptr;  // last captured block
   crsht::GraphKey graph_key;
   crsht::BlockPC pc;                    // per-m block preconditioner (built on request)

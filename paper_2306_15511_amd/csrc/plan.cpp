@@ -97,6 +97,14 @@ void free_plan_memory(crsht_plan* P) {
   }
   crsht::block_pc_free(P->pc);
   if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
+  for (int k = 0; k < crsht_plan::kRingAux; ++k) {
+    if (P->ring_aux[k]) (void)hipStreamDestroy(P->ring_aux[k]);
+    if (P->ring_join[k]) (void)hipEventDestroy(P->ring_join[k]);
+    P->ring_aux[k] = nullptr;
+    P->ring_join[k] = nullptr;
+  }
+  if (P->ring_fork) (void)hipEventDestroy(P->ring_fork);
+  P->ring_fork = nullptr;
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
   if (P->exec_stream) (void)hipStreamDestroy(P->exec_stream);
   P->exec_stream = nullptr;
@@ -421,6 +429,20 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int ncomp, i
       *e = nullptr;
       return CR_EDEVICE;
     }
+  if (hipEventCreateWithFlags(&P->ring_fork, hipEventDisableTiming) != hipSuccess) {
+    P->ring_fork = nullptr;
+    return CR_EDEVICE;
+  }
+  for (int k = 0; k < crsht_plan::kRingAux; ++k) {
+    if (hipStreamCreateWithFlags(&P->ring_aux[k], hipStreamNonBlocking) != hipSuccess) {
+      P->ring_aux[k] = nullptr;
+      return CR_EDEVICE;
+    }
+    if (hipEventCreateWithFlags(&P->ring_join[k], hipEventDisableTiming) != hipSuccess) {
+      P->ring_join[k] = nullptr;
+      return CR_EDEVICE;
+    }
+  }
   {
     unsigned char* ds = nullptr;
     if ((rc = dalloc(&ds, R * sizeof(cr_stats), total))) return rc;

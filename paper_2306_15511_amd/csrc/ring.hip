@@ -583,15 +583,28 @@ hipError_t ring_launch(const crsht_plan* P, int nrhs, const V* eo, double* map, 
                        const V* tw, const V* chirp, const V* kern, RingCols cols, hipStream_t s) {
   const Geometry& g = P->g;
   const int64_t stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
-  for (size_t k = 0; k < P->ring_cls.size(); ++k) {
+  // the classes are independent (disjoint ring pairs): class 0 runs on the
+  // caller's stream, class k > 0 on auxiliary stream (k - 1) mod kRingAux,
+  // forked from and joined back to it (parallel branches when captured), so
+  // that the short launches of the small-ring classes overlap the large ones
+  const int ncls = (int)P->ring_cls.size();
+  const int naux = ncls - 1 < crsht_plan::kRingAux ? ncls - 1 : crsht_plan::kRingAux;
+  hipError_t e;
+  if (naux > 0) {
+    if ((e = hipEventRecord(P->ring_fork, s)) != hipSuccess) return e;
+    for (int a = 0; a < naux; ++a)
+      if ((e = hipStreamWaitEvent(P->ring_aux[a], P->ring_fork, 0)) != hipSuccess) return e;
+  }
+  for (int k = 0; k < ncls; ++k) {
     const RingClass& rc = P->ring_cls[k];
     const size_t lds = ring_lds<V>(rc.L);
-    const int nt = ring_class_threads(P, (int)k);
+    const int nt = ring_class_threads(P, k);
     const int64_t items = (int64_t)rc.count * nrhs;
     const unsigned nb = (unsigned)((items + 7) / 8 * 8);
+    hipStream_t q = k == 0 ? s : P->ring_aux[(k - 1) % crsht_plan::kRingAux];
 #define CRSHT_RING_LAUNCH(NT)                                                                                   \
   do {                                                                                                          \
-    hipLaunchKernelGGL((k_ring<V, MODE, NT>), dim3(nb), dim3(nt), lds, s, P->t, g.nside, g.mmax, g.fft_max,      \
+    hipLaunchKernelGGL((k_ring<V, MODE, NT>), dim3(nb), dim3(nt), lds, q, P->t, g.nside, g.mmax, g.fft_max,      \
                        P->t.ring_pairs + rc.off, rc.count, nrhs, rc.L, tw, chirp, kern, eo, stride, map,         \
                        (int64_t)g.npix, ninv, geo, stride, cols, P->pred);                                      \
   } while (0)
@@ -600,8 +613,11 @@ hipError_t ring_launch(const crsht_plan* P, int nrhs, const V* eo, double* map, 
     else
       CRSHT_RING_LAUNCH(1024);
 #undef CRSHT_RING_LAUNCH
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  for (int a = 0; a < naux; ++a) {
+    if ((e = hipEventRecord(P->ring_join[a], P->ring_aux[a])) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, P->ring_join[a], 0)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
