@@ -285,11 +285,12 @@ struct crsht_plan {
   static constexpr int kRoundEvents = 3;
   hipEvent_t ev_round[kRoundEvents] = {};
   hipStream_t cap_stream = nullptr;     // stream used only to capture iteration blocks
-  // ring passes: the FFT-length classes after the first run on these
-  // streams, forked from and joined back to the caller's stream
-  static constexpr int kRingAux = 3;
-  hipStream_t ring_aux[kRingAux] = {};
-  hipEvent_t ring_fork = nullptr, ring_join[kRingAux] = {};
+  // independent launches of one operation (ring-pass FFT-length classes,
+  // FP64 adjoint column groups) after the first run on these streams,
+  // forked from and joined back to the caller's stream (aux_fork / aux_join)
+  static constexpr int kAux = 3;
+  hipStream_t aux_stream[kAux] = {};
+  hipEvent_t aux_fork_ev = nullptr, aux_join_ev[kAux] = {};
   hipGraphExec_t graph_exec = nullptr;  // last captured block
   crsht::GraphKey graph_key;
   crsht::BlockPC pc;                    // per-m block preconditioner (built on request)
@@ -381,6 +382,11 @@ struct RingCols {
 hipError_t launch_ring(const crsht_plan* P, int nrhs, RingMode mode, const void* eo, double* map,
                        const double* ninv, void* geo, bool f32, hipStream_t s, RingCols cols = RingCols());
 void ring_classes(const std::vector<int>& fft_len, std::vector<RingClass>& cls, std::vector<int>& pairs);
+// the auxiliary streams 0 .. n - 1 wait for the work so far on s; aux_join:
+// s waits for them; aux_q(k): s for k = 0, else auxiliary stream (k - 1) mod kAux
+hipError_t aux_fork(const crsht_plan* P, int n, hipStream_t s);
+hipError_t aux_join(const crsht_plan* P, int n, hipStream_t s);
+hipStream_t aux_q(const crsht_plan* P, int k, hipStream_t s);
 // plan set-up: allow the dynamic LDS of the ring kernels the plan's classes need
 hipError_t ring_prepare(const crsht_plan* P);
 // once per plan: LDS limit of the FP64 matrix-core adjoint

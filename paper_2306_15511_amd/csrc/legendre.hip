@@ -745,16 +745,23 @@ hipError_t launch_legendre_adjoint(const crsht_plan* P, int nrhs, const double2*
     const int nb = ((g.mmax + 1 + 31) / 32) * 32;
     const size_t lds = (size_t)kAmWaves * 64 * kAmRow * sizeof(double);
     const int cpl = std::max(1, std::min(kAmCols, P->tune.f64_adj_cols));
+    // column groups are independent: group k on aux_q(k) (the launches over
+    // ring pairs of one group stay in order on its stream)
+    const int ngrp = (nrhs + cpl - 1) / cpl;
+    const int naux = std::min(ngrp - 1, crsht_plan::kAux);
+    err = aux_fork(P, naux, s);
     for (int c0 = 0; c0 < nrhs && err == hipSuccess; c0 += cpl) {
       const int nc = std::min(cpl, nrhs - c0);
+      hipStream_t q = aux_q(P, c0 / cpl, s);
       for (int p0 = 0; p0 < g.npairs && err == hipSuccess; p0 += kAmPairs) {
-        hipLaunchKernelGGL(k_legendre_adj_mfma, dim3(nb), dim3(kAmWaves * 64), lds, s, g.lmax, g.mmax, g.npairs,
+        hipLaunchKernelGGL(k_legendre_adj_mfma, dim3(nb), dim3(kAmWaves * 64), lds, q, g.lmax, g.mmax, g.npairs,
                            g.npairs, p0, p0 > 0 ? 1 : 0, nc, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
                            geo + (int64_t)c0 * geo_stride, geo_stride, raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm,
                            P->pred);
         err = hipGetLastError();
       }
     }
+    if (err == hipSuccess) err = aux_join(P, naux, s);
   } else {
     const int64_t geo_stride = (int64_t)P->g.npairs * (P->g.mmax + 1) * 2;
     const int nr_cap = adj_max_nr(adj_rpt(P));

@@ -97,14 +97,14 @@ void free_plan_memory(crsht_plan* P) {
   }
   crsht::block_pc_free(P->pc);
   if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
-  for (int k = 0; k < crsht_plan::kRingAux; ++k) {
-    if (P->ring_aux[k]) (void)hipStreamDestroy(P->ring_aux[k]);
-    if (P->ring_join[k]) (void)hipEventDestroy(P->ring_join[k]);
-    P->ring_aux[k] = nullptr;
-    P->ring_join[k] = nullptr;
+  for (int k = 0; k < crsht_plan::kAux; ++k) {
+    if (P->aux_stream[k]) (void)hipStreamDestroy(P->aux_stream[k]);
+    if (P->aux_join_ev[k]) (void)hipEventDestroy(P->aux_join_ev[k]);
+    P->aux_stream[k] = nullptr;
+    P->aux_join_ev[k] = nullptr;
   }
-  if (P->ring_fork) (void)hipEventDestroy(P->ring_fork);
-  P->ring_fork = nullptr;
+  if (P->aux_fork_ev) (void)hipEventDestroy(P->aux_fork_ev);
+  P->aux_fork_ev = nullptr;
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
   if (P->exec_stream) (void)hipStreamDestroy(P->exec_stream);
   P->exec_stream = nullptr;
@@ -429,17 +429,17 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int ncomp, i
       *e = nullptr;
       return CR_EDEVICE;
     }
-  if (hipEventCreateWithFlags(&P->ring_fork, hipEventDisableTiming) != hipSuccess) {
-    P->ring_fork = nullptr;
+  if (hipEventCreateWithFlags(&P->aux_fork_ev, hipEventDisableTiming) != hipSuccess) {
+    P->aux_fork_ev = nullptr;
     return CR_EDEVICE;
   }
-  for (int k = 0; k < crsht_plan::kRingAux; ++k) {
-    if (hipStreamCreateWithFlags(&P->ring_aux[k], hipStreamNonBlocking) != hipSuccess) {
-      P->ring_aux[k] = nullptr;
+  for (int k = 0; k < crsht_plan::kAux; ++k) {
+    if (hipStreamCreateWithFlags(&P->aux_stream[k], hipStreamNonBlocking) != hipSuccess) {
+      P->aux_stream[k] = nullptr;
       return CR_EDEVICE;
     }
-    if (hipEventCreateWithFlags(&P->ring_join[k], hipEventDisableTiming) != hipSuccess) {
-      P->ring_join[k] = nullptr;
+    if (hipEventCreateWithFlags(&P->aux_join_ev[k], hipEventDisableTiming) != hipSuccess) {
+      P->aux_join_ev[k] = nullptr;
       return CR_EDEVICE;
     }
   }

@@ -584,24 +584,20 @@ hipError_t ring_launch(const crsht_plan* P, int nrhs, const V* eo, double* map, 
   const Geometry& g = P->g;
   const int64_t stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
   // the classes are independent (disjoint ring pairs): class 0 runs on the
-  // caller's stream, class k > 0 on auxiliary stream (k - 1) mod kRingAux,
+  // caller's stream, class k > 0 on auxiliary stream (k - 1) mod kAux,
   // forked from and joined back to it (parallel branches when captured), so
   // that the short launches of the small-ring classes overlap the large ones
   const int ncls = (int)P->ring_cls.size();
-  const int naux = ncls - 1 < crsht_plan::kRingAux ? ncls - 1 : crsht_plan::kRingAux;
+  const int naux = ncls - 1 < crsht_plan::kAux ? ncls - 1 : crsht_plan::kAux;
   hipError_t e;
-  if (naux > 0) {
-    if ((e = hipEventRecord(P->ring_fork, s)) != hipSuccess) return e;
-    for (int a = 0; a < naux; ++a)
-      if ((e = hipStreamWaitEvent(P->ring_aux[a], P->ring_fork, 0)) != hipSuccess) return e;
-  }
+  if ((e = aux_fork(P, naux, s)) != hipSuccess) return e;
   for (int k = 0; k < ncls; ++k) {
     const RingClass& rc = P->ring_cls[k];
     const size_t lds = ring_lds<V>(rc.L);
     const int nt = ring_class_threads(P, k);
     const int64_t items = (int64_t)rc.count * nrhs;
     const unsigned nb = (unsigned)((items + 7) / 8 * 8);
-    hipStream_t q = k == 0 ? s : P->ring_aux[(k - 1) % crsht_plan::kRingAux];
+    hipStream_t q = aux_q(P, k, s);
 #define CRSHT_RING_LAUNCH(NT)                                                                                   \
   do {                                                                                                          \
     hipLaunchKernelGGL((k_ring<V, MODE, NT>), dim3(nb), dim3(nt), lds, q, P->t, g.nside, g.mmax, g.fft_max,      \
@@ -615,11 +611,7 @@ hipError_t ring_launch(const crsht_plan* P, int nrhs, const V* eo, double* map, 
 #undef CRSHT_RING_LAUNCH
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  for (int a = 0; a < naux; ++a) {
-    if ((e = hipEventRecord(P->ring_join[a], P->ring_aux[a])) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(s, P->ring_join[a], 0)) != hipSuccess) return e;
-  }
-  return hipSuccess;
+  return aux_join(P, naux, s);
 }
 
 template <class V>
@@ -695,6 +687,26 @@ size_t ring_lds_bytes(const crsht_plan* P, bool f32) {
     mx = b > mx ? b : mx;
   }
   return mx;
+}
+
+hipError_t aux_fork(const crsht_plan* P, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipError_t e = hipEventRecord(P->aux_fork_ev, s);
+  for (int a = 0; a < n && e == hipSuccess; ++a) e = hipStreamWaitEvent(P->aux_stream[a], P->aux_fork_ev, 0);
+  return e;
+}
+
+hipError_t aux_join(const crsht_plan* P, int n, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (int a = 0; a < n && e == hipSuccess; ++a) {
+    e = hipEventRecord(P->aux_join_ev[a], P->aux_stream[a]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, P->aux_join_ev[a], 0);
+  }
+  return e;
+}
+
+hipStream_t aux_q(const crsht_plan* P, int k, hipStream_t s) {
+  return k == 0 ? s : P->aux_stream[(k - 1) % crsht_plan::kAux];
 }
 
 hipError_t launch_ring(const crsht_plan* P, int nrhs, RingMode mode, const void* eo, double* map,
