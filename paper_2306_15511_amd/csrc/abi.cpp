@@ -365,9 +365,11 @@ int adjoint_f64(const crsht_plan* P, int nrhs, const double* map, double2* alm, 
 // HIP graph (kept with its key) and replayed on s; a different key
 // re-captures. Kernel timing (per-launch events) forces direct launches.
 template <class F>
-int run_block(const crsht_plan* Pc, const GraphKey& key, bool use_graph, hipStream_t s, F body) {
+int run_block(const crsht_plan* Pc, const GraphKey& key0, bool use_graph, hipStream_t s, F body) {
   crsht_plan* P = const_cast<crsht_plan*>(Pc);
   if (!use_graph || P->timing.on || !P->cap_stream) return body(s);
+  GraphKey key = key0;
+  key.aux_off = P->aux_off;
   if (!(P->graph_exec && P->graph_key == key)) {
     if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
     P->graph_exec = nullptr;
@@ -854,6 +856,7 @@ int dsolve_graphs(const DSolve& d, bool use_graph, bool* graphs) {
   key.itol = d.a.itol;
   key.maxref = d.a.maxref;
   key.maxiter = d.a.maxiter;
+  key.aux_off = P->aux_off;
   if (!(P->dgraph[0] && P->dgraph[1] && P->dgraph_key == key)) {
     if (P->dgraph[0] || P->dgraph[1]) {
       // replays of the old graphs may still be queued on some stream
@@ -1255,6 +1258,16 @@ extern "C" int cr_solve_batched(const crsht_plan* const* plans, const cr_problem
   for (int i = 0; i < nprob; ++i)
     if (plans[i]->device != dev) return CR_EINVAL;
   hipStream_t s = S(stream);
+  // the problems run concurrently on their plans' streams: no forked
+  // launches inside them for the duration of the call
+  struct AuxOff {
+    const crsht_plan* const* p;
+    int n;
+    ~AuxOff() {
+      for (int i = 0; i < n; ++i) p[i]->aux_off = false;
+    }
+  } aux_guard{plans, nprob};
+  for (int i = 0; i < nprob; ++i) plans[i]->aux_off = true;
   std::vector<DSolve> ds(nprob);
   std::vector<char> graphs(nprob, 0);
   for (int i = 0; i < nprob; ++i) {

@@ -247,9 +247,11 @@ struct GraphKey {
   double tol = 0.0;
   double itol = 0.0;        // device-driven solve: replacement factor, replacement and iteration limits
   int maxref = 0, maxiter = 0;
+  bool aux_off = false;     // captured without forked launches (batched solve)
   bool operator==(const GraphKey& o) const {
     return kind == o.kind && nrhs == o.nrhs && n == o.n && first_update == o.first_update && pc == o.pc &&
-           ninv == o.ninv && tol == o.tol && itol == o.itol && maxref == o.maxref && maxiter == o.maxiter;
+           ninv == o.ninv && tol == o.tol && itol == o.itol && maxref == o.maxref && maxiter == o.maxiter &&
+           aux_off == o.aux_off;
   }
 };
 }  // namespace crsht
@@ -289,6 +291,9 @@ struct crsht_plan {
   // FP64 adjoint column groups) after the first run on these streams,
   // forked from and joined back to the caller's stream (aux_fork / aux_join)
   static constexpr int kAux = 3;
+  // set while a batched solve runs the plan (its problems already run
+  // concurrently on their own streams): no forks then
+  mutable bool aux_off = false;
   hipStream_t aux_stream[kAux] = {};
   hipEvent_t aux_fork_ev = nullptr, aux_join_ev[kAux] = {};
   hipGraphExec_t graph_exec = nullptr;  // last captured block

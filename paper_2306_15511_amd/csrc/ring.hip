@@ -690,7 +690,7 @@ size_t ring_lds_bytes(const crsht_plan* P, bool f32) {
 }
 
 hipError_t aux_fork(const crsht_plan* P, int n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
+  if (n <= 0 || P->aux_off) return hipSuccess;
   hipError_t e = hipEventRecord(P->aux_fork_ev, s);
   for (int a = 0; a < n && e == hipSuccess; ++a) e = hipStreamWaitEvent(P->aux_stream[a], P->aux_fork_ev, 0);
   return e;
@@ -698,6 +698,7 @@ hipError_t aux_fork(const crsht_plan* P, int n, hipStream_t s) {
 
 hipError_t aux_join(const crsht_plan* P, int n, hipStream_t s) {
   hipError_t e = hipSuccess;
+  if (P->aux_off) return e;
   for (int a = 0; a < n && e == hipSuccess; ++a) {
     e = hipEventRecord(P->aux_join_ev[a], P->aux_stream[a]);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, P->aux_join_ev[a], 0);
@@ -706,7 +707,7 @@ hipError_t aux_join(const crsht_plan* P, int n, hipStream_t s) {
 }
 
 hipStream_t aux_q(const crsht_plan* P, int k, hipStream_t s) {
-  return k == 0 ? s : P->aux_stream[(k - 1) % crsht_plan::kAux];
+  return (k == 0 || P->aux_off) ? s : P->aux_stream[(k - 1) % crsht_plan::kAux];
 }
 
 hipError_t launch_ring(const crsht_plan* P, int nrhs, RingMode mode, const void* eo, double* map,
