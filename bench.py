@@ -54,10 +54,10 @@ HBM_PEAK_GBS = 8000.0
 # `src`. (k_adj_mfma has none: the probe runs its plain form, the solve its
 # PCG form, which also reads p and writes q.)
 TRAFFIC = {
-    "k_synth_mfma": {"bytes": 699248576, "src": "cdd511f347359444"},
-    "k_ring<float2, RING_FUSED>": {"bytes": 851798528, "src": "bd3b18c2827acee1"},   # one pass (4 class launches)
-    "k_legendre_synth_mfma": {"bytes": 680593408, "src": "74e6c305f36a5103"},    # one launch of 8 columns
-    "k_legendre_adj_mfma": {"bytes": 2 * 606706688, "src": "74e6c305f36a5103"},  # one transform (2 launches)
+    "k_synth_mfma": {"bytes": 698111936, "src": "cdd511f347359444"},
+    "k_ring<float2, RING_FUSED>": {"bytes": 851819264, "src": "76e554674a4903a5"},   # one pass (4 class launches)
+    "k_legendre_synth_mfma": {"bytes": 680150712, "src": "1b132e3aa1e8de89"},    # one launch of 8 columns
+    "k_legendre_adj_mfma": {"bytes": 2 * 606401768, "src": "1b132e3aa1e8de89"},  # one transform (2 launches)
     "k_pc_apply": {"bytes": 2286730421, "src": "afb34cda84ace42e"},
 }
 
