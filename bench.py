@@ -56,8 +56,8 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC = {
     "k_synth_mfma": {"bytes": 698111936, "src": "cdd511f347359444"},
     "k_ring<float2, RING_FUSED>": {"bytes": 851819264, "src": "76e554674a4903a5"},   # one pass (4 class launches)
-    "k_legendre_synth_mfma": {"bytes": 680150712, "src": "1b132e3aa1e8de89"},    # one launch of 8 columns
-    "k_legendre_adj_mfma": {"bytes": 2 * 606401768, "src": "1b132e3aa1e8de89"},  # one transform (2 launches)
+    "k_legendre_synth_mfma": {"bytes": 2 * 680435432, "src": "950022753ad0e9f2"},  # one transform (2 launches)
+    "k_legendre_adj_mfma": {"bytes": 2 * 606622440, "src": "950022753ad0e9f2"},  # one transform (2 launches)
     "k_pc_apply": {"bytes": 2286730421, "src": "afb34cda84ace42e"},
 }
 
@@ -615,8 +615,9 @@ def kernel_roofline(args, plan, one_solve, nside, lmax, R, nc, mixed, use_block,
         return [min(8, n - c) for c in range(0, n, 8)] if n >= 2 else [1]
     gs, ga = fp64_groups(cs), fp64_groups(ca)
     f64m = cs >= 2
-    kinfo[0] = ("k_legendre_synth_mfma (FP64 MFMA Legendre synthesis)" if f64m else "k_legendre_synth (FP64 VALU)",
-                "mfma" if f64m else "alu", sum((3 + 4 * g) * T for g in gs) / len(gs),
+    kinfo[0] = ("k_legendre_synth_mfma (FP64 MFMA Legendre synthesis, whole transform)" if f64m
+                else "k_legendre_synth (FP64 VALU)",
+                "mfma" if f64m else "alu", sum((3 + 4 * g) * T for g in gs) / (1 if f64m else len(gs)),
                 FP64_MATRIX_PEAK_TFLOPS if f64m else FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s", "legendre.hip")
     kinfo[1] = ("k_legendre_adj_mfma (FP64 MFMA Legendre adjoint, whole transform)" if ca >= 2
                 else "k_legendre_adj (FP64 VALU, whole transform)", "mfma" if ca >= 2 else "alu",

@@ -665,19 +665,22 @@ hipError_t launch_legendre_synth(const crsht_plan* P, int nrhs, const double2* a
     const int ngroups = (g.npairs + 63) / 64;
     const int nb = 8 * ngroups * ((g.mmax + 1 + 7) / 8);
     const int cpl = std::max(1, std::min(kAmCols, P->tune.f64_synth_cols));
-    for (int c0 = 0; c0 < nrhs; c0 += cpl) {
+    // column groups are independent: group k on aux_q(k); timed as a whole
+    const int ngrp = (nrhs + cpl - 1) / cpl;
+    const int naux = std::min(ngrp - 1, crsht_plan::kAux);
+    timing_begin(P, 0, s);
+    hipError_t err = aux_fork(P, naux, s);
+    for (int c0 = 0; c0 < nrhs && err == hipSuccess; c0 += cpl) {
       const int nc = std::min(cpl, nrhs - c0);
-      timing_begin(P, 0, s);
-      hipLaunchKernelGGL(k_legendre_synth_mfma, dim3(nb), dim3(64), 0, s, g.lmax, g.mmax, g.npairs, g.npairs, nc,
-                         ngroups,
-                         P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
-                         alms + (int64_t)c0 * g.nalm, (int64_t)g.nalm, eo + (int64_t)c0 * eo_stride, eo_stride,
-                         P->pred);
-      timing_end(P, 0, s);
-      const hipError_t err = hipGetLastError();
-      if (err != hipSuccess) return err;
+      hipLaunchKernelGGL(k_legendre_synth_mfma, dim3(nb), dim3(64), 0, aux_q(P, c0 / cpl, s), g.lmax, g.mmax,
+                         g.npairs, g.npairs, nc, ngroups, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s,
+                         P->t.mstart, alms + (int64_t)c0 * g.nalm, (int64_t)g.nalm, eo + (int64_t)c0 * eo_stride,
+                         eo_stride, P->pred);
+      err = hipGetLastError();
     }
-    return hipSuccess;
+    if (err == hipSuccess) err = aux_join(P, naux, s);
+    timing_end(P, 0, s);
+    return err;
   }
   for (int c0 = 0; c0 < nrhs;) {
     const int nr = pick_nr(nrhs - c0);
