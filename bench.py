@@ -58,7 +58,7 @@ TRAFFIC = {
     "k_ring<float2, RING_FUSED>": {"bytes": 851819264, "src": "76e554674a4903a5"},   # one pass (4 class launches)
     "k_legendre_synth_mfma": {"bytes": 2 * 680435432, "src": "950022753ad0e9f2"},  # one transform (2 launches)
     "k_legendre_adj_mfma": {"bytes": 2 * 606622440, "src": "950022753ad0e9f2"},  # one transform (2 launches)
-    "k_pc_apply": {"bytes": 2286730421, "src": "afb34cda84ace42e"},
+    "k_pc_apply": {"bytes": 2288146197, "src": "fc77c053960ec824"},
 }
 
 

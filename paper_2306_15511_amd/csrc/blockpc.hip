@@ -29,12 +29,13 @@
 // kernel, the Gram matrix L L^T is formed with rocBLAS SYRK, the prior
 // diagonal added, and the inverse computed with rocSOLVER (Cholesky, then
 // inverse from the factor); the inverses are stored Jacobi-scaled, full
-// symmetric, per block in FP16 where that provably keeps them positive
-// definite, else in FP32 (see k_pc_store).
+// symmetric, per block in FP16 (in MFMA operand tiles, see k_pc_half) where
+// that provably keeps them positive definite, else in FP32 (see k_pc_store).
 // Application (every PCG iteration): z_b = M_b^-1 r_b for the real and
 // imaginary parts of every column and every block of every component on the
-// matrix cores (FP32 products), one workgroup per 128 rows of both parity
-// blocks of one m (one wavefront each).
+// matrix cores (FP16 products for FP16 blocks, FP32 for the others, FP32
+// accumulation), one workgroup per 128 rows of both parity blocks of one m
+// (one wavefront each).
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
