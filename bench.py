@@ -47,12 +47,13 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0     # dense
 HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of a kernel per timed unit from rocprofv3 --pmc FETCH_SIZE /
-# WRITE_SIZE runs of this script's probe workloads (probe-operator --nrhs 16
-# --prec mixed / f64; probe-precond --nrhs 16) at Nside 512, scaled by the same
-# counters on a 1 GiB copy (FETCH x 2.0, WRITE x 1.0); valid only for the
-# 16-column temperature workload and while the kernel's source file hashes to
-# `src`. (k_adj_mfma has none: the probe runs its plain form, the solve its
-# PCG form, which also reads p and writes q.)
+# WRITE_SIZE runs of this script's probe workload probe-operator (--nrhs 16
+# --prec mixed / f64) and, for k_pc_apply, of the headline solve itself (its
+# FP32-z form), at Nside 512, scaled by the same counters on a 1 GiB copy
+# (FETCH x 2.0, WRITE x 1.0); valid only for the 16-column temperature
+# workload and while the kernel's source file hashes to `src`. (k_adj_mfma
+# has none: the probe runs its plain form, the solve its PCG form, which
+# also reads p and writes q.)
 TRAFFIC = {
     "k_synth_mfma": {"bytes": 698111936, "src": "cdd511f347359444"},
     "k_ring<float2, RING_FUSED>": {"bytes": 851819264, "src": "76e554674a4903a5"},   # one pass (4 class launches)
@@ -625,11 +626,12 @@ def kernel_roofline(args, plan, one_solve, nside, lmax, R, nc, mixed, use_block,
                 FP64_MATRIX_PEAK_TFLOPS if ca >= 2 else FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s", "legendre.hip")
     if use_block:
         # the n x n entries of the stored scaled inverses (FP16 or FP32 per
-        # block, as the build chose) + their FP32 diagonal scales + r read +
-        # z written
+        # block, as the build chose) + their FP32 diagonal scales + r read
+        # (FP64) + z written (FP32 in the mixed T solve, else FP64)
         pcb = plan.precond_info()[0]
+        zb = 8 if (mixed and not tqu) else 16
         kinfo[5] = ("k_pc_apply (block preconditioner, FP16 blocks on FP16 MFMA, FP32 blocks on FP32 MFMA)", "hbm",
-                    pcb + 4 * plan.vlen + 2 * R * plan.vlen * 16, HBM_PEAK_GBS, "GB/s", "blockpc.hip")
+                    pcb + 4 * plan.vlen + R * plan.vlen * (16 + zb), HBM_PEAK_GBS, "GB/s", "blockpc.hip")
     roofs = {}
     for kid, (name, bound, work, peak, unit, src) in kinfo.items():
         ms, nl = tm[kid]

@@ -264,9 +264,16 @@ int operator_core(const crsht_plan* P, int nrhs, const double2* x, const double2
 // column (fused with the MFMA operand preparation). out = sinv * p + bk *
 // (Y^T N^-1 Y)(bk p); block partials of <p, out> in row 0.
 // and alpha = <r, z> / <p, q> (the T form sums the adjoint's own <p, q>
-// partials)
+// partials). The T form stores q in FP32 (float2 at the start of out, the
+// precision of the bf16x3 operator that produced it); pcg_update then reads
+// it with q32 = cg_q32(P).
+// With the block preconditioner the T form also keeps z in FP32 (float2 at
+// the start of w.cg_z: the preconditioner's products are FP32), z32 =
+// cg_z32(P, pc), for every kernel that writes or reads z in that solve.
+bool cg_q32(const crsht_plan* P) { return P->ncomp == 1; }
+bool cg_z32(const crsht_plan* P, bool pc) { return pc && P->ncomp == 1; }
 int operator_core_cg(const crsht_plan* P, int nrhs, bool update, const double* ninv, double2* out, int nb, double tol,
-                     hipStream_t s) {
+                     hipStream_t s, bool z32 = false) {
   Workspace const& w = P->w;
   if (P->ncomp == 3) {
     if (update) CR_TRY(launch_cg_pupdate(P, nrhs, w.cg_z, w.cg_p, w.alm_a, s));
@@ -274,9 +281,9 @@ int operator_core_cg(const crsht_plan* P, int nrhs, bool update, const double* n
     CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, s));
     return CR_OK;
   }
-  CR_TRY(launch_legendre_synth_mixed_cg(P, nrhs, w.cg_z, w.cg_p, update, F2(w.eo), s));
+  CR_TRY(launch_legendre_synth_mixed_cg(P, nrhs, w.cg_z, w.cg_p, update, F2(w.eo), s, z32));
   CR_TRY(launch_ring(P, nrhs, RING_FUSED, w.eo, nullptr, ninv, w.geo, true, s));
-  CR_TRY(launch_legendre_adjoint_mixed_q(P, nrhs, F2(w.geo), w.cg_p, out, s));
+  CR_TRY(launch_legendre_adjoint_mixed_q(P, nrhs, F2(w.geo), w.cg_p, F2(out), s));
   CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, s, w.adj_part, (int)P->t.mx_ntiles));
   return CR_OK;
 }
@@ -478,20 +485,21 @@ int true_residual(const crsht_plan* P, int nrhs, const double* ninv, const doubl
 // relative residuals. iters[] receives the iterations per column.
 // z = P r and the start of PCG (p = z, <r, z>, <r, r>, <b, b>) for the
 // Jacobi (pc false) or the block preconditioner
-int pcg_start(const crsht_plan* P, int nrhs, const double2* b, bool pc, hipStream_t s) {
+int pcg_start(const crsht_plan* P, int nrhs, const double2* b, bool pc, hipStream_t s, bool z32 = false) {
   Workspace const& w = P->w;
-  if (pc) CR_TRY(launch_pc_apply(P, nrhs, w.cg_r, w.cg_z, s));
-  CR_TRY(launch_cg_start(P, nrhs, b, w.cg_r, w.cg_z, w.cg_p, w.alm_a, s, pc));
+  if (pc) CR_TRY(launch_pc_apply(P, nrhs, w.cg_r, w.cg_z, s, false, z32));
+  CR_TRY(launch_cg_start(P, nrhs, b, w.cg_r, w.cg_z, w.cg_p, w.alm_a, s, pc, z32));
   return CR_OK;
 }
 
 // x += alpha p, r -= alpha q, z = P r; <r, z>, <r, r> and beta (the block
 // preconditioner sums its own <r, z> partials as it writes z)
-int pcg_update(const crsht_plan* P, int nrhs, bool pc, int nb, double tol, hipStream_t s) {
+int pcg_update(const crsht_plan* P, int nrhs, bool pc, int nb, double tol, hipStream_t s, bool q32 = false,
+               bool z32 = false) {
   Workspace const& w = P->w;
-  CR_TRY(launch_cg_update(P, nrhs, w.cg_x, w.cg_r, w.cg_z, w.cg_p, w.cg_q, s, pc));
+  CR_TRY(launch_cg_update(P, nrhs, w.cg_x, w.cg_r, w.cg_z, w.cg_p, w.cg_q, s, pc, q32 ? F2(w.cg_q) : nullptr));
   if (pc) {
-    CR_TRY(launch_pc_apply(P, nrhs, w.cg_r, w.cg_z, s, true));
+    CR_TRY(launch_pc_apply(P, nrhs, w.cg_r, w.cg_z, s, true, z32));
     CR_TRY(launch_cg_scalars(P, nrhs, 2, nb, tol, 0, s, P->pc.part, P->pc.ntasks));
   } else {
     CR_TRY(launch_cg_scalars(P, nrhs, 2, nb, tol, 0, s));
@@ -617,7 +625,8 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
   refine.assign(nrhs, 0);
   CR_TRY(hipMemsetAsync(w.cg_x, 0, (size_t)nrhs * na * sizeof(double2), s));
   CR_TRY(hipMemcpyAsync(w.cg_r, w.cg_b, (size_t)nrhs * na * sizeof(double2), hipMemcpyDeviceToDevice, s));
-  CR_CHECK(pcg_start(P, nrhs, w.cg_b, pc, s));
+  const bool z32 = cg_z32(P, pc);
+  CR_CHECK(pcg_start(P, nrhs, w.cg_b, pc, s, z32));
   CR_TRY(launch_cg_scalars(P, nrhs, 0, nb, tol, 0, s));
   CR_CHECK(read_scalars(P, nrhs, s));
   std::vector<double> last(nrhs, 1.0);   // true relative residual at the last replacement
@@ -678,8 +687,8 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
       // direction update stays pending (fused into the next operator)
       CR_CHECK(write_scalars(P, nrhs, s));
       if (pc) {
-        CR_TRY(launch_pc_apply(P, nrhs, w.cg_r, w.cg_z, s));
-        CR_TRY(launch_pc_dots(P, nrhs, w.cg_r, w.cg_z, true, s));
+        CR_TRY(launch_pc_apply(P, nrhs, w.cg_r, w.cg_z, s, false, z32));
+        CR_TRY(launch_pc_dots(P, nrhs, w.cg_r, w.cg_z, true, s, z32));
       } else {
         CR_TRY(launch_cg_replace(P, nrhs, w.cg_r, w.cg_z, s));
       }
@@ -707,8 +716,8 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
     const bool first = pending;
     CR_CHECK(run_block(P, key, o->use_graph != 0, s, [&](hipStream_t q) -> int {
       for (int k = 0; k < n; ++k) {
-        CR_CHECK(operator_core_cg(P, nrhs, k > 0 || first, ninv, w.cg_q, nb, tol, q));
-        CR_CHECK(pcg_update(P, nrhs, pc, nb, tol, q));
+        CR_CHECK(operator_core_cg(P, nrhs, k > 0 || first, ninv, w.cg_q, nb, tol, q, z32));
+        CR_CHECK(pcg_update(P, nrhs, pc, nb, tol, q, cg_q32(P), z32));
       }
       return CR_OK;
     }));
@@ -806,8 +815,9 @@ int dsolve_check_replace(const DSolve& d, hipStream_t q, bool tail) {
   if (!tail) return CR_OK;
   PredScope ps(P, w.ctl + C_SKIP_TAIL);
   if (d.pc) {
-    CR_TRY(launch_pc_apply(P, d.nrhs, w.cg_r, w.cg_z, q));
-    CR_TRY(launch_pc_dots(P, d.nrhs, w.cg_r, w.cg_z, true, q));
+    const bool z32 = d.mixed && cg_z32(P, d.pc);
+    CR_TRY(launch_pc_apply(P, d.nrhs, w.cg_r, w.cg_z, q, false, z32));
+    CR_TRY(launch_pc_dots(P, d.nrhs, w.cg_r, w.cg_z, true, q, z32));
   } else {
     CR_TRY(launch_cg_replace(P, d.nrhs, w.cg_r, w.cg_z, q));
   }
@@ -822,18 +832,19 @@ int dsolve_step(const DSolve& d, bool first, hipStream_t q) {
   const int nb = vec_reduce_blocks(P);
   CR_CHECK(dsolve_check_replace(d, q, true));
   CR_TRY(launch_dctl(P, DC_PRE_BLOCK, d.a, nullptr, q));
+  const bool z32 = d.mixed && cg_z32(P, d.pc);
   {
     PredScope ps(P, w.ctl + C_SKIP_ITER);
     for (int k = 0; k < d.a.every; ++k) {
       const bool upd = k > 0 || first;
       if (d.mixed) {
-        CR_CHECK(operator_core_cg(P, d.nrhs, upd, d.ninv, w.cg_q, nb, d.a.tol, q));
+        CR_CHECK(operator_core_cg(P, d.nrhs, upd, d.ninv, w.cg_q, nb, d.a.tol, q, z32));
       } else {
         if (upd) CR_TRY(launch_cg_pupdate(P, d.nrhs, w.cg_z, w.cg_p, w.alm_a, q));
         CR_CHECK(operator_core(P, d.nrhs, w.cg_p, w.alm_a, d.ninv, w.cg_q, q));
         CR_TRY(launch_cg_scalars(P, d.nrhs, 1, nb, d.a.tol, 0, q));
       }
-      CR_CHECK(pcg_update(P, d.nrhs, d.pc, nb, d.a.tol, q));
+      CR_CHECK(pcg_update(P, d.nrhs, d.pc, nb, d.a.tol, q, d.mixed && cg_q32(P), z32));
     }
   }
   CR_TRY(launch_dctl(P, DC_AFTER_BLOCK, d.a, nullptr, q));
@@ -910,7 +921,7 @@ int dsolve_prologue(const DSolve& d, const cr_problem* prob, const double* dm, c
     CR_CHECK(assemble_rhs(P, d.nrhs, prob->ninv, dm, w0, w1, w.cg_b, s));
   CR_TRY(hipMemsetAsync(w.cg_x, 0, vbytes, s));
   CR_TRY(hipMemcpyAsync(w.cg_r, w.cg_b, vbytes, hipMemcpyDeviceToDevice, s));
-  CR_CHECK(pcg_start(P, d.nrhs, w.cg_b, d.pc, s));
+  CR_CHECK(pcg_start(P, d.nrhs, w.cg_b, d.pc, s, d.mixed && cg_z32(P, d.pc)));
   CR_TRY(launch_cg_scalars(P, d.nrhs, 0, vec_reduce_blocks(P), d.a.tol, 0, s));
   CR_TRY(launch_dctl(P, DC_INIT, d.a, nullptr, s));
   return CR_OK;

@@ -341,10 +341,10 @@ __device__ __forceinline__ void pc_stage(float (*rs)[kPcJ][33], int j0, int c0, 
 // h) writes this wavefront's results of columns h .. h + 7 as
 // stage[column - h][2 (row - i0) + w][re, im]. With part, the per-task
 // partials of <r, z>.
-template <class Fill>
+template <class Fill, class Z>
 __device__ __forceinline__ void pc_output(Fill&& fill, float (*rs)[kPcJ][33], int c0, int nc, int n0, int n1, int i0,
                                           int64_t vlen, int64_t e00, const float* __restrict__ scale,
-                                          const double2* __restrict__ r, double2* __restrict__ z,
+                                          const double2* __restrict__ r, Z* __restrict__ z,
                                           double* __restrict__ part, int pstride, double wt, double* red, int w,
                                           int lane) {
   float* stage = &rs[0][0][0];   // [8 columns][256 coefficients][re, im]
@@ -390,8 +390,8 @@ __device__ __forceinline__ void pc_output(Fill&& fill, float (*rs)[kPcJ][33], in
         if (c < nc && row < (q ? n1 : n0)) {
           const float* v = stage + idx * 2;
           const double sr = (double)so[k & 1];
-          const double2 zv = make_double2(sr * (double)v[0], sr * (double)v[1]);
-          z[(int64_t)(c0 + c) * vlen + e00 + 2 * i0 + er] = zv;
+          const double2 zv = zstore(z + (int64_t)(c0 + c) * vlen + e00 + 2 * i0 + er,
+                                    make_double2(sr * (double)v[0], sr * (double)v[1]));
           if (part) rzp[(k0 + k) >> 1] += fma(rv[k].x, zv.x, rv[k].y * zv.y);
         }
       }
@@ -423,9 +423,10 @@ __device__ __forceinline__ void pc_output(Fill&& fill, float (*rs)[kPcJ][33], in
 // row n - 1 and lanes past the padded row width read columns 0 .. 3, all
 // finite entries whose products meet zero B operands (rows j >= n of the
 // staged tile) or land in output rows never written.
+template <class Z>
 __device__ __forceinline__ void pc_apply_wave32(const float* __restrict__ Ab, int nrhs, int64_t vlen,
                                                 const float* __restrict__ scale, const double2* __restrict__ r,
-                                                double2* __restrict__ z, float (*rs)[kPcJ][33], int w, int il,
+                                                Z* __restrict__ z, float (*rs)[kPcJ][33], int w, int il,
                                                 int kk, int n, int n0, int n1, int ld, int i0, int64_t e00,
                                                 double* __restrict__ part, int pstride, double wt, double* red) {
   const int lane = threadIdx.x & 63;
@@ -497,9 +498,10 @@ __device__ __forceinline__ void pc_apply_wave32(const float* __restrict__ Ab, in
 // rows past the block are never written). At: the block's first tile of row
 // tile i0 / 32, plus this lane's 8 entries. Steps past the block's last
 // column tile read that tile again and meet zero B operands.
+template <class Z>
 __device__ __forceinline__ void pc_apply_wave16(const _Float16* __restrict__ At, int ntj, int ntr, int nrhs,
                                                 int64_t vlen, const float* __restrict__ scale,
-                                                const double2* __restrict__ r, double2* __restrict__ z,
+                                                const double2* __restrict__ r, Z* __restrict__ z,
                                                 float (*rs)[kPcJ][33], int w, int il, int kk, int n, int n0,
                                                 int n1, int i0, int64_t e00, double* __restrict__ part,
                                                 int pstride, double wt, double* red) {
@@ -583,12 +585,13 @@ __device__ __forceinline__ void pc_apply_wave16(const _Float16* __restrict__ At,
 }
 
 // (three wavefronts per SIMD: more loads in flight per CU)
+template <class Z>
 __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_pc_apply(
     int nrhs, int64_t vlen, const int64_t* __restrict__ be0, const int* __restrict__ task_b,
     const int* __restrict__ task_b1, const int* __restrict__ task_r0, const int* __restrict__ bn,
     const int64_t* __restrict__ boff, const int* __restrict__ bhalf, const float* __restrict__ inv,
     const int64_t* __restrict__ boff16, const _Float16* __restrict__ inv16, const float* __restrict__ scale,
-    const int* __restrict__ bm, const double2* __restrict__ r, double2* __restrict__ z,
+    const int* __restrict__ bm, const double2* __restrict__ r, Z* __restrict__ z,
     double* __restrict__ part, int pstride, const int* __restrict__ pred) {
   if (pred && *pred) return;
   static_assert((kPcJ / 2) % kPcPre == 0, "tile must hold whole prefetch groups");
@@ -627,8 +630,9 @@ __global__ __launch_bounds__(kPcWaves * 64) __attribute__((amdgpu_waves_per_eu(3
 }
 
 // partial <r, z> (row 0) and, with rr, <r, r> (row 1) per column
+template <class Z>
 __global__ void k_pc_dots(int64_t vlen, const int* __restrict__ idx_m, const double2* __restrict__ r,
-                          const double2* __restrict__ z, int rr, double* __restrict__ partial, int npart,
+                          const Z* __restrict__ z, int rr, double* __restrict__ partial, int npart,
                           const int* __restrict__ pred) {
   if (pred && *pred) return;
   __shared__ double sh[256];
@@ -638,7 +642,7 @@ __global__ void k_pc_dots(int64_t vlen, const int* __restrict__ idx_m, const dou
     const int64_t ci = c * vlen + i;
     const int m = idx_m[i];
     const double2 rv = r[ci];
-    rz += wdot(m, rv, z[ci]);
+    rz += wdot(m, rv, zload(z + ci));
     if (rr) r2 += wdot(m, rv, rv);
   }
   rz = block_sum(rz, sh);
@@ -936,21 +940,32 @@ int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s) {
   return CR_OK;
 }
 
-hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s, bool dots) {
+hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s, bool dots,
+                           bool z32) {
   const BlockPC& pc = P->pc;
   timing_begin(P, 5, s);
-  hipLaunchKernelGGL(k_pc_apply, dim3(pc.ntasks), dim3(kPcWaves * 64), 0, s, nrhs, vlen(P), pc.be0, pc.task_b,
-                     pc.task_b1, pc.task_r0, pc.bn, pc.boff, pc.bhalf, pc.inv, pc.boff16, pc.inv16, pc.scale, pc.bm, r, z,
-                     dots ? pc.part : nullptr, pc.ntasks, P->pred);
+  if (z32)
+    hipLaunchKernelGGL(k_pc_apply<float2>, dim3(pc.ntasks), dim3(kPcWaves * 64), 0, s, nrhs, vlen(P), pc.be0,
+                       pc.task_b, pc.task_b1, pc.task_r0, pc.bn, pc.boff, pc.bhalf, pc.inv, pc.boff16, pc.inv16,
+                       pc.scale, pc.bm, r, reinterpret_cast<float2*>(z), dots ? pc.part : nullptr, pc.ntasks,
+                       P->pred);
+  else
+    hipLaunchKernelGGL(k_pc_apply<double2>, dim3(pc.ntasks), dim3(kPcWaves * 64), 0, s, nrhs, vlen(P), pc.be0,
+                       pc.task_b, pc.task_b1, pc.task_r0, pc.bn, pc.boff, pc.bhalf, pc.inv, pc.boff16, pc.inv16,
+                       pc.scale, pc.bm, r, z, dots ? pc.part : nullptr, pc.ntasks, P->pred);
   timing_end(P, 5, s);
   return hipGetLastError();
 }
 
 hipError_t launch_pc_dots(const crsht_plan* P, int nrhs, const double2* r, const double2* z, bool rr,
-                          hipStream_t s) {
+                          hipStream_t s, bool z32) {
   const int nb = vec_reduce_blocks(P);
-  hipLaunchKernelGGL(k_pc_dots, dim3(nb, nrhs), dim3(256), 0, s, vlen(P), P->t.idx_mv, r, z, rr ? 1 : 0,
-                     P->w.partial, P->w.npart, P->pred);
+  if (z32)
+    hipLaunchKernelGGL(k_pc_dots<float2>, dim3(nb, nrhs), dim3(256), 0, s, vlen(P), P->t.idx_mv, r,
+                       reinterpret_cast<const float2*>(z), rr ? 1 : 0, P->w.partial, P->w.npart, P->pred);
+  else
+    hipLaunchKernelGGL(k_pc_dots<double2>, dim3(nb, nrhs), dim3(256), 0, s, vlen(P), P->t.idx_mv, r, z, rr ? 1 : 0,
+                       P->w.partial, P->w.npart, P->pred);
   return hipGetLastError();
 }
 

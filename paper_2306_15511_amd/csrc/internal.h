@@ -322,6 +322,25 @@ namespace crsht {
 // elements of one solver vector column: ncomp blocks of nalm coefficients
 inline int64_t vlen(const crsht_plan* P) { return (int64_t)P->ncomp * P->g.nalm; }
 
+// element access of a solver vector stored as double2 or as float2 (the
+// preconditioned residual z of the mixed-precision T iteration, at the start
+// of its buffer with the same element index); zstore returns the value as
+// stored, so that dot products use what later kernels read
+__device__ __forceinline__ double2 zload(const double2* p) { return *p; }
+__device__ __forceinline__ double2 zload(const float2* p) {
+  const float2 v = *p;
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ double2 zstore(double2* p, double2 v) {
+  *p = v;
+  return v;
+}
+__device__ __forceinline__ double2 zstore(float2* p, double2 v) {
+  const float2 f = make_float2((float)v.x, (float)v.y);
+  *p = f;
+  return make_double2(f.x, f.y);
+}
+
 // ---- timing (timing.cpp) ----
 void timing_begin(const crsht_plan* P, int id, hipStream_t s);
 void timing_end(const crsht_plan* P, int id, hipStream_t s);
@@ -362,13 +381,14 @@ hipError_t launch_legendre_synth_mixed(const crsht_plan* P, int nrhs, const doub
 // for done columns or when !update) fused with the operand preparation, then
 // eo from bk * p
 hipError_t launch_legendre_synth_mixed_cg(const crsht_plan* P, int nrhs, const double2* z, double2* p, bool update,
-                                          float2* eo, hipStream_t s);
+                                          float2* eo, hipStream_t s, bool z32 = false);
 // raw sums as launch_legendre_adjoint (non-diag) from float2 geo, bf16x3 /
 // FP32 accumulation
-// T plans, PCG: the bf16x3 adjoint fused with q = camp.x sinv p + bk raw and
-// the per-tile partials of <p, q> (w.adj_part, [nrhs][t.mx_ntiles])
+// T plans, PCG: the bf16x3 adjoint fused with q = camp.x sinv p + bk raw,
+// stored as FP32 ([nrhs][nalm] float2), and the per-tile partials of <p, q>
+// of the stored q (w.adj_part, [nrhs][t.mx_ntiles])
 hipError_t launch_legendre_adjoint_mixed_q(const crsht_plan* P, int nrhs, const float2* geo, const double2* p,
-                                           double2* q, hipStream_t s);
+                                           float2* q, hipStream_t s);
 hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const float2* geo, double2* raw,
                                          hipStream_t s);
 
@@ -441,12 +461,13 @@ hipError_t launch_diag_tqu(const crsht_plan* P, const double2* rawt, const doubl
 int block_pc_build(crsht_plan* P, int lmin, const double* ninv, hipStream_t s);
 void block_pc_free(BlockPC& pc);
 // z = M^-1 r per column (r, z: [nrhs][vlen])
-// with dots, also the per-task partials of <r, z> into pc.part ([nrhs][ntasks])
+// with dots, also the per-task partials of <r, z> into pc.part ([nrhs][ntasks]);
+// z32: z stored as float2 at the start of the z buffer (zstore)
 hipError_t launch_pc_apply(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s,
-                           bool dots = false);
+                           bool dots = false, bool z32 = false);
 // partial <r, z> (row 0) and, with rr, <r, r> (row 1), nb = vec_reduce_blocks
 hipError_t launch_pc_dots(const crsht_plan* P, int nrhs, const double2* r, const double2* z, bool rr,
-                          hipStream_t s);
+                          hipStream_t s, bool z32 = false);
 
 // ---- allocation-free synthesis (noalloc.hip) ----
 // device address of the static scratch on `device` (current), once per device
@@ -481,17 +502,19 @@ hipError_t launch_map_axpby(int64_t n, double a, const double* x, double b, cons
                             hipStream_t s);
 hipError_t launch_alm_axpby(int64_t n, double a, const double2* x, double b, const double2* y, double2* out,
                             hipStream_t s);
-// zgiven: z already holds the preconditioned residual (block preconditioner)
+// zgiven: z already holds the preconditioned residual (block preconditioner),
+// as float2 with z32
 hipError_t launch_cg_start(const crsht_plan* P, int nrhs, const double2* b, const double2* r, double2* z,
-                           double2* p, double2* pt, hipStream_t s, bool zgiven = false);
+                           double2* p, double2* pt, hipStream_t s, bool zgiven = false, bool z32 = false);
 // part0 (optional): row 0 (<r, z>) comes from part0[c * n0 + i], i < n0,
 // instead of the block partials (the block preconditioner's own partials)
 hipError_t launch_cg_scalars(const crsht_plan* P, int nrhs, int what, int nb, double tol, int restart,
                              hipStream_t s, const double* part0 = nullptr, int n0 = 0);
 // noz == false: z = r / D with <r, z> in row 0; true: z untouched, row 0 = 0
-// (the block preconditioner follows, with its own <r, z> partials)
+// (the block preconditioner follows, with its own <r, z> partials). q32:
+// q is read as FP32 from there instead of q (the mixed T iteration)
 hipError_t launch_cg_update(const crsht_plan* P, int nrhs, double2* x, double2* r, double2* z, const double2* p,
-                            const double2* q, hipStream_t s, bool noz = false);
+                            const double2* q, hipStream_t s, bool noz = false, const float2* q32 = nullptr);
 hipError_t launch_cg_replace(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s);
 hipError_t launch_cg_pupdate(const crsht_plan* P, int nrhs, const double2* z, double2* p, double2* pt,
                              hipStream_t s);

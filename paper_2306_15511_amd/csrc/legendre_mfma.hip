@@ -263,9 +263,11 @@ __global__ __launch_bounds__(64) void k_prep_synth(int lmax, int nrhs, const int
 // 0), written back in FP64, and the ab tiles built from bk * p. z, p: [rhs][nalm]
 // at column stride nalm; the block stages bk * p (float) in LDS as
 // [q][rhs][comp][16 steps] so that each lane reads its 8 steps contiguously.
+// Z: the stored type of z (float2 after the block preconditioner).
+template <typename Z>
 __global__ __launch_bounds__(64) void k_pupdate_prep(int lmax, int nrhs, int64_t nalm, const int64_t* __restrict__ mstart,
                                                      const int64_t* __restrict__ cstart, const double* __restrict__ bk,
-                                                     const double2* __restrict__ z, double2* __restrict__ p,
+                                                     const Z* __restrict__ z, double2* __restrict__ p,
                                                      const double* __restrict__ scal, int update,
                                                      bf16x8* __restrict__ ab, int64_t ab_gstride,
                                                      const int* __restrict__ pred) {
@@ -297,7 +299,7 @@ __global__ __launch_bounds__(64) void k_pupdate_prep(int lmax, int nrhs, int64_t
     const int64_t e = ok ? rhs * nalm + base + st : base;
     pv[i] = p[e];
     if (update) {
-      zv[i] = z[e];
+      zv[i] = zload(z + e);
       const double* sc = scal + (ok ? rhs : 0) * kScalSlots;
       done[i] = sc[S_DONE];
       beta[i] = sc[S_BETA];
@@ -637,7 +639,8 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
                                                   const int* __restrict__ tile_m, const int* __restrict__ order,
                                                   int maxq, const double2* __restrict__ ckpt,
                                                   const bf16x8* __restrict__ ag, int64_t ag_gstride,
-                                                  double2* __restrict__ out, int64_t out_stride,
+                                                  double2* __restrict__ out, float2* __restrict__ q32,
+                                                  int64_t out_stride,
                                                   const double2* __restrict__ qp, const double* __restrict__ sinv,
                                                   const double2* __restrict__ camp, const double* __restrict__ bk,
                                                   double* __restrict__ part, int64_t ntiles,
@@ -807,7 +810,9 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
     return;
   }
   // PCG form (one column group): q = camp.x sinv p + bk raw, component by
-  // component, and the tile's partial of <p, q>
+  // component, stored as FP32 into q32, and the tile's partial of <p, q> of
+  // the stored (rounded) q, so that alpha and the update r -= alpha q use the
+  // same q
   static_assert(NG == 1 && kAdjWaves == 4, "PCG form: one column group, four wavefronts");
   const int ln = lane, comp = w & 1;
   const int n = ln & 31;
@@ -825,9 +830,9 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
       for (int ww = 0; ww < kAdjWaves; ++ww) acc += (&lds[ww][0][0][0])[(q * 16 + r) * 64 + ln];
       const int st = st0 + 2 * n + q;
       if (rhs < nrhs && st < nsteps) {
-        const double qv = fma(qca[k] * qsi[q], qpv[k][q], qbk[q] * (double)acc);
-        reinterpret_cast<double*>(out + rhs * out_stride + base + st)[comp] = qv;
-        pz[k] = fma(qpv[k][q], qv, pz[k]);
+        const float qv = (float)fma(qca[k] * qsi[q], qpv[k][q], qbk[q] * (double)acc);
+        reinterpret_cast<float*>(q32 + rhs * out_stride + base + st)[comp] = qv;
+        pz[k] = fma(qpv[k][q], (double)qv, pz[k]);
       }
     }
   }
@@ -969,7 +974,7 @@ hipError_t launch_legendre_synth_mixed(const crsht_plan* P, int nrhs, const doub
 
 // (the PCG inner operator: bf16x3 always)
 hipError_t launch_legendre_synth_mixed_cg(const crsht_plan* P, int nrhs, const double2* z, double2* p, bool update,
-                                          float2* eo, hipStream_t s) {
+                                          float2* eo, hipStream_t s, bool z32) {
   const Geometry& g = P->g;
   const int64_t eo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
   bf16x8* ab = reinterpret_cast<bf16x8*>(P->w.mx_ab);
@@ -977,9 +982,15 @@ hipError_t launch_legendre_synth_mixed_cg(const crsht_plan* P, int nrhs, const d
   for (int c0 = 0; c0 < nrhs; c0 += per) {
     const int nr = min(nrhs - c0, per);
     dim3 gp((g.lmax + kSynChunk) / kSynChunk, g.mmax + 1, launch_groups(nr));
-    hipLaunchKernelGGL(k_pupdate_prep, gp, dim3(64), 0, s, g.lmax, nr, g.nalm, P->t.mstart, P->t.mx_cstart,
-                       P->w.bk, z + (int64_t)c0 * g.nalm, p + (int64_t)c0 * g.nalm,
-                       P->w.scal + (int64_t)c0 * kScalSlots, update ? 1 : 0, ab, ab_group(g), P->pred);
+    if (z32)
+      hipLaunchKernelGGL(k_pupdate_prep<float2>, gp, dim3(64), 0, s, g.lmax, nr, g.nalm, P->t.mstart,
+                         P->t.mx_cstart, P->w.bk, reinterpret_cast<const float2*>(z) + (int64_t)c0 * g.nalm,
+                         p + (int64_t)c0 * g.nalm, P->w.scal + (int64_t)c0 * kScalSlots, update ? 1 : 0, ab,
+                         ab_group(g), P->pred);
+    else
+      hipLaunchKernelGGL(k_pupdate_prep<double2>, gp, dim3(64), 0, s, g.lmax, nr, g.nalm, P->t.mstart,
+                         P->t.mx_cstart, P->w.bk, z + (int64_t)c0 * g.nalm, p + (int64_t)c0 * g.nalm,
+                         P->w.scal + (int64_t)c0 * kScalSlots, update ? 1 : 0, ab, ab_group(g), P->pred);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = synth_mfma_launch(P, nr, 2, ab, eo + (int64_t)c0 * eo_stride, eo_stride, s);
@@ -1014,8 +1025,8 @@ hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const fl
   hipLaunchKernelGGL((k_adj_mfma<1, NS>), dim3(8u * (unsigned)P->t.mx_maxq), dim3(kAdjWaves * 64), 0, s, g.lmax,   \
                      g.mmax, g.npairs, nr, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,        \
                      P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_order, P->t.mx_maxq, P->t.mx_ckpt, (const bf16x8*)ag, \
-                     ag_group(g), raw + (int64_t)c0 * g.nalm, (int64_t)g.nalm, nullptr, nullptr, nullptr, nullptr, \
-                     nullptr, 0, P->pred)
+                     ag_group(g), raw + (int64_t)c0 * g.nalm, nullptr, (int64_t)g.nalm, nullptr, nullptr, nullptr,   \
+                     nullptr, nullptr, 0, P->pred)
     if (ns == 3)
       CRSHT_ADJ_LAUNCH(3);
     else
@@ -1029,7 +1040,7 @@ hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const fl
 }
 
 hipError_t launch_legendre_adjoint_mixed_q(const crsht_plan* P, int nrhs, const float2* geo, const double2* p,
-                                           double2* q, hipStream_t s) {
+                                           float2* q, hipStream_t s) {
   const Geometry& g = P->g;
   const int64_t geo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
   bf16x8* ag = reinterpret_cast<bf16x8*>(P->w.mx_ag);
@@ -1045,7 +1056,7 @@ hipError_t launch_legendre_adjoint_mixed_q(const crsht_plan* P, int nrhs, const 
     hipLaunchKernelGGL((k_adj_mfma<1, 2>), dim3(8u * (unsigned)P->t.mx_maxq), dim3(kAdjWaves * 64), 0, s, g.lmax,
                        g.mmax, g.npairs, nr, P->t.pair_z, P->t.rec_alpha, P->t.lst_g, P->t.lst_s, P->t.mstart,
                        P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_order, P->t.mx_maxq, P->t.mx_ckpt, (const bf16x8*)ag,
-                       ag_group(g), q + (int64_t)c0 * g.nalm, (int64_t)g.nalm, p + (int64_t)c0 * g.nalm,
+                       ag_group(g), nullptr, q + (int64_t)c0 * g.nalm, (int64_t)g.nalm, p + (int64_t)c0 * g.nalm,
                        (const double*)P->w.sinv, (const double2*)P->w.camp + c0, (const double*)P->w.bk,
                        P->w.adj_part + (int64_t)c0 * P->t.mx_ntiles, P->t.mx_ntiles, P->pred);
     timing_end(P, 4, s);

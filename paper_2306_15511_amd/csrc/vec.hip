@@ -155,10 +155,12 @@ __global__ void k_alm_axpby(int64_t n, double a, const double2* __restrict__ x, 
 // weighted dot partials of one column: w_m (a.x c.x + a.y c.y)
 
 // start: x = 0 (or given), r = b - A x0 computed by caller in r, z = r / D,
-// p = z, pt = bk * p; partial sums of <r,z>, <r,r>, <b,b>
+// p = z, pt = bk * p; partial sums of <r,z>, <r,r>, <b,b>. Z: the stored
+// type of z (float2 only with zgiven)
+template <typename Z>
 __global__ void k_cg_start(int64_t nalm, const int* __restrict__ idx_m, const double* __restrict__ diag,
                            const double* __restrict__ bk, const double2* __restrict__ b,
-                           const double2* __restrict__ r, double2* __restrict__ z, double2* __restrict__ p,
+                           const double2* __restrict__ r, Z* __restrict__ z, double2* __restrict__ p,
                            double2* __restrict__ pt, double* __restrict__ partial, int npart,
                            const double* __restrict__ scal, int zgiven, const int* __restrict__ pred) {
   if (pred && *pred) return;
@@ -172,11 +174,10 @@ __global__ void k_cg_start(int64_t nalm, const int* __restrict__ idx_m, const do
       const double2 rv = r[ci];
       double2 zv;
       if (zgiven) {
-        zv = z[ci];
+        zv = zload(z + ci);
       } else {
         const double dinv = 1.0 / diag[i];
-        zv = make_double2(rv.x * dinv, rv.y * dinv);
-        z[ci] = zv;
+        zv = zstore(z + ci, make_double2(rv.x * dinv, rv.y * dinv));
       }
       p[ci] = zv;
       pt[ci] = make_double2(bk[i] * zv.x, bk[i] * zv.y);
@@ -270,10 +271,12 @@ __global__ __launch_bounds__(kScalBlock) void k_cg_scalars(int what, int nb, con
   }
 }
 
-// x += alpha p; r -= alpha q; z = r / D; partial <r,z>, <r,r>
+// x += alpha p; r -= alpha q; z = r / D; partial <r,z>, <r,r>. Q: the
+// vector type of q (float2 in the mixed-precision T iteration)
+template <typename Q>
 __global__ void k_cg_update(int64_t nalm, const int* __restrict__ idx_m, const double* __restrict__ diag,
                             const double* __restrict__ bk, double2* __restrict__ x, double2* __restrict__ r,
-                            double2* __restrict__ z, const double2* __restrict__ p, const double2* __restrict__ q,
+                            double2* __restrict__ z, const double2* __restrict__ p, const Q* __restrict__ q,
                             double* __restrict__ partial, int npart, const double* __restrict__ scal, int noz,
                             const int* __restrict__ pred) {
   if (pred && *pred) return;
@@ -287,7 +290,9 @@ __global__ void k_cg_update(int64_t nalm, const int* __restrict__ idx_m, const d
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nalm; i += (int64_t)gridDim.x * blockDim.x) {
       const int64_t ci = c * nalm + i;
       const int m = idx_m[i];
-      const double2 pv = p[ci], qv = q[ci];
+      const double2 pv = p[ci];
+      const Q qq = q[ci];
+      const double2 qv = make_double2((double)qq.x, (double)qq.y);
       double2 xv = x[ci], rv = r[ci];
       xv.x = fma(a, pv.x, xv.x);
       xv.y = fma(a, pv.y, xv.y);
@@ -651,10 +656,15 @@ hipError_t launch_alm_axpby(int64_t n, double a, const double2* x, double b, con
 }
 
 hipError_t launch_cg_start(const crsht_plan* P, int nrhs, const double2* b, const double2* r, double2* z,
-                           double2* p, double2* pt, hipStream_t s, bool zgiven) {
+                           double2* p, double2* pt, hipStream_t s, bool zgiven, bool z32) {
   const int nb = vec_reduce_blocks(P);
-  hipLaunchKernelGGL(k_cg_start, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, P->w.diag,
-                     P->w.bk, b, r, z, p, pt, P->w.partial, P->w.npart, P->w.scal, zgiven ? 1 : 0, P->pred);
+  if (z32 && zgiven)
+    hipLaunchKernelGGL(k_cg_start<float2>, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, P->w.diag,
+                       P->w.bk, b, r, reinterpret_cast<float2*>(z), p, pt, P->w.partial, P->w.npart, P->w.scal, 1,
+                       P->pred);
+  else
+    hipLaunchKernelGGL(k_cg_start<double2>, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, P->w.diag,
+                       P->w.bk, b, r, z, p, pt, P->w.partial, P->w.npart, P->w.scal, zgiven ? 1 : 0, P->pred);
   return hipGetLastError();
 }
 
@@ -680,10 +690,14 @@ hipError_t launch_diag(const crsht_plan* P, const double2* raw, double* diag, hi
 }
 
 hipError_t launch_cg_update(const crsht_plan* P, int nrhs, double2* x, double2* r, double2* z, const double2* p,
-                            const double2* q, hipStream_t s, bool noz) {
+                            const double2* q, hipStream_t s, bool noz, const float2* q32) {
   const int nb = vec_reduce_blocks(P);
-  hipLaunchKernelGGL(k_cg_update, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, P->w.diag,
-                     P->w.bk, x, r, z, p, q, P->w.partial, P->w.npart, P->w.scal, noz ? 1 : 0, P->pred);
+  if (q32)
+    hipLaunchKernelGGL(k_cg_update<float2>, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, P->w.diag,
+                       P->w.bk, x, r, z, p, q32, P->w.partial, P->w.npart, P->w.scal, noz ? 1 : 0, P->pred);
+  else
+    hipLaunchKernelGGL(k_cg_update<double2>, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, P->w.diag,
+                       P->w.bk, x, r, z, p, q, P->w.partial, P->w.npart, P->w.scal, noz ? 1 : 0, P->pred);
   return hipGetLastError();
 }
 
