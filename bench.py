@@ -55,11 +55,11 @@ HBM_PEAK_GBS = 8000.0
 # has none: the probe runs its plain form, the solve its PCG form, which
 # also reads p and writes q.)
 TRAFFIC = {
-    "k_synth_mfma": {"bytes": 698111936, "src": "cdd511f347359444"},
+    "k_synth_mfma": {"bytes": 696476416, "src": "29b0e93d1254f353"},
     "k_ring<float2, RING_FUSED>": {"bytes": 851819264, "src": "76e554674a4903a5"},   # one pass (4 class launches)
     "k_legendre_synth_mfma": {"bytes": 2 * 680435432, "src": "950022753ad0e9f2"},  # one transform (2 launches)
     "k_legendre_adj_mfma": {"bytes": 2 * 606622440, "src": "950022753ad0e9f2"},  # one transform (2 launches)
-    "k_pc_apply": {"bytes": 2288146197, "src": "fc77c053960ec824"},
+    "k_pc_apply": {"bytes": 2389456395, "src": "648961bc9f2460e7"},   # solve form: FP32 z, <r, z> partials
 }
 
 
