@@ -353,16 +353,23 @@ __global__ __launch_bounds__(kAdjBlock) void k_legendre_adj(
 //   D_par[i][j] += sum_k mu(l0 + 2 i + par, p_k) G_par(p_k, j),
 // par = E (even l - m, G_N + G_S) and O (odd, G_N - G_S), j = 2 c + (re, im)
 // over up to 8 complex columns. The G operands of the wavefront's 128 pairs
-// stay in registers for the whole m. After both subsets the 8 wavefronts'
-// 16 x 16 tiles are summed through LDS in a fixed order (deterministic) and
-// the 32 l-steps x ncols results written. A block covers kAmPairs ring pairs
-// from p_off; grids with more pairs take one launch per kAmPairs, the later
-// ones adding to what the earlier wrote (accumulate = 1), in launch order.
-// All products and sums are FP64.
+// stay in registers for the whole m. After both subsets the kAmWaves
+// wavefronts' 16 x 16 tiles are summed through LDS in a fixed order
+// (deterministic) and the 32 l-steps x ncols results written. A block covers
+// kAmPairs ring pairs from p_off; grids with more pairs take one launch per
+// kAmPairs, the later ones adding to what the earlier wrote (accumulate = 1),
+// in launch order. All products and sums are FP64. Four wavefronts per block
+// (two launches at Nside 512) rather than eight (one launch): a CU then holds
+// two independent blocks, whose barriers (two per chunk) do not hold each
+// other, so one block's recurrence overlaps the other's matrix products
+// (1.98 against 2.36 ms per 16-column transform at Nside 512, although the
+// later launch re-reads the sums the earlier one wrote); with eight
+// wavefronts, one block per CU, both wavefronts of a SIMD left each barrier
+// together and competed for the same unit.
 // FP64 MFMA 16x16x4 lane layout: A[i][k] in lane i + 16 k, B[k][j] in lane
 // j + 16 k, D[i][j] in lane j + 16 (i % 4), register i / 4.
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
-constexpr int kAmWaves = 8;
+constexpr int kAmWaves = 4;
 constexpr int kAmChunk = 32;     // l-steps per chunk: 16 rows of each parity
 constexpr int kAmRow = 33;       // LDS row stride (doubles) of the mu staging
 constexpr int kAmCols = 8;       // complex columns per launch (16 real MFMA columns)
@@ -470,10 +477,11 @@ __global__ __launch_bounds__(kAmWaves * 64) void k_legendre_adj_mfma(
       for (int r = 0; r < 4; ++r) my[par * 256 + r * 64 + lane] = acc[par][0][r] + acc[par][1][r];
     __syncthreads();
     {
-      // thread t: column t / 64, l-step l0 + (t % 64) / 2, re/im t % 2 (coalesced stores)
-      const int c = t >> 6, sq = (t & 63) >> 1, rr = t & 1;
+      // thread t: columns t / 64 + kAmWaves k, l-step l0 + (t % 64) / 2,
+      // re/im t % 2 (coalesced stores)
+      const int sq = (t & 63) >> 1, rr = t & 1;
       const int stp = l0 + sq;
-      if (c < ncols && stp < nsteps) {
+      for (int c = t >> 6; c < ncols && stp < nsteps; c += kAmWaves) {
         const int par = sq & 1, i = sq >> 1;
         const int idx = par * 256 + (i >> 2) * 64 + (2 * c + rr) + 16 * (i & 3);
         double sum = 0.0;
