@@ -57,8 +57,8 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC = {
     "k_synth_mfma": {"bytes": 696476416, "src": "29b0e93d1254f353"},
     "k_ring<float2, RING_FUSED>": {"bytes": 851819264, "src": "76e554674a4903a5"},   # one pass (4 class launches)
-    "k_legendre_synth_mfma": {"bytes": 2 * 680435432, "src": "950022753ad0e9f2"},  # one transform (2 launches)
-    "k_legendre_adj_mfma": {"bytes": 2 * 606622440, "src": "950022753ad0e9f2"},  # one transform (2 launches)
+    "k_legendre_synth_mfma": {"bytes": 2 * 679587920, "src": "4759d7b6f7f34de0"},  # one transform (2 launches)
+    "k_legendre_adj_mfma": {"bytes": 4 * 464820008, "src": "4759d7b6f7f34de0"},  # one transform (2 x 2 launches)
     "k_pc_apply": {"bytes": 2389456395, "src": "648961bc9f2460e7"},   # solve form: FP32 z, <r, z> partials
 }
 
