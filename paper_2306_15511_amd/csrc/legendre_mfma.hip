@@ -528,17 +528,29 @@ __global__ __launch_bounds__(256) void k_synth_mfma(int lmax, int mmax, int npai
 constexpr int kPrepM = 8;                       // m per block
 constexpr int kPrepMS = 2 * 16 * 2 * 16 + 8;   // floats per m in LDS ([q][rhs][comp][pair], padded)
 template <int NS>
-__global__ __launch_bounds__(256) void k_prep_adj(int mmax, int npairs, int nrhs, const float2* __restrict__ geo,
+__global__ __launch_bounds__(256) void k_prep_adj(int lmax, int mmax, int npairs, int nrhs,
+                                                  const int* __restrict__ lst_g, const float2* __restrict__ geo,
                                                   int64_t geo_stride, bf16x8* __restrict__ ag, int64_t ag_gstride,
                                                   const int* __restrict__ pred) {
   if (pred && *pred) return;
   __shared__ __attribute__((aligned(16))) float G[kPrepM * kPrepMS];
+  __shared__ int live[kPrepM];
   const int kb = blockIdx.x, m0 = blockIdx.y * kPrepM, grp = blockIdx.z;   // right-hand sides 16 grp ..
   nrhs -= 16 * grp;
   geo += (int64_t)16 * grp * geo_stride;
   ag += grp * ag_gstride;
   const int nkb = (npairs + 15) / 16;
   const int t = threadIdx.x;
+  // (m, block of 16 pairs) tiles in which no pair starts before the last
+  // step of m hold mu = 0 for every l: the adjoint skips their products
+  // (the same test per tile of steps), so they are neither read nor written
+  if (t < kPrepM) live[t] = 0;
+  __syncthreads();
+  if (t < kPrepM * 16) {
+    const int mm = t >> 4, pair = kb * 16 + (t & 15), m = m0 + mm;
+    if (pair < npairs && m <= mmax && lst_g[(size_t)m * npairs + pair] <= (lmax - m) / kGroup) live[mm] = 1;
+  }
+  __syncthreads();
   // load: row = rhs * 16 + pair (256 rows), 8 m per row, one float4 (q = 0, 1) per (row, m)
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
@@ -547,7 +559,7 @@ __global__ __launch_bounds__(256) void k_prep_adj(int mmax, int npairs, int nrhs
     const int rhs = row >> 4, pr = row & 15;
     const int pair = kb * 16 + pr, m = m0 + mm;
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (rhs < nrhs && pair < npairs && m <= mmax)
+    if (rhs < nrhs && pair < npairs && m <= mmax && live[mm])
       v = *reinterpret_cast<const float4*>(geo + rhs * geo_stride + ((size_t)pair * (mmax + 1) + m) * 2);
     float* d = G + mm * kPrepMS + rhs * 32 + pr;
     d[0 * 512 + 0] = v.x;    // q = 0, re
@@ -562,7 +574,7 @@ __global__ __launch_bounds__(256) void k_prep_adj(int mmax, int npairs, int nrhs
 #pragma unroll
   for (int pass = 0; pass < kPrepM / 2; ++pass) {
     const int mm = pass * 2 + (t >> 7), m = m0 + mm;
-    if (m > mmax) continue;
+    if (m > mmax || !live[mm]) continue;
     const float* src = G + mm * kPrepMS + q * 512 + c * 16 + kg * 8;
     const float4 lo4 = *reinterpret_cast<const float4*>(src), hi4 = *reinterpret_cast<const float4*>(src + 4);
     const float x[8] = {lo4.x, lo4.y, lo4.z, lo4.w, hi4.x, hi4.y, hi4.z, hi4.w};
@@ -694,8 +706,12 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
     PairData nxt = cur;
     if (r0 + 64 < rend) nxt = load_pairs(r0 + 64);
     const int gs = cur.gs;
-    // skip the round when no pair becomes live before the end of the tile
-    if (wave_min(gs) <= (st0 + kAdjTile - 1) / kGroup) {
+    // skip the round when no pair becomes live before the end of the tile,
+    // and within it the blocks of 16 pairs of which none does: their mu are
+    // exactly 0 in this tile, and their operand tiles may not have been
+    // written (k_prep_adj skips (m, 16-pair) tiles that stay 0 for every l)
+    const uint64_t livemask = __ballot(gs <= (st0 + kAdjTile - 1) / kGroup);
+    if (livemask != 0) {
       // G operands of the round's 4 blocks of 16 pairs, issued before the recurrence
       bf16x8 aq[4][2][NS];   // [block of 16 pairs][parity][part]
 #pragma unroll
@@ -726,9 +742,11 @@ __global__ __launch_bounds__(256) void k_adj_mfma(int lmax, int mmax, int npairs
           }
         }
         // blocks of 16 pairs past the last pair: their mu are 0 (no start
-        // state, zero checkpoint), so the clamped operands add nothing
+        // state, zero checkpoint) and they are skipped like blocks of pairs
+        // not yet live
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
+          if (((livemask >> (16 * kb)) & 0xffffull) == 0) continue;   // wavefront-uniform
           // B[k][n] = mu(pair 16 kb + k, step pair n): lane n + 32 (k/8) reads 8 pairs of row n
           const int p0 = 16 * kb + 8 * kg;
           float xe[8], xo[8];
@@ -1013,10 +1031,12 @@ hipError_t launch_legendre_adjoint_mixed(const crsht_plan* P, int nrhs, const fl
     const int nr = min(nrhs - c0, per);
     dim3 gp((g.npairs + 15) / 16, (g.mmax + kPrepM) / kPrepM, 1);
     if (ns == 3)
-      hipLaunchKernelGGL(k_prep_adj<3>, gp, dim3(256), 0, s, g.mmax, g.npairs, nr, geo + (int64_t)c0 * geo_stride,
+      hipLaunchKernelGGL(k_prep_adj<3>, gp, dim3(256), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.lst_g,
+                         geo + (int64_t)c0 * geo_stride,
                          geo_stride, ag, ag_group(g), P->pred);
     else
-      hipLaunchKernelGGL(k_prep_adj<2>, gp, dim3(256), 0, s, g.mmax, g.npairs, nr, geo + (int64_t)c0 * geo_stride,
+      hipLaunchKernelGGL(k_prep_adj<2>, gp, dim3(256), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.lst_g,
+                         geo + (int64_t)c0 * geo_stride,
                          geo_stride, ag, ag_group(g), P->pred);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1048,7 +1068,8 @@ hipError_t launch_legendre_adjoint_mixed_q(const crsht_plan* P, int nrhs, const 
   for (int c0 = 0; c0 < nrhs; c0 += per) {
     const int nr = min(nrhs - c0, per);
     dim3 gp((g.npairs + 15) / 16, (g.mmax + kPrepM) / kPrepM, 1);
-    hipLaunchKernelGGL(k_prep_adj<2>, gp, dim3(256), 0, s, g.mmax, g.npairs, nr, geo + (int64_t)c0 * geo_stride,
+    hipLaunchKernelGGL(k_prep_adj<2>, gp, dim3(256), 0, s, g.lmax, g.mmax, g.npairs, nr, P->t.lst_g,
+                       geo + (int64_t)c0 * geo_stride,
                        geo_stride, ag, ag_group(g), P->pred);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
