@@ -19,6 +19,9 @@ namespace crsht {
 constexpr int kScaleBits = 600;
 constexpr double kRescaleAbove = 0x1p500;     // |v| above this triggers rescaling
 constexpr double kRescaleBy = 0x1p-600;       // 2^-kScaleBits
+// l - m steps per group of the start table (lst_g counts groups): a ring pair
+// contributes at m iff its first live group g satisfies g <= (lmax - m) / kStartGroup
+constexpr int kStartGroup = 16;
 
 // Sizes of a plan.
 struct Geometry {
@@ -56,6 +59,8 @@ struct Tables {
   double* lmm_v = nullptr;         // [mmax+1][npairs] start value mantissa
   int* lmm_k = nullptr;            // [mmax+1][npairs] start scale index k <= 0
   int* lst_g = nullptr;            // [mmax+1][npairs] first live group of 16 steps (INT_MAX: never)
+  int* pair_mtop = nullptr;        // [npairs] largest m at which the pair's recurrence starts by l = lmax:
+                                   // above it lambda_lm of the pair stays 0 for every l
   double2* lst_s = nullptr;        // [mmax+1][npairs] (mu_{l-2}, mu_{l-1}) at the start of that group
   int64_t* mstart = nullptr;       // [mmax+2] index of a_{m,m}; mstart[mmax+1] = nalm
   double* ones = nullptr;          // [nalm] 1.0
@@ -403,6 +408,10 @@ enum RingMode { RING_SYNTH = 0, RING_ADJOINT = 1, RING_FUSED = 2 };
 struct RingCols {
   int group = 1, eo_cols = 1, geo_cols = 1;
   int64_t ninv_stride = 0;
+  // per ring pair, the largest m the pass reads and writes (t.pair_mtop), or
+  // null for all m: launch_ring sets it for the FP32 fused pass of T plans,
+  // whose consumer (k_prep_adj) reads no m above it
+  const int* mtop = nullptr;
 };
 hipError_t launch_ring(const crsht_plan* P, int nrhs, RingMode mode, const void* eo, double* map,
                        const double* ninv, void* geo, bool f32, hipStream_t s, RingCols cols = RingCols());

@@ -25,7 +25,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kNever = 0x7fffffff;
-constexpr int kGroup = 16;      // start-table group (steps)
+constexpr int kGroup = kStartGroup;   // start-table group (steps)
 constexpr int kSynChunk = 32;   // steps per synthesis K chunk (16 even + 16 odd)
 constexpr int kAdjTile = 64;    // steps per adjoint output tile (32 even + 32 odd)
 constexpr int kAdjWaves = 4;
@@ -534,7 +534,8 @@ __global__ __launch_bounds__(256) void k_prep_adj(int lmax, int mmax, int npairs
                                                   const int* __restrict__ pred) {
   if (pred && *pred) return;
   __shared__ __attribute__((aligned(16))) float G[kPrepM * kPrepMS];
-  __shared__ int live[kPrepM];
+  __shared__ int live[kPrepM];            // m holds a live pair of this block of 16
+  __shared__ unsigned char livep[kPrepM][16];   // (m, pair) live
   const int kb = blockIdx.x, m0 = blockIdx.y * kPrepM, grp = blockIdx.z;   // right-hand sides 16 grp ..
   nrhs -= 16 * grp;
   geo += (int64_t)16 * grp * geo_stride;
@@ -548,7 +549,9 @@ __global__ __launch_bounds__(256) void k_prep_adj(int lmax, int mmax, int npairs
   __syncthreads();
   if (t < kPrepM * 16) {
     const int mm = t >> 4, pair = kb * 16 + (t & 15), m = m0 + mm;
-    if (pair < npairs && m <= mmax && lst_g[(size_t)m * npairs + pair] <= (lmax - m) / kGroup) live[mm] = 1;
+    const bool lv = pair < npairs && m <= mmax && lst_g[(size_t)m * npairs + pair] <= (lmax - m) / kGroup;
+    livep[mm][t & 15] = lv ? 1 : 0;
+    if (lv) live[mm] = 1;
   }
   __syncthreads();
   // load: row = rhs * 16 + pair (256 rows), 8 m per row, one float4 (q = 0, 1) per (row, m)
@@ -559,7 +562,9 @@ __global__ __launch_bounds__(256) void k_prep_adj(int lmax, int mmax, int npairs
     const int rhs = row >> 4, pr = row & 15;
     const int pair = kb * 16 + pr, m = m0 + mm;
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (rhs < nrhs && pair < npairs && m <= mmax && live[mm])
+    // pairs not live at m take 0 (their mu are 0; the FP32 fused ring pass
+    // writes no m above the pair's largest live m)
+    if (rhs < nrhs && livep[mm][pr])
       v = *reinterpret_cast<const float4*>(geo + rhs * geo_stride + ((size_t)pair * (mmax + 1) + m) * 2);
     float* d = G + mm * kPrepMS + rhs * 32 + pr;
     d[0 * 512 + 0] = v.x;    // q = 0, re

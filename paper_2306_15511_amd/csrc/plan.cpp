@@ -74,7 +74,7 @@ int upload(T** p, const std::vector<T>& h, size_t* total) {
 void free_plan_memory(crsht_plan* P) {
   void* ptrs[] = {P->t.pair_z, P->t.pair_nphi, P->t.pair_phi0, P->t.pair_first_n, P->t.pair_first_s,
                   P->t.pair_fft_len, P->t.pair_bs_off, P->t.pair_bk_off, P->t.bs_chirp, P->t.bs_kern,
-                  P->t.twiddle, P->t.bs_chirp32, P->t.bs_kern32, P->t.twiddle32, P->t.ring_pairs, P->t.rec_alpha, P->t.rec_kappa, P->t.lmm_v, P->t.lmm_k, P->t.lst_g, P->t.lst_s, P->t.mstart, P->t.ones,
+                  P->t.twiddle, P->t.bs_chirp32, P->t.bs_kern32, P->t.twiddle32, P->t.ring_pairs, P->t.rec_alpha, P->t.rec_kappa, P->t.lmm_v, P->t.lmm_k, P->t.lst_g, P->t.pair_mtop, P->t.lst_s, P->t.mstart, P->t.ones,
                   P->t.mx_cstart, P->t.mx_tstart, P->t.mx_tile_m, P->t.mx_order, P->t.mx_ckpt, P->w.cg_xacc, P->w.cg_bin, P->w.bin_edges, P->w.bin_part, P->w.bin_grad, P->w.lfac, P->w.camp,
                   P->w.mx_ab, P->w.mx_ag, P->w.adj_part, P->w.pol,
                   P->t.idx_l, P->t.idx_m, P->w.eo, P->w.geo, P->w.alm_a, P->w.alm_b, P->w.cg_x, P->w.cg_r, P->t.idx_mv, P->w.bl_keep, P->w.sblk,
@@ -305,6 +305,17 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int ncomp, i
   if ((rc = dalloc(&P->t.lst_s, (size_t)(mmax + 1) * np, total))) return rc;
   if (crsht::launch_legendre_start(P, nullptr) != hipSuccess) return CR_EDEVICE;
   if (hipDeviceSynchronize() != hipSuccess) return CR_EDEVICE;
+  {
+    // largest m at which each ring pair's recurrence becomes live by l = lmax
+    std::vector<int> lg((size_t)(mmax + 1) * np);
+    if (hipMemcpy(lg.data(), P->t.lst_g, lg.size() * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+      return CR_EDEVICE;
+    std::vector<int> mtop(np, 0);
+    for (int m = 0; m <= mmax; ++m)
+      for (int p = 0; p < np; ++p)
+        if (lg[(size_t)m * np + p] <= (lmax - m) / crsht::kStartGroup) mtop[p] = m;
+    if ((rc = upload(&P->t.pair_mtop, mtop, total))) return rc;
+  }
   {
     std::vector<double> ones(g.nalm, 1.0);
     if ((rc = upload(&P->t.ones, ones, total))) return rc;

@@ -527,8 +527,10 @@ __global__ __launch_bounds__(NT) void k_ring(Tables T, int nside, int mmax, int 
   double* __restrict__ mp = map + c * map_stride;
   if (ninv) ninv += kc * rc.ninv_stride;
 
+  // m above the pair's last live m: no Legendre sums to fold, no G written
+  const int mtop = rc.mtop ? min(mmax, rc.mtop[p]) : mmax;
   if (MODE == RING_FUSED) {
-    ring_inverse(buf, scratch, q, eop, mmax, tw, lf);
+    ring_inverse(buf, scratch, q, eop, mtop, tw, lf);
     // N^-1 of the ring (n <= 8 blockDim): all loads issued before the
     // products, without per-lane conditions (indices past the ring read its
     // first pixel; the values are not used)
@@ -563,7 +565,7 @@ __global__ __launch_bounds__(NT) void k_ring(Tables T, int nside, int mmax, int 
   }
   ring_forward(buf, q, tw, lf);
   lds_barrier();
-  write_geo(geop, buf, q, mmax);
+  write_geo(geop, buf, q, mtop);
 }
 
 // threads of a class of FFT length Lc with Lc / div points per thread
@@ -716,6 +718,7 @@ hipError_t launch_ring(const crsht_plan* P, int nrhs, RingMode mode, const void*
   const int tid = mode == RING_FUSED ? (f32 ? 2 : 6) : -1;
   timing_begin(P, tid, s);
   hipError_t e;
+  if (f32 && mode == RING_FUSED && P->ncomp == 1) cols.mtop = P->t.pair_mtop;
   if (f32)
     e = ring_mode<float2>(P, nrhs, mode, (const float2*)eo, map, ninv, (float2*)geo, P->t.twiddle32, P->t.bs_chirp32,
                           P->t.bs_kern32, cols, s);
