@@ -55,8 +55,8 @@ HBM_PEAK_GBS = 8000.0
 # has none: the probe runs its plain form, the solve its PCG form, which
 # also reads p and writes q.)
 TRAFFIC = {
-    "k_synth_mfma": {"bytes": 696476416, "src": "29b0e93d1254f353"},
-    "k_ring<float2, RING_FUSED>": {"bytes": 851819264, "src": "76e554674a4903a5"},   # one pass (4 class launches)
+    "k_synth_mfma": {"bytes": 696603776, "src": "cf97a06e5dd06004"},
+    "k_ring<float2, RING_FUSED>": {"bytes": 626375360, "src": "e3e614dbe0919562"},   # one pass (4 class launches)
     "k_legendre_synth_mfma": {"bytes": 2 * 679587920, "src": "4759d7b6f7f34de0"},  # one transform (2 launches)
     "k_legendre_adj_mfma": {"bytes": 4 * 464820008, "src": "4759d7b6f7f34de0"},  # one transform (2 x 2 launches)
     "k_pc_apply": {"bytes": 2389456395, "src": "648961bc9f2460e7"},   # solve form: FP32 z, <r, z> partials
@@ -595,9 +595,13 @@ def kernel_roofline(args, plan, one_solve, nside, lmax, R, nc, mixed, use_block,
     # scalar Legendre columns per transform: a T+Q+U column is 9 in the
     # synthesis and 7 in the adjoint; the ring pass sees nc maps per column
     cs, ca = (9 * R, 7 * R) if tqu else (R, R)
+    # the FP32 fused pass of T plans reads and writes the sums only at the
+    # (ring pair, m) where the pair's Legendre values are live (E and O,
+    # float2 each)
+    eo32_pass = 2 * plan.live_pair_m * 2 * 8 if not tqu else 2 * eo32
     kinfo = {
         2: ("k_ring<float2, RING_FUSED> (azimuthal FFT pass, N^-1 fused, FP32)", "hbm",
-            nc * R * 2 * eo32 + nc * plan.npix * 8, HBM_PEAK_GBS, "GB/s", "ring.hip"),
+            nc * R * eo32_pass + nc * plan.npix * 8, HBM_PEAK_GBS, "GB/s", "ring.hip"),
         6: ("k_ring<double2, RING_FUSED> (azimuthal FFT pass, N^-1 fused, FP64)", "hbm",
             nc * R * 2 * 2 * eo32 + nc * plan.npix * 8, HBM_PEAK_GBS, "GB/s", "ring.hip"),
     }

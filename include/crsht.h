@@ -125,6 +125,11 @@ typedef struct {
                                 block-preconditioner inverses, each read once
                                 per cr_block_precond_apply (0 if none is built) */
   int precond_blocks, precond_half_blocks;   /* blocks stored, of which in FP16 */
+  int64_t live_pair_m;       /* (ring pair, m) combinations at which the pair's
+                                Legendre values are not all below the underflow
+                                threshold, of npairs x (mmax + 1): the Legendre
+                                sums the mixed-precision T operator's ring pass
+                                reads and writes per column */
 } crsht_info;
 
 /* Fill *info (host). */

@@ -36,7 +36,8 @@ class _Info(ctypes.Structure):
     _fields_ = [("nside", ctypes.c_int), ("lmax", ctypes.c_int), ("mmax", ctypes.c_int), ("ncomp", ctypes.c_int),
                 ("nrhs_max", ctypes.c_int), ("nrings", ctypes.c_int), ("npix", ctypes.c_int64),
                 ("nalm", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64), ("precond_bytes", ctypes.c_int64),
-                ("precond_blocks", ctypes.c_int), ("precond_half_blocks", ctypes.c_int)]
+                ("precond_blocks", ctypes.c_int), ("precond_half_blocks", ctypes.c_int),
+                ("live_pair_m", ctypes.c_int64)]
 
 
 class _Problem(ctypes.Structure):
@@ -227,6 +228,7 @@ class Plan:
         self.vlen = self.ncomp * self.nalm      # coefficients per column
         self.mlen = self.ncomp * self.npix      # map values per column
         self.workspace_bytes = int(info.workspace_bytes)
+        self.live_pair_m = int(info.live_pair_m)   # (ring pair, m) with live Legendre values
 
     def precond_info(self):
         """(bytes of the stored block-preconditioner inverses one application

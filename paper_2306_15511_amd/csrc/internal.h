@@ -61,6 +61,7 @@ struct Tables {
   int* lst_g = nullptr;            // [mmax+1][npairs] first live group of 16 steps (INT_MAX: never)
   int* pair_mtop = nullptr;        // [npairs] largest m at which the pair's recurrence starts by l = lmax:
                                    // above it lambda_lm of the pair stays 0 for every l
+  int64_t live_pair_m = 0;         // sum over pairs of pair_mtop + 1
   double2* lst_s = nullptr;        // [mmax+1][npairs] (mu_{l-2}, mu_{l-1}) at the start of that group
   int64_t* mstart = nullptr;       // [mmax+2] index of a_{m,m}; mstart[mmax+1] = nalm
   double* ones = nullptr;          // [nalm] 1.0

@@ -315,6 +315,7 @@ static int build_plan(crsht_plan* P, int nside, int lmax, int mmax, int ncomp, i
       for (int p = 0; p < np; ++p)
         if (lg[(size_t)m * np + p] <= (lmax - m) / crsht::kStartGroup) mtop[p] = m;
     if ((rc = upload(&P->t.pair_mtop, mtop, total))) return rc;
+    for (int p = 0; p < np; ++p) P->t.live_pair_m += mtop[p] + 1;
   }
   {
     std::vector<double> ones(g.nalm, 1.0);
@@ -528,6 +529,7 @@ extern "C" int crsht_plan_info(const crsht_plan* P, crsht_info* info) {
   info->precond_bytes = P->pc.built ? P->pc.stored_bytes : 0;
   info->precond_blocks = P->pc.built ? P->pc.nblocks : 0;
   info->precond_half_blocks = P->pc.built ? P->pc.nhalf : 0;
+  info->live_pair_m = P->t.live_pair_m;
   return CR_OK;
 }
 
