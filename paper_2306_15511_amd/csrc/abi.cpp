@@ -281,7 +281,10 @@ int operator_core_cg(const crsht_plan* P, int nrhs, bool update, const double* n
     CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, s));
     return CR_OK;
   }
-  CR_TRY(launch_legendre_synth_mixed_cg(P, nrhs, w.cg_z, w.cg_p, update, F2(w.eo), s, z32));
+  // T plans: the pending x += alpha p of the last update goes with the
+  // direction update, which reads that p anyway (pcg_update defers it)
+  CR_TRY(launch_legendre_synth_mixed_cg(P, nrhs, w.cg_z, w.cg_p, update, F2(w.eo), s, z32,
+                                        cg_q32(P) ? w.cg_x : nullptr));
   CR_TRY(launch_ring(P, nrhs, RING_FUSED, w.eo, nullptr, ninv, w.geo, true, s));
   CR_TRY(launch_legendre_adjoint_mixed_q(P, nrhs, F2(w.geo), w.cg_p, F2(out), s));
   CR_TRY(launch_cg_scalars(P, nrhs, 1, nb, tol, 0, s, w.adj_part, (int)P->t.mx_ntiles));
@@ -626,6 +629,14 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
   CR_TRY(hipMemsetAsync(w.cg_x, 0, (size_t)nrhs * na * sizeof(double2), s));
   CR_TRY(hipMemcpyAsync(w.cg_r, w.cg_b, (size_t)nrhs * na * sizeof(double2), hipMemcpyDeviceToDevice, s));
   const bool z32 = cg_z32(P, pc);
+  // the iterations of T plans leave the last x += alpha p pending (scal
+  // S_XA): applied before x is read, here and on the host copy of the scalars
+  auto flush_x = [&]() -> int {
+    if (!cg_q32(P)) return CR_OK;
+    CR_TRY(launch_x_flush(P, nrhs, s));
+    for (int c = 0; c < nrhs; ++c) P->w.host_scal[c * kScalSlots + S_XA] = 0.0;
+    return CR_OK;
+  };
   CR_CHECK(pcg_start(P, nrhs, w.cg_b, pc, s, z32));
   CR_TRY(launch_cg_scalars(P, nrhs, 0, nb, tol, 0, s));
   CR_CHECK(read_scalars(P, nrhs, s));
@@ -653,6 +664,7 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
         if (sc[S_BREAK] != 0.0 || rel[c] <= tol) continue;
         if (sc[S_DONE] != 0.0 || sc[S_REL] < kLowReplaceFloor) low = false;
       }
+      CR_CHECK(flush_x());
       std::vector<double> keep(P->w.host_scal, P->w.host_scal + (size_t)nrhs * kScalSlots);
       CR_CHECK(true_residual(P, nrhs, ninv, w.cg_x, w.cg_b, w.cg_r, rel, s, low));
       fresh = !low;
@@ -701,6 +713,7 @@ int solve_refined(const crsht_plan* P, int nrhs, const double* ninv, const cr_op
       // out of iterations, or (once max_refine replacements are spent)
       // stopped on its recursive residual; report the true residual of the x
       // that is returned
+      CR_CHECK(flush_x());
       if (!fresh) CR_CHECK(true_residual(P, nrhs, ninv, w.cg_x, w.cg_b, w.cg_r, rel, s));
       break;
     }
@@ -803,12 +816,16 @@ int dsolve_check_replace(const DSolve& d, hipStream_t q, bool tail) {
   const crsht_plan* P = d.P;
   Workspace const& w = P->w;
   CR_TRY(launch_dctl(P, DC_CHECK, d.a, nullptr, q));
+  // (mixed T iterations leave the last x += alpha p pending: applied first)
+  const bool defer = d.mixed && cg_q32(P);
   {
     PredScope ps(P, w.ctl + C_SKIP_REPL);
+    if (defer) CR_TRY(launch_x_flush(P, d.nrhs, q));
     CR_CHECK(true_residual_dev(P, d.nrhs, d.ninv, w.cg_x, w.cg_b, w.cg_r, q));
   }
   if (d.mixed) {
     PredScope ps(P, w.ctl + C_SKIP_REPL_LOW);
+    if (defer) CR_TRY(launch_x_flush(P, d.nrhs, q));
     CR_CHECK(true_residual_dev(P, d.nrhs, d.ninv, w.cg_x, w.cg_b, w.cg_r, q, true));
   }
   CR_TRY(launch_dctl(P, DC_AFTER_REPL, d.a, nullptr, q));
@@ -933,6 +950,7 @@ int dsolve_epilogue(const DSolve& d, double* s_out, void* stats_dev, hipStream_t
   const crsht_plan* P = d.P;
   Workspace const& w = P->w;
   CR_CHECK(dsolve_check_replace(d, s, false));
+  if (d.mixed && cg_q32(P)) CR_TRY(launch_x_flush(P, d.nrhs, s));   // any pending x += alpha p
   CR_TRY(launch_dctl(P, DC_FINAL_PRE, d.a, nullptr, s));
   {
     PredScope ps(P, w.ctl + C_SKIP_FINAL);

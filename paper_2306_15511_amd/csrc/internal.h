@@ -165,6 +165,10 @@ enum ScalSlot {
   S_LAST = 16,     // true relative residual at the last replacement (1 before the first)
   S_REFINE = 17,   // residual replacements of the column
   S_TRUE = 18,     // last true relative residual
+  // mixed-precision T iteration: the x += alpha p of the last update, still
+  // to be applied (by the next direction update, which reads that p, or by
+  // launch_x_flush before x is used); 0 when none is pending
+  S_XA = 19,
 };
 
 // Control block of a device-driven solve (int32, plan workspace w.ctl).
@@ -386,8 +390,10 @@ hipError_t launch_legendre_synth_mixed(const crsht_plan* P, int nrhs, const doub
 // the same inside PCG: p = z + beta p per column (scalars in w.scal; skipped
 // for done columns or when !update) fused with the operand preparation, then
 // eo from bk * p
+// x (optional): first x += scal[S_XA] p per column, the pending solution
+// update of the last iteration (with p before its update)
 hipError_t launch_legendre_synth_mixed_cg(const crsht_plan* P, int nrhs, const double2* z, double2* p, bool update,
-                                          float2* eo, hipStream_t s, bool z32 = false);
+                                          float2* eo, hipStream_t s, bool z32 = false, double2* x = nullptr);
 // raw sums as launch_legendre_adjoint (non-diag) from float2 geo, bf16x3 /
 // FP32 accumulation
 // T plans, PCG: the bf16x3 adjoint fused with q = camp.x sinv p + bk raw,
@@ -522,9 +528,14 @@ hipError_t launch_cg_scalars(const crsht_plan* P, int nrhs, int what, int nb, do
                              hipStream_t s, const double* part0 = nullptr, int n0 = 0);
 // noz == false: z = r / D with <r, z> in row 0; true: z untouched, row 0 = 0
 // (the block preconditioner follows, with its own <r, z> partials). q32:
-// q is read as FP32 from there instead of q (the mixed T iteration)
+// q is read as FP32 from there instead of q, and x is not touched: alpha
+// (0 for columns that were done) goes to scal[S_XA] for the next direction
+// update (the mixed T iteration)
 hipError_t launch_cg_update(const crsht_plan* P, int nrhs, double2* x, double2* r, double2* z, const double2* p,
                             const double2* q, hipStream_t s, bool noz = false, const float2* q32 = nullptr);
+// x += scal[S_XA] p per column, then scal[S_XA] = 0 (the pending solution
+// update of the mixed T iteration, before x is read)
+hipError_t launch_x_flush(const crsht_plan* P, int nrhs, hipStream_t s);
 hipError_t launch_cg_replace(const crsht_plan* P, int nrhs, const double2* r, double2* z, hipStream_t s);
 hipError_t launch_cg_pupdate(const crsht_plan* P, int nrhs, const double2* z, double2* p, double2* pt,
                              hipStream_t s);

@@ -263,13 +263,15 @@ __global__ __launch_bounds__(64) void k_prep_synth(int lmax, int nrhs, const int
 // 0), written back in FP64, and the ab tiles built from bk * p. z, p: [rhs][nalm]
 // at column stride nalm; the block stages bk * p (float) in LDS as
 // [q][rhs][comp][16 steps] so that each lane reads its 8 steps contiguously.
-// Z: the stored type of z (float2 after the block preconditioner).
+// Z: the stored type of z (float2 after the block preconditioner). x
+// (optional): the pending solution update x += scal[S_XA] p, with the p read
+// here before its update.
 template <typename Z>
 __global__ __launch_bounds__(64) void k_pupdate_prep(int lmax, int nrhs, int64_t nalm, const int64_t* __restrict__ mstart,
                                                      const int64_t* __restrict__ cstart, const double* __restrict__ bk,
                                                      const Z* __restrict__ z, double2* __restrict__ p,
-                                                     const double* __restrict__ scal, int update,
-                                                     bf16x8* __restrict__ ab, int64_t ab_gstride,
+                                                     double2* __restrict__ x, const double* __restrict__ scal,
+                                                     int update, bf16x8* __restrict__ ab, int64_t ab_gstride,
                                                      const int* __restrict__ pred) {
   if (pred && *pred) return;
   __shared__ __attribute__((aligned(16))) float st_lds[2][16][2][16];
@@ -277,6 +279,7 @@ __global__ __launch_bounds__(64) void k_pupdate_prep(int lmax, int nrhs, int64_t
   nrhs -= 16 * grp;
   z += (int64_t)16 * grp * nalm;
   p += (int64_t)16 * grp * nalm;
+  if (x) x += (int64_t)16 * grp * nalm;
   scal += 16 * grp * kScalSlots;
   ab += grp * ab_gstride;
   const int nsteps = lmax - m + 1;
@@ -290,17 +293,21 @@ __global__ __launch_bounds__(64) void k_pupdate_prep(int lmax, int nrhs, int64_t
   // every load first and without per-lane conditions (a load under one is
   // waited for at once): elements outside the chunk or the columns read the
   // m's first element of column 0, and their values are not used
-  double2 pv[8], zv[8];
-  double done[8], beta[8];
+  double2 pv[8], zv[8], xv[8];
+  double done[8], beta[8], xa[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int rhs = (lane >> 5) + 2 * i;
     const bool ok = rhs < nrhs && live;
     const int64_t e = ok ? rhs * nalm + base + st : base;
     pv[i] = p[e];
+    const double* sc = scal + (ok ? rhs : 0) * kScalSlots;
+    if (x) {
+      xv[i] = x[e];
+      xa[i] = sc[S_XA];
+    }
     if (update) {
       zv[i] = zload(z + e);
-      const double* sc = scal + (ok ? rhs : 0) * kScalSlots;
       done[i] = sc[S_DONE];
       beta[i] = sc[S_BETA];
     }
@@ -311,6 +318,11 @@ __global__ __launch_bounds__(64) void k_pupdate_prep(int lmax, int nrhs, int64_t
     double2 v = make_double2(0.0, 0.0);
     if (rhs < nrhs && live) {
       v = pv[i];
+      if (x && xa[i] != 0.0) {
+        xv[i].x = fma(xa[i], v.x, xv[i].x);
+        xv[i].y = fma(xa[i], v.y, xv[i].y);
+        x[rhs * nalm + base + st] = xv[i];
+      }
       if (update && done[i] == 0.0) {
         v.x = fma(beta[i], v.x, zv[i].x);
         v.y = fma(beta[i], v.y, zv[i].y);
@@ -997,7 +1009,7 @@ hipError_t launch_legendre_synth_mixed(const crsht_plan* P, int nrhs, const doub
 
 // (the PCG inner operator: bf16x3 always)
 hipError_t launch_legendre_synth_mixed_cg(const crsht_plan* P, int nrhs, const double2* z, double2* p, bool update,
-                                          float2* eo, hipStream_t s, bool z32) {
+                                          float2* eo, hipStream_t s, bool z32, double2* x) {
   const Geometry& g = P->g;
   const int64_t eo_stride = (int64_t)g.npairs * (g.mmax + 1) * 2;
   bf16x8* ab = reinterpret_cast<bf16x8*>(P->w.mx_ab);
@@ -1008,12 +1020,13 @@ hipError_t launch_legendre_synth_mixed_cg(const crsht_plan* P, int nrhs, const d
     if (z32)
       hipLaunchKernelGGL(k_pupdate_prep<float2>, gp, dim3(64), 0, s, g.lmax, nr, g.nalm, P->t.mstart,
                          P->t.mx_cstart, P->w.bk, reinterpret_cast<const float2*>(z) + (int64_t)c0 * g.nalm,
-                         p + (int64_t)c0 * g.nalm, P->w.scal + (int64_t)c0 * kScalSlots, update ? 1 : 0, ab,
-                         ab_group(g), P->pred);
+                         p + (int64_t)c0 * g.nalm, x ? x + (int64_t)c0 * g.nalm : nullptr,
+                         P->w.scal + (int64_t)c0 * kScalSlots, update ? 1 : 0, ab, ab_group(g), P->pred);
     else
       hipLaunchKernelGGL(k_pupdate_prep<double2>, gp, dim3(64), 0, s, g.lmax, nr, g.nalm, P->t.mstart,
                          P->t.mx_cstart, P->w.bk, z + (int64_t)c0 * g.nalm, p + (int64_t)c0 * g.nalm,
-                         P->w.scal + (int64_t)c0 * kScalSlots, update ? 1 : 0, ab, ab_group(g), P->pred);
+                         x ? x + (int64_t)c0 * g.nalm : nullptr, P->w.scal + (int64_t)c0 * kScalSlots,
+                         update ? 1 : 0, ab, ab_group(g), P->pred);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = synth_mfma_launch(P, nr, 2, ab, eo + (int64_t)c0 * eo_stride, eo_stride, s);

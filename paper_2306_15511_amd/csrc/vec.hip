@@ -233,6 +233,7 @@ __global__ __launch_bounds__(kScalBlock) void k_cg_scalars(int what, int nb, con
       sc[S_BB] = s2;
       sc[S_ITERS] = 0.0;
       sc[S_BREAK] = 0.0;
+      sc[S_XA] = 0.0;
     }
     const double bb = sc[S_BB];
     sc[S_REL] = bb > 0.0 ? sqrt(s1 / bb) : 0.0;
@@ -273,32 +274,39 @@ __global__ __launch_bounds__(kScalBlock) void k_cg_scalars(int what, int nb, con
 
 // x += alpha p; r -= alpha q; z = r / D; partial <r,z>, <r,r>. Q: the
 // vector type of q (float2 in the mixed-precision T iteration)
+// With defer (FP32 q of the mixed T iteration) x and p are not touched: the
+// column's alpha (0 if it is done) is left in scal[S_XA] for the next
+// direction update, which reads that p anyway.
 template <typename Q>
 __global__ void k_cg_update(int64_t nalm, const int* __restrict__ idx_m, const double* __restrict__ diag,
                             const double* __restrict__ bk, double2* __restrict__ x, double2* __restrict__ r,
                             double2* __restrict__ z, const double2* __restrict__ p, const Q* __restrict__ q,
-                            double* __restrict__ partial, int npart, const double* __restrict__ scal, int noz,
+                            double* __restrict__ partial, int npart, double* __restrict__ scal, int noz, int defer,
                             const int* __restrict__ pred) {
   if (pred && *pred) return;
   __shared__ double sh[kVecBlock];
   const int c = blockIdx.y;
-  const double* sc = scal + c * kScalSlots;
+  double* sc = scal + c * kScalSlots;
   const bool skip = sc[S_DONE] != 0.0;
   const double a = sc[S_ALPHA];
+  if (defer && blockIdx.x == 0 && threadIdx.x == 0) sc[S_XA] = skip ? 0.0 : a;
   double rz = 0.0, rr = 0.0;
   if (!skip) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nalm; i += (int64_t)gridDim.x * blockDim.x) {
       const int64_t ci = c * nalm + i;
       const int m = idx_m[i];
-      const double2 pv = p[ci];
       const Q qq = q[ci];
       const double2 qv = make_double2((double)qq.x, (double)qq.y);
-      double2 xv = x[ci], rv = r[ci];
-      xv.x = fma(a, pv.x, xv.x);
-      xv.y = fma(a, pv.y, xv.y);
+      double2 rv = r[ci];
+      if (!defer) {
+        const double2 pv = p[ci];
+        double2 xv = x[ci];
+        xv.x = fma(a, pv.x, xv.x);
+        xv.y = fma(a, pv.y, xv.y);
+        x[ci] = xv;
+      }
       rv.x = fma(-a, qv.x, rv.x);
       rv.y = fma(-a, qv.y, rv.y);
-      x[ci] = xv;
       r[ci] = rv;
       if (!noz) {
         const double dinv = 1.0 / diag[i];
@@ -694,10 +702,42 @@ hipError_t launch_cg_update(const crsht_plan* P, int nrhs, double2* x, double2* 
   const int nb = vec_reduce_blocks(P);
   if (q32)
     hipLaunchKernelGGL(k_cg_update<float2>, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, P->w.diag,
-                       P->w.bk, x, r, z, p, q32, P->w.partial, P->w.npart, P->w.scal, noz ? 1 : 0, P->pred);
+                       P->w.bk, x, r, z, p, q32, P->w.partial, P->w.npart, P->w.scal, noz ? 1 : 0, 1, P->pred);
   else
     hipLaunchKernelGGL(k_cg_update<double2>, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->t.idx_mv, P->w.diag,
-                       P->w.bk, x, r, z, p, q, P->w.partial, P->w.npart, P->w.scal, noz ? 1 : 0, P->pred);
+                       P->w.bk, x, r, z, p, q, P->w.partial, P->w.npart, P->w.scal, noz ? 1 : 0, 0, P->pred);
+  return hipGetLastError();
+}
+
+// x += scal[S_XA] p per column
+__global__ void k_x_flush(int64_t nalm, double2* __restrict__ x, const double2* __restrict__ p,
+                          const double* __restrict__ scal, const int* __restrict__ pred) {
+  if (pred && *pred) return;
+  const int c = blockIdx.y;
+  const double a = scal[c * kScalSlots + S_XA];
+  if (a == 0.0) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nalm; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ci = c * nalm + i;
+    const double2 pv = p[ci];
+    double2 xv = x[ci];
+    xv.x = fma(a, pv.x, xv.x);
+    xv.y = fma(a, pv.y, xv.y);
+    x[ci] = xv;
+  }
+}
+
+__global__ void k_xa_clear(int nrhs, double* __restrict__ scal, const int* __restrict__ pred) {
+  if (pred && *pred) return;
+  for (int c = threadIdx.x; c < nrhs; c += blockDim.x) scal[c * kScalSlots + S_XA] = 0.0;
+}
+
+hipError_t launch_x_flush(const crsht_plan* P, int nrhs, hipStream_t s) {
+  const int nb = vec_reduce_blocks(P);
+  hipLaunchKernelGGL(k_x_flush, dim3(nb, nrhs), dim3(kVecBlock), 0, s, vlen(P), P->w.cg_x, P->w.cg_p, P->w.scal,
+                     P->pred);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_xa_clear, dim3(1), dim3(1024), 0, s, nrhs, P->w.scal, P->pred);
   return hipGetLastError();
 }
 
